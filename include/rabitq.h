@@ -1,0 +1,281 @@
+/*
+ * rabitq.h — C ABI of the MI355X (gfx950) RaBitQ query-phase library.
+ *
+ * RaBitQ (Gao & Long, SIGMOD 2024) estimates squared Euclidean distances from
+ * D-bit codes of randomly rotated, centroid-normalised vectors, and reranks
+ * the candidates whose error-bound interval can still reach the current k-th
+ * nearest exact distance. This library implements
+ *   - the index phase (Algorithm 1; Sec. 3.1) on the GPU: rotation by P,
+ *     normalisation against the IVF centroid, sign codes, <o_bar,o> and
+ *     ||o_r - c||;
+ *   - the query phase (Algorithm 2; Sec. 3.2-3.3) and IVF search with the
+ *     error-bound rerank (Sec. 4): rotate, probe the nearest lists, quantise
+ *     the query to B_q = 4 bits with randomised rounding per (query, list),
+ *     integer <x_b, q_u> by AND + popcount or int8 MFMA, the unbiased estimate,
+ *     the lower distance bound, exact rerank, top-k.
+ *
+ * Conventions for every function:
+ *   - Returns an rbq_status. Nothing aborts and no C++ exception crosses the
+ *     ABI. On error the outputs are unspecified, the index is unchanged and
+ *     rbq_last_error() returns a message (thread-local, valid until the next
+ *     call on the same thread).
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the current device. Each argument states which; a
+ *     pointer of the wrong kind is rejected with RBQ_EINVAL.
+ *   - The caller owns all buffers it passes. The index copies what it needs
+ *     at build/load time and owns that copy until rbq_index_destroy.
+ *   - `stream` is a hipStream_t (NULL = default stream). Device outputs are
+ *     written asynchronously on it; the caller synchronises. Functions that
+ *     return host outputs synchronise the stream before returning.
+ *   - An index owns one search workspace. rbq_search calls on one index are
+ *     serialised by an internal mutex, and each search first waits (on its own
+ *     stream, without blocking the host) for the kernels of the previous
+ *     search, so searches issued on different streams are safe but do not
+ *     overlap. rbq_index_build, rbq_index_destroy and rbq_nprobe_model_set
+ *     must not run concurrently with any other call on the same index.
+ */
+#ifndef RABITQ_H
+#define RABITQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBQ_OK = 0,
+  RBQ_EINVAL = 1,        /* bad argument (null, out of range, wrong pointer kind) */
+  RBQ_ENOMEM = 2,        /* host or device allocation failed */
+  RBQ_EDEVICE = 3,       /* a HIP runtime call failed */
+  RBQ_ESTATE = 4,        /* index not built, or call not allowed in this state */
+  RBQ_EFORMAT = 5,       /* corrupt or truncated index file */
+  RBQ_EUNSUPPORTED = 6   /* valid request this build does not implement */
+} rbq_status;
+
+/* Rotation arithmetic (S1 of the query path and the index-time rotation). */
+enum {
+  RBQ_ROT_FP32 = 0,      /* FP32 FMA GEMM */
+  RBQ_ROT_BF16X3 = 1     /* split-BF16 (hi + lo) MFMA GEMM, FP32 accumulation:
+                            hi*hi + hi*lo + lo*hi */
+};
+
+/* Kernel that computes the integer <x_b, q_u> (Sec. 3.3.2). */
+enum {
+  RBQ_SCAN_AUTO = 0,     /* autotuned / heuristic choice per search */
+  RBQ_SCAN_POPCNT = 1,   /* bit-plane AND + popcount, one code per lane */
+  RBQ_SCAN_MFMA = 2      /* int8 MFMA over queries grouped by list */
+};
+
+typedef struct rbq_index rbq_index;
+
+/* Index parameters (Sec. 5.1 gives eps0 = 1.9, B_q = 4 and the default code
+ * length, the smallest multiple of 64 not below D). */
+typedef struct {
+  int32_t dim;           /* D, raw vector length, >= 1 */
+  int32_t code_bits;     /* 0 => 64*ceil(D/64); else a multiple of 64, >= D, <= 4096 */
+  int32_t nlist;         /* number of IVF lists (1 = flat index) */
+  int32_t bq;            /* bits of the quantised query; must be 4 */
+  float eps0;            /* confidence parameter of the error bound (Theorem 3.2) */
+  int32_t rot_precision; /* RBQ_ROT_FP32 or RBQ_ROT_BF16X3 */
+  uint64_t seed;         /* seeds the randomised rounding (and P if none is given) */
+} rbq_params;
+
+/* Per-search options. */
+typedef struct {
+  int32_t k;                       /* neighbours to return, 1..256 */
+  int32_t nprobe;                  /* lists probed per query, 1..min(nlist, 1024) */
+  int32_t scan_kernel;             /* RBQ_SCAN_* */
+  int32_t use_learned_nprobe;      /* 1: per-query nprobe from the loaded MLP
+                                      (falls back to `nprobe` when none is set) */
+  const int32_t* nprobe_per_query; /* device, nq entries in 1..nprobe, or NULL */
+  int64_t qid_base;                /* query i uses id qid_base + i in the rounding RNG */
+} rbq_search_opts;
+
+/* Counters of one search (filled only when a stats pointer is passed; that
+ * makes rbq_search synchronise its stream before returning). */
+typedef struct {
+  int64_t queries;
+  int64_t pairs;              /* (query, list) pairs probed */
+  int64_t codes_scanned;      /* codes whose distance was estimated */
+  int64_t reranked;           /* exact distances computed */
+  int64_t candidates;         /* codes that passed the bound filter during the scan */
+} rbq_search_stats;
+
+typedef struct {
+  int32_t dim, code_bits, nlist, rot_precision;
+  int64_t n;                  /* vectors indexed */
+  int64_t device_bytes;       /* device memory held by the index (excl. workspace) */
+} rbq_index_info;
+
+/* Fills defaults: code_bits 0, bq 4, eps0 1.9, FP32 rotation, seed 0. */
+rbq_status rbq_params_default(rbq_params* p, int32_t dim, int32_t nlist);
+
+/* Creates an empty index with validated parameters. *out is owned by the caller
+ * and released with rbq_index_destroy. */
+rbq_status rbq_index_create(const rbq_params* p, rbq_index** out);
+
+/* Index phase (Algorithm 1; Sec. 3.1; IVF buckets of Sec. 4).
+ *   data      host, n x dim float32, row-major; vector i gets id i
+ *   centroids host, nlist x dim float32 (the IVF centroids, e.g. k-means)
+ *   assign    host, n int32 in [0, nlist): list of each vector
+ *   gauss     host, code_bits x code_bits float64 standard Gaussian draw, or
+ *             NULL to draw it from params.seed. P is obtained by
+ *             orthonormalising its rows (Gram-Schmidt, Appendix B), so P is
+ *             Haar distributed. Codes are sign(P^T (o_r - c)) (Sec. 3.1.3).
+ * Rebuilding an index replaces its contents. */
+rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t n,
+                           const float* centroids, const int32_t* assign,
+                           const double* gauss, void* stream);
+
+/* Query phase + IVF search (Algorithm 2; Sec. 4).
+ *   queries   device, nq x dim float32 row-major
+ *   out_ids   device, nq x k int64: ids of the k nearest by exact distance among
+ *             the reranked candidates of the probed lists, ordered by
+ *             (distance, id); -1 pads when fewer than k vectors were probed
+ *   out_dists device, nq x k float32 exact squared distances (+inf pads)
+ *   stats     host or NULL (see rbq_search_stats)
+ * nq may be 0 (nothing is launched). */
+rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t nq,
+                      const rbq_search_opts* opts, int64_t* out_ids, float* out_dists,
+                      rbq_search_stats* stats, void* stream);
+
+rbq_status rbq_index_info_get(const rbq_index* idx, rbq_index_info* out);
+
+/* Sizes of the IVF lists: host, nlist int64. */
+rbq_status rbq_index_list_sizes(const rbq_index* idx, int64_t* sizes);
+
+/* Versioned binary file: header, P, centroids, codes, factors, ids, raw vectors,
+ * and a 64-bit checksum. load returns RBQ_EFORMAT on a bad or truncated file. */
+rbq_status rbq_index_save(const rbq_index* idx, const char* path);
+rbq_status rbq_index_load(const char* path, rbq_index** out);
+
+rbq_status rbq_index_destroy(rbq_index* idx);
+
+const char* rbq_last_error(void);
+
+/* Preferred scan kernel and chunk length chosen by timing both kernels on a
+ * query sample (host queries, nq x dim). The choice is stored in the index and
+ * used by RBQ_SCAN_AUTO for batches near that size. */
+rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t nq, int32_t k,
+                        int32_t nprobe, void* stream);
+
+/* Kernel timing. When enabled, rbq_search records HIP events on its stream
+ * around each launch group and accumulates, on the device, the number of codes
+ * each scan phase estimated. rbq_profile_read synchronises the device and
+ * returns the sums since the last enable (times in milliseconds). */
+typedef struct {
+  int64_t searches;
+  double ms_front;        /* rotation + centroid scoring + probe selection */
+  double ms_prep;         /* per-pair quantisation + work planning */
+  double ms_scan0;        /* bootstrap scan (first chunks of each query) */
+  double ms_tau;          /* bootstrap rerank / threshold */
+  double ms_scan1;        /* main scan (all other chunks) */
+  double ms_finalize;     /* rerank + top-k */
+  int64_t codes_scan0;    /* codes estimated by the bootstrap scan */
+  int64_t codes_scan1;    /* codes estimated by the main scan */
+} rbq_profile;
+
+rbq_status rbq_profile_enable(rbq_index* idx, int32_t on);
+rbq_status rbq_profile_read(rbq_index* idx, rbq_profile* out);
+
+/* ---------------------------------------------------------------------------
+ * Learned per-query nprobe (not part of the paper): an MLP
+ *   features[96] -> 128 (ReLU) -> 32 logits over nprobe buckets
+ * with BF16 weights and FP32 accumulation.
+ *   features: log of the 64 nearest centroid distances relative to the
+ *   nearest (slot 0 holds log d_(1)), then for the 8 nearest lists
+ *   (||q_r-c_k||/||q_r-c_1||, v_l, v_r, sum q_u/(15*code_bits)).
+ *   bucket j maps to nprobe b_j = max(b_{j-1}+1, round(4 * 2^(7j/31))), so
+ *   b_0 = 4 and b_31 = 512. A query takes the smallest bucket whose cumulative
+ *   softmax reaches `threshold`.
+ */
+#define RBQ_MLP_IN 96
+#define RBQ_MLP_HIDDEN 128
+#define RBQ_MLP_OUT 32
+
+typedef struct {
+  int32_t epochs;
+  int32_t batch;
+  float lr;              /* Adam step size */
+  float beta1, beta2, eps;
+  uint64_t seed;         /* initialisation and shuffling */
+} rbq_train_cfg;
+
+/* Features of nq queries: queries device nq x dim, feats device nq x 96 float32. */
+rbq_status rbq_nprobe_features(rbq_index* idx, const float* queries, int64_t nq,
+                               int64_t qid_base, float* feats, void* stream);
+
+/* Trains the MLP on the GPU (own BF16 forward/backward kernels, FP32 master
+ * weights, Adam). feats device n x 96, labels device n int32 in [0, 32).
+ * losses: host, epochs floats (mean loss per epoch) or NULL. */
+rbq_status rbq_nprobe_model_train(rbq_index* idx, const float* feats, const int32_t* labels,
+                                  int64_t n, const rbq_train_cfg* cfg, float* losses,
+                                  void* stream);
+
+/* Weights as FP32 host arrays in the order W1[96x128], b1[128], W2[128x32], b2[32]
+ * (16,544 floats); NULL disables the model (fixed nprobe fallback). */
+rbq_status rbq_nprobe_model_set(rbq_index* idx, const float* weights, float threshold);
+rbq_status rbq_nprobe_model_get(const rbq_index* idx, float* weights, float* threshold);
+
+/* Per-query nprobe from the model: feats device nq x 96 -> nprobe device nq int32,
+ * logits device nq x 32 float32 (or NULL). */
+rbq_status rbq_nprobe_predict(rbq_index* idx, const float* feats, int64_t nq,
+                              int32_t* nprobe, float* logits, void* stream);
+
+/* One forward/backward of the MLP on given FP32 weights, for gradient checks:
+ * x device n x 96, labels device n, weights/grads device 16,544 floats,
+ * loss host float (mean cross-entropy). */
+rbq_status rbq_mlp_loss_grad(const float* x, const int32_t* labels, int64_t n,
+                             const float* weights, float* grads, float* loss, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Parity / debug exports. They run the same kernels as rbq_search on inputs
+ * chosen by the caller; not meant for production use.
+ */
+
+/* Codes and factors as encoded on the GPU, in the caller's original vector
+ * order: codes host n x (code_bits/64) uint64 (bit i%64 of word i/64 is the
+ * sign bit of coordinate i), norm host n float (||o_r - c||), ipo host n float
+ * (<o_bar, o>). Any output may be NULL. */
+rbq_status rbq_debug_export_codes(const rbq_index* idx, uint64_t* codes, float* norm,
+                                  float* ipo);
+
+/* Rotated queries: queries device nq x dim -> out device nq x code_bits. */
+rbq_status rbq_debug_rotate(rbq_index* idx, const float* queries, int64_t nq, float* out,
+                            void* stream);
+
+/* Probe step: queries device nq x dim -> lists device nq x nprobe int32 (nearest
+ * first, ties to the lower id), dists device nq x nprobe float32 (squared). */
+rbq_status rbq_debug_probe(rbq_index* idx, const float* queries, int64_t nq, int32_t nprobe,
+                           int32_t* lists, float* dists, void* stream);
+
+/* Per-pair quantisation (S3): queries device nq x dim, lists device nq x nprobe.
+ * qu device (nq*nprobe) x code_bits uint8 (0..15); scal device (nq*nprobe) x 4
+ * float32 {||q_r - c||, v_l, Delta, sum q_u}. */
+rbq_status rbq_debug_quantize(rbq_index* idx, const float* queries, int64_t nq,
+                              const int32_t* lists, int32_t nprobe, int64_t qid_base,
+                              uint8_t* qu, float* scal, void* stream);
+
+/* Scan arithmetic of one list for a caller-given quantised query (S4 + S6):
+ * qu device code_bits uint8, scal host 4 floats {b, v_l, Delta, (unused)};
+ * outputs device, one per member of the list in list order (ids of
+ * rbq_debug_list_ids): ip, pc int32; est, dist, lb float32.
+ * kernel: RBQ_SCAN_POPCNT or RBQ_SCAN_MFMA. */
+rbq_status rbq_debug_scan(rbq_index* idx, int32_t list, const uint8_t* qu, const float* scal,
+                          int32_t kernel, int32_t* ip, int32_t* pc, float* est, float* dist,
+                          float* lb, void* stream);
+
+/* Ids of the members of a list in stored order: host, size of the list. */
+rbq_status rbq_debug_list_ids(const rbq_index* idx, int32_t list, int64_t* ids);
+
+/* Test hook: the n-th device allocation after this call fails with RBQ_ENOMEM
+ * (0 disables). Process-wide; for failure-path tests only. */
+rbq_status rbq_debug_fail_alloc_after(int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RABITQ_H */

@@ -1,0 +1,145 @@
+// IVF probing (Sec. 4): per query, the nprobe lists with the smallest squared
+// centroid distance, nearest first, ties to the lower list id.
+#include "rbq_internal.hpp"
+
+namespace rbq {
+namespace {
+
+constexpr int kSelThreads = 256;
+
+// Bitonic sort of n (power of two) 64-bit keys in LDS, ascending.
+__device__ void bitonic_sort_u64(uint64_t* a, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = ((lo & size) == 0);
+        const uint64_t x = a[lo], y = a[hi];
+        if ((x > y) == up) {
+          a[lo] = y;
+          a[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// keys: distances as uint32 (non-negative floats order like their bit patterns).
+// Radix select of the P-th smallest key, then ordered collection of ties.
+__global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __restrict__ D,
+                                                              int nlist, int nprobe,
+                                                              const int32_t* __restrict__ nprobe_q,
+                                                              int32_t* __restrict__ lists,
+                                                              float* __restrict__ dists) {
+  extern __shared__ uint32_t keys[];                    // nlist
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t sel[kMaxNprobe];
+  __shared__ uint32_t sh_prefix, sh_rank, sh_nless;
+  __shared__ uint32_t tie_scan[kSelThreads];
+  const int64_t q = blockIdx.x;
+  int P = nprobe;
+  if (nprobe_q) P = uniform_i32(min(max(nprobe_q[q], 1), nprobe));
+  P = min(P, nlist);
+  const float* row = D + q * (int64_t)nlist;
+  for (int k = threadIdx.x; k < nlist; k += blockDim.x) keys[k] = __float_as_uint(fmaxf(row[k], 0.f));
+  if (threadIdx.x == 0) {
+    sh_prefix = 0;
+    sh_rank = P;
+  }
+  __syncthreads();
+  uint32_t mask = 0;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const uint32_t prefix = (uint32_t)uniform_i32((int)sh_prefix);
+    for (int k = threadIdx.x; k < nlist; k += blockDim.x) {
+      const uint32_t key = keys[k];
+      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t rank = sh_rank, cum = 0;
+      int b = 0;
+      for (; b < 256; ++b) {
+        if (cum + hist[b] >= rank) break;
+        cum += hist[b];
+      }
+      sh_rank = rank - cum;
+      sh_prefix = prefix | ((uint32_t)b << shift);
+    }
+    mask |= 255u << shift;
+    __syncthreads();
+  }
+  const uint32_t thr = (uint32_t)uniform_i32((int)sh_prefix);   // key of the P-th smallest
+  const uint32_t need = (uint32_t)uniform_i32((int)sh_rank);    // how many keys equal to thr to take
+  if (threadIdx.x == 0) sh_nless = 0;
+  __syncthreads();
+  // keys strictly below the threshold (P - need of them), any order
+  for (int k = threadIdx.x; k < nlist; k += blockDim.x) {
+    if (keys[k] < thr) {
+      const uint32_t at = atomicAdd(&sh_nless, 1u);
+      sel[at] = ((uint64_t)keys[k] << 32) | (uint32_t)k;
+    }
+  }
+  // ties: the first `need` in list-id order; thread t scans a contiguous range
+  const int per = (nlist + blockDim.x - 1) / blockDim.x;
+  const int kb = threadIdx.x * per, ke = min(nlist, kb + per);
+  uint32_t mine = 0;
+  for (int k = kb; k < ke; ++k) mine += (keys[k] == thr);
+  tie_scan[threadIdx.x] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      const uint32_t c = tie_scan[t];
+      tie_scan[t] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  const uint32_t nless = (uint32_t)P - need;
+  uint32_t rank = tie_scan[threadIdx.x];
+  for (int k = kb; k < ke && rank < need; ++k) {
+    if (keys[k] == thr) {
+      sel[nless + rank] = ((uint64_t)thr << 32) | (uint32_t)k;
+      ++rank;
+    }
+  }
+  __syncthreads();
+  int n2 = 1;
+  while (n2 < P) n2 <<= 1;
+  for (int i = P + threadIdx.x; i < n2; i += blockDim.x) sel[i] = ~0ull;
+  __syncthreads();
+  bitonic_sort_u64(sel, n2);
+  for (int i = threadIdx.x; i < nprobe; i += blockDim.x) {
+    if (i < P) {
+      lists[q * nprobe + i] = (int32_t)(uint32_t)(sel[i] & 0xffffffffu);
+      if (dists) dists[q * nprobe + i] = __uint_as_float((uint32_t)(sel[i] >> 32));
+    } else {
+      lists[q * nprobe + i] = -1;
+      if (dists) dists[q * nprobe + i] = __builtin_inff();
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_select_probe(const float* D, int64_t nq, int nlist, int nprobe,
+                               const int32_t* nprobe_q, int32_t* lists, float* dists,
+                               hipStream_t st) {
+  if (nq <= 0) return hipSuccess;
+  const size_t shm = (size_t)nlist * sizeof(uint32_t);
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)k_select_probe, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        96 * 1024);
+    attr_done = true;
+  }
+  hipLaunchKernelGGL(k_select_probe, dim3((unsigned)nq), dim3(kSelThreads), shm, st, D, nlist,
+                     nprobe, nprobe_q, lists, dists);
+  return hipGetLastError();
+}
+
+}  // namespace rbq

@@ -1,0 +1,798 @@
+// Query phase on the GPU: per-(query, list) quantisation, the bit-plane
+// popcount scan with the estimator epilogue, and the error-bound rerank.
+//
+// Work layout. Every probed (query, list) pair is cut into chunks of at most
+// `chunk` codes; a chunk is the unit a wave takes from a global work counter
+// (persistent grid). A query's chunks, in probe order, are numbered 0..nch-1
+// and its probed codes 0..ncode-1 ("query code space"). Each chunk owns the
+// slots of its codes in a per-query candidate segment, so results land at
+// positions fixed by (query, list, chunk), independent of scheduling.
+//
+// Rerank (Sec. 4). A code whose distance lower bound exceeds tau, the k-th
+// smallest exact distance known, cannot be among the k nearest and is dropped;
+// the others get their exact distance. tau must never be below the true k-th
+// distance; it only controls how much is reranked:
+//   phase 0: the first chunks of each query (at least k codes, nearest list
+//            first) are scanned and all their codes kept as candidates;
+//   tau:     the k of them with the smallest estimated distance get exact
+//            distances; the k-th of those bounds the true k-th distance;
+//   phase 1: the remaining chunks keep only codes with lb <= tau;
+//   final:   candidates are reranked in probe order with tau tightened after
+//            every round (the running k-th exact distance), giving the top-k.
+#include "rbq_internal.hpp"
+
+namespace rbq {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+
+// ------------------------------------------------------------------ prep (S3)
+// One wave per pair: b = ||q_r - c||; residual r = P^T q_r - P^T c in the
+// rotated space; q'_i = r_i / b; v_l, v_r, Delta; randomised rounding
+// q_u = min(15, floor((q' - v_l)/Delta + u)) computed as
+// 15 (r_i - r_min)/(r_max - r_min) + u (the 1/b scale cancels); bit planes by
+// ballot: plane j word t bit l = bit j of q_u at coordinate 64 t + l.
+__global__ __launch_bounds__(kThreads) void k_prep(SearchDev s) {
+  const int64_t g = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int64_t npairs = s.nq * s.nprobe;
+  if (g >= npairs) return;
+  const int lane = lane_id();
+  const int64_t q = g / s.nprobe;
+  const int r = (int)(g - q * s.nprobe);
+  int P = s.nprobe;
+  if (s.nprobe_q) P = uniform_i32(min(max(s.nprobe_q[q], 1), s.nprobe));
+  const int list = uniform_i32(s.probe[g]);
+  PairRec rec;
+  if (r >= P || list < 0) {
+    if (lane == 0) {
+      rec.k1 = rec.k2 = rec.k0 = rec.b = rec.vl = rec.delta = 0.f;
+      rec.sq = 0;
+      rec.list = -1;
+      s.pairs[g] = rec;
+    }
+    return;
+  }
+  const float* qr = s.q + q * s.dim;
+  const float* c = s.cent + (int64_t)list * s.dim;
+  float acc = 0.f;
+  for (int i = lane; i < s.dim; i += kWave) {
+    const float d = qr[i] - c[i];
+    acc = fmaf(d, d, acc);
+  }
+  const float b = sqrtf(wave_sum(acc));
+  const float* qrot = s.qrot + q * s.dp;
+  const float* crot = s.crot + (int64_t)list * s.dp;
+  float rmin = __builtin_inff(), rmax = -__builtin_inff();
+  for (int t = 0; t < s.W; ++t) {
+    const int i = t * kWave + lane;
+    const float v = qrot[i] - crot[i];
+    rmin = fminf(rmin, v);
+    rmax = fmaxf(rmax, v);
+  }
+  rmin = wave_min(rmin);
+  rmax = wave_max(rmax);
+  const float range = rmax - rmin;
+  const bool live = (b > 0.f) && (range > 0.f);
+  const float scale = live ? 15.f / range : 0.f;
+  const uint64_t qid = (uint64_t)(s.qid_base + q);
+  int sq = 0;
+  uint64_t* pl = s.planes + g * 4 * s.W;
+  int8_t* q8 = s.qu8 ? s.qu8 + g * s.dp : nullptr;
+  for (int t = 0; t < s.W; ++t) {
+    const int i = t * kWave + lane;
+    int qu = 0;
+    if (live) {
+      const float x = (qrot[i] - crot[i] - rmin) * scale;
+      qu = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list, (uint32_t)i)));
+    }
+    sq += qu;
+    if (q8) q8[i] = (int8_t)qu;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t w = __ballot((qu >> j) & 1);
+      if (lane == 0) pl[j * s.W + t] = w;
+    }
+  }
+  sq = wave_sum_i(sq);
+  if (lane == 0) {
+    // <x_bar, q_bar> = (2 Delta/sqrt D) ip + (2 v_l/sqrt D) pc - (Delta/sqrt D) sq - sqrt(D) v_l
+    const double rd = sqrt((double)s.dp);
+    double vl = 0.0, delta = 0.0;
+    if (b > 0.f) {
+      vl = (double)rmin / (double)b;
+      delta = (double)range / (15.0 * (double)b);
+    }
+    rec.k1 = (float)(2.0 * delta / rd);
+    rec.k2 = (float)(2.0 * vl / rd);
+    rec.k0 = (float)(-(delta / rd) * (double)sq - rd * vl);
+    rec.b = b;
+    rec.vl = (float)vl;
+    rec.delta = (float)delta;
+    rec.sq = sq;
+    rec.list = list;
+    s.pairs[g] = rec;
+  }
+}
+
+// ------------------------------------------------------------------ planning
+// One thread per query: chunk and code prefixes over its probed pairs, and the
+// bootstrap (phase-0) chunk count.
+__global__ void k_plan(SearchDev s) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= s.nq) return;
+  int P = s.nprobe;
+  if (s.nprobe_q) P = min(max(s.nprobe_q[q], 1), s.nprobe);
+  int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
+  int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
+  int32_t ch = 0, code = 0, p0 = -1, n0 = 0;
+  for (int r = 0; r < s.nprobe; ++r) {
+    choff[r] = ch;
+    codeoff[r] = code;
+    const int list = (r < P) ? s.probe[q * s.nprobe + r] : -1;
+    if (list < 0) continue;
+    const int n = s.list_off[list + 1] - s.list_off[list];
+    const int nc = (n + s.chunk - 1) / s.chunk;
+    if (p0 < 0) {
+      for (int c = 0; c < nc; ++c) {
+        n0 += min(s.chunk, n - c * s.chunk);
+        if (n0 >= s.k) {
+          p0 = ch + c + 1;
+          break;
+        }
+      }
+    }
+    ch += nc;
+    code += n;
+  }
+  choff[s.nprobe] = ch;
+  codeoff[s.nprobe] = code;
+  if (p0 < 0) p0 = ch;   // fewer than k codes probed: everything is bootstrap
+  s.q_nch[q] = ch;
+  s.q_p0[q] = p0;
+  s.q_n0[q] = n0;
+  s.q_ncode[q] = code;
+}
+
+// Exclusive prefix sums over queries (single block) and work-counter reset.
+__global__ __launch_bounds__(1024) void k_offsets(SearchDev s) {
+  __shared__ int64_t buf[5][1024];
+  __shared__ int64_t carry[5];
+  if (threadIdx.x < 5) carry[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    s.counters[0] = 0;
+    s.counters[1] = 0;
+  }
+  __syncthreads();
+  for (int64_t base = 0; base < s.nq; base += 1024) {
+    const int64_t q = base + threadIdx.x;
+    int64_t v[5] = {0, 0, 0, 0, 0};
+    if (q < s.nq) {
+      v[0] = s.q_nch[q];
+      v[1] = s.q_p0[q];
+      v[2] = s.q_nch[q] - s.q_p0[q];
+      v[3] = s.q_ncode[q];
+      v[4] = s.q_n0[q];
+    }
+    for (int a = 0; a < 5; ++a) buf[a][threadIdx.x] = v[a];
+    __syncthreads();
+    // Hillis-Steele inclusive scan
+    for (int o = 1; o < 1024; o <<= 1) {
+      int64_t t[5];
+      for (int a = 0; a < 5; ++a) t[a] = (threadIdx.x >= (unsigned)o) ? buf[a][threadIdx.x - o] : 0;
+      __syncthreads();
+      for (int a = 0; a < 5; ++a) buf[a][threadIdx.x] += t[a];
+      __syncthreads();
+    }
+    int64_t* outs[5] = {s.off_ch, s.off_p0, s.off_p1, s.off_seg, s.off_n0};
+    if (q < s.nq)
+      for (int a = 0; a < 5; ++a) outs[a][q] = carry[a] + buf[a][threadIdx.x] - v[a];
+    __syncthreads();
+    if (threadIdx.x == 1023)
+      for (int a = 0; a < 5; ++a) carry[a] += buf[a][1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int64_t* outs[5] = {s.off_ch, s.off_p0, s.off_p1, s.off_seg, s.off_n0};
+    for (int a = 0; a < 5; ++a) outs[a][s.nq] = carry[a];
+  }
+}
+
+// ------------------------------------------------------------------ scan arithmetic (S4 + S6)
+// Integer <x_b, q_u> = sum_j 2^j popcount(x_b AND plane_j) and popcount(x_b)
+// for the code at position p. WS > 0: planes held in registers (W == WS).
+template <int WS>
+struct Planes {
+  uint64_t w[4][WS];
+  __device__ __forceinline__ void load(const uint64_t* src, int) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int t = 0; t < WS; ++t) w[j][t] = src[j * WS + t];
+  }
+  __device__ __forceinline__ uint64_t get(int j, int t) const { return w[j][t]; }
+};
+template <>
+struct Planes<0> {
+  const uint64_t* p;   // LDS copy, [4][W]
+  int W;
+  __device__ __forceinline__ uint64_t get(int j, int t) const { return p[j * W + t]; }
+};
+
+template <int WS>
+__device__ __forceinline__ void code_ip(const uint64_t* __restrict__ codes, int64_t p, int W,
+                                        const Planes<WS>& pl, int& ip, int& pc) {
+  const int Wn = WS > 0 ? WS : W;
+  int s0 = 0, s1 = 0, s2 = 0, s3 = 0, c = 0;
+#pragma unroll
+  for (int t = 0; t < Wn; ++t) {
+    const uint64_t x = codes[code_word_index(p, t, W)];
+    c += __popcll(x);
+    s0 += __popcll(x & pl.get(0, t));
+    s1 += __popcll(x & pl.get(1, t));
+    s2 += __popcll(x & pl.get(2, t));
+    s3 += __popcll(x & pl.get(3, t));
+  }
+  ip = s0 + 2 * s1 + 4 * s2 + 8 * s3;
+  pc = c;
+}
+
+// est = <x_bar, q_bar>/<o_bar,o> (Theorem 3.2); Eq. (2) gives the distance;
+// the lower bound plugs est + half-width into Eq. (2).
+__device__ __forceinline__ void estimate(const PairRec& r, float2 f, int ip, int pc, float hwk,
+                                         float& est, float& dist, float& lb) {
+  const float a = f.x, ipo = f.y;
+  const float xq = fmaf(r.k1, (float)ip, fmaf(r.k2, (float)pc, r.k0));
+  const float inv = __builtin_amdgcn_rcpf(ipo);
+  est = xq * inv;
+  const float ab2 = 2.f * a * r.b;
+  const float base = fmaf(a, a, r.b * r.b);
+  dist = fmaf(-ab2, est, base);
+  const float hw = sqrtf(fmaxf(fmaf(-ipo, ipo, 1.f), 0.f)) * inv * hwk;
+  lb = fmaf(-ab2, hw, dist);
+}
+
+__device__ __forceinline__ int64_t upper_bound64(const int64_t* a, int64_t n, int64_t v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ int upper_bound32(const int32_t* a, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Resolves work unit u of a phase into its chunk; returns false when done.
+struct Unit {
+  int64_t q;
+  int j;       // local chunk index
+  int r;       // probe rank
+  int c;       // chunk within the pair
+  int64_t start, end;   // code positions
+  int64_t codeoff;      // query code space offset of the chunk start
+};
+
+__device__ __forceinline__ void resolve_unit(const SearchDev& s, int phase, int64_t u, Unit& w) {
+  const int64_t* off = phase == 0 ? s.off_p0 : s.off_p1;
+  const int64_t q = upper_bound64(off, s.nq + 1, u) - 1;
+  const int j = (phase == 0 ? 0 : s.q_p0[q]) + (int)(u - off[q]);
+  const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
+  const int r = upper_bound32(choff, s.nprobe + 1, j) - 1;
+  const int c = j - choff[r];
+  const int list = s.probe[q * s.nprobe + r];
+  const int64_t lbeg = s.list_off[list], lend = s.list_off[list + 1];
+  w.q = uniform_i64(q);
+  w.j = uniform_i32(j);
+  w.r = uniform_i32(r);
+  w.c = uniform_i32(c);
+  w.start = uniform_i64(lbeg + (int64_t)c * s.chunk);
+  w.end = uniform_i64(lend < w.start + s.chunk ? lend : w.start + s.chunk);
+  w.codeoff = uniform_i64((int64_t)s.pair_codeoff[q * (s.nprobe + 1) + r] + (int64_t)c * s.chunk);
+}
+
+template <int WS>
+__global__ __launch_bounds__(kThreads) void k_scan_popcnt(SearchDev s, int phase) {
+  __shared__ uint64_t lds_planes[kWaves][4 * (kMaxCodeBits / 64)];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t total = uniform_i64((phase == 0 ? s.off_p0 : s.off_p1)[s.nq]);
+  const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
+  for (;;) {
+    // Claim one unit per wave. Every lane issues the atomic (increment 1 on
+    // lane 0, 0 elsewhere) so no lane-dependent branch sits in the loop;
+    // lane 0's result, the first active lane's, is the claimed unit.
+    const int64_t u = uniform_i64((int64_t)atomicAdd(&s.counters[phase], lane == 0 ? 1ull : 0ull));
+    if (u >= total) break;
+    Unit w;
+    resolve_unit(s, phase, u, w);
+    const int64_t g = w.q * s.nprobe + w.r;
+    const PairRec rec = s.pairs[g];
+    const uint64_t* src = s.planes + g * 4 * s.W;
+    Planes<WS> pl;
+    if constexpr (WS > 0) {
+      pl.load(src, s.W);
+    } else {
+      uint64_t* dst = lds_planes[wave];
+      for (int i = lane; i < 4 * s.W; i += kWave) dst[i] = src[i];
+      pl.p = dst;
+      pl.W = s.W;
+    }
+    const float tau = phase == 0 ? __builtin_inff() : uniform_f32(s.tau[w.q]);
+    const int64_t seg_base = s.off_seg[w.q] + w.codeoff;
+    int count = 0;
+    for (int64_t p0 = w.start; p0 < w.end; p0 += kWave) {
+      const bool valid = p0 + lane < w.end;
+      // lanes past the end read the chunk's first code (in bounds) and are masked
+      const int64_t p = valid ? p0 + lane : w.start;
+      float est, dist, lb;
+      int ip, pc;
+      code_ip<WS>(s.codes, p, s.W, pl, ip, pc);
+      estimate(rec, s.fac[p], ip, pc, hwk, est, dist, lb);
+      lb = valid ? lb : __builtin_inff();
+      if (phase == 0) {
+        if (valid) {
+          const int64_t off = p - w.start;
+          Cand cd;
+          cd.pos = (int32_t)p;
+          cd.lb = lb;
+          s.seg[seg_base + off] = cd;
+          EstEnt e;
+          e.dist = dist;
+          e.slot = (int32_t)(w.codeoff + off);
+          s.p0buf[s.off_n0[w.q] + w.codeoff + off] = e;
+        }
+      } else {
+        const bool pass = valid && (lb <= tau);
+        const uint64_t m = __ballot(pass);
+        if (pass) {
+          Cand cd;
+          cd.pos = (int32_t)p;
+          cd.lb = lb;
+          s.seg[seg_base + count + __popcll(m & lanemask_lt())] = cd;
+        }
+        count += __popcll(m);
+      }
+    }
+    if (lane == 0) {
+      if (phase == 0) count = (int)(w.end - w.start);
+      s.seg_count[s.off_ch[w.q] + w.j] = count;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ exact distance
+// Wave-cooperative ||o_r - q_r||^2 for the raw vector at position pos.
+__device__ __forceinline__ float exact_dist(const float* __restrict__ raw, int64_t pos, int dim,
+                                            const float* __restrict__ qv) {
+  const float* o = raw + pos * dim;
+  float acc = 0.f;
+  for (int i = lane_id(); i < dim; i += kWave) {
+    const float d = o[i] - qv[i];
+    acc = fmaf(d, d, acc);
+  }
+  return wave_sum(acc);
+}
+
+__device__ __forceinline__ bool less_di(float d1, int64_t i1, float d2, int64_t i2) {
+  return d1 < d2 || (d1 == d2 && i1 < i2);
+}
+
+// ------------------------------------------------------------------ bootstrap tau
+// Per query: the k bootstrap codes with the smallest estimated distance get
+// their exact distance; they seed the top-k and tau; their segment entries are
+// marked done (pos = -1).
+__global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
+  __shared__ uint64_t key[kMaxP0];
+  __shared__ float qv[kMaxCodeBits];
+  __shared__ float topd[kMaxK];
+  __shared__ int32_t toppos[kMaxK];
+  __shared__ uint64_t key2[kMaxK];
+  const int64_t q = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int n0 = uniform_i32(s.q_n0[q]);
+  const int64_t b0 = uniform_i64(s.off_n0[q]);
+  for (int i = threadIdx.x; i < s.dim; i += kThreads) qv[i] = s.q[q * s.dim + i];
+  int n2 = 1;
+  while (n2 < n0) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += kThreads) {
+    if (i < n0) {
+      const EstEnt e = s.p0buf[b0 + i];
+      // order by estimated distance (as a sortable key), then slot
+      uint32_t kb = __float_as_uint(e.dist);
+      kb = (kb & 0x80000000u) ? ~kb : (kb | 0x80000000u);
+      key[i] = ((uint64_t)kb << 32) | (uint32_t)e.slot;
+    } else {
+      key[i] = ~0ull;
+    }
+  }
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < n2 / 2; i += kThreads) {
+        const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t x = key[lo], y = key[hi];
+        if ((x > y) == up) {
+          key[lo] = y;
+          key[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  const int m = min(s.k, n0);
+  const int64_t seg0 = uniform_i64(s.off_seg[q]);
+  for (int i = wave; i < m; i += kWaves) {
+    const int32_t slot = (int32_t)(uint32_t)(key[i] & 0xffffffffu);
+    const int32_t pos = s.seg[seg0 + slot].pos;
+    const float d = exact_dist(s.raw, pos, s.dim, qv);
+    if (lane == 0) {
+      topd[i] = d;
+      toppos[i] = pos;
+      s.seg[seg0 + slot].pos = -1;
+    }
+  }
+  __syncthreads();
+  // order the seeds by (distance, original id)
+  int m2 = 1;
+  while (m2 < m) m2 <<= 1;
+  for (int i = threadIdx.x; i < m2; i += kThreads)
+    key2[i] = (i < m) ? (((uint64_t)__float_as_uint(topd[i]) << 32) | (uint32_t)i) : ~0ull;
+  __syncthreads();
+  // distances are >= 0, so float bits sort like values; ties: by original id below
+  for (int size = 2; size <= m2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < m2 / 2; i += kThreads) {
+        const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t x = key2[lo], y = key2[hi];
+        bool gt;
+        if ((x >> 32) != (y >> 32)) {
+          gt = x > y;
+        } else if (x == ~0ull || y == ~0ull) {
+          gt = x > y;
+        } else {
+          gt = s.ids[toppos[(uint32_t)x]] > s.ids[toppos[(uint32_t)y]];
+        }
+        if (gt == up) {
+          key2[lo] = y;
+          key2[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < s.k; i += kThreads) {
+    SeedEnt e;
+    if (i < m) {
+      const int src = (int)(uint32_t)(key2[i] & 0xffffffffu);
+      e.dist = topd[src];
+      e.pos = toppos[src];
+    } else {
+      e.dist = __builtin_inff();
+      e.pos = -1;
+    }
+    s.seedk[q * s.k + i] = e;
+  }
+  if (threadIdx.x == 0) {
+    float t = __builtin_inff();
+    if (m == s.k) t = topd[(uint32_t)(key2[s.k - 1] & 0xffffffffu)];
+    s.tau[q] = t;
+  }
+}
+
+// ------------------------------------------------------------------ finalize (S7)
+__global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
+  __shared__ float qv[kMaxCodeBits];
+  __shared__ float td[kMaxK];
+  __shared__ int64_t tid[kMaxK];
+  __shared__ int32_t cpos[kWave];
+  __shared__ float cd[kWave];
+  __shared__ int sh_n, sh_cnt;
+  __shared__ float sh_tau;
+  const int64_t q = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int K = s.k;
+  for (int i = threadIdx.x; i < s.dim; i += kThreads) qv[i] = s.q[q * s.dim + i];
+  int cnt0 = 0;
+  for (int i = 0; i < K; ++i) {
+    const SeedEnt e = s.seedk[q * K + i];
+    if (e.pos < 0) break;
+    ++cnt0;
+  }
+  for (int i = threadIdx.x; i < K; i += kThreads) {
+    const SeedEnt e = s.seedk[q * K + i];
+    td[i] = e.dist;
+    tid[i] = e.pos >= 0 ? s.ids[e.pos] : (int64_t)-1;
+  }
+  if (threadIdx.x == 0) {
+    sh_cnt = cnt0;
+    sh_tau = (cnt0 == K) ? s.seedk[q * K + K - 1].dist : __builtin_inff();
+  }
+  __syncthreads();
+  cnt0 = uniform_i32(cnt0);
+  int reranked = cnt0;
+  int ncand_total = 0;
+  int P = s.nprobe;
+  if (s.nprobe_q) P = uniform_i32(min(max(s.nprobe_q[q], 1), s.nprobe));
+  const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
+  const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
+  const int64_t seg0 = uniform_i64(s.off_seg[q]);
+  const int64_t ch0 = uniform_i64(s.off_ch[q]);
+  for (int r = 0; r < P; ++r) {
+    const int nc = uniform_i32(choff[r + 1] - choff[r]);
+    for (int c = 0; c < nc; ++c) {
+      const int count = uniform_i32(s.seg_count[ch0 + choff[r] + c]);
+      const Cand* seg = s.seg + seg0 + codeoff[r] + (int64_t)c * s.chunk;
+      ncand_total += count;
+      for (int e0 = 0; e0 < count; e0 += kWave) {
+        if (wave == 0) {
+          const int e = e0 + lane;
+          bool pass = false;
+          Cand cand;
+          cand.pos = -1;
+          if (e < count) {
+            cand = seg[e];
+            pass = cand.pos >= 0 && cand.lb <= sh_tau;
+          }
+          const uint64_t m = __ballot(pass);
+          if (pass) cpos[__popcll(m & lanemask_lt())] = cand.pos;
+          if (lane == 0) sh_n = __popcll(m);
+        }
+        __syncthreads();
+        const int n = uniform_i32(sh_n);
+        if (n == 0) {
+          __syncthreads();
+          continue;
+        }
+        for (int i = wave; i < n; i += kWaves) {
+          const float d = exact_dist(s.raw, cpos[i], s.dim, qv);
+          if (lane == 0) cd[i] = d;
+        }
+        __syncthreads();
+        if (wave == 0) {
+          int cnt = uniform_i32(sh_cnt);
+          for (int i = 0; i < n; ++i) {
+            const float d = uniform_f32(cd[i]);
+            const int64_t id = uniform_i64(s.ids[cpos[i]]);
+            if (cnt == K && !less_di(d, id, td[K - 1], tid[K - 1])) continue;
+            // insertion position: entries that order before (d, id)
+            int before = 0;
+            for (int t = lane; t < cnt; t += kWave) before += less_di(td[t], tid[t], d, id);
+            before = wave_sum_i(before);
+            const int last = min(cnt, K - 1);   // entries [before, last) shift right by one
+            float sd[kMaxK / kWave];
+            int64_t si[kMaxK / kWave];
+#pragma unroll
+            for (int t = 0; t < kMaxK / kWave; ++t) {
+              const int x = lane + t * kWave;
+              if (x >= before && x < last) {
+                sd[t] = td[x];
+                si[t] = tid[x];
+              }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int t = 0; t < kMaxK / kWave; ++t) {
+              const int x = lane + t * kWave;
+              if (x >= before && x < last) {
+                td[x + 1] = sd[t];
+                tid[x + 1] = si[t];
+              }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+              td[before] = d;
+              tid[before] = id;
+            }
+            __builtin_amdgcn_wave_barrier();
+            cnt = min(cnt + 1, K);
+          }
+          if (lane == 0) {
+            sh_cnt = cnt;
+            if (cnt == K) sh_tau = fminf(sh_tau, td[K - 1]);
+          }
+        }
+        reranked += n;
+        __syncthreads();
+      }
+    }
+  }
+  const int cnt = uniform_i32(sh_cnt);
+  for (int i = threadIdx.x; i < K; i += kThreads) {
+    s.out_ids[q * K + i] = i < cnt ? tid[i] : (int64_t)-1;
+    s.out_d[q * K + i] = i < cnt ? td[i] : __builtin_inff();
+  }
+  if (threadIdx.x == 0) {
+    s.q_rerank[q] = reranked;
+    s.q_cand[q] = ncand_total;
+  }
+}
+
+// ------------------------------------------------------------------ debug
+__global__ void k_debug_pack(const uint8_t* __restrict__ qu, int dp, int W, float b, float vl,
+                             float delta, PairRec* rec, uint64_t* planes, int8_t* qu8,
+                             int32_t list) {
+  // one wave
+  const int lane = lane_id();
+  int sq = 0;
+  for (int t = 0; t < W; ++t) {
+    const int i = t * kWave + lane;
+    const int v = qu[i];
+    sq += v;
+    if (qu8) qu8[i] = (int8_t)v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t w = __ballot((v >> j) & 1);
+      if (lane == 0) planes[j * W + t] = w;
+    }
+  }
+  sq = wave_sum_i(sq);
+  if (lane == 0) {
+    const double rd = sqrt((double)dp);
+    PairRec r;
+    r.k1 = (float)(2.0 * (double)delta / rd);
+    r.k2 = (float)(2.0 * (double)vl / rd);
+    r.k0 = (float)(-((double)delta / rd) * (double)sq - rd * (double)vl);
+    r.b = b;
+    r.vl = vl;
+    r.delta = delta;
+    r.sq = sq;
+    r.list = list;
+    *rec = r;
+  }
+}
+
+template <int WS>
+__global__ __launch_bounds__(kThreads) void k_debug_scan(SearchDev s, const PairRec* recp,
+                                                         const uint64_t* planes, int32_t list,
+                                                         int32_t* ip_o, int32_t* pc_o, float* est_o,
+                                                         float* dist_o, float* lb_o) {
+  __shared__ uint64_t lds_planes[4 * (kMaxCodeBits / 64)];
+  const int64_t beg = uniform_i64(s.list_off[list]), end = uniform_i64(s.list_off[list + 1]);
+  const PairRec rec = *recp;
+  for (int i = threadIdx.x; i < 4 * s.W; i += blockDim.x) lds_planes[i] = planes[i];
+  __syncthreads();
+  Planes<WS> pl;
+  if constexpr (WS > 0) {
+    pl.load(planes, s.W);
+  } else {
+    pl.p = lds_planes;
+    pl.W = s.W;
+  }
+  const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
+  const int64_t p = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= end) return;
+  int ip, pc;
+  float est, dist, lb;
+  code_ip<WS>(s.codes, p, s.W, pl, ip, pc);
+  estimate(rec, s.fac[p], ip, pc, hwk, est, dist, lb);
+  const int64_t o = p - beg;
+  ip_o[o] = ip;
+  pc_o[o] = pc;
+  est_o[o] = est;
+  dist_o[o] = dist;
+  lb_o[o] = lb;
+}
+
+template <int WS>
+void launch_scan_ws(const SearchDev& s, int phase, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_popcnt<WS>, dim3(grid), dim3(kThreads), 0, st, s, phase);
+}
+
+}  // namespace
+
+hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st) {
+  const int64_t npairs = s.nq * s.nprobe;
+  if (npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((npairs + kWaves - 1) / kWaves)), dim3(kThreads), 0,
+                     st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
+  if (s.nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan, dim3((unsigned)((s.nq + 255) / 256)), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st) {
+  switch (s.W) {
+    case 1: launch_scan_ws<1>(s, phase, grid, st); break;
+    case 2: launch_scan_ws<2>(s, phase, grid, st); break;
+    case 3: launch_scan_ws<3>(s, phase, grid, st); break;
+    case 4: launch_scan_ws<4>(s, phase, grid, st); break;
+    default: launch_scan_ws<0>(s, phase, grid, st); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tau(const SearchDev& s, hipStream_t st) {
+  if (s.nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tau, dim3((unsigned)s.nq), dim3(kThreads), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const SearchDev& s, hipStream_t st) {
+  if (s.nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)s.nq), dim3(kThreads), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, float b, float vl, float delta,
+                             PairRec* rec, uint64_t* planes, int8_t* qu8, int32_t list,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_debug_pack, dim3(1), dim3(kWave), 0, st, qu, dp, W, b, vl, delta, rec,
+                     planes, qu8, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_scan(const SearchDev& s, const PairRec* rec, const uint64_t* planes,
+                             const int8_t* qu8, int32_t list, int kernel, int32_t* ip,
+                             int32_t* pc, float* est, float* dist, float* lb, hipStream_t st) {
+  int n = 0;
+  {
+    int32_t off[2];
+    hipError_t e = hipMemcpy(off, s.list_off + list, sizeof(off), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    n = off[1] - off[0];
+  }
+  if (n == 0) return hipSuccess;
+  if (kernel == 2)
+    return launch_debug_mfma(s, rec, qu8, list, (n + s.chunk - 1) / s.chunk, ip, pc, est, dist, lb, st);
+  const dim3 grid((n + kThreads - 1) / kThreads);
+  switch (s.W) {
+    case 2:
+      hipLaunchKernelGGL(k_debug_scan<2>, grid, dim3(kThreads), 0, st, s, rec, planes, list, ip, pc,
+                         est, dist, lb);
+      break;
+    default:
+      hipLaunchKernelGGL(k_debug_scan<0>, grid, dim3(kThreads), 0, st, s, rec, planes, list, ip, pc,
+                         est, dist, lb);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rbq
+
+namespace rbq {
+namespace {
+__global__ void k_pairs_to_scal(const PairRec* __restrict__ pairs, int64_t n, float* __restrict__ scal) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const PairRec r = pairs[i];
+  scal[i * 4 + 0] = r.b;
+  scal[i * 4 + 1] = r.vl;
+  scal[i * 4 + 2] = r.delta;
+  scal[i * 4 + 3] = (float)r.sq;
+}
+}  // namespace
+hipError_t launch_pairs_to_scal(const SearchDev& s, float* scal, hipStream_t st) {
+  const int64_t n = s.nq * s.nprobe;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pairs_to_scal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.pairs, n, scal);
+  return hipGetLastError();
+}
+}  // namespace rbq
+
+namespace rbq {
+namespace {
+__global__ void k_profile_accum(const int64_t* __restrict__ off_seg, const int64_t* __restrict__ off_n0,
+                                int64_t nq, unsigned long long* __restrict__ acc) {
+  if (threadIdx.x == 0) {
+    atomicAdd(&acc[0], (unsigned long long)off_n0[nq]);
+    atomicAdd(&acc[1], (unsigned long long)(off_seg[nq] - off_n0[nq]));
+  }
+}
+}  // namespace
+hipError_t launch_profile_accum(const SearchDev& s, unsigned long long* acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_profile_accum, dim3(1), dim3(64), 0, st, s.off_seg, s.off_n0, s.nq, acc);
+  return hipGetLastError();
+}
+}  // namespace rbq

@@ -1,0 +1,222 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+namespace rbq {
+
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kMaxK = 256;         // largest k returned by a search
+constexpr int kMaxNprobe = 1024;
+constexpr int kMaxCodeBits = 4096;
+constexpr int kDefaultChunk = 1024;  // codes per scan work unit
+constexpr int kMaxP0 = 2048;       // bootstrap codes per query: k - 1 + chunk <= kMaxP0
+
+// Per (query, probed list) constants of the quantised query (Sec. 3.3.1-3.3.2).
+// <x_bar, q_bar> = k1 * <x_b, q_u> + k2 * popcount(x_b) + k0
+struct PairRec {
+  float k1, k2, k0;
+  float b;        // ||q_r - c||
+  float vl;       // v_l
+  float delta;    // Delta
+  int32_t sq;     // sum of q_u
+  int32_t list;   // list id (-1: unused slot)
+};
+
+// Rerank candidate written by the scan: position in list order + lower bound.
+struct Cand {
+  int32_t pos;
+  float lb;
+};
+
+// Bootstrap entry: estimated distance + slot in the query's segment space.
+struct EstEnt {
+  float dist;
+  int32_t slot;
+};
+
+struct SeedEnt {
+  float dist;
+  int32_t pos;
+};
+
+// ------------------------------------------------------------------ device helpers
+#if defined(__HIPCC__)
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Value of the first active lane, as a wave-uniform (scalar) value. Every loop
+// bound or exit test that encloses cross-lane operations or barriers goes
+// through these, so the compiler emits uniform control flow for it (a loop whose
+// exit it believes divergent may be split per lane, which strands lanes that
+// wait on a cross-lane read).
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float uniform_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// SplitMix64 output for state x (Steele, Lea & Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Uniform in [0,1) with 24 bits for coordinate i of the (query, list) pair.
+__device__ __forceinline__ float rounding_u(uint64_t seed, uint64_t qid, uint32_t list, uint32_t i) {
+  const uint64_t key = seed ^ ((qid << 40) + ((uint64_t)list << 12) + (uint64_t)i);
+  return (float)(uint32_t)(splitmix64(key) >> 40) * (1.0f / 16777216.0f);
+}
+
+// Interleaved code layout: for position p (list order), 64-bit word w lives at
+// codes[((p >> 6) * W + w) * 64 + (p & 63)], so word w of 64 consecutive codes
+// is one contiguous 512-byte row.
+__device__ __forceinline__ size_t code_word_index(int64_t p, int w, int W) {
+  return ((size_t)(p >> 6) * W + w) * 64 + (size_t)(p & 63);
+}
+
+#endif  // __HIPCC__
+
+// ------------------------------------------------------------------ launchers
+// (defined in the .hip files; all take a hipStream_t and return hipError_t of the launch)
+
+// Y[M x N] = (A[M x K] - C[sel[m]]) * B[K x N]   (A row stride lda; B row stride ldb)
+// sel == nullptr: no subtraction. FP32 FMA tiles.
+hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* sub, const int32_t* sel,
+                           const float* B, int64_t ldb, float* Y, int64_t ldy, int64_t M, int N,
+                           int K, hipStream_t st);
+// Same product with split-BF16 MFMA: Bhi/Blo are [K x N] BF16 (stored as uint16).
+hipError_t launch_gemm_bf16x3(const float* A, int64_t lda, const float* sub, const int32_t* sel,
+                              const uint16_t* Bhi, const uint16_t* Blo, float* Y, int64_t ldy,
+                              int64_t M, int N, int K, hipStream_t st);
+// D[b][k] = ||q_b||^2 + cn[k] - 2 <q_b, c_k>, clamped at 0 (Ct is [K x nlist]).
+hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float* Ct,
+                                const float* cn, int nlist, float* D, hipStream_t st);
+// FP64 product of rows with P: Y[M x N] = X[M x K] * P[K x N] (stored as FP32).
+hipError_t launch_rotate_f64(const float* X, int64_t M, int K, const double* P, int N, float* Y,
+                             hipStream_t st);
+
+hipError_t launch_encode(const float* Y, int64_t m, int W, const float* raw, const float* cent,
+                         const int32_t* list_of, int dim, int64_t pos0, uint64_t* codes,
+                         float2* fac, hipStream_t st);
+
+hipError_t launch_select_probe(const float* D, int64_t nq, int nlist, int nprobe,
+                               const int32_t* nprobe_q, int32_t* lists, float* dists,
+                               hipStream_t st);
+
+struct SearchDev {
+  // index
+  const uint64_t* codes;
+  const float2* fac;        // {||o_r - c||, <o_bar,o>}
+  const float* raw;         // list order
+  const int64_t* ids;       // list order -> original id
+  const int32_t* list_off;  // nlist + 1
+  const float* cent;        // nlist x dim
+  const float* crot;        // nlist x Dp (P^T c_k)
+  int dim, dp, W, nlist;
+  float eps0;
+  uint64_t seed;
+  // batch
+  const float* q;           // nq x dim
+  const float* qrot;        // nq x Dp
+  int64_t nq;
+  int64_t qid_base;
+  int nprobe;               // row stride of per-pair arrays
+  int k;
+  int chunk;                // codes per work unit
+  const int32_t* probe;     // nq x nprobe
+  const int32_t* nprobe_q;  // nq or null
+  // per pair
+  PairRec* pairs;           // nq x nprobe
+  uint64_t* planes;         // nq x nprobe x 4 x W
+  int8_t* qu8;              // nq x nprobe x Dp (MFMA path) or null
+  int32_t* pair_choff;      // nq x (nprobe+1) local chunk prefix
+  int32_t* pair_codeoff;    // nq x (nprobe+1) local code prefix
+  // per query
+  int32_t* q_nch;           // chunks
+  int32_t* q_p0;            // bootstrap chunks
+  int32_t* q_n0;            // bootstrap codes
+  int64_t* q_ncode;         // probed codes
+  int64_t* off_ch;          // nq+1 exclusive prefix of q_nch
+  int64_t* off_p0;          // nq+1 prefix of q_p0
+  int64_t* off_p1;          // nq+1 prefix of q_nch - q_p0
+  int64_t* off_seg;         // nq+1 prefix of q_ncode
+  int64_t* off_n0;          // nq+1 prefix of q_n0
+  unsigned long long* counters;  // work counters: [0] bootstrap scan, [1] main scan, [2] MFMA scan
+  // buffers
+  Cand* seg;                // segment slots
+  int32_t* seg_count;       // per chunk
+  EstEnt* p0buf;
+  float* tau;               // nq
+  SeedEnt* seedk;           // nq x k
+  int32_t* q_rerank;        // nq
+  int32_t* q_cand;          // nq
+  // MFMA grouping of main-phase pairs by list
+  int32_t* mf_cnt;          // nlist: pairs per list
+  int32_t* mf_fill;         // nlist: scatter cursors
+  int64_t* mf_pair_off;     // nlist + 1
+  int64_t* mf_unit_off;     // nlist + 1: (chunk, 16-pair group) units per list
+  int32_t* mf_pairs;        // pair ids bucketed by list
+  // outputs
+  int64_t* out_ids;
+  float* out_d;
+};
+
+hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st);
+hipError_t launch_plan(const SearchDev& s, hipStream_t st);
+hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st);
+hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t st);
+hipError_t launch_tau(const SearchDev& s, hipStream_t st);
+hipError_t launch_finalize(const SearchDev& s, hipStream_t st);
+
+// debug: list scan with a given quantised query
+hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, float b, float vl, float delta,
+                             PairRec* rec, uint64_t* planes, int8_t* qu8, int32_t list,
+                             hipStream_t st);
+hipError_t launch_debug_mfma(const SearchDev& s, const PairRec* rec, const int8_t* qu8,
+                             int32_t list, int nchunks, int32_t* ip, int32_t* pc, float* est,
+                             float* dist, float* lb, hipStream_t st);
+hipError_t launch_debug_scan(const SearchDev& s, const PairRec* rec, const uint64_t* planes,
+                             const int8_t* qu8, int32_t list, int kernel, int32_t* ip,
+                             int32_t* pc, float* est, float* dist, float* lb, hipStream_t st);
+
+}  // namespace rbq

@@ -1,0 +1,114 @@
+// Host-side index object and workspace (runtime.cpp, mlp_runtime.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rabitq.h"
+#include "rbq_internal.hpp"
+
+namespace rbq {
+
+// Device buffer that grows on demand and is freed with its owner.
+struct DBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes);
+  void release();
+};
+
+hipError_t dmalloc(void** p, size_t bytes);
+bool is_device_ptr(const void* p);
+uint64_t host_splitmix64(uint64_t x);
+
+struct Workspace {
+  DBuf qrot, cd, probe, probe_d, pairs, planes, qu8, pair_choff, pair_codeoff;
+  DBuf q_nch, q_p0, q_n0, q_ncode, offs, counters, seg, seg_count, p0buf, tau, seedk;
+  DBuf q_rerank, q_cand, nprobe_q, feats, tmp;
+  DBuf mf_cnt, mf_fill, mf_pair_off, mf_unit_off, mf_pairs;
+};
+
+struct ProfState {
+  bool on = false;
+  int64_t searches = 0;
+  // per search: 7 events delimiting front, prep, scan0, tau, scan1, finalize
+  std::vector<hipEvent_t> events;
+  DBuf acc;    // int64 [2]: codes of scan0, scan1
+  void clear();
+};
+
+struct MlpState {
+  bool has_model = false;
+  float threshold = 0.9f;
+  std::vector<float> host_w;   // FP32 weights, rbq_nprobe_model_set order
+  DBuf w32, wbf, grad, m, v, act;
+};
+
+// MFMA scan availability (kernels_mfma.hip).
+bool mfma_available();
+hipError_t launch_pairs_to_scal(const SearchDev& s, float* scal, hipStream_t st);
+hipError_t launch_profile_accum(const SearchDev& s, unsigned long long* acc, hipStream_t st);
+
+}  // namespace rbq
+
+struct rbq_index {
+  rbq_params prm{};
+  int dim = 0, dp = 0, W = 0, nlist = 0;
+  int64_t n = 0;
+  bool built = false;
+  int64_t device_bytes = 0;
+  std::mutex mu;
+  hipEvent_t done_event = nullptr;
+
+  // host copies
+  std::vector<double> h_P;          // dp x dp
+  std::vector<float> h_cent;        // nlist x dim
+  std::vector<int64_t> h_list_off;  // nlist + 1
+  std::vector<int64_t> h_ids;       // position -> original id
+  std::vector<int64_t> sizes_desc, codes_prefix;
+
+  // device index
+  rbq::DBuf d_codes, d_fac, d_raw, d_ids, d_list_off, d_cent, d_centT, d_cnorm, d_crot;
+  rbq::DBuf d_P32, d_Phi, d_Plo;
+
+  rbq::Workspace ws;
+  rbq::MlpState mlp;
+  rbq::ProfState prof;
+
+  // autotuned choices
+  int tuned_chunk = 0;
+  int tuned_kernel_small = RBQ_SCAN_POPCNT;   // for batches below tuned_batch_split
+  int tuned_kernel_large = RBQ_SCAN_POPCNT;
+  int64_t tuned_batch_split = 0;
+
+  ~rbq_index();
+  std::vector<rbq::DBuf*> all_buffers();
+  int64_t max_codes(int nprobe) const;
+  int64_t max_chunks(int nprobe, int chunk) const;
+  void graphs_clear() {}
+  int pick_kernel(int64_t nq, int nprobe) const {
+    (void)nprobe;
+    if (!rbq::mfma_available()) return RBQ_SCAN_POPCNT;
+    return nq >= tuned_batch_split && tuned_batch_split > 0 ? tuned_kernel_large : tuned_kernel_small;
+  }
+};
+
+namespace rbq {
+rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int nprobe_max,
+                          int64_t qid_base, hipStream_t st, const int32_t** out);
+rbq_status rotate_rows(rbq_index* idx, const float* X, int64_t lda, const float* sub,
+                       const int32_t* sel, int64_t M, float* Y, hipStream_t st);
+rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma);
+SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe, int k, int chunk,
+                   const int32_t* nprobe_q, int64_t qid_base, bool mfma, int64_t* out_ids,
+                   float* out_d);
+rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
+                 const int32_t* nprobe_q, hipStream_t st);
+rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& o,
+                      int scan_kernel, int chunk, const int32_t* nprobe_q, int64_t* out_ids,
+                      float* out_d, hipStream_t st);
+}  // namespace rbq

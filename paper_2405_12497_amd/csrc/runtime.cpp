@@ -1,0 +1,1008 @@
+// Host runtime behind the C ABI of include/rabitq.h: index construction
+// (Algorithm 1), search orchestration (Algorithm 2 + the Sec. 4 rerank),
+// workspace management, persistence and the debug exports.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/rabitq.h"
+#include "rbq_internal.hpp"
+#include "rbq_runtime.hpp"
+
+using namespace rbq;
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_err;
+
+rbq_status fail(rbq_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+}  // namespace
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      (void)hipGetLastError();                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? RBQ_ENOMEM : RBQ_EDEVICE, "%s: %s (%s:%d)", #expr, \
+                  hipGetErrorString(e_), __FILE__, __LINE__);                                 \
+    }                                                                                         \
+  } while (0)
+
+namespace rbq {
+
+// test hook: make the n-th following device allocation fail (0 = off)
+static int g_fail_alloc_after = 0;
+
+hipError_t dmalloc(void** p, size_t bytes) {
+  if (g_fail_alloc_after > 0 && --g_fail_alloc_after == 0) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  if (bytes == 0) bytes = 16;
+  return hipMalloc(p, bytes);
+}
+
+hipError_t DBuf::ensure(size_t bytes) {
+  if (bytes <= cap) return hipSuccess;
+  release();
+  size_t want = std::max<size_t>(bytes, 256);
+  hipError_t e = dmalloc(&p, want);
+  if (e != hipSuccess) {
+    p = nullptr;
+    cap = 0;
+    return e;
+  }
+  cap = want;
+  return hipSuccess;
+}
+
+void DBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+bool is_device_ptr(const void* ptr) {
+  if (!ptr) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+uint64_t host_splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace rbq
+
+// ------------------------------------------------------------------ helpers
+namespace {
+
+uint16_t f2bf_host(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf2f_host(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Standard Gaussian draws from the seed (used only when the caller gives no
+// matrix): SplitMix64 counter stream -> Box-Muller.
+void gaussian_from_seed(uint64_t seed, int dp, std::vector<double>& g) {
+  g.resize((size_t)dp * dp);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (size_t i = 0; i < g.size(); i += 2) {
+    const uint64_t a = host_splitmix64(seed ^ (0x5052000000000000ull + 2 * i));
+    const uint64_t b = host_splitmix64(seed ^ (0x5052000000000000ull + 2 * i + 1));
+    const double u1 = ((double)(a >> 11) + 1.0) * (1.0 / 9007199254740992.0);   // (0, 1]
+    const double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);
+    const double r = std::sqrt(-2.0 * std::log(u1));
+    g[i] = r * std::cos(two_pi * u2);
+    if (i + 1 < g.size()) g[i + 1] = r * std::sin(two_pi * u2);
+  }
+}
+
+// Rows of G orthonormalised in order (Gram-Schmidt, as the random rotation is
+// built in Appendix B), each projection applied twice for numerical
+// orthogonality. Returns false if a row is (numerically) dependent.
+bool orthonormalise_rows(std::vector<double>& p, int d) {
+  for (int i = 0; i < d; ++i) {
+    double* pi = &p[(size_t)i * d];
+    const double n0 = std::sqrt(std::inner_product(pi, pi + d, pi, 0.0));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j < i; ++j) {
+        const double* pj = &p[(size_t)j * d];
+        const double c = std::inner_product(pi, pi + d, pj, 0.0);
+        for (int t = 0; t < d; ++t) pi[t] -= c * pj[t];
+      }
+    }
+    const double nrm = std::sqrt(std::inner_product(pi, pi + d, pi, 0.0));
+    if (!(nrm > 1e-10 * n0) || !std::isfinite(nrm)) return false;
+    for (int t = 0; t < d; ++t) pi[t] /= nrm;
+  }
+  return true;
+}
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+  const unsigned char* c = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 0x100000001B3ull;
+  }
+  return h;
+}
+
+int device_cu_count() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) == hipSuccess) cus = pr.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+rbq_status check_params(const rbq_params* p) {
+  if (!p) return fail(RBQ_EINVAL, "params is NULL");
+  if (p->dim < 1 || p->dim > kMaxCodeBits) return fail(RBQ_EINVAL, "dim %d out of range [1, %d]", p->dim, kMaxCodeBits);
+  if (p->code_bits != 0 && (p->code_bits % 64 != 0 || p->code_bits < p->dim || p->code_bits > kMaxCodeBits))
+    return fail(RBQ_EINVAL, "code_bits %d must be 0 or a multiple of 64 in [dim, %d]", p->code_bits, kMaxCodeBits);
+  if (p->nlist < 1 || p->nlist > (1 << 20)) return fail(RBQ_EINVAL, "nlist %d out of range", p->nlist);
+  if (p->bq != 4) return fail(RBQ_EUNSUPPORTED, "bq=%d: only 4-bit queries are implemented", p->bq);
+  if (!(p->eps0 >= 0.f) || !std::isfinite(p->eps0)) return fail(RBQ_EINVAL, "eps0 must be finite and >= 0");
+  if (p->rot_precision != RBQ_ROT_FP32 && p->rot_precision != RBQ_ROT_BF16X3)
+    return fail(RBQ_EINVAL, "unknown rot_precision %d", p->rot_precision);
+  return RBQ_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ index object
+rbq_index::~rbq_index() {
+  prof.clear();
+  prof.acc.release();
+  for (DBuf* b : all_buffers()) b->release();
+  if (done_event) (void)hipEventDestroy(done_event);
+}
+
+std::vector<DBuf*> rbq_index::all_buffers() {
+  return {&d_codes, &d_fac, &d_raw, &d_ids, &d_list_off, &d_cent, &d_centT, &d_cnorm, &d_crot,
+          &d_P32, &d_Phi, &d_Plo, &ws.qrot, &ws.cd, &ws.probe, &ws.probe_d, &ws.pairs,
+          &ws.planes, &ws.qu8, &ws.pair_choff, &ws.pair_codeoff, &ws.q_nch, &ws.q_p0, &ws.q_n0,
+          &ws.q_ncode, &ws.offs, &ws.counters, &ws.seg, &ws.seg_count, &ws.p0buf, &ws.tau,
+          &ws.seedk, &ws.q_rerank, &ws.q_cand, &ws.nprobe_q, &ws.feats, &ws.tmp,
+          &ws.mf_cnt, &ws.mf_fill, &ws.mf_pair_off, &ws.mf_unit_off, &ws.mf_pairs,
+          &mlp.w32, &mlp.wbf, &mlp.grad, &mlp.m, &mlp.v, &mlp.act};
+}
+
+int64_t rbq_index::max_codes(int nprobe) const {
+  const int p = std::min<int>(nprobe, (int)sizes_desc.size());
+  return p > 0 ? codes_prefix[p - 1] : 0;
+}
+
+int64_t rbq_index::max_chunks(int nprobe, int chunk) const {
+  int64_t s = 0;
+  const int p = std::min<int>(nprobe, (int)sizes_desc.size());
+  for (int i = 0; i < p; ++i) s += (sizes_desc[i] + chunk - 1) / chunk;
+  return s;
+}
+
+extern "C" {
+
+const char* rbq_last_error(void) { return g_err.c_str(); }
+
+rbq_status rbq_params_default(rbq_params* p, int32_t dim, int32_t nlist) {
+  if (!p) return fail(RBQ_EINVAL, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->dim = dim;
+  p->code_bits = 0;
+  p->nlist = nlist;
+  p->bq = 4;
+  p->eps0 = 1.9f;
+  p->rot_precision = RBQ_ROT_FP32;
+  p->seed = 0;
+  return RBQ_OK;
+}
+
+rbq_status rbq_index_create(const rbq_params* p, rbq_index** out) {
+  if (!out) return fail(RBQ_EINVAL, "out is NULL");
+  rbq_status st = check_params(p);
+  if (st != RBQ_OK) return st;
+  rbq_index* idx = new (std::nothrow) rbq_index();
+  if (!idx) return fail(RBQ_ENOMEM, "host allocation failed");
+  idx->prm = *p;
+  idx->dim = p->dim;
+  idx->dp = p->code_bits ? p->code_bits : 64 * ((p->dim + 63) / 64);
+  idx->W = idx->dp / 64;
+  idx->nlist = p->nlist;
+  *out = idx;
+  return RBQ_OK;
+}
+
+rbq_status rbq_index_destroy(rbq_index* idx) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  delete idx;
+  return RBQ_OK;
+}
+
+rbq_status rbq_index_info_get(const rbq_index* idx, rbq_index_info* out) {
+  if (!idx || !out) return fail(RBQ_EINVAL, "NULL argument");
+  out->dim = idx->dim;
+  out->code_bits = idx->dp;
+  out->nlist = idx->nlist;
+  out->rot_precision = idx->prm.rot_precision;
+  out->n = idx->n;
+  out->device_bytes = idx->device_bytes;
+  return RBQ_OK;
+}
+
+rbq_status rbq_index_list_sizes(const rbq_index* idx, int64_t* sizes) {
+  if (!idx || !sizes) return fail(RBQ_EINVAL, "NULL argument");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  for (int k = 0; k < idx->nlist; ++k) sizes[k] = idx->h_list_off[k + 1] - idx->h_list_off[k];
+  return RBQ_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ build
+namespace rbq {
+
+// Uploads P-derived tensors and centroid tensors; assumes h_P, h_cent set.
+rbq_status upload_model(rbq_index* idx, hipStream_t st) {
+  const int D = idx->dim, dp = idx->dp, L = idx->nlist;
+  // P restricted to the first D rows: [D x dp] (rows of a zero-padded vector beyond D add nothing)
+  std::vector<float> p32((size_t)D * dp);
+  std::vector<uint16_t> phi((size_t)dp * D), plo((size_t)dp * D);
+  for (int k = 0; k < D; ++k)
+    for (int n = 0; n < dp; ++n) {
+      const float v = (float)idx->h_P[(size_t)k * dp + n];
+      p32[(size_t)k * dp + n] = v;
+      const uint16_t h = f2bf_host(v);
+      phi[(size_t)n * D + k] = h;
+      plo[(size_t)n * D + k] = f2bf_host(v - bf2f_host(h));
+    }
+  HIPCHK(idx->d_P32.ensure(p32.size() * 4));
+  HIPCHK(idx->d_Phi.ensure(phi.size() * 2));
+  HIPCHK(idx->d_Plo.ensure(plo.size() * 2));
+  HIPCHK(hipMemcpyAsync(idx->d_P32.p, p32.data(), p32.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(idx->d_Phi.p, phi.data(), phi.size() * 2, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(idx->d_Plo.p, plo.data(), plo.size() * 2, hipMemcpyHostToDevice, st));
+  // centroids, transposed centroids, squared norms
+  std::vector<float> ct((size_t)D * L), cn(L);
+  for (int k = 0; k < L; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < D; ++i) {
+      const float v = idx->h_cent[(size_t)k * D + i];
+      ct[(size_t)i * L + k] = v;
+      s += (double)v * v;
+    }
+    cn[k] = (float)s;
+  }
+  HIPCHK(idx->d_cent.ensure((size_t)L * D * 4));
+  HIPCHK(idx->d_centT.ensure((size_t)L * D * 4));
+  HIPCHK(idx->d_cnorm.ensure((size_t)L * 4));
+  HIPCHK(idx->d_crot.ensure((size_t)L * dp * 4));
+  HIPCHK(hipMemcpyAsync(idx->d_cent.p, idx->h_cent.data(), (size_t)L * D * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(idx->d_centT.p, ct.data(), ct.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(idx->d_cnorm.p, cn.data(), cn.size() * 4, hipMemcpyHostToDevice, st));
+  // P^T c_k in FP64 on the device, stored as FP32
+  DBuf p64;
+  HIPCHK(p64.ensure((size_t)D * dp * 8));
+  HIPCHK(hipMemcpyAsync(p64.p, idx->h_P.data(), (size_t)D * dp * 8, hipMemcpyHostToDevice, st));
+  for (int k0 = 0; k0 < L; k0 += 32768) {
+    const int m = std::min(32768, L - k0);
+    HIPCHK(launch_rotate_f64((const float*)idx->d_cent.p + (size_t)k0 * D, m, D,
+                             (const double*)p64.p, dp, (float*)idx->d_crot.p + (size_t)k0 * dp, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  p64.release();
+  std::vector<int32_t> lo(L + 1);
+  for (int k = 0; k <= L; ++k) lo[k] = (int32_t)idx->h_list_off[k];
+  HIPCHK(idx->d_list_off.ensure(lo.size() * 4));
+  HIPCHK(hipMemcpyAsync(idx->d_list_off.p, lo.data(), lo.size() * 4, hipMemcpyHostToDevice, st));
+  // bounds for workspace sizing
+  idx->sizes_desc.resize(L);
+  for (int k = 0; k < L; ++k) idx->sizes_desc[k] = idx->h_list_off[k + 1] - idx->h_list_off[k];
+  std::sort(idx->sizes_desc.begin(), idx->sizes_desc.end(), std::greater<int64_t>());
+  idx->codes_prefix.resize(L);
+  int64_t run = 0;
+  for (int k = 0; k < L; ++k) idx->codes_prefix[k] = (run += idx->sizes_desc[k]);
+  HIPCHK(hipStreamSynchronize(st));
+  return RBQ_OK;
+}
+
+rbq_status rotate_rows(rbq_index* idx, const float* X, int64_t lda, const float* sub,
+                       const int32_t* sel, int64_t M, float* Y, hipStream_t st) {
+  if (idx->prm.rot_precision == RBQ_ROT_BF16X3) {
+    HIPCHK(launch_gemm_bf16x3(X, lda, sub, sel, (const uint16_t*)idx->d_Phi.p,
+                              (const uint16_t*)idx->d_Plo.p, Y, idx->dp, M, idx->dp, idx->dim, st));
+  } else {
+    HIPCHK(launch_gemm_f32(X, lda, sub, sel, (const float*)idx->d_P32.p, idx->dp, Y, idx->dp, M,
+                           idx->dp, idx->dim, st));
+  }
+  return RBQ_OK;
+}
+
+void account_bytes(rbq_index* idx) {
+  int64_t b = 0;
+  for (DBuf* d : {&idx->d_codes, &idx->d_fac, &idx->d_raw, &idx->d_ids, &idx->d_list_off,
+                  &idx->d_cent, &idx->d_centT, &idx->d_cnorm, &idx->d_crot, &idx->d_P32,
+                  &idx->d_Phi, &idx->d_Plo})
+    b += (int64_t)d->cap;
+  idx->device_bytes = b;
+}
+
+}  // namespace rbq
+
+extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t n,
+                                      const float* centroids, const int32_t* assign,
+                                      const double* gauss, void* stream) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!data || !centroids || !assign) return fail(RBQ_EINVAL, "data, centroids and assign are required");
+  if (is_device_ptr(data) || is_device_ptr(centroids) || is_device_ptr(assign) ||
+      (gauss && is_device_ptr(gauss)))
+    return fail(RBQ_EINVAL, "rbq_index_build takes host pointers");
+  if (n < 1 || n > (int64_t)INT32_MAX - 64) return fail(RBQ_EINVAL, "n=%lld out of range", (long long)n);
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  const int D = idx->dim, dp = idx->dp, L = idx->nlist, W = idx->W;
+  // list layout (counting sort, stable in the original id)
+  std::vector<int64_t> off(L + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t a = assign[i];
+    if (a < 0 || a >= L) return fail(RBQ_EINVAL, "assign[%lld]=%d outside [0, %d)", (long long)i, a, L);
+    off[a + 1]++;
+  }
+  for (int k = 0; k < L; ++k) off[k + 1] += off[k];
+  std::vector<int64_t> ids(n);
+  {
+    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+    for (int64_t i = 0; i < n; ++i) ids[fill[assign[i]]++] = i;
+  }
+  // rotation P
+  std::vector<double> P;
+  if (gauss) {
+    P.assign(gauss, gauss + (size_t)dp * dp);
+  } else {
+    gaussian_from_seed(idx->prm.seed, dp, P);
+  }
+  for (double v : P)
+    if (!std::isfinite(v)) return fail(RBQ_EINVAL, "gauss has non-finite entries");
+  if (!orthonormalise_rows(P, dp)) return fail(RBQ_EINVAL, "gauss is rank deficient");
+  // release an old build
+  idx->built = false;
+  for (DBuf* b : idx->all_buffers()) b->release();
+  idx->graphs_clear();
+  idx->h_P.swap(P);
+  idx->h_cent.assign(centroids, centroids + (size_t)L * D);
+  idx->h_list_off = off;
+  idx->h_ids = ids;
+  idx->n = n;
+  rbq_status rs = upload_model(idx, st);
+  if (rs != RBQ_OK) return rs;
+  const int64_t npad = (n + 63) / 64 * 64;
+  HIPCHK(idx->d_codes.ensure((size_t)npad * W * 8));
+  HIPCHK(idx->d_fac.ensure((size_t)npad * sizeof(float2)));
+  HIPCHK(idx->d_raw.ensure((size_t)n * D * 4));
+  HIPCHK(idx->d_ids.ensure((size_t)n * 8));
+  HIPCHK(hipMemsetAsync(idx->d_codes.p, 0, (size_t)npad * W * 8, st));
+  HIPCHK(hipMemsetAsync(idx->d_fac.p, 0, (size_t)npad * sizeof(float2), st));
+  HIPCHK(hipMemcpyAsync(idx->d_ids.p, ids.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
+  DBuf listof;
+  HIPCHK(listof.ensure((size_t)n * 4));
+  {
+    std::vector<int32_t> lof(n);
+    for (int k = 0; k < L; ++k)
+      for (int64_t p = off[k]; p < off[k + 1]; ++p) lof[p] = k;
+    HIPCHK(hipMemcpy(listof.p, lof.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+  }
+  // raw vectors in list order, staged in blocks
+  {
+    const int64_t blk = std::max<int64_t>(1, (int64_t)(64ll << 20) / ((int64_t)D * 4));
+    std::vector<float> stage((size_t)std::min(blk, n) * D);
+    for (int64_t p0 = 0; p0 < n; p0 += blk) {
+      const int64_t m = std::min(blk, n - p0);
+      for (int64_t r = 0; r < m; ++r)
+        std::memcpy(&stage[(size_t)r * D], data + (size_t)ids[p0 + r] * D, (size_t)D * 4);
+      HIPCHK(hipMemcpy((float*)idx->d_raw.p + (size_t)p0 * D, stage.data(), (size_t)m * D * 4,
+                       hipMemcpyHostToDevice));
+    }
+  }
+  // rotate residuals and encode, in blocks of rows
+  {
+    const int64_t blk = std::max<int64_t>(64, std::min<int64_t>(n, (int64_t)(256ll << 20) / ((int64_t)dp * 4)));
+    DBuf y;
+    HIPCHK(y.ensure((size_t)blk * dp * 4));
+    for (int64_t p0 = 0; p0 < n; p0 += blk) {
+      const int64_t m = std::min(blk, n - p0);
+      rs = rotate_rows(idx, (const float*)idx->d_raw.p + (size_t)p0 * D, D, (const float*)idx->d_cent.p,
+                       (const int32_t*)listof.p + p0, m, (float*)y.p, st);
+      if (rs != RBQ_OK) return rs;
+      HIPCHK(launch_encode((const float*)y.p, m, W, (const float*)idx->d_raw.p, (const float*)idx->d_cent.p,
+                           (const int32_t*)listof.p, D, p0, (uint64_t*)idx->d_codes.p,
+                           (float2*)idx->d_fac.p, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  account_bytes(idx);
+  idx->built = true;
+  return RBQ_OK;
+}
+
+// ------------------------------------------------------------------ search
+namespace rbq {
+
+rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma) {
+  Workspace& w = idx->ws;
+  const int dp = idx->dp, W = idx->W;
+  const int64_t np = nq * nprobe;
+  HIPCHK(w.qrot.ensure((size_t)nq * dp * 4));
+  HIPCHK(w.cd.ensure((size_t)nq * ((size_t)idx->nlist + 1) * 4));
+  HIPCHK(w.probe.ensure((size_t)np * 4));
+  HIPCHK(w.probe_d.ensure((size_t)np * 4));
+  HIPCHK(w.pairs.ensure((size_t)np * sizeof(PairRec)));
+  HIPCHK(w.planes.ensure((size_t)np * 4 * W * 8));
+  if (mfma) {
+    HIPCHK(w.qu8.ensure((size_t)np * dp));
+    HIPCHK(w.mf_cnt.ensure((size_t)idx->nlist * 4));
+    HIPCHK(w.mf_fill.ensure((size_t)idx->nlist * 4));
+    HIPCHK(w.mf_pair_off.ensure((size_t)(idx->nlist + 1) * 8));
+    HIPCHK(w.mf_unit_off.ensure((size_t)(idx->nlist + 1) * 8));
+    HIPCHK(w.mf_pairs.ensure((size_t)np * 4));
+  }
+  HIPCHK(w.pair_choff.ensure((size_t)nq * (nprobe + 1) * 4));
+  HIPCHK(w.pair_codeoff.ensure((size_t)nq * (nprobe + 1) * 4));
+  HIPCHK(w.q_nch.ensure((size_t)nq * 4));
+  HIPCHK(w.q_p0.ensure((size_t)nq * 4));
+  HIPCHK(w.q_n0.ensure((size_t)nq * 4));
+  HIPCHK(w.q_ncode.ensure((size_t)nq * 8));
+  HIPCHK(w.offs.ensure((size_t)5 * (nq + 1) * 8));
+  HIPCHK(w.counters.ensure(64));
+  HIPCHK(w.seg.ensure((size_t)nq * std::max<int64_t>(1, idx->max_codes(nprobe)) * sizeof(Cand)));
+  HIPCHK(w.seg_count.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
+  HIPCHK(w.p0buf.ensure((size_t)nq * (k - 1 + chunk) * sizeof(EstEnt)));
+  HIPCHK(w.tau.ensure((size_t)nq * 4));
+  HIPCHK(w.seedk.ensure((size_t)nq * k * sizeof(SeedEnt)));
+  HIPCHK(w.q_rerank.ensure((size_t)nq * 4));
+  HIPCHK(w.q_cand.ensure((size_t)nq * 4));
+  return RBQ_OK;
+}
+
+SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe, int k, int chunk,
+                   const int32_t* nprobe_q, int64_t qid_base, bool mfma, int64_t* out_ids,
+                   float* out_d) {
+  Workspace& w = idx->ws;
+  SearchDev s;
+  std::memset(&s, 0, sizeof(s));
+  s.codes = (const uint64_t*)idx->d_codes.p;
+  s.fac = (const float2*)idx->d_fac.p;
+  s.raw = (const float*)idx->d_raw.p;
+  s.ids = (const int64_t*)idx->d_ids.p;
+  s.list_off = (const int32_t*)idx->d_list_off.p;
+  s.cent = (const float*)idx->d_cent.p;
+  s.crot = (const float*)idx->d_crot.p;
+  s.dim = idx->dim;
+  s.dp = idx->dp;
+  s.W = idx->W;
+  s.nlist = idx->nlist;
+  s.eps0 = idx->prm.eps0;
+  s.seed = idx->prm.seed;
+  s.q = queries;
+  s.qrot = (const float*)w.qrot.p;
+  s.nq = nq;
+  s.qid_base = qid_base;
+  s.nprobe = nprobe;
+  s.k = k;
+  s.chunk = chunk;
+  s.probe = (const int32_t*)w.probe.p;
+  s.nprobe_q = nprobe_q;
+  s.pairs = (PairRec*)w.pairs.p;
+  s.planes = (uint64_t*)w.planes.p;
+  s.qu8 = mfma ? (int8_t*)w.qu8.p : nullptr;
+  s.pair_choff = (int32_t*)w.pair_choff.p;
+  s.pair_codeoff = (int32_t*)w.pair_codeoff.p;
+  s.q_nch = (int32_t*)w.q_nch.p;
+  s.q_p0 = (int32_t*)w.q_p0.p;
+  s.q_n0 = (int32_t*)w.q_n0.p;
+  s.q_ncode = (int64_t*)w.q_ncode.p;
+  int64_t* offs = (int64_t*)w.offs.p;
+  s.off_ch = offs;
+  s.off_p0 = offs + (nq + 1);
+  s.off_p1 = offs + 2 * (nq + 1);
+  s.off_seg = offs + 3 * (nq + 1);
+  s.off_n0 = offs + 4 * (nq + 1);
+  s.counters = (unsigned long long*)w.counters.p;
+  s.seg = (Cand*)w.seg.p;
+  s.seg_count = (int32_t*)w.seg_count.p;
+  s.p0buf = (EstEnt*)w.p0buf.p;
+  s.tau = (float*)w.tau.p;
+  s.seedk = (SeedEnt*)w.seedk.p;
+  s.q_rerank = (int32_t*)w.q_rerank.p;
+  s.q_cand = (int32_t*)w.q_cand.p;
+  s.mf_cnt = (int32_t*)w.mf_cnt.p;
+  s.mf_fill = (int32_t*)w.mf_fill.p;
+  s.mf_pair_off = (int64_t*)w.mf_pair_off.p;
+  s.mf_unit_off = (int64_t*)w.mf_unit_off.p;
+  s.mf_pairs = (int32_t*)w.mf_pairs.p;
+  s.out_ids = out_ids;
+  s.out_d = out_d;
+  return s;
+}
+
+// Rotation, centroid scoring and probe selection for a batch.
+rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
+                 const int32_t* nprobe_q, hipStream_t st) {
+  Workspace& w = idx->ws;
+  rbq_status rs = rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, (float*)w.qrot.p, st);
+  if (rs != RBQ_OK) return rs;
+  HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
+                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)w.cd.p, st));
+  HIPCHK(launch_select_probe((const float*)w.cd.p, nq, idx->nlist, nprobe, nprobe_q,
+                             (int32_t*)w.probe.p, (float*)w.probe_d.p, st));
+  return RBQ_OK;
+}
+
+int scan_grid(rbq_index* idx, int64_t nq, int nprobe, int chunk) {
+  const int64_t ub = std::max<int64_t>(1, nq * idx->max_chunks(nprobe, chunk));
+  const int64_t g = std::min<int64_t>((int64_t)device_cu_count() * 8, (ub + 3) / 4);
+  return (int)std::max<int64_t>(1, g);
+}
+
+rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& o,
+                      int scan_kernel, int chunk, const int32_t* nprobe_q, int64_t* out_ids,
+                      float* out_d, hipStream_t st) {
+  const bool mfma = scan_kernel == RBQ_SCAN_MFMA;
+  rbq_status rs = ensure_workspace(idx, nq, o.nprobe, o.k, chunk, mfma);
+  if (rs != RBQ_OK) return rs;
+  ProfState& pf = idx->prof;
+  hipEvent_t ev[7] = {};
+  if (pf.on) {
+    for (int i = 0; i < 7; ++i) {
+      HIPCHK(hipEventCreate(&ev[i]));
+      pf.events.push_back(ev[i]);
+    }
+    HIPCHK(hipEventRecord(ev[0], st));
+  }
+  rs = front(idx, queries, nq, o.nprobe, nprobe_q, st);
+  if (rs != RBQ_OK) return rs;
+  SearchDev s = make_dev(idx, queries, nq, o.nprobe, o.k, chunk, nprobe_q, o.qid_base, mfma,
+                         out_ids, out_d);
+  if (pf.on) HIPCHK(hipEventRecord(ev[1], st));
+  HIPCHK(launch_prep_pairs(s, st));
+  HIPCHK(launch_plan(s, st));
+  const int grid = scan_grid(idx, nq, o.nprobe, chunk);
+  if (pf.on) HIPCHK(hipEventRecord(ev[2], st));
+  HIPCHK(launch_scan_popcnt(s, 0, grid, st));
+  if (pf.on) HIPCHK(hipEventRecord(ev[3], st));
+  HIPCHK(launch_tau(s, st));
+  if (pf.on) HIPCHK(hipEventRecord(ev[4], st));
+  if (mfma) {
+    HIPCHK(launch_scan_mfma(s, 1, grid, st));
+  } else {
+    HIPCHK(launch_scan_popcnt(s, 1, grid, st));
+  }
+  if (pf.on) HIPCHK(hipEventRecord(ev[5], st));
+  HIPCHK(launch_finalize(s, st));
+  if (pf.on) {
+    HIPCHK(hipEventRecord(ev[6], st));
+    HIPCHK(launch_profile_accum(s, (unsigned long long*)pf.acc.p, st));
+    pf.searches++;
+  }
+  return RBQ_OK;
+}
+
+}  // namespace rbq
+
+extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t nq,
+                                 const rbq_search_opts* opts, int64_t* out_ids, float* out_dists,
+                                 rbq_search_stats* stats, void* stream) {
+  if (!idx || !opts) return fail(RBQ_EINVAL, "NULL argument");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  const rbq_search_opts o = *opts;
+  if (o.k < 1 || o.k > kMaxK) return fail(RBQ_EINVAL, "k=%d outside [1, %d]", o.k, kMaxK);
+  if (o.nprobe < 1 || o.nprobe > std::min(idx->nlist, kMaxNprobe))
+    return fail(RBQ_EINVAL, "nprobe=%d outside [1, %d]", o.nprobe, std::min(idx->nlist, kMaxNprobe));
+  if (o.scan_kernel < RBQ_SCAN_AUTO || o.scan_kernel > RBQ_SCAN_MFMA)
+    return fail(RBQ_EINVAL, "unknown scan_kernel %d", o.scan_kernel);
+  if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (nq == 0) return RBQ_OK;
+  if (!is_device_ptr(queries) || !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
+    return fail(RBQ_EINVAL, "queries, out_ids and out_dists must be device pointers");
+  if (o.nprobe_per_query && !is_device_ptr(o.nprobe_per_query))
+    return fail(RBQ_EINVAL, "nprobe_per_query must be a device pointer");
+  if (o.qid_base < 0 || o.qid_base + nq > (1ll << 24))
+    return fail(RBQ_EINVAL, "query ids must stay below 2^24 (qid_base %lld, nq %lld)",
+                (long long)o.qid_base, (long long)nq);
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  if (idx->done_event) HIPCHK(hipStreamWaitEvent(st, idx->done_event, 0));
+  int kernel = o.scan_kernel;
+  int chunk = idx->tuned_chunk > 0 ? idx->tuned_chunk : kDefaultChunk;
+  if (kernel == RBQ_SCAN_AUTO) kernel = idx->pick_kernel(nq, o.nprobe);
+  if (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())
+    return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this build");
+  const int32_t* npq = o.nprobe_per_query;
+  rbq_status rs = RBQ_OK;
+  if (!npq && o.use_learned_nprobe && idx->mlp.has_model) {
+    rs = rbq::learned_nprobe(idx, queries, nq, o.nprobe, o.qid_base, st, &npq);
+    if (rs != RBQ_OK) return rs;
+  }
+  rs = run_search(idx, queries, nq, o, kernel, chunk, npq, out_ids, out_dists, st);
+  if (rs != RBQ_OK) return rs;
+  if (!idx->done_event) HIPCHK(hipEventCreateWithFlags(&idx->done_event, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(idx->done_event, st));
+  if (stats) {
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int32_t> rr(nq), cc(nq), p0(nq);
+    std::vector<int64_t> nc(nq);
+    HIPCHK(hipMemcpy(rr.data(), idx->ws.q_rerank.p, nq * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cc.data(), idx->ws.q_cand.p, nq * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(nc.data(), idx->ws.q_ncode.p, nq * 8, hipMemcpyDeviceToHost));
+    std::vector<int32_t> probe((size_t)nq * o.nprobe);
+    HIPCHK(hipMemcpy(probe.data(), idx->ws.probe.p, probe.size() * 4, hipMemcpyDeviceToHost));
+    stats->queries = nq;
+    for (int64_t i = 0; i < nq; ++i) {
+      stats->reranked += rr[i];
+      stats->candidates += cc[i];
+      stats->codes_scanned += nc[i];
+    }
+    for (int32_t l : probe) stats->pairs += (l >= 0);
+  }
+  return RBQ_OK;
+}
+
+// ------------------------------------------------------------------ persistence
+namespace {
+const char kMagic[8] = {'R', 'B', 'Q', 'I', 'D', 'X', '0', '1'};
+struct FileHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t dim, dp, nlist, bq, rot_precision;
+  float eps0;
+  uint32_t pad;
+  uint64_t seed;
+  int64_t n;
+};
+}  // namespace
+
+extern "C" rbq_status rbq_index_save(const rbq_index* cidx, const char* path) {
+  rbq_index* idx = const_cast<rbq_index*>(cidx);
+  if (!idx || !path) return fail(RBQ_EINVAL, "NULL argument");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  const int64_t n = idx->n, npad = (n + 63) / 64 * 64;
+  std::vector<uint64_t> codes((size_t)npad * idx->W);
+  std::vector<float2> fac(npad);
+  std::vector<float> raw((size_t)n * idx->dim);
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(codes.data(), idx->d_codes.p, codes.size() * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(fac.data(), idx->d_fac.p, fac.size() * sizeof(float2), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(raw.data(), idx->d_raw.p, raw.size() * 4, hipMemcpyDeviceToHost));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(RBQ_EINVAL, "cannot open %s for writing", path);
+  FileHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kMagic, 8);
+  h.version = 1;
+  h.dim = idx->dim;
+  h.dp = idx->dp;
+  h.nlist = idx->nlist;
+  h.bq = idx->prm.bq;
+  h.rot_precision = idx->prm.rot_precision;
+  h.eps0 = idx->prm.eps0;
+  h.seed = idx->prm.seed;
+  h.n = n;
+  uint64_t sum = 0xcbf29ce484222325ull;
+  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+  auto put = [&](const void* p, size_t bytes) {
+    if (!ok) return;
+    sum = fnv1a(sum, p, bytes);
+    ok = std::fwrite(p, 1, bytes, f) == bytes;
+  };
+  put(idx->h_P.data(), idx->h_P.size() * 8);
+  put(idx->h_cent.data(), idx->h_cent.size() * 4);
+  put(idx->h_list_off.data(), idx->h_list_off.size() * 8);
+  put(idx->h_ids.data(), idx->h_ids.size() * 8);
+  put(raw.data(), raw.size() * 4);
+  put(codes.data(), codes.size() * 8);
+  put(fac.data(), fac.size() * sizeof(float2));
+  if (ok) ok = std::fwrite(&sum, 8, 1, f) == 1;
+  std::fclose(f);
+  if (!ok) return fail(RBQ_EINVAL, "write to %s failed", path);
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_index_load(const char* path, rbq_index** out) {
+  if (!path || !out) return fail(RBQ_EINVAL, "NULL argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(RBQ_EINVAL, "cannot open %s", path);
+  FileHeader h;
+  if (std::fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kMagic, 8) != 0 || h.version != 1) {
+    std::fclose(f);
+    return fail(RBQ_EFORMAT, "%s: not an index file (bad header)", path);
+  }
+  rbq_params p;
+  rbq_params_default(&p, h.dim, h.nlist);
+  p.code_bits = h.dp;
+  p.bq = h.bq;
+  p.eps0 = h.eps0;
+  p.rot_precision = h.rot_precision;
+  p.seed = h.seed;
+  if (check_params(&p) != RBQ_OK || h.n < 1 || h.n > (int64_t)INT32_MAX) {
+    std::fclose(f);
+    return fail(RBQ_EFORMAT, "%s: invalid header fields", path);
+  }
+  rbq_index* idx = nullptr;
+  if (rbq_index_create(&p, &idx) != RBQ_OK) {
+    std::fclose(f);
+    return RBQ_EFORMAT;
+  }
+  const int64_t n = h.n, npad = (n + 63) / 64 * 64;
+  std::vector<uint64_t> codes;
+  std::vector<float2> fac;
+  std::vector<float> raw;
+  uint64_t sum = 0xcbf29ce484222325ull;
+  bool ok = true;
+  auto get = [&](void* dst, size_t bytes) {
+    if (!ok) return;
+    ok = std::fread(dst, 1, bytes, f) == bytes;
+    if (ok) sum = fnv1a(sum, dst, bytes);
+  };
+  try {
+    idx->h_P.resize((size_t)idx->dp * idx->dp);
+    idx->h_cent.resize((size_t)idx->nlist * idx->dim);
+    idx->h_list_off.resize(idx->nlist + 1);
+    idx->h_ids.resize(n);
+    raw.resize((size_t)n * idx->dim);
+    codes.resize((size_t)npad * idx->W);
+    fac.resize(npad);
+  } catch (...) {
+    std::fclose(f);
+    delete idx;
+    return fail(RBQ_ENOMEM, "host allocation failed");
+  }
+  get(idx->h_P.data(), idx->h_P.size() * 8);
+  get(idx->h_cent.data(), idx->h_cent.size() * 4);
+  get(idx->h_list_off.data(), idx->h_list_off.size() * 8);
+  get(idx->h_ids.data(), idx->h_ids.size() * 8);
+  get(raw.data(), raw.size() * 4);
+  get(codes.data(), codes.size() * 8);
+  get(fac.data(), fac.size() * sizeof(float2));
+  uint64_t stored = 0;
+  if (ok) ok = std::fread(&stored, 8, 1, f) == 1;
+  std::fclose(f);
+  if (!ok) {
+    delete idx;
+    return fail(RBQ_EFORMAT, "%s: truncated file", path);
+  }
+  if (stored != sum) {
+    delete idx;
+    return fail(RBQ_EFORMAT, "%s: checksum mismatch", path);
+  }
+  bool sane = idx->h_list_off[0] == 0 && idx->h_list_off[idx->nlist] == n;
+  for (int k = 0; sane && k < idx->nlist; ++k) sane = idx->h_list_off[k] <= idx->h_list_off[k + 1];
+  if (!sane) {
+    delete idx;
+    return fail(RBQ_EFORMAT, "%s: inconsistent list offsets", path);
+  }
+  idx->n = n;
+  hipStream_t st = nullptr;
+  rbq_status rs = upload_model(idx, st);
+  if (rs != RBQ_OK) {
+    delete idx;
+    return rs;
+  }
+  auto up = [&](DBuf& b, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = b.ensure(bytes);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e = up(idx->d_codes, codes.data(), codes.size() * 8);
+  if (e == hipSuccess) e = up(idx->d_fac, fac.data(), fac.size() * sizeof(float2));
+  if (e == hipSuccess) e = up(idx->d_raw, raw.data(), raw.size() * 4);
+  if (e == hipSuccess) e = up(idx->d_ids, idx->h_ids.data(), idx->h_ids.size() * 8);
+  if (e != hipSuccess) {
+    delete idx;
+    return fail(e == hipErrorOutOfMemory ? RBQ_ENOMEM : RBQ_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+  }
+  account_bytes(idx);
+  idx->built = true;
+  *out = idx;
+  return RBQ_OK;
+}
+
+// ------------------------------------------------------------------ debug exports
+extern "C" rbq_status rbq_debug_export_codes(const rbq_index* cidx, uint64_t* codes, float* norm,
+                                             float* ipo) {
+  rbq_index* idx = const_cast<rbq_index*>(cidx);
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  const int64_t n = idx->n, npad = (n + 63) / 64 * 64;
+  const int W = idx->W;
+  std::vector<uint64_t> c((size_t)npad * W);
+  std::vector<float2> fac(npad);
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(c.data(), idx->d_codes.p, c.size() * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(fac.data(), idx->d_fac.p, fac.size() * sizeof(float2), hipMemcpyDeviceToHost));
+  for (int64_t p = 0; p < n; ++p) {
+    const int64_t id = idx->h_ids[p];
+    if (codes)
+      for (int w = 0; w < W; ++w) codes[(size_t)id * W + w] = c[((size_t)(p >> 6) * W + w) * 64 + (p & 63)];
+    if (norm) norm[id] = fac[p].x;
+    if (ipo) ipo[id] = fac[p].y;
+  }
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_debug_list_ids(const rbq_index* idx, int32_t list, int64_t* ids) {
+  if (!idx || !ids) return fail(RBQ_EINVAL, "NULL argument");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  if (list < 0 || list >= idx->nlist) return fail(RBQ_EINVAL, "list out of range");
+  for (int64_t p = idx->h_list_off[list]; p < idx->h_list_off[list + 1]; ++p)
+    ids[p - idx->h_list_off[list]] = idx->h_ids[p];
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_debug_rotate(rbq_index* idx, const float* queries, int64_t nq,
+                                       float* out, void* stream) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
+  if (nq == 0) return RBQ_OK;
+  if (!is_device_ptr(queries) || !is_device_ptr(out)) return fail(RBQ_EINVAL, "device pointers required");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  return rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, out, (hipStream_t)stream);
+}
+
+extern "C" rbq_status rbq_debug_probe(rbq_index* idx, const float* queries, int64_t nq,
+                                      int32_t nprobe, int32_t* lists, float* dists, void* stream) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  if (nprobe < 1 || nprobe > std::min(idx->nlist, kMaxNprobe)) return fail(RBQ_EINVAL, "nprobe out of range");
+  if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
+  if (nq == 0) return RBQ_OK;
+  if (!is_device_ptr(queries) || !is_device_ptr(lists) || (dists && !is_device_ptr(dists)))
+    return fail(RBQ_EINVAL, "device pointers required");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  rbq_status rs = ensure_workspace(idx, nq, nprobe, 1, kDefaultChunk, false);
+  if (rs != RBQ_OK) return rs;
+  HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
+                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)idx->ws.cd.p, st));
+  HIPCHK(launch_select_probe((const float*)idx->ws.cd.p, nq, idx->nlist, nprobe, nullptr, lists,
+                             dists, st));
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_debug_quantize(rbq_index* idx, const float* queries, int64_t nq,
+                                         const int32_t* lists, int32_t nprobe, int64_t qid_base,
+                                         uint8_t* qu, float* scal, void* stream) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  if (nprobe < 1 || nprobe > kMaxNprobe) return fail(RBQ_EINVAL, "nprobe out of range");
+  if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
+  if (nq == 0) return RBQ_OK;
+  if (!is_device_ptr(queries) || !is_device_ptr(lists) || !is_device_ptr(qu) || !is_device_ptr(scal))
+    return fail(RBQ_EINVAL, "device pointers required");
+  if (qid_base < 0 || qid_base + nq > (1ll << 24)) return fail(RBQ_EINVAL, "query ids must stay below 2^24");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  rbq_status rs = ensure_workspace(idx, nq, nprobe, 1, kDefaultChunk, true);
+  if (rs != RBQ_OK) return rs;
+  rs = rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, (float*)idx->ws.qrot.p, st);
+  if (rs != RBQ_OK) return rs;
+  HIPCHK(hipMemcpyAsync(idx->ws.probe.p, lists, (size_t)nq * nprobe * 4, hipMemcpyDeviceToDevice, st));
+  SearchDev s = make_dev(idx, queries, nq, nprobe, 1, kDefaultChunk, nullptr, qid_base, true,
+                         nullptr, nullptr);
+  HIPCHK(launch_prep_pairs(s, st));
+  HIPCHK(hipMemcpyAsync(qu, idx->ws.qu8.p, (size_t)nq * nprobe * idx->dp, hipMemcpyDeviceToDevice, st));
+  HIPCHK(launch_pairs_to_scal(s, scal, st));
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_debug_scan(rbq_index* idx, int32_t list, const uint8_t* qu,
+                                     const float* scal, int32_t kernel, int32_t* ip, int32_t* pc,
+                                     float* est, float* dist, float* lb, void* stream) {
+  if (!idx || !scal) return fail(RBQ_EINVAL, "NULL argument");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  if (list < 0 || list >= idx->nlist) return fail(RBQ_EINVAL, "list out of range");
+  if (kernel != RBQ_SCAN_POPCNT && kernel != RBQ_SCAN_MFMA) return fail(RBQ_EINVAL, "kernel must be POPCNT or MFMA");
+  if (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available()) return fail(RBQ_EUNSUPPORTED, "MFMA scan not available");
+  for (const void* p : {(const void*)qu, (const void*)ip, (const void*)pc, (const void*)est,
+                        (const void*)dist, (const void*)lb})
+    if (!is_device_ptr(p)) return fail(RBQ_EINVAL, "qu and outputs must be device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  rbq_status rs = ensure_workspace(idx, 1, 1, 1, kDefaultChunk, true);
+  if (rs != RBQ_OK) return rs;
+  Workspace& w = idx->ws;
+  HIPCHK(launch_debug_pack(qu, idx->dp, idx->W, scal[0], scal[1], scal[2], (PairRec*)w.pairs.p,
+                           (uint64_t*)w.planes.p, (int8_t*)w.qu8.p, list, st));
+  SearchDev s = make_dev(idx, nullptr, 1, 1, 1, kDefaultChunk, nullptr, 0, true, nullptr, nullptr);
+  HIPCHK(launch_debug_scan(s, (const PairRec*)w.pairs.p, (const uint64_t*)w.planes.p,
+                           (const int8_t*)w.qu8.p, list, kernel, ip, pc, est, dist, lb, st));
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_debug_fail_alloc_after(int32_t n) {
+  rbq::g_fail_alloc_after = n;
+  return RBQ_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+void rbq::ProfState::clear() {
+  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  events.clear();
+  searches = 0;
+}
+
+extern "C" rbq_status rbq_profile_enable(rbq_index* idx, int32_t on) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  HIPCHK(hipDeviceSynchronize());
+  idx->prof.clear();
+  idx->prof.on = on != 0;
+  if (idx->prof.on) {
+    HIPCHK(idx->prof.acc.ensure(16));
+    HIPCHK(hipMemset(idx->prof.acc.p, 0, 16));
+  }
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_profile_read(rbq_index* idx, rbq_profile* out) {
+  if (!idx || !out) return fail(RBQ_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  std::memset(out, 0, sizeof(*out));
+  HIPCHK(hipDeviceSynchronize());
+  ProfState& pf = idx->prof;
+  out->searches = pf.searches;
+  double* f[6] = {&out->ms_front, &out->ms_prep, &out->ms_scan0, &out->ms_tau, &out->ms_scan1,
+                  &out->ms_finalize};
+  for (size_t b = 0; b + 7 <= pf.events.size(); b += 7)
+    for (int i = 0; i < 6; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, pf.events[b + i], pf.events[b + i + 1]));
+      *f[i] += ms;
+    }
+  if (pf.acc.p) {
+    long long acc[2];
+    HIPCHK(hipMemcpy(acc, pf.acc.p, 16, hipMemcpyDeviceToHost));
+    out->codes_scan0 = acc[0];
+    out->codes_scan1 = acc[1];
+  }
+  return RBQ_OK;
+}

@@ -1,0 +1,266 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (derived from the arithmetic, see the design notes):
+  integer <x_b, q_u> and popcount          bit-exact
+  est                                      |d| <= 1e-5 max(1, |est|)
+  dist_est, lb                             |d| <= 1e-5 max(|oracle|, a^2 + b^2)
+  codes / quantised query                  may differ only where the FP64 value
+                                           sits within the rotation's error of a
+                                           sign change / rounding boundary
+  top-k                                    exact top-k of the probed lists, except
+                                           exact-distance near-ties and queries
+                                           where a member's lower bound exceeded
+                                           its true distance (bound failure)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rabitq_oracle as O
+
+from gpu_common import (Built, make_case, near_integer, oracle_estimates_on, rel_ok, sqdist64,
+                        tie_equivalent)
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["flat128", "ivf128", "pad100", "ivf960z", "ivf768"]
+_BUILT = {}
+
+
+def built(name) -> Built:
+    print(f"[case {name}]", flush=True)
+    sys.stdout.flush()
+    if name not in _BUILT:
+        _BUILT[name] = Built(make_case(name))
+    return _BUILT[name]
+
+
+def _rot_tol(case):
+    from paper_2405_12497_amd import rabitq as R
+    return 2e-6 if case.rot == R.RBQ_ROT_FP32 else 6e-5
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_codes_and_factors_match_oracle(name):
+    b = built(name)
+    c = b.case
+    o = b.oidx
+    np.testing.assert_allclose(b.norm, o.norm, rtol=2e-6, atol=1e-6)
+    # y = P^T (o_r - c) unnormalised; a sign may differ only where |y_i| is within
+    # the rotation error of 0
+    y = o.z * o.norm[:, None]
+    diff = b.bits != o.bits
+    tol = np.broadcast_to(_rot_tol(c) * 4 * o.norm[:, None], diff.shape)
+    assert np.all(np.abs(y[diff]) <= tol[diff]), f"{diff.sum()} sign flips, some far from zero"
+    assert diff.mean() < 1e-3
+    # <o_bar,o> from the GPU's own bits and FP64 z
+    xbar = (2.0 * b.bits - 1) / np.sqrt(c.dp)
+    ipo_own = (xbar * o.z).sum(1)
+    np.testing.assert_allclose(b.ipo, ipo_own, atol=50 * _rot_tol(c))
+    np.testing.assert_allclose(b.ipo, o.ipo, atol=50 * _rot_tol(c) + 1e-6)
+    print(f"{name}: code bits differing from FP64: {int(diff.sum())} of {diff.size}; "
+          f"max |ipo - oracle| {np.max(np.abs(b.ipo - o.ipo)):.2e}")
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rotation_error_vs_fp64(name):
+    from paper_2405_12497_amd import rabitq as R
+    b = built(name)
+    c = b.case
+    rot = R.rbq_debug_rotate(b.idx.h, b.q, c.dp).cpu().numpy().astype(np.float64)
+    ref = O.pad(c.queries, c.dp) @ b.oidx.p
+    err = np.abs(rot - ref)
+    scale = np.linalg.norm(c.queries.astype(np.float64), axis=1)[:, None]
+    rel = err / scale
+    print(f"{name}: rotation max|err|/||q|| = {rel.max():.3e}, mean = {rel.mean():.3e}")
+    assert rel.max() <= _rot_tol(c)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_probe_matches_oracle(name):
+    b = built(name)
+    c = b.case
+    lists, d = b.probe()
+    for qi, q in enumerate(c.queries):
+        want = O.probe_lists(q, c.cent, c.nprobe)
+        if np.array_equal(lists[qi], want):
+            continue
+        # only near-ties in the centroid distance may reorder
+        dg = sqdist64(c.cent[lists[qi]], q)
+        dw = sqdist64(c.cent[want], q)
+        assert np.allclose(dg, dw, rtol=1e-5, atol=1e-5 * dw.max()), f"query {qi}"
+    np.testing.assert_allclose(d, sqdist64(c.cent[lists][..., :], c.queries[:, None, :]),
+                               rtol=1e-4, atol=1e-4 * float(np.max(d)))
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_quantized_query_matches_oracle(name):
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    b = built(name)
+    c = b.case
+    lists, _ = b.probe()
+    qu, scal = R.rbq_debug_quantize(b.idx.h, b.q, torch.from_numpy(lists).to(b.dev), c.dp, qid_base=0)
+    qu = qu.cpu().numpy().reshape(len(c.queries), c.nprobe, c.dp).astype(np.int64)
+    scal = scal.cpu().numpy().reshape(len(c.queries), c.nprobe, 4)
+    rot = R.rbq_debug_rotate(b.idx.h, b.q, c.dp).cpu().numpy().astype(np.float64)
+    ref_rot = O.pad(c.queries, c.dp) @ b.oidx.p
+    flips = total = 0
+    for qi in range(len(c.queries)):
+        rot_err = np.abs(rot[qi] - ref_rot[qi]).max()
+        for r in range(c.nprobe):
+            lid = int(lists[qi, r])
+            u = O.rounding_uniforms_fast(c.seed, qi, lid, c.dp)
+            oq = O.quantize_query(c.queries[qi], c.cent[lid], b.oidx.p, u)
+            bb, vl, delta, sq = scal[qi, r]
+            assert bb == pytest.approx(oq.b, rel=2e-6)
+            if oq.b == 0:
+                continue
+            assert vl == pytest.approx(oq.vl, rel=1e-4, abs=1e-6)
+            assert delta == pytest.approx(oq.delta, rel=1e-4)
+            assert int(sq) == int(qu[qi, r].sum())
+            # (q' - v_l)/Delta + u in FP64; flips allowed within the rotation error of an integer
+            x = (oq.qprime - oq.vl) / oq.delta + u
+            resid_scale = oq.b * (oq.vr - oq.vl)          # range of the unnormalised residual
+            tol = 15.0 * (2 * rot_err + 2e-7 * np.linalg.norm(c.cent[lid]) * 4) / resid_scale + 1e-5
+            d = qu[qi, r] != oq.qu
+            assert np.all(near_integer(x[d], tol)), f"query {qi} list {lid}: {d.sum()} codes differ"
+            assert np.all(np.abs(qu[qi, r] - oq.qu) <= 1)
+            flips += int(d.sum())
+            total += c.dp
+    print(f"{name}: quantised coordinates differing from FP64: {flips} of {total}")
+
+
+@pytest.mark.parametrize("kernel", ["popcnt", "mfma"])
+@pytest.mark.parametrize("name", CASES)
+def test_scan_bitexact_and_estimates(name, kernel):
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    b = built(name)
+    kern = R.RBQ_SCAN_POPCNT if kernel == "popcnt" else R.RBQ_SCAN_MFMA
+    c = b.case
+    sizes = b.idx.list_sizes()
+    rng = np.random.default_rng(5)
+    lists = np.argsort(-sizes)[:3].tolist() + rng.choice(len(sizes), size=min(3, len(sizes)), replace=False).tolist()
+    for lid in lists:
+        n = int(sizes[lid])
+        if n == 0:
+            continue
+        ids = R.rbq_debug_list_ids(b.idx.h, int(lid), n)
+        qi = int(rng.integers(len(c.queries)))
+        u = O.rounding_uniforms_fast(c.seed, qi, int(lid), c.dp)
+        oq = O.quantize_query(c.queries[qi], c.cent[lid], b.oidx.p, u)
+        qb, vl, dl = np.float32(oq.b), np.float32(oq.vl), np.float32(oq.delta)
+        qu_t = torch.from_numpy(oq.qu.astype(np.uint8)).to(b.dev)
+        ip, pc, est, dist, lb = R.rbq_debug_scan(b.idx.h, int(lid), qu_t, qb, vl, dl, n, kernel=kern)
+        ip, pc = ip.cpu().numpy(), pc.cpu().numpy()
+        est, dist, lb = est.cpu().numpy(), dist.cpu().numpy(), lb.cpu().numpy()
+        oip, opc, oest, odist, olb = oracle_estimates_on(b.bits[ids], b.norm[ids], b.ipo[ids], oq.qu,
+                                                         float(qb), float(vl), float(dl), c.dp)
+        np.testing.assert_array_equal(ip, oip)
+        np.testing.assert_array_equal(pc, opc)
+        # the three integer formulas agree on the GPU's codes
+        np.testing.assert_array_equal(O.ip_bitplanes(b.bits[ids], oq.qu), oip)
+        assert np.all(rel_ok(est, oest, np.maximum(1.0, np.abs(oest)), 1e-5))
+        scale = b.norm[ids].astype(np.float64) ** 2 + float(qb) ** 2
+        assert np.all(rel_ok(dist, odist, np.maximum(np.abs(odist), scale), 1e-5))
+        assert np.all(rel_ok(lb, olb, np.maximum(np.abs(olb), scale), 1e-5))
+        assert np.all(lb <= dist)
+
+
+def _violations(b, lists, qi, top_ids, top_d):
+    """True-top-k members whose GPU-path lower bound exceeds their true distance."""
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    c = b.case
+    qu, scal = R.rbq_debug_quantize(b.idx.h, b.q[qi:qi + 1].contiguous(),
+                                    torch.from_numpy(lists[qi:qi + 1]).to(b.dev), c.dp, qid_base=qi)
+    qu = qu.cpu().numpy().astype(np.int64)
+    scal = scal.cpu().numpy()
+    bad = []
+    for oid, d in zip(top_ids, top_d):
+        r = int(np.flatnonzero(lists[qi] == c.assign[oid])[0])
+        _, _, _, _, lbv = oracle_estimates_on(b.bits[oid:oid + 1], b.norm[oid:oid + 1], b.ipo[oid:oid + 1],
+                                              qu[r], scal[r, 0], scal[r, 1], scal[r, 2], c.dp)
+        if lbv[0] > d * (1 + 1e-6):
+            bad.append(int(oid))
+    return bad
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_search_returns_exact_topk_of_probed_lists(name):
+    b = built(name)
+    c = b.case
+    ids, d, st = b.search(scan_kernel=b.R.RBQ_SCAN_POPCNT, stats=True)
+    lists, _ = b.probe()
+    flagged = mism = 0
+    for qi, q in enumerate(c.queries):
+        cand = np.flatnonzero(np.isin(c.assign, lists[qi]))
+        t_ids, t_d = O.exact_topk(c.data, q, c.k, cand)
+        # returned distances are the exact distances of the returned ids
+        got = ids[qi][ids[qi] >= 0]
+        np.testing.assert_allclose(d[qi][:len(got)], sqdist64(c.data[got], q), rtol=2e-5,
+                                   atol=1e-6 * float(np.max(t_d)) + 1e-6)
+        assert np.all(np.diff(d[qi][:len(got)]) >= 0)
+        if tie_equivalent(ids[qi], t_ids, q, c.data):
+            continue
+        mism += 1
+        viol = _violations(b, lists, qi, t_ids, t_d)
+        assert viol, f"query {qi}: top-{c.k} differs from the exact top-{c.k} without a bound failure"
+        flagged += 1
+    assert st["codes_scanned"] == sum(int(np.isin(c.assign, lists[qi]).sum()) for qi in range(len(c.queries)))
+    assert st["reranked"] >= min(c.k, len(c.data)) * len(c.queries)
+    print(f"{name}: mismatches {mism} (all with bound failures: {flagged}); stats {st}")
+    assert mism <= max(1, len(c.queries) // 4)
+
+
+@pytest.mark.parametrize("name", ["ivf128", "ivf960z"])
+def test_search_is_deterministic(name):
+    b = built(name)
+    a1, d1, s1 = b.search(scan_kernel=b.R.RBQ_SCAN_POPCNT, stats=True)
+    a2, d2, s2 = b.search(scan_kernel=b.R.RBQ_SCAN_POPCNT, stats=True)
+    np.testing.assert_array_equal(a1, a2)
+    np.testing.assert_array_equal(d1, d2)
+    assert s1 == s2
+
+
+def test_recall_at_eps0_is_near_perfect():
+    """Sec. 5.2.4: with every distance estimated (flat index), eps0 = 1.9 keeps
+    the true neighbours in the rerank set."""
+    b = built("flat128")
+    c = b.case
+    ids, _, _ = b.search(scan_kernel=b.R.RBQ_SCAN_POPCNT)
+    hits = 0
+    for qi, q in enumerate(c.queries):
+        t_ids, _ = O.exact_topk(c.data, q, c.k)
+        hits += len(set(ids[qi].tolist()) & set(t_ids.tolist()))
+    assert hits / (c.k * len(c.queries)) >= 0.99
+
+
+@pytest.mark.parametrize("name", ["ivf128", "ivf960z", "ivf768", "pad100"])
+def test_search_mfma_matches_popcount(name):
+    b = built(name)
+    c = b.case
+    a1, d1, s1 = b.search(scan_kernel=b.R.RBQ_SCAN_POPCNT, stats=True)
+    a2, d2, s2 = b.search(scan_kernel=b.R.RBQ_SCAN_MFMA, stats=True)
+    assert s1["codes_scanned"] == s2["codes_scanned"]
+    for qi, q in enumerate(c.queries):
+        assert tie_equivalent(a2[qi], a1[qi], q, c.data), f"query {qi}"
+    np.testing.assert_allclose(d2, d1, rtol=1e-6)
+    print(f"{name}: popcount stats {s1}; mfma stats {s2}")
+
+
+def test_mfma_large_batch_groups():
+    """Many queries per list: groups of 16 pairs, several groups per list."""
+    import torch
+    b = built("ivf128")
+    c = b.case
+    rng = np.random.default_rng(9)
+    qs = (c.queries[rng.integers(0, len(c.queries), 200)] + rng.normal(0, 2, (200, c.dim))).astype(np.float32)
+    qt = torch.from_numpy(qs).to(b.dev)
+    a1, d1, _ = b.idx.search(qt, 10, 8, scan_kernel=b.R.RBQ_SCAN_POPCNT)
+    a2, d2, _ = b.idx.search(qt, 10, 8, scan_kernel=b.R.RBQ_SCAN_MFMA)
+    a1, a2 = a1.cpu().numpy(), a2.cpu().numpy()
+    for qi in range(len(qs)):
+        assert tie_equivalent(a2[qi], a1[qi], qs[qi], c.data), f"query {qi}"
