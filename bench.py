@@ -61,7 +61,7 @@ def recall(ids, gt_d, data, queries, k):
     return hits / (k * len(ids))
 
 
-def cpu_baseline(wl, nprobe, k, budget_s=15.0, max_q=400):
+def cpu_baseline(wl, nprobe, k, budget_s=15.0, max_q=5000):
     """The FP64 oracle (paper's sequential rerank rule) on a bounded query sample, 1 thread."""
     from threadpoolctl import threadpool_limits
 

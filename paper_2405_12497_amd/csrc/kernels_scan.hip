@@ -252,68 +252,148 @@ __device__ __forceinline__ void estimate(const PairRec& r, float2 f, int ip, int
   lb = fmaf(-ab2, hw, dist);
 }
 
-__device__ __forceinline__ int64_t upper_bound64(const int64_t* a, int64_t n, int64_t v) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a[mid] <= v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-__device__ __forceinline__ int upper_bound32(const int32_t* a, int n, int v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (a[mid] <= v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+// Work-unit tables: entry = (query << 38) | (probe rank << 28) | chunk.
+__device__ __forceinline__ uint64_t pack_unit(int64_t q, int r, int c) {
+  return ((uint64_t)q << 38) | ((uint64_t)r << 28) | (uint64_t)c;
 }
 
-// Resolves work unit u of a phase into its chunk; returns false when done.
+// One thread per query: its chunks in probe order, bootstrap ones to units0
+// (at off_p0[q]) and the others to units1 (at off_p1[q]).
+__global__ void k_units(SearchDev s) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= s.nq) return;
+  const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
+  const int p0 = s.q_p0[q];
+  const int64_t b0 = s.off_p0[q], b1 = s.off_p1[q];
+  int j = 0;
+  for (int r = 0; r < s.nprobe; ++r) {
+    const int nc = choff[r + 1] - choff[r];
+    for (int c = 0; c < nc; ++c, ++j) {
+      const uint64_t e = pack_unit(q, r, c);
+      if (j < p0) s.units0[b0 + j] = e; else s.units1[b1 + (j - p0)] = e;
+    }
+  }
+}
+
 struct Unit {
   int64_t q;
-  int j;       // local chunk index
-  int r;       // probe rank
-  int c;       // chunk within the pair
+  int r, c;
+  int64_t g;            // pair index
   int64_t start, end;   // code positions
-  int64_t codeoff;      // query code space offset of the chunk start
+  int64_t codeoff;      // query code-space offset of the chunk start
+  int64_t count_slot;   // seg_count index
 };
 
-__device__ __forceinline__ void resolve_unit(const SearchDev& s, int phase, int64_t u, Unit& w) {
-  const int64_t* off = phase == 0 ? s.off_p0 : s.off_p1;
-  const int64_t q = upper_bound64(off, s.nq + 1, u) - 1;
-  const int j = (phase == 0 ? 0 : s.q_p0[q]) + (int)(u - off[q]);
-  const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
-  const int r = upper_bound32(choff, s.nprobe + 1, j) - 1;
-  const int c = j - choff[r];
-  const int list = s.probe[q * s.nprobe + r];
-  const int64_t lbeg = s.list_off[list], lend = s.list_off[list + 1];
-  w.q = uniform_i64(q);
-  w.j = uniform_i32(j);
-  w.r = uniform_i32(r);
-  w.c = uniform_i32(c);
-  w.start = uniform_i64(lbeg + (int64_t)c * s.chunk);
-  w.end = uniform_i64(lend < w.start + s.chunk ? lend : w.start + s.chunk);
-  w.codeoff = uniform_i64((int64_t)s.pair_codeoff[q * (s.nprobe + 1) + r] + (int64_t)c * s.chunk);
+__device__ __forceinline__ Unit load_unit(const SearchDev& s, uint64_t e) {
+  Unit w;
+  w.q = uniform_i64((int64_t)(e >> 38));
+  w.r = uniform_i32((int)((e >> 28) & 1023u));
+  w.c = uniform_i32((int)(e & ((1u << 28) - 1u)));
+  w.g = w.q * s.nprobe + w.r;
+  const int list = uniform_i32(s.pairs[w.g].list);
+  const int32_t* choff = s.pair_choff + w.q * (s.nprobe + 1);
+  const int32_t* codeoff = s.pair_codeoff + w.q * (s.nprobe + 1);
+  const int64_t lbeg = uniform_i64(s.list_off[list]), lend = uniform_i64(s.list_off[list + 1]);
+  w.start = lbeg + (int64_t)w.c * s.chunk;
+  w.end = lend < w.start + s.chunk ? lend : w.start + s.chunk;
+  w.codeoff = uniform_i64((int64_t)codeoff[w.r] + (int64_t)w.c * s.chunk);
+  w.count_slot = uniform_i64(s.off_ch[w.q] + choff[w.r] + w.c);
+  return w;
 }
 
-template <int WS>
+// Scan of one chunk: UN blocks of 64 codes per iteration, one code per lane
+// per block, all loads of an iteration issued before the arithmetic.
+template <int WS, int UN>
+__device__ __forceinline__ int scan_chunk(const SearchDev& s, int phase, const Unit& w,
+                                          const PairRec& rec, const Planes<WS>& pl, float tau,
+                                          float hwk) {
+  const int lane = lane_id();
+  const int64_t seg_base = s.off_seg[w.q] + w.codeoff;
+  const int64_t p0base = phase == 0 ? s.off_n0[w.q] + w.codeoff : 0;
+  int count = 0;
+  for (int64_t b0 = w.start; b0 < w.end; b0 += 64 * UN) {
+    int64_t p[UN];
+    bool valid[UN];
+    float2 f[UN];
+    int ip[UN], pc[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      valid[u] = b0 + 64 * u + lane < w.end;
+      p[u] = valid[u] ? b0 + 64 * u + lane : w.start;   // masked lanes read an in-bounds code
+      f[u] = s.fac[p[u]];
+    }
+    if constexpr (WS > 0) {
+      uint64_t x[UN][WS];
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int t = 0; t < WS; ++t) x[u][t] = s.codes[code_word_index(p[u], t, WS)];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        int s0 = 0, s1 = 0, s2 = 0, s3 = 0, c = 0;
+#pragma unroll
+        for (int t = 0; t < WS; ++t) {
+          c += __popcll(x[u][t]);
+          s0 += __popcll(x[u][t] & pl.get(0, t));
+          s1 += __popcll(x[u][t] & pl.get(1, t));
+          s2 += __popcll(x[u][t] & pl.get(2, t));
+          s3 += __popcll(x[u][t] & pl.get(3, t));
+        }
+        ip[u] = s0 + 2 * s1 + 4 * s2 + 8 * s3;
+        pc[u] = c;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < UN; ++u) code_ip<WS>(s.codes, p[u], s.W, pl, ip[u], pc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      float est, dist, lb;
+      estimate(rec, f[u], ip[u], pc[u], hwk, est, dist, lb);
+      lb = valid[u] ? lb : __builtin_inff();
+      const int64_t off = p[u] - w.start;
+      if (phase == 0) {
+        if (valid[u]) {
+          Cand cd;
+          cd.pos = (int32_t)p[u];
+          cd.lb = lb;
+          s.seg[seg_base + off] = cd;
+          EstEnt e;
+          e.dist = dist;
+          e.slot = (int32_t)(w.codeoff + off);
+          s.p0buf[p0base + off] = e;
+        }
+      } else {
+        const bool pass = valid[u] && (lb <= tau);
+        const uint64_t m = __ballot(pass);
+        if (pass) {
+          Cand cd;
+          cd.pos = (int32_t)p[u];
+          cd.lb = lb;
+          s.seg[seg_base + count + __popcll(m & lanemask_lt())] = cd;
+        }
+        count += __popcll(m);
+      }
+    }
+  }
+  return phase == 0 ? (int)(w.end - w.start) : count;
+}
+
+// Persistent scan: wave i of the grid takes units i, i + nwaves, ... of the
+// phase's unit table (units are chunks of at most `chunk` codes, so a static
+// round-robin balances them; no atomics and no per-unit searches).
+template <int WS, int UN>
 __global__ __launch_bounds__(kThreads) void k_scan_popcnt(SearchDev s, int phase) {
   __shared__ uint64_t lds_planes[kWaves][4 * (kMaxCodeBits / 64)];
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int64_t total = uniform_i64((phase == 0 ? s.off_p0 : s.off_p1)[s.nq]);
+  const uint64_t* tab = phase == 0 ? s.units0 : s.units1;
   const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
-  for (;;) {
-    // Claim one unit per wave. Every lane issues the atomic (increment 1 on
-    // lane 0, 0 elsewhere) so no lane-dependent branch sits in the loop;
-    // lane 0's result, the first active lane's, is the claimed unit.
-    const int64_t u = uniform_i64((int64_t)atomicAdd(&s.counters[phase], lane == 0 ? 1ull : 0ull));
-    if (u >= total) break;
-    Unit w;
-    resolve_unit(s, phase, u, w);
-    const int64_t g = w.q * s.nprobe + w.r;
-    const PairRec rec = s.pairs[g];
-    const uint64_t* src = s.planes + g * 4 * s.W;
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t u = uniform_i64((int64_t)blockIdx.x * kWaves + wave); u < total; u += nw) {
+    const Unit w = load_unit(s, tab[u]);
+    const PairRec rec = s.pairs[w.g];
+    const uint64_t* src = s.planes + w.g * 4 * s.W;
     Planes<WS> pl;
     if constexpr (WS > 0) {
       pl.load(src, s.W);
@@ -324,59 +404,24 @@ __global__ __launch_bounds__(kThreads) void k_scan_popcnt(SearchDev s, int phase
       pl.W = s.W;
     }
     const float tau = phase == 0 ? __builtin_inff() : uniform_f32(s.tau[w.q]);
-    const int64_t seg_base = s.off_seg[w.q] + w.codeoff;
-    int count = 0;
-    for (int64_t p0 = w.start; p0 < w.end; p0 += kWave) {
-      const bool valid = p0 + lane < w.end;
-      // lanes past the end read the chunk's first code (in bounds) and are masked
-      const int64_t p = valid ? p0 + lane : w.start;
-      float est, dist, lb;
-      int ip, pc;
-      code_ip<WS>(s.codes, p, s.W, pl, ip, pc);
-      estimate(rec, s.fac[p], ip, pc, hwk, est, dist, lb);
-      lb = valid ? lb : __builtin_inff();
-      if (phase == 0) {
-        if (valid) {
-          const int64_t off = p - w.start;
-          Cand cd;
-          cd.pos = (int32_t)p;
-          cd.lb = lb;
-          s.seg[seg_base + off] = cd;
-          EstEnt e;
-          e.dist = dist;
-          e.slot = (int32_t)(w.codeoff + off);
-          s.p0buf[s.off_n0[w.q] + w.codeoff + off] = e;
-        }
-      } else {
-        const bool pass = valid && (lb <= tau);
-        const uint64_t m = __ballot(pass);
-        if (pass) {
-          Cand cd;
-          cd.pos = (int32_t)p;
-          cd.lb = lb;
-          s.seg[seg_base + count + __popcll(m & lanemask_lt())] = cd;
-        }
-        count += __popcll(m);
-      }
-    }
-    if (lane == 0) {
-      if (phase == 0) count = (int)(w.end - w.start);
-      s.seg_count[s.off_ch[w.q] + w.j] = count;
-    }
+    const int count = scan_chunk<WS, UN>(s, phase, w, rec, pl, tau, hwk);
+    if (lane == 0) s.seg_count[w.count_slot] = count;
   }
 }
 
 // ------------------------------------------------------------------ exact distance
-// Wave-cooperative ||o_r - q_r||^2 for the raw vector at position pos.
-__device__ __forceinline__ float exact_dist(const float* __restrict__ raw, int64_t pos, int dim,
-                                            const float* __restrict__ qv) {
+// Squared distance of the raw vector at `pos` to the query in LDS, computed by
+// a group of `lpc` consecutive lanes (lpc divides 64).
+__device__ __forceinline__ float group_dist(const float* __restrict__ raw, int64_t pos, int dim,
+                                            const float* __restrict__ qv, int sub, int lpc) {
   const float* o = raw + pos * dim;
   float acc = 0.f;
-  for (int i = lane_id(); i < dim; i += kWave) {
+  for (int i = sub; i < dim; i += lpc) {
     const float d = o[i] - qv[i];
     acc = fmaf(d, d, acc);
   }
-  return wave_sum(acc);
+  for (int off = lpc >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  return acc;
 }
 
 __device__ __forceinline__ bool less_di(float d1, int64_t i1, float d2, int64_t i2) {
@@ -388,13 +433,11 @@ __device__ __forceinline__ bool less_di(float d1, int64_t i1, float d2, int64_t 
 // their exact distance; they seed the top-k and tau; their segment entries are
 // marked done (pos = -1).
 __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
+  extern __shared__ float qv[];          // dim floats
   __shared__ uint64_t key[kMaxP0];
-  __shared__ float qv[kMaxCodeBits];
-  __shared__ float topd[kMaxK];
   __shared__ int32_t toppos[kMaxK];
   __shared__ uint64_t key2[kMaxK];
   const int64_t q = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = lane_id();
   const int n0 = uniform_i32(s.q_n0[q]);
   const int64_t b0 = uniform_i64(s.off_n0[q]);
   for (int i = threadIdx.x; i < s.dim; i += kThreads) qv[i] = s.q[q * s.dim + i];
@@ -427,41 +470,36 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
     }
   const int m = min(s.k, n0);
   const int64_t seg0 = uniform_i64(s.off_seg[q]);
-  for (int i = wave; i < m; i += kWaves) {
+  const int lpc = s.dim <= 256 ? 16 : 64;
+  const int grp = threadIdx.x / lpc, sub = threadIdx.x % lpc;
+  for (int i = grp; i < m; i += kThreads / lpc) {
     const int32_t slot = (int32_t)(uint32_t)(key[i] & 0xffffffffu);
     const int32_t pos = s.seg[seg0 + slot].pos;
-    const float d = exact_dist(s.raw, pos, s.dim, qv);
-    if (lane == 0) {
-      topd[i] = d;
+    const float d = group_dist(s.raw, pos, s.dim, qv, sub, lpc);
+    if (sub == 0) {
       toppos[i] = pos;
       s.seg[seg0 + slot].pos = -1;
+      // exact distances are >= 0, so their bits order like the values; ids < 2^31
+      key2[i] = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)s.ids[pos];
     }
   }
-  __syncthreads();
-  // order the seeds by (distance, original id)
   int m2 = 1;
   while (m2 < m) m2 <<= 1;
-  for (int i = threadIdx.x; i < m2; i += kThreads)
-    key2[i] = (i < m) ? (((uint64_t)__float_as_uint(topd[i]) << 32) | (uint32_t)i) : ~0ull;
+  for (int i = m + threadIdx.x; i < m2; i += kThreads) key2[i] = ~0ull;
   __syncthreads();
-  // distances are >= 0, so float bits sort like values; ties: by original id below
+  // sort the seeds by (distance, original id), carrying their positions
   for (int size = 2; size <= m2; size <<= 1)
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = threadIdx.x; i < m2 / 2; i += kThreads) {
         const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
         const bool up = (lo & size) == 0;
         const uint64_t x = key2[lo], y = key2[hi];
-        bool gt;
-        if ((x >> 32) != (y >> 32)) {
-          gt = x > y;
-        } else if (x == ~0ull || y == ~0ull) {
-          gt = x > y;
-        } else {
-          gt = s.ids[toppos[(uint32_t)x]] > s.ids[toppos[(uint32_t)y]];
-        }
-        if (gt == up) {
+        if ((x > y) == up) {
           key2[lo] = y;
           key2[hi] = x;
+          const int32_t t = toppos[lo];   // padding entries carry garbage positions
+          toppos[lo] = toppos[hi];        // and sort to the end with their keys
+          toppos[hi] = t;
         }
       }
       __syncthreads();
@@ -469,30 +507,37 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
   for (int i = threadIdx.x; i < s.k; i += kThreads) {
     SeedEnt e;
     if (i < m) {
-      const int src = (int)(uint32_t)(key2[i] & 0xffffffffu);
-      e.dist = topd[src];
-      e.pos = toppos[src];
+      e.dist = __uint_as_float((uint32_t)(key2[i] >> 32));
+      e.pos = toppos[i];
     } else {
       e.dist = __builtin_inff();
       e.pos = -1;
     }
     s.seedk[q * s.k + i] = e;
   }
-  if (threadIdx.x == 0) {
-    float t = __builtin_inff();
-    if (m == s.k) t = topd[(uint32_t)(key2[s.k - 1] & 0xffffffffu)];
-    s.tau[q] = t;
-  }
+  if (threadIdx.x == 0) s.tau[q] = (m == s.k) ? __uint_as_float((uint32_t)(key2[s.k - 1] >> 32)) : __builtin_inff();
 }
 
 // ------------------------------------------------------------------ finalize (S7)
+// One block per query. The top-k starts from the bootstrap seeds (tau = their
+// k-th distance). Candidates are visited in probe order in rounds of 256: the
+// ones whose lower bound is still <= tau get their exact distance (groups of
+// lanes per candidate), then wave 0 inserts them in order and tau drops to the
+// running k-th exact distance.
+constexpr int kFinChunks = 1024;
+
 __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
-  __shared__ float qv[kMaxCodeBits];
+  extern __shared__ float qv[];          // dim floats
   __shared__ float td[kMaxK];
   __shared__ int64_t tid[kMaxK];
-  __shared__ int32_t cpos[kWave];
-  __shared__ float cd[kWave];
-  __shared__ int sh_n, sh_cnt;
+  __shared__ int64_t cbase[kFinChunks];
+  __shared__ int32_t cpre[kFinChunks + 1];
+  __shared__ int32_t part[kThreads];
+  __shared__ int32_t cpos[kThreads];
+  __shared__ float cd[kThreads];
+  __shared__ int64_t cid[kThreads];
+  __shared__ int32_t wcnt[kWaves];
+  __shared__ int sh_cnt;
   __shared__ float sh_tau;
   const int64_t q = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = lane_id();
@@ -500,10 +545,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
   for (int i = threadIdx.x; i < s.dim; i += kThreads) qv[i] = s.q[q * s.dim + i];
   int cnt0 = 0;
   for (int i = 0; i < K; ++i) {
-    const SeedEnt e = s.seedk[q * K + i];
-    if (e.pos < 0) break;
+    if (s.seedk[q * K + i].pos < 0) break;
     ++cnt0;
   }
+  cnt0 = uniform_i32(cnt0);
   for (int i = threadIdx.x; i < K; i += kThreads) {
     const SeedEnt e = s.seedk[q * K + i];
     td[i] = e.dist;
@@ -514,93 +559,124 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
     sh_tau = (cnt0 == K) ? s.seedk[q * K + K - 1].dist : __builtin_inff();
   }
   __syncthreads();
-  cnt0 = uniform_i32(cnt0);
+  const int lpc = s.dim <= 256 ? 16 : 64;
+  const int ngroups = kThreads / lpc;
+  const int grp = threadIdx.x / lpc, sub = threadIdx.x % lpc;
   int reranked = cnt0;
   int ncand_total = 0;
-  int P = s.nprobe;
-  if (s.nprobe_q) P = uniform_i32(min(max(s.nprobe_q[q], 1), s.nprobe));
-  const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
+  const int nch = uniform_i32(s.q_nch[q]);
+  const int p0 = uniform_i32(s.q_p0[q]);
+  const int64_t off0 = uniform_i64(s.off_p0[q]), off1 = uniform_i64(s.off_p1[q]);
+  const int64_t seg0 = uniform_i64(s.off_seg[q]), ch0 = uniform_i64(s.off_ch[q]);
   const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
-  const int64_t seg0 = uniform_i64(s.off_seg[q]);
-  const int64_t ch0 = uniform_i64(s.off_ch[q]);
-  for (int r = 0; r < P; ++r) {
-    const int nc = uniform_i32(choff[r + 1] - choff[r]);
-    for (int c = 0; c < nc; ++c) {
-      const int count = uniform_i32(s.seg_count[ch0 + choff[r] + c]);
-      const Cand* seg = s.seg + seg0 + codeoff[r] + (int64_t)c * s.chunk;
-      ncand_total += count;
-      for (int e0 = 0; e0 < count; e0 += kWave) {
-        if (wave == 0) {
-          const int e = e0 + lane;
-          bool pass = false;
-          Cand cand;
-          cand.pos = -1;
-          if (e < count) {
-            cand = seg[e];
-            pass = cand.pos >= 0 && cand.lb <= sh_tau;
-          }
-          const uint64_t m = __ballot(pass);
-          if (pass) cpos[__popcll(m & lanemask_lt())] = cand.pos;
-          if (lane == 0) sh_n = __popcll(m);
-        }
-        __syncthreads();
-        const int n = uniform_i32(sh_n);
-        if (n == 0) {
-          __syncthreads();
-          continue;
-        }
-        for (int i = wave; i < n; i += kWaves) {
-          const float d = exact_dist(s.raw, cpos[i], s.dim, qv);
-          if (lane == 0) cd[i] = d;
-        }
-        __syncthreads();
-        if (wave == 0) {
-          int cnt = uniform_i32(sh_cnt);
-          for (int i = 0; i < n; ++i) {
-            const float d = uniform_f32(cd[i]);
-            const int64_t id = uniform_i64(s.ids[cpos[i]]);
-            if (cnt == K && !less_di(d, id, td[K - 1], tid[K - 1])) continue;
-            // insertion position: entries that order before (d, id)
-            int before = 0;
-            for (int t = lane; t < cnt; t += kWave) before += less_di(td[t], tid[t], d, id);
-            before = wave_sum_i(before);
-            const int last = min(cnt, K - 1);   // entries [before, last) shift right by one
-            float sd[kMaxK / kWave];
-            int64_t si[kMaxK / kWave];
-#pragma unroll
-            for (int t = 0; t < kMaxK / kWave; ++t) {
-              const int x = lane + t * kWave;
-              if (x >= before && x < last) {
-                sd[t] = td[x];
-                si[t] = tid[x];
-              }
-            }
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int t = 0; t < kMaxK / kWave; ++t) {
-              const int x = lane + t * kWave;
-              if (x >= before && x < last) {
-                td[x + 1] = sd[t];
-                tid[x + 1] = si[t];
-              }
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) {
-              td[before] = d;
-              tid[before] = id;
-            }
-            __builtin_amdgcn_wave_barrier();
-            cnt = min(cnt + 1, K);
-          }
-          if (lane == 0) {
-            sh_cnt = cnt;
-            if (cnt == K) sh_tau = fminf(sh_tau, td[K - 1]);
-          }
-        }
-        reranked += n;
-        __syncthreads();
-      }
+  for (int j0 = 0; j0 < nch; j0 += kFinChunks) {
+    const int nj = min(kFinChunks, nch - j0);
+    // chunk bases and counts of this window, then an exclusive prefix of the counts
+    const int per = (nj + kThreads - 1) / kThreads;
+    int run = 0;
+    for (int t = threadIdx.x * per; t < min(nj, (int)(threadIdx.x + 1) * per); ++t) {
+      const int j = j0 + t;
+      const uint64_t e = j < p0 ? s.units0[off0 + j] : s.units1[off1 + (j - p0)];
+      const int r = (int)((e >> 28) & 1023u), c = (int)(e & ((1u << 28) - 1u));
+      cbase[t] = seg0 + codeoff[r] + (int64_t)c * s.chunk;
+      const int cnt = s.seg_count[ch0 + j];
+      cpre[t] = run;
+      run += cnt;
     }
+    part[threadIdx.x] = run;
+    __syncthreads();
+    for (int o = 1; o < kThreads; o <<= 1) {
+      const int v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+      __syncthreads();
+      part[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int before = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+    for (int t = threadIdx.x * per; t < min(nj, (int)(threadIdx.x + 1) * per); ++t) cpre[t] += before;
+    if (threadIdx.x == kThreads - 1) cpre[nj] = part[kThreads - 1];
+    __syncthreads();
+    const int T = uniform_i32(cpre[nj]);
+    ncand_total += T;
+    for (int e0 = 0; e0 < T; e0 += kThreads) {
+      const int e = e0 + threadIdx.x;
+      const int ec = e < T ? e : T - 1;     // lanes past the end re-read the last entry
+      const float tau = sh_tau;
+      int lo = 0, hi = nj;                  // last chunk with cpre <= ec
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cpre[mid] <= ec) lo = mid; else hi = mid;
+      }
+      const Cand cand = s.seg[cbase[lo] + (ec - cpre[lo])];
+      const int32_t pos = cand.pos;
+      const bool pass = e < T && cand.pos >= 0 && cand.lb <= tau;
+      const uint64_t m = __ballot(pass);
+      if (lane == 0) wcnt[wave] = __popcll(m);
+      __syncthreads();
+      int base = 0;
+      for (int w = 0; w < wave; ++w) base += wcnt[w];
+      if (pass) cpos[base + __popcll(m & lanemask_lt())] = pos;
+      const int n = uniform_i32(wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
+      __syncthreads();
+      if (n == 0) continue;
+      for (int i = grp; i < n; i += ngroups) {
+        const int32_t pi = cpos[i];
+        const float d = group_dist(s.raw, pi, s.dim, qv, sub, lpc);
+        if (sub == 0) {
+          cd[i] = d;
+          cid[i] = s.ids[pi];
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {
+        int cnt = uniform_i32(sh_cnt);
+        float kth = uniform_f32(td[K - 1]);
+        int64_t kid = uniform_i64(tid[K - 1]);
+        for (int i = 0; i < n; ++i) {
+          const float d = uniform_f32(cd[i]);
+          const int64_t id = uniform_i64(cid[i]);
+          if (cnt == K && !less_di(d, id, kth, kid)) continue;
+          int bef = 0;
+          for (int t = lane; t < cnt; t += kWave) bef += less_di(td[t], tid[t], d, id);
+          bef = wave_sum_i(bef);
+          const int last = min(cnt, K - 1);   // entries [bef, last) shift right by one
+          float sd[kMaxK / kWave];
+          int64_t si[kMaxK / kWave];
+#pragma unroll
+          for (int t = 0; t < kMaxK / kWave; ++t) {
+            const int x = lane + t * kWave;
+            if (x >= bef && x < last) {
+              sd[t] = td[x];
+              si[t] = tid[x];
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int t = 0; t < kMaxK / kWave; ++t) {
+            const int x = lane + t * kWave;
+            if (x >= bef && x < last) {
+              td[x + 1] = sd[t];
+              tid[x + 1] = si[t];
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (lane == 0) {
+            td[bef] = d;
+            tid[bef] = id;
+          }
+          __builtin_amdgcn_wave_barrier();
+          cnt = min(cnt + 1, K);
+          kth = uniform_f32(td[K - 1]);
+          kid = uniform_i64(tid[K - 1]);
+        }
+        if (lane == 0) {
+          sh_cnt = cnt;
+          if (cnt == K) sh_tau = fminf(sh_tau, td[K - 1]);
+        }
+      }
+      reranked += n;
+      __syncthreads();
+    }
+    __syncthreads();
   }
   const int cnt = uniform_i32(sh_cnt);
   for (int i = threadIdx.x; i < K; i += kThreads) {
@@ -679,9 +755,9 @@ __global__ __launch_bounds__(kThreads) void k_debug_scan(SearchDev s, const Pair
   lb_o[o] = lb;
 }
 
-template <int WS>
+template <int WS, int UN>
 void launch_scan_ws(const SearchDev& s, int phase, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan_popcnt<WS>, dim3(grid), dim3(kThreads), 0, st, s, phase);
+  hipLaunchKernelGGL((k_scan_popcnt<WS, UN>), dim3(grid), dim3(kThreads), 0, st, s, phase);
 }
 
 }  // namespace
@@ -698,29 +774,30 @@ hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_plan, dim3((unsigned)((s.nq + 255) / 256)), dim3(256), 0, st, s);
   hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, st, s);
+  hipLaunchKernelGGL(k_units, dim3((unsigned)((s.nq + 255) / 256)), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 
 hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st) {
   switch (s.W) {
-    case 1: launch_scan_ws<1>(s, phase, grid, st); break;
-    case 2: launch_scan_ws<2>(s, phase, grid, st); break;
-    case 3: launch_scan_ws<3>(s, phase, grid, st); break;
-    case 4: launch_scan_ws<4>(s, phase, grid, st); break;
-    default: launch_scan_ws<0>(s, phase, grid, st); break;
+    case 1: launch_scan_ws<1, 4>(s, phase, grid, st); break;
+    case 2: launch_scan_ws<2, 4>(s, phase, grid, st); break;
+    case 3: launch_scan_ws<3, 4>(s, phase, grid, st); break;
+    case 4: launch_scan_ws<4, 2>(s, phase, grid, st); break;
+    default: launch_scan_ws<0, 2>(s, phase, grid, st); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_tau(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tau, dim3((unsigned)s.nq), dim3(kThreads), 0, st, s);
+  hipLaunchKernelGGL(k_tau, dim3((unsigned)s.nq), dim3(kThreads), (size_t)s.dim * 4, st, s);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)s.nq), dim3(kThreads), 0, st, s);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)s.nq), dim3(kThreads), (size_t)s.dim * 4, st, s);
   return hipGetLastError();
 }
 

@@ -181,7 +181,9 @@ struct SearchDev {
   int64_t* off_p1;          // nq+1 prefix of q_nch - q_p0
   int64_t* off_seg;         // nq+1 prefix of q_ncode
   int64_t* off_n0;          // nq+1 prefix of q_n0
-  unsigned long long* counters;  // work counters: [0] bootstrap scan, [1] main scan, [2] MFMA scan
+  unsigned long long* counters;  // work counters: [2] MFMA scan
+  uint64_t* units0;         // bootstrap work units (query, rank, chunk)
+  uint64_t* units1;         // main-phase work units
   // buffers
   Cand* seg;                // segment slots
   int32_t* seg_count;       // per chunk

@@ -29,7 +29,7 @@ struct Workspace {
   DBuf qrot, cd, probe, probe_d, pairs, planes, qu8, pair_choff, pair_codeoff;
   DBuf q_nch, q_p0, q_n0, q_ncode, offs, counters, seg, seg_count, p0buf, tau, seedk;
   DBuf q_rerank, q_cand, nprobe_q, feats, tmp;
-  DBuf mf_cnt, mf_fill, mf_pair_off, mf_unit_off, mf_pairs;
+  DBuf mf_cnt, mf_fill, mf_pair_off, mf_unit_off, mf_pairs, units0, units1;
 };
 
 struct ProfState {

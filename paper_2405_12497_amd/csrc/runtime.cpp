@@ -202,7 +202,8 @@ std::vector<DBuf*> rbq_index::all_buffers() {
           &ws.planes, &ws.qu8, &ws.pair_choff, &ws.pair_codeoff, &ws.q_nch, &ws.q_p0, &ws.q_n0,
           &ws.q_ncode, &ws.offs, &ws.counters, &ws.seg, &ws.seg_count, &ws.p0buf, &ws.tau,
           &ws.seedk, &ws.q_rerank, &ws.q_cand, &ws.nprobe_q, &ws.feats, &ws.tmp,
-          &ws.mf_cnt, &ws.mf_fill, &ws.mf_pair_off, &ws.mf_unit_off, &ws.mf_pairs,
+          &ws.mf_cnt, &ws.mf_fill, &ws.mf_pair_off, &ws.mf_unit_off, &ws.mf_pairs, &ws.units0,
+          &ws.units1,
           &mlp.w32, &mlp.wbf, &mlp.grad, &mlp.m, &mlp.v, &mlp.act};
 }
 
@@ -492,6 +493,8 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.counters.ensure(64));
   HIPCHK(w.seg.ensure((size_t)nq * std::max<int64_t>(1, idx->max_codes(nprobe)) * sizeof(Cand)));
   HIPCHK(w.seg_count.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
+  HIPCHK(w.units0.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 8));
+  HIPCHK(w.units1.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 8));
   HIPCHK(w.p0buf.ensure((size_t)nq * (k - 1 + chunk) * sizeof(EstEnt)));
   HIPCHK(w.tau.ensure((size_t)nq * 4));
   HIPCHK(w.seedk.ensure((size_t)nq * k * sizeof(SeedEnt)));
@@ -556,6 +559,8 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.mf_pair_off = (int64_t*)w.mf_pair_off.p;
   s.mf_unit_off = (int64_t*)w.mf_unit_off.p;
   s.mf_pairs = (int32_t*)w.mf_pairs.p;
+  s.units0 = (uint64_t*)w.units0.p;
+  s.units1 = (uint64_t*)w.units1.p;
   s.out_ids = out_ids;
   s.out_d = out_d;
   return s;
