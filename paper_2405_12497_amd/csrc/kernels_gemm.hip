@@ -81,6 +81,91 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float* __restrict__ A, i
   }
 }
 
+// 128 x 128 output tile, 8 x 8 per thread (rows ty*4 + {0..3, 64..67}, cols
+// tx*4 + {0..3, 64..67}), K step 8. Same modes as k_gemm_f32.
+constexpr int BM = 128, BN = 128, BKF = 8;
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_f32_big(const float* __restrict__ A, int64_t lda,
+                                                      const float* __restrict__ sub,
+                                                      const int32_t* __restrict__ sel,
+                                                      const float* __restrict__ B, int64_t ldb,
+                                                      float* __restrict__ Y, int64_t ldy, int64_t M,
+                                                      int N, int K, const float* __restrict__ an,
+                                                      const float* __restrict__ bn) {
+  __shared__ __attribute__((aligned(16))) float As[BKF][BM];
+  __shared__ __attribute__((aligned(16))) float Bs[BKF][BN];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  float acc[8][8] = {};
+  // A loader: 128 rows x 8 k: thread loads 4 consecutive k of row tid>>1
+  const int la_r = tid >> 1, la_k = (tid & 1) * 4;
+  const int64_t am = m0 + la_r;
+  const float* arow = (am < M) ? A + am * lda : nullptr;
+  const float* srow = (am < M && sel) ? sub + (int64_t)sel[am] * K : nullptr;
+  // B loader: 8 k x 128 n: thread loads 4 consecutive n of k = tid>>5
+  const int lb_k = tid >> 5, lb_n = (tid & 31) * 4;
+  for (int k0 = 0; k0 < K; k0 += BKF) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int kk = k0 + la_k + i;
+      float v = 0.f;
+      if (arow && kk < K) {
+        v = arow[kk];
+        if (srow) v -= srow[kk];
+      }
+      As[la_k + i][la_r] = v;
+    }
+    {
+      const int kk = k0 + lb_k;
+      const int nn = n0 + lb_n;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (kk < K) {
+        const float* brow = B + (int64_t)kk * ldb;
+        if (nn + 3 < N && ((ldb & 3) == 0)) {
+          v = *reinterpret_cast<const float4*>(brow + nn);
+        } else {
+          if (nn < N) v.x = brow[nn];
+          if (nn + 1 < N) v.y = brow[nn + 1];
+          if (nn + 2 < N) v.z = brow[nn + 2];
+          if (nn + 3 < N) v.w = brow[nn + 3];
+        }
+      }
+      *reinterpret_cast<float4*>(&Bs[lb_k][lb_n]) = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BKF; ++kk) {
+      const float4 a0 = *reinterpret_cast<const float4*>(&As[kk][ty * 4]);
+      const float4 a1 = *reinterpret_cast<const float4*>(&As[kk][ty * 4 + 64]);
+      const float4 b0 = *reinterpret_cast<const float4*>(&Bs[kk][tx * 4]);
+      const float4 b1 = *reinterpret_cast<const float4*>(&Bs[kk][tx * 4 + 64]);
+      const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+      const float b[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t m = m0 + ty * 4 + (i & 3) + (i >> 2) * 64;
+    if (m >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int n = n0 + tx * 4 + (j & 3) + (j >> 2) * 64;
+      if (n >= N) continue;
+      float v = acc[i][j];
+      if (MODE == 1) v = fmaxf(an[m] + bn[n] - 2.f * v, 0.f);
+      Y[m * ldy + n] = v;
+    }
+  }
+}
+
 __global__ void k_rownorm(const float* __restrict__ X, int64_t M, int K, float* __restrict__ out) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= M) return;
@@ -263,9 +348,15 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* sub, const 
                            const float* B, int64_t ldb, float* Y, int64_t ldy, int64_t M, int N,
                            int K, hipStream_t st) {
   if (M <= 0) return hipSuccess;
-  dim3 grid((unsigned)((M + TM - 1) / TM), (N + TN - 1) / TN);
-  hipLaunchKernelGGL(k_gemm_f32<0>, grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy, M,
-                     N, K, nullptr, nullptr);
+  if (M >= 2048) {
+    dim3 grid((unsigned)((M + BM - 1) / BM), (N + BN - 1) / BN);
+    hipLaunchKernelGGL(k_gemm_f32_big<0>, grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
+                       M, N, K, nullptr, nullptr);
+  } else {
+    dim3 grid((unsigned)((M + TM - 1) / TM), (N + TN - 1) / TN);
+    hipLaunchKernelGGL(k_gemm_f32<0>, grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy, M,
+                       N, K, nullptr, nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -285,9 +376,15 @@ hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float
   // separate small buffer carved after D (caller provides nq floats there).
   float* qn = D + nq * (int64_t)nlist;
   hipLaunchKernelGGL(k_rownorm, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, Q, nq, dim, qn);
-  dim3 grid((unsigned)((nq + TM - 1) / TM), (nlist + TN - 1) / TN);
-  hipLaunchKernelGGL(k_gemm_f32<1>, grid, dim3(256), 0, st, Q, (int64_t)dim, nullptr, nullptr, Ct,
-                     (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim, qn, cn);
+  if (nq >= 256 && nlist >= 128) {
+    dim3 grid((unsigned)((nq + BM - 1) / BM), (nlist + BN - 1) / BN);
+    hipLaunchKernelGGL(k_gemm_f32_big<1>, grid, dim3(256), 0, st, Q, (int64_t)dim, nullptr, nullptr,
+                       Ct, (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim, qn, cn);
+  } else {
+    dim3 grid((unsigned)((nq + TM - 1) / TM), (nlist + TN - 1) / TN);
+    hipLaunchKernelGGL(k_gemm_f32<1>, grid, dim3(256), 0, st, Q, (int64_t)dim, nullptr, nullptr, Ct,
+                       (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim, qn, cn);
+  }
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@ namespace rbq {
 namespace {
 
 constexpr int kSelThreads = 256;
+constexpr int kSelCap = 2048;   // keys kept by the sampled threshold (>= kMaxNprobe)
 
 // Bitonic sort of n (power of two) 64-bit keys in LDS, ascending.
 __device__ void bitonic_sort_u64(uint64_t* a, int n) {
@@ -35,15 +36,75 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __res
                                                               float* __restrict__ dists) {
   extern __shared__ uint32_t keys[];                    // nlist
   __shared__ uint32_t hist[256];
-  __shared__ uint64_t sel[kMaxNprobe];
+  __shared__ uint64_t sel[kSelCap];
+  __shared__ uint32_t samp[256];
   __shared__ uint32_t sh_prefix, sh_rank, sh_nless;
   __shared__ uint32_t tie_scan[kSelThreads];
+  __shared__ int32_t wcnt[kSelThreads / 64];
   const int64_t q = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int P = nprobe;
   if (nprobe_q) P = uniform_i32(min(max(nprobe_q[q], 1), nprobe));
   P = min(P, nlist);
   const float* row = D + q * (int64_t)nlist;
   for (int k = threadIdx.x; k < nlist; k += blockDim.x) keys[k] = __float_as_uint(fmaxf(row[k], 0.f));
+  __syncthreads();
+  // Sampled threshold: sort 256 evenly spaced keys and cut at a sample rank
+  // expected to leave about 1.5 P + 32 keys at or below it. If that many keys
+  // are kept (and they fit), sorting only them gives the answer; otherwise the
+  // exact radix selection below runs.
+  if (nlist >= 1024) {
+    const int stride = nlist / 256;
+    samp[threadIdx.x] = keys[threadIdx.x * stride];
+    __syncthreads();
+    for (int size = 2; size <= 256; size <<= 1)
+      for (int st = size >> 1; st > 0; st >>= 1) {
+        if (threadIdx.x < 128) {
+          const int i = threadIdx.x;
+          const int lo = 2 * i - (i & (st - 1)), hi = lo + st;
+          const bool up = (lo & size) == 0;
+          const uint32_t x = samp[lo], y = samp[hi];
+          if ((x > y) == up) {
+            samp[lo] = y;
+            samp[hi] = x;
+          }
+        }
+        __syncthreads();
+      }
+    const int sidx = min(255, (int)((1.5f * P + 32.f) * 256.f / (float)nlist) + 1);
+    const uint32_t cut = (uint32_t)uniform_i32((int)samp[sidx]);
+    int nk = 0;
+    for (int k0 = 0; k0 < nlist; k0 += kSelThreads) {
+      const int k = k0 + threadIdx.x;
+      const bool keep = k < nlist && keys[k] <= cut;
+      const uint64_t m = __ballot(keep);
+      if (lane == 0) wcnt[wave] = __popcll(m);
+      __syncthreads();
+      int at = nk;
+      for (int w = 0; w < wave; ++w) at += wcnt[w];
+      const int idx = at + __popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+      if (keep && idx < kSelCap) sel[idx] = ((uint64_t)keys[k] << 32) | (uint32_t)k;
+      nk = uniform_i32(nk + wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
+      __syncthreads();
+    }
+    if (nk >= P && nk <= kSelCap) {
+      int n2 = 1;
+      while (n2 < nk) n2 <<= 1;
+      for (int i = nk + threadIdx.x; i < n2; i += blockDim.x) sel[i] = ~0ull;
+      __syncthreads();
+      bitonic_sort_u64(sel, n2);
+      for (int i = threadIdx.x; i < nprobe; i += blockDim.x) {
+        if (i < P) {
+          lists[q * nprobe + i] = (int32_t)(uint32_t)(sel[i] & 0xffffffffu);
+          if (dists) dists[q * nprobe + i] = __uint_as_float((uint32_t)(sel[i] >> 32));
+        } else {
+          lists[q * nprobe + i] = -1;
+          if (dists) dists[q * nprobe + i] = __builtin_inff();
+        }
+      }
+      return;
+    }
+  }
   if (threadIdx.x == 0) {
     sh_prefix = 0;
     sh_rank = P;

@@ -115,6 +115,120 @@ __global__ __launch_bounds__(kThreads) void k_prep(SearchDev s) {
   }
 }
 
+// Same computation for short codes (W <= 4 words): 4 pairs per wave, every
+// load of the 4 pairs issued before the reductions, values kept in registers.
+template <int WS>
+__global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
+  constexpr int PPW = 4;
+  const int lane = lane_id();
+  const int64_t npairs = s.nq * s.nprobe;
+  const int64_t g0 = uniform_i64(((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * PPW);
+  if (g0 >= npairs) return;
+  float rv[PPW][WS];
+  float bacc[PPW];
+  int list[PPW];
+  bool act[PPW];
+#pragma unroll
+  for (int j = 0; j < PPW; ++j) {
+    const int64_t g = g0 + j;
+    act[j] = false;
+    list[j] = -1;
+    bacc[j] = 0.f;
+#pragma unroll
+    for (int t = 0; t < WS; ++t) rv[j][t] = 0.f;
+    if (g < npairs) {
+      const int64_t q = g / s.nprobe;
+      const int r = (int)(g - q * s.nprobe);
+      int P = s.nprobe;
+      if (s.nprobe_q) P = uniform_i32(min(max(s.nprobe_q[q], 1), s.nprobe));
+      list[j] = uniform_i32(s.probe[g]);
+      act[j] = r < P && list[j] >= 0;
+      if (act[j]) {
+        const float* qrot = s.qrot + q * s.dp;
+        const float* crot = s.crot + (int64_t)list[j] * s.dp;
+#pragma unroll
+        for (int t = 0; t < WS; ++t) rv[j][t] = qrot[t * kWave + lane] - crot[t * kWave + lane];
+        const float* qr = s.q + q * s.dim;
+        const float* c = s.cent + (int64_t)list[j] * s.dim;
+#pragma unroll
+        for (int t = 0; t < WS; ++t) {
+          const int i = t * kWave + lane;
+          if (i < s.dim) {
+            const float d = qr[i] - c[i];
+            bacc[j] = fmaf(d, d, bacc[j]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PPW; ++j) {
+    const int64_t g = g0 + j;
+    if (g >= npairs) break;
+    PairRec rec;
+    if (!act[j]) {
+      if (lane == 0) {
+        rec.k1 = rec.k2 = rec.k0 = rec.b = rec.vl = rec.delta = 0.f;
+        rec.sq = 0;
+        rec.list = -1;
+        s.pairs[g] = rec;
+      }
+      continue;
+    }
+    const int64_t q = g / s.nprobe;
+    float rmin = rv[j][0], rmax = rv[j][0];
+#pragma unroll
+    for (int t = 1; t < WS; ++t) {
+      rmin = fminf(rmin, rv[j][t]);
+      rmax = fmaxf(rmax, rv[j][t]);
+    }
+    const float b = sqrtf(wave_sum(bacc[j]));
+    rmin = wave_min(rmin);
+    rmax = wave_max(rmax);
+    const float range = rmax - rmin;
+    const bool live = (b > 0.f) && (range > 0.f);
+    const float scale = live ? 15.f / range : 0.f;
+    const uint64_t qid = (uint64_t)(s.qid_base + q);
+    int sq = 0;
+    uint64_t* pl = s.planes + g * 4 * WS;
+    int8_t* q8 = s.qu8 ? s.qu8 + g * s.dp : nullptr;
+#pragma unroll
+    for (int t = 0; t < WS; ++t) {
+      const int i = t * kWave + lane;
+      int qu = 0;
+      if (live) {
+        const float x = (rv[j][t] - rmin) * scale;
+        qu = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
+      }
+      sq += qu;
+      if (q8) q8[i] = (int8_t)qu;
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        const uint64_t w = __ballot((qu >> jb) & 1);
+        if (lane == 0) pl[jb * WS + t] = w;
+      }
+    }
+    sq = wave_sum_i(sq);
+    if (lane == 0) {
+      const double rd = sqrt((double)s.dp);
+      double vl = 0.0, delta = 0.0;
+      if (b > 0.f) {
+        vl = (double)rmin / (double)b;
+        delta = (double)range / (15.0 * (double)b);
+      }
+      rec.k1 = (float)(2.0 * delta / rd);
+      rec.k2 = (float)(2.0 * vl / rd);
+      rec.k0 = (float)(-(delta / rd) * (double)sq - rd * vl);
+      rec.b = b;
+      rec.vl = (float)vl;
+      rec.delta = (float)delta;
+      rec.sq = sq;
+      rec.list = list[j];
+      s.pairs[g] = rec;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ planning
 // One thread per query: chunk and code prefixes over its probed pairs, and the
 // bootstrap (phase-0) chunk count.
@@ -416,9 +530,22 @@ __device__ __forceinline__ float group_dist(const float* __restrict__ raw, int64
                                             const float* __restrict__ qv, int sub, int lpc) {
   const float* o = raw + pos * dim;
   float acc = 0.f;
-  for (int i = sub; i < dim; i += lpc) {
-    const float d = o[i] - qv[i];
-    acc = fmaf(d, d, acc);
+  if ((dim & 3) == 0) {   // rows are 16-byte aligned: float4 loads
+    const float4* o4 = reinterpret_cast<const float4*>(o);
+    const float4* q4 = reinterpret_cast<const float4*>(qv);
+    for (int i = sub; i < (dim >> 2); i += lpc) {
+      const float4 a = o4[i], b = q4[i];
+      const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
+      acc = fmaf(dx, dx, acc);
+      acc = fmaf(dy, dy, acc);
+      acc = fmaf(dz, dz, acc);
+      acc = fmaf(dw, dw, acc);
+    }
+  } else {
+    for (int i = sub; i < dim; i += lpc) {
+      const float d = o[i] - qv[i];
+      acc = fmaf(d, d, acc);
+    }
   }
   for (int off = lpc >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
   return acc;
@@ -520,11 +647,23 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
 
 // ------------------------------------------------------------------ finalize (S7)
 // One block per query. The top-k starts from the bootstrap seeds (tau = their
-// k-th distance). Candidates are visited in probe order in rounds of 256: the
-// ones whose lower bound is still <= tau get their exact distance (groups of
-// lanes per candidate), then wave 0 inserts them in order and tau drops to the
-// running k-th exact distance.
-constexpr int kFinChunks = 1024;
+// k-th exact distance). The query's candidates are gathered in windows of up
+// to kFinWin entries, sorted by lower bound, and reranked in ascending-bound
+// rounds: a candidate is dropped when its bound exceeds tau (and, the window
+// being sorted, so is the rest of the window); the others get their exact
+// distance (groups of lanes per candidate), wave 0 inserts them in order and
+// tau drops to the running k-th exact distance.
+constexpr int kFinChunks = 256;
+constexpr int kFinWin = 1024;
+constexpr int kFinRound = 128;
+
+__device__ __forceinline__ uint32_t sortable_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float from_sortable(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
 
 __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
   extern __shared__ float qv[];          // dim floats
@@ -533,9 +672,9 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
   __shared__ int64_t cbase[kFinChunks];
   __shared__ int32_t cpre[kFinChunks + 1];
   __shared__ int32_t part[kThreads];
-  __shared__ int32_t cpos[kThreads];
-  __shared__ float cd[kThreads];
-  __shared__ int64_t cid[kThreads];
+  __shared__ uint64_t win[kFinWin];      // (sortable lb << 32) | position
+  __shared__ float cd[kFinRound];
+  __shared__ int64_t cid[kFinRound];
   __shared__ int32_t wcnt[kWaves];
   __shared__ int sh_cnt;
   __shared__ float sh_tau;
@@ -571,7 +710,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
   const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
   for (int j0 = 0; j0 < nch; j0 += kFinChunks) {
     const int nj = min(kFinChunks, nch - j0);
-    // chunk bases and counts of this window, then an exclusive prefix of the counts
+    // chunk bases and counts of this chunk window, then an exclusive prefix of the counts
     const int per = (nj + kThreads - 1) / kThreads;
     int run = 0;
     for (int t = threadIdx.x * per; t < min(nj, (int)(threadIdx.x + 1) * per); ++t) {
@@ -579,9 +718,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
       const uint64_t e = j < p0 ? s.units0[off0 + j] : s.units1[off1 + (j - p0)];
       const int r = (int)((e >> 28) & 1023u), c = (int)(e & ((1u << 28) - 1u));
       cbase[t] = seg0 + codeoff[r] + (int64_t)c * s.chunk;
-      const int cnt = s.seg_count[ch0 + j];
       cpre[t] = run;
-      run += cnt;
+      run += s.seg_count[ch0 + j];
     }
     part[threadIdx.x] = run;
     __syncthreads();
@@ -597,83 +735,121 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
     __syncthreads();
     const int T = uniform_i32(cpre[nj]);
     ncand_total += T;
-    for (int e0 = 0; e0 < T; e0 += kThreads) {
-      const int e = e0 + threadIdx.x;
-      const int ec = e < T ? e : T - 1;     // lanes past the end re-read the last entry
-      const float tau = sh_tau;
-      int lo = 0, hi = nj;                  // last chunk with cpre <= ec
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (cpre[mid] <= ec) lo = mid; else hi = mid;
-      }
-      const Cand cand = s.seg[cbase[lo] + (ec - cpre[lo])];
-      const int32_t pos = cand.pos;
-      const bool pass = e < T && cand.pos >= 0 && cand.lb <= tau;
-      const uint64_t m = __ballot(pass);
-      if (lane == 0) wcnt[wave] = __popcll(m);
-      __syncthreads();
-      int base = 0;
-      for (int w = 0; w < wave; ++w) base += wcnt[w];
-      if (pass) cpos[base + __popcll(m & lanemask_lt())] = pos;
-      const int n = uniform_i32(wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
-      __syncthreads();
-      if (n == 0) continue;
-      for (int i = grp; i < n; i += ngroups) {
-        const int32_t pi = cpos[i];
-        const float d = group_dist(s.raw, pi, s.dim, qv, sub, lpc);
-        if (sub == 0) {
-          cd[i] = d;
-          cid[i] = s.ids[pi];
+    for (int w0 = 0; w0 < T; w0 += kFinWin) {
+      const int nw = min(kFinWin, T - w0);
+      // gather the window: live entries whose bound does not exceed tau
+      const float tau0 = uniform_f32(sh_tau);
+      int nk = 0;
+      for (int e0 = 0; e0 < nw; e0 += kThreads) {
+        const int e = w0 + e0 + threadIdx.x;
+        const int ec = e < w0 + nw ? e : w0 + nw - 1;   // lanes past the end re-read the last entry
+        int lo = 0, hi = nj;                             // last chunk with cpre <= ec
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (cpre[mid] <= ec) lo = mid; else hi = mid;
         }
+        const Cand cand = s.seg[cbase[lo] + (ec - cpre[lo])];
+        const bool keep = e < w0 + nw && cand.pos >= 0 && cand.lb <= tau0;
+        const uint64_t m = __ballot(keep);
+        if (lane == 0) wcnt[wave] = __popcll(m);
+        __syncthreads();
+        int at = nk;
+        for (int w = 0; w < wave; ++w) at += wcnt[w];
+        if (keep) win[at + __popcll(m & lanemask_lt())] = ((uint64_t)sortable_bits(cand.lb) << 32) | (uint32_t)cand.pos;
+        nk = uniform_i32(nk + wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
+        __syncthreads();
       }
+      if (nk == 0) continue;
+      int n2 = 1;
+      while (n2 < nk) n2 <<= 1;
+      for (int i = nk + threadIdx.x; i < n2; i += kThreads) win[i] = ~0ull;
       __syncthreads();
-      if (wave == 0) {
-        int cnt = uniform_i32(sh_cnt);
-        float kth = uniform_f32(td[K - 1]);
-        int64_t kid = uniform_i64(tid[K - 1]);
-        for (int i = 0; i < n; ++i) {
-          const float d = uniform_f32(cd[i]);
-          const int64_t id = uniform_i64(cid[i]);
-          if (cnt == K && !less_di(d, id, kth, kid)) continue;
-          int bef = 0;
-          for (int t = lane; t < cnt; t += kWave) bef += less_di(td[t], tid[t], d, id);
-          bef = wave_sum_i(bef);
-          const int last = min(cnt, K - 1);   // entries [bef, last) shift right by one
-          float sd[kMaxK / kWave];
-          int64_t si[kMaxK / kWave];
-#pragma unroll
-          for (int t = 0; t < kMaxK / kWave; ++t) {
-            const int x = lane + t * kWave;
-            if (x >= bef && x < last) {
-              sd[t] = td[x];
-              si[t] = tid[x];
+      for (int size = 2; size <= n2; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          for (int i = threadIdx.x; i < n2 / 2; i += kThreads) {
+            const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+            const bool up = (lo & size) == 0;
+            const uint64_t x = win[lo], y = win[hi];
+            if ((x > y) == up) {
+              win[lo] = y;
+              win[hi] = x;
             }
           }
-          __builtin_amdgcn_wave_barrier();
-#pragma unroll
-          for (int t = 0; t < kMaxK / kWave; ++t) {
-            const int x = lane + t * kWave;
-            if (x >= bef && x < last) {
-              td[x + 1] = sd[t];
-              tid[x + 1] = si[t];
-            }
+          __syncthreads();
+        }
+      // ascending-bound rounds
+      for (int r0 = 0; r0 < nk; r0 += kFinRound) {
+        const float tau = uniform_f32(sh_tau);
+        const float lb0 = uniform_f32(from_sortable((uint32_t)(win[r0] >> 32)));
+        if (lb0 > tau) break;   // sorted: the rest of the window is above tau too
+        const int rn = min(kFinRound, nk - r0);
+        int n = 0;                         // prefix of the round with bound <= tau
+        {
+          int lo = 0, hi = rn;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (from_sortable((uint32_t)(win[r0 + mid] >> 32)) <= tau) lo = mid + 1; else hi = mid;
           }
-          __builtin_amdgcn_wave_barrier();
+          n = uniform_i32(lo);
+        }
+        for (int i = grp; i < n; i += ngroups) {
+          const int32_t pi = (int32_t)(uint32_t)(win[r0 + i] & 0xffffffffu);
+          const float d = group_dist(s.raw, pi, s.dim, qv, sub, lpc);
+          if (sub == 0) {
+            cd[i] = d;
+            cid[i] = s.ids[pi];
+          }
+        }
+        __syncthreads();
+        if (wave == 0) {
+          int cnt = uniform_i32(sh_cnt);
+          float kth = uniform_f32(td[K - 1]);
+          int64_t kid = uniform_i64(tid[K - 1]);
+          for (int i = 0; i < n; ++i) {
+            const float d = uniform_f32(cd[i]);
+            const int64_t id = uniform_i64(cid[i]);
+            if (cnt == K && !less_di(d, id, kth, kid)) continue;
+            int bef = 0;
+            for (int t = lane; t < cnt; t += kWave) bef += less_di(td[t], tid[t], d, id);
+            bef = wave_sum_i(bef);
+            const int last = min(cnt, K - 1);   // entries [bef, last) shift right by one
+            float sd[kMaxK / kWave];
+            int64_t si[kMaxK / kWave];
+#pragma unroll
+            for (int t = 0; t < kMaxK / kWave; ++t) {
+              const int x = lane + t * kWave;
+              if (x >= bef && x < last) {
+                sd[t] = td[x];
+                si[t] = tid[x];
+              }
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int t = 0; t < kMaxK / kWave; ++t) {
+              const int x = lane + t * kWave;
+              if (x >= bef && x < last) {
+                td[x + 1] = sd[t];
+                tid[x + 1] = si[t];
+              }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+              td[bef] = d;
+              tid[bef] = id;
+            }
+            __builtin_amdgcn_wave_barrier();
+            cnt = min(cnt + 1, K);
+            kth = uniform_f32(td[K - 1]);
+            kid = uniform_i64(tid[K - 1]);
+          }
           if (lane == 0) {
-            td[bef] = d;
-            tid[bef] = id;
+            sh_cnt = cnt;
+            if (cnt == K) sh_tau = fminf(sh_tau, td[K - 1]);
           }
-          __builtin_amdgcn_wave_barrier();
-          cnt = min(cnt + 1, K);
-          kth = uniform_f32(td[K - 1]);
-          kid = uniform_i64(tid[K - 1]);
         }
-        if (lane == 0) {
-          sh_cnt = cnt;
-          if (cnt == K) sh_tau = fminf(sh_tau, td[K - 1]);
-        }
+        reranked += n;
+        __syncthreads();
       }
-      reranked += n;
       __syncthreads();
     }
     __syncthreads();
@@ -765,8 +941,16 @@ void launch_scan_ws(const SearchDev& s, int phase, int grid, hipStream_t st) {
 hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st) {
   const int64_t npairs = s.nq * s.nprobe;
   if (npairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)((npairs + kWaves - 1) / kWaves)), dim3(kThreads), 0,
-                     st, s);
+  const unsigned g4 = (unsigned)((npairs + 4 * kWaves - 1) / (4 * kWaves));
+  switch (s.W) {
+    case 1: hipLaunchKernelGGL(k_prep_reg<1>, dim3(g4), dim3(kThreads), 0, st, s); break;
+    case 2: hipLaunchKernelGGL(k_prep_reg<2>, dim3(g4), dim3(kThreads), 0, st, s); break;
+    case 3: hipLaunchKernelGGL(k_prep_reg<3>, dim3(g4), dim3(kThreads), 0, st, s); break;
+    case 4: hipLaunchKernelGGL(k_prep_reg<4>, dim3(g4), dim3(kThreads), 0, st, s); break;
+    default:
+      hipLaunchKernelGGL(k_prep, dim3((unsigned)((npairs + kWaves - 1) / kWaves)), dim3(kThreads),
+                         0, st, s);
+  }
   return hipGetLastError();
 }
 

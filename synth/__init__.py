@@ -165,12 +165,13 @@ def _assign_numpy(x, cent, chunk=1 << 15):
 
 
 def _assign_torch(x, cent, device, chunk=1 << 16):
+    """Nearest-centroid assignment on a GPU in float64, so repeated runs agree."""
     import torch
-    c = torch.as_tensor(cent, dtype=torch.float32, device=device)
+    c = torch.as_tensor(cent, dtype=torch.float64, device=device)
     cn = (c * c).sum(1)
     out = np.empty(x.shape[0], dtype=np.int64)
     for s in range(0, x.shape[0], chunk):
-        xs = torch.as_tensor(x[s:s + chunk], dtype=torch.float32, device=device)
+        xs = torch.as_tensor(x[s:s + chunk], dtype=torch.float64, device=device)
         d = cn[None, :] - 2.0 * (xs @ c.T)
         out[s:s + chunk] = torch.argmin(d, dim=1).cpu().numpy()
     return out

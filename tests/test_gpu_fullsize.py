@@ -1,0 +1,111 @@
+"""Parity at full size: the 1M x 128 SIFT-like workload with 4096 lists, 10,000
+queries in one batch at nprobe = 32 (the configuration bench.py times),
+checked against the FP64 oracle on a sample of queries, plus probe selection
+at many lists / large batches (the sampled-threshold selection and the large
+GEMM tile)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rabitq_oracle as O
+
+from gpu_common import oracle_estimates_on, sqdist64, tie_equivalent, unpack_codes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[{msg}]", flush=True)
+    sys.stdout.flush()
+
+
+def test_probe_selection_many_lists_large_batch():
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    _say("probe selection, 4096 lists, 600 queries")
+    rng = np.random.default_rng(21)
+    cent = (rng.standard_normal((4096, 64)) * 3).astype(np.float32)
+    data = cent[rng.integers(0, 4096, 8192)] + rng.standard_normal((8192, 64)).astype(np.float32)
+    assign = np.argmin(((data[:, None, :] - cent[None]) ** 2).sum(-1), 1).astype(np.int32)
+    q = (cent[rng.integers(0, 4096, 600)] + rng.standard_normal((600, 64))).astype(np.float32)
+    # duplicated centroids force ties and the exact (radix) fallback for some queries
+    cent2 = cent.copy()
+    cent2[1000:3200] = cent2[999]
+    for cs in (cent, cent2):
+        idx = R.Index(64, 4096, seed=3)
+        idx.build(data, cs, assign, rng.standard_normal((64, 64)))
+        qt = torch.from_numpy(q).to("cuda")
+        for nprobe in (1, 7, 32, 300, 1024):
+            lists, d = R.rbq_debug_probe(idx.h, qt, nprobe)
+            lists, d = lists.cpu().numpy(), d.cpu().numpy()
+            for qi in range(0, 600, 37):
+                want = O.probe_lists(q[qi], cs, nprobe)
+                if np.array_equal(lists[qi], want):
+                    continue
+                dg = sqdist64(cs[lists[qi]], q[qi])
+                dw = sqdist64(cs[want], q[qi])
+                np.testing.assert_allclose(np.sort(dg), np.sort(dw), rtol=1e-5, atol=1e-4)
+            # nearest first, and distances match
+            assert np.all(np.diff(d, axis=1) >= 0)
+            np.testing.assert_allclose(d[::37], sqdist64(cs[lists[::37]], q[::37, None, :]), rtol=2e-4,
+                                       atol=2e-4 * float(d.max()))
+
+
+@pytest.fixture(scope="module")
+def sift1m():
+    import synth
+    _say("generating the 1M x 128 SIFT-like workload")
+    wl = synth.workload(2, n=1_000_000, nq=10_000, nlist=4096, device="cuda")
+    return wl
+
+
+def test_fullsize_search_sampled_against_oracle(sift1m):
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    wl = sift1m
+    _say("building the full-size index")
+    idx = R.Index(wl.dim, wl.centroids.shape[0], rot_precision=R.RBQ_ROT_FP32, seed=wl.seed)
+    idx.build(wl.data, wl.centroids, wl.assign, wl.gauss)
+    q = torch.from_numpy(wl.queries).to("cuda")
+    _say("searching 10000 queries, nprobe 32")
+    ids, dists, st = idx.search(q, 10, 32, scan_kernel=R.RBQ_SCAN_POPCNT, stats=True)
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    lists, _ = R.rbq_debug_probe(idx.h, q, 32)
+    lists = lists.cpu().numpy()
+    codes, norm, ipo = R.rbq_debug_export_codes(idx.h, len(wl.data), wl.dim_pad // 64)
+    bits = unpack_codes(codes, wl.dim_pad)
+    p = O.orthogonal_from_gaussian(wl.gauss)
+    rng = np.random.default_rng(0)
+    sample = rng.choice(len(wl.queries), 40, replace=False)
+    order = np.argsort(wl.assign, kind="stable")
+    bounds = np.searchsorted(wl.assign[order], np.arange(4097))
+    mism = viol = 0
+    for qi in sample:
+        qv = wl.queries[qi]
+        # probe lists: the oracle's nearest 32 centroids, up to near-ties
+        want = O.probe_lists(qv, wl.centroids, 32)
+        if not np.array_equal(np.sort(want), np.sort(lists[qi])):
+            dg = np.sort(sqdist64(wl.centroids[lists[qi]], qv))
+            dw = np.sort(sqdist64(wl.centroids[want], qv))
+            np.testing.assert_allclose(dg, dw, rtol=1e-5)
+        cand = np.concatenate([order[bounds[k]:bounds[k + 1]] for k in lists[qi]])
+        t_ids, t_d = O.exact_topk(wl.data, qv, 10, cand)
+        np.testing.assert_allclose(dists[qi], sqdist64(wl.data[ids[qi]], qv), rtol=2e-5, atol=1e-3)
+        if tie_equivalent(ids[qi], t_ids, qv, wl.data):
+            continue
+        mism += 1
+        # a differing query must have a true neighbour whose GPU-path bound failed
+        qu, scal = R.rbq_debug_quantize(idx.h, q[qi:qi + 1].contiguous(),
+                                        torch.from_numpy(lists[qi:qi + 1]).cuda(), wl.dim_pad, qid_base=int(qi))
+        qu, scal = qu.cpu().numpy().astype(np.int64), scal.cpu().numpy()
+        bad = False
+        for oid, dv in zip(t_ids, t_d):
+            r = int(np.flatnonzero(lists[qi] == wl.assign[oid])[0])
+            lbv = oracle_estimates_on(bits[oid:oid + 1], norm[oid:oid + 1], ipo[oid:oid + 1], qu[r],
+                                      scal[r, 0], scal[r, 1], scal[r, 2], wl.dim_pad)[4][0]
+            bad |= lbv > dv * (1 + 1e-6)
+        assert bad, f"query {qi}: differs from the exact top-10 of its probed lists without a bound failure"
+        viol += 1
+    print(f"full size: {mism} of {len(sample)} sampled queries differ, all with bound failures; stats {st}")
+    assert mism <= 6
