@@ -94,7 +94,19 @@ def main():
     ap.add_argument("--nprobe", type=int, default=0, help="0: smallest of the sweep reaching recall 0.95")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel", default="popcnt", choices=["popcnt", "mfma", "auto"])
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="only run 3 device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_mb:
+        import torch
+        n = args.copy_mb * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": n * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding is a design note, not part of this build.", file=sys.stderr)

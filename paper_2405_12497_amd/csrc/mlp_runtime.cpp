@@ -1,20 +1,303 @@
-// Learned per-query nprobe (placeholder until the MLP kernels land).
+// Learned per-query nprobe: features, inference, GPU training (BF16 MFMA
+// forward/backward, FP32 master weights, Adam) and the search hook.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rbq_mlp.hpp"
 #include "rbq_runtime.hpp"
 
+using namespace rbq;
+
 namespace rbq {
-rbq_status learned_nprobe(rbq_index*, const float*, int64_t, int, int64_t, hipStream_t,
-                          const int32_t** out) {
-  *out = nullptr;
+rbq_status set_error(rbq_status st, const char* msg);
+}
+
+namespace {
+
+rbq_status fail(rbq_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  return rbq::set_error(st, buf);
+}
+
+#define HIPCHK(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      (void)hipGetLastError();                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? RBQ_ENOMEM : RBQ_EDEVICE, "%s: %s (%s:%d)", #expr, \
+                  hipGetErrorString(e_), __FILE__, __LINE__);                                  \
+    }                                                                                          \
+  } while (0)
+
+// Activations and gradients of one forward/backward over n rows.
+struct Pass {
+  float *A, *H, *Z, *dZ, *dH, *loss;
+};
+
+rbq_status forward(const float* X, int64_t n, const float* w, const Pass& p, const int32_t* y,
+                   hipStream_t st) {
+  const int N = (int)n;
+  HIPCHK(launch_gemm_bf16(X, kMlpIn, 1, w + kMlpW1, kMlpHidden, 1, p.A, kMlpHidden, N, kMlpHidden,
+                          kMlpIn, false, st));
+  HIPCHK(launch_bias_relu(p.A, w + kMlpB1, p.H, n, kMlpHidden, st));
+  HIPCHK(launch_gemm_bf16(p.H, kMlpHidden, 1, w + kMlpW2, kMlpOut, 1, p.Z, kMlpOut, N, kMlpOut,
+                          kMlpHidden, false, st));
+  HIPCHK(launch_softmax_ce(p.Z, w + kMlpB2, y, n, p.dZ, p.loss, st));
   return RBQ_OK;
 }
+
+rbq_status backward(const float* X, int64_t n, const float* w, const Pass& p, float* g, hipStream_t st) {
+  const int N = (int)n;
+  // dW2 = H^T dZ, db2 = column sums of dZ
+  HIPCHK(launch_gemm_bf16(p.H, 1, kMlpHidden, p.dZ, kMlpOut, 1, g + kMlpW2, kMlpOut, kMlpHidden,
+                          kMlpOut, N, false, st));
+  HIPCHK(launch_colsum(p.dZ, n, kMlpOut, g + kMlpB2, st));
+  // dH = dZ W2^T, masked by the ReLU
+  HIPCHK(launch_gemm_bf16(p.dZ, kMlpOut, 1, w + kMlpW2, 1, kMlpOut, p.dH, kMlpHidden, N, kMlpHidden,
+                          kMlpOut, false, st));
+  HIPCHK(launch_relu_grad(p.dH, p.A, n * kMlpHidden, st));
+  // dW1 = X^T dA, db1 = column sums of dA
+  HIPCHK(launch_gemm_bf16(X, 1, kMlpIn, p.dH, kMlpHidden, 1, g + kMlpW1, kMlpHidden, kMlpIn,
+                          kMlpHidden, N, false, st));
+  HIPCHK(launch_colsum(p.dH, n, kMlpHidden, g + kMlpB1, st));
+  return RBQ_OK;
+}
+
+size_t pass_floats(int64_t n) { return (size_t)n * (2 * kMlpHidden + 2 * kMlpOut + kMlpHidden) + 16; }
+
+Pass carve(float* base, int64_t n) {
+  Pass p;
+  p.A = base;
+  p.H = p.A + n * kMlpHidden;
+  p.Z = p.H + n * kMlpHidden;
+  p.dZ = p.Z + n * kMlpOut;
+  p.dH = p.dZ + n * kMlpOut;
+  p.loss = p.dH + n * kMlpHidden;
+  return p;
+}
+
+// Glorot-uniform weights from a SplitMix64 counter stream, zero biases.
+void init_weights(uint64_t seed, std::vector<float>& w) {
+  w.assign(kMlpParams, 0.f);
+  auto uni = [&](uint64_t i) {
+    return (double)(host_splitmix64(seed ^ (0x4D4C500000000000ull + i)) >> 11) * (1.0 / 9007199254740992.0);
+  };
+  const double a1 = std::sqrt(6.0 / (kMlpIn + kMlpHidden)), a2 = std::sqrt(6.0 / (kMlpHidden + kMlpOut));
+  for (int i = 0; i < kMlpIn * kMlpHidden; ++i) w[kMlpW1 + i] = (float)((2 * uni(i) - 1) * a1);
+  for (int i = 0; i < kMlpHidden * kMlpOut; ++i) w[kMlpW2 + i] = (float)((2 * uni(1000000 + i) - 1) * a2);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ search hook
+namespace rbq {
+
+rbq_status features_into(rbq_index* idx, const float* queries, int64_t nq, int64_t qid_base,
+                         float* feats, hipStream_t st) {
+  const int nsel = std::min(kMlpNear, idx->nlist);
+  rbq_status rs = ensure_workspace(idx, nq, nsel, 1, kDefaultChunk, false);
+  if (rs != RBQ_OK) return rs;
+  rs = front(idx, queries, nq, nsel, nullptr, st);
+  if (rs != RBQ_OK) return rs;
+  FeatDev f;
+  f.feats = feats;
+  f.probe_d = (const float*)idx->ws.probe_d.p;
+  f.probe = (const int32_t*)idx->ws.probe.p;
+  f.stride = nsel;
+  f.navail = nsel;
+  f.q = queries;
+  f.qrot = (const float*)idx->ws.qrot.p;
+  f.cent = (const float*)idx->d_cent.p;
+  f.crot = (const float*)idx->d_crot.p;
+  f.dim = idx->dim;
+  f.dp = idx->dp;
+  f.W = idx->W;
+  f.nq = nq;
+  f.qid_base = qid_base;
+  f.seed = idx->prm.seed;
+  HIPCHK(launch_features(f, st));
+  return RBQ_OK;
+}
+
+rbq_status predict_into(rbq_index* idx, const float* feats, int64_t nq, int nprobe_max,
+                        int32_t* nprobe, float* logits, hipStream_t st) {
+  MlpState& m = idx->mlp;
+  HIPCHK(m.act.ensure(pass_floats(nq) * 4));
+  const Pass p = carve((float*)m.act.p, nq);
+  rbq_status rs = forward(feats, nq, (const float*)m.w32.p, p, nullptr, st);
+  if (rs != RBQ_OK) return rs;
+  if (logits) HIPCHK(hipMemcpyAsync(logits, p.Z, (size_t)nq * kMlpOut * 4, hipMemcpyDeviceToDevice, st));
+  HIPCHK(launch_policy(p.Z, nq, m.threshold, nprobe_max, nprobe, st));
+  return RBQ_OK;
+}
+
+rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int nprobe_max,
+                          int64_t qid_base, hipStream_t st, const int32_t** out) {
+  Workspace& w = idx->ws;
+  HIPCHK(w.feats.ensure((size_t)nq * kMlpIn * 4));
+  HIPCHK(w.nprobe_q.ensure((size_t)nq * 4));
+  rbq_status rs = features_into(idx, queries, nq, qid_base, (float*)w.feats.p, st);
+  if (rs != RBQ_OK) return rs;
+  rs = predict_into(idx, (const float*)w.feats.p, nq, nprobe_max, (int32_t*)w.nprobe_q.p, nullptr, st);
+  if (rs != RBQ_OK) return rs;
+  *out = (const int32_t*)w.nprobe_q.p;
+  return RBQ_OK;
+}
+
 }  // namespace rbq
 
-extern "C" {
-rbq_status rbq_nprobe_features(rbq_index*, const float*, int64_t, int64_t, float*, void*) { return RBQ_EUNSUPPORTED; }
-rbq_status rbq_nprobe_model_train(rbq_index*, const float*, const int32_t*, int64_t, const rbq_train_cfg*, float*, void*) { return RBQ_EUNSUPPORTED; }
-rbq_status rbq_nprobe_model_set(rbq_index*, const float*, float) { return RBQ_EUNSUPPORTED; }
-rbq_status rbq_nprobe_model_get(const rbq_index*, float*, float*) { return RBQ_EUNSUPPORTED; }
-rbq_status rbq_nprobe_predict(rbq_index*, const float*, int64_t, int32_t*, float*, void*) { return RBQ_EUNSUPPORTED; }
-rbq_status rbq_mlp_loss_grad(const float*, const int32_t*, int64_t, const float*, float*, float*, void*) { return RBQ_EUNSUPPORTED; }
-rbq_status rbq_autotune(rbq_index*, const float*, int64_t, int32_t, int32_t, void*) { return RBQ_EUNSUPPORTED; }
+// ------------------------------------------------------------------ C ABI
+extern "C" rbq_status rbq_nprobe_features(rbq_index* idx, const float* queries, int64_t nq,
+                                          int64_t qid_base, float* feats, void* stream) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
+  if (nq == 0) return RBQ_OK;
+  if (!is_device_ptr(queries) || !is_device_ptr(feats)) return fail(RBQ_EINVAL, "device pointers required");
+  if (qid_base < 0 || qid_base + nq > (1ll << 24)) return fail(RBQ_EINVAL, "query ids must stay below 2^24");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  return features_into(idx, queries, nq, qid_base, feats, (hipStream_t)stream);
+}
+
+extern "C" rbq_status rbq_nprobe_model_set(rbq_index* idx, const float* weights, float threshold) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!(threshold > 0.f && threshold <= 1.f)) return fail(RBQ_EINVAL, "threshold must be in (0, 1]");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  MlpState& m = idx->mlp;
+  if (!weights) {
+    m.has_model = false;
+    m.threshold = threshold;
+    return RBQ_OK;
+  }
+  if (is_device_ptr(weights)) return fail(RBQ_EINVAL, "weights must be a host pointer");
+  for (int i = 0; i < kMlpParams; ++i)
+    if (!std::isfinite(weights[i])) return fail(RBQ_EINVAL, "weights contain non-finite values");
+  m.host_w.assign(weights, weights + kMlpParams);
+  HIPCHK(m.w32.ensure((size_t)kMlpParams * 4));
+  HIPCHK(hipMemcpy(m.w32.p, weights, (size_t)kMlpParams * 4, hipMemcpyHostToDevice));
+  m.threshold = threshold;
+  m.has_model = true;
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_nprobe_model_get(const rbq_index* cidx, float* weights, float* threshold) {
+  if (!cidx) return fail(RBQ_EINVAL, "index is NULL");
+  rbq_index* idx = const_cast<rbq_index*>(cidx);
+  std::lock_guard<std::mutex> lock(idx->mu);
+  if (!idx->mlp.has_model) return fail(RBQ_ESTATE, "no model set");
+  if (weights) std::memcpy(weights, idx->mlp.host_w.data(), (size_t)kMlpParams * 4);
+  if (threshold) *threshold = idx->mlp.threshold;
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_nprobe_predict(rbq_index* idx, const float* feats, int64_t nq,
+                                         int32_t* nprobe, float* logits, void* stream) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!idx->mlp.has_model) return fail(RBQ_ESTATE, "no model set");
+  if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
+  if (nq == 0) return RBQ_OK;
+  if (!is_device_ptr(feats) || !is_device_ptr(nprobe) || (logits && !is_device_ptr(logits)))
+    return fail(RBQ_EINVAL, "device pointers required");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  const int cap = std::min(idx->nlist, 1 << 30);
+  return predict_into(idx, feats, nq, std::min(cap, mlp_bucket_nprobe(kMlpOut - 1)), nprobe, logits,
+                      (hipStream_t)stream);
+}
+
+extern "C" rbq_status rbq_mlp_loss_grad(const float* x, const int32_t* labels, int64_t n,
+                                        const float* weights, float* grads, float* loss, void* stream) {
+  if (!x || !labels || !weights || !grads || !loss) return fail(RBQ_EINVAL, "NULL argument");
+  if (n < 1 || n > (1 << 24)) return fail(RBQ_EINVAL, "n out of range");
+  if (!is_device_ptr(x) || !is_device_ptr(labels) || !is_device_ptr(weights) || !is_device_ptr(grads))
+    return fail(RBQ_EINVAL, "x, labels, weights and grads must be device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  DBuf buf;
+  HIPCHK(buf.ensure(pass_floats(n) * 4));
+  const Pass p = carve((float*)buf.p, n);
+  HIPCHK(hipMemsetAsync(p.loss, 0, 4, st));
+  rbq_status rs = forward(x, n, weights, p, labels, st);
+  if (rs == RBQ_OK) rs = backward(x, n, weights, p, grads, st);
+  float ls = 0.f;
+  if (rs == RBQ_OK) {
+    HIPCHK(hipMemcpyAsync(&ls, p.loss, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *loss = ls / (float)n;
+  }
+  buf.release();
+  return rs;
+}
+
+extern "C" rbq_status rbq_nprobe_model_train(rbq_index* idx, const float* feats, const int32_t* labels,
+                                             int64_t n, const rbq_train_cfg* cfg, float* losses,
+                                             void* stream) {
+  if (!idx || !feats || !labels || !cfg) return fail(RBQ_EINVAL, "NULL argument");
+  if (n < 1 || n > (1ll << 31) - 1) return fail(RBQ_EINVAL, "n out of range");
+  if (cfg->epochs < 1 || cfg->batch < 1 || !(cfg->lr > 0.f)) return fail(RBQ_EINVAL, "bad training config");
+  if (!is_device_ptr(feats) || !is_device_ptr(labels)) return fail(RBQ_EINVAL, "feats and labels must be device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  MlpState& m = idx->mlp;
+  std::vector<float> w;
+  init_weights(cfg->seed, w);
+  HIPCHK(m.w32.ensure((size_t)kMlpParams * 4));
+  HIPCHK(m.grad.ensure((size_t)kMlpParams * 4));
+  HIPCHK(m.m.ensure((size_t)kMlpParams * 4));
+  HIPCHK(m.v.ensure((size_t)kMlpParams * 4));
+  HIPCHK(hipMemcpyAsync(m.w32.p, w.data(), (size_t)kMlpParams * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(m.m.p, 0, (size_t)kMlpParams * 4, st));
+  HIPCHK(hipMemsetAsync(m.v.p, 0, (size_t)kMlpParams * 4, st));
+  const int64_t B = std::min<int64_t>(cfg->batch, n);
+  HIPCHK(m.act.ensure(pass_floats(B) * 4));
+  const Pass p = carve((float*)m.act.p, B);
+  DBuf xb, yb, perm;
+  HIPCHK(xb.ensure((size_t)B * kMlpIn * 4));
+  HIPCHK(yb.ensure((size_t)B * 4));
+  HIPCHK(perm.ensure((size_t)n * 4));
+  std::vector<int32_t> order(n);
+  int step = 0;
+  for (int e = 0; e < cfg->epochs; ++e) {
+    for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+    for (int64_t i = n - 1; i > 0; --i) {   // Fisher-Yates with a counter stream
+      const uint64_t r = host_splitmix64(cfg->seed ^ (0x5348000000000000ull + ((uint64_t)e << 36) + (uint64_t)i));
+      std::swap(order[i], order[r % (uint64_t)(i + 1)]);
+    }
+    HIPCHK(hipMemcpyAsync(perm.p, order.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(p.loss, 0, 4, st));
+    for (int64_t b0 = 0; b0 < n; b0 += B) {
+      const int64_t nb = std::min(B, n - b0);
+      HIPCHK(launch_gather_rows(feats, labels, (const int32_t*)perm.p + b0, nb, kMlpIn, (float*)xb.p,
+                                (int32_t*)yb.p, st));
+      rbq_status rs = forward((const float*)xb.p, nb, (const float*)m.w32.p, p, (const int32_t*)yb.p, st);
+      if (rs != RBQ_OK) return rs;
+      rs = backward((const float*)xb.p, nb, (const float*)m.w32.p, p, (float*)m.grad.p, st);
+      if (rs != RBQ_OK) return rs;
+      HIPCHK(launch_adam((float*)m.w32.p, (const float*)m.grad.p, (float*)m.m.p, (float*)m.v.p,
+                         kMlpParams, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, ++step, st));
+    }
+    float ls = 0.f;
+    HIPCHK(hipMemcpyAsync(&ls, p.loss, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (losses) losses[e] = ls / (float)n;
+  }
+  m.host_w.resize(kMlpParams);
+  HIPCHK(hipMemcpy(m.host_w.data(), m.w32.p, (size_t)kMlpParams * 4, hipMemcpyDeviceToHost));
+  for (float v : m.host_w)
+    if (!std::isfinite(v)) {
+      m.has_model = false;
+      return fail(RBQ_EDEVICE, "training diverged (non-finite weights); model disabled");
+    }
+  m.has_model = true;
+  return RBQ_OK;
 }

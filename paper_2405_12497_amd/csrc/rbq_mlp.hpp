@@ -1,0 +1,56 @@
+// Learned per-query nprobe: shapes, bucket table, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+namespace rbq {
+
+constexpr int kMlpIn = 96, kMlpHidden = 128, kMlpOut = 32;
+constexpr int kMlpNear = 64;   // nearest centroid distances in the features
+constexpr int kMlpStats = 8;   // nearest lists whose quantiser statistics are used
+constexpr int kMlpW1 = 0, kMlpB1 = kMlpIn * kMlpHidden, kMlpW2 = kMlpB1 + kMlpHidden,
+              kMlpB2 = kMlpW2 + kMlpHidden * kMlpOut, kMlpParams = kMlpB2 + kMlpOut;
+
+// nprobe of bucket j: b_0 = 4, b_j = max(b_{j-1} + 1, round(4 * 2^(7j/31))).
+__host__ __device__ inline int mlp_bucket_nprobe(int j) {
+  int b = 4;
+  for (int i = 1; i <= j; ++i) {
+    const int v = (int)floor(4.0 * exp2(7.0 * i / 31.0) + 0.5);
+    b = v > b + 1 ? v : b + 1;
+  }
+  return b;
+}
+
+struct FeatDev {
+  float* feats;            // nq x 96
+  const float* probe_d;    // nq x stride (nearest first)
+  const int32_t* probe;    // nq x stride
+  int stride, navail;
+  const float* q;          // nq x dim
+  const float* qrot;       // nq x dp
+  const float* cent;       // nlist x dim
+  const float* crot;       // nlist x dp
+  int dim, dp, W;
+  int64_t nq, qid_base;
+  uint64_t seed;
+};
+
+hipError_t launch_features(const FeatDev& f, hipStream_t st);
+hipError_t launch_gemm_bf16(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk,
+                            int64_t sbn, float* C, int64_t ldc, int M, int N, int K, bool accumulate,
+                            hipStream_t st);
+hipError_t launch_bias_relu(float* A, const float* bias, float* H, int64_t rows, int cols, hipStream_t st);
+hipError_t launch_softmax_ce(float* Z, const float* b2, const int32_t* y, int64_t n, float* dZ,
+                             float* loss_sum, hipStream_t st);
+hipError_t launch_relu_grad(float* dH, const float* A, int64_t total, hipStream_t st);
+hipError_t launch_colsum(const float* X, int64_t rows, int cols, float* out, hipStream_t st);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t st);
+hipError_t launch_gather_rows(const float* X, const int32_t* y, const int32_t* idx, int64_t n, int cols,
+                              float* Xo, int32_t* yo, hipStream_t st);
+hipError_t launch_policy(const float* Z, int64_t n, float thr, int nprobe_max, int32_t* out, hipStream_t st);
+
+}  // namespace rbq

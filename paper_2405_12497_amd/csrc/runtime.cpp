@@ -47,6 +47,11 @@ rbq_status fail(rbq_status st, const char* fmt, ...) {
 
 namespace rbq {
 
+rbq_status set_error(rbq_status st, const char* msg) {
+  g_err = msg;
+  return st;
+}
+
 // test hook: make the n-th following device allocation fail (0 = off)
 static int g_fail_alloc_after = 0;
 
@@ -656,6 +661,7 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
   if (idx->done_event) HIPCHK(hipStreamWaitEvent(st, idx->done_event, 0));
   int kernel = o.scan_kernel;
   int chunk = idx->tuned_chunk > 0 ? idx->tuned_chunk : kDefaultChunk;
+  chunk = std::min(chunk, kMaxP0 + 1 - o.k);   // bootstrap codes (k - 1 + chunk) fit the seed sort
   if (kernel == RBQ_SCAN_AUTO) kernel = idx->pick_kernel(nq, o.nprobe);
   if (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())
     return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this build");
@@ -1009,5 +1015,77 @@ extern "C" rbq_status rbq_profile_read(rbq_index* idx, rbq_profile* out) {
     out->codes_scan0 = acc[0];
     out->codes_scan1 = acc[1];
   }
+  return RBQ_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+extern "C" rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t nq, int32_t k,
+                                   int32_t nprobe, void* stream) {
+  if (!idx || !queries) return fail(RBQ_EINVAL, "NULL argument");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  if (is_device_ptr(queries)) return fail(RBQ_EINVAL, "rbq_autotune takes host queries");
+  if (nq < 1 || k < 1 || k > kMaxK || nprobe < 1 || nprobe > std::min(idx->nlist, kMaxNprobe))
+    return fail(RBQ_EINVAL, "bad nq, k or nprobe");
+  hipStream_t st = (hipStream_t)stream;
+  DBuf dq, di, dd;
+  HIPCHK(dq.ensure((size_t)nq * idx->dim * 4));
+  HIPCHK(di.ensure((size_t)nq * k * 8));
+  HIPCHK(dd.ensure((size_t)nq * k * 4));
+  HIPCHK(hipMemcpy(dq.p, queries, (size_t)nq * idx->dim * 4, hipMemcpyHostToDevice));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  rbq_search_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.k = k;
+  o.nprobe = nprobe;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  if (idx->done_event) HIPCHK(hipStreamWaitEvent(st, idx->done_event, 0));
+  auto timed = [&](int64_t n, int kernel, int chunk, float* ms) -> rbq_status {
+    float best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+      HIPCHK(hipEventRecord(e0, st));
+      rbq_status rs = run_search(idx, (const float*)dq.p, n, o, kernel, chunk, nullptr, (int64_t*)di.p,
+                                 (float*)dd.p, st);
+      if (rs != RBQ_OK) return rs;
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      if (rep > 0) best = std::min(best, t);   // the first run allocates and warms up
+    }
+    *ms = best;
+    return RBQ_OK;
+  };
+  const int chunks[] = {256, 512, 1024, 2048};
+  const int kernels[] = {RBQ_SCAN_POPCNT, RBQ_SCAN_MFMA};
+  float best = 1e30f;
+  int best_chunk = kDefaultChunk, best_kernel = RBQ_SCAN_POPCNT;
+  for (int c : chunks) {
+    if (c > kMaxP0 + 1 - k) continue;
+    for (int kern : kernels) {
+      float ms = 0.f;
+      rbq_status rs = timed(nq, kern, c, &ms);
+      if (rs != RBQ_OK) return rs;
+      if (ms < best) {
+        best = ms;
+        best_chunk = c;
+        best_kernel = kern;
+      }
+    }
+  }
+  // kernel choice for small batches at the chosen chunk length
+  const int64_t small = std::max<int64_t>(1, nq / 16);
+  float tp = 0.f, tm = 0.f;
+  rbq_status rs = timed(small, RBQ_SCAN_POPCNT, best_chunk, &tp);
+  if (rs == RBQ_OK) rs = timed(small, RBQ_SCAN_MFMA, best_chunk, &tm);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rs != RBQ_OK) return rs;
+  idx->tuned_chunk = best_chunk;
+  idx->tuned_kernel_large = best_kernel;
+  idx->tuned_kernel_small = tm < tp ? RBQ_SCAN_MFMA : RBQ_SCAN_POPCNT;
+  idx->tuned_batch_split = std::max<int64_t>(2, (nq + small) / 2);
+  HIPCHK(hipStreamSynchronize(st));
   return RBQ_OK;
 }
