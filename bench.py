@@ -83,6 +83,161 @@ def cpu_baseline(wl, nprobe, k, budget_s=15.0, max_q=5000):
                       f"{codes / dt:.3g} codes/s"}
 
 
+def labels_from_gt(gt_i, assign, centroids, queries, dev, chunk=4096):
+    """Smallest nprobe whose probed lists contain all k true neighbours: one
+    plus the largest probe rank (nearest-centroid order, ties to the lower
+    list) among the lists of the neighbours."""
+    import torch
+    c = torch.from_numpy(centroids).to(dev).double()
+    cn = (c * c).sum(1)
+    out = np.empty(len(queries), np.int64)
+    for s0 in range(0, len(queries), chunk):
+        q = torch.from_numpy(queries[s0:s0 + chunk]).to(dev).double()
+        d = cn[None, :] - 2.0 * (q @ c.T)
+        order = torch.argsort(d, dim=1, stable=True)
+        rank = torch.empty_like(order)
+        rank.scatter_(1, order, torch.arange(order.shape[1], device=dev).expand_as(order))
+        nn_lists = torch.from_numpy(assign[gt_i[s0:s0 + chunk]].astype(np.int64)).to(dev)
+        out[s0:s0 + chunk] = (torch.gather(rank, 1, nn_lists).max(1).values + 1).cpu().numpy()
+    return out
+
+
+def time_search(idx, q, k, nprobe, steps, warmup, **kw):
+    """Seconds per search of the whole batch, plus the per-stage device times
+    (ms per search) from a separate profiled pass of the same searches."""
+    import torch
+
+    from paper_2405_12497_amd import rabitq as R
+    out_i = torch.empty((q.shape[0], k), dtype=torch.int64, device=q.device)
+    out_d = torch.empty((q.shape[0], k), dtype=torch.float32, device=q.device)
+    for _ in range(warmup):
+        idx.search(q, k, nprobe, out_ids=out_i, out_dists=out_d, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        idx.search(q, k, nprobe, out_ids=out_i, out_dists=out_d, **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    R.rbq_profile_enable(idx.h, True)
+    for _ in range(3):
+        idx.search(q, k, nprobe, out_ids=out_i, out_dists=out_d, **kw)
+    torch.cuda.synchronize()
+    prof = R.rbq_profile_read(idx.h)
+    R.rbq_profile_enable(idx.h, False)
+    stages = {key: round(prof[key] / max(1, prof["searches"]), 3) for key in prof if key.startswith("ms_")}
+    return dt, stages
+
+
+def bench_learned(args):
+    """Learned per-query nprobe vs the best fixed nprobe, both at recall@10 >= 0.95."""
+    import torch
+
+    import synth
+    from oracle import mlp_oracle as M
+    from paper_2405_12497_amd import rabitq as R
+    dev = torch.device("cuda:0")
+    k = 10
+    n, ntr, nva, nte = args.n, args.ntrain, 10_000, args.nq
+    log(f"learned nprobe: embedding-like n={n} D=768 nlist={args.nlist}, {ntr} training queries")
+    data, qall = synth.embedding_like(n, ntr + nva + nte, seed_data=1004, seed_query=2005)
+    cent, assign = synth.kmeans(data, args.nlist, iters=10, seed=5004, device=dev)
+    gauss = synth.gaussian_matrix(768, 3004)
+    idx = R.Index(768, args.nlist, rot_precision=R.RBQ_ROT_BF16X3, seed=4004)
+    idx.build(data, cent, assign, gauss)
+    log("index built; ground truth for all queries")
+    gt_i, gt_d = ground_truth(data, qall, k, dev)
+    need = labels_from_gt(gt_i, assign, cent, qall, dev)
+    labels = M.label_of(need).astype(np.int32)
+    qtr, qva, qte = qall[:ntr], qall[ntr:ntr + nva], qall[ntr + nva:]
+    log(f"label histogram (buckets): {np.bincount(labels, minlength=32).tolist()}")
+    # features: each query with the id it will search with (qid_base 0 per set)
+    feats = []
+    for part in (qtr, qva, qte):
+        qt = torch.from_numpy(part).to(dev)
+        f = torch.empty((len(part), 96), dtype=torch.float32, device=dev)
+        for s0 in range(0, len(part), 20000):
+            R.rbq_nprobe_features(idx.h, qt[s0:s0 + 20000], qid_base=s0, feats=f[s0:s0 + 20000])
+        feats.append(f)
+    t0 = time.perf_counter()
+    losses = R.rbq_nprobe_model_train(idx.h, feats[0], torch.from_numpy(labels[:ntr]).to(dev),
+                                      epochs=args.epochs, batch=2048, lr=args.lr, seed=11)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"trained {args.epochs} epochs in {train_s:.1f}s, losses {np.round(losses, 4).tolist()}")
+    w, _ = R.rbq_nprobe_model_get(idx.h)
+    cap = 512
+    qva_t, qte_t = torch.from_numpy(qva).to(dev), torch.from_numpy(qte).to(dev)
+    gva_d, gte_d = gt_d[ntr:ntr + nva], gt_d[ntr + nva:]
+    target = 0.95
+
+    def val_learned(thr):
+        R.rbq_nprobe_model_set(idx.h, w, thr)
+        ids, _, st = idx.search(qva_t, k, cap, use_learned_nprobe=True, stats=True)
+        rc = recall(ids.cpu().numpy(), gva_d, data, qva, k)
+        log(f"  threshold {thr:.5f}: validation recall {rc:.4f}, mean nprobe {st['pairs'] / nva:.1f}")
+        return rc
+
+    def val_fixed(p):
+        ids, _, _ = idx.search(qva_t, k, p)
+        rc = recall(ids.cpu().numpy(), gva_d, data, qva, k)
+        log(f"  fixed nprobe {p}: validation recall {rc:.4f}")
+        return rc
+
+    # both operating points are calibrated on the validation queries: the
+    # smallest cumulative-softmax threshold (bisection) and the smallest fixed
+    # nprobe (bisection over integers) whose recall@10 reaches the target
+    lo, hi = 0.3, 0.9995
+    if val_learned(hi) < target:
+        best_thr = hi
+    else:
+        for _ in range(12):
+            mid = 0.5 * (lo + hi)
+            if val_learned(mid) >= target:
+                hi = mid
+            else:
+                lo = mid
+        best_thr = hi
+    R.rbq_nprobe_model_set(idx.h, w, best_thr)
+    ids, _, st_l = idx.search(qte_t, k, cap, use_learned_nprobe=True, stats=True)
+    rc_l = recall(ids.cpu().numpy(), gte_d, data, qte, k)
+    t_l, prof_l = time_search(idx, qte_t, k, cap, args.steps, args.warmup, use_learned_nprobe=True)
+    R.rbq_nprobe_model_set(idx.h, None, 0.9)
+    plo, phi = 1, cap
+    while plo < phi:
+        mid = (plo + phi) // 2
+        if val_fixed(mid) >= target:
+            phi = mid
+        else:
+            plo = mid + 1
+    fixed = phi
+    ids, _, st_f = idx.search(qte_t, k, fixed, stats=True)
+    rc_f = recall(ids.cpu().numpy(), gte_d, data, qte, k)
+    t_f, prof_f = time_search(idx, qte_t, k, fixed, args.steps, args.warmup)
+    res = {
+        "metric": METRIC,
+        "value": nte / t_l,
+        "unit": "queries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_l * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int1xint4->int32 scan, bf16 MLP, fp32 estimator/rerank", "data": "synthetic",
+        "config": {
+            "workload": f"learned per-query nprobe: {n} embedding-like vectors D=768 (power-law spectrum, "
+                        f"unit norm), {args.nlist} lists, BF16x3 rotation, {ntr} training / {nva} validation / "
+                        f"{nte} test queries, top-10",
+            "learned": {"qps": nte / t_l, "recall@10": round(rc_l, 4), "threshold": best_thr,
+                        "mean_nprobe": st_l["pairs"] / nte, "reranked_per_query": st_l["reranked"] / nte,
+                        "codes_per_query": st_l["codes_scanned"] / nte, "stage_ms": prof_l},
+            "fixed": {"qps": nte / t_f, "recall@10": round(rc_f, 4), "nprobe": fixed,
+                      "reranked_per_query": st_f["reranked"] / nte,
+                      "codes_per_query": st_f["codes_scanned"] / nte, "stage_ms": prof_f},
+            "speedup_learned_over_fixed": t_f / t_l,
+            "calibration": "threshold and fixed nprobe both chosen on the validation queries",
+            "train_s": round(train_s, 2), "epochs": args.epochs, "lr": args.lr, "losses": [round(float(x), 4) for x in losses],
+        },
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +249,10 @@ def main():
     ap.add_argument("--nprobe", type=int, default=0, help="0: smallest of the sweep reaching recall 0.95")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel", default="popcnt", choices=["popcnt", "mfma", "auto"])
+    ap.add_argument("--workload", default="sift1m", choices=["sift1m", "learned"])
+    ap.add_argument("--ntrain", type=int, default=100_000)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run 3 device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -106,6 +265,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each": n * 4, "copies": 3}))
+        return
+    if args.workload == "learned":
+        bench_learned(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "

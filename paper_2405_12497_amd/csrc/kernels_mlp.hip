@@ -258,7 +258,55 @@ __global__ void k_policy(const float* __restrict__ Z, int64_t n, float thr, int 
   out[r] = min(max(mlp_bucket_nprobe(pick), 1), nprobe_max);
 }
 
+// Per-feature mean and 1/std (population), one block per feature.
+__global__ void k_feat_stats(const float* __restrict__ X, int64_t rows, int cols, float* __restrict__ mu,
+                             float* __restrict__ inv_sd) {
+  __shared__ double part[2][4];
+  const int c = blockIdx.x;
+  double s = 0.0, s2 = 0.0;
+  for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
+    const double v = X[r * cols + c];
+    s += v;
+    s2 += v * v;
+  }
+  s = wave_sum_d(s);
+  s2 = wave_sum_d(s2);
+  if (lane_id() == 0) {
+    part[0][threadIdx.x >> 6] = s;
+    part[1][threadIdx.x >> 6] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = (part[0][0] + part[0][1] + part[0][2] + part[0][3]) / (double)rows;
+    const double v = (part[1][0] + part[1][1] + part[1][2] + part[1][3]) / (double)rows - m * m;
+    mu[c] = (float)m;
+    inv_sd[c] = (float)(v > 1e-20 ? 1.0 / sqrt(v) : 1.0);
+  }
+}
+
+__global__ void k_standardize(const float* __restrict__ X, int64_t rows, int cols, const float* __restrict__ mu,
+                              const float* __restrict__ inv_sd, float* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * cols) return;
+  const int c = (int)(i % cols);
+  Y[i] = (X[i] - mu[c]) * inv_sd[c];
+}
+
 }  // namespace
+
+hipError_t launch_feat_stats(const float* X, int64_t rows, int cols, float* mu, float* inv_sd, hipStream_t st) {
+  hipLaunchKernelGGL(k_feat_stats, dim3(cols), dim3(256), 0, st, X, rows, cols, mu, inv_sd);
+  return hipGetLastError();
+}
+
+hipError_t launch_standardize(const float* X, int64_t rows, int cols, const float* mu, const float* inv_sd,
+                              float* Y, hipStream_t st) {
+  const int64_t n = rows * cols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_standardize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, rows, cols, mu,
+                     inv_sd, Y);
+  return hipGetLastError();
+}
 
 hipError_t launch_features(const FeatDev& f, hipStream_t st) {
   if (f.nq <= 0) return hipSuccess;

@@ -2,9 +2,10 @@
 // popcount scan with the estimator epilogue, and the error-bound rerank.
 //
 // Work layout. Every probed (query, list) pair is cut into chunks of at most
-// `chunk` codes; a chunk is the unit a wave takes from a global work counter
-// (persistent grid). A query's chunks, in probe order, are numbered 0..nch-1
-// and its probed codes 0..ncode-1 ("query code space"). Each chunk owns the
+// `chunk` codes; a chunk is one entry of a phase's unit table, which the waves
+// of the persistent grid take in static round-robin. A query's chunks, in
+// probe order, are numbered 0..nch-1 and its probed codes 0..ncode-1 ("query
+// code space"). Each chunk owns the
 // slots of its codes in a per-query candidate segment, so results land at
 // positions fixed by (query, list, chunk), independent of scheduling.
 //
@@ -27,105 +28,23 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 
-// ------------------------------------------------------------------ prep (S3)
-// One wave per pair: b = ||q_r - c||; residual r = P^T q_r - P^T c in the
-// rotated space; q'_i = r_i / b; v_l, v_r, Delta; randomised rounding
-// q_u = min(15, floor((q' - v_l)/Delta + u)) computed as
-// 15 (r_i - r_min)/(r_max - r_min) + u (the 1/b scale cancels); bit planes by
-// ballot: plane j word t bit l = bit j of q_u at coordinate 64 t + l.
-__global__ __launch_bounds__(kThreads) void k_prep(SearchDev s) {
-  const int64_t g = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int64_t npairs = s.nq * s.nprobe;
-  if (g >= npairs) return;
-  const int lane = lane_id();
-  const int64_t q = g / s.nprobe;
-  const int r = (int)(g - q * s.nprobe);
-  int P = s.nprobe;
-  if (s.nprobe_q) P = uniform_i32(min(max(s.nprobe_q[q], 1), s.nprobe));
-  const int list = uniform_i32(s.probe[g]);
-  PairRec rec;
-  if (r >= P || list < 0) {
-    if (lane == 0) {
-      rec.k1 = rec.k2 = rec.k0 = rec.b = rec.vl = rec.delta = 0.f;
-      rec.sq = 0;
-      rec.list = -1;
-      s.pairs[g] = rec;
-    }
-    return;
-  }
-  const float* qr = s.q + q * s.dim;
-  const float* c = s.cent + (int64_t)list * s.dim;
-  float acc = 0.f;
-  for (int i = lane; i < s.dim; i += kWave) {
-    const float d = qr[i] - c[i];
-    acc = fmaf(d, d, acc);
-  }
-  const float b = sqrtf(wave_sum(acc));
-  const float* qrot = s.qrot + q * s.dp;
-  const float* crot = s.crot + (int64_t)list * s.dp;
-  float rmin = __builtin_inff(), rmax = -__builtin_inff();
-  for (int t = 0; t < s.W; ++t) {
-    const int i = t * kWave + lane;
-    const float v = qrot[i] - crot[i];
-    rmin = fminf(rmin, v);
-    rmax = fmaxf(rmax, v);
-  }
-  rmin = wave_min(rmin);
-  rmax = wave_max(rmax);
-  const float range = rmax - rmin;
-  const bool live = (b > 0.f) && (range > 0.f);
-  const float scale = live ? 15.f / range : 0.f;
-  const uint64_t qid = (uint64_t)(s.qid_base + q);
-  int sq = 0;
-  uint64_t* pl = s.planes + g * 4 * s.W;
-  int8_t* q8 = s.qu8 ? s.qu8 + g * s.dp : nullptr;
-  for (int t = 0; t < s.W; ++t) {
-    const int i = t * kWave + lane;
-    int qu = 0;
-    if (live) {
-      const float x = (qrot[i] - crot[i] - rmin) * scale;
-      qu = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list, (uint32_t)i)));
-    }
-    sq += qu;
-    if (q8) q8[i] = (int8_t)qu;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint64_t w = __ballot((qu >> j) & 1);
-      if (lane == 0) pl[j * s.W + t] = w;
-    }
-  }
-  sq = wave_sum_i(sq);
-  if (lane == 0) {
-    // <x_bar, q_bar> = (2 Delta/sqrt D) ip + (2 v_l/sqrt D) pc - (Delta/sqrt D) sq - sqrt(D) v_l
-    const double rd = sqrt((double)s.dp);
-    double vl = 0.0, delta = 0.0;
-    if (b > 0.f) {
-      vl = (double)rmin / (double)b;
-      delta = (double)range / (15.0 * (double)b);
-    }
-    rec.k1 = (float)(2.0 * delta / rd);
-    rec.k2 = (float)(2.0 * vl / rd);
-    rec.k0 = (float)(-(delta / rd) * (double)sq - rd * vl);
-    rec.b = b;
-    rec.vl = (float)vl;
-    rec.delta = (float)delta;
-    rec.sq = sq;
-    rec.list = list;
-    s.pairs[g] = rec;
-  }
-}
-
-// Same computation for short codes (W <= 4 words): 4 pairs per wave, every
-// load of the 4 pairs issued before the reductions, values kept in registers.
-template <int WS>
+// Per (query, list) pair, Section 3.3.1: residual r = q_rot - c_rot (the
+// rotated-space form of P^T (q_r - c)), b = ||r|| (= ||q_r - c|| since P is
+// orthogonal), v_l / v_r = min / max of r / b, Delta = (v_r - v_l) / 15 and
+// the randomized rounding q_u[i] = min(15, floor((r_i/b - v_l)/Delta + u_i)),
+// written as 4 bit planes (and as int8 for the MFMA scan), plus the pair's
+// estimator constants. One wave handles PPW pairs with the residual held in
+// registers (WS >= W words of 64 coordinates, compile-time bound), so each
+// coordinate is loaded once.
+template <int WS, int PPW>
 __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
-  constexpr int PPW = 4;
   const int lane = lane_id();
+  const int W = s.W;
   const int64_t npairs = s.nq * s.nprobe;
   const int64_t g0 = uniform_i64(((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * PPW);
   if (g0 >= npairs) return;
   float rv[PPW][WS];
-  float bacc[PPW];
+  float qq[PPW];
   int list[PPW];
   bool act[PPW];
 #pragma unroll
@@ -133,7 +52,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     const int64_t g = g0 + j;
     act[j] = false;
     list[j] = -1;
-    bacc[j] = 0.f;
+    qq[j] = 0.f;
 #pragma unroll
     for (int t = 0; t < WS; ++t) rv[j][t] = 0.f;
     if (g < npairs) {
@@ -141,21 +60,17 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
       const int r = (int)(g - q * s.nprobe);
       int P = s.nprobe;
       if (s.nprobe_q) P = uniform_i32(min(max(s.nprobe_q[q], 1), s.nprobe));
-      list[j] = uniform_i32(s.probe[g]);
-      act[j] = r < P && list[j] >= 0;
+      list[j] = r < P ? uniform_i32(s.probe[g]) : -1;
+      act[j] = list[j] >= 0;
       if (act[j]) {
         const float* qrot = s.qrot + q * s.dp;
         const float* crot = s.crot + (int64_t)list[j] * s.dp;
 #pragma unroll
-        for (int t = 0; t < WS; ++t) rv[j][t] = qrot[t * kWave + lane] - crot[t * kWave + lane];
-        const float* qr = s.q + q * s.dim;
-        const float* c = s.cent + (int64_t)list[j] * s.dim;
-#pragma unroll
         for (int t = 0; t < WS; ++t) {
-          const int i = t * kWave + lane;
-          if (i < s.dim) {
-            const float d = qr[i] - c[i];
-            bacc[j] = fmaf(d, d, bacc[j]);
+          if (t < W) {
+            const float x = qrot[t * kWave + lane];
+            rv[j][t] = x - crot[t * kWave + lane];
+            qq[j] = fmaf(x, x, qq[j]);
           }
         }
       }
@@ -176,13 +91,30 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
       continue;
     }
     const int64_t q = g / s.nprobe;
-    float rmin = rv[j][0], rmax = rv[j][0];
+    float rmin = rv[j][0], rmax = rv[j][0], ss = 0.f;
 #pragma unroll
-    for (int t = 1; t < WS; ++t) {
-      rmin = fminf(rmin, rv[j][t]);
-      rmax = fmaxf(rmax, rv[j][t]);
+    for (int t = 0; t < WS; ++t) {
+      if (t < W) {
+        rmin = fminf(rmin, rv[j][t]);
+        rmax = fmaxf(rmax, rv[j][t]);
+        ss = fmaf(rv[j][t], rv[j][t], ss);
+      }
     }
-    const float b = sqrtf(wave_sum(bacc[j]));
+    float b = uniform_f32(sqrtf(wave_sum(ss)));
+    // Near a centroid the rotated residual is dominated by the rotation's
+    // rounding (~1e-6 (||q|| + ||c||)): take b from the raw vectors there, so
+    // that b is exactly 0 when the query coincides with the centroid.
+    const float scale_qc = uniform_f32(sqrtf(wave_sum(qq[j])) + sqrtf(s.cnorm[list[j]]));
+    if (b <= 1e-4f * scale_qc) {
+      const float* qr = s.q + q * s.dim;
+      const float* c = s.cent + (int64_t)list[j] * s.dim;
+      float acc = 0.f;
+      for (int i = lane; i < s.dim; i += kWave) {
+        const float d = qr[i] - c[i];
+        acc = fmaf(d, d, acc);
+      }
+      b = uniform_f32(sqrtf(wave_sum(acc)));
+    }
     rmin = wave_min(rmin);
     rmax = wave_max(rmax);
     const float range = rmax - rmin;
@@ -190,26 +122,29 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     const float scale = live ? 15.f / range : 0.f;
     const uint64_t qid = (uint64_t)(s.qid_base + q);
     int sq = 0;
-    uint64_t* pl = s.planes + g * 4 * WS;
+    uint64_t* pl = s.planes + g * 4 * W;
     int8_t* q8 = s.qu8 ? s.qu8 + g * s.dp : nullptr;
 #pragma unroll
     for (int t = 0; t < WS; ++t) {
-      const int i = t * kWave + lane;
-      int qu = 0;
-      if (live) {
-        const float x = (rv[j][t] - rmin) * scale;
-        qu = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
-      }
-      sq += qu;
-      if (q8) q8[i] = (int8_t)qu;
+      if (t < W) {
+        const int i = t * kWave + lane;
+        int qu = 0;
+        if (live) {
+          const float x = (rv[j][t] - rmin) * scale;
+          qu = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
+        }
+        sq += qu;
+        if (q8) q8[i] = (int8_t)qu;
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
-        const uint64_t w = __ballot((qu >> jb) & 1);
-        if (lane == 0) pl[jb * WS + t] = w;
+        for (int jb = 0; jb < 4; ++jb) {
+          const uint64_t w = __ballot((qu >> jb) & 1);
+          if (lane == 0) pl[jb * W + t] = w;
+        }
       }
     }
     sq = wave_sum_i(sq);
     if (lane == 0) {
+      // <x_bar, q_bar> = (2 Delta/sqrt D) ip + (2 v_l/sqrt D) pc - (Delta/sqrt D) sq - sqrt(D) v_l
       const double rd = sqrt((double)s.dp);
       double vl = 0.0, delta = 0.0;
       if (b > 0.f) {
@@ -941,15 +876,23 @@ void launch_scan_ws(const SearchDev& s, int phase, int grid, hipStream_t st) {
 hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st) {
   const int64_t npairs = s.nq * s.nprobe;
   if (npairs <= 0) return hipSuccess;
-  const unsigned g4 = (unsigned)((npairs + 4 * kWaves - 1) / (4 * kWaves));
+  auto grid = [&](int ppw) { return dim3((unsigned)((npairs + ppw * kWaves - 1) / (ppw * kWaves))); };
+  if (s.W <= 0 || s.W > 64) return hipErrorInvalidValue;
   switch (s.W) {
-    case 1: hipLaunchKernelGGL(k_prep_reg<1>, dim3(g4), dim3(kThreads), 0, st, s); break;
-    case 2: hipLaunchKernelGGL(k_prep_reg<2>, dim3(g4), dim3(kThreads), 0, st, s); break;
-    case 3: hipLaunchKernelGGL(k_prep_reg<3>, dim3(g4), dim3(kThreads), 0, st, s); break;
-    case 4: hipLaunchKernelGGL(k_prep_reg<4>, dim3(g4), dim3(kThreads), 0, st, s); break;
+    case 1: hipLaunchKernelGGL((k_prep_reg<1, 4>), grid(4), dim3(kThreads), 0, st, s); break;
+    case 2: hipLaunchKernelGGL((k_prep_reg<2, 4>), grid(4), dim3(kThreads), 0, st, s); break;
+    case 3: hipLaunchKernelGGL((k_prep_reg<3, 4>), grid(4), dim3(kThreads), 0, st, s); break;
+    case 4: hipLaunchKernelGGL((k_prep_reg<4, 4>), grid(4), dim3(kThreads), 0, st, s); break;
     default:
-      hipLaunchKernelGGL(k_prep, dim3((unsigned)((npairs + kWaves - 1) / kWaves)), dim3(kThreads),
-                         0, st, s);
+      if (s.W <= 8) {
+        hipLaunchKernelGGL((k_prep_reg<8, 2>), grid(2), dim3(kThreads), 0, st, s);
+      } else if (s.W <= 16) {
+        hipLaunchKernelGGL((k_prep_reg<16, 1>), grid(1), dim3(kThreads), 0, st, s);
+      } else if (s.W <= 32) {
+        hipLaunchKernelGGL((k_prep_reg<32, 1>), grid(1), dim3(kThreads), 0, st, s);
+      } else {
+        hipLaunchKernelGGL((k_prep_reg<64, 1>), grid(1), dim3(kThreads), 0, st, s);
+      }
   }
   return hipGetLastError();
 }

@@ -143,13 +143,33 @@ rbq_status predict_into(rbq_index* idx, const float* feats, int64_t nq, int npro
   return RBQ_OK;
 }
 
-rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int nprobe_max,
+// Learned path of a search: one centroid scoring / probe selection with `stride`
+// lists per query (>= 64 when the index has that many lists); the features
+// read the nearest 64 of them, and the search reuses the same selection.
+rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int nprobe_max, int stride,
                           int64_t qid_base, hipStream_t st, const int32_t** out) {
   Workspace& w = idx->ws;
   HIPCHK(w.feats.ensure((size_t)nq * kMlpIn * 4));
   HIPCHK(w.nprobe_q.ensure((size_t)nq * 4));
-  rbq_status rs = features_into(idx, queries, nq, qid_base, (float*)w.feats.p, st);
+  rbq_status rs = front(idx, queries, nq, stride, nullptr, st);
   if (rs != RBQ_OK) return rs;
+  FeatDev f;
+  f.feats = (float*)w.feats.p;
+  f.probe_d = (const float*)w.probe_d.p;
+  f.probe = (const int32_t*)w.probe.p;
+  f.stride = stride;
+  f.navail = std::min(stride, kMlpNear);
+  f.q = queries;
+  f.qrot = (const float*)w.qrot.p;
+  f.cent = (const float*)idx->d_cent.p;
+  f.crot = (const float*)idx->d_crot.p;
+  f.dim = idx->dim;
+  f.dp = idx->dp;
+  f.W = idx->W;
+  f.nq = nq;
+  f.qid_base = qid_base;
+  f.seed = idx->prm.seed;
+  HIPCHK(launch_features(f, st));
   rs = predict_into(idx, (const float*)w.feats.p, nq, nprobe_max, (int32_t*)w.nprobe_q.p, nullptr, st);
   if (rs != RBQ_OK) return rs;
   *out = (const int32_t*)w.nprobe_q.p;
@@ -258,6 +278,16 @@ extern "C" rbq_status rbq_nprobe_model_train(rbq_index* idx, const float* feats,
   HIPCHK(hipMemcpyAsync(m.w32.p, w.data(), (size_t)kMlpParams * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(m.m.p, 0, (size_t)kMlpParams * 4, st));
   HIPCHK(hipMemsetAsync(m.v.p, 0, (size_t)kMlpParams * 4, st));
+  // Inputs are standardised per feature for training; the statistics are
+  // folded into W1 and b1 afterwards, so the model consumes raw features.
+  DBuf xs, stats;
+  HIPCHK(xs.ensure((size_t)n * kMlpIn * 4));
+  HIPCHK(stats.ensure((size_t)2 * kMlpIn * 4));
+  float* mu = (float*)stats.p;
+  float* isd = mu + kMlpIn;
+  HIPCHK(launch_feat_stats(feats, n, kMlpIn, mu, isd, st));
+  HIPCHK(launch_standardize(feats, n, kMlpIn, mu, isd, (float*)xs.p, st));
+  feats = (const float*)xs.p;
   const int64_t B = std::min<int64_t>(cfg->batch, n);
   HIPCHK(m.act.ensure(pass_floats(B) * 4));
   const Pass p = carve((float*)m.act.p, B);
@@ -293,6 +323,22 @@ extern "C" rbq_status rbq_nprobe_model_train(rbq_index* idx, const float* feats,
   }
   m.host_w.resize(kMlpParams);
   HIPCHK(hipMemcpy(m.host_w.data(), m.w32.p, (size_t)kMlpParams * 4, hipMemcpyDeviceToHost));
+  {
+    // fold the standardisation: x' = (x - mu) * isd  =>  W1[i][j] *= isd_i,
+    // b1[j] -= sum_i mu_i * isd_i * W1[i][j]
+    std::vector<float> hs(2 * kMlpIn);
+    HIPCHK(hipMemcpy(hs.data(), stats.p, hs.size() * 4, hipMemcpyDeviceToHost));
+    for (int j = 0; j < kMlpHidden; ++j) {
+      double shift = 0.0;
+      for (int i = 0; i < kMlpIn; ++i) {
+        float& wij = m.host_w[kMlpW1 + i * kMlpHidden + j];
+        wij *= hs[kMlpIn + i];
+        shift += (double)hs[i] * wij;
+      }
+      m.host_w[kMlpB1 + j] -= (float)shift;
+    }
+    HIPCHK(hipMemcpy(m.w32.p, m.host_w.data(), (size_t)kMlpParams * 4, hipMemcpyHostToDevice));
+  }
   for (float v : m.host_w)
     if (!std::isfinite(v)) {
       m.has_model = false;

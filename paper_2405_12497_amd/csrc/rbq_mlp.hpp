@@ -51,6 +51,9 @@ hipError_t launch_adam(float* w, const float* g, float* m, float* v, int n, floa
                        float b2, float eps, int step, hipStream_t st);
 hipError_t launch_gather_rows(const float* X, const int32_t* y, const int32_t* idx, int64_t n, int cols,
                               float* Xo, int32_t* yo, hipStream_t st);
+hipError_t launch_feat_stats(const float* X, int64_t rows, int cols, float* mu, float* inv_sd, hipStream_t st);
+hipError_t launch_standardize(const float* X, int64_t rows, int cols, const float* mu, const float* inv_sd,
+                              float* Y, hipStream_t st);
 hipError_t launch_policy(const float* Z, int64_t n, float thr, int nprobe_max, int32_t* out, hipStream_t st);
 
 }  // namespace rbq

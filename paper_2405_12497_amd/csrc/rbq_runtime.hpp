@@ -98,7 +98,7 @@ struct rbq_index {
 };
 
 namespace rbq {
-rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int nprobe_max,
+rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int nprobe_max, int stride,
                           int64_t qid_base, hipStream_t st, const int32_t** out);
 rbq_status rotate_rows(rbq_index* idx, const float* X, int64_t lda, const float* sub,
                        const int32_t* sel, int64_t M, float* Y, hipStream_t st);
@@ -108,7 +108,10 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
                    float* out_d);
 rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
                  const int32_t* nprobe_q, hipStream_t st);
-rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& o,
-                      int scan_kernel, int chunk, const int32_t* nprobe_q, int64_t* out_ids,
-                      float* out_d, hipStream_t st);
+// One search on `st`. `learned`: per-query nprobe from the model (the caller
+// checked that one is set). Reports the per-query nprobe array in effect
+// (NULL: all use the fixed value) and the probe stride.
+rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& opts,
+                      int scan_kernel, int chunk, bool learned, int64_t* out_ids, float* out_d,
+                      hipStream_t st, const int32_t** used_npq, int* used_stride);
 }  // namespace rbq

@@ -16,6 +16,7 @@
 
 #include "../../include/rabitq.h"
 #include "rbq_internal.hpp"
+#include "rbq_mlp.hpp"
 #include "rbq_runtime.hpp"
 
 using namespace rbq;
@@ -521,6 +522,7 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.list_off = (const int32_t*)idx->d_list_off.p;
   s.cent = (const float*)idx->d_cent.p;
   s.crot = (const float*)idx->d_crot.p;
+  s.cnorm = (const float*)idx->d_cnorm.p;
   s.dim = idx->dim;
   s.dp = idx->dp;
   s.W = idx->W;
@@ -590,10 +592,16 @@ int scan_grid(rbq_index* idx, int64_t nq, int nprobe, int chunk) {
   return (int)std::max<int64_t>(1, g);
 }
 
-rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& o,
-                      int scan_kernel, int chunk, const int32_t* nprobe_q, int64_t* out_ids,
-                      float* out_d, hipStream_t st) {
+rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& opts,
+                      int scan_kernel, int chunk, bool learned, int64_t* out_ids, float* out_d,
+                      hipStream_t st, const int32_t** used_npq, int* used_stride) {
   const bool mfma = scan_kernel == RBQ_SCAN_MFMA;
+  rbq_search_opts o = opts;
+  const int32_t* nprobe_q = o.nprobe_per_query;
+  // The learned path runs one probe selection of at least the 64 nearest
+  // lists: the features read those, and the search reuses the selection with
+  // its per-query nprobe (at most the caller's nprobe).
+  if (learned) o.nprobe = std::max(o.nprobe, std::min(kMlpNear, idx->nlist));
   rbq_status rs = ensure_workspace(idx, nq, o.nprobe, o.k, chunk, mfma);
   if (rs != RBQ_OK) return rs;
   ProfState& pf = idx->prof;
@@ -605,8 +613,14 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
     }
     HIPCHK(hipEventRecord(ev[0], st));
   }
-  rs = front(idx, queries, nq, o.nprobe, nprobe_q, st);
+  if (learned) {
+    rs = learned_nprobe(idx, queries, nq, opts.nprobe, o.nprobe, o.qid_base, st, &nprobe_q);
+  } else {
+    rs = front(idx, queries, nq, o.nprobe, nprobe_q, st);
+  }
   if (rs != RBQ_OK) return rs;
+  *used_npq = nprobe_q;
+  *used_stride = o.nprobe;
   SearchDev s = make_dev(idx, queries, nq, o.nprobe, o.k, chunk, nprobe_q, o.qid_base, mfma,
                          out_ids, out_d);
   if (pf.on) HIPCHK(hipEventRecord(ev[1], st));
@@ -665,13 +679,10 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
   if (kernel == RBQ_SCAN_AUTO) kernel = idx->pick_kernel(nq, o.nprobe);
   if (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())
     return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this build");
-  const int32_t* npq = o.nprobe_per_query;
-  rbq_status rs = RBQ_OK;
-  if (!npq && o.use_learned_nprobe && idx->mlp.has_model) {
-    rs = rbq::learned_nprobe(idx, queries, nq, o.nprobe, o.qid_base, st, &npq);
-    if (rs != RBQ_OK) return rs;
-  }
-  rs = run_search(idx, queries, nq, o, kernel, chunk, npq, out_ids, out_dists, st);
+  const bool learned = !o.nprobe_per_query && o.use_learned_nprobe && idx->mlp.has_model;
+  const int32_t* npq = nullptr;
+  int stride = o.nprobe;
+  rbq_status rs = run_search(idx, queries, nq, o, kernel, chunk, learned, out_ids, out_dists, st, &npq, &stride);
   if (rs != RBQ_OK) return rs;
   if (!idx->done_event) HIPCHK(hipEventCreateWithFlags(&idx->done_event, hipEventDisableTiming));
   HIPCHK(hipEventRecord(idx->done_event, st));
@@ -682,7 +693,7 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
     HIPCHK(hipMemcpy(rr.data(), idx->ws.q_rerank.p, nq * 4, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(cc.data(), idx->ws.q_cand.p, nq * 4, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(nc.data(), idx->ws.q_ncode.p, nq * 8, hipMemcpyDeviceToHost));
-    std::vector<int32_t> probe((size_t)nq * o.nprobe);
+    std::vector<int32_t> probe((size_t)nq * stride);
     HIPCHK(hipMemcpy(probe.data(), idx->ws.probe.p, probe.size() * 4, hipMemcpyDeviceToHost));
     stats->queries = nq;
     for (int64_t i = 0; i < nq; ++i) {
@@ -690,7 +701,15 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
       stats->candidates += cc[i];
       stats->codes_scanned += nc[i];
     }
-    for (int32_t l : probe) stats->pairs += (l >= 0);
+    std::vector<int32_t> pq;
+    if (npq) {
+      pq.resize(nq);
+      HIPCHK(hipMemcpy(pq.data(), npq, nq * 4, hipMemcpyDeviceToHost));
+    }
+    for (int64_t i = 0; i < nq; ++i) {
+      const int P = npq ? std::min(std::max(pq[i], 1), stride) : stride;
+      for (int r = 0; r < P; ++r) stats->pairs += (probe[(size_t)i * stride + r] >= 0);
+    }
   }
   return RBQ_OK;
 }
@@ -1045,8 +1064,10 @@ extern "C" rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t
     float best = 1e30f;
     for (int rep = 0; rep < 4; ++rep) {
       HIPCHK(hipEventRecord(e0, st));
-      rbq_status rs = run_search(idx, (const float*)dq.p, n, o, kernel, chunk, nullptr, (int64_t*)di.p,
-                                 (float*)dd.p, st);
+      const int32_t* npq = nullptr;
+      int stride = 0;
+      rbq_status rs = run_search(idx, (const float*)dq.p, n, o, kernel, chunk, false, (int64_t*)di.p,
+                                 (float*)dd.p, st, &npq, &stride);
       if (rs != RBQ_OK) return rs;
       HIPCHK(hipEventRecord(e1, st));
       HIPCHK(hipEventSynchronize(e1));

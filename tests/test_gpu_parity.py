@@ -114,7 +114,10 @@ def test_quantized_query_matches_oracle(name):
             u = O.rounding_uniforms_fast(c.seed, qi, lid, c.dp)
             oq = O.quantize_query(c.queries[qi], c.cent[lid], b.oidx.p, u)
             bb, vl, delta, sq = scal[qi, r]
-            assert bb == pytest.approx(oq.b, rel=2e-6)
+            # b is the norm of the rotated residual q_rot - c_rot (P orthogonal): by the
+            # triangle inequality it is off by at most the residual's error norm
+            crot_err = 2e-7 * np.linalg.norm(c.cent[lid]) * 4
+            assert abs(bb - oq.b) <= np.sqrt(c.dp) * (rot_err + crot_err) + 2e-6 * oq.b
             if oq.b == 0:
                 continue
             assert vl == pytest.approx(oq.vl, rel=1e-4, abs=1e-6)
