@@ -117,6 +117,20 @@ def test_code_is_codebook_argmin_bruteforce():
         assert idx.norm[0] == pytest.approx(np.linalg.norm(data[0] - cen[0]), rel=1e-14)
 
 
+def test_zero_coordinates_get_bit_zero():
+    """A zero coordinate of P^{-1} o (here: identity rotation, exact zeros and the
+    zero padding up to the code length) is a tie in the codebook argmin
+    (Sec. 3.1.3); the reading gives it bit 0. It adds 0 to <o_bar, o> either way."""
+    d, dp = 70, O.code_length(70)
+    rng = np.random.default_rng(31)
+    v = rng.standard_normal(d)
+    v[::3] = 0.0
+    idx = O.OracleIndex(v[None, :], np.zeros((1, d)), [0], np.eye(dp))
+    want = np.concatenate([(v > 0), np.zeros(dp - d, bool)]).astype(np.uint8)
+    np.testing.assert_array_equal(idx.bits[0], want)
+    assert idx.ipo[0] == pytest.approx(np.abs(v).sum() / np.linalg.norm(v) / math.sqrt(dp), rel=1e-14)
+
+
 def test_ipo_is_l1_norm_and_geometric_inner_product():
     rng = np.random.default_rng(3)
     d = 64
@@ -175,6 +189,13 @@ def test_quantization_definition_and_clamp():
     # u -> 1 would push the max coordinate to 2^Bq; the clamp keeps it at 15
     qq1 = O.quantize_query(q, c, p, np.full(d, 1.0 - 2 ** -24))
     assert qq1.qu.max() == 15 and qq1.qu[np.argmax(qp)] == 15
+    # u = 1, the closed end of the paper's interval: floor reaches 2^Bq at the
+    # maximum coordinate and the clamp brings it back to 15; elsewhere it is floor(x) + 1
+    qq2 = O.quantize_query(q, c, p, np.ones(d))
+    x = (qp - qq.vl) / qq.delta
+    assert qq2.qu[np.argmax(qp)] == 15 and qq2.qu.max() == 15
+    inner = x < 14.0 - 1e-9
+    np.testing.assert_array_equal(qq2.qu[inner], np.floor(x[inner]).astype(np.int64) + 1)
     # all-equal coordinates: Delta = 0
     p1 = np.eye(4)
     qz = O.quantize_query(np.ones(4), np.zeros(4), p1, np.full(4, 0.9))
@@ -360,6 +381,19 @@ def test_bound_failure_rate_matches_exact_law(mc128):
     assert O.bound_failure_probability(0.0, d) == pytest.approx(0.0571, abs=2e-4)
     assert O.bound_failure_probability(0.999999, d) == 0.0
     assert O.bound_failure_probability(0.5, d, eps0=0.0) == pytest.approx(1.0)
+
+
+def test_bound_failure_rate_small_dimension():
+    """At small D the exact law separates the bound's 1/sqrt(D-1) (Theorem 3.2)
+    from nearby forms: D = 8, <o,q> = 0.5, eps0 = 1.9 fails with probability
+    0.0109 (1/sqrt(D) in the half-width would give 0.0237, 9.5 standard errors
+    away at 6000 samples)."""
+    d, r = 8, 0.5
+    _, est, _, _, hw = _sample_ipo_and_est(d, r, 6000, 32, quantize=False)
+    fails = np.abs(est - r) > hw
+    p = O.bound_failure_probability(r, d)
+    assert p == pytest.approx(0.0109, abs=1e-4)
+    assert abs(fails.mean() - p) < 4 * math.sqrt(p * (1 - p) / len(est))
 
 
 def test_estimator_unbiased_with_4bit_query():
