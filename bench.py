@@ -24,8 +24,45 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+
+# Sources of the phase-1 popcount scan kernel; stored counter readings apply
+# only while their hash matches.
+SCAN_SOURCES = ("paper_2405_12497_amd/csrc/kernels_popcnt.hip",
+                "paper_2405_12497_amd/csrc/scan_code.hpp",
+                "paper_2405_12497_amd/csrc/rbq_internal.hpp")
+# HBM traffic of one phase-1 scan launch (k_scan_popcnt<2,4>) on the default
+# workload, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per
+# dispatch, mean over the timed steps' phase-1 dispatches), each scaled by the
+# reading of the same counter for a 1 GiB device-to-device copy
+# (FETCH_SIZE reads 0.5x the copied bytes, WRITE_SIZE 1.0x).
+SCAN_COUNTERS = {
+    "sources_sha256": "ff49686233dbc25da05dc9fd7311aba8acf9aa0faad68071ff846f3997646379",
+    "workload": "sift-like n=1000000 nq=10000 nlist=4096 nprobe=32 kernel=popcnt",
+    "fetch_kib": 847885.6,
+    "write_kib": 89042.3,
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+}
 NPROBE_SWEEP = (8, 16, 32, 64, 128, 256)
 METRIC = "QPS at recall@10≥0.95, learned vs fixed nprobe; code-scan GB/s vs HBM peak"
+
+
+def scan_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SCAN_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def scan_traffic(workload_key):
+    """HBM bytes per phase-1 scan launch from the stored counter readings, or
+    None when they were taken on other sources or another workload."""
+    c = SCAN_COUNTERS
+    if c["sources_sha256"] != scan_sources_sha256() or c["workload"] != workload_key:
+        return None
+    return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
 
 
 def log(msg):
@@ -336,6 +373,7 @@ def main():
     log(f"timed {args.steps} steps: {dt * 1e3 / args.steps:.3f} ms/step, {qps:.0f} QPS, recall {rc:.4f}; "
         f"per-step kernel ms {kernel_ms}; scan {achieved:.0f} GB/s")
 
+    wkey = f"sift-like n={args.n} nq={args.nq} nlist={args.nlist} nprobe={chosen} kernel={args.kernel}"
     line = {
         "metric": METRIC,
         "value": qps,
@@ -358,10 +396,11 @@ def main():
             "kernel_ms_per_step": kernel_ms,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_scan_popcnt (main scan)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": scan_traffic(wkey),
+                     "kernel": "k_scan_popcnt (phase-1 scan)",
                      "algorithmic_bytes_per_code": bytes_per_code,
-                     "bytes_per_launch": bytes_launch, "avg_launch_ms": scan_ms},
+                     "bytes_per_launch": bytes_launch, "avg_launch_ms": scan_ms,
+                     "scan_sources_sha256": scan_sources_sha256(), "counters_workload": wkey},
         "cpu_baseline": None,
     }
     if not args.no_cpu:

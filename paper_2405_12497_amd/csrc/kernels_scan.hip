@@ -21,6 +21,7 @@
 //   final:   candidates are reranked in probe order with tau tightened after
 //            every round (the running k-th exact distance), giving the top-k.
 #include "rbq_internal.hpp"
+#include "scan_code.hpp"
 
 namespace rbq {
 namespace {
@@ -247,60 +248,6 @@ __global__ __launch_bounds__(1024) void k_offsets(SearchDev s) {
   }
 }
 
-// ------------------------------------------------------------------ scan arithmetic (S4 + S6)
-// Integer <x_b, q_u> = sum_j 2^j popcount(x_b AND plane_j) and popcount(x_b)
-// for the code at position p. WS > 0: planes held in registers (W == WS).
-template <int WS>
-struct Planes {
-  uint64_t w[4][WS];
-  __device__ __forceinline__ void load(const uint64_t* src, int) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int t = 0; t < WS; ++t) w[j][t] = src[j * WS + t];
-  }
-  __device__ __forceinline__ uint64_t get(int j, int t) const { return w[j][t]; }
-};
-template <>
-struct Planes<0> {
-  const uint64_t* p;   // LDS copy, [4][W]
-  int W;
-  __device__ __forceinline__ uint64_t get(int j, int t) const { return p[j * W + t]; }
-};
-
-template <int WS>
-__device__ __forceinline__ void code_ip(const uint64_t* __restrict__ codes, int64_t p, int W,
-                                        const Planes<WS>& pl, int& ip, int& pc) {
-  const int Wn = WS > 0 ? WS : W;
-  int s0 = 0, s1 = 0, s2 = 0, s3 = 0, c = 0;
-#pragma unroll
-  for (int t = 0; t < Wn; ++t) {
-    const uint64_t x = codes[code_word_index(p, t, W)];
-    c += __popcll(x);
-    s0 += __popcll(x & pl.get(0, t));
-    s1 += __popcll(x & pl.get(1, t));
-    s2 += __popcll(x & pl.get(2, t));
-    s3 += __popcll(x & pl.get(3, t));
-  }
-  ip = s0 + 2 * s1 + 4 * s2 + 8 * s3;
-  pc = c;
-}
-
-// est = <x_bar, q_bar>/<o_bar,o> (Theorem 3.2); Eq. (2) gives the distance;
-// the lower bound plugs est + half-width into Eq. (2).
-__device__ __forceinline__ void estimate(const PairRec& r, float2 f, int ip, int pc, float hwk,
-                                         float& est, float& dist, float& lb) {
-  const float a = f.x, ipo = f.y;
-  const float xq = fmaf(r.k1, (float)ip, fmaf(r.k2, (float)pc, r.k0));
-  const float inv = __builtin_amdgcn_rcpf(ipo);
-  est = xq * inv;
-  const float ab2 = 2.f * a * r.b;
-  const float base = fmaf(a, a, r.b * r.b);
-  dist = fmaf(-ab2, est, base);
-  const float hw = sqrtf(fmaxf(fmaf(-ipo, ipo, 1.f), 0.f)) * inv * hwk;
-  lb = fmaf(-ab2, hw, dist);
-}
-
 // Work-unit tables: entry = (query << 38) | (probe rank << 28) | chunk.
 __device__ __forceinline__ uint64_t pack_unit(int64_t q, int r, int c) {
   return ((uint64_t)q << 38) | ((uint64_t)r << 28) | (uint64_t)c;
@@ -321,140 +268,6 @@ __global__ void k_units(SearchDev s) {
       const uint64_t e = pack_unit(q, r, c);
       if (j < p0) s.units0[b0 + j] = e; else s.units1[b1 + (j - p0)] = e;
     }
-  }
-}
-
-struct Unit {
-  int64_t q;
-  int r, c;
-  int64_t g;            // pair index
-  int64_t start, end;   // code positions
-  int64_t codeoff;      // query code-space offset of the chunk start
-  int64_t count_slot;   // seg_count index
-};
-
-__device__ __forceinline__ Unit load_unit(const SearchDev& s, uint64_t e) {
-  Unit w;
-  w.q = uniform_i64((int64_t)(e >> 38));
-  w.r = uniform_i32((int)((e >> 28) & 1023u));
-  w.c = uniform_i32((int)(e & ((1u << 28) - 1u)));
-  w.g = w.q * s.nprobe + w.r;
-  const int list = uniform_i32(s.pairs[w.g].list);
-  const int32_t* choff = s.pair_choff + w.q * (s.nprobe + 1);
-  const int32_t* codeoff = s.pair_codeoff + w.q * (s.nprobe + 1);
-  const int64_t lbeg = uniform_i64(s.list_off[list]), lend = uniform_i64(s.list_off[list + 1]);
-  w.start = lbeg + (int64_t)w.c * s.chunk;
-  w.end = lend < w.start + s.chunk ? lend : w.start + s.chunk;
-  w.codeoff = uniform_i64((int64_t)codeoff[w.r] + (int64_t)w.c * s.chunk);
-  w.count_slot = uniform_i64(s.off_ch[w.q] + choff[w.r] + w.c);
-  return w;
-}
-
-// Scan of one chunk: UN blocks of 64 codes per iteration, one code per lane
-// per block, all loads of an iteration issued before the arithmetic.
-template <int WS, int UN>
-__device__ __forceinline__ int scan_chunk(const SearchDev& s, int phase, const Unit& w,
-                                          const PairRec& rec, const Planes<WS>& pl, float tau,
-                                          float hwk) {
-  const int lane = lane_id();
-  const int64_t seg_base = s.off_seg[w.q] + w.codeoff;
-  const int64_t p0base = phase == 0 ? s.off_n0[w.q] + w.codeoff : 0;
-  int count = 0;
-  for (int64_t b0 = w.start; b0 < w.end; b0 += 64 * UN) {
-    int64_t p[UN];
-    bool valid[UN];
-    float2 f[UN];
-    int ip[UN], pc[UN];
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      valid[u] = b0 + 64 * u + lane < w.end;
-      p[u] = valid[u] ? b0 + 64 * u + lane : w.start;   // masked lanes read an in-bounds code
-      f[u] = s.fac[p[u]];
-    }
-    if constexpr (WS > 0) {
-      uint64_t x[UN][WS];
-#pragma unroll
-      for (int u = 0; u < UN; ++u)
-#pragma unroll
-        for (int t = 0; t < WS; ++t) x[u][t] = s.codes[code_word_index(p[u], t, WS)];
-#pragma unroll
-      for (int u = 0; u < UN; ++u) {
-        int s0 = 0, s1 = 0, s2 = 0, s3 = 0, c = 0;
-#pragma unroll
-        for (int t = 0; t < WS; ++t) {
-          c += __popcll(x[u][t]);
-          s0 += __popcll(x[u][t] & pl.get(0, t));
-          s1 += __popcll(x[u][t] & pl.get(1, t));
-          s2 += __popcll(x[u][t] & pl.get(2, t));
-          s3 += __popcll(x[u][t] & pl.get(3, t));
-        }
-        ip[u] = s0 + 2 * s1 + 4 * s2 + 8 * s3;
-        pc[u] = c;
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < UN; ++u) code_ip<WS>(s.codes, p[u], s.W, pl, ip[u], pc[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < UN; ++u) {
-      float est, dist, lb;
-      estimate(rec, f[u], ip[u], pc[u], hwk, est, dist, lb);
-      lb = valid[u] ? lb : __builtin_inff();
-      const int64_t off = p[u] - w.start;
-      if (phase == 0) {
-        if (valid[u]) {
-          Cand cd;
-          cd.pos = (int32_t)p[u];
-          cd.lb = lb;
-          s.seg[seg_base + off] = cd;
-          EstEnt e;
-          e.dist = dist;
-          e.slot = (int32_t)(w.codeoff + off);
-          s.p0buf[p0base + off] = e;
-        }
-      } else {
-        const bool pass = valid[u] && (lb <= tau);
-        const uint64_t m = __ballot(pass);
-        if (pass) {
-          Cand cd;
-          cd.pos = (int32_t)p[u];
-          cd.lb = lb;
-          s.seg[seg_base + count + __popcll(m & lanemask_lt())] = cd;
-        }
-        count += __popcll(m);
-      }
-    }
-  }
-  return phase == 0 ? (int)(w.end - w.start) : count;
-}
-
-// Persistent scan: wave i of the grid takes units i, i + nwaves, ... of the
-// phase's unit table (units are chunks of at most `chunk` codes, so a static
-// round-robin balances them; no atomics and no per-unit searches).
-template <int WS, int UN>
-__global__ __launch_bounds__(kThreads) void k_scan_popcnt(SearchDev s, int phase) {
-  __shared__ uint64_t lds_planes[kWaves][4 * (kMaxCodeBits / 64)];
-  const int wave = threadIdx.x >> 6, lane = lane_id();
-  const int64_t total = uniform_i64((phase == 0 ? s.off_p0 : s.off_p1)[s.nq]);
-  const uint64_t* tab = phase == 0 ? s.units0 : s.units1;
-  const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
-  const int64_t nw = (int64_t)gridDim.x * kWaves;
-  for (int64_t u = uniform_i64((int64_t)blockIdx.x * kWaves + wave); u < total; u += nw) {
-    const Unit w = load_unit(s, tab[u]);
-    const PairRec rec = s.pairs[w.g];
-    const uint64_t* src = s.planes + w.g * 4 * s.W;
-    Planes<WS> pl;
-    if constexpr (WS > 0) {
-      pl.load(src, s.W);
-    } else {
-      uint64_t* dst = lds_planes[wave];
-      for (int i = lane; i < 4 * s.W; i += kWave) dst[i] = src[i];
-      pl.p = dst;
-      pl.W = s.W;
-    }
-    const float tau = phase == 0 ? __builtin_inff() : uniform_f32(s.tau[w.q]);
-    const int count = scan_chunk<WS, UN>(s, phase, w, rec, pl, tau, hwk);
-    if (lane == 0) s.seg_count[w.count_slot] = count;
   }
 }
 
@@ -866,10 +679,6 @@ __global__ __launch_bounds__(kThreads) void k_debug_scan(SearchDev s, const Pair
   lb_o[o] = lb;
 }
 
-template <int WS, int UN>
-void launch_scan_ws(const SearchDev& s, int phase, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_scan_popcnt<WS, UN>), dim3(grid), dim3(kThreads), 0, st, s, phase);
-}
 
 }  // namespace
 
@@ -905,16 +714,6 @@ hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st) {
-  switch (s.W) {
-    case 1: launch_scan_ws<1, 4>(s, phase, grid, st); break;
-    case 2: launch_scan_ws<2, 4>(s, phase, grid, st); break;
-    case 3: launch_scan_ws<3, 4>(s, phase, grid, st); break;
-    case 4: launch_scan_ws<4, 2>(s, phase, grid, st); break;
-    default: launch_scan_ws<0, 2>(s, phase, grid, st); break;
-  }
-  return hipGetLastError();
-}
 
 hipError_t launch_tau(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
