@@ -338,9 +338,10 @@ def main():
         ids, _, st = idx.search(q, k, p, scan_kernel=kern, stats=True)
         rc = recall(ids.cpu().numpy(), gt_d, wl.data, wl.queries, k)
         sweep[p] = {"recall@10": round(rc, 4), "reranked_per_query": st["reranked"] / len(wl.queries),
+                    "candidates_per_query": st["candidates"] / len(wl.queries),
                     "codes_per_query": st["codes_scanned"] / len(wl.queries)}
         log(f"nprobe={p}: recall@10={rc:.4f} reranked/q={sweep[p]['reranked_per_query']:.1f} "
-            f"codes/q={sweep[p]['codes_per_query']:.0f}")
+            f"candidates/q={sweep[p]['candidates_per_query']:.1f} codes/q={sweep[p]['codes_per_query']:.0f}")
         if not args.nprobe and rc >= 0.95:
             chosen = p
             break

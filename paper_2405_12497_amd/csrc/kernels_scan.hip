@@ -186,7 +186,7 @@ __global__ void k_plan(SearchDev s) {
     if (p0 < 0) {
       for (int c = 0; c < nc; ++c) {
         n0 += min(s.chunk, n - c * s.chunk);
-        if (n0 >= s.k) {
+        if (n0 >= s.boot) {
           p0 = ch + c + 1;
           break;
         }
@@ -197,7 +197,7 @@ __global__ void k_plan(SearchDev s) {
   }
   choff[s.nprobe] = ch;
   codeoff[s.nprobe] = code;
-  if (p0 < 0) p0 = ch;   // fewer than k codes probed: everything is bootstrap
+  if (p0 < 0) p0 = ch;   // fewer than boot codes probed: everything is bootstrap
   s.q_nch[q] = ch;
   s.q_p0[q] = p0;
   s.q_n0[q] = n0;
@@ -205,47 +205,69 @@ __global__ void k_plan(SearchDev s) {
 }
 
 // Exclusive prefix sums over queries (single block) and work-counter reset.
+// Thread t owns the contiguous queries [t*per, (t+1)*per): it sums them, the
+// block scans the 1024 sums (shuffle scan in each wave, then the 16 wave
+// totals), and the thread writes its queries' offsets in a second pass.
 __global__ __launch_bounds__(1024) void k_offsets(SearchDev s) {
-  __shared__ int64_t buf[5][1024];
-  __shared__ int64_t carry[5];
-  if (threadIdx.x < 5) carry[threadIdx.x] = 0;
-  if (threadIdx.x == 0) {
+  constexpr int kT = 1024, kNW = kT / kWave;
+  __shared__ int64_t wtot[kNW][5];
+  const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+  if (t == 0) {
     s.counters[0] = 0;
     s.counters[1] = 0;
   }
+  const int64_t per = (s.nq + kT - 1) / kT;
+  const int64_t q0 = min<int64_t>(s.nq, t * per), q1 = min<int64_t>(s.nq, q0 + per);
+  auto vals = [&](int64_t q, int64_t (&v)[5]) {
+    const int64_t nch = s.q_nch[q], p0 = s.q_p0[q];
+    v[0] = nch;
+    v[1] = p0;
+    v[2] = nch - p0;
+    v[3] = s.q_ncode[q];
+    v[4] = s.q_n0[q];
+  };
+  int64_t sum[5] = {0, 0, 0, 0, 0};
+  for (int64_t q = q0; q < q1; ++q) {
+    int64_t v[5];
+    vals(q, v);
+#pragma unroll
+    for (int a = 0; a < 5; ++a) sum[a] += v[a];
+  }
+  int64_t inc[5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    int64_t x = sum[a];
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t y = __shfl_up(x, o, kWave);
+      if (lane >= o) x += y;
+    }
+    inc[a] = x;
+  }
+  if (lane == kWave - 1)
+#pragma unroll
+    for (int a = 0; a < 5; ++a) wtot[wave][a] = inc[a];
   __syncthreads();
-  for (int64_t base = 0; base < s.nq; base += 1024) {
-    const int64_t q = base + threadIdx.x;
-    int64_t v[5] = {0, 0, 0, 0, 0};
-    if (q < s.nq) {
-      v[0] = s.q_nch[q];
-      v[1] = s.q_p0[q];
-      v[2] = s.q_nch[q] - s.q_p0[q];
-      v[3] = s.q_ncode[q];
-      v[4] = s.q_n0[q];
-    }
-    for (int a = 0; a < 5; ++a) buf[a][threadIdx.x] = v[a];
-    __syncthreads();
-    // Hillis-Steele inclusive scan
-    for (int o = 1; o < 1024; o <<= 1) {
-      int64_t t[5];
-      for (int a = 0; a < 5; ++a) t[a] = (threadIdx.x >= (unsigned)o) ? buf[a][threadIdx.x - o] : 0;
-      __syncthreads();
-      for (int a = 0; a < 5; ++a) buf[a][threadIdx.x] += t[a];
-      __syncthreads();
-    }
-    int64_t* outs[5] = {s.off_ch, s.off_p0, s.off_p1, s.off_seg, s.off_n0};
-    if (q < s.nq)
-      for (int a = 0; a < 5; ++a) outs[a][q] = carry[a] + buf[a][threadIdx.x] - v[a];
-    __syncthreads();
-    if (threadIdx.x == 1023)
-      for (int a = 0; a < 5; ++a) carry[a] += buf[a][1023];
-    __syncthreads();
+  int64_t run[5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    int64_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wtot[w][a];
+    run[a] = before + inc[a] - sum[a];
   }
-  if (threadIdx.x == 0) {
-    int64_t* outs[5] = {s.off_ch, s.off_p0, s.off_p1, s.off_seg, s.off_n0};
-    for (int a = 0; a < 5; ++a) outs[a][s.nq] = carry[a];
+  int64_t* outs[5] = {s.off_ch, s.off_p0, s.off_p1, s.off_seg, s.off_n0};
+  for (int64_t q = q0; q < q1; ++q) {
+    int64_t v[5];
+    vals(q, v);
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      outs[a][q] = run[a];
+      run[a] += v[a];
+    }
   }
+  if (t == kT - 1)
+#pragma unroll
+    for (int a = 0; a < 5; ++a) outs[a][s.nq] = run[a];
 }
 
 // Work-unit tables: entry = (query << 38) | (probe rank << 28) | chunk.
@@ -272,31 +294,63 @@ __global__ void k_units(SearchDev s) {
 }
 
 // ------------------------------------------------------------------ exact distance
-// Squared distance of the raw vector at `pos` to the query in LDS, computed by
-// a group of `lpc` consecutive lanes (lpc divides 64).
-__device__ __forceinline__ float group_dist(const float* __restrict__ raw, int64_t pos, int dim,
-                                            const float* __restrict__ qv, int sub, int lpc) {
-  const float* o = raw + pos * dim;
-  float acc = 0.f;
-  if ((dim & 3) == 0) {   // rows are 16-byte aligned: float4 loads
-    const float4* o4 = reinterpret_cast<const float4*>(o);
+// Squared distances of up to NC raw vectors (list-order positions pos[j],
+// -1 = none) to the query in LDS, by a group of 8 consecutive lanes: lane
+// `sub` accumulates the columns sub, sub + 8, ... (float4 columns when rows are
+// 16-byte aligned) in order, then the group reduces by xor-shuffles 4, 2, 1.
+// The loads of all NC vectors are issued together. Every exact distance on
+// the device comes from this routine, so equal vectors get equal bits.
+constexpr int kLpc = 8;
+
+template <int N>
+struct IntC {
+  static constexpr int value = N;
+};
+
+template <int NC>
+__device__ __forceinline__ void group_dists(const float* __restrict__ raw, const int32_t (&pos)[NC], int dim,
+                                            const float* __restrict__ qv, int sub, float (&out)[NC]) {
+  float acc[NC];
+  int64_t base[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    acc[j] = 0.f;
+    base[j] = (int64_t)(pos[j] >= 0 ? pos[j] : 0) * dim;   // absent entries read row 0
+  }
+  if ((dim & 3) == 0) {
     const float4* q4 = reinterpret_cast<const float4*>(qv);
-    for (int i = sub; i < (dim >> 2); i += lpc) {
-      const float4 a = o4[i], b = q4[i];
-      const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
-      acc = fmaf(dx, dx, acc);
-      acc = fmaf(dy, dy, acc);
-      acc = fmaf(dz, dz, acc);
-      acc = fmaf(dw, dw, acc);
+    for (int i = sub; i < (dim >> 2); i += kLpc) {
+      const float4 b = q4[i];
+      float4 a[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) a[j] = reinterpret_cast<const float4*>(raw + base[j])[i];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const float dx = a[j].x - b.x, dy = a[j].y - b.y, dz = a[j].z - b.z, dw = a[j].w - b.w;
+        acc[j] = fmaf(dx, dx, acc[j]);
+        acc[j] = fmaf(dy, dy, acc[j]);
+        acc[j] = fmaf(dz, dz, acc[j]);
+        acc[j] = fmaf(dw, dw, acc[j]);
+      }
     }
   } else {
-    for (int i = sub; i < dim; i += lpc) {
-      const float d = o[i] - qv[i];
-      acc = fmaf(d, d, acc);
+    for (int i = sub; i < dim; i += kLpc) {
+      const float b = qv[i];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const float d = raw[base[j] + i] - b;
+        acc[j] = fmaf(d, d, acc[j]);
+      }
     }
   }
-  for (int off = lpc >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-  return acc;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    float v = acc[j];
+    v += __shfl_xor(v, 4, kWave);
+    v += __shfl_xor(v, 2, kWave);
+    v += __shfl_xor(v, 1, kWave);
+    out[j] = v;
+  }
 }
 
 __device__ __forceinline__ bool less_di(float d1, int64_t i1, float d2, int64_t i2) {
@@ -309,26 +363,90 @@ __device__ __forceinline__ bool less_di(float d1, int64_t i1, float d2, int64_t 
 // marked done (pos = -1).
 __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
   extern __shared__ float qv[];          // dim floats
-  __shared__ uint64_t key[kMaxP0];
+  __shared__ uint64_t key[kMaxP0];       // the selected keys, sorted
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sh_prefix, sh_need, sh_cnt;
   __shared__ int32_t toppos[kMaxK];
   __shared__ uint64_t key2[kMaxK];
+  constexpr int kPerT = kMaxP0 / kThreads;
   const int64_t q = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
   const int n0 = uniform_i32(s.q_n0[q]);
   const int64_t b0 = uniform_i64(s.off_n0[q]);
+  const int m = min(n0, min(kMaxK, 4 * s.k));
   for (int i = threadIdx.x; i < s.dim; i += kThreads) qv[i] = s.q[q * s.dim + i];
-  int n2 = 1;
-  while (n2 < n0) n2 <<= 1;
-  for (int i = threadIdx.x; i < n2; i += kThreads) {
+  // keys (sortable estimated distance << 32 | slot) held in registers
+  uint64_t kk[kPerT];
+#pragma unroll
+  for (int j = 0; j < kPerT; ++j) {
+    const int i = threadIdx.x + j * kThreads;
+    kk[j] = ~0ull;
     if (i < n0) {
       const EstEnt e = s.p0buf[b0 + i];
-      // order by estimated distance (as a sortable key), then slot
       uint32_t kb = __float_as_uint(e.dist);
       kb = (kb & 0x80000000u) ? ~kb : (kb | 0x80000000u);
-      key[i] = ((uint64_t)kb << 32) | (uint32_t)e.slot;
-    } else {
-      key[i] = ~0ull;
+      kk[j] = ((uint64_t)kb << 32) | (uint32_t)e.slot;
     }
   }
+  // radix select (8 bits per pass) of the m-th smallest high word T
+  uint32_t prefix = 0, mask = 0, need = (uint32_t)m;
+  for (int pass = 0; pass < 4 && m > 0; ++pass) {
+    const int shift = 24 - 8 * pass;
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+      const int i = threadIdx.x + j * kThreads;
+      const uint32_t hi = (uint32_t)(kk[j] >> 32);
+      if (i < n0 && (hi & mask) == prefix) atomicAdd(&hist[(hi >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const uint32_t c0 = hist[4 * lane], c1 = hist[4 * lane + 1], c2 = hist[4 * lane + 2], c3 = hist[4 * lane + 3];
+      const uint32_t tot = c0 + c1 + c2 + c3;
+      uint32_t inc = tot;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += y;
+      }
+      const uint32_t exc = inc - tot;
+      if (exc < need && need <= inc) {   // exactly one lane holds the m-th key's bin
+        uint32_t before = exc, bin = 4 * lane;
+        if (before + c0 < need) {
+          before += c0;
+          ++bin;
+          if (before + c1 < need) {
+            before += c1;
+            ++bin;
+            if (before + c2 < need) {
+              before += c2;
+              ++bin;
+            }
+          }
+        }
+        sh_prefix = prefix | (bin << shift);
+        sh_need = need - before;
+      }
+    }
+    __syncthreads();
+    prefix = sh_prefix;
+    need = sh_need;
+    mask |= 0xFFu << shift;
+  }
+  // compact the keys with high word <= T (the m smallest plus ties at T), then sort them
+  if (threadIdx.x == 0) sh_cnt = 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kPerT; ++j) {
+    const int i = threadIdx.x + j * kThreads;
+    if (i < n0 && m > 0 && (uint32_t)(kk[j] >> 32) <= prefix) key[atomicAdd(&sh_cnt, 1u)] = kk[j];
+  }
+  __syncthreads();
+  const int nsel = uniform_i32((int)sh_cnt);
+  int n2 = 1;
+  while (n2 < nsel) n2 <<= 1;
+  for (int i = nsel + threadIdx.x; i < n2; i += kThreads) key[i] = ~0ull;
   __syncthreads();
   for (int size = 2; size <= n2; size <<= 1)
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -343,20 +461,41 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
       }
       __syncthreads();
     }
-  const int m = min(s.k, n0);
+  // Exact distances for the m best-estimated bootstrap codes (m = 4k, at most
+  // kMaxK and n0). The k best of them by (distance, id) seed the top-k and
+  // tau = the k-th; the others cannot enter the top-k (k better ones are
+  // known), so all m are marked done.
   const int64_t seg0 = uniform_i64(s.off_seg[q]);
-  const int lpc = s.dim <= 256 ? 16 : 64;
-  const int grp = threadIdx.x / lpc, sub = threadIdx.x % lpc;
-  for (int i = grp; i < m; i += kThreads / lpc) {
-    const int32_t slot = (int32_t)(uint32_t)(key[i] & 0xffffffffu);
-    const int32_t pos = s.seg[seg0 + slot].pos;
-    const float d = group_dist(s.raw, pos, s.dim, qv, sub, lpc);
-    if (sub == 0) {
-      toppos[i] = pos;
-      s.seg[seg0 + slot].pos = -1;
-      // exact distances are >= 0, so their bits order like the values; ids < 2^31
-      key2[i] = ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)s.ids[pos];
-    }
+  {
+    constexpr int kGroups = kThreads / kLpc;
+    const int grp = threadIdx.x / kLpc, sub = threadIdx.x % kLpc;
+    auto run = [&](auto nc_tag) {
+      constexpr int NC = decltype(nc_tag)::value;
+      int32_t pos[NC], slot[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int i = grp + j * kGroups;
+        slot[j] = i < m ? (int32_t)(uint32_t)(key[i] & 0xffffffffu) : -1;
+        pos[j] = i < m ? s.seg[seg0 + slot[j]].pos : -1;
+      }
+      float d[NC];
+      group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int i = grp + j * kGroups;
+        if (sub == 0 && i < m) {
+          toppos[i] = pos[j];
+          s.seg[seg0 + slot[j]].pos = -1;
+          // exact distances are >= 0, so their bits order like the values; ids < 2^31
+          key2[i] = ((uint64_t)__float_as_uint(d[j]) << 32) | (uint64_t)(uint32_t)s.ids[pos[j]];
+        }
+      }
+    };
+    const int per = uniform_i32((m + kGroups - 1) / kGroups);
+    if (per <= 1) run(IntC<1>{});
+    else if (per <= 2) run(IntC<2>{});
+    else if (per <= 4) run(IntC<4>{});
+    else run(IntC<8>{});
   }
   int m2 = 1;
   while (m2 < m) m2 <<= 1;
@@ -381,7 +520,7 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
     }
   for (int i = threadIdx.x; i < s.k; i += kThreads) {
     SeedEnt e;
-    if (i < m) {
+    if (i < min(m, s.k)) {
       e.dist = __uint_as_float((uint32_t)(key2[i] >> 32));
       e.pos = toppos[i];
     } else {
@@ -390,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
     }
     s.seedk[q * s.k + i] = e;
   }
-  if (threadIdx.x == 0) s.tau[q] = (m == s.k) ? __uint_as_float((uint32_t)(key2[s.k - 1] >> 32)) : __builtin_inff();
+  if (threadIdx.x == 0) s.tau[q] = (m >= s.k) ? __uint_as_float((uint32_t)(key2[s.k - 1] >> 32)) : __builtin_inff();
 }
 
 // ------------------------------------------------------------------ finalize (S7)
@@ -399,8 +538,8 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
 // to kFinWin entries, sorted by lower bound, and reranked in ascending-bound
 // rounds: a candidate is dropped when its bound exceeds tau (and, the window
 // being sorted, so is the rest of the window); the others get their exact
-// distance (groups of lanes per candidate), wave 0 inserts them in order and
-// tau drops to the running k-th exact distance.
+// distance (groups of lanes per candidate), the round is merged into the
+// top-k by parallel ranking, and tau drops to the running k-th exact distance.
 constexpr int kFinChunks = 256;
 constexpr int kFinWin = 1024;
 constexpr int kFinRound = 128;
@@ -446,9 +585,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
     sh_tau = (cnt0 == K) ? s.seedk[q * K + K - 1].dist : __builtin_inff();
   }
   __syncthreads();
-  const int lpc = s.dim <= 256 ? 16 : 64;
-  const int ngroups = kThreads / lpc;
-  const int grp = threadIdx.x / lpc, sub = threadIdx.x % lpc;
+  constexpr int ngroups = kThreads / kLpc;
+  const int grp = threadIdx.x / kLpc, sub = threadIdx.x % kLpc;
   int reranked = cnt0;
   int ncand_total = 0;
   const int nch = uniform_i32(s.q_nch[q]);
@@ -540,59 +678,70 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
           }
           n = uniform_i32(lo);
         }
-        for (int i = grp; i < n; i += ngroups) {
-          const int32_t pi = (int32_t)(uint32_t)(win[r0 + i] & 0xffffffffu);
-          const float d = group_dist(s.raw, pi, s.dim, qv, sub, lpc);
-          if (sub == 0) {
-            cd[i] = d;
-            cid[i] = s.ids[pi];
-          }
+        {
+          // exact distances of the round's n candidates: 32 groups of 8 lanes,
+          // up to 4 candidates per group with their loads in flight together
+          auto run = [&](auto nc_tag) {
+            constexpr int NC = decltype(nc_tag)::value;
+            int32_t pos[NC];
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              const int i = grp + j * ngroups;
+              pos[j] = i < n ? (int32_t)(uint32_t)(win[r0 + i] & 0xffffffffu) : -1;
+            }
+            float d[NC];
+            group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              const int i = grp + j * ngroups;
+              if (sub == 0 && i < n) {
+                cd[i] = d[j];
+                cid[i] = s.ids[pos[j]];
+              }
+            }
+          };
+          static_assert(kFinRound <= 4 * ngroups, "a round is at most 4 candidates per group");
+          const int per = (n + ngroups - 1) / ngroups;
+          if (per <= 1) run(IntC<1>{});
+          else if (per <= 2) run(IntC<2>{});
+          else run(IntC<4>{});
         }
         __syncthreads();
-        if (wave == 0) {
-          int cnt = uniform_i32(sh_cnt);
-          float kth = uniform_f32(td[K - 1]);
-          int64_t kid = uniform_i64(tid[K - 1]);
-          for (int i = 0; i < n; ++i) {
-            const float d = uniform_f32(cd[i]);
-            const int64_t id = uniform_i64(cid[i]);
-            if (cnt == K && !less_di(d, id, kth, kid)) continue;
-            int bef = 0;
-            for (int t = lane; t < cnt; t += kWave) bef += less_di(td[t], tid[t], d, id);
-            bef = wave_sum_i(bef);
-            const int last = min(cnt, K - 1);   // entries [bef, last) shift right by one
-            float sd[kMaxK / kWave];
-            int64_t si[kMaxK / kWave];
+        {
+          // merge the round into the top-k: every element of (top-k so far) u
+          // (round) takes its rank by (distance, id) among all of them (ids are
+          // distinct, so ranks are too) and the first K ranks are written back
+          const int cnt = uniform_i32(sh_cnt);
+          const int mtot = cnt + n;   // <= K + kFinRound <= 2 * kThreads
+          float ed[2];
+          int64_t eid[2];
+          int er[2];
 #pragma unroll
-            for (int t = 0; t < kMaxK / kWave; ++t) {
-              const int x = lane + t * kWave;
-              if (x >= bef && x < last) {
-                sd[t] = td[x];
-                si[t] = tid[x];
-              }
+          for (int h = 0; h < 2; ++h) {
+            const int e = threadIdx.x + h * kThreads;
+            er[h] = K;
+            if (e < mtot) {
+              ed[h] = e < cnt ? td[e] : cd[e - cnt];
+              eid[h] = e < cnt ? tid[e] : cid[e - cnt];
+              int r = 0;
+              for (int t = 0; t < cnt; ++t) r += less_di(td[t], tid[t], ed[h], eid[h]);
+              for (int t = 0; t < n; ++t) r += less_di(cd[t], cid[t], ed[h], eid[h]);
+              er[h] = r;
             }
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int t = 0; t < kMaxK / kWave; ++t) {
-              const int x = lane + t * kWave;
-              if (x >= bef && x < last) {
-                td[x + 1] = sd[t];
-                tid[x + 1] = si[t];
-              }
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) {
-              td[bef] = d;
-              tid[bef] = id;
-            }
-            __builtin_amdgcn_wave_barrier();
-            cnt = min(cnt + 1, K);
-            kth = uniform_f32(td[K - 1]);
-            kid = uniform_i64(tid[K - 1]);
           }
-          if (lane == 0) {
-            sh_cnt = cnt;
-            if (cnt == K) sh_tau = fminf(sh_tau, td[K - 1]);
+          __syncthreads();
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (er[h] < K) {
+              td[er[h]] = ed[h];
+              tid[er[h]] = eid[h];
+            }
+          }
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            const int c2 = min(mtot, K);
+            sh_cnt = c2;
+            if (c2 == K) sh_tau = fminf(sh_tau, td[K - 1]);
           }
         }
         reranked += n;

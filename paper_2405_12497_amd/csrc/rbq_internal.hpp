@@ -13,7 +13,16 @@ constexpr int kMaxK = 256;         // largest k returned by a search
 constexpr int kMaxNprobe = 1024;
 constexpr int kMaxCodeBits = 4096;
 constexpr int kDefaultChunk = 1024;  // codes per scan work unit
-constexpr int kMaxP0 = 2048;       // bootstrap codes per query: k - 1 + chunk <= kMaxP0
+constexpr int kMaxP0 = 2048;       // bootstrap codes per query: boot - 1 + chunk <= kMaxP0
+constexpr int kBootCodes = 512;    // bootstrap target: at least this many codes (and k)
+
+// Bootstrap target for a search with k results and `chunk` codes per unit
+// (chunk <= kMaxP0 + 1 - k): a query's bootstrap covers whole chunks until it
+// holds >= boot codes, i.e. at most boot - 1 + chunk <= kMaxP0 codes.
+inline int boot_codes(int k, int chunk) {
+  const int cap = kMaxP0 + 1 - chunk;
+  return k > (kBootCodes < cap ? kBootCodes : cap) ? k : (kBootCodes < cap ? kBootCodes : cap);
+}
 
 // Per (query, probed list) constants of the quantised query (Sec. 3.3.1-3.3.2).
 // <x_bar, q_bar> = k1 * <x_b, q_u> + k2 * popcount(x_b) + k0
@@ -46,10 +55,47 @@ struct SeedEnt {
 // ------------------------------------------------------------------ device helpers
 #if defined(__HIPCC__)
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+// Wave-wide reductions for full waves (all 64 lanes active). Within each row
+// of 16 lanes: DPP quad swaps (xor 1, xor 2), half-row mirror, row mirror —
+// plain VALU ops, every lane ends with its row's result; the four row results
+// are combined through readlane, so the result is uniform and bit-identical
+// in every lane.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
+}
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(dpp_i32<kCtrl>(__float_as_int(v)));
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within 8
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within 16
+
+template <typename T, typename Op>
+__device__ __forceinline__ T row_reduce(T v, Op op) {
+  if constexpr (sizeof(T) == 4 && !__is_same(T, int)) {
+    v = op(v, dpp_f32<kDppXor1>(v));
+    v = op(v, dpp_f32<kDppXor2>(v));
+    v = op(v, dpp_f32<kDppHalfMirror>(v));
+    v = op(v, dpp_f32<kDppMirror>(v));
+  } else {
+    v = op(v, dpp_i32<kDppXor1>(v));
+    v = op(v, dpp_i32<kDppXor2>(v));
+    v = op(v, dpp_i32<kDppHalfMirror>(v));
+    v = op(v, dpp_i32<kDppMirror>(v));
+  }
   return v;
+}
+__device__ __forceinline__ float readlane_f32(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  auto add = [](float a, float b) { return a + b; };
+  v = row_reduce(v, add);
+  return (readlane_f32(v, 0) + readlane_f32(v, 16)) + (readlane_f32(v, 32) + readlane_f32(v, 48));
 }
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -57,19 +103,20 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 __device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  auto add = [](int a, int b) { return a + b; };
+  v = row_reduce(v, add);
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
-  return v;
+  auto mn = [](float a, float b) { return fminf(a, b); };
+  v = row_reduce(v, mn);
+  return fminf(fminf(readlane_f32(v, 0), readlane_f32(v, 16)), fminf(readlane_f32(v, 32), readlane_f32(v, 48)));
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-  return v;
+  auto mx = [](float a, float b) { return fmaxf(a, b); };
+  v = row_reduce(v, mx);
+  return fmaxf(fmaxf(readlane_f32(v, 0), readlane_f32(v, 16)), fmaxf(readlane_f32(v, 32), readlane_f32(v, 48)));
 }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
@@ -176,6 +223,7 @@ struct SearchDev {
   int nprobe;               // row stride of per-pair arrays
   int k;
   int chunk;                // codes per work unit
+  int boot;                 // bootstrap target: phase 0 covers >= boot codes (boot >= k)
   const int32_t* probe;     // nq x nprobe
   const int32_t* nprobe_q;  // nq or null
   // per pair

@@ -501,7 +501,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.seg_count.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
   HIPCHK(w.units0.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 8));
   HIPCHK(w.units1.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 8));
-  HIPCHK(w.p0buf.ensure((size_t)nq * (k - 1 + chunk) * sizeof(EstEnt)));
+  HIPCHK(w.p0buf.ensure((size_t)nq * (boot_codes(k, chunk) - 1 + chunk) * sizeof(EstEnt)));
   HIPCHK(w.tau.ensure((size_t)nq * 4));
   HIPCHK(w.seedk.ensure((size_t)nq * k * sizeof(SeedEnt)));
   HIPCHK(w.q_rerank.ensure((size_t)nq * 4));
@@ -536,6 +536,7 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.nprobe = nprobe;
   s.k = k;
   s.chunk = chunk;
+  s.boot = boot_codes(k, chunk);
   s.probe = (const int32_t*)w.probe.p;
   s.nprobe_q = nprobe_q;
   s.pairs = (PairRec*)w.pairs.p;
