@@ -75,7 +75,7 @@ typedef struct rbq_index rbq_index;
 typedef struct {
   int32_t dim;           /* D, raw vector length, >= 1 */
   int32_t code_bits;     /* 0 => 64*ceil(D/64); else a multiple of 64, >= D, <= 4096 */
-  int32_t nlist;         /* number of IVF lists (1 = flat index) */
+  int32_t nlist;         /* number of IVF lists, 1..24576 (1 = flat index) */
   int32_t bq;            /* bits of the quantised query; must be 4 */
   float eps0;            /* confidence parameter of the error bound (Theorem 3.2) */
   int32_t rot_precision; /* RBQ_ROT_FP32 or RBQ_ROT_BF16X3 */
@@ -85,7 +85,7 @@ typedef struct {
 /* Per-search options. */
 typedef struct {
   int32_t k;                       /* neighbours to return, 1..256 */
-  int32_t nprobe;                  /* lists probed per query, 1..min(nlist, 1024) */
+  int32_t nprobe;                  /* lists probed per query, 1..min(nlist, 16384) */
   int32_t scan_kernel;             /* RBQ_SCAN_* */
   int32_t use_learned_nprobe;      /* 1: per-query nprobe from the loaded MLP
                                       (falls back to `nprobe` when none is set) */

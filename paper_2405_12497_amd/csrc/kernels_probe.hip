@@ -6,7 +6,7 @@ namespace rbq {
 namespace {
 
 constexpr int kSelThreads = 256;
-constexpr int kSelCap = 2048;   // keys kept by the sampled threshold (>= kMaxNprobe)
+constexpr int kSelCap = 2048;   // nprobe handled with the keys in LDS; above: k_select_probe_large
 
 // Bitonic sort of n (power of two) 64-bit keys in LDS, ascending.
 __device__ void bitonic_sort_u64(uint64_t* a, int n) {
@@ -185,12 +185,125 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __res
   }
 }
 
+// nprobe above kSelCap: the same exact selection with the keys read from the
+// distance row in global memory and the selected (key, list) pairs sorted in
+// dynamic LDS (next power of two of nprobe entries).
+__global__ __launch_bounds__(kSelThreads) void k_select_probe_large(const float* __restrict__ D, int nlist,
+                                                                    int nprobe,
+                                                                    const int32_t* __restrict__ nprobe_q,
+                                                                    int32_t* __restrict__ lists,
+                                                                    float* __restrict__ dists) {
+  extern __shared__ uint64_t selbig[];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sh_prefix, sh_rank, sh_nless;
+  __shared__ uint32_t tie_scan[kSelThreads];
+  const int64_t q = blockIdx.x;
+  int P = nprobe;
+  if (nprobe_q) P = uniform_i32(min(max(nprobe_q[q], 1), nprobe));
+  P = min(P, nlist);
+  const float* row = D + q * (int64_t)nlist;
+  auto key_of = [&](int k) { return __float_as_uint(fmaxf(row[k], 0.f)); };
+  if (threadIdx.x == 0) {
+    sh_prefix = 0;
+    sh_rank = P;
+  }
+  __syncthreads();
+  uint32_t mask = 0;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t prefix = (uint32_t)uniform_i32((int)sh_prefix);
+    for (int k = threadIdx.x; k < nlist; k += blockDim.x) {
+      const uint32_t key = key_of(k);
+      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t rank = sh_rank, cum = 0;
+      int b = 0;
+      for (; b < 256; ++b) {
+        if (cum + hist[b] >= rank) break;
+        cum += hist[b];
+      }
+      sh_rank = rank - cum;
+      sh_prefix = prefix | ((uint32_t)b << shift);
+    }
+    mask |= 255u << shift;
+    __syncthreads();
+  }
+  const uint32_t thr = (uint32_t)uniform_i32((int)sh_prefix);
+  const uint32_t need = (uint32_t)uniform_i32((int)sh_rank);
+  if (threadIdx.x == 0) sh_nless = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < nlist; k += blockDim.x) {
+    const uint32_t key = key_of(k);
+    if (key < thr) selbig[atomicAdd(&sh_nless, 1u)] = ((uint64_t)key << 32) | (uint32_t)k;
+  }
+  const int per = (nlist + blockDim.x - 1) / blockDim.x;
+  const int kb = threadIdx.x * per, ke = min(nlist, kb + per);
+  uint32_t mine = 0;
+  for (int k = kb; k < ke; ++k) mine += (key_of(k) == thr);
+  tie_scan[threadIdx.x] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      const uint32_t c = tie_scan[t];
+      tie_scan[t] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  const uint32_t nless = (uint32_t)P - need;
+  uint32_t rank = tie_scan[threadIdx.x];
+  for (int k = kb; k < ke && rank < need; ++k) {
+    if (key_of(k) == thr) {
+      selbig[nless + rank] = ((uint64_t)thr << 32) | (uint32_t)k;
+      ++rank;
+    }
+  }
+  __syncthreads();
+  int n2 = 1;
+  while (n2 < P) n2 <<= 1;
+  for (int i = P + threadIdx.x; i < n2; i += blockDim.x) selbig[i] = ~0ull;
+  __syncthreads();
+  bitonic_sort_u64(selbig, n2);
+  for (int i = threadIdx.x; i < nprobe; i += blockDim.x) {
+    if (i < P) {
+      lists[q * nprobe + i] = (int32_t)(uint32_t)(selbig[i] & 0xffffffffu);
+      if (dists) dists[q * nprobe + i] = __uint_as_float((uint32_t)(selbig[i] >> 32));
+    } else {
+      lists[q * nprobe + i] = -1;
+      if (dists) dists[q * nprobe + i] = __builtin_inff();
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_select_probe(const float* D, int64_t nq, int nlist, int nprobe,
                                const int32_t* nprobe_q, int32_t* lists, float* dists,
                                hipStream_t st) {
   if (nq <= 0) return hipSuccess;
+  if (nprobe > kSelCap) {
+    int n2 = 1;
+    while (n2 < nprobe) n2 <<= 1;
+    const size_t big = (size_t)n2 * sizeof(uint64_t);
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return hipErrorInvalidValue;
+    if (big + 4096 > (size_t)lim) return hipErrorInvalidConfiguration;
+    static bool big_attr = false;
+    if (!big_attr) {
+      (void)hipFuncSetAttribute((const void*)k_select_probe_large,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim - 4096);
+      big_attr = true;
+    }
+    hipLaunchKernelGGL(k_select_probe_large, dim3((unsigned)nq), dim3(kSelThreads), big, st, D, nlist,
+                       nprobe, nprobe_q, lists, dists);
+    return hipGetLastError();
+  }
   const size_t shm = (size_t)nlist * sizeof(uint32_t);
   static bool attr_done = false;
   if (!attr_done) {

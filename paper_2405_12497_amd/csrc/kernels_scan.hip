@@ -166,42 +166,65 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
 }
 
 // ------------------------------------------------------------------ planning
-// One thread per query: chunk and code prefixes over its probed pairs, and the
-// bootstrap (phase-0) chunk count.
-__global__ void k_plan(SearchDev s) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= s.nq) return;
+// One wave per query: chunk and code prefixes over its probed pairs (64 ranks
+// per step, shuffle scans), and the bootstrap: whole chunks in probe order up
+// to the first chunk at which the covered codes reach s.boot.
+__global__ __launch_bounds__(kThreads) void k_plan(SearchDev s) {
+  const int64_t q = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (q >= s.nq) return;   // whole waves
+  const int lane = lane_id();
   int P = s.nprobe;
-  if (s.nprobe_q) P = min(max(s.nprobe_q[q], 1), s.nprobe);
+  if (s.nprobe_q) P = uniform_i32(min(max(s.nprobe_q[q], 1), s.nprobe));
   int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
   int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
-  int32_t ch = 0, code = 0, p0 = -1, n0 = 0;
-  for (int r = 0; r < s.nprobe; ++r) {
-    choff[r] = ch;
-    codeoff[r] = code;
+  int32_t ch = 0, code = 0, p0 = -1, n0 = 0;   // wave-uniform running values
+  for (int r0 = 0; r0 < s.nprobe; r0 += kWave) {
+    const int r = r0 + lane;
+    int n = 0, nc = 0;
     const int list = (r < P) ? s.probe[q * s.nprobe + r] : -1;
-    if (list < 0) continue;
-    const int n = s.list_off[list + 1] - s.list_off[list];
-    const int nc = (n + s.chunk - 1) / s.chunk;
-    if (p0 < 0) {
-      for (int c = 0; c < nc; ++c) {
-        n0 += min(s.chunk, n - c * s.chunk);
-        if (n0 >= s.boot) {
-          p0 = ch + c + 1;
-          break;
-        }
+    if (list >= 0) {
+      n = s.list_off[list + 1] - s.list_off[list];
+      nc = (n + s.chunk - 1) / s.chunk;
+    }
+    int in = n, ic = nc;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int yn = __shfl_up(in, o, kWave), yc = __shfl_up(ic, o, kWave);
+      if (lane >= o) {
+        in += yn;
+        ic += yc;
       }
     }
-    ch += nc;
-    code += n;
+    const int exn = code + in - n, exc = ch + ic - nc;
+    if (r < s.nprobe) {
+      choff[r] = exc;
+      codeoff[r] = exn;
+    }
+    if (p0 < 0) {
+      const uint64_t m = __ballot(r < s.nprobe && exn + n >= s.boot);
+      if (m) {
+        const int l = __ffsll((long long)m) - 1;   // first rank whose codes reach boot
+        const int exn_l = __shfl(exn, l, kWave), exc_l = __shfl(exc, l, kWave), n_l = __shfl(n, l, kWave);
+        const int cstar = (s.boot - exn_l + s.chunk - 1) / s.chunk - 1;
+        p0 = uniform_i32(exc_l + cstar + 1);
+        n0 = uniform_i32(exn_l + min((cstar + 1) * s.chunk, n_l));
+      }
+    }
+    code = uniform_i32(code + __shfl(in, kWave - 1, kWave));
+    ch = uniform_i32(ch + __shfl(ic, kWave - 1, kWave));
   }
-  choff[s.nprobe] = ch;
-  codeoff[s.nprobe] = code;
-  if (p0 < 0) p0 = ch;   // fewer than boot codes probed: everything is bootstrap
-  s.q_nch[q] = ch;
-  s.q_p0[q] = p0;
-  s.q_n0[q] = n0;
-  s.q_ncode[q] = code;
+  if (p0 < 0) {   // fewer than boot codes probed: everything is bootstrap
+    p0 = ch;
+    n0 = code;
+  }
+  if (lane == 0) {
+    choff[s.nprobe] = ch;
+    codeoff[s.nprobe] = code;
+    s.q_nch[q] = ch;
+    s.q_p0[q] = p0;
+    s.q_n0[q] = n0;
+    s.q_ncode[q] = code;
+  }
 }
 
 // Exclusive prefix sums over queries (single block) and work-counter reset.
@@ -270,23 +293,25 @@ __global__ __launch_bounds__(1024) void k_offsets(SearchDev s) {
     for (int a = 0; a < 5; ++a) outs[a][s.nq] = run[a];
 }
 
-// Work-unit tables: entry = (query << 38) | (probe rank << 28) | chunk.
+// Work-unit tables: entry = (query << 40) | (probe rank << 24) | chunk, with
+// query < 2^24 (the rounding-key layout), rank < 2^16, chunk < 2^24.
 __device__ __forceinline__ uint64_t pack_unit(int64_t q, int r, int c) {
-  return ((uint64_t)q << 38) | ((uint64_t)r << 28) | (uint64_t)c;
+  return ((uint64_t)q << 40) | ((uint64_t)r << 24) | (uint64_t)c;
 }
 
-// One thread per query: its chunks in probe order, bootstrap ones to units0
-// (at off_p0[q]) and the others to units1 (at off_p1[q]).
-__global__ void k_units(SearchDev s) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per query, a lane per probe rank: its chunks, bootstrap ones to
+// units0 (at off_p0[q]) and the others to units1 (at off_p1[q]).
+__global__ __launch_bounds__(kThreads) void k_units(SearchDev s) {
+  const int64_t q = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (q >= s.nq) return;
+  const int lane = lane_id();
   const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
   const int p0 = s.q_p0[q];
   const int64_t b0 = s.off_p0[q], b1 = s.off_p1[q];
-  int j = 0;
-  for (int r = 0; r < s.nprobe; ++r) {
-    const int nc = choff[r + 1] - choff[r];
-    for (int c = 0; c < nc; ++c, ++j) {
+  for (int r = lane; r < s.nprobe; r += kWave) {
+    const int c0 = choff[r], nc = choff[r + 1] - c0;
+    for (int c = 0; c < nc; ++c) {
+      const int j = c0 + c;
       const uint64_t e = pack_unit(q, r, c);
       if (j < p0) s.units0[b0 + j] = e; else s.units1[b1 + (j - p0)] = e;
     }
@@ -602,7 +627,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
     for (int t = threadIdx.x * per; t < min(nj, (int)(threadIdx.x + 1) * per); ++t) {
       const int j = j0 + t;
       const uint64_t e = j < p0 ? s.units0[off0 + j] : s.units1[off1 + (j - p0)];
-      const int r = (int)((e >> 28) & 1023u), c = (int)(e & ((1u << 28) - 1u));
+      const int r = (int)((e >> 24) & 0xFFFFu), c = (int)(e & 0xFFFFFFu);
       cbase[t] = seg0 + codeoff[r] + (int64_t)c * s.chunk;
       cpre[t] = run;
       run += s.seg_count[ch0 + j];
@@ -857,9 +882,10 @@ hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st) {
 
 hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan, dim3((unsigned)((s.nq + 255) / 256)), dim3(256), 0, st, s);
+  const dim3 gq((unsigned)((s.nq + kWaves - 1) / kWaves));
+  hipLaunchKernelGGL(k_plan, gq, dim3(kThreads), 0, st, s);
   hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, st, s);
-  hipLaunchKernelGGL(k_units, dim3((unsigned)((s.nq + 255) / 256)), dim3(256), 0, st, s);
+  hipLaunchKernelGGL(k_units, gq, dim3(kThreads), 0, st, s);
   return hipGetLastError();
 }
 

@@ -10,7 +10,8 @@ namespace rbq {
 
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kMaxK = 256;         // largest k returned by a search
-constexpr int kMaxNprobe = 1024;
+constexpr int kMaxNprobe = 16384;   // the selection of more than 2048 lists sorts them in LDS
+constexpr int kMaxNlist = 24576;    // probe selection keeps a query's centroid distances in LDS
 constexpr int kMaxCodeBits = 4096;
 constexpr int kDefaultChunk = 1024;  // codes per scan work unit
 constexpr int kMaxP0 = 2048;       // bootstrap codes per query: boot - 1 + chunk <= kMaxP0

@@ -184,7 +184,8 @@ rbq_status check_params(const rbq_params* p) {
   if (p->dim < 1 || p->dim > kMaxCodeBits) return fail(RBQ_EINVAL, "dim %d out of range [1, %d]", p->dim, kMaxCodeBits);
   if (p->code_bits != 0 && (p->code_bits % 64 != 0 || p->code_bits < p->dim || p->code_bits > kMaxCodeBits))
     return fail(RBQ_EINVAL, "code_bits %d must be 0 or a multiple of 64 in [dim, %d]", p->code_bits, kMaxCodeBits);
-  if (p->nlist < 1 || p->nlist > (1 << 20)) return fail(RBQ_EINVAL, "nlist %d out of range", p->nlist);
+  if (p->nlist < 1 || p->nlist > kMaxNlist)
+    return fail(RBQ_EINVAL, "nlist %d outside [1, %d]", p->nlist, kMaxNlist);
   if (p->bq != 4) return fail(RBQ_EUNSUPPORTED, "bq=%d: only 4-bit queries are implemented", p->bq);
   if (!(p->eps0 >= 0.f) || !std::isfinite(p->eps0)) return fail(RBQ_EINVAL, "eps0 must be finite and >= 0");
   if (p->rot_precision != RBQ_ROT_FP32 && p->rot_precision != RBQ_ROT_BF16X3)

@@ -73,9 +73,9 @@ struct Unit {
 
 __device__ __forceinline__ Unit load_unit(const SearchDev& s, uint64_t e) {
   Unit w;
-  w.q = uniform_i64((int64_t)(e >> 38));
-  w.r = uniform_i32((int)((e >> 28) & 1023u));
-  w.c = uniform_i32((int)(e & ((1u << 28) - 1u)));
+  w.q = uniform_i64((int64_t)(e >> 40));
+  w.r = uniform_i32((int)((e >> 24) & 0xFFFFu));
+  w.c = uniform_i32((int)(e & 0xFFFFFFu));
   w.g = w.q * s.nprobe + w.r;
   const int list = uniform_i32(s.pairs[w.g].list);
   const int32_t* choff = s.pair_choff + w.q * (s.nprobe + 1);

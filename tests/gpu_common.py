@@ -62,6 +62,16 @@ def make_case(name: str) -> Case:
         cent, assign = synth.kmeans(data, 32, iters=4, seed=143)
         return Case(name, data, qs, cent, assign, synth.gaussian_matrix(768, 144), 10, 4,
                     R.RBQ_ROT_BF16X3, 4105)
+    if name == "many2500":
+        # many small lists and nprobe above 2048 (the large probe selection)
+        data, qs = synth.mixture_flat(12000, 12, dim=64, seed_data=151, seed_query=152)
+        rng = np.random.default_rng(153)
+        cent = data[rng.choice(len(data), 3000, replace=False)].copy()
+        x, c = data.astype(np.float64), cent.astype(np.float64)
+        d = (x * x).sum(1)[:, None] + (c * c).sum(1)[None, :] - 2.0 * (x @ c.T)
+        assign = np.argmin(d, 1).astype(np.int32)
+        return Case(name, data, qs, cent, assign, synth.gaussian_matrix(64, 154), 10, 2500,
+                    R.RBQ_ROT_FP32, 4106)
     raise KeyError(name)
 
 

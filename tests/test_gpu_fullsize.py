@@ -36,7 +36,7 @@ def test_probe_selection_many_lists_large_batch():
         idx = R.Index(64, 4096, seed=3)
         idx.build(data, cs, assign, rng.standard_normal((64, 64)))
         qt = torch.from_numpy(q).to("cuda")
-        for nprobe in (1, 7, 32, 300, 1024):
+        for nprobe in (1, 7, 32, 300, 1024, 2500, 4096):
             lists, d = R.rbq_debug_probe(idx.h, qt, nprobe)
             lists, d = lists.cpu().numpy(), d.cpu().numpy()
             for qi in range(0, 600, 37):

@@ -24,7 +24,7 @@ from gpu_common import (Built, make_case, near_integer, oracle_estimates_on, rel
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["flat128", "ivf128", "pad100", "ivf960z", "ivf768"]
+CASES = ["flat128", "ivf128", "pad100", "ivf960z", "ivf768", "many2500"]
 _BUILT = {}
 
 
@@ -54,10 +54,13 @@ def test_codes_and_factors_match_oracle(name):
     tol = np.broadcast_to(_rot_tol(c) * 4 * o.norm[:, None], diff.shape)
     assert np.all(np.abs(y[diff]) <= tol[diff]), f"{diff.sum()} sign flips, some far from zero"
     assert diff.mean() < 1e-3
-    # <o_bar,o> from the GPU's own bits and FP64 z
+    # <o_bar,o> from the GPU's own bits and FP64 z (vectors off their centroid)
+    live = o.norm > 0
     xbar = (2.0 * b.bits - 1) / np.sqrt(c.dp)
     ipo_own = (xbar * o.z).sum(1)
-    np.testing.assert_allclose(b.ipo, ipo_own, atol=50 * _rot_tol(c))
+    np.testing.assert_allclose(b.ipo[live], ipo_own[live], atol=50 * _rot_tol(c))
+    # a vector at its centroid: bits 0 and <o_bar,o> = 1 (its estimate is multiplied by a = 0)
+    assert np.all(b.bits[~live] == 0) and np.all(b.ipo[~live] == 1.0)
     np.testing.assert_allclose(b.ipo, o.ipo, atol=50 * _rot_tol(c) + 1e-6)
     print(f"{name}: code bits differing from FP64: {int(diff.sum())} of {diff.size}; "
           f"max |ipo - oracle| {np.max(np.abs(b.ipo - o.ipo)):.2e}")
