@@ -91,7 +91,21 @@ typedef struct {
                                       (falls back to `nprobe` when none is set) */
   const int32_t* nprobe_per_query; /* device, nq entries in 1..nprobe, or NULL */
   int64_t qid_base;                /* query i uses id qid_base + i in the rounding RNG */
+  int32_t use_graph;               /* 1: run the search as one replay of a captured HIP
+                                      graph (see below); 0: launch its kernels directly */
+  int32_t reserved;                /* 0 */
 } rbq_search_opts;
+
+/* Graph replay (use_graph = 1). The kernel sequence of a search is captured
+ * once per shape (batch size rounded up to at most 12.5% more rows, k,
+ * nprobe, scan kernel, learned or not, qid_base) and replayed: the queries are
+ * copied into a staging buffer of the rounded size, the graph runs, and the
+ * first nq rows of its results are copied out. Rows past nq search the staging
+ * buffer's leftover (finite) contents and are discarded. The first search of a
+ * shape runs once eagerly (allocation, warm-up) and is then captured. Results
+ * are identical to use_graph = 0. Captured graphs are dropped when the index
+ * is rebuilt, its workspace grows, or the nprobe model changes. With
+ * profiling enabled the search runs eagerly. */
 
 /* Counters of one search (filled only when a stats pointer is passed; that
  * makes rbq_search synchronise its stream before returning). */

@@ -313,16 +313,29 @@ __global__ __launch_bounds__(kThreads) void k_debug_mfma(SearchDev s, const Pair
   mfma_unit<true>(s, start, end, rows, A, masks, rowcnt, hwk, ip, pc, est, dist, lb, lbeg);
 }
 
+// Clears the per-list pair counters (a kernel rather than a memset, so that
+// the sequence can be captured in a graph).
+__global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 }  // namespace
 
 bool mfma_available() { return true; }
+
+hipError_t launch_zero_u32(void* p, int64_t nwords, hipStream_t st) {
+  if (nwords <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, st, (uint32_t*)p, nwords);
+  return hipGetLastError();
+}
 
 hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t st) {
   (void)phase;
   const int64_t np = s.nq * s.nprobe;
   const unsigned g1 = (unsigned)((np + 255) / 256);
-  hipError_t e = hipMemsetAsync(s.mf_cnt, 0, (size_t)s.nlist * 4, st);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((s.nlist + 255) / 256)), dim3(256), 0, st,
+                     (uint32_t*)s.mf_cnt, (int64_t)s.nlist);
   hipLaunchKernelGGL(k_group_count, dim3(g1), dim3(256), 0, st, s);
   hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, st, s);
   hipLaunchKernelGGL(k_group_scatter, dim3(g1), dim3(256), 0, st, s);

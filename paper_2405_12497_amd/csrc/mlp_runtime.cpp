@@ -195,6 +195,7 @@ extern "C" rbq_status rbq_nprobe_model_set(rbq_index* idx, const float* weights,
   if (!idx) return fail(RBQ_EINVAL, "index is NULL");
   if (!(threshold > 0.f && threshold <= 1.f)) return fail(RBQ_EINVAL, "threshold must be in (0, 1]");
   std::lock_guard<std::mutex> lock(idx->mu);
+  idx->graphs_clear();   // captured searches hold the policy threshold
   MlpState& m = idx->mlp;
   if (!weights) {
     m.has_model = false;
@@ -268,6 +269,7 @@ extern "C" rbq_status rbq_nprobe_model_train(rbq_index* idx, const float* feats,
   if (!is_device_ptr(feats) || !is_device_ptr(labels)) return fail(RBQ_EINVAL, "feats and labels must be device pointers");
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> lock(idx->mu);
+  idx->graphs_clear();
   MlpState& m = idx->mlp;
   std::vector<float> w;
   init_weights(cfg->seed, w);

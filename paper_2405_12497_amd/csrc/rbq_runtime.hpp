@@ -21,6 +21,21 @@ struct DBuf {
   void release();
 };
 
+// Bumped whenever any DBuf is (re)allocated or released: a captured graph
+// holds device addresses and is replayed only while this is unchanged.
+uint64_t buffer_generation();
+
+// One captured search (graph replay of rbq_search with use_graph = 1).
+struct GraphEntry {
+  int64_t nqb = 0;        // rows (rounded batch size)
+  int k = 0, nprobe = 0, kernel = 0, chunk = 0;
+  bool learned = false, per_query = false;
+  int64_t qid_base = 0;
+  uint64_t gen = 0;       // buffer_generation() at capture
+  uint64_t last_use = 0;
+  hipGraphExec_t exec = nullptr;
+};
+
 hipError_t dmalloc(void** p, size_t bytes);
 bool is_device_ptr(const void* p);
 uint64_t host_splitmix64(uint64_t x);
@@ -50,6 +65,8 @@ struct MlpState {
 
 // MFMA scan availability (kernels_mfma.hip).
 bool mfma_available();
+// Zero-fill by a kernel (no memset node when a caller captures the stream).
+hipError_t launch_zero_u32(void* p, int64_t nwords, hipStream_t st);
 hipError_t launch_pairs_to_scal(const SearchDev& s, float* scal, hipStream_t st);
 hipError_t launch_profile_accum(const SearchDev& s, unsigned long long* acc, hipStream_t st);
 
@@ -89,7 +106,12 @@ struct rbq_index {
   std::vector<rbq::DBuf*> all_buffers();
   int64_t max_codes(int nprobe) const;
   int64_t max_chunks(int nprobe, int chunk) const;
-  void graphs_clear() {}
+  // captured searches (LRU, at most kMaxGraphs) and their staging buffers
+  std::vector<rbq::GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  hipStream_t cap_stream = nullptr;
+  rbq::DBuf g_q, g_ids, g_d, g_npq;
+  void graphs_clear();
   int pick_kernel(int64_t nq, int nprobe) const {
     (void)nprobe;
     if (!rbq::mfma_available()) return RBQ_SCAN_POPCNT;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -65,9 +66,16 @@ hipError_t dmalloc(void** p, size_t bytes) {
   return hipMalloc(p, bytes);
 }
 
+namespace {
+std::atomic<uint64_t> g_buffer_gen{1};
+}
+
+uint64_t buffer_generation() { return g_buffer_gen.load(); }
+
 hipError_t DBuf::ensure(size_t bytes) {
   if (bytes <= cap) return hipSuccess;
   release();
+  g_buffer_gen.fetch_add(1);
   size_t want = std::max<size_t>(bytes, 256);
   hipError_t e = dmalloc(&p, want);
   if (e != hipSuccess) {
@@ -80,6 +88,7 @@ hipError_t DBuf::ensure(size_t bytes) {
 }
 
 void DBuf::release() {
+  if (p) g_buffer_gen.fetch_add(1);
   if (p) (void)hipFree(p);
   p = nullptr;
   cap = 0;
@@ -196,7 +205,16 @@ rbq_status check_params(const rbq_params* p) {
 }  // namespace
 
 // ------------------------------------------------------------------ index object
+void rbq_index::graphs_clear() {
+  for (rbq::GraphEntry& g : graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  graphs.clear();
+}
+
 rbq_index::~rbq_index() {
+  graphs_clear();
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  for (DBuf* b : {&g_q, &g_ids, &g_d, &g_npq}) b->release();
   prof.clear();
   prof.acc.release();
   for (DBuf* b : all_buffers()) b->release();
@@ -649,6 +667,120 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   return RBQ_OK;
 }
 
+// ------------------------------------------------------------------ graph replay
+namespace {
+constexpr size_t kMaxGraphs = 96;
+
+// Rows of the captured batch for nq queries: exact up to 16, else rounded up
+// to a multiple of 1/8 of the largest power of two <= nq (<= 12.5% extra).
+int64_t graph_rows(int64_t nq) {
+  if (nq <= 16) return nq;
+  int64_t p = 1;
+  while (p * 2 <= nq) p *= 2;
+  const int64_t step = p / 8;
+  return (nq + step - 1) / step * step;
+}
+
+__attribute__((unused)) bool same_shape(const GraphEntry& g, const GraphEntry& k) {
+  return g.nqb == k.nqb && g.k == k.k && g.nprobe == k.nprobe && g.kernel == k.kernel &&
+         g.chunk == k.chunk && g.learned == k.learned && g.per_query == k.per_query &&
+         g.qid_base == k.qid_base;
+}
+}  // namespace
+
+// rbq_search with use_graph = 1 (the caller holds idx->mu).
+rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& o,
+                        int kernel, int chunk, bool learned, int64_t* out_ids, float* out_d,
+                        hipStream_t st, const int32_t** used_npq, int* used_stride) {
+  GraphEntry key;
+  key.nqb = graph_rows(nq);
+  key.k = o.k;
+  key.nprobe = o.nprobe;
+  key.kernel = kernel;
+  key.chunk = chunk;
+  key.learned = learned;
+  key.per_query = o.nprobe_per_query != nullptr;
+  key.qid_base = o.qid_base;
+  const int64_t nqb = key.nqb;
+  // staging buffers; a fresh query buffer is zero-filled so rows past nq are finite
+  const size_t qbytes = (size_t)nqb * idx->dim * 4;
+  if (idx->g_q.cap < qbytes) {
+    HIPCHK(idx->g_q.ensure(qbytes));
+    HIPCHK(launch_zero_u32(idx->g_q.p, (int64_t)(idx->g_q.cap / 4), st));
+  }
+  HIPCHK(idx->g_ids.ensure((size_t)nqb * o.k * 8));
+  HIPCHK(idx->g_d.ensure((size_t)nqb * o.k * 4));
+  if (key.per_query && idx->g_npq.cap < (size_t)nqb * 4) {
+    HIPCHK(idx->g_npq.ensure((size_t)nqb * 4));
+    HIPCHK(launch_zero_u32(idx->g_npq.p, (int64_t)(idx->g_npq.cap / 4), st));   // clamped to 1 by the kernels
+  }
+  HIPCHK(hipMemcpyAsync(idx->g_q.p, queries, (size_t)nq * idx->dim * 4, hipMemcpyDeviceToDevice, st));
+  rbq_search_opts og = o;
+  if (key.per_query) {
+    HIPCHK(hipMemcpyAsync(idx->g_npq.p, o.nprobe_per_query, (size_t)nq * 4, hipMemcpyDeviceToDevice, st));
+    og.nprobe_per_query = (const int32_t*)idx->g_npq.p;
+  }
+  const float* gq = (const float*)idx->g_q.p;
+  int64_t* gi = (int64_t*)idx->g_ids.p;
+  float* gd = (float*)idx->g_d.p;
+  GraphEntry* ent = nullptr;
+  for (GraphEntry& g : idx->graphs)
+    if (same_shape(g, key)) ent = &g;
+  if (ent && ent->gen != buffer_generation()) {   // some buffer moved: every graph is stale
+    idx->graphs_clear();
+    ent = nullptr;
+  }
+  if (!ent) {
+    // eager run of the staged batch: allocates and sizes everything the capture replays
+    rbq_status rs = run_search(idx, gq, nqb, og, kernel, chunk, learned, gi, gd, st, used_npq, used_stride);
+    if (rs != RBQ_OK) return rs;
+    if (!idx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&idx->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint64_t gen0 = buffer_generation();
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(idx->cap_stream, hipStreamCaptureModeRelaxed));
+    const int32_t* npq_c = nullptr;
+    int stride_c = 0;
+    rs = run_search(idx, gq, nqb, og, kernel, chunk, learned, gi, gd, idx->cap_stream, &npq_c, &stride_c);
+    const hipError_t ec = hipStreamEndCapture(idx->cap_stream, &graph);
+    if (rs != RBQ_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rs;
+    }
+    if (ec != hipSuccess || !graph) return fail(RBQ_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+    if (buffer_generation() != gen0) {
+      (void)hipGraphDestroy(graph);
+      return fail(RBQ_EDEVICE, "a buffer was allocated during graph capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(RBQ_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    if (idx->graphs.size() >= kMaxGraphs) {   // evict the least recently used
+      size_t lru = 0;
+      for (size_t i = 1; i < idx->graphs.size(); ++i)
+        if (idx->graphs[i].last_use < idx->graphs[lru].last_use) lru = i;
+      (void)hipGraphExecDestroy(idx->graphs[lru].exec);
+      idx->graphs.erase(idx->graphs.begin() + (long)lru);
+    }
+    key.gen = gen0;
+    key.exec = exec;
+    idx->graphs.push_back(key);
+    ent = &idx->graphs.back();
+    *used_npq = npq_c;
+    *used_stride = stride_c;
+  } else {
+    // the pointers a replay uses are the ones captured: workspace and staging
+    *used_stride = learned ? std::max(o.nprobe, std::min(kMlpNear, idx->nlist)) : o.nprobe;
+    *used_npq = learned ? (const int32_t*)idx->ws.nprobe_q.p : og.nprobe_per_query;
+  }
+  ent->last_use = ++idx->graph_clock;
+  HIPCHK(hipGraphLaunch(ent->exec, st));
+  HIPCHK(hipMemcpyAsync(out_ids, gi, (size_t)nq * o.k * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(out_d, gd, (size_t)nq * o.k * 4, hipMemcpyDeviceToDevice, st));
+  return RBQ_OK;
+}
+
 }  // namespace rbq
 
 extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t nq,
@@ -660,6 +792,7 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
   if (o.k < 1 || o.k > kMaxK) return fail(RBQ_EINVAL, "k=%d outside [1, %d]", o.k, kMaxK);
   if (o.nprobe < 1 || o.nprobe > std::min(idx->nlist, kMaxNprobe))
     return fail(RBQ_EINVAL, "nprobe=%d outside [1, %d]", o.nprobe, std::min(idx->nlist, kMaxNprobe));
+  if (o.use_graph != 0 && o.use_graph != 1) return fail(RBQ_EINVAL, "use_graph must be 0 or 1");
   if (o.scan_kernel < RBQ_SCAN_AUTO || o.scan_kernel > RBQ_SCAN_MFMA)
     return fail(RBQ_EINVAL, "unknown scan_kernel %d", o.scan_kernel);
   if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
@@ -684,7 +817,11 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
   const bool learned = !o.nprobe_per_query && o.use_learned_nprobe && idx->mlp.has_model;
   const int32_t* npq = nullptr;
   int stride = o.nprobe;
-  rbq_status rs = run_search(idx, queries, nq, o, kernel, chunk, learned, out_ids, out_dists, st, &npq, &stride);
+  rbq_status rs = (o.use_graph && !idx->prof.on)
+                      ? rbq::search_graph(idx, queries, nq, o, kernel, chunk, learned, out_ids, out_dists, st,
+                                          &npq, &stride)
+                      : run_search(idx, queries, nq, o, kernel, chunk, learned, out_ids, out_dists, st, &npq,
+                                   &stride);
   if (rs != RBQ_OK) return rs;
   if (!idx->done_event) HIPCHK(hipEventCreateWithFlags(&idx->done_event, hipEventDisableTiming));
   HIPCHK(hipEventRecord(idx->done_event, st));

@@ -55,7 +55,7 @@ def test_create_rejects_bad_params(field, value, status):
 
 def test_calls_on_unbuilt_index_fail_with_estate():
     h = R.rbq_index_create(R.rbq_params_default(64, 4))
-    o = R.RbqSearchOpts(10, 1, 0, 0, None, 0)
+    o = R.RbqSearchOpts(10, 1, 0, 0, None, 0, 0, 0)
     st = R.lib().rbq_search(h, None, 1, o, None, None, None, None)
     assert st == R.RBQ_ESTATE
     assert R.lib().rbq_index_save(h, b"/tmp/never.rbq") == R.RBQ_ESTATE

@@ -116,7 +116,7 @@ def test_argument_errors():
             idx.search(q, k, nprobe)
         assert e.value.status == R.RBQ_EINVAL
     # host pointer where a device pointer is required
-    o = R.RbqSearchOpts(5, 1, 0, 0, None, 0)
+    o = R.RbqSearchOpts(5, 1, 0, 0, None, 0, 0, 0)
     out_i = torch.empty((2, 5), dtype=torch.int64, device=_dev())
     out_d = torch.empty((2, 5), dtype=torch.float32, device=_dev())
     host_q = np.ascontiguousarray(data[:2])
