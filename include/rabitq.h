@@ -121,6 +121,8 @@ typedef struct {
   int32_t dim, code_bits, nlist, rot_precision;
   int64_t n;                  /* vectors indexed */
   int64_t device_bytes;       /* device memory held by the index (excl. workspace) */
+  int64_t graph_captures;     /* searches captured as graphs so far (use_graph = 1) */
+  int64_t graphs_cached;      /* captured graphs currently held */
 } rbq_index_info;
 
 /* Fills defaults: code_bits 0, bq 4, eps0 1.9, FP32 rotation, seed 0. */
@@ -138,6 +140,8 @@ rbq_status rbq_index_create(const rbq_params* p, rbq_index** out);
  *             NULL to draw it from params.seed. P is obtained by
  *             orthonormalising its rows (Gram-Schmidt, Appendix B), so P is
  *             Haar distributed. Codes are sign(P^T (o_r - c)) (Sec. 3.1.3).
+ * n is below 2^31 - 64, and 64*ceil(n/64) * code_bits/64 below 2^32 (32-bit
+ * word offsets in the scan).
  * Rebuilding an index replaces its contents. */
 rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t n,
                            const float* centroids, const int32_t* assign,

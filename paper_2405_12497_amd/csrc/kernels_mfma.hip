@@ -324,6 +324,21 @@ __global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
 
 bool mfma_available() { return true; }
 
+int scan_mfma_blocks_per_cu(int dp) {
+  static int nb = 0, for_dp = -1;
+  if (for_dp != dp) {
+    int v = 0;
+    (void)hipFuncSetAttribute((const void*)k_scan_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, (const void*)k_scan_mfma, kThreads, (size_t)16 * dp) !=
+            hipSuccess ||
+        v < 1)
+      v = 1;
+    nb = v;
+    for_dp = dp;
+  }
+  return nb;
+}
+
 hipError_t launch_zero_u32(void* p, int64_t nwords, hipStream_t st) {
   if (nwords <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, st, (uint32_t*)p, nwords);

@@ -293,27 +293,38 @@ __global__ __launch_bounds__(1024) void k_offsets(SearchDev s) {
     for (int a = 0; a < 5; ++a) outs[a][s.nq] = run[a];
 }
 
-// Work-unit tables: entry = (query << 40) | (probe rank << 24) | chunk, with
-// query < 2^24 (the rounding-key layout), rank < 2^16, chunk < 2^24.
-__device__ __forceinline__ uint64_t pack_unit(int64_t q, int r, int c) {
-  return ((uint64_t)q << 40) | ((uint64_t)r << 24) | (uint64_t)c;
-}
-
-// One wave per query, a lane per probe rank: its chunks, bootstrap ones to
-// units0 (at off_p0[q]) and the others to units1 (at off_p1[q]).
+// One wave per query, a lane per probe rank: the descriptors of its chunks,
+// bootstrap ones to units0 (at off_p0[q]) and the others to units1 (at
+// off_p1[q]).
 __global__ __launch_bounds__(kThreads) void k_units(SearchDev s) {
   const int64_t q = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (q >= s.nq) return;
   const int lane = lane_id();
   const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
+  const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
   const int p0 = s.q_p0[q];
   const int64_t b0 = s.off_p0[q], b1 = s.off_p1[q];
+  const int64_t seg0 = s.off_seg[q], n00 = s.off_n0[q], ch0 = s.off_ch[q];
   for (int r = lane; r < s.nprobe; r += kWave) {
     const int c0 = choff[r], nc = choff[r + 1] - c0;
+    if (nc == 0) continue;
+    const int64_t g = q * s.nprobe + r;
+    const int list = s.pairs[g].list;
+    const int64_t lbeg = s.list_off[list];
+    const int n = s.list_off[list + 1] - s.list_off[list];
     for (int c = 0; c < nc; ++c) {
       const int j = c0 + c;
-      const uint64_t e = pack_unit(q, r, c);
-      if (j < p0) s.units0[b0 + j] = e; else s.units1[b1 + (j - p0)] = e;
+      UnitDesc d;
+      d.start = lbeg + (int64_t)c * s.chunk;
+      d.len = min(s.chunk, n - c * s.chunk);
+      d.g = g;
+      d.qcode = (int64_t)codeoff[r] + (int64_t)c * s.chunk;
+      d.seg = seg0 + d.qcode;
+      d.p0slot = n00 + d.qcode;
+      d.count_slot = ch0 + j;
+      d.q = (int32_t)q;
+      d.pad = 0;
+      if (j < p0) s.units0[b0 + j] = d; else s.units1[b1 + (j - p0)] = d;
     }
   }
 }
@@ -617,8 +628,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
   const int nch = uniform_i32(s.q_nch[q]);
   const int p0 = uniform_i32(s.q_p0[q]);
   const int64_t off0 = uniform_i64(s.off_p0[q]), off1 = uniform_i64(s.off_p1[q]);
-  const int64_t seg0 = uniform_i64(s.off_seg[q]), ch0 = uniform_i64(s.off_ch[q]);
-  const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
+  const int64_t ch0 = uniform_i64(s.off_ch[q]);
   for (int j0 = 0; j0 < nch; j0 += kFinChunks) {
     const int nj = min(kFinChunks, nch - j0);
     // chunk bases and counts of this chunk window, then an exclusive prefix of the counts
@@ -626,9 +636,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
     int run = 0;
     for (int t = threadIdx.x * per; t < min(nj, (int)(threadIdx.x + 1) * per); ++t) {
       const int j = j0 + t;
-      const uint64_t e = j < p0 ? s.units0[off0 + j] : s.units1[off1 + (j - p0)];
-      const int r = (int)((e >> 24) & 0xFFFFu), c = (int)(e & 0xFFFFFFu);
-      cbase[t] = seg0 + codeoff[r] + (int64_t)c * s.chunk;
+      cbase[t] = j < p0 ? s.units0[off0 + j].seg : s.units1[off1 + (j - p0)].seg;
       cpre[t] = run;
       run += s.seg_count[ch0 + j];
     }
@@ -831,19 +839,19 @@ __global__ __launch_bounds__(kThreads) void k_debug_scan(SearchDev s, const Pair
   const PairRec rec = *recp;
   for (int i = threadIdx.x; i < 4 * s.W; i += blockDim.x) lds_planes[i] = planes[i];
   __syncthreads();
-  Planes<WS> pl;
-  if constexpr (WS > 0) {
-    pl.load(planes, s.W);
+  PlanesFor<WS> pl;
+  if constexpr (WS >= 1 && WS <= 4) {
+    pl.load(planes);
   } else {
     pl.p = lds_planes;
-    pl.W = s.W;
+    pl.Wr = s.W;
   }
   const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
   const int64_t p = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= end) return;
   int ip, pc;
   float est, dist, lb;
-  code_ip<WS>(s.codes, p, s.W, pl, ip, pc);
+  code_ip<WS>(code_row(s.codes, (int32_t)p, s.W), s.W, pl, ip, pc);
   estimate(rec, s.fac[p], ip, pc, hwk, est, dist, lb);
   const int64_t o = p - beg;
   ip_o[o] = ip;

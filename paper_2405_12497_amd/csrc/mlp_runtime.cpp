@@ -131,6 +131,11 @@ rbq_status features_into(rbq_index* idx, const float* queries, int64_t nq, int64
   return RBQ_OK;
 }
 
+rbq_status mlp_reserve(rbq_index* idx, int64_t rows) {
+  HIPCHK(idx->mlp.act.ensure(pass_floats(rows) * 4));
+  return RBQ_OK;
+}
+
 rbq_status predict_into(rbq_index* idx, const float* feats, int64_t nq, int nprobe_max,
                         int32_t* nprobe, float* logits, hipStream_t st) {
   MlpState& m = idx->mlp;

@@ -53,6 +53,20 @@ struct SeedEnt {
   int32_t pos;
 };
 
+// One work unit of a scan phase: at most `chunk` consecutive codes of one
+// probed (query, list) pair, with every offset the scan needs precomputed.
+struct __attribute__((aligned(16))) UnitDesc {
+  int64_t start;       // first code position (list order)
+  int64_t g;           // pair index q * nprobe + rank
+  int64_t seg;         // candidate-segment slot of the first code
+  int64_t qcode;       // the first code's index in the query's probed-code space
+  int64_t p0slot;      // bootstrap-buffer slot of the first code
+  int64_t count_slot;  // seg_count entry of the unit
+  int32_t len;         // codes
+  int32_t q;           // query
+  int64_t pad;
+};
+
 // ------------------------------------------------------------------ device helpers
 #if defined(__HIPCC__)
 
@@ -244,8 +258,8 @@ struct SearchDev {
   int64_t* off_seg;         // nq+1 prefix of q_ncode
   int64_t* off_n0;          // nq+1 prefix of q_n0
   unsigned long long* counters;  // work counters: [2] MFMA scan
-  uint64_t* units0;         // bootstrap work units (query, rank, chunk)
-  uint64_t* units1;         // main-phase work units
+  UnitDesc* units0;         // bootstrap work units
+  UnitDesc* units1;         // main-phase work units
   // buffers
   Cand* seg;                // segment slots
   int32_t* seg_count;       // per chunk
@@ -267,6 +281,8 @@ struct SearchDev {
 
 hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st);
 hipError_t launch_plan(const SearchDev& s, hipStream_t st);
+int scan_popcnt_blocks_per_cu(int W);
+int scan_mfma_blocks_per_cu(int dp);
 hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st);
 hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t st);
 hipError_t launch_tau(const SearchDev& s, hipStream_t st);

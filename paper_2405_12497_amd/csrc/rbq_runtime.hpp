@@ -109,6 +109,9 @@ struct rbq_index {
   // captured searches (LRU, at most kMaxGraphs) and their staging buffers
   std::vector<rbq::GraphEntry> graphs;
   uint64_t graph_clock = 0;
+  int64_t graph_rows_hint = 0;   // rows the graph-mode workspace is sized for
+  int64_t graph_mem_cap = 0;     // bytes of candidate segments graph mode may reserve
+  int64_t graph_captures = 0;
   hipStream_t cap_stream = nullptr;
   rbq::DBuf g_q, g_ids, g_d, g_npq;
   void graphs_clear();
@@ -122,6 +125,8 @@ struct rbq_index {
 namespace rbq {
 rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int nprobe_max, int stride,
                           int64_t qid_base, hipStream_t st, const int32_t** out);
+// Reserves the MLP activation buffers for `rows` queries.
+rbq_status mlp_reserve(rbq_index* idx, int64_t rows);
 rbq_status rotate_rows(rbq_index* idx, const float* X, int64_t lda, const float* sub,
                        const int32_t* sel, int64_t M, float* Y, hipStream_t st);
 rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma);

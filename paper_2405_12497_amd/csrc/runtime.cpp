@@ -290,6 +290,8 @@ rbq_status rbq_index_info_get(const rbq_index* idx, rbq_index_info* out) {
   out->rot_precision = idx->prm.rot_precision;
   out->n = idx->n;
   out->device_bytes = idx->device_bytes;
+  out->graph_captures = idx->graph_captures;
+  out->graphs_cached = (int64_t)idx->graphs.size();
   return RBQ_OK;
 }
 
@@ -401,6 +403,8 @@ extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t
       (gauss && is_device_ptr(gauss)))
     return fail(RBQ_EINVAL, "rbq_index_build takes host pointers");
   if (n < 1 || n > (int64_t)INT32_MAX - 64) return fail(RBQ_EINVAL, "n=%lld out of range", (long long)n);
+  if ((uint64_t)((n + 63) / 64 * 64) * (uint64_t)idx->W >= (1ull << 32))
+    return fail(RBQ_EINVAL, "n=%lld codes of %d words exceed 2^32 words", (long long)n, idx->W);
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> lock(idx->mu);
   const int D = idx->dim, dp = idx->dp, L = idx->nlist, W = idx->W;
@@ -518,8 +522,8 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.counters.ensure(64));
   HIPCHK(w.seg.ensure((size_t)nq * std::max<int64_t>(1, idx->max_codes(nprobe)) * sizeof(Cand)));
   HIPCHK(w.seg_count.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
-  HIPCHK(w.units0.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 8));
-  HIPCHK(w.units1.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 8));
+  HIPCHK(w.units0.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * sizeof(UnitDesc)));
+  HIPCHK(w.units1.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * sizeof(UnitDesc)));
   HIPCHK(w.p0buf.ensure((size_t)nq * (boot_codes(k, chunk) - 1 + chunk) * sizeof(EstEnt)));
   HIPCHK(w.tau.ensure((size_t)nq * 4));
   HIPCHK(w.seedk.ensure((size_t)nq * k * sizeof(SeedEnt)));
@@ -586,8 +590,8 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.mf_pair_off = (int64_t*)w.mf_pair_off.p;
   s.mf_unit_off = (int64_t*)w.mf_unit_off.p;
   s.mf_pairs = (int32_t*)w.mf_pairs.p;
-  s.units0 = (uint64_t*)w.units0.p;
-  s.units1 = (uint64_t*)w.units1.p;
+  s.units0 = (UnitDesc*)w.units0.p;
+  s.units1 = (UnitDesc*)w.units1.p;
   s.out_ids = out_ids;
   s.out_d = out_d;
   return s;
@@ -606,9 +610,11 @@ rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   return RBQ_OK;
 }
 
-int scan_grid(rbq_index* idx, int64_t nq, int nprobe, int chunk) {
-  const int64_t ub = std::max<int64_t>(1, nq * idx->max_chunks(nprobe, chunk));
-  const int64_t g = std::min<int64_t>((int64_t)device_cu_count() * 8, (ub + 3) / 4);
+// Persistent scan grid: the blocks that fit on the device at once (per the
+// kernel's occupancy), or fewer when there are fewer units than waves.
+int scan_grid(rbq_index* idx, int64_t nq, int64_t units_per_query, int blocks_per_cu) {
+  const int64_t ub = std::max<int64_t>(1, nq * units_per_query);
+  const int64_t g = std::min<int64_t>((int64_t)device_cu_count() * blocks_per_cu, (ub + 3) / 4);
   return (int)std::max<int64_t>(1, g);
 }
 
@@ -646,14 +652,18 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   if (pf.on) HIPCHK(hipEventRecord(ev[1], st));
   HIPCHK(launch_prep_pairs(s, st));
   HIPCHK(launch_plan(s, st));
-  const int grid = scan_grid(idx, nq, o.nprobe, chunk);
+  const int64_t chunks = idx->max_chunks(o.nprobe, chunk);
+  const int bpc = scan_popcnt_blocks_per_cu(idx->W);
+  // bootstrap chunks per query: whole chunks until >= boot codes, so at most boot of them
+  const int grid0 = scan_grid(idx, nq, std::min<int64_t>(chunks, s.boot), bpc);
+  const int grid = scan_grid(idx, nq, chunks, bpc);
   if (pf.on) HIPCHK(hipEventRecord(ev[2], st));
-  HIPCHK(launch_scan_popcnt(s, 0, grid, st));
+  HIPCHK(launch_scan_popcnt(s, 0, grid0, st));
   if (pf.on) HIPCHK(hipEventRecord(ev[3], st));
   HIPCHK(launch_tau(s, st));
   if (pf.on) HIPCHK(hipEventRecord(ev[4], st));
   if (mfma) {
-    HIPCHK(launch_scan_mfma(s, 1, grid, st));
+    HIPCHK(launch_scan_mfma(s, 1, scan_grid(idx, nq, chunks, scan_mfma_blocks_per_cu(idx->dp)), st));
   } else {
     HIPCHK(launch_scan_popcnt(s, 1, grid, st));
   }
@@ -702,16 +712,45 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
   key.per_query = o.nprobe_per_query != nullptr;
   key.qid_base = o.qid_base;
   const int64_t nqb = key.nqb;
+  // Graph mode sizes the workspace and staging for a row count that grows by
+  // powers of two (at least 1024), so that batches of varying size do not
+  // reallocate buffers (and invalidate every captured graph) one after another.
+  if (idx->graph_rows_hint < nqb) {
+    int64_t h = std::max<int64_t>(1024, idx->graph_rows_hint);
+    while (h < nqb) h *= 2;
+    idx->graph_rows_hint = h;
+  }
+  const int stride = learned ? std::max(o.nprobe, std::min(kMlpNear, idx->nlist)) : o.nprobe;
+  int64_t hint = idx->graph_rows_hint;
+  // ... as long as the candidate segments stay below a quarter of the device
+  // memory that was free when graph mode was first used
+  if (idx->graph_mem_cap == 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    idx->graph_mem_cap = std::max<int64_t>(1ll << 30, (int64_t)(fr / 4));
+  }
+  const int64_t seg_row = std::max<int64_t>(1, idx->max_codes(stride)) * (int64_t)sizeof(Cand);
+  while (hint > nqb && hint * seg_row > idx->graph_mem_cap) hint = std::max(nqb, hint / 2);
+  {
+    rbq_status rs = ensure_workspace(idx, hint, stride, o.k, chunk, kernel == RBQ_SCAN_MFMA);
+    if (rs != RBQ_OK) return rs;
+    if (learned) {
+      HIPCHK(idx->ws.feats.ensure((size_t)hint * kMlpIn * 4));
+      HIPCHK(idx->ws.nprobe_q.ensure((size_t)hint * 4));
+      rs = mlp_reserve(idx, hint);
+      if (rs != RBQ_OK) return rs;
+    }
+  }
   // staging buffers; a fresh query buffer is zero-filled so rows past nq are finite
-  const size_t qbytes = (size_t)nqb * idx->dim * 4;
+  const size_t qbytes = (size_t)hint * idx->dim * 4;
   if (idx->g_q.cap < qbytes) {
     HIPCHK(idx->g_q.ensure(qbytes));
     HIPCHK(launch_zero_u32(idx->g_q.p, (int64_t)(idx->g_q.cap / 4), st));
   }
-  HIPCHK(idx->g_ids.ensure((size_t)nqb * o.k * 8));
-  HIPCHK(idx->g_d.ensure((size_t)nqb * o.k * 4));
-  if (key.per_query && idx->g_npq.cap < (size_t)nqb * 4) {
-    HIPCHK(idx->g_npq.ensure((size_t)nqb * 4));
+  HIPCHK(idx->g_ids.ensure((size_t)hint * kMaxK * 8));
+  HIPCHK(idx->g_d.ensure((size_t)hint * kMaxK * 4));
+  if (key.per_query && idx->g_npq.cap < (size_t)hint * 4) {
+    HIPCHK(idx->g_npq.ensure((size_t)hint * 4));
     HIPCHK(launch_zero_u32(idx->g_npq.p, (int64_t)(idx->g_npq.cap / 4), st));   // clamped to 1 by the kernels
   }
   HIPCHK(hipMemcpyAsync(idx->g_q.p, queries, (size_t)nq * idx->dim * 4, hipMemcpyDeviceToDevice, st));
@@ -724,11 +763,15 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
   int64_t* gi = (int64_t*)idx->g_ids.p;
   float* gd = (float*)idx->g_d.p;
   GraphEntry* ent = nullptr;
-  for (GraphEntry& g : idx->graphs)
-    if (same_shape(g, key)) ent = &g;
-  if (ent && ent->gen != buffer_generation()) {   // some buffer moved: every graph is stale
-    idx->graphs_clear();
-    ent = nullptr;
+  for (size_t i = 0; i < idx->graphs.size(); ++i) {
+    if (!same_shape(idx->graphs[i], key)) continue;
+    if (idx->graphs[i].gen == buffer_generation()) {
+      ent = &idx->graphs[i];
+    } else {   // captured before some buffer moved: recapture
+      (void)hipGraphExecDestroy(idx->graphs[i].exec);
+      idx->graphs.erase(idx->graphs.begin() + (long)i);
+    }
+    break;
   }
   if (!ent) {
     // eager run of the staged batch: allocates and sizes everything the capture replays
@@ -765,6 +808,7 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
     }
     key.gen = gen0;
     key.exec = exec;
+    ++idx->graph_captures;
     idx->graphs.push_back(key);
     ent = &idx->graphs.back();
     *used_npq = npq_c;

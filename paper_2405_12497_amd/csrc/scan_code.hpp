@@ -3,18 +3,20 @@
 #ifndef RBQ_SCAN_CODE_HPP
 #define RBQ_SCAN_CODE_HPP
 
+#include <type_traits>
+
 #include "rbq_internal.hpp"
 
 namespace rbq {
 namespace {
 
 // ------------------------------------------------------------------ scan arithmetic (S4 + S6)
-// Integer <x_b, q_u> = sum_j 2^j popcount(x_b AND plane_j) and popcount(x_b)
-// for the code at position p. WS > 0: planes held in registers (W == WS).
+// Integer <x_b, q_u> = sum_j 2^j popcount(x_b AND plane_j) and popcount(x_b).
+// Planes<WS>: the pair's 4 bit planes in registers (1 <= WS <= 4 words, W == WS).
 template <int WS>
 struct Planes {
   uint64_t w[4][WS];
-  __device__ __forceinline__ void load(const uint64_t* src, int) {
+  __device__ __forceinline__ void load(const uint64_t* src) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -22,21 +24,32 @@ struct Planes {
   }
   __device__ __forceinline__ uint64_t get(int j, int t) const { return w[j][t]; }
 };
-template <>
-struct Planes<0> {
-  const uint64_t* p;   // LDS copy, [4][W]
-  int W;
-  __device__ __forceinline__ uint64_t get(int j, int t) const { return p[j * W + t]; }
-};
-
+// PlanesLds<WS>: the planes in LDS ([4][W]), W == WS > 4 known at compile
+// time, or runtime W when WS == 0.
 template <int WS>
-__device__ __forceinline__ void code_ip(const uint64_t* __restrict__ codes, int64_t p, int W,
-                                        const Planes<WS>& pl, int& ip, int& pc) {
+struct PlanesLds {
+  const uint64_t* p;
+  int Wr;
+  __device__ __forceinline__ uint64_t get(int j, int t) const { return p[j * (WS > 0 ? WS : Wr) + t]; }
+};
+template <int WS>
+using PlanesFor = typename std::conditional<(WS >= 1 && WS <= 4), Planes<WS>, PlanesLds<WS>>::type;
+
+// Word 0 of the code at list-order position p; word t is row[64 * t]
+// (interleaved layout: word w of 64 consecutive codes is one 512-byte row).
+// Word offsets are 32-bit: the index keeps npad * W below 2^32.
+__device__ __forceinline__ const uint64_t* code_row(const uint64_t* __restrict__ codes, int32_t p, int W) {
+  return codes + ((uint32_t)(p >> 6) * (uint32_t)(W * 64) + (uint32_t)(p & 63));
+}
+
+template <int WS, typename PL>
+__device__ __forceinline__ void code_ip(const uint64_t* __restrict__ row, int W, const PL& pl, int& ip,
+                                        int& pc) {
   const int Wn = WS > 0 ? WS : W;
   int s0 = 0, s1 = 0, s2 = 0, s3 = 0, c = 0;
 #pragma unroll
   for (int t = 0; t < Wn; ++t) {
-    const uint64_t x = codes[code_word_index(p, t, W)];
+    const uint64_t x = row[64 * t];
     c += __popcll(x);
     s0 += __popcll(x & pl.get(0, t));
     s1 += __popcll(x & pl.get(1, t));
@@ -62,29 +75,19 @@ __device__ __forceinline__ void estimate(const PairRec& r, float2 f, int ip, int
   lb = fmaf(-ab2, hw, dist);
 }
 
-struct Unit {
-  int64_t q;
-  int r, c;
-  int64_t g;            // pair index
-  int64_t start, end;   // code positions
-  int64_t codeoff;      // query code-space offset of the chunk start
-  int64_t count_slot;   // seg_count index
-};
-
-__device__ __forceinline__ Unit load_unit(const SearchDev& s, uint64_t e) {
-  Unit w;
-  w.q = uniform_i64((int64_t)(e >> 40));
-  w.r = uniform_i32((int)((e >> 24) & 0xFFFFu));
-  w.c = uniform_i32((int)(e & 0xFFFFFFu));
-  w.g = w.q * s.nprobe + w.r;
-  const int list = uniform_i32(s.pairs[w.g].list);
-  const int32_t* choff = s.pair_choff + w.q * (s.nprobe + 1);
-  const int32_t* codeoff = s.pair_codeoff + w.q * (s.nprobe + 1);
-  const int64_t lbeg = uniform_i64(s.list_off[list]), lend = uniform_i64(s.list_off[list + 1]);
-  w.start = lbeg + (int64_t)w.c * s.chunk;
-  w.end = lend < w.start + s.chunk ? lend : w.start + s.chunk;
-  w.codeoff = uniform_i64((int64_t)codeoff[w.r] + (int64_t)w.c * s.chunk);
-  w.count_slot = uniform_i64(s.off_ch[w.q] + choff[w.r] + w.c);
+// A unit descriptor read with a wave-uniform address, made wave-uniform.
+__device__ __forceinline__ UnitDesc load_unit(const UnitDesc* __restrict__ tab, int64_t u) {
+  const UnitDesc d = tab[u];
+  UnitDesc w;
+  w.start = uniform_i64(d.start);
+  w.g = uniform_i64(d.g);
+  w.seg = uniform_i64(d.seg);
+  w.qcode = uniform_i64(d.qcode);
+  w.p0slot = uniform_i64(d.p0slot);
+  w.count_slot = uniform_i64(d.count_slot);
+  w.len = uniform_i32(d.len);
+  w.q = uniform_i32(d.q);
+  w.pad = 0;
   return w;
 }
 

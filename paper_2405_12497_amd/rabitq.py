@@ -16,6 +16,7 @@ RBQ_OK, RBQ_EINVAL, RBQ_ENOMEM, RBQ_EDEVICE, RBQ_ESTATE, RBQ_EFORMAT, RBQ_EUNSUP
 RBQ_ROT_FP32, RBQ_ROT_BF16X3 = 0, 1
 RBQ_SCAN_AUTO, RBQ_SCAN_POPCNT, RBQ_SCAN_MFMA = 0, 1, 2
 MLP_IN, MLP_HIDDEN, MLP_OUT = 96, 128, 32
+MAX_K, MAX_NPROBE, MAX_NLIST = 256, 16384, 24576
 MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
 
 
@@ -41,7 +42,8 @@ class RbqSearchStats(C.Structure):
 
 class RbqIndexInfo(C.Structure):
     _fields_ = [("dim", C.c_int32), ("code_bits", C.c_int32), ("nlist", C.c_int32),
-                ("rot_precision", C.c_int32), ("n", C.c_int64), ("device_bytes", C.c_int64)]
+                ("rot_precision", C.c_int32), ("n", C.c_int64), ("device_bytes", C.c_int64),
+                ("graph_captures", C.c_int64), ("graphs_cached", C.c_int64)]
 
 
 class RbqProfile(C.Structure):

@@ -25,7 +25,9 @@ __all__ = [
     "sift_like",
     "gist_like",
     "embedding_like",
+    "embedding_like_gpu",
     "kmeans",
+    "kmeans_gpu",
     "workload",
     "query_batch_sizes",
 ]
@@ -137,6 +139,68 @@ def embedding_like(n: int, nq: int, dim: int = 768, seed_data: int = 1004,
     data = draw(rng, n)
     queries = draw(np.random.default_rng(seed_query), nq)
     return data, queries
+
+
+def embedding_like_gpu(n: int, nq: int, device, dim: int = 768, seed_data: int = 1004,
+                       seed_query: int = 2004, exponent: float = 1.0, chunk: int = 1 << 18):
+    """The distribution of `embedding_like` drawn on the GPU (for tens of
+    millions of vectors): the same seeded basis, Gaussian coefficients from a
+    seeded torch generator on `device`. Returns float32 tensors on `device`.
+    (Not the same numbers as `embedding_like` for equal seeds.)"""
+    import torch
+    rng = np.random.default_rng(seed_data)
+    lam = np.arange(1, dim + 1, dtype=np.float64) ** (-exponent)
+    qm, r = np.linalg.qr(rng.standard_normal((dim, dim)))
+    u = qm * np.sign(np.diag(r))
+    basis = torch.from_numpy((u * np.sqrt(lam)[None, :]).T.astype(np.float32)).to(device)
+
+    def draw(seed, m):
+        g = torch.Generator(device=device)
+        g.manual_seed(seed)
+        out = torch.empty((m, dim), dtype=torch.float32, device=device)
+        for s in range(0, m, chunk):
+            e = min(m, s + chunk)
+            z = torch.randn((e - s, dim), generator=g, device=device, dtype=torch.float32)
+            x = z @ basis
+            out[s:e] = x / torch.linalg.vector_norm(x, dim=1, keepdim=True)
+        return out
+
+    return draw(seed_data, n), draw(seed_query, nq)
+
+
+def kmeans_gpu(x, nlist: int, iters: int = 10, seed: int = 7, sample: int | None = None,
+               chunk: int = 8192):
+    """Lloyd k-means of a float32 GPU tensor x [n, dim]: seeded init from a
+    seeded sample of `sample` rows (all rows when None), `iters` rounds of
+    FP64 nearest-centroid assignment + mean update on the sample, then a final
+    FP64 assignment of every row. Empty clusters keep their centroid.
+    Returns (centroids float32 numpy, assign int32 numpy)."""
+    import torch
+    n, dim = x.shape
+    rng = np.random.default_rng(seed)
+    xs = x
+    if sample is not None and sample < n:
+        xs = x[torch.from_numpy(np.sort(rng.choice(n, size=sample, replace=False))).to(x.device)]
+    cent = xs[torch.from_numpy(rng.choice(xs.shape[0], size=nlist, replace=False)).to(x.device)].double()
+
+    def assign(rows):
+        cn = (cent * cent).sum(1)
+        lab = torch.empty(rows.shape[0], dtype=torch.int64, device=x.device)
+        for s0 in range(0, rows.shape[0], chunk):
+            d = cn[None, :] - 2.0 * (rows[s0:s0 + chunk].double() @ cent.T)
+            lab[s0:s0 + chunk] = torch.argmin(d, dim=1)
+        return lab
+
+    for _ in range(iters):
+        lab = assign(xs)
+        sums = torch.zeros((nlist, dim), dtype=torch.float64, device=x.device)
+        for s0 in range(0, xs.shape[0], 1 << 16):
+            sums.index_add_(0, lab[s0:s0 + (1 << 16)], xs[s0:s0 + (1 << 16)].double())
+        cnt = torch.bincount(lab, minlength=nlist).double()
+        nz = cnt > 0
+        cent[nz] = sums[nz] / cnt[nz, None]
+    lab = assign(x)
+    return cent.float().cpu().numpy(), lab.to(torch.int32).cpu().numpy()
 
 
 def query_batch_sizes(total: int, seed: int = 2104, lo: int = 1, hi: int = 1024):

@@ -48,6 +48,8 @@ def test_graph_replays_match_eager(kernel):
     batches = {n: _batch(b, n, 100 + n) for n in sizes}
     eager = {n: b.idx.search(batches[n], 10, 8, scan_kernel=kern, stats=True) for n in sizes}
     for rep in range(3):
+        if rep == 1:
+            captured = b.idx.info()["graph_captures"]
         for n in sizes:
             g = b.idx.search(batches[n], 10, 8, scan_kernel=kern, stats=True, use_graph=True)
             _same(eager[n], g)
@@ -56,6 +58,8 @@ def test_graph_replays_match_eager(kernel):
             e2 = b.idx.search(batches[other], 10, 8, scan_kernel=kern, stats=True)
             _same(eager[other], e2)
             torch.cuda.synchronize()
+    # later rounds replay: no shape is captured again
+    assert b.idx.info()["graph_captures"] == captured
 
 
 def test_graph_with_per_query_nprobe_and_qid_base():
