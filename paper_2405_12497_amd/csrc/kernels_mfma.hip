@@ -320,6 +320,11 @@ __global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
   if (i < n) p[i] = 0u;
 }
 
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 }  // namespace
 
 bool mfma_available() { return true; }
@@ -337,6 +342,12 @@ int scan_mfma_blocks_per_cu(int dp) {
     for_dp = dp;
   }
   return nb;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_u32(void* p, int64_t nwords, hipStream_t st) {

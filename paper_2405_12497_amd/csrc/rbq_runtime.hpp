@@ -67,6 +67,7 @@ struct MlpState {
 bool mfma_available();
 // Zero-fill by a kernel (no memset node when a caller captures the stream).
 hipError_t launch_zero_u32(void* p, int64_t nwords, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_pairs_to_scal(const SearchDev& s, float* scal, hipStream_t st);
 hipError_t launch_profile_accum(const SearchDev& s, unsigned long long* acc, hipStream_t st);
 

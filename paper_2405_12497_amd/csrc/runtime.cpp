@@ -709,7 +709,7 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
   key.kernel = kernel;
   key.chunk = chunk;
   key.learned = learned;
-  key.per_query = o.nprobe_per_query != nullptr;
+  key.per_query = !learned;   // non-learned graphs always read a staged per-query nprobe
   key.qid_base = o.qid_base;
   const int64_t nqb = key.nqb;
   // Graph mode sizes the workspace and staging for a row count that grows by
@@ -749,15 +749,24 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
   }
   HIPCHK(idx->g_ids.ensure((size_t)hint * kMaxK * 8));
   HIPCHK(idx->g_d.ensure((size_t)hint * kMaxK * 4));
-  if (key.per_query && idx->g_npq.cap < (size_t)hint * 4) {
-    HIPCHK(idx->g_npq.ensure((size_t)hint * 4));
-    HIPCHK(launch_zero_u32(idx->g_npq.p, (int64_t)(idx->g_npq.cap / 4), st));   // clamped to 1 by the kernels
-  }
-  HIPCHK(hipMemcpyAsync(idx->g_q.p, queries, (size_t)nq * idx->dim * 4, hipMemcpyDeviceToDevice, st));
+  HIPCHK(idx->g_npq.ensure((size_t)hint * 4));
+  // Padding rows [nq, nqb) repeat real queries (a zero vector would tie every
+  // distance and rerank whole lists); without a model they probe one list.
+  const size_t row_bytes = (size_t)idx->dim * 4;
+  HIPCHK(hipMemcpyAsync(idx->g_q.p, queries, (size_t)nq * row_bytes, hipMemcpyDeviceToDevice, st));
+  if (nqb > nq)
+    HIPCHK(hipMemcpyAsync((char*)idx->g_q.p + (size_t)nq * row_bytes, idx->g_q.p, (size_t)(nqb - nq) * row_bytes,
+                          hipMemcpyDeviceToDevice, st));
   rbq_search_opts og = o;
-  if (key.per_query) {
-    HIPCHK(hipMemcpyAsync(idx->g_npq.p, o.nprobe_per_query, (size_t)nq * 4, hipMemcpyDeviceToDevice, st));
-    og.nprobe_per_query = (const int32_t*)idx->g_npq.p;
+  if (!learned) {
+    int32_t* npq = (int32_t*)idx->g_npq.p;
+    if (o.nprobe_per_query) {
+      HIPCHK(hipMemcpyAsync(npq, o.nprobe_per_query, (size_t)nq * 4, hipMemcpyDeviceToDevice, st));
+    } else {
+      HIPCHK(launch_fill_i32(npq, nq, o.nprobe, st));
+    }
+    HIPCHK(launch_fill_i32(npq + nq, nqb - nq, 1, st));
+    og.nprobe_per_query = npq;
   }
   const float* gq = (const float*)idx->g_q.p;
   int64_t* gi = (int64_t*)idx->g_ids.p;

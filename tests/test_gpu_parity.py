@@ -251,6 +251,11 @@ def test_search_mfma_matches_popcount(name):
     a1, d1, s1 = b.search(scan_kernel=b.R.RBQ_SCAN_POPCNT, stats=True)
     a2, d2, s2 = b.search(scan_kernel=b.R.RBQ_SCAN_MFMA, stats=True)
     assert s1["codes_scanned"] == s2["codes_scanned"]
+    # both scans compute the same integers and the same estimator arithmetic:
+    # identical bounds, so the same candidates and the same reranked codes
+    assert s1["candidates"] == s2["candidates"] and s1["reranked"] == s2["reranked"]
+    # and the bounds prune: most scanned codes are never reranked
+    assert s1["reranked"] < 0.5 * s1["codes_scanned"]
     for qi, q in enumerate(c.queries):
         assert tie_equivalent(a2[qi], a1[qi], q, c.data), f"query {qi}"
     np.testing.assert_allclose(d2, d1, rtol=1e-6)
