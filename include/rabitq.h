@@ -288,6 +288,13 @@ rbq_status rbq_debug_scan(rbq_index* idx, int32_t list, const uint8_t* qu, const
 /* Ids of the members of a list in stored order: host, size of the list. */
 rbq_status rbq_debug_list_ids(const rbq_index* idx, int32_t list, int64_t* ids);
 
+/* Searches split a batch into sub-batches whose candidate segments (8 bytes
+ * per probed code per query, sized for the largest lists) stay within a
+ * budget: by default a quarter of the device memory free at the first search,
+ * at least 8 GiB. This sets the budget (bytes; 0 restores the default) so that
+ * tests can force the split. Process-wide. */
+rbq_status rbq_debug_seg_budget(int64_t bytes);
+
 /* Test hook: the n-th device allocation after this call fails with RBQ_ENOMEM
  * (0 disables). Process-wide; for failure-path tests only. */
 rbq_status rbq_debug_fail_alloc_after(int32_t n);

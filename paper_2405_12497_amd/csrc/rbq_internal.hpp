@@ -16,6 +16,7 @@ constexpr int kMaxCodeBits = 4096;
 constexpr int kDefaultChunk = 1024;  // codes per scan work unit
 constexpr int kMaxP0 = 2048;       // bootstrap codes per query: boot - 1 + chunk <= kMaxP0
 constexpr int kBootCodes = 512;    // bootstrap target: at least this many codes (and k)
+constexpr int64_t kSegBudget = 8ll << 30;   // bytes of candidate segments per (sub-)batch
 
 // Bootstrap target for a search with k results and `chunk` codes per unit
 // (chunk <= kMaxP0 + 1 - k): a query's bootstrap covers whole chunks until it

@@ -24,6 +24,9 @@ struct DBuf {
 // Bumped whenever any DBuf is (re)allocated or released: a captured graph
 // holds device addresses and is replayed only while this is unchanged.
 uint64_t buffer_generation();
+// Bytes of candidate segments a (sub-)batch may use (see rbq_debug_seg_budget).
+int64_t seg_budget();
+void g_seg_budget_set(int64_t b);
 
 // One captured search (graph replay of rbq_search with use_graph = 1).
 struct GraphEntry {

@@ -68,7 +68,19 @@ hipError_t dmalloc(void** p, size_t bytes) {
 
 namespace {
 std::atomic<uint64_t> g_buffer_gen{1};
+std::atomic<int64_t> g_seg_budget{0};   // 0: a quarter of free device memory (at least kSegBudget)
 }
+
+int64_t seg_budget() {
+  int64_t b = g_seg_budget.load();
+  if (b > 0) return b;
+  size_t fr = 0, tot = 0;
+  b = kSegBudget;
+  if (hipMemGetInfo(&fr, &tot) == hipSuccess) b = std::max<int64_t>(kSegBudget, (int64_t)(fr / 4));
+  g_seg_budget.store(b);
+  return b;
+}
+void g_seg_budget_set(int64_t b) { g_seg_budget.store(b); }
 
 uint64_t buffer_generation() { return g_buffer_gen.load(); }
 
@@ -868,41 +880,59 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
   if (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())
     return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this build");
   const bool learned = !o.nprobe_per_query && o.use_learned_nprobe && idx->mlp.has_model;
-  const int32_t* npq = nullptr;
-  int stride = o.nprobe;
-  rbq_status rs = (o.use_graph && !idx->prof.on)
-                      ? rbq::search_graph(idx, queries, nq, o, kernel, chunk, learned, out_ids, out_dists, st,
-                                          &npq, &stride)
-                      : run_search(idx, queries, nq, o, kernel, chunk, learned, out_ids, out_dists, st, &npq,
-                                   &stride);
-  if (rs != RBQ_OK) return rs;
-  if (!idx->done_event) HIPCHK(hipEventCreateWithFlags(&idx->done_event, hipEventDisableTiming));
-  HIPCHK(hipEventRecord(idx->done_event, st));
-  if (stats) {
+  // A query's candidate segment reserves a slot for each probed code, so a
+  // batch is searched in sub-batches whose segments stay within kSegBudget
+  // (same stream and workspace; queries keep their ids qid_base + i).
+  const int stride_req = learned ? std::max(o.nprobe, std::min(kMlpNear, idx->nlist)) : o.nprobe;
+  const int64_t seg_row = std::max<int64_t>(1, idx->max_codes(stride_req)) * (int64_t)sizeof(Cand);
+  const int64_t sub = std::max<int64_t>(1, std::min<int64_t>(nq, seg_budget() / seg_row));
+  const bool graph = o.use_graph && !idx->prof.on && sub == nq;
+  auto add_stats = [&](int64_t m, const int32_t* npq, int stride) -> rbq_status {
     HIPCHK(hipStreamSynchronize(st));
-    std::vector<int32_t> rr(nq), cc(nq), p0(nq);
-    std::vector<int64_t> nc(nq);
-    HIPCHK(hipMemcpy(rr.data(), idx->ws.q_rerank.p, nq * 4, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(cc.data(), idx->ws.q_cand.p, nq * 4, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(nc.data(), idx->ws.q_ncode.p, nq * 8, hipMemcpyDeviceToHost));
-    std::vector<int32_t> probe((size_t)nq * stride);
+    std::vector<int32_t> rr(m), cc(m);
+    std::vector<int64_t> nc(m);
+    HIPCHK(hipMemcpy(rr.data(), idx->ws.q_rerank.p, m * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cc.data(), idx->ws.q_cand.p, m * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(nc.data(), idx->ws.q_ncode.p, m * 8, hipMemcpyDeviceToHost));
+    std::vector<int32_t> probe((size_t)m * stride);
     HIPCHK(hipMemcpy(probe.data(), idx->ws.probe.p, probe.size() * 4, hipMemcpyDeviceToHost));
-    stats->queries = nq;
-    for (int64_t i = 0; i < nq; ++i) {
+    stats->queries += m;
+    for (int64_t i = 0; i < m; ++i) {
       stats->reranked += rr[i];
       stats->candidates += cc[i];
       stats->codes_scanned += nc[i];
     }
     std::vector<int32_t> pq;
     if (npq) {
-      pq.resize(nq);
-      HIPCHK(hipMemcpy(pq.data(), npq, nq * 4, hipMemcpyDeviceToHost));
+      pq.resize(m);
+      HIPCHK(hipMemcpy(pq.data(), npq, m * 4, hipMemcpyDeviceToHost));
     }
-    for (int64_t i = 0; i < nq; ++i) {
+    for (int64_t i = 0; i < m; ++i) {
       const int P = npq ? std::min(std::max(pq[i], 1), stride) : stride;
       for (int r = 0; r < P; ++r) stats->pairs += (probe[(size_t)i * stride + r] >= 0);
     }
+    return RBQ_OK;
+  };
+  for (int64_t q0 = 0; q0 < nq; q0 += sub) {
+    const int64_t m = std::min(sub, nq - q0);
+    rbq_search_opts os = o;
+    os.qid_base = o.qid_base + q0;
+    if (o.nprobe_per_query) os.nprobe_per_query = o.nprobe_per_query + q0;
+    const float* qs = queries + q0 * idx->dim;
+    int64_t* oi = out_ids + q0 * o.k;
+    float* od = out_dists + q0 * o.k;
+    const int32_t* npq = nullptr;
+    int stride = o.nprobe;
+    rbq_status rs = graph ? rbq::search_graph(idx, qs, m, os, kernel, chunk, learned, oi, od, st, &npq, &stride)
+                          : run_search(idx, qs, m, os, kernel, chunk, learned, oi, od, st, &npq, &stride);
+    if (rs != RBQ_OK) return rs;
+    if (stats) {
+      rs = add_stats(m, npq, stride);
+      if (rs != RBQ_OK) return rs;
+    }
   }
+  if (!idx->done_event) HIPCHK(hipEventCreateWithFlags(&idx->done_event, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(idx->done_event, st));
   return RBQ_OK;
 }
 
@@ -1177,6 +1207,12 @@ extern "C" rbq_status rbq_debug_scan(rbq_index* idx, int32_t list, const uint8_t
   SearchDev s = make_dev(idx, nullptr, 1, 1, 1, kDefaultChunk, nullptr, 0, true, nullptr, nullptr);
   HIPCHK(launch_debug_scan(s, (const PairRec*)w.pairs.p, (const uint64_t*)w.planes.p,
                            (const int8_t*)w.qu8.p, list, kernel, ip, pc, est, dist, lb, st));
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_debug_seg_budget(int64_t bytes) {
+  if (bytes < 0) return fail(RBQ_EINVAL, "bytes < 0");
+  rbq::g_seg_budget_set(bytes);   // 0: back to the free-memory default
   return RBQ_OK;
 }
 

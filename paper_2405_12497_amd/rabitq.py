@@ -96,6 +96,7 @@ _SIGS = {
     "rbq_debug_scan": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
     "rbq_debug_list_ids": (C.c_int, [_P, C.c_int32, _P]),
     "rbq_debug_fail_alloc_after": (C.c_int, [C.c_int32]),
+    "rbq_debug_seg_budget": (C.c_int, [C.c_int64]),
 }
 
 _lib = None
@@ -356,6 +357,10 @@ def rbq_debug_list_ids(idx, list_id, size):
     out = np.zeros(size, dtype=np.int64)
     _check(lib().rbq_debug_list_ids(idx, list_id, out.ctypes.data_as(C.c_void_p)))
     return out
+
+
+def rbq_debug_seg_budget(nbytes: int):
+    _check(lib().rbq_debug_seg_budget(int(nbytes)))
 
 
 def rbq_debug_fail_alloc_after(n: int):

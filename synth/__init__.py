@@ -169,11 +169,12 @@ def embedding_like_gpu(n: int, nq: int, device, dim: int = 768, seed_data: int =
 
 
 def kmeans_gpu(x, nlist: int, iters: int = 10, seed: int = 7, sample: int | None = None,
-               chunk: int = 8192):
+               chunk: int = 8192, init: np.ndarray | None = None):
     """Lloyd k-means of a float32 GPU tensor x [n, dim]: seeded init from a
     seeded sample of `sample` rows (all rows when None), `iters` rounds of
     FP64 nearest-centroid assignment + mean update on the sample, then a final
-    FP64 assignment of every row. Empty clusters keep their centroid.
+    FP64 assignment of every row. `init` (nlist x dim) replaces the seeded
+    initial centroids. Empty clusters keep their centroid.
     Returns (centroids float32 numpy, assign int32 numpy)."""
     import torch
     n, dim = x.shape
@@ -181,7 +182,10 @@ def kmeans_gpu(x, nlist: int, iters: int = 10, seed: int = 7, sample: int | None
     xs = x
     if sample is not None and sample < n:
         xs = x[torch.from_numpy(np.sort(rng.choice(n, size=sample, replace=False))).to(x.device)]
-    cent = xs[torch.from_numpy(rng.choice(xs.shape[0], size=nlist, replace=False)).to(x.device)].double()
+    if init is not None:
+        cent = torch.as_tensor(np.asarray(init, dtype=np.float64), device=x.device).clone()
+    else:
+        cent = xs[torch.from_numpy(rng.choice(xs.shape[0], size=nlist, replace=False)).to(x.device)].double()
 
     def assign(rows):
         cn = (cent * cent).sum(1)

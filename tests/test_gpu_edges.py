@@ -190,3 +190,29 @@ def test_generated_rotation_when_none_given():
     ids, d, _ = idx.search(q, 3, 1)
     assert list(ids.cpu().numpy()[:, 0]) == [0, 1, 2, 3]
     np.testing.assert_allclose(d.cpu().numpy()[:, 0], sqdist64(data[:4], data[:4] + 0.01), rtol=1e-3)
+
+
+def test_sub_batches_equal_one_batch():
+    """A batch whose candidate segments exceed the budget is searched in
+    sub-batches (query ids, per-query nprobe and outputs offset per
+    sub-batch): same ids, distances and counters as one batch."""
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    from gpu_common import Built, make_case
+    _say("sub-batches")
+    b = Built(make_case("ivf128"))
+    rng = np.random.default_rng(13)
+    qs = (b.case.queries[rng.integers(0, len(b.case.queries), 37)] +
+          rng.normal(0, 1, (37, b.case.dim))).astype(np.float32)
+    q = torch.from_numpy(qs).to(_dev())
+    npq = torch.from_numpy(rng.integers(1, 9, 37).astype(np.int32)).to(_dev())
+    one = b.idx.search(q, 10, 8, nprobe_per_query=npq, qid_base=100, stats=True)
+    row = int(b.idx.list_sizes()[np.argsort(-b.idx.list_sizes())[:8]].sum()) * 8
+    try:
+        R.rbq_debug_seg_budget(row * 5)          # 5 queries per sub-batch
+        split = b.idx.search(q, 10, 8, nprobe_per_query=npq, qid_base=100, stats=True)
+    finally:
+        R.rbq_debug_seg_budget(0)
+    np.testing.assert_array_equal(one[0].cpu().numpy(), split[0].cpu().numpy())
+    np.testing.assert_array_equal(one[1].cpu().numpy(), split[1].cpu().numpy())
+    assert one[2] == split[2]
