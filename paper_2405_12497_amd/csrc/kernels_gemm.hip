@@ -6,163 +6,170 @@
 
 namespace rbq {
 
-// ---------------------------------------------------------------- FP32 tiled GEMM
-// 64 x 64 output tile per 256-thread block, 4 x 4 per thread, K step 16.
+// ---------------------------------------------------------------- FP32 GEMM modes
 // MODE 0: Y = (A - sub[sel]) * B.  MODE 1: centroid distances
 //   Y[m][n] = an[m] + bn[n] - 2 * (A * B)[m][n], clamped at 0.
 namespace {
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TM = 64, TN = 64;
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_gemm_f32(const float* __restrict__ A, int64_t lda,
-                                                  const float* __restrict__ sub,
-                                                  const int32_t* __restrict__ sel,
-                                                  const float* __restrict__ B, int64_t ldb,
-                                                  float* __restrict__ Y, int64_t ldy, int64_t M,
-                                                  int N, int K, const float* __restrict__ an,
-                                                  const float* __restrict__ bn) {
-  __shared__ float As[TK][TM + 4];
-  __shared__ float Bs[TK][TN + 4];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int64_t m0 = (int64_t)blockIdx.x * TM;
-  const int n0 = blockIdx.y * TN;
-  float acc[4][4] = {};
-  // A tile loader: 64 rows x 16 k, thread loads 4 consecutive k of one row
-  const int la_r = tid >> 2, la_k = (tid & 3) * 4;
-  // B tile loader: 16 k x 64 n, thread loads 4 consecutive n of one k
-  const int lb_k = tid >> 4, lb_n = (tid & 15) * 4;
-  const int64_t am = m0 + la_r;
-  const float* arow = (am < M) ? A + am * lda : nullptr;
-  const float* srow = (am < M && sel) ? sub + (int64_t)sel[am] * K : nullptr;
-  for (int k0 = 0; k0 < K; k0 += TK) {
+// ---------------------------------------------------------------- FP32 MFMA GEMM
+// Same modes on the matrix cores (v_mfma_f32_16x16x4_f32: FP32 products, FP32
+// accumulation). Four waves in a 2 x 2 grid, each owning WT x WT blocks of
+// 16 x 16 outputs, so the block tile is 32 WT square; K steps of 16. In MFMA
+// sub-step s, lane l contributes k = 4 s + l / 16 of its row (A, LDS [m][k])
+// and column (B, LDS [k][n]); the B rows are padded by 16 floats so the four
+// k rows a wave reads fall in different banks.
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+constexpr int MKS = 16, MKP = MKS + 4;
+
+template <int MODE, int WT>
+__global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__ A, int64_t lda,
+                                                       const float* __restrict__ sub,
+                                                       const int32_t* __restrict__ sel,
+                                                       const float* __restrict__ B, int64_t ldb,
+                                                       float* __restrict__ Y, int64_t ldy, int64_t M,
+                                                       int N, int K, const float* __restrict__ an,
+                                                       const float* __restrict__ bn) {
+  constexpr int BT = 32 * WT;        // block tile (rows and columns)
+  constexpr int NLD = BT * 4 / 256;  // float4 loads per thread per operand and K step
+  __shared__ __attribute__((aligned(16))) float As[BT][MKP];
+  __shared__ __attribute__((aligned(16))) float Bs[MKS][BT + 16];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t m0 = (int64_t)blockIdx.x * BT;
+  const int n0 = blockIdx.y * BT;
+  const int wm = (wave >> 1) * (16 * WT), wn = (wave & 1) * (16 * WT);
+  f32x4v acc[WT][WT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int kk = k0 + la_k + i;
-      float v = 0.f;
-      if (arow && kk < K) {
-        v = arow[kk];
-        if (srow) v -= srow[kk];
-      }
-      As[la_k + i][la_r] = v;
-    }
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int kk = k0 + lb_k, nn = n0 + lb_n + i;
-      Bs[lb_k][lb_n + i] = (kk < K && nn < N) ? B[(int64_t)kk * ldb + nn] : 0.f;
-    }
-    __syncthreads();
+    for (int j = 0; j < WT; ++j) acc[i][j] = f32x4v{0.f, 0.f, 0.f, 0.f};
+  const bool a_vec = (lda & 3) == 0 && (K & 3) == 0;   // rows (and centroid rows) 16-byte aligned
+  const bool b_vec = (ldb & 3) == 0;
+  // tiles entirely inside the matrices take unconditional float4 loads
+  const bool interior = a_vec && b_vec && m0 + BT <= M && n0 + BT <= N;
+  const float* arow[NLD];
+  const float* srow[NLD];
 #pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      float a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
+  for (int u = 0; u < NLD; ++u) {
+    const int64_t m = m0 + ((tid + 256 * u) >> 2);
+    arow[u] = m < M ? A + m * lda : nullptr;
+    srow[u] = (m < M && sel) ? sub + (int64_t)sel[m] * K : nullptr;
   }
+  float4 ra[NLD], rb[NLD];
+  auto fetch = [&](int k0) {
+    if (interior && k0 + MKS <= K) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t m = m0 + ty * 4 + i;
-    if (m >= M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tx * 4 + j;
-      if (n >= N) continue;
-      float v = acc[i][j];
-      if (MODE == 1) v = fmaxf(an[m] + bn[n] - 2.f * v, 0.f);
-      Y[m * ldy + n] = v;
-    }
-  }
-}
-
-// 128 x 128 output tile, 8 x 8 per thread (rows ty*4 + {0..3, 64..67}, cols
-// tx*4 + {0..3, 64..67}), K step 8. Same modes as k_gemm_f32.
-constexpr int BM = 128, BN = 128, BKF = 8;
-
-template <int MODE>
-__global__ __launch_bounds__(256) void k_gemm_f32_big(const float* __restrict__ A, int64_t lda,
-                                                      const float* __restrict__ sub,
-                                                      const int32_t* __restrict__ sel,
-                                                      const float* __restrict__ B, int64_t ldb,
-                                                      float* __restrict__ Y, int64_t ldy, int64_t M,
-                                                      int N, int K, const float* __restrict__ an,
-                                                      const float* __restrict__ bn) {
-  __shared__ __attribute__((aligned(16))) float As[BKF][BM];
-  __shared__ __attribute__((aligned(16))) float Bs[BKF][BN];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
-  float acc[8][8] = {};
-  // A loader: 128 rows x 8 k: thread loads 4 consecutive k of row tid>>1
-  const int la_r = tid >> 1, la_k = (tid & 1) * 4;
-  const int64_t am = m0 + la_r;
-  const float* arow = (am < M) ? A + am * lda : nullptr;
-  const float* srow = (am < M && sel) ? sub + (int64_t)sel[am] * K : nullptr;
-  // B loader: 8 k x 128 n: thread loads 4 consecutive n of k = tid>>5
-  const int lb_k = tid >> 5, lb_n = (tid & 31) * 4;
-  for (int k0 = 0; k0 < K; k0 += BKF) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int kk = k0 + la_k + i;
-      float v = 0.f;
-      if (arow && kk < K) {
-        v = arow[kk];
-        if (srow) v -= srow[kk];
+      for (int u = 0; u < NLD; ++u) {
+        const int f = tid + 256 * u;
+        ra[u] = *reinterpret_cast<const float4*>(arow[u] + k0 + (f & 3) * 4);
+        rb[u] = *reinterpret_cast<const float4*>(B + (int64_t)(k0 + f / (BT / 4)) * ldb + n0 + (f % (BT / 4)) * 4);
       }
-      As[la_k + i][la_r] = v;
-    }
-    {
-      const int kk = k0 + lb_k;
-      const int nn = n0 + lb_n;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (kk < K) {
-        const float* brow = B + (int64_t)kk * ldb;
-        if (nn + 3 < N && ((ldb & 3) == 0)) {
-          v = *reinterpret_cast<const float4*>(brow + nn);
-        } else {
-          if (nn < N) v.x = brow[nn];
-          if (nn + 1 < N) v.y = brow[nn + 1];
-          if (nn + 2 < N) v.z = brow[nn + 2];
-          if (nn + 3 < N) v.w = brow[nn + 3];
+      if (sel) {
+        float4 c[NLD];
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) c[u] = *reinterpret_cast<const float4*>(srow[u] + k0 + ((tid + 256 * u) & 3) * 4);
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+          ra[u].x -= c[u].x;
+          ra[u].y -= c[u].y;
+          ra[u].z -= c[u].z;
+          ra[u].w -= c[u].w;
         }
       }
-      *reinterpret_cast<float4*>(&Bs[lb_k][lb_n]) = v;
+      return;
     }
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int f = tid + 256 * u;
+      const int kq = (f & 3) * 4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (arow[u]) {
+        const int k = k0 + kq;
+        float t[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t[i] = (k + i < K) ? arow[u][k + i] - (srow[u] ? srow[u][k + i] : 0.f) : 0.f;
+        v = make_float4(t[0], t[1], t[2], t[3]);
+      }
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int f = tid + 256 * u;
+      const int kr = f / (BT / 4), nq = (f % (BT / 4)) * 4;
+      const int k = k0 + kr, n = n0 + nq;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (k < K) {
+        const float* brow = B + (int64_t)k * ldb;
+        if (n < N) v.x = brow[n];
+        if (n + 1 < N) v.y = brow[n + 1];
+        if (n + 2 < N) v.z = brow[n + 2];
+        if (n + 3 < N) v.w = brow[n + 3];
+      }
+      rb[u] = v;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int f = tid + 256 * u;
+      *reinterpret_cast<float4*>(&As[f >> 2][(f & 3) * 4]) = ra[u];
+      *reinterpret_cast<float4*>(&Bs[f / (BT / 4)][(f % (BT / 4)) * 4]) = rb[u];
+    }
+  };
+  fetch(0);
+  const int fr = lane & 15, fg = lane >> 4;
+  for (int k0 = 0; k0 < K; k0 += MKS) {
+    stash();
     __syncthreads();
+    if (k0 + MKS < K) fetch(k0 + MKS);   // next step's operands in flight during this one
 #pragma unroll
-    for (int kk = 0; kk < BKF; ++kk) {
-      const float4 a0 = *reinterpret_cast<const float4*>(&As[kk][ty * 4]);
-      const float4 a1 = *reinterpret_cast<const float4*>(&As[kk][ty * 4 + 64]);
-      const float4 b0 = *reinterpret_cast<const float4*>(&Bs[kk][tx * 4]);
-      const float4 b1 = *reinterpret_cast<const float4*>(&Bs[kk][tx * 4 + 64]);
-      const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-      const float b[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+    for (int ss = 0; ss < 4; ++ss) {
+      float a[WT], b[WT];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < WT; ++i) a[i] = As[wm + i * 16 + fr][4 * ss + fg];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+      for (int j = 0; j < WT; ++j) b[j] = Bs[4 * ss + fg][wn + j * 16 + fr];
+#pragma unroll
+      for (int i = 0; i < WT; ++i)
+#pragma unroll
+        for (int j = 0; j < WT; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
+  // output block (i, j): lane holds rows 4 (lane / 16) + e, column lane % 16
+  const int oc = lane & 15, orow = (lane >> 4) * 4;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int64_t m = m0 + ty * 4 + (i & 3) + (i >> 2) * 64;
-    if (m >= M) continue;
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int n = n0 + tx * 4 + (j & 3) + (j >> 2) * 64;
+    for (int j = 0; j < WT; ++j) {
+      const int n = n0 + wn + j * 16 + oc;
       if (n >= N) continue;
-      float v = acc[i][j];
-      if (MODE == 1) v = fmaxf(an[m] + bn[n] - 2.f * v, 0.f);
-      Y[m * ldy + n] = v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t m = m0 + wm + i * 16 + orow + e;
+        if (m >= M) continue;
+        float v = acc[i][j][e];
+        if (MODE == 1) v = fmaxf(an[m] + bn[n] - 2.f * v, 0.f);
+        Y[m * ldy + n] = v;
+      }
     }
+}
+
+template <int MODE>
+void launch_f32_mfma(const float* A, int64_t lda, const float* sub, const int32_t* sel, const float* B,
+                     int64_t ldb, float* Y, int64_t ldy, int64_t M, int N, int K, const float* an,
+                     const float* bn, hipStream_t st) {
+  // the 128 tile when it still gives at least 1024 blocks, else the 64 tile
+  const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
+  if (big >= 1024) {
+    dim3 grid((unsigned)((M + 127) / 128), (N + 127) / 128);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 4>), grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
+                       M, N, K, an, bn);
+  } else {
+    dim3 grid((unsigned)((M + 63) / 64), (N + 63) / 64);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 2>), grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
+                       M, N, K, an, bn);
   }
 }
 
@@ -348,15 +355,7 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* sub, const 
                            const float* B, int64_t ldb, float* Y, int64_t ldy, int64_t M, int N,
                            int K, hipStream_t st) {
   if (M <= 0) return hipSuccess;
-  if (M >= 2048) {
-    dim3 grid((unsigned)((M + BM - 1) / BM), (N + BN - 1) / BN);
-    hipLaunchKernelGGL(k_gemm_f32_big<0>, grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
-                       M, N, K, nullptr, nullptr);
-  } else {
-    dim3 grid((unsigned)((M + TM - 1) / TM), (N + TN - 1) / TN);
-    hipLaunchKernelGGL(k_gemm_f32<0>, grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy, M,
-                       N, K, nullptr, nullptr);
-  }
+  launch_f32_mfma<0>(A, lda, sub, sel, B, ldb, Y, ldy, M, N, K, nullptr, nullptr, st);
   return hipGetLastError();
 }
 
@@ -376,15 +375,8 @@ hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float
   // separate small buffer carved after D (caller provides nq floats there).
   float* qn = D + nq * (int64_t)nlist;
   hipLaunchKernelGGL(k_rownorm, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, Q, nq, dim, qn);
-  if (nq >= 256 && nlist >= 128) {
-    dim3 grid((unsigned)((nq + BM - 1) / BM), (nlist + BN - 1) / BN);
-    hipLaunchKernelGGL(k_gemm_f32_big<1>, grid, dim3(256), 0, st, Q, (int64_t)dim, nullptr, nullptr,
-                       Ct, (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim, qn, cn);
-  } else {
-    dim3 grid((unsigned)((nq + TM - 1) / TM), (nlist + TN - 1) / TN);
-    hipLaunchKernelGGL(k_gemm_f32<1>, grid, dim3(256), 0, st, Q, (int64_t)dim, nullptr, nullptr, Ct,
-                       (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim, qn, cn);
-  }
+  launch_f32_mfma<1>(Q, (int64_t)dim, nullptr, nullptr, Ct, (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim,
+                     qn, cn, st);
   return hipGetLastError();
 }
 

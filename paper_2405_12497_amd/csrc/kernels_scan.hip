@@ -48,33 +48,35 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
   float qq[PPW];
   int list[PPW];
   bool act[PPW];
+  // index loads first, then every coordinate load unconditionally (clamped
+  // rows and words), so all of them are in flight together
+  int64_t qj[PPW];
+  int32_t pl_raw[PPW], npq_raw[PPW];
+#pragma unroll
+  for (int j = 0; j < PPW; ++j) {
+    const int64_t g = min(g0 + j, npairs - 1);
+    qj[j] = g / s.nprobe;
+    pl_raw[j] = s.probe[g];
+    npq_raw[j] = s.nprobe_q ? s.nprobe_q[qj[j]] : s.nprobe;
+  }
 #pragma unroll
   for (int j = 0; j < PPW; ++j) {
     const int64_t g = g0 + j;
-    act[j] = false;
-    list[j] = -1;
+    const int r = (int)(min(g, npairs - 1) - qj[j] * s.nprobe);
+    const int P = min(max(npq_raw[j], 1), s.nprobe);
+    list[j] = uniform_i32((g < npairs && r < P) ? pl_raw[j] : -1);
+    act[j] = list[j] >= 0;
     qq[j] = 0.f;
+    const float* qrot = s.qrot + qj[j] * s.dp;
+    const float* crot = s.crot + (int64_t)max(list[j], 0) * s.dp;
 #pragma unroll
-    for (int t = 0; t < WS; ++t) rv[j][t] = 0.f;
-    if (g < npairs) {
-      const int64_t q = g / s.nprobe;
-      const int r = (int)(g - q * s.nprobe);
-      int P = s.nprobe;
-      if (s.nprobe_q) P = uniform_i32(min(max(s.nprobe_q[q], 1), s.nprobe));
-      list[j] = r < P ? uniform_i32(s.probe[g]) : -1;
-      act[j] = list[j] >= 0;
-      if (act[j]) {
-        const float* qrot = s.qrot + q * s.dp;
-        const float* crot = s.crot + (int64_t)list[j] * s.dp;
-#pragma unroll
-        for (int t = 0; t < WS; ++t) {
-          if (t < W) {
-            const float x = qrot[t * kWave + lane];
-            rv[j][t] = x - crot[t * kWave + lane];
-            qq[j] = fmaf(x, x, qq[j]);
-          }
-        }
-      }
+    for (int t = 0; t < WS; ++t) {
+      const int tt = min(t, W - 1);
+      const float x = qrot[tt * kWave + lane];
+      const float c = crot[tt * kWave + lane];
+      const bool in = t < W;
+      rv[j][t] = in ? x - c : 0.f;
+      qq[j] = in ? fmaf(x, x, qq[j]) : qq[j];
     }
   }
 #pragma unroll
@@ -228,69 +230,78 @@ __global__ __launch_bounds__(kThreads) void k_plan(SearchDev s) {
 }
 
 // Exclusive prefix sums over queries (single block) and work-counter reset.
-// Thread t owns the contiguous queries [t*per, (t+1)*per): it sums them, the
-// block scans the 1024 sums (shuffle scan in each wave, then the 16 wave
-// totals), and the thread writes its queries' offsets in a second pass.
+// Tiles of 4096 queries: thread t reads queries 4t..4t+3 of the tile (adjacent
+// threads read adjacent words); each of the five sums is scanned in turn
+// (shuffle scan in each wave, then the 16 wave totals), with its carry across
+// tiles in LDS.
 __global__ __launch_bounds__(1024) void k_offsets(SearchDev s) {
-  constexpr int kT = 1024, kNW = kT / kWave;
-  __shared__ int64_t wtot[kNW][5];
+  constexpr int kT = 1024, kNW = kT / kWave, kPer = 4;
+  __shared__ int64_t wtot[kNW];
+  __shared__ int64_t carry[5];
   const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
   if (t == 0) {
     s.counters[0] = 0;
     s.counters[1] = 0;
   }
-  const int64_t per = (s.nq + kT - 1) / kT;
-  const int64_t q0 = min<int64_t>(s.nq, t * per), q1 = min<int64_t>(s.nq, q0 + per);
-  auto vals = [&](int64_t q, int64_t (&v)[5]) {
-    const int64_t nch = s.q_nch[q], p0 = s.q_p0[q];
-    v[0] = nch;
-    v[1] = p0;
-    v[2] = nch - p0;
-    v[3] = s.q_ncode[q];
-    v[4] = s.q_n0[q];
-  };
-  int64_t sum[5] = {0, 0, 0, 0, 0};
-  for (int64_t q = q0; q < q1; ++q) {
-    int64_t v[5];
-    vals(q, v);
-#pragma unroll
-    for (int a = 0; a < 5; ++a) sum[a] += v[a];
-  }
-  int64_t inc[5];
-#pragma unroll
-  for (int a = 0; a < 5; ++a) {
-    int64_t x = sum[a];
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int64_t y = __shfl_up(x, o, kWave);
-      if (lane >= o) x += y;
-    }
-    inc[a] = x;
-  }
-  if (lane == kWave - 1)
-#pragma unroll
-    for (int a = 0; a < 5; ++a) wtot[wave][a] = inc[a];
+  if (t < 5) carry[t] = 0;
   __syncthreads();
-  int64_t run[5];
+  for (int64_t base = 0; base < s.nq; base += kT * kPer) {
+    const int64_t q0 = base + (int64_t)t * kPer;
+    int32_t nch[kPer], p0[kPer], ncode[kPer], n0[kPer];
 #pragma unroll
-  for (int a = 0; a < 5; ++a) {
-    int64_t before = 0;
-    for (int w = 0; w < wave; ++w) before += wtot[w][a];
-    run[a] = before + inc[a] - sum[a];
-  }
-  int64_t* outs[5] = {s.off_ch, s.off_p0, s.off_p1, s.off_seg, s.off_n0};
-  for (int64_t q = q0; q < q1; ++q) {
-    int64_t v[5];
-    vals(q, v);
-#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t q = q0 + u;
+      const bool in = q < s.nq;
+      nch[u] = in ? s.q_nch[q] : 0;
+      p0[u] = in ? s.q_p0[q] : 0;
+      ncode[u] = in ? s.q_ncode[q] : 0;
+      n0[u] = in ? s.q_n0[q] : 0;
+    }
+#pragma unroll 1
     for (int a = 0; a < 5; ++a) {
-      outs[a][q] = run[a];
-      run[a] += v[a];
+      // per query: nch, p0, nch - p0, ncode, n0
+      int32_t v[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u)
+        v[u] = a == 0 ? nch[u] : a == 1 ? p0[u] : a == 2 ? nch[u] - p0[u] : a == 3 ? ncode[u] : n0[u];
+      int64_t sum = 0;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) sum += v[u];
+      int64_t inc = sum;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t y = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += y;
+      }
+      if (lane == kWave - 1) wtot[wave] = inc;
+      __syncthreads();
+      int64_t before = 0, total = 0;
+#pragma unroll
+      for (int w = 0; w < kNW; ++w) {
+        const int64_t x = wtot[w];
+        before += (w < wave) ? x : 0;
+        total += x;
+      }
+      const int64_t c = carry[a];
+      int64_t* out = a == 0 ? s.off_ch : a == 1 ? s.off_p0 : a == 2 ? s.off_p1 : a == 3 ? s.off_seg : s.off_n0;
+      int64_t run = c + before + inc - sum;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        if (q0 + u < s.nq) out[q0 + u] = run;
+        run += v[u];
+      }
+      __syncthreads();   // wtot and carry[a] are read by all before they change
+      if (t == 0) carry[a] = c + total;
     }
   }
-  if (t == kT - 1)
-#pragma unroll
-    for (int a = 0; a < 5; ++a) outs[a][s.nq] = run[a];
+  __syncthreads();
+  if (t == 0) {
+    s.off_ch[s.nq] = carry[0];
+    s.off_p0[s.nq] = carry[1];
+    s.off_p1[s.nq] = carry[2];
+    s.off_seg[s.nq] = carry[3];
+    s.off_n0[s.nq] = carry[4];
+  }
 }
 
 // One wave per query, a lane per probe rank: the descriptors of its chunks,
@@ -337,11 +348,6 @@ __global__ __launch_bounds__(kThreads) void k_units(SearchDev s) {
 // The loads of all NC vectors are issued together. Every exact distance on
 // the device comes from this routine, so equal vectors get equal bits.
 constexpr int kLpc = 8;
-
-template <int N>
-struct IntC {
-  static constexpr int value = N;
-};
 
 template <int NC>
 __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const int32_t (&pos)[NC], int dim,
@@ -413,16 +419,15 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
   for (int i = threadIdx.x; i < s.dim; i += kThreads) qv[i] = s.q[q * s.dim + i];
   // keys (sortable estimated distance << 32 | slot) held in registers
   uint64_t kk[kPerT];
+  EstEnt ee[kPerT];
+#pragma unroll
+  for (int j = 0; j < kPerT; ++j) ee[j] = s.p0buf[n0 > 0 ? b0 + min((int)threadIdx.x + j * kThreads, n0 - 1) : 0];
 #pragma unroll
   for (int j = 0; j < kPerT; ++j) {
     const int i = threadIdx.x + j * kThreads;
-    kk[j] = ~0ull;
-    if (i < n0) {
-      const EstEnt e = s.p0buf[b0 + i];
-      uint32_t kb = __float_as_uint(e.dist);
-      kb = (kb & 0x80000000u) ? ~kb : (kb | 0x80000000u);
-      kk[j] = ((uint64_t)kb << 32) | (uint32_t)e.slot;
-    }
+    uint32_t kb = __float_as_uint(ee[j].dist);
+    kb = (kb & 0x80000000u) ? ~kb : (kb | 0x80000000u);
+    kk[j] = i < n0 ? ((uint64_t)kb << 32) | (uint32_t)ee[j].slot : ~0ull;
   }
   // radix select (8 bits per pass) of the m-th smallest high word T
   uint32_t prefix = 0, mask = 0, need = (uint32_t)m;
@@ -740,43 +745,76 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
           else run(IntC<4>{});
         }
         __syncthreads();
-        {
-          // merge the round into the top-k: every element of (top-k so far) u
-          // (round) takes its rank by (distance, id) among all of them (ids are
-          // distinct, so ranks are too) and the first K ranks are written back
+        if (wave == 0) {
+          // merge the round into the top-k (sorted by (distance, id), ids
+          // distinct): only round entries below the current k-th can enter
+          // (all of them while fewer than K are known). They are compacted to
+          // the front of cd/cid; each element of the union then takes its rank:
+          // a top-k element its index plus the entrants below it, an entrant
+          // the top-k elements below it (binary search) plus the entrants below
+          // it. Every value is read before any is written.
           const int cnt = uniform_i32(sh_cnt);
-          const int mtot = cnt + n;   // <= K + kFinRound <= 2 * kThreads
-          float ed[2];
-          int64_t eid[2];
-          int er[2];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int e = threadIdx.x + h * kThreads;
-            er[h] = K;
-            if (e < mtot) {
-              ed[h] = e < cnt ? td[e] : cd[e - cnt];
-              eid[h] = e < cnt ? tid[e] : cid[e - cnt];
-              int r = 0;
-              for (int t = 0; t < cnt; ++t) r += less_di(td[t], tid[t], ed[h], eid[h]);
-              for (int t = 0; t < n; ++t) r += less_di(cd[t], cid[t], ed[h], eid[h]);
-              er[h] = r;
+          const bool full = cnt == K;
+          const float kd = full ? td[K - 1] : 0.f;
+          const int64_t kid = full ? tid[K - 1] : 0;
+          int m = 0;
+          for (int i0 = 0; i0 < n; i0 += kWave) {
+            const int i = i0 + lane;
+            const float d = i < n ? cd[i] : 0.f;
+            const int64_t id = i < n ? cid[i] : 0;
+            const bool in = i < n && (!full || less_di(d, id, kd, kid));
+            const uint64_t b = __ballot(in);
+            if (in) {
+              const int at = m + __popcll(b & lanemask_lt());
+              cd[at] = d;
+              cid[at] = id;
             }
+            m += __popcll(b);
           }
-          __syncthreads();
+          if (m > 0) {
+            constexpr int kPerLane = (kMaxK + kFinRound + kWave - 1) / kWave;
+            const int mtot = cnt + m;
+            float ed[kPerLane];
+            int64_t eid[kPerLane];
+            int er[kPerLane];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            if (er[h] < K) {
-              td[er[h]] = ed[h];
-              tid[er[h]] = eid[h];
+            for (int h = 0; h < kPerLane; ++h) {
+              const int e = lane + h * kWave;
+              er[h] = K;
+              if (e < mtot) {
+                const bool top = e < cnt;
+                ed[h] = top ? td[e] : cd[e - cnt];
+                eid[h] = top ? tid[e] : cid[e - cnt];
+                int r = 0;
+                if (top) {
+                  r = e;
+                } else {
+                  int lo = 0, hi = cnt;   // top-k elements below the entrant
+                  while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (less_di(td[mid], tid[mid], ed[h], eid[h])) lo = mid + 1; else hi = mid;
+                  }
+                  r = lo;
+                }
+                for (int t = 0; t < m; ++t) r += less_di(cd[t], cid[t], ed[h], eid[h]);
+                er[h] = r;
+              }
             }
-          }
-          __syncthreads();
-          if (threadIdx.x == 0) {
-            const int c2 = min(mtot, K);
-            sh_cnt = c2;
-            if (c2 == K) sh_tau = fminf(sh_tau, td[K - 1]);
+#pragma unroll
+            for (int h = 0; h < kPerLane; ++h) {
+              if (er[h] < K) {
+                td[er[h]] = ed[h];
+                tid[er[h]] = eid[h];
+              }
+            }
+            if (lane == 0) {
+              const int c2 = min(mtot, K);
+              sh_cnt = c2;
+              if (c2 == K) sh_tau = fminf(sh_tau, td[K - 1]);
+            }
           }
         }
+        __syncthreads();
         reranked += n;
         __syncthreads();
       }

@@ -151,6 +151,13 @@ __device__ __forceinline__ float uniform_f32(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// Compile-time integer carried as a type, for dispatching a runtime count to
+// one of a few unrolled template instances.
+template <int N>
+struct IntC {
+  static constexpr int value = N;
+};
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int l = lane_id();
   return l == 0 ? 0ull : (~0ull >> (64 - l));
