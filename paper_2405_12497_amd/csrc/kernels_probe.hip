@@ -1,6 +1,7 @@
 // IVF probing (Sec. 4): per query, the nprobe lists with the smallest squared
 // centroid distance, nearest first, ties to the lower list id.
 #include "rbq_internal.hpp"
+#include "wave_select.hpp"
 
 namespace rbq {
 namespace {
@@ -280,94 +281,11 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_large(const float*
 }
 
 // ------------------------------------------------------------------ wave select
-// One wave per query for nprobe <= kWSelMaxP: no block barriers. A sorted
-// sample of 256 keys gives a cut expected to keep about 1.5 P + 48 keys; the
-// keys at or below it are compacted into the wave's LDS region and sorted
-// there as (key << 32 | list) in registers. When the cut keeps fewer than P or
-// more than kWSelCap keys, bisection over the key bits finds the P-th smallest
-// key exactly, and the ties at it are taken in list-id order.
-constexpr int kWSelCap = 1024;
+// One wave per query for nprobe <= kWSelMaxP: the wave selection over the
+// query's distance row (keys: distance bits, non-negative floats ordering like
+// their bit patterns; ties to the lower list id), no block barriers.
 constexpr int kWSelMaxP = 256;
 constexpr int kWSelWaves = kSelThreads / kWave;
-
-// Bitonic sort of N * 64 64-bit values held as v[r] at element r * 64 + lane,
-// ascending: strides below 64 exchange across lanes, larger ones across registers.
-template <int N>
-__device__ __forceinline__ void wave_bitonic_u64(uint64_t (&v)[N]) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int size = 2; size <= N * kWave; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      if (stride >= kWave) {
-        const int rs = stride / kWave;
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          if ((r & rs) == 0) {
-            const bool up = (((r * kWave) & size) == 0);
-            const uint64_t x = v[r], y = v[r + rs];
-            if ((x > y) == up) {
-              v[r] = y;
-              v[r + rs] = x;
-            }
-          }
-        }
-      } else {
-        const bool lower = (lane & stride) == 0;
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-          const bool up = (((r * kWave + lane) & size) == 0);
-          const uint64_t y = __shfl_xor(v[r], stride, kWave);
-          const bool take_min = (lower == up);
-          v[r] = take_min ? (v[r] < y ? v[r] : y) : (v[r] < y ? y : v[r]);
-        }
-      }
-    }
-  }
-}
-
-// The same network over n (power of two) values in one wave's LDS region;
-// the wave's LDS operations complete in order, so a fence between stages is
-// all the ordering needed.
-__device__ void wave_bitonic_lds_u64(uint64_t* a, int n) {
-  const int lane = lane_id();
-  for (int size = 2; size <= n; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = lane; i < n / 2; i += kWave) {
-        const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t x = a[lo], y = a[hi];
-        if ((x > y) == up) {
-          a[lo] = y;
-          a[hi] = x;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-  }
-}
-
-__device__ __forceinline__ int wave_incl_scan_i(int x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int y = __shfl_up(x, o, kWave);
-    if (lane >= o) x += y;
-  }
-  return x;
-}
-
-// Entries past the row become keys above every real one (+inf bits at most).
-__device__ __forceinline__ uint32_t probe_key(const float* row, int k, int nlist) {
-  return k < nlist ? __float_as_uint(fmaxf(row[k], 0.f)) : 0xFFFFFFFFu;
-}
-
-// The row is streamed in batches of kWSelBatch keys per lane (element
-// c0 + j * 64 + lane); only the compaction pass and, when it fails, the exact
-// bisection read it, so no key is held across passes.
-constexpr int kWSelBatch = 16;
 
 __global__ __launch_bounds__(kSelThreads) void k_select_probe_wave(const float* __restrict__ D, int64_t nq,
                                                                    int nlist, int nprobe,
@@ -375,7 +293,6 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_wave(const float* 
                                                                    int32_t* __restrict__ lists,
                                                                    float* __restrict__ dists) {
   __shared__ uint64_t selw[kWSelWaves][kWSelCap];
-  constexpr int B = kWSelBatch;
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int64_t q = (int64_t)blockIdx.x * kWSelWaves + wave;
   if (q >= nq) return;   // whole waves
@@ -384,139 +301,12 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_wave(const float* 
   if (nprobe_q) P = uniform_i32(min(max(nprobe_q[q], 1), nprobe));
   P = min(P, nlist);
   const float* row = D + q * (int64_t)nlist;
-  // f(id, key) for every key, batch by batch. Full batches load without
-  // bounds tests (so all B loads of a lane are in flight together); only a
-  // ragged last batch is checked.
-  auto stream = [&](auto&& f) {
-    int c0 = 0;
-    for (; c0 + B * kWave <= nlist; c0 += B * kWave) {
-      float kv[B];
-#pragma unroll
-      for (int j = 0; j < B; ++j) kv[j] = row[c0 + j * kWave + lane];
-#pragma unroll
-      for (int j = 0; j < B; ++j) f(c0 + j * kWave + lane, __float_as_uint(fmaxf(kv[j], 0.f)));
-    }
-    if (c0 < nlist) {
-#pragma unroll
-      for (int j = 0; j < B; ++j) f(c0 + j * kWave + lane, probe_key(row, c0 + j * kWave + lane, nlist));
-    }
-  };
-  // cut from a sorted sample of 256 keys (every key when nlist <= 256); a cut
-  // that keeps fewer than P or more than kWSelCap keys is moved along the
-  // sample (4x further or closer) and tried again, and each failed cut narrows
-  // the key range [lo, hi] that the exact bisection searches
-  uint32_t lo = 0, hi = 0x7F800000u;
-  int total = 0;   // wave-uniform count of keys <= cut
-  bool ok = false;
-  auto compact = [&](uint32_t cut) {
-    total = 0;
-    stream([&](int id, uint32_t key) {
-      const bool keep = key <= cut;
-      const uint64_t m = __ballot(keep);
-      const int at = total + __popcll(m & lanemask_lt());
-      if (keep && at < kWSelCap) sel[at] = ((uint64_t)key << 32) | (uint32_t)id;
-      total += __popcll(m);
-    });
-    if (total < P) lo = max(lo, cut + 1);
-    else if (total > kWSelCap) hi = min(hi, cut);
-    return total >= P && total <= kWSelCap;
-  };
-  if (nlist > 256) {
-    const int stride = nlist / 256;
-    uint64_t sm[4];
-    float sv[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) sv[r] = row[(r * kWave + lane) * stride];   // < 256 stride <= nlist
-#pragma unroll
-    for (int r = 0; r < 4; ++r) sm[r] = (uint64_t)__float_as_uint(fmaxf(sv[r], 0.f)) << 32;
-    wave_bitonic_u64<4>(sm);
-    int sidx = min(255, (int)((1.5f * P + 32.f) * 256.f / (float)nlist) + 1);
-    for (int attempt = 0; attempt < 3 && !ok; ++attempt) {
-      uint64_t pick = sm[0];
-#pragma unroll
-      for (int r = 1; r < 4; ++r) pick = (sidx / kWave == r) ? sm[r] : pick;
-      const uint32_t cut = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(pick >> 32), sidx % kWave);
-      ok = compact(cut);
-      if (ok) break;
-      const int next = total < P ? min(255, 4 * sidx + 8) : sidx / 4;
-      if (next == sidx) break;
-      sidx = next;
-    }
-  } else {
-    ok = compact(0x7F800000u);
-  }
-  if (!ok) {
-    // exact: T = the smallest key with at least P keys <= T (in [lo, hi])
-    auto count_le = [&](uint32_t t) {
-      int c = 0;
-      stream([&](int, uint32_t key) { c += (key <= t); });
-      return wave_sum_i(c);
-    };
-    while (lo < hi) {
-      const uint32_t mid = lo + ((hi - lo) >> 1);
-      if (count_le(mid) >= P) hi = mid; else lo = mid + 1;
-    }
-    const uint32_t T = lo;
-    int nless = 0;
-    stream([&](int, uint32_t key) { nless += (key < T); });
-    nless = wave_sum_i(nless);
-    const int need = P - nless;   // ties at T, lowest list ids first
-    int at_less = 0, tie_run = 0;
-    stream([&](int id, uint32_t key) {
-      const uint64_t ml = __ballot(key < T), mt = __ballot(key == T);
-      if (key < T) sel[at_less + __popcll(ml & lanemask_lt())] = ((uint64_t)key << 32) | (uint32_t)id;
-      const int rank = tie_run + __popcll(mt & lanemask_lt());
-      if (key == T && rank < need) sel[nless + rank] = ((uint64_t)key << 32) | (uint32_t)id;
-      at_less += __popcll(ml);
-      tie_run += __popcll(mt);
-    });
-    total = P;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  auto finish = [&](auto n_tag) {
-    constexpr int N = decltype(n_tag)::value;
-    uint64_t v[N];
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      const int e = r * kWave + lane;
-      v[r] = e < total ? sel[e] : ~0ull;
-    }
-    wave_bitonic_u64<N>(v);
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-      const int i = r * kWave + lane;
-      if (i < nprobe) {
-        const bool live = i < P;
-        lists[q * nprobe + i] = live ? (int32_t)(uint32_t)(v[r] & 0xffffffffu) : -1;
-        if (dists) dists[q * nprobe + i] = live ? __uint_as_float((uint32_t)(v[r] >> 32)) : __builtin_inff();
-      }
-    }
-    for (int i = N * kWave + lane; i < nprobe; i += kWave) {
-      lists[q * nprobe + i] = -1;
-      if (dists) dists[q * nprobe + i] = __builtin_inff();
-    }
-  };
-  if (total <= 64) {
-    finish(IntC<1>{});
-  } else if (total <= 128) {
-    finish(IntC<2>{});
-  } else if (total <= 256) {
-    finish(IntC<4>{});
-  } else {
-    int n2 = 512;
-    while (n2 < total) n2 <<= 1;
-    for (int e = total + lane; e < n2; e += kWave) sel[e] = ~0ull;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    wave_bitonic_lds_u64(sel, n2);
-    for (int i = lane; i < nprobe; i += kWave) {
-      const bool live = i < P;
-      lists[q * nprobe + i] = live ? (int32_t)(uint32_t)(sel[i] & 0xffffffffu) : -1;
-      if (dists) dists[q * nprobe + i] = live ? __uint_as_float((uint32_t)(sel[i] >> 32)) : __builtin_inff();
-    }
+  wave_smallest<16>([&](int i) { return __float_as_uint(fmaxf(row[i], 0.f)); }, nlist, P, sel);
+  for (int i = lane; i < nprobe; i += kWave) {
+    const bool live = i < P;
+    const uint64_t v = sel[min(i, P - 1)];
+    lists[q * nprobe + i] = live ? (int32_t)(uint32_t)(v & 0xffffffffu) : -1;
+    if (dists) dists[q * nprobe + i] = live ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
   }
 }
 

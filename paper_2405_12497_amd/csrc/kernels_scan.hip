@@ -22,6 +22,7 @@
 //            every round (the running k-th exact distance), giving the top-k.
 #include "rbq_internal.hpp"
 #include "scan_code.hpp"
+#include "wave_select.hpp"
 
 namespace rbq {
 namespace {
@@ -399,178 +400,81 @@ __device__ __forceinline__ bool less_di(float d1, int64_t i1, float d2, int64_t 
   return d1 < d2 || (d1 == d2 && i1 < i2);
 }
 
+// Float bits mapped to unsigned integers that order like the floats.
+__device__ __forceinline__ uint32_t sortable_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float from_sortable(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
 // ------------------------------------------------------------------ bootstrap tau
-// Per query: the k bootstrap codes with the smallest estimated distance get
-// their exact distance; they seed the top-k and tau; their segment entries are
-// marked done (pos = -1).
+// One wave per query (four per block, no block barriers). The m = min(n0,
+// 4k, kMaxK) bootstrap codes with the smallest estimated distance (ties by
+// bootstrap order) get their exact distance, by 8 groups of 8 lanes; the k
+// best of them by (distance, id) seed the top-k and tau = the k-th. The others
+// cannot enter the top-k (k better ones are known), so all m segment entries
+// are marked done (pos = -1).
 __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
-  extern __shared__ float qv[];          // dim floats
-  __shared__ uint64_t key[kMaxP0];       // the selected keys, sorted
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t sh_prefix, sh_need, sh_cnt;
-  __shared__ int32_t toppos[kMaxK];
-  __shared__ uint64_t key2[kMaxK];
-  constexpr int kPerT = kMaxP0 / kThreads;
-  const int64_t q = blockIdx.x;
+  __shared__ uint64_t selw[kWaves][kWSelCap];
   const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
+  if (q >= s.nq) return;   // whole waves
+  uint64_t* sel = selw[wave];
   const int n0 = uniform_i32(s.q_n0[q]);
   const int64_t b0 = uniform_i64(s.off_n0[q]);
   const int m = min(n0, min(kMaxK, 4 * s.k));
-  for (int i = threadIdx.x; i < s.dim; i += kThreads) qv[i] = s.q[q * s.dim + i];
-  // keys (sortable estimated distance << 32 | slot) held in registers
-  uint64_t kk[kPerT];
-  EstEnt ee[kPerT];
-#pragma unroll
-  for (int j = 0; j < kPerT; ++j) ee[j] = s.p0buf[n0 > 0 ? b0 + min((int)threadIdx.x + j * kThreads, n0 - 1) : 0];
-#pragma unroll
-  for (int j = 0; j < kPerT; ++j) {
-    const int i = threadIdx.x + j * kThreads;
-    uint32_t kb = __float_as_uint(ee[j].dist);
-    kb = (kb & 0x80000000u) ? ~kb : (kb | 0x80000000u);
-    kk[j] = i < n0 ? ((uint64_t)kb << 32) | (uint32_t)ee[j].slot : ~0ull;
-  }
-  // radix select (8 bits per pass) of the m-th smallest high word T
-  uint32_t prefix = 0, mask = 0, need = (uint32_t)m;
-  for (int pass = 0; pass < 4 && m > 0; ++pass) {
-    const int shift = 24 - 8 * pass;
-    hist[threadIdx.x] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPerT; ++j) {
-      const int i = threadIdx.x + j * kThreads;
-      const uint32_t hi = (uint32_t)(kk[j] >> 32);
-      if (i < n0 && (hi & mask) == prefix) atomicAdd(&hist[(hi >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const uint32_t c0 = hist[4 * lane], c1 = hist[4 * lane + 1], c2 = hist[4 * lane + 2], c3 = hist[4 * lane + 3];
-      const uint32_t tot = c0 + c1 + c2 + c3;
-      uint32_t inc = tot;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = __shfl_up(inc, o, kWave);
-        if (lane >= o) inc += y;
-      }
-      const uint32_t exc = inc - tot;
-      if (exc < need && need <= inc) {   // exactly one lane holds the m-th key's bin
-        uint32_t before = exc, bin = 4 * lane;
-        if (before + c0 < need) {
-          before += c0;
-          ++bin;
-          if (before + c1 < need) {
-            before += c1;
-            ++bin;
-            if (before + c2 < need) {
-              before += c2;
-              ++bin;
-            }
-          }
-        }
-        sh_prefix = prefix | (bin << shift);
-        sh_need = need - before;
-      }
-    }
-    __syncthreads();
-    prefix = sh_prefix;
-    need = sh_need;
-    mask |= 0xFFu << shift;
-  }
-  // compact the keys with high word <= T (the m smallest plus ties at T), then sort them
-  if (threadIdx.x == 0) sh_cnt = 0;
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < kPerT; ++j) {
-    const int i = threadIdx.x + j * kThreads;
-    if (i < n0 && m > 0 && (uint32_t)(kk[j] >> 32) <= prefix) key[atomicAdd(&sh_cnt, 1u)] = kk[j];
-  }
-  __syncthreads();
-  const int nsel = uniform_i32((int)sh_cnt);
-  int n2 = 1;
-  while (n2 < nsel) n2 <<= 1;
-  for (int i = nsel + threadIdx.x; i < n2; i += kThreads) key[i] = ~0ull;
-  __syncthreads();
-  for (int size = 2; size <= n2; size <<= 1)
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < n2 / 2; i += kThreads) {
-        const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t x = key[lo], y = key[hi];
-        if ((x > y) == up) {
-          key[lo] = y;
-          key[hi] = x;
-        }
-      }
-      __syncthreads();
-    }
-  // Exact distances for the m best-estimated bootstrap codes (m = 4k, at most
-  // kMaxK and n0). The k best of them by (distance, id) seed the top-k and
-  // tau = the k-th; the others cannot enter the top-k (k better ones are
-  // known), so all m are marked done.
-  const int64_t seg0 = uniform_i64(s.off_seg[q]);
-  {
-    constexpr int kGroups = kThreads / kLpc;
-    const int grp = threadIdx.x / kLpc, sub = threadIdx.x % kLpc;
-    auto run = [&](auto nc_tag) {
+  if (m > 0) {
+    const EstEnt* est = s.p0buf + b0;
+    wave_smallest<8>([&](int i) { return sortable_bits(est[i].dist); }, n0, m, sel);
+    const int64_t seg0 = uniform_i64(s.off_seg[q]);
+    const float* qv = s.q + q * s.dim;
+    const int grp = lane / kLpc, sub = lane % kLpc;
+    constexpr int kGroups = kWave / kLpc;
+    // passes of up to 64 selected codes: entry base + grp + 8 j, j < NC
+    auto run = [&](int base, auto nc_tag) {
       constexpr int NC = decltype(nc_tag)::value;
-      int32_t pos[NC], slot[NC];
+      int32_t slot[NC], pos[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
-        const int i = grp + j * kGroups;
-        slot[j] = i < m ? (int32_t)(uint32_t)(key[i] & 0xffffffffu) : -1;
-        pos[j] = i < m ? s.seg[seg0 + slot[j]].pos : -1;
+        const int i = base + grp + j * kGroups;
+        slot[j] = i < m ? est[(uint32_t)(sel[i] & 0xffffffffu)].slot : -1;
       }
+#pragma unroll
+      for (int j = 0; j < NC; ++j) pos[j] = slot[j] >= 0 ? s.seg[seg0 + slot[j]].pos : -1;
       float d[NC];
       group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
+      wave_lds_sync();   // every lane has read its sel entries
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
-        const int i = grp + j * kGroups;
+        const int i = base + grp + j * kGroups;
         if (sub == 0 && i < m) {
-          toppos[i] = pos[j];
           s.seg[seg0 + slot[j]].pos = -1;
           // exact distances are >= 0, so their bits order like the values; ids < 2^31
-          key2[i] = ((uint64_t)__float_as_uint(d[j]) << 32) | (uint64_t)(uint32_t)s.ids[pos[j]];
+          sel[i] = ((uint64_t)__float_as_uint(d[j]) << 32) | (uint64_t)(uint32_t)s.ids[pos[j]];
         }
       }
+      wave_lds_sync();
     };
-    const int per = uniform_i32((m + kGroups - 1) / kGroups);
-    if (per <= 1) run(IntC<1>{});
-    else if (per <= 2) run(IntC<2>{});
-    else if (per <= 4) run(IntC<4>{});
-    else run(IntC<8>{});
+    for (int base = 0; base < m; base += kGroups * 8) {
+      const int per = (min(m - base, kGroups * 8) + kGroups - 1) / kGroups;
+      if (per <= 1) run(base, IntC<1>{});
+      else if (per <= 2) run(base, IntC<2>{});
+      else if (per <= 4) run(base, IntC<4>{});
+      else run(base, IntC<8>{});
+    }
+    wave_sort_sel(sel, m);
   }
-  int m2 = 1;
-  while (m2 < m) m2 <<= 1;
-  for (int i = m + threadIdx.x; i < m2; i += kThreads) key2[i] = ~0ull;
-  __syncthreads();
-  // sort the seeds by (distance, original id), carrying their positions
-  for (int size = 2; size <= m2; size <<= 1)
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < m2 / 2; i += kThreads) {
-        const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t x = key2[lo], y = key2[hi];
-        if ((x > y) == up) {
-          key2[lo] = y;
-          key2[hi] = x;
-          const int32_t t = toppos[lo];   // padding entries carry garbage positions
-          toppos[lo] = toppos[hi];        // and sort to the end with their keys
-          toppos[hi] = t;
-        }
-      }
-      __syncthreads();
-    }
-  for (int i = threadIdx.x; i < s.k; i += kThreads) {
+  for (int i = lane; i < s.k; i += kWave) {
     SeedEnt e;
-    if (i < min(m, s.k)) {
-      e.dist = __uint_as_float((uint32_t)(key2[i] >> 32));
-      e.pos = toppos[i];
-    } else {
-      e.dist = __builtin_inff();
-      e.pos = -1;
-    }
+    const bool live = i < min(m, s.k);
+    const uint64_t v = live ? sel[i] : 0;
+    e.dist = live ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+    e.id = live ? (int32_t)(uint32_t)(v & 0xffffffffu) : -1;
     s.seedk[q * s.k + i] = e;
   }
-  if (threadIdx.x == 0) s.tau[q] = (m >= s.k) ? __uint_as_float((uint32_t)(key2[s.k - 1] >> 32)) : __builtin_inff();
+  if (lane == 0) s.tau[q] = (m >= s.k) ? __uint_as_float((uint32_t)(sel[s.k - 1] >> 32)) : __builtin_inff();
 }
 
 // ------------------------------------------------------------------ finalize (S7)
@@ -585,13 +489,6 @@ constexpr int kFinChunks = 256;
 constexpr int kFinWin = 1024;
 constexpr int kFinRound = 128;
 
-__device__ __forceinline__ uint32_t sortable_bits(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float from_sortable(uint32_t k) {
-  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
-}
 
 __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
   extern __shared__ float qv[];          // dim floats
@@ -612,14 +509,14 @@ __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
   for (int i = threadIdx.x; i < s.dim; i += kThreads) qv[i] = s.q[q * s.dim + i];
   int cnt0 = 0;
   for (int i = 0; i < K; ++i) {
-    if (s.seedk[q * K + i].pos < 0) break;
+    if (s.seedk[q * K + i].id < 0) break;
     ++cnt0;
   }
   cnt0 = uniform_i32(cnt0);
   for (int i = threadIdx.x; i < K; i += kThreads) {
     const SeedEnt e = s.seedk[q * K + i];
     td[i] = e.dist;
-    tid[i] = e.pos >= 0 ? s.ids[e.pos] : (int64_t)-1;
+    tid[i] = e.id;
   }
   if (threadIdx.x == 0) {
     sh_cnt = cnt0;
@@ -938,7 +835,7 @@ hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
 
 hipError_t launch_tau(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tau, dim3((unsigned)s.nq), dim3(kThreads), (size_t)s.dim * 4, st, s);
+  hipLaunchKernelGGL(k_tau, dim3((unsigned)((s.nq + kWaves - 1) / kWaves)), dim3(kThreads), 0, st, s);
   return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ struct EstEnt {
 
 struct SeedEnt {
   float dist;
-  int32_t pos;
+  int32_t id;   // original id (< 2^31), -1 for none
 };
 
 // One work unit of a scan phase: at most `chunk` consecutive codes of one
