@@ -478,255 +478,223 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
 }
 
 // ------------------------------------------------------------------ finalize (S7)
-// One block per query. The top-k starts from the bootstrap seeds (tau = their
-// k-th exact distance). The query's candidates are gathered in windows of up
-// to kFinWin entries, sorted by lower bound, and reranked in ascending-bound
-// rounds: a candidate is dropped when its bound exceeds tau (and, the window
-// being sorted, so is the rest of the window); the others get their exact
-// distance (groups of lanes per candidate), the round is merged into the
-// top-k by parallel ranking, and tau drops to the running k-th exact distance.
-constexpr int kFinChunks = 256;
-constexpr int kFinWin = 1024;
-constexpr int kFinRound = 128;
+// One wave per query (four per block, no block barriers). The top-k starts
+// from the bootstrap seeds (tau = their k-th exact distance). The query's live
+// candidate entries with bound <= tau are gathered chunk by chunk into a window
+// of kFinWin entries, and a window is reranked in rounds: a round takes the
+// entries whose bound is at or below a cut read from a sorted sample of the
+// window's bounds (about 64 of them; all when at most 64 are left), computes
+// their exact distances (groups of 8 lanes: the routine every exact distance
+// uses), merges them into the top-k and lowers tau to the k-th exact distance.
+// The window keeps only the entries above the cut whose bound is still <= tau.
+// Top-k entries are (distance bits << 32 | id) keys: distances are >= 0 and
+// ids < 2^31, so the keys order by (distance, id).
+constexpr int kFinWin = 512;
+constexpr int kFinRoundMax = 128;
 
+__device__ __forceinline__ int fin_lds_words(int k) { return kFinWin + kFinRoundMax + k; }
 
 __global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
-  extern __shared__ float qv[];          // dim floats
-  __shared__ float td[kMaxK];
-  __shared__ int64_t tid[kMaxK];
-  __shared__ int64_t cbase[kFinChunks];
-  __shared__ int32_t cpre[kFinChunks + 1];
-  __shared__ int32_t part[kThreads];
-  __shared__ uint64_t win[kFinWin];      // (sortable lb << 32) | position
-  __shared__ float cd[kFinRound];
-  __shared__ int64_t cid[kFinRound];
-  __shared__ int32_t wcnt[kWaves];
-  __shared__ int sh_cnt;
-  __shared__ float sh_tau;
-  const int64_t q = blockIdx.x;
+  extern __shared__ uint64_t fin_lds[];
   const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
+  if (q >= s.nq) return;   // whole waves
   const int K = s.k;
-  for (int i = threadIdx.x; i < s.dim; i += kThreads) qv[i] = s.q[q * s.dim + i];
-  int cnt0 = 0;
-  for (int i = 0; i < K; ++i) {
-    if (s.seedk[q * K + i].id < 0) break;
-    ++cnt0;
+  uint64_t* win = fin_lds + (size_t)wave * fin_lds_words(K);
+  uint64_t* rnd = win + kFinWin;
+  uint64_t* top = rnd + kFinRoundMax;
+  // seeds: the valid ones first, in (distance, id) order
+  int cnt = 0;
+  for (int i0 = 0; i0 < K; i0 += kWave) {
+    const int i = i0 + lane;
+    const SeedEnt e = s.seedk[q * K + min(i, K - 1)];
+    const bool v = i < K && e.id >= 0;
+    if (i < K) top[i] = v ? ((uint64_t)__float_as_uint(e.dist) << 32) | (uint32_t)e.id : ~0ull;
+    cnt += __popcll(__ballot(v));
   }
-  cnt0 = uniform_i32(cnt0);
-  for (int i = threadIdx.x; i < K; i += kThreads) {
-    const SeedEnt e = s.seedk[q * K + i];
-    td[i] = e.dist;
-    tid[i] = e.id;
-  }
-  if (threadIdx.x == 0) {
-    sh_cnt = cnt0;
-    sh_tau = (cnt0 == K) ? s.seedk[q * K + K - 1].dist : __builtin_inff();
-  }
-  __syncthreads();
-  constexpr int ngroups = kThreads / kLpc;
-  const int grp = threadIdx.x / kLpc, sub = threadIdx.x % kLpc;
-  int reranked = cnt0;
-  int ncand_total = 0;
+  wave_lds_sync();
+  float tau = uniform_f32(cnt == K ? __uint_as_float((uint32_t)(top[K - 1] >> 32)) : __builtin_inff());
+  int reranked = cnt, ncand = 0, nk = 0;
+  const float* qv = s.q + q * s.dim;
+  const int grp = lane / kLpc, sub = lane % kLpc;
+  constexpr int kGroups = kWave / kLpc;
+
+  // rnd[0..n): (distance << 32 | id) of a round. Entries below the current
+  // k-th (all of them while fewer than K are known) are compacted to the
+  // front; each element of the union of top and those takes its rank: a top
+  // element its index plus the entrants below it, an entrant the top elements
+  // below it (binary search) plus the entrants below it.
+  auto merge = [&](int n) {
+    const uint64_t kth = cnt == K ? top[K - 1] : ~0ull;
+    int m = 0;
+    for (int i0 = 0; i0 < n; i0 += kWave) {
+      const int i = i0 + lane;
+      const uint64_t x = rnd[min(i, n - 1)];
+      const bool in = i < n && x < kth;
+      const uint64_t b = __ballot(in);
+      if (in) rnd[m + __popcll(b & lanemask_lt())] = x;
+      m += __popcll(b);
+    }
+    if (m == 0) return;
+    wave_lds_sync();
+    constexpr int kPer = (kMaxK + kFinRoundMax + kWave - 1) / kWave;
+    const int mtot = cnt + m;
+    uint64_t ev[kPer];
+    int er[kPer];
+#pragma unroll
+    for (int h = 0; h < kPer; ++h) {
+      const int e = lane + h * kWave;
+      er[h] = K;
+      ev[h] = ~0ull;
+      if (e < mtot) {
+        const bool t = e < cnt;
+        ev[h] = t ? top[e] : rnd[e - cnt];
+        int r = e;
+        if (!t) {
+          int lo = 0, hi = cnt;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (top[mid] < ev[h]) lo = mid + 1; else hi = mid;
+          }
+          r = lo;
+        }
+        for (int u = 0; u < m; ++u) r += rnd[u] < ev[h];
+        er[h] = r;
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int h = 0; h < kPer; ++h)
+      if (er[h] < K) top[er[h]] = ev[h];
+    cnt = min(mtot, K);
+    wave_lds_sync();
+    if (cnt == K) tau = uniform_f32(fminf(tau, __uint_as_float((uint32_t)(top[K - 1] >> 32))));
+  };
+
+  // exact distances of rnd[0..n) ((sortable bound << 32 | position) entries),
+  // in passes of 64: entry base + grp + 8 j, j < NC; each entry becomes
+  // (distance << 32 | id)
+  auto rerank = [&](int n) {
+    auto pass = [&](int base, auto nc_tag) {
+      constexpr int NC = decltype(nc_tag)::value;
+      int32_t pos[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int i = base + grp + j * kGroups;
+        pos[j] = i < n ? (int32_t)(uint32_t)(rnd[i] & 0xffffffffu) : -1;
+      }
+      float d[NC];
+      group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
+      wave_lds_sync();   // every lane has read its entries
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int i = base + grp + j * kGroups;
+        if (sub == 0 && i < n) rnd[i] = ((uint64_t)__float_as_uint(d[j]) << 32) | (uint32_t)s.ids[pos[j]];
+      }
+      wave_lds_sync();
+    };
+    for (int base = 0; base < n; base += kGroups * 8) {
+      const int per = (min(n - base, kGroups * 8) + kGroups - 1) / kGroups;
+      if (per <= 1) pass(base, IntC<1>{});
+      else if (per <= 2) pass(base, IntC<2>{});
+      else if (per <= 4) pass(base, IntC<4>{});
+      else pass(base, IntC<8>{});
+    }
+  };
+
+  auto process_window = [&]() {
+    while (nk > 0) {
+      uint32_t cut = 0xFFFFFFFFu;
+      if (nk > kWave) {
+        uint32_t sv[1] = {(uint32_t)(win[(int)(((int64_t)lane * nk) >> 6)] >> 32)};
+        wave_bitonic<1>(sv);
+        const int sidx = max(0, kWave * kWave / nk - 1);   // about (sidx + 1) nk / 64 entries <= cut
+        cut = (uint32_t)__builtin_amdgcn_readlane((int)sv[0], sidx);
+      }
+      // entries with bound <= tau: those <= cut to the round (at most
+      // kFinRoundMax; the rest stay), the others stay in the window
+      const uint32_t tkey = sortable_bits(tau);
+      int nr = 0, keep = 0;
+      for (int i0 = 0; i0 < nk; i0 += kWave) {
+        const int i = i0 + lane;
+        const uint64_t x = win[min(i, nk - 1)];
+        const uint32_t k = (uint32_t)(x >> 32);
+        const bool live = i < nk && k <= tkey;
+        const bool to_r = live && k <= cut;
+        const uint64_t br = __ballot(to_r);
+        const int ar = nr + __popcll(br & lanemask_lt());
+        const bool take = to_r && ar < kFinRoundMax;
+        const bool stay = live && !take;
+        const uint64_t bs = __ballot(stay);
+        if (take) rnd[ar] = x;
+        if (stay) win[keep + __popcll(bs & lanemask_lt())] = x;
+        nr = min(nr + __popcll(br), kFinRoundMax);
+        keep += __popcll(bs);
+      }
+      nk = keep;
+      if (nr == 0) break;   // no live entry at or below the cut: none is live at all
+      wave_lds_sync();
+      reranked += nr;
+      rerank(nr);
+      merge(nr);
+    }
+    nk = 0;
+  };
+
+  // gather: chunks in groups of 64 (lane j: chunk j0 + j), entries by a
+  // shuffle scan of the chunk counts
   const int nch = uniform_i32(s.q_nch[q]);
   const int p0 = uniform_i32(s.q_p0[q]);
   const int64_t off0 = uniform_i64(s.off_p0[q]), off1 = uniform_i64(s.off_p1[q]);
   const int64_t ch0 = uniform_i64(s.off_ch[q]);
-  for (int j0 = 0; j0 < nch; j0 += kFinChunks) {
-    const int nj = min(kFinChunks, nch - j0);
-    // chunk bases and counts of this chunk window, then an exclusive prefix of the counts
-    const int per = (nj + kThreads - 1) / kThreads;
-    int run = 0;
-    for (int t = threadIdx.x * per; t < min(nj, (int)(threadIdx.x + 1) * per); ++t) {
-      const int j = j0 + t;
-      cbase[t] = j < p0 ? s.units0[off0 + j].seg : s.units1[off1 + (j - p0)].seg;
-      cpre[t] = run;
-      run += s.seg_count[ch0 + j];
+  for (int j0 = 0; j0 < nch; j0 += kWave) {
+    const int j = j0 + lane;
+    int64_t base = 0;
+    int cj = 0;
+    if (j < nch) {
+      base = j < p0 ? s.units0[off0 + j].seg : s.units1[off1 + (j - p0)].seg;
+      cj = s.seg_count[ch0 + j];
     }
-    part[threadIdx.x] = run;
-    __syncthreads();
-    for (int o = 1; o < kThreads; o <<= 1) {
-      const int v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
-      __syncthreads();
-      part[threadIdx.x] += v;
-      __syncthreads();
+    int incl = cj;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
     }
-    const int before = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
-    for (int t = threadIdx.x * per; t < min(nj, (int)(threadIdx.x + 1) * per); ++t) cpre[t] += before;
-    if (threadIdx.x == kThreads - 1) cpre[nj] = part[kThreads - 1];
-    __syncthreads();
-    const int T = uniform_i32(cpre[nj]);
-    ncand_total += T;
-    for (int w0 = 0; w0 < T; w0 += kFinWin) {
-      const int nw = min(kFinWin, T - w0);
-      // gather the window: live entries whose bound does not exceed tau
-      const float tau0 = uniform_f32(sh_tau);
-      int nk = 0;
-      for (int e0 = 0; e0 < nw; e0 += kThreads) {
-        const int e = w0 + e0 + threadIdx.x;
-        const int ec = e < w0 + nw ? e : w0 + nw - 1;   // lanes past the end re-read the last entry
-        int lo = 0, hi = nj;                             // last chunk with cpre <= ec
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (cpre[mid] <= ec) lo = mid; else hi = mid;
-        }
-        const Cand cand = s.seg[cbase[lo] + (ec - cpre[lo])];
-        const bool keep = e < w0 + nw && cand.pos >= 0 && cand.lb <= tau0;
-        const uint64_t m = __ballot(keep);
-        if (lane == 0) wcnt[wave] = __popcll(m);
-        __syncthreads();
-        int at = nk;
-        for (int w = 0; w < wave; ++w) at += wcnt[w];
-        if (keep) win[at + __popcll(m & lanemask_lt())] = ((uint64_t)sortable_bits(cand.lb) << 32) | (uint32_t)cand.pos;
-        nk = uniform_i32(nk + wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
-        __syncthreads();
+    const int pre = incl - cj;
+    const int Tg = __builtin_amdgcn_readlane(incl, kWave - 1);
+    ncand += Tg;
+    const int64_t base0 = uniform_i64(base);   // chunk j0 (Tg > 0 implies it exists)
+    int ccur = 0;
+    for (int e0 = 0; e0 < Tg; e0 += kWave) {
+      if (nk + kWave > kFinWin) process_window();
+      const int idx = e0 + lane;
+      int myc = ccur;
+      for (int c = ccur + 1; c < kWave; ++c) {   // chunks starting inside this batch
+        const int pc = __builtin_amdgcn_readlane(pre, c);
+        if (pc > e0 + kWave - 1) break;
+        if (idx >= pc) myc = c;
       }
-      if (nk == 0) continue;
-      int n2 = 1;
-      while (n2 < nk) n2 <<= 1;
-      for (int i = nk + threadIdx.x; i < n2; i += kThreads) win[i] = ~0ull;
-      __syncthreads();
-      for (int size = 2; size <= n2; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          for (int i = threadIdx.x; i < n2 / 2; i += kThreads) {
-            const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
-            const bool up = (lo & size) == 0;
-            const uint64_t x = win[lo], y = win[hi];
-            if ((x > y) == up) {
-              win[lo] = y;
-              win[hi] = x;
-            }
-          }
-          __syncthreads();
-        }
-      // ascending-bound rounds
-      for (int r0 = 0; r0 < nk; r0 += kFinRound) {
-        const float tau = uniform_f32(sh_tau);
-        const float lb0 = uniform_f32(from_sortable((uint32_t)(win[r0] >> 32)));
-        if (lb0 > tau) break;   // sorted: the rest of the window is above tau too
-        const int rn = min(kFinRound, nk - r0);
-        int n = 0;                         // prefix of the round with bound <= tau
-        {
-          int lo = 0, hi = rn;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (from_sortable((uint32_t)(win[r0 + mid] >> 32)) <= tau) lo = mid + 1; else hi = mid;
-          }
-          n = uniform_i32(lo);
-        }
-        {
-          // exact distances of the round's n candidates: 32 groups of 8 lanes,
-          // up to 4 candidates per group with their loads in flight together
-          auto run = [&](auto nc_tag) {
-            constexpr int NC = decltype(nc_tag)::value;
-            int32_t pos[NC];
-#pragma unroll
-            for (int j = 0; j < NC; ++j) {
-              const int i = grp + j * ngroups;
-              pos[j] = i < n ? (int32_t)(uint32_t)(win[r0 + i] & 0xffffffffu) : -1;
-            }
-            float d[NC];
-            group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
-#pragma unroll
-            for (int j = 0; j < NC; ++j) {
-              const int i = grp + j * ngroups;
-              if (sub == 0 && i < n) {
-                cd[i] = d[j];
-                cid[i] = s.ids[pos[j]];
-              }
-            }
-          };
-          static_assert(kFinRound <= 4 * ngroups, "a round is at most 4 candidates per group");
-          const int per = (n + ngroups - 1) / ngroups;
-          if (per <= 1) run(IntC<1>{});
-          else if (per <= 2) run(IntC<2>{});
-          else run(IntC<4>{});
-        }
-        __syncthreads();
-        if (wave == 0) {
-          // merge the round into the top-k (sorted by (distance, id), ids
-          // distinct): only round entries below the current k-th can enter
-          // (all of them while fewer than K are known). They are compacted to
-          // the front of cd/cid; each element of the union then takes its rank:
-          // a top-k element its index plus the entrants below it, an entrant
-          // the top-k elements below it (binary search) plus the entrants below
-          // it. Every value is read before any is written.
-          const int cnt = uniform_i32(sh_cnt);
-          const bool full = cnt == K;
-          const float kd = full ? td[K - 1] : 0.f;
-          const int64_t kid = full ? tid[K - 1] : 0;
-          int m = 0;
-          for (int i0 = 0; i0 < n; i0 += kWave) {
-            const int i = i0 + lane;
-            const float d = i < n ? cd[i] : 0.f;
-            const int64_t id = i < n ? cid[i] : 0;
-            const bool in = i < n && (!full || less_di(d, id, kd, kid));
-            const uint64_t b = __ballot(in);
-            if (in) {
-              const int at = m + __popcll(b & lanemask_lt());
-              cd[at] = d;
-              cid[at] = id;
-            }
-            m += __popcll(b);
-          }
-          if (m > 0) {
-            constexpr int kPerLane = (kMaxK + kFinRound + kWave - 1) / kWave;
-            const int mtot = cnt + m;
-            float ed[kPerLane];
-            int64_t eid[kPerLane];
-            int er[kPerLane];
-#pragma unroll
-            for (int h = 0; h < kPerLane; ++h) {
-              const int e = lane + h * kWave;
-              er[h] = K;
-              if (e < mtot) {
-                const bool top = e < cnt;
-                ed[h] = top ? td[e] : cd[e - cnt];
-                eid[h] = top ? tid[e] : cid[e - cnt];
-                int r = 0;
-                if (top) {
-                  r = e;
-                } else {
-                  int lo = 0, hi = cnt;   // top-k elements below the entrant
-                  while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (less_di(td[mid], tid[mid], ed[h], eid[h])) lo = mid + 1; else hi = mid;
-                  }
-                  r = lo;
-                }
-                for (int t = 0; t < m; ++t) r += less_di(cd[t], cid[t], ed[h], eid[h]);
-                er[h] = r;
-              }
-            }
-#pragma unroll
-            for (int h = 0; h < kPerLane; ++h) {
-              if (er[h] < K) {
-                td[er[h]] = ed[h];
-                tid[er[h]] = eid[h];
-              }
-            }
-            if (lane == 0) {
-              const int c2 = min(mtot, K);
-              sh_cnt = c2;
-              if (c2 == K) sh_tau = fminf(sh_tau, td[K - 1]);
-            }
-          }
-        }
-        __syncthreads();
-        reranked += n;
-        __syncthreads();
-      }
-      __syncthreads();
+      const int64_t mybase = __shfl(base, myc, kWave);
+      const int mypre = __shfl(pre, myc, kWave);
+      const Cand cand = s.seg[idx < Tg ? mybase + (idx - mypre) : base0];
+      const bool keep = idx < Tg && cand.pos >= 0 && cand.lb <= tau;
+      const uint64_t b = __ballot(keep);
+      if (keep) win[nk + __popcll(b & lanemask_lt())] = ((uint64_t)sortable_bits(cand.lb) << 32) | (uint32_t)cand.pos;
+      nk += __popcll(b);
+      ccur = __builtin_amdgcn_readlane(myc, kWave - 1);
     }
-    __syncthreads();
   }
-  const int cnt = uniform_i32(sh_cnt);
-  for (int i = threadIdx.x; i < K; i += kThreads) {
-    s.out_ids[q * K + i] = i < cnt ? tid[i] : (int64_t)-1;
-    s.out_d[q * K + i] = i < cnt ? td[i] : __builtin_inff();
+  process_window();
+  for (int i = lane; i < K; i += kWave) {
+    const uint64_t v = top[i];
+    const bool live = i < cnt;
+    s.out_ids[q * K + i] = live ? (int64_t)(uint32_t)(v & 0xffffffffu) : (int64_t)-1;
+    s.out_d[q * K + i] = live ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     s.q_rerank[q] = reranked;
-    s.q_cand[q] = ncand_total;
+    s.q_cand[q] = ncand;
   }
 }
 
@@ -841,7 +809,8 @@ hipError_t launch_tau(const SearchDev& s, hipStream_t st) {
 
 hipError_t launch_finalize(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)s.nq), dim3(kThreads), (size_t)s.dim * 4, st, s);
+  const size_t shm = (size_t)kWaves * (kFinWin + kFinRoundMax + s.k) * sizeof(uint64_t);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((s.nq + kWaves - 1) / kWaves)), dim3(kThreads), shm, st, s);
   return hipGetLastError();
 }
 
