@@ -168,6 +168,143 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
   }
 }
 
+// Row-local (16-lane DPP row) integer reductions; every lane of the row gets
+// the result.
+__device__ __forceinline__ uint32_t row_or_u32(uint32_t v) {
+  int x = (int)v;
+  x |= dpp_i32<kDppXor1>(x);
+  x |= dpp_i32<kDppXor2>(x);
+  x |= dpp_i32<kDppHalfMirror>(x);
+  x |= dpp_i32<kDppMirror>(x);
+  return (uint32_t)x;
+}
+__device__ __forceinline__ int row_sum_i32(int x) {
+  x += dpp_i32<kDppXor1>(x);
+  x += dpp_i32<kDppXor2>(x);
+  x += dpp_i32<kDppHalfMirror>(x);
+  x += dpp_i32<kDppMirror>(x);
+  return x;
+}
+__device__ __forceinline__ float row_sum_f32(float v) {
+  return row_reduce(v, [](float a, float b) { return a + b; });
+}
+
+// Quarter-wave form of the same per-pair quantisation for W <= 4 (D <= 256):
+// the 16 lanes of a DPP row own one pair (lane l of the row holds coordinates
+// 64 t + l + 16 j, j < 4, of every word t), so a pair's reductions are four
+// row-local DPP steps, its plane words are row-local ORs, and one wave
+// quantises four pairs at once. The per-coordinate arithmetic (residual,
+// scale, randomized rounding) is that of k_prep_reg; only the summation
+// order of ||r||^2 differs. Every lane stays active around the DPP steps:
+// per-row conditions are applied as values, not branches.
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_prep_q(SearchDev s) {
+  const int lane = lane_id(), row = lane >> 4, l = lane & 15;
+  const int64_t npairs = s.nq * s.nprobe;
+  const int64_t g0 = uniform_i64(((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * 4);
+  if (g0 >= npairs) return;   // whole waves
+  const int64_t g = g0 + row;
+  const bool valid = g < npairs;
+  const int64_t gc = min(g, npairs - 1);
+  const int64_t q = gc / s.nprobe;
+  const int r = (int)(gc - q * s.nprobe);
+  const int npq = s.nprobe_q ? s.nprobe_q[q] : s.nprobe;
+  const int pl_raw = s.probe[gc];
+  const int P = min(max(npq, 1), s.nprobe);
+  const int list = (valid && r < P) ? pl_raw : -1;
+  const bool act = list >= 0;
+  const float* qrot = s.qrot + q * s.dp;
+  const float* crot = s.crot + (int64_t)max(list, 0) * s.dp;
+  const float cn = s.cnorm[max(list, 0)];
+  float rv[W][4];
+  float rmin = __builtin_inff(), rmax = -__builtin_inff(), ss = 0.f, qq = 0.f;
+#pragma unroll
+  for (int t = 0; t < W; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = t * kWave + l + 16 * j;
+      const float x = qrot[i];
+      rv[t][j] = x - crot[i];
+      ss = fmaf(rv[t][j], rv[t][j], ss);
+      qq = fmaf(x, x, qq);
+      rmin = fminf(rmin, rv[t][j]);
+      rmax = fmaxf(rmax, rv[t][j]);
+    }
+  ss = row_sum_f32(ss);
+  qq = row_sum_f32(qq);
+  rmin = row_reduce(rmin, [](float a, float b) { return fminf(a, b); });
+  rmax = row_reduce(rmax, [](float a, float b) { return fmaxf(a, b); });
+  float b = sqrtf(ss);
+  // near a centroid: b from the raw vectors (see k_prep_reg)
+  const bool degen = act && b <= 1e-4f * (sqrtf(qq) + sqrtf(cn));
+  if (__ballot(degen)) {
+    float acc = 0.f;
+    if (degen) {
+      const float* qr = s.q + q * s.dim;
+      const float* c = s.cent + (int64_t)list * s.dim;
+      for (int i = l; i < s.dim; i += 16) {
+        const float d = qr[i] - c[i];
+        acc = fmaf(d, d, acc);
+      }
+    }
+    acc = row_sum_f32(acc);
+    if (degen) b = sqrtf(acc);
+  }
+  const float range = rmax - rmin;
+  const bool live = act && (b > 0.f) && (range > 0.f);
+  const float scale = live ? 15.f / range : 0.f;
+  const uint64_t qid = (uint64_t)(s.qid_base + q);
+  int8_t* q8 = (s.qu8 && act) ? s.qu8 + g * s.dp : nullptr;
+  int sq = 0;
+  uint64_t myword = 0;   // lane l < 4 W of the row: plane word l (= plane jb * W + word t)
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    int qu[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = t * kWave + l + 16 * j;
+      const float x = (rv[t][j] - rmin) * scale;
+      qu[j] = live ? min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)max(list, 0), (uint32_t)i))) : 0;
+      sq += qu[j];
+      if (q8) q8[i] = (int8_t)qu[j];
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const uint32_t lo = (((uint32_t)qu[0] >> jb) & 1u) << l | (((uint32_t)qu[1] >> jb) & 1u) << (l + 16);
+      const uint32_t hi = (((uint32_t)qu[2] >> jb) & 1u) << l | (((uint32_t)qu[3] >> jb) & 1u) << (l + 16);
+      const uint64_t w = ((uint64_t)row_or_u32(hi) << 32) | row_or_u32(lo);
+      if (l == jb * W + t) myword = w;
+    }
+  }
+  sq = row_sum_i32(sq);
+  if (act && l < 4 * W) s.planes[g * 4 * W + l] = myword;
+  if (valid && l == 0) {
+    PairRec rec;
+    if (!act) {
+      rec.k1 = rec.k2 = rec.k0 = rec.b = rec.vl = rec.delta = 0.f;
+      rec.sq = 0;
+      rec.list = -1;
+    } else {
+      // <x_bar, q_bar> = (2 Delta/sqrt D) ip + (2 v_l/sqrt D) pc - (Delta/sqrt D) sq - sqrt(D) v_l
+      const double rd = sqrt((double)s.dp);
+      double vl = 0.0, delta = 0.0;
+      if (b > 0.f) {
+        vl = (double)rmin / (double)b;
+        delta = (double)range / (15.0 * (double)b);
+      }
+      rec.k1 = (float)(2.0 * delta / rd);
+      rec.k2 = (float)(2.0 * vl / rd);
+      rec.k0 = (float)(-(delta / rd) * (double)sq - rd * vl);
+      rec.b = b;
+      rec.vl = (float)vl;
+      rec.delta = (float)delta;
+      rec.sq = sq;
+      rec.list = list;
+    }
+    s.pairs[g] = rec;
+  }
+}
+
 // ------------------------------------------------------------------ planning
 // One wave per query: chunk and code prefixes over its probed pairs (64 ranks
 // per step, shuffle scans), and the bootstrap: whole chunks in probe order up
@@ -773,10 +910,10 @@ hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st) {
   auto grid = [&](int ppw) { return dim3((unsigned)((npairs + ppw * kWaves - 1) / (ppw * kWaves))); };
   if (s.W <= 0 || s.W > 64) return hipErrorInvalidValue;
   switch (s.W) {
-    case 1: hipLaunchKernelGGL((k_prep_reg<1, 4>), grid(4), dim3(kThreads), 0, st, s); break;
-    case 2: hipLaunchKernelGGL((k_prep_reg<2, 4>), grid(4), dim3(kThreads), 0, st, s); break;
-    case 3: hipLaunchKernelGGL((k_prep_reg<3, 4>), grid(4), dim3(kThreads), 0, st, s); break;
-    case 4: hipLaunchKernelGGL((k_prep_reg<4, 4>), grid(4), dim3(kThreads), 0, st, s); break;
+    case 1: hipLaunchKernelGGL((k_prep_q<1>), grid(4), dim3(kThreads), 0, st, s); break;
+    case 2: hipLaunchKernelGGL((k_prep_q<2>), grid(4), dim3(kThreads), 0, st, s); break;
+    case 3: hipLaunchKernelGGL((k_prep_q<3>), grid(4), dim3(kThreads), 0, st, s); break;
+    case 4: hipLaunchKernelGGL((k_prep_q<4>), grid(4), dim3(kThreads), 0, st, s); break;
     default:
       if (s.W <= 8) {
         hipLaunchKernelGGL((k_prep_reg<8, 2>), grid(2), dim3(kThreads), 0, st, s);
