@@ -32,8 +32,8 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
                                                        const float* __restrict__ bn) {
   constexpr int BT = 32 * WT;        // block tile (rows and columns)
   constexpr int NLD = BT * 4 / 256;  // float4 loads per thread per operand and K step
-  __shared__ __attribute__((aligned(16))) float As[BT][MKP];
-  __shared__ __attribute__((aligned(16))) float Bs[MKS][BT + 16];
+  __shared__ __attribute__((aligned(16))) float As[2][BT][MKP];
+  __shared__ __attribute__((aligned(16))) float Bs[2][MKS][BT + 16];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t m0 = (int64_t)blockIdx.x * BT;
   const int n0 = blockIdx.y * BT;
@@ -108,34 +108,41 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
       rb[u] = v;
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
       const int f = tid + 256 * u;
-      *reinterpret_cast<float4*>(&As[f >> 2][(f & 3) * 4]) = ra[u];
-      *reinterpret_cast<float4*>(&Bs[f / (BT / 4)][(f % (BT / 4)) * 4]) = rb[u];
+      *reinterpret_cast<float4*>(&As[buf][f >> 2][(f & 3) * 4]) = ra[u];
+      *reinterpret_cast<float4*>(&Bs[buf][f / (BT / 4)][(f % (BT / 4)) * 4]) = rb[u];
     }
   };
+  // double-buffered K steps: the next step's global loads are in flight
+  // during this step's MFMAs and land in the other LDS buffer; one barrier
+  // per step
   fetch(0);
+  stash(0);
+  __syncthreads();
   const int fr = lane & 15, fg = lane >> 4;
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += MKS) {
-    stash();
-    __syncthreads();
-    if (k0 + MKS < K) fetch(k0 + MKS);   // next step's operands in flight during this one
+    const bool more = k0 + MKS < K;
+    if (more) fetch(k0 + MKS);
 #pragma unroll
     for (int ss = 0; ss < 4; ++ss) {
       float a[WT], b[WT];
 #pragma unroll
-      for (int i = 0; i < WT; ++i) a[i] = As[wm + i * 16 + fr][4 * ss + fg];
+      for (int i = 0; i < WT; ++i) a[i] = As[buf][wm + i * 16 + fr][4 * ss + fg];
 #pragma unroll
-      for (int j = 0; j < WT; ++j) b[j] = Bs[4 * ss + fg][wn + j * 16 + fr];
+      for (int j = 0; j < WT; ++j) b[j] = Bs[buf][4 * ss + fg][wn + j * 16 + fr];
 #pragma unroll
       for (int i = 0; i < WT; ++i)
 #pragma unroll
         for (int j = 0; j < WT; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   // output block (i, j): lane holds rows 4 (lane / 16) + e, column lane % 16
   const int oc = lane & 15, orow = (lane >> 4) * 4;

@@ -367,78 +367,122 @@ __global__ __launch_bounds__(kThreads) void k_plan(SearchDev s) {
   }
 }
 
-// Exclusive prefix sums over queries (single block) and work-counter reset.
-// Tiles of 4096 queries: thread t reads queries 4t..4t+3 of the tile (adjacent
-// threads read adjacent words); each of the five sums is scanned in turn
-// (shuffle scan in each wave, then the 16 wave totals), with its carry across
-// tiles in LDS.
-__global__ __launch_bounds__(1024) void k_offsets(SearchDev s) {
-  constexpr int kT = 1024, kNW = kT / kWave, kPer = 4;
-  __shared__ int64_t wtot[kNW];
-  __shared__ int64_t carry[5];
+// Exclusive prefix sums over queries of five per-query counts (chunks,
+// bootstrap chunks, other chunks, codes, bootstrap codes), in two launches
+// over blocks of kOffQ queries (thread t: queries 4t..4t+3 of the block):
+// k_offsets_sum writes each block's five sums; k_offsets_scan adds the sums
+// of the blocks before it and scans its own queries (shuffle scan in each
+// wave, then the four wave totals).
+constexpr int kOffThreads = kOffQ / 4;
+
+__device__ __forceinline__ void off_counts(const SearchDev& s, int64_t q, int64_t (&v)[5]) {
+  const bool in = q < s.nq;
+  const int64_t nch = in ? s.q_nch[q] : 0, p0 = in ? s.q_p0[q] : 0;
+  v[0] = nch;
+  v[1] = p0;
+  v[2] = nch - p0;
+  v[3] = in ? s.q_ncode[q] : 0;
+  v[4] = in ? s.q_n0[q] : 0;
+}
+
+__device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__global__ __launch_bounds__(kOffThreads) void k_offsets_sum(SearchDev s) {
+  __shared__ int64_t wtot[kOffThreads / kWave][5];
   const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-  if (t == 0) {
+  if (blockIdx.x == 0 && t == 0) {
     s.counters[0] = 0;
     s.counters[1] = 0;
   }
-  if (t < 5) carry[t] = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < s.nq; base += kT * kPer) {
-    const int64_t q0 = base + (int64_t)t * kPer;
-    int32_t nch[kPer], p0[kPer], ncode[kPer], n0[kPer];
+  const int64_t q0 = (int64_t)blockIdx.x * kOffQ + (int64_t)t * 4;
+  int64_t sum[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int64_t q = q0 + u;
-      const bool in = q < s.nq;
-      nch[u] = in ? s.q_nch[q] : 0;
-      p0[u] = in ? s.q_p0[q] : 0;
-      ncode[u] = in ? s.q_ncode[q] : 0;
-      n0[u] = in ? s.q_n0[q] : 0;
-    }
-#pragma unroll 1
-    for (int a = 0; a < 5; ++a) {
-      // per query: nch, p0, nch - p0, ncode, n0
-      int32_t v[kPer];
+  for (int u = 0; u < 4; ++u) {
+    int64_t v[5];
+    off_counts(s, q0 + u, v);
 #pragma unroll
-      for (int u = 0; u < kPer; ++u)
-        v[u] = a == 0 ? nch[u] : a == 1 ? p0[u] : a == 2 ? nch[u] - p0[u] : a == 3 ? ncode[u] : n0[u];
-      int64_t sum = 0;
+    for (int a = 0; a < 5; ++a) sum[a] += v[a];
+  }
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) sum += v[u];
-      int64_t inc = sum;
+  for (int a = 0; a < 5; ++a) {
+    int64_t x = sum[a];
 #pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int64_t y = __shfl_up(inc, o, kWave);
-        if (lane >= o) inc += y;
-      }
-      if (lane == kWave - 1) wtot[wave] = inc;
-      __syncthreads();
-      int64_t before = 0, total = 0;
-#pragma unroll
-      for (int w = 0; w < kNW; ++w) {
-        const int64_t x = wtot[w];
-        before += (w < wave) ? x : 0;
-        total += x;
-      }
-      const int64_t c = carry[a];
-      int64_t* out = a == 0 ? s.off_ch : a == 1 ? s.off_p0 : a == 2 ? s.off_p1 : a == 3 ? s.off_seg : s.off_n0;
-      int64_t run = c + before + inc - sum;
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        if (q0 + u < s.nq) out[q0 + u] = run;
-        run += v[u];
-      }
-      __syncthreads();   // wtot and carry[a] are read by all before they change
-      if (t == 0) carry[a] = c + total;
-    }
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    if (lane == 0) wtot[wave][a] = x;
   }
   __syncthreads();
-  if (t == 0) {
-    s.off_ch[s.nq] = carry[0];
-    s.off_p0[s.nq] = carry[1];
-    s.off_p1[s.nq] = carry[2];
-    s.off_seg[s.nq] = carry[3];
-    s.off_n0[s.nq] = carry[4];
+  if (t < 5) {
+    int64_t x = 0;
+    for (int w = 0; w < kOffThreads / kWave; ++w) x += wtot[w][t];
+    s.blk_sums[(int64_t)blockIdx.x * 5 + t] = x;
+  }
+}
+
+__global__ __launch_bounds__(kOffThreads) void k_offsets_scan(SearchDev s) {
+  __shared__ int64_t wtot[kOffThreads / kWave][5];
+  __shared__ int64_t carry[5];
+  const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+  constexpr int kNW = kOffThreads / kWave;
+  // carry: the sums of the blocks before this one
+  {
+    int64_t c[5] = {0, 0, 0, 0, 0};
+    for (int b = t; b < (int)blockIdx.x; b += kOffThreads)
+#pragma unroll
+      for (int a = 0; a < 5; ++a) c[a] += s.blk_sums[(int64_t)b * 5 + a];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      int64_t x = c[a];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+      if (lane == 0) wtot[wave][a] = x;
+    }
+    __syncthreads();
+    if (t < 5) {
+      int64_t x = 0;
+      for (int w = 0; w < kNW; ++w) x += wtot[w][t];
+      carry[t] = x;
+    }
+    __syncthreads();
+  }
+  const int64_t q0 = (int64_t)blockIdx.x * kOffQ + (int64_t)t * 4;
+  int64_t v[4][5];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) off_counts(s, q0 + u, v[u]);
+  int64_t sum[5], inc[5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    sum[a] = v[0][a] + v[1][a] + v[2][a] + v[3][a];
+    inc[a] = wave_incl_scan_i64(sum[a]);
+  }
+  __syncthreads();   // the carry reduction's wtot reads are done
+  if (lane == kWave - 1)
+#pragma unroll
+    for (int a = 0; a < 5; ++a) wtot[wave][a] = inc[a];
+  __syncthreads();
+  int64_t* outs[5] = {s.off_ch, s.off_p0, s.off_p1, s.off_seg, s.off_n0};
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    int64_t before = carry[a], total = carry[a];
+#pragma unroll
+    for (int w = 0; w < kNW; ++w) {
+      before += (w < wave) ? wtot[w][a] : 0;
+      total += wtot[w][a];
+    }
+    int64_t run = before + inc[a] - sum[a];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (q0 + u < s.nq) outs[a][q0 + u] = run;
+      run += v[u][a];
+    }
+    if (blockIdx.x == gridDim.x - 1 && t == 0) outs[a][s.nq] = total;
   }
 }
 
@@ -932,7 +976,9 @@ hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
   const dim3 gq((unsigned)((s.nq + kWaves - 1) / kWaves));
   hipLaunchKernelGGL(k_plan, gq, dim3(kThreads), 0, st, s);
-  hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, st, s);
+  const dim3 gb((unsigned)((s.nq + kOffQ - 1) / kOffQ));
+  hipLaunchKernelGGL(k_offsets_sum, gb, dim3(kOffThreads), 0, st, s);
+  hipLaunchKernelGGL(k_offsets_scan, gb, dim3(kOffThreads), 0, st, s);
   hipLaunchKernelGGL(k_units, gq, dim3(kThreads), 0, st, s);
   return hipGetLastError();
 }

@@ -15,6 +15,7 @@ constexpr int kMaxNlist = 24576;    // probe selection keeps a query's centroid 
 constexpr int kMaxCodeBits = 4096;
 constexpr int kDefaultChunk = 1024;  // codes per scan work unit
 constexpr int kMaxP0 = 2048;       // bootstrap codes per query: boot - 1 + chunk <= kMaxP0
+constexpr int kOffQ = 1024;       // queries per block of the query-offset scan
 constexpr int kBootCodes = 512;    // bootstrap target: at least this many codes (and k)
 constexpr int64_t kSegBudget = 8ll << 30;   // bytes of candidate segments per (sub-)batch
 
@@ -265,6 +266,7 @@ struct SearchDev {
   int64_t* off_p1;          // nq+1 prefix of q_nch - q_p0
   int64_t* off_seg;         // nq+1 prefix of q_ncode
   int64_t* off_n0;          // nq+1 prefix of q_n0
+  int64_t* blk_sums;        // 5 per block of kOffQ queries (query-offset scan)
   unsigned long long* counters;  // work counters: [2] MFMA scan
   UnitDesc* units0;         // bootstrap work units
   UnitDesc* units1;         // main-phase work units

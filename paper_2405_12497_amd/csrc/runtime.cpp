@@ -530,7 +530,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.q_p0.ensure((size_t)nq * 4));
   HIPCHK(w.q_n0.ensure((size_t)nq * 4));
   HIPCHK(w.q_ncode.ensure((size_t)nq * 8));
-  HIPCHK(w.offs.ensure((size_t)5 * (nq + 1) * 8));
+  HIPCHK(w.offs.ensure((size_t)5 * (nq + 1 + (nq + kOffQ - 1) / kOffQ) * 8));
   HIPCHK(w.counters.ensure(64));
   HIPCHK(w.seg.ensure((size_t)nq * std::max<int64_t>(1, idx->max_codes(nprobe)) * sizeof(Cand)));
   HIPCHK(w.seg_count.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
@@ -589,6 +589,7 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.off_p1 = offs + 2 * (nq + 1);
   s.off_seg = offs + 3 * (nq + 1);
   s.off_n0 = offs + 4 * (nq + 1);
+  s.blk_sums = offs + 5 * (nq + 1);
   s.counters = (unsigned long long*)w.counters.p;
   s.seg = (Cand*)w.seg.p;
   s.seg_count = (int32_t*)w.seg_count.p;

@@ -120,36 +120,53 @@ __device__ inline void wave_sort_sel(uint64_t* sel, int total) {
 template <int B, class Key>
 __device__ void wave_smallest(Key key, int n, int P, uint64_t* sel) {
   const int lane = lane_id();
-  // f(i, key) for every value, batch by batch. Full batches load without
-  // bounds tests (so all B loads of a lane are in flight together); only a
-  // ragged last batch is checked.
-  auto stream = [&](auto&& f) {
+  // fb(c0, kv): batch by batch, kv[j] = key of value c0 + j * 64 + lane
+  // (0xFFFFFFFF past n). Full batches load without bounds tests (so all B
+  // loads of a lane are in flight together); only a ragged last batch is
+  // checked.
+  auto stream = [&](auto&& fb) {
     int c0 = 0;
     for (; c0 + B * kWave <= n; c0 += B * kWave) {
       uint32_t kv[B];
 #pragma unroll
       for (int j = 0; j < B; ++j) kv[j] = key(c0 + j * kWave + lane);
-#pragma unroll
-      for (int j = 0; j < B; ++j) f(c0 + j * kWave + lane, kv[j]);
+      fb(c0, kv);
     }
     if (c0 < n) {
+      uint32_t kv[B];
 #pragma unroll
       for (int j = 0; j < B; ++j) {
         const int i = c0 + j * kWave + lane;
-        f(i, i < n ? key(i) : 0xFFFFFFFFu);
+        kv[j] = i < n ? key(i) : 0xFFFFFFFFu;
       }
+      fb(c0, kv);
     }
   };
   uint32_t lo = 0, hi = 0xFFFFFFFEu;
   int total = 0;   // wave-uniform count of values <= cut
+  // each lane counts its kept values of a batch, one wave scan of the counts
+  // places them, and each lane writes its own (order within sel is
+  // immaterial: the sort orders by (key, index))
   auto compact = [&](uint32_t cut) {
     total = 0;
-    stream([&](int i, uint32_t k) {
-      const bool keep = k <= cut;
-      const uint64_t m = __ballot(keep);
-      const int at = total + __popcll(m & lanemask_lt());
-      if (keep && at < kWSelCap) sel[at] = ((uint64_t)k << 32) | (uint32_t)i;
-      total += __popcll(m);
+    stream([&](int c0, const uint32_t (&kv)[B]) {
+      int cnt = 0;
+#pragma unroll
+      for (int j = 0; j < B; ++j) cnt += kv[j] <= cut;
+      int incl = cnt;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+      }
+      const int tot = __builtin_amdgcn_readlane(incl, kWave - 1);
+      if (total + tot <= kWSelCap) {
+        int at = total + incl - cnt;
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+          if (kv[j] <= cut) sel[at++] = ((uint64_t)kv[j] << 32) | (uint32_t)(c0 + j * kWave + lane);
+      }
+      total += tot;
     });
     if (total < P) lo = max(lo, cut + 1);
     else if (total > kWSelCap) hi = min(hi, cut);
@@ -181,7 +198,10 @@ __device__ void wave_smallest(Key key, int n, int P, uint64_t* sel) {
     // exact: T = the smallest key with at least P values <= T (in [lo, hi])
     auto count_le = [&](uint32_t t) {
       int c = 0;
-      stream([&](int, uint32_t k) { c += (k <= t); });
+      stream([&](int, const uint32_t (&kv)[B]) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) c += (kv[j] <= t);
+      });
       return wave_sum_i(c);
     };
     while (lo < hi) {
@@ -190,17 +210,25 @@ __device__ void wave_smallest(Key key, int n, int P, uint64_t* sel) {
     }
     const uint32_t T = lo;
     int nless = 0;
-    stream([&](int, uint32_t k) { nless += (k < T); });
+    stream([&](int, const uint32_t (&kv)[B]) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) nless += (kv[j] < T);
+    });
     nless = wave_sum_i(nless);
     const int need = P - nless;   // ties at T, lowest indices first
     int at_less = 0, tie_run = 0;
-    stream([&](int i, uint32_t k) {
-      const uint64_t ml = __ballot(k < T), mt = __ballot(k == T);
-      if (k < T) sel[at_less + __popcll(ml & lanemask_lt())] = ((uint64_t)k << 32) | (uint32_t)i;
-      const int rank = tie_run + __popcll(mt & lanemask_lt());
-      if (k == T && rank < need) sel[nless + rank] = ((uint64_t)k << 32) | (uint32_t)i;
-      at_less += __popcll(ml);
-      tie_run += __popcll(mt);
+    stream([&](int c0, const uint32_t (&kv)[B]) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const uint32_t k = kv[j];
+        const uint32_t i = (uint32_t)(c0 + j * kWave + lane);
+        const uint64_t ml = __ballot(k < T), mt = __ballot(k == T);
+        if (k < T) sel[at_less + __popcll(ml & lanemask_lt())] = ((uint64_t)k << 32) | i;
+        const int rank = tie_run + __popcll(mt & lanemask_lt());
+        if (k == T && rank < need) sel[nless + rank] = ((uint64_t)k << 32) | i;
+        at_less += __popcll(ml);
+        tie_run += __popcll(mt);
+      }
     });
     total = P;
   }
