@@ -301,7 +301,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_wave(const float* 
   if (nprobe_q) P = uniform_i32(min(max(nprobe_q[q], 1), nprobe));
   P = min(P, nlist);
   const float* row = D + q * (int64_t)nlist;
-  wave_smallest<16>([&](int i) { return __float_as_uint(fmaxf(row[i], 0.f)); }, nlist, P, sel);
+  wave_smallest<16, 64>([&](int i) { return __float_as_uint(row[i]); },
+                        [](uint32_t v) { return __float_as_uint(fmaxf(__uint_as_float(v), 0.f)); }, nlist, P,
+                        sel);
   for (int i = lane; i < nprobe; i += kWave) {
     const bool live = i < P;
     const uint64_t v = sel[min(i, P - 1)];

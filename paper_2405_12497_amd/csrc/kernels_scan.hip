@@ -608,7 +608,8 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
   const int m = min(n0, min(kMaxK, 4 * s.k));
   if (m > 0) {
     const EstEnt* est = s.p0buf + b0;
-    wave_smallest<8>([&](int i) { return sortable_bits(est[i].dist); }, n0, m, sel);
+    wave_smallest<8, kMaxP0 / kWave>([&](int i) { return __float_as_uint(est[i].dist); },
+                                     [](uint32_t v) { return sortable_bits(__uint_as_float(v)); }, n0, m, sel);
     const int64_t seg0 = uniform_i64(s.off_seg[q]);
     const float* qv = s.q + q * s.dim;
     const int grp = lane / kLpc, sub = lane % kLpc;

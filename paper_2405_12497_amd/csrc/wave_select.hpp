@@ -117,9 +117,20 @@ __device__ inline void wave_sort_sel(uint64_t* sel, int total) {
 // along the sample (4x further or closer) and tried again; each failed cut
 // narrows the key range [lo, hi] that a final exact bisection searches, after
 // which the ties at the P-th key are taken in index order.
-template <int B, class Key>
-__device__ void wave_smallest(Key key, int n, int P, uint64_t* sel) {
+//
+// Rows of at most 64 R values take a faster path first: each lane loads all
+// of its values at once (R loads in flight), and the cut is the P-th smallest
+// of 256 group minima (lane l, group r: the minimum of its values in batches
+// j = r mod 4). The P smallest group minima are P distinct values at or below
+// the cut, so the cut always keeps at least P values; only more than
+// kWSelCap sends the row to the exact path.
+//
+// load(i) returns the raw 32-bit word of value i and xf(raw) its key, so the
+// loads of a batch stay independent of the key arithmetic.
+template <int B, int R, class Load, class Xf>
+__device__ void wave_smallest(Load load, Xf xf, int n, int P, uint64_t* sel) {
   const int lane = lane_id();
+  auto key = [&](int i) { return xf(load(i)); };
   // fb(c0, kv): batch by batch, kv[j] = key of value c0 + j * 64 + lane
   // (0xFFFFFFFF past n). Full batches load without bounds tests (so all B
   // loads of a lane are in flight together); only a ragged last batch is
@@ -173,7 +184,49 @@ __device__ void wave_smallest(Key key, int n, int P, uint64_t* sel) {
     return total >= P && total <= kWSelCap;
   };
   bool ok = false;
-  if (n > 256) {
+  if (R > 0 && n <= R * kWave) {
+    constexpr int RR = R > 0 ? R : 1;
+    uint32_t kr[RR];
+#pragma unroll
+    for (int j = 0; j < RR; ++j) {
+      if ((j + 1) * kWave <= n) kr[j] = load(j * kWave + lane);
+      else if (j * kWave < n) kr[j] = load(min(j * kWave + lane, n - 1));
+      else kr[j] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < RR; ++j) kr[j] = (j * kWave + lane < n) ? xf(kr[j]) : 0xFFFFFFFFu;
+    uint32_t cut = 0xFFFFFFFEu;
+    if (n > 256) {
+      uint32_t gm[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+#pragma unroll
+      for (int j = 0; j < RR; ++j) gm[j & 3] = min(gm[j & 3], kr[j]);
+      wave_bitonic<4>(gm);
+      const int sidx = P - 1;
+      uint32_t pick = gm[0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) pick = (sidx / kWave == r) ? gm[r] : pick;
+      cut = (uint32_t)__builtin_amdgcn_readlane((int)pick, sidx % kWave);
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < RR; ++j) cnt += kr[j] <= cut;
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    total = __builtin_amdgcn_readlane(incl, kWave - 1);
+    if (total <= kWSelCap) {
+      int at = incl - cnt;
+#pragma unroll
+      for (int j = 0; j < RR; ++j)
+        if (kr[j] <= cut) sel[at++] = ((uint64_t)kr[j] << 32) | (uint32_t)(j * kWave + lane);
+    }
+    if (total < P) lo = max(lo, cut + 1);
+    else if (total > kWSelCap) hi = min(hi, cut);
+    ok = total >= P && total <= kWSelCap;
+  } else if (n > 256) {
     const int stride = n / 256;
     uint32_t sm[4];
 #pragma unroll
