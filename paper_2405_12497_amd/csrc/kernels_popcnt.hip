@@ -70,7 +70,7 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
         s.seg[w.seg + off] = cd;
         EstEnt e;
         e.dist = dist;
-        e.slot = (int32_t)(w.qcode + off);
+        e.pos = p[u];
         s.p0buf[w.p0slot + off] = e;
       }
     } else {

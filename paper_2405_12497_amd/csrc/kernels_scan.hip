@@ -614,17 +614,18 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
     const float* qv = s.q + q * s.dim;
     const int grp = lane / kLpc, sub = lane % kLpc;
     constexpr int kGroups = kWave / kLpc;
-    // passes of up to 64 selected codes: entry base + grp + 8 j, j < NC
+    // passes of up to 64 selected codes: entry base + grp + 8 j, j < NC (a
+    // bootstrap entry's index is its slot in the query's segment)
     auto run = [&](int base, auto nc_tag) {
       constexpr int NC = decltype(nc_tag)::value;
       int32_t slot[NC], pos[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const int i = base + grp + j * kGroups;
-        slot[j] = i < m ? est[(uint32_t)(sel[i] & 0xffffffffu)].slot : -1;
+        slot[j] = i < m ? (int32_t)(uint32_t)(sel[i] & 0xffffffffu) : -1;
       }
 #pragma unroll
-      for (int j = 0; j < NC; ++j) pos[j] = slot[j] >= 0 ? s.seg[seg0 + slot[j]].pos : -1;
+      for (int j = 0; j < NC; ++j) pos[j] = slot[j] >= 0 ? est[slot[j]].pos : -1;
       float d[NC];
       group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
       wave_lds_sync();   // every lane has read its sel entries
@@ -676,7 +677,7 @@ constexpr int kFinRoundMax = 128;
 
 __device__ __forceinline__ int fin_lds_words(int k) { return kFinWin + kFinRoundMax + k; }
 
-__global__ __launch_bounds__(kThreads) void k_finalize(SearchDev s) {
+__global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
   extern __shared__ uint64_t fin_lds[];
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int64_t q = (int64_t)blockIdx.x * kWaves + wave;

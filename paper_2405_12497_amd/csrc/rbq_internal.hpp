@@ -44,10 +44,11 @@ struct Cand {
   float lb;
 };
 
-// Bootstrap entry: estimated distance + slot in the query's segment space.
+// Bootstrap entry: estimated distance + list-order position. Entry i of a
+// query's bootstrap buffer is its code i, so its segment slot is i.
 struct EstEnt {
   float dist;
-  int32_t slot;
+  int32_t pos;   // list-order position of the code (its slot is the entry's index)
 };
 
 struct SeedEnt {
