@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets_scan(SearchDev s) {
 
 // One wave per query, a lane per probe rank: the descriptors of its chunks,
 // bootstrap ones to units0 (at off_p0[q]) and the others to units1 (at
-// off_p1[q]).
+// off_p1[q]); and each chunk's first query-code index, for finalize.
 __global__ __launch_bounds__(kThreads) void k_units(SearchDev s) {
   const int64_t q = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (q >= s.nq) return;
@@ -517,6 +517,7 @@ __global__ __launch_bounds__(kThreads) void k_units(SearchDev s) {
       d.count_slot = ch0 + j;
       d.q = (int32_t)q;
       d.pad = 0;
+      s.chunk_qcode[ch0 + j] = (int32_t)d.qcode;
       if (j < p0) s.units0[b0 + j] = d; else s.units1[b1 + (j - p0)] = d;
     }
   }
@@ -827,15 +828,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
   // gather: chunks in groups of 64 (lane j: chunk j0 + j), entries by a
   // shuffle scan of the chunk counts
   const int nch = uniform_i32(s.q_nch[q]);
-  const int p0 = uniform_i32(s.q_p0[q]);
-  const int64_t off0 = uniform_i64(s.off_p0[q]), off1 = uniform_i64(s.off_p1[q]);
+  const int64_t seg0 = uniform_i64(s.off_seg[q]);
   const int64_t ch0 = uniform_i64(s.off_ch[q]);
   for (int j0 = 0; j0 < nch; j0 += kWave) {
     const int j = j0 + lane;
     int64_t base = 0;
     int cj = 0;
     if (j < nch) {
-      base = j < p0 ? s.units0[off0 + j].seg : s.units1[off1 + (j - p0)].seg;
+      base = seg0 + s.chunk_qcode[ch0 + j];
       cj = s.seg_count[ch0 + j];
     }
     int incl = cj;

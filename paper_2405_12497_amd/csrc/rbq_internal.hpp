@@ -268,6 +268,7 @@ struct SearchDev {
   int64_t* off_seg;         // nq+1 prefix of q_ncode
   int64_t* off_n0;          // nq+1 prefix of q_n0
   int64_t* blk_sums;        // 5 per block of kOffQ queries (query-offset scan)
+  int32_t* chunk_qcode;     // per chunk (query order): first query-code index of the chunk
   unsigned long long* counters;  // work counters: [2] MFMA scan
   UnitDesc* units0;         // bootstrap work units
   UnitDesc* units1;         // main-phase work units

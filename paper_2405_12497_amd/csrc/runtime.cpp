@@ -238,6 +238,7 @@ std::vector<DBuf*> rbq_index::all_buffers() {
           &d_P32, &d_Phi, &d_Plo, &ws.qrot, &ws.cd, &ws.probe, &ws.probe_d, &ws.pairs,
           &ws.planes, &ws.qu8, &ws.pair_choff, &ws.pair_codeoff, &ws.q_nch, &ws.q_p0, &ws.q_n0,
           &ws.q_ncode, &ws.offs, &ws.counters, &ws.seg, &ws.seg_count, &ws.p0buf, &ws.tau,
+          &ws.chunk_qcode,
           &ws.seedk, &ws.q_rerank, &ws.q_cand, &ws.nprobe_q, &ws.feats, &ws.tmp,
           &ws.mf_cnt, &ws.mf_fill, &ws.mf_pair_off, &ws.mf_unit_off, &ws.mf_pairs, &ws.units0,
           &ws.units1,
@@ -534,6 +535,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.counters.ensure(64));
   HIPCHK(w.seg.ensure((size_t)nq * std::max<int64_t>(1, idx->max_codes(nprobe)) * sizeof(Cand)));
   HIPCHK(w.seg_count.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
+  HIPCHK(w.chunk_qcode.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
   HIPCHK(w.units0.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * sizeof(UnitDesc)));
   HIPCHK(w.units1.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * sizeof(UnitDesc)));
   HIPCHK(w.p0buf.ensure((size_t)nq * (boot_codes(k, chunk) - 1 + chunk) * sizeof(EstEnt)));
@@ -605,6 +607,7 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.mf_pairs = (int32_t*)w.mf_pairs.p;
   s.units0 = (UnitDesc*)w.units0.p;
   s.units1 = (UnitDesc*)w.units1.p;
+  s.chunk_qcode = (int32_t*)w.chunk_qcode.p;
   s.out_ids = out_ids;
   s.out_d = out_d;
   return s;
