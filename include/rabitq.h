@@ -184,7 +184,7 @@ rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t nq, int32_
  * each scan phase estimated. rbq_profile_read synchronises the device and
  * returns the sums since the last enable (times in milliseconds). */
 typedef struct {
-  int64_t searches;
+  int64_t searches;       /* rbq_search calls profiled (a call may run several sub-batches) */
   double ms_front;        /* rotation + centroid scoring + probe selection */
   double ms_prep;         /* per-pair quantisation + work planning */
   double ms_scan0;        /* bootstrap scan (first chunks of each query) */

@@ -356,6 +356,14 @@ __global__ __launch_bounds__(256) void k_encode(const float* __restrict__ Y, int
     fac[pos] = make_float2((float)a, (float)fmin(ipo, 1.0));
   }
 }
+// Scan factors per code (see estimate), in FP64 from the stored factors.
+__global__ void k_scan_factors(const float2* __restrict__ fac, int64_t n, float2* __restrict__ sfac) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = fac[i].x, ipo = fac[i].y;
+  const double g = ipo > 0.0 ? a / ipo : 0.0;
+  sfac[i] = make_float2((float)g, (float)(g * sqrt(fmax(1.0 - ipo * ipo, 0.0))));
+}
 }  // namespace
 
 hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* sub, const int32_t* sel,
@@ -401,6 +409,12 @@ hipError_t launch_encode(const float* Y, int64_t m, int W, const float* raw, con
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_encode, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, Y, m, W, raw, cent,
                      list_of, dim, pos0, codes, fac);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_factors(const float2* fac, int64_t n, float2* sfac, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_factors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, fac, n, sfac);
   return hipGetLastError();
 }
 

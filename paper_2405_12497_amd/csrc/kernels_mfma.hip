@@ -13,6 +13,7 @@
 // the segments are identical to those of the popcount scan.
 #include "rbq_internal.hpp"
 #include "rbq_runtime.hpp"
+#include "scan_code.hpp"
 
 namespace rbq {
 namespace {
@@ -63,7 +64,7 @@ __device__ void mfma_unit(const SearchDev& s, int64_t start, int64_t end, const 
     // popcount of the code: the four lane groups hold its four 16-bit slices
     int pc = pcp + __shfl_xor(pcp, 16, kWave);
     pc += __shfl_xor(pc, 32, kWave);
-    const float2 f = s.fac[p];
+    const float2 sf = s.sfac[p];
     // acc[i] = IP of row 4 grp + i with code `col`
     bool pass[4];
     float lbv[4];
@@ -72,20 +73,15 @@ __device__ void mfma_unit(const SearchDev& s, int64_t start, int64_t end, const 
       const int row = 4 * grp + i;
       const RowInfo& ri = rows[row];
       const PairRec& r = ri.rec;
-      const float a = f.x, ipo = f.y;
-      const float xq = fmaf(r.k1, (float)acc[i], fmaf(r.k2, (float)pc, r.k0));
-      const float inv = __builtin_amdgcn_rcpf(ipo);
-      const float est = xq * inv;
-      const float ab2 = 2.f * a * r.b;
-      const float dist = fmaf(-ab2, est, fmaf(a, a, r.b * r.b));
-      const float hw = sqrtf(fmaxf(fmaf(-ipo, ipo, 1.f), 0.f)) * inv * hwk;
+      float dist, lbe;
+      estimate(r, pair_terms(r, hwk), sf, acc[i], pc, dist, lbe);
       const bool live = pvalid && ri.valid;
-      const float lb = live ? fmaf(-ab2, hw, dist) : __builtin_inff();
+      const float lb = live ? lbe : __builtin_inff();
       if (DEBUG && row == 0 && live) {
         const int64_t o = p - dbg_base;
         dbg_ip[o] = acc[i];
         dbg_pc[o] = pc;
-        dbg_est[o] = est;
+        dbg_est[o] = estimate_est(r, s.fac[p].y, acc[i], pc);
         dbg_dist[o] = dist;
         dbg_lb[o] = lb;
       }

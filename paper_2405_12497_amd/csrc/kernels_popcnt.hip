@@ -17,7 +17,7 @@ constexpr int kWaves = kThreads / kWave;
 // PHASE 1 keeps the codes with lb <= tau, compacted into the segment.
 template <int WS, int UN, int PHASE, typename PL>
 __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w, int32_t b0, int32_t wend,
-                                          const PairRec& rec, const PL& pl, float tau, float hwk, int& count) {
+                                          const PairRec& rec, const PairTerms& pt, const PL& pl, float tau, int& count) {
   const int lane = lane_id();
   const int32_t start = (int32_t)w.start;
   const int W = WS > 0 ? WS : s.W;
@@ -30,7 +30,7 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
   for (int u = 0; u < UN; ++u) {
     valid[u] = b0 + 64 * u + lane < wend;
     p[u] = valid[u] ? b0 + 64 * u + lane : start;   // masked lanes read an in-bounds code
-    f[u] = s.fac[p[u]];
+    f[u] = s.sfac[p[u]];
     row[u] = code_row(s.codes, p[u], W);
   }
   if constexpr (WS > 0) {
@@ -59,8 +59,8 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
   }
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
-    float est, dist, lb;
-    estimate(rec, f[u], ip[u], pc[u], hwk, est, dist, lb);
+    float dist, lb;
+    estimate(rec, pt, f[u], ip[u], pc[u], dist, lb);
     const int32_t off = p[u] - start;
     if constexpr (PHASE == 0) {
       if (valid[u]) {
@@ -92,6 +92,7 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
 template <int WS, int UN, int PHASE, typename PL>
 __device__ __forceinline__ int scan_unit(const SearchDev& s, const UnitDesc& w, const PairRec& rec, const PL& pl,
                                          float tau, float hwk) {
+  const PairTerms pt = pair_terms(rec, hwk);
   const int32_t start = (int32_t)w.start, wend = (int32_t)(w.start + w.len);
   int count = 0;
   int32_t b0 = start;
@@ -99,9 +100,9 @@ __device__ __forceinline__ int scan_unit(const SearchDev& s, const UnitDesc& w, 
     // LDS planes are re-read every step (shared by its UN codes) rather than
     // hoisted into 8W registers, which would cut the occupancy
     if constexpr (!(WS >= 1 && WS <= 4)) asm volatile("" ::: "memory");
-    scan_step<WS, UN, PHASE>(s, w, b0, wend, rec, pl, tau, hwk, count);
+    scan_step<WS, UN, PHASE>(s, w, b0, wend, rec, pt, pl, tau, count);
   }
-  for (; b0 < wend; b0 += 64) scan_step<WS, 1, PHASE>(s, w, b0, wend, rec, pl, tau, hwk, count);
+  for (; b0 < wend; b0 += 64) scan_step<WS, 1, PHASE>(s, w, b0, wend, rec, pt, pl, tau, count);
   return PHASE == 0 ? w.len : count;
 }
 

@@ -938,7 +938,8 @@ __global__ __launch_bounds__(kThreads) void k_debug_scan(SearchDev s, const Pair
   int ip, pc;
   float est, dist, lb;
   code_ip<WS>(code_row(s.codes, (int32_t)p, s.W), s.W, pl, ip, pc);
-  estimate(rec, s.fac[p], ip, pc, hwk, est, dist, lb);
+  estimate(rec, pair_terms(rec, hwk), s.sfac[p], ip, pc, dist, lb);
+  est = estimate_est(rec, s.fac[p].y, ip, pc);
   const int64_t o = p - beg;
   ip_o[o] = ip;
   pc_o[o] = pc;

@@ -222,6 +222,7 @@ hipError_t launch_rotate_f64(const float* X, int64_t M, int K, const double* P, 
 hipError_t launch_encode(const float* Y, int64_t m, int W, const float* raw, const float* cent,
                          const int32_t* list_of, int dim, int64_t pos0, uint64_t* codes,
                          float2* fac, hipStream_t st);
+hipError_t launch_scan_factors(const float2* fac, int64_t n, float2* sfac, hipStream_t st);
 
 hipError_t launch_select_probe(const float* D, int64_t nq, int nlist, int nprobe,
                                const int32_t* nprobe_q, int32_t* lists, float* dists,
@@ -231,6 +232,7 @@ struct SearchDev {
   // index
   const uint64_t* codes;
   const float2* fac;        // {||o_r - c||, <o_bar,o>}
+  const float2* sfac;       // scan factors {a / <o_bar,o>, a sqrt(1 - <o_bar,o>^2) / <o_bar,o>}
   const float* raw;         // list order
   const int64_t* ids;       // list order -> original id
   const int32_t* list_off;  // nlist + 1

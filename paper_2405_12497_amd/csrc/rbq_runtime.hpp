@@ -95,6 +95,7 @@ struct rbq_index {
 
   // device index
   rbq::DBuf d_codes, d_fac, d_raw, d_ids, d_list_off, d_cent, d_centT, d_cnorm, d_crot;
+  rbq::DBuf d_sfac;   // scan factors per code (see estimate), derived from d_fac
   rbq::DBuf d_P32, d_Phi, d_Plo;
 
   rbq::Workspace ws;
@@ -138,6 +139,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
 SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe, int k, int chunk,
                    const int32_t* nprobe_q, int64_t qid_base, bool mfma, int64_t* out_ids,
                    float* out_d);
+rbq_status scan_factors(rbq_index* idx, hipStream_t st);
 rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
                  const int32_t* nprobe_q, hipStream_t st);
 // One search on `st`. `learned`: per-query nprobe from the model (the caller

@@ -234,7 +234,7 @@ rbq_index::~rbq_index() {
 }
 
 std::vector<DBuf*> rbq_index::all_buffers() {
-  return {&d_codes, &d_fac, &d_raw, &d_ids, &d_list_off, &d_cent, &d_centT, &d_cnorm, &d_crot,
+  return {&d_codes, &d_fac, &d_sfac, &d_raw, &d_ids, &d_list_off, &d_cent, &d_centT, &d_cnorm, &d_crot,
           &d_P32, &d_Phi, &d_Plo, &ws.qrot, &ws.cd, &ws.probe, &ws.probe_d, &ws.pairs,
           &ws.planes, &ws.qu8, &ws.pair_choff, &ws.pair_codeoff, &ws.q_nch, &ws.q_p0, &ws.q_n0,
           &ws.q_ncode, &ws.offs, &ws.counters, &ws.seg, &ws.seg_count, &ws.p0buf, &ws.tau,
@@ -398,7 +398,7 @@ rbq_status rotate_rows(rbq_index* idx, const float* X, int64_t lda, const float*
 
 void account_bytes(rbq_index* idx) {
   int64_t b = 0;
-  for (DBuf* d : {&idx->d_codes, &idx->d_fac, &idx->d_raw, &idx->d_ids, &idx->d_list_off,
+  for (DBuf* d : {&idx->d_codes, &idx->d_fac, &idx->d_sfac, &idx->d_raw, &idx->d_ids, &idx->d_list_off,
                   &idx->d_cent, &idx->d_centT, &idx->d_cnorm, &idx->d_crot, &idx->d_P32,
                   &idx->d_Phi, &idx->d_Plo})
     b += (int64_t)d->cap;
@@ -499,6 +499,8 @@ extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t
     }
     HIPCHK(hipStreamSynchronize(st));
   }
+  rs = scan_factors(idx, st);
+  if (rs != RBQ_OK) return rs;
   account_bytes(idx);
   idx->built = true;
   return RBQ_OK;
@@ -554,6 +556,7 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   std::memset(&s, 0, sizeof(s));
   s.codes = (const uint64_t*)idx->d_codes.p;
   s.fac = (const float2*)idx->d_fac.p;
+  s.sfac = (const float2*)idx->d_sfac.p;
   s.raw = (const float*)idx->d_raw.p;
   s.ids = (const int64_t*)idx->d_ids.p;
   s.list_off = (const int32_t*)idx->d_list_off.p;
@@ -611,6 +614,16 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.out_ids = out_ids;
   s.out_d = out_d;
   return s;
+}
+
+// Scan factors per code from the stored (a, <o_bar,o>); run after every
+// build and load, so saved indexes do not carry them.
+rbq_status scan_factors(rbq_index* idx, hipStream_t st) {
+  const int64_t npad = (idx->n + 63) / 64 * 64;
+  HIPCHK(idx->d_sfac.ensure((size_t)std::max<int64_t>(1, npad) * sizeof(float2)));
+  HIPCHK(launch_scan_factors((const float2*)idx->d_fac.p, npad, (float2*)idx->d_sfac.p, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RBQ_OK;
 }
 
 // Rotation, centroid scoring and probe selection for a batch.
@@ -688,7 +701,6 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   if (pf.on) {
     HIPCHK(hipEventRecord(ev[6], st));
     HIPCHK(launch_profile_accum(s, (unsigned long long*)pf.acc.p, st));
-    pf.searches++;
   }
   return RBQ_OK;
 }
@@ -935,6 +947,7 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
       if (rs != RBQ_OK) return rs;
     }
   }
+  if (idx->prof.on) idx->prof.searches++;   // one per call, however many sub-batches it ran
   if (!idx->done_event) HIPCHK(hipEventCreateWithFlags(&idx->done_event, hipEventDisableTiming));
   HIPCHK(hipEventRecord(idx->done_event, st));
   return RBQ_OK;
@@ -1093,6 +1106,11 @@ extern "C" rbq_status rbq_index_load(const char* path, rbq_index** out) {
   if (e != hipSuccess) {
     delete idx;
     return fail(e == hipErrorOutOfMemory ? RBQ_ENOMEM : RBQ_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+  }
+  rs = scan_factors(idx, nullptr);
+  if (rs != RBQ_OK) {
+    delete idx;
+    return rs;
   }
   account_bytes(idx);
   idx->built = true;

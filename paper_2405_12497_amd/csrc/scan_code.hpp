@@ -62,17 +62,35 @@ __device__ __forceinline__ void code_ip(const uint64_t* __restrict__ row, int W,
 
 // est = <x_bar, q_bar>/<o_bar,o> (Theorem 3.2); Eq. (2) gives the distance;
 // the lower bound plugs est + half-width into Eq. (2).
-__device__ __forceinline__ void estimate(const PairRec& r, float2 f, int ip, int pc, float hwk,
-                                         float& est, float& dist, float& lb) {
-  const float a = f.x, ipo = f.y;
+// Scan factors of a code, precomputed in FP64 from (a, <o_bar,o>) when the
+// index is built or loaded: G = a / <o_bar,o> and H = a sqrt(1 - <o_bar,o>^2)
+// / <o_bar,o>, so that a^2 = G^2 - H^2. With the pair's b and
+// x = <x_bar, q_bar> (Sec. 3.3.2 decomposition):
+//   dist = a^2 + b^2 - 2 b G x       (Eq. (2) with est = x / <o_bar,o>, Theorem 3.2)
+//   lb   = dist - 2 b (eps0 / sqrt(D - 1)) H   (2ab times the half-width of Theorem 3.2)
+// The per-pair constants are b^2, -2b and -2b eps0 / sqrt(D - 1). Every scan
+// uses this form, so all of them give identical bits.
+struct PairTerms {
+  float b2, m2b, m2bh;
+};
+__device__ __forceinline__ PairTerms pair_terms(const PairRec& r, float hwk) {
+  PairTerms t;
+  t.b2 = r.b * r.b;
+  t.m2b = -2.f * r.b;
+  t.m2bh = t.m2b * hwk;
+  return t;
+}
+__device__ __forceinline__ void estimate(const PairRec& r, const PairTerms& t, float2 sf, int ip, int pc,
+                                         float& dist, float& lb) {
   const float xq = fmaf(r.k1, (float)ip, fmaf(r.k2, (float)pc, r.k0));
-  const float inv = __builtin_amdgcn_rcpf(ipo);
-  est = xq * inv;
-  const float ab2 = 2.f * a * r.b;
-  const float base = fmaf(a, a, r.b * r.b);
-  dist = fmaf(-ab2, est, base);
-  const float hw = sqrtf(fmaxf(fmaf(-ipo, ipo, 1.f), 0.f)) * inv * hwk;
-  lb = fmaf(-ab2, hw, dist);
+  const float a2 = fmaf(sf.x, sf.x, -sf.y * sf.y);
+  dist = fmaf(t.m2b * sf.x, xq, a2 + t.b2);
+  lb = fmaf(t.m2bh, sf.y, dist);
+}
+// The estimate itself, from the stored (a, <o_bar,o>) (the parity exports).
+__device__ __forceinline__ float estimate_est(const PairRec& r, float ipo, int ip, int pc) {
+  const float xq = fmaf(r.k1, (float)ip, fmaf(r.k2, (float)pc, r.k0));
+  return xq / ipo;
 }
 
 // A unit descriptor read with a wave-uniform address, made wave-uniform.
