@@ -72,6 +72,18 @@ def make_case(name: str) -> Case:
         assign = np.argmin(d, 1).astype(np.int32)
         return Case(name, data, qs, cent, assign, synth.gaussian_matrix(64, 154), 10, 2500,
                     R.RBQ_ROT_FP32, 4106)
+    if name == "ivf192":
+        # W = 3 words per code (the quarter-wave quantisation's odd width)
+        data, qs = synth.mixture_flat(5000, 12, dim=192, seed_data=161, seed_query=162)
+        cent, assign = synth.kmeans(data, 24, iters=4, seed=163)
+        return Case(name, data, qs, cent, assign, synth.gaussian_matrix(192, 164), 10, 5,
+                    R.RBQ_ROT_FP32, 4107)
+    if name == "ivf256":
+        # W = 4 words per code, split-BF16 rotation
+        data, qs = synth.mixture_flat(5000, 12, dim=256, seed_data=171, seed_query=172)
+        cent, assign = synth.kmeans(data, 24, iters=4, seed=173)
+        return Case(name, data, qs, cent, assign, synth.gaussian_matrix(256, 174), 10, 5,
+                    R.RBQ_ROT_BF16X3, 4108)
     raise KeyError(name)
 
 
