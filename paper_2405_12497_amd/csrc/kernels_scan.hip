@@ -675,6 +675,7 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
 // ids < 2^31, so the keys order by (distance, id).
 constexpr int kFinWin = 512;
 constexpr int kFinRoundMax = 128;
+constexpr int kFinGather = 4;   // gather batches of 64 entries loaded together
 
 __device__ __forceinline__ int fin_lds_words(int k) { return kFinWin + kFinRoundMax + k; }
 
@@ -848,24 +849,39 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
     const int Tg = __builtin_amdgcn_readlane(incl, kWave - 1);
     ncand += Tg;
     const int64_t base0 = uniform_i64(base);   // chunk j0 (Tg > 0 implies it exists)
+    // kFinGather batches of 64 entries at a time: their chunks are located
+    // first, then all their segment loads are issued together
     int ccur = 0;
-    for (int e0 = 0; e0 < Tg; e0 += kWave) {
-      if (nk + kWave > kFinWin) process_window();
-      const int idx = e0 + lane;
-      int myc = ccur;
-      for (int c = ccur + 1; c < kWave; ++c) {   // chunks starting inside this batch
-        const int pc = __builtin_amdgcn_readlane(pre, c);
-        if (pc > e0 + kWave - 1) break;
-        if (idx >= pc) myc = c;
+    for (int e0 = 0; e0 < Tg; e0 += kFinGather * kWave) {
+      if (nk + kFinGather * kWave > kFinWin) process_window();
+      int64_t at[kFinGather];
+      bool in[kFinGather];
+#pragma unroll
+      for (int g = 0; g < kFinGather; ++g) {
+        const int eb = e0 + g * kWave, idx = eb + lane;
+        int myc = ccur;
+        for (int c = ccur + 1; c < kWave; ++c) {   // chunks starting inside this batch
+          const int pc = __builtin_amdgcn_readlane(pre, c);
+          if (pc > eb + kWave - 1) break;
+          if (idx >= pc) myc = c;
+        }
+        const int64_t mybase = __shfl(base, myc, kWave);
+        const int mypre = __shfl(pre, myc, kWave);
+        in[g] = idx < Tg;
+        at[g] = in[g] ? mybase + (idx - mypre) : base0;
+        ccur = __builtin_amdgcn_readlane(myc, kWave - 1);
       }
-      const int64_t mybase = __shfl(base, myc, kWave);
-      const int mypre = __shfl(pre, myc, kWave);
-      const Cand cand = s.seg[idx < Tg ? mybase + (idx - mypre) : base0];
-      const bool keep = idx < Tg && cand.pos >= 0 && cand.lb <= tau;
-      const uint64_t b = __ballot(keep);
-      if (keep) win[nk + __popcll(b & lanemask_lt())] = ((uint64_t)sortable_bits(cand.lb) << 32) | (uint32_t)cand.pos;
-      nk += __popcll(b);
-      ccur = __builtin_amdgcn_readlane(myc, kWave - 1);
+      Cand cd[kFinGather];
+#pragma unroll
+      for (int g = 0; g < kFinGather; ++g) cd[g] = s.seg[at[g]];
+#pragma unroll
+      for (int g = 0; g < kFinGather; ++g) {
+        const bool keep = in[g] && cd[g].pos >= 0 && cd[g].lb <= tau;
+        const uint64_t b = __ballot(keep);
+        if (keep)
+          win[nk + __popcll(b & lanemask_lt())] = ((uint64_t)sortable_bits(cd[g].lb) << 32) | (uint32_t)cd[g].pos;
+        nk += __popcll(b);
+      }
     }
   }
   process_window();
