@@ -43,7 +43,7 @@ SCAN_COUNTERS = {
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
-NPROBE_SWEEP = (8, 16, 32, 64, 128, 256)
+NPROBE_SWEEP = (8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256)
 METRIC = "QPS at recall@10≥0.95, learned vs fixed nprobe; code-scan GB/s vs HBM peak"
 
 
