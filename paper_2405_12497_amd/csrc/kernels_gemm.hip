@@ -18,7 +18,10 @@ constexpr int TM = 64, TN = 64;
 // 16 x 16 outputs, so the block tile is 32 WT square; K steps of 16. In MFMA
 // sub-step s, lane l contributes k = 4 s + l / 16 of its row (A, LDS [m][k])
 // and column (B, LDS [k][n]); the B rows are padded by 16 floats so the four
-// k rows a wave reads fall in different banks.
+// k rows a wave reads fall in different banks. The instruction is given the
+// B fragment first, so it forms the transposed block and lane l ends with row
+// l % 16 and the four adjacent columns 4 (l / 16) .. + 3: one 16-byte store
+// per block instead of four scattered 4-byte ones.
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 constexpr int MKS = 16, MKP = MKS + 4;
 
@@ -138,29 +141,38 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
       for (int i = 0; i < WT; ++i)
 #pragma unroll
         for (int j = 0; j < WT; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[i], acc[i][j], 0, 0, 0);
     }
     if (more) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
-  // output block (i, j): lane holds rows 4 (lane / 16) + e, column lane % 16
-  const int oc = lane & 15, orow = (lane >> 4) * 4;
+  // output block (i, j): lane holds row fr, columns 4 fg .. 4 fg + 3
+  const bool y_vec = (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0;
 #pragma unroll
-  for (int i = 0; i < WT; ++i)
+  for (int i = 0; i < WT; ++i) {
+    const int64_t m = m0 + wm + i * 16 + fr;
+    if (m >= M) continue;
+    const float am = MODE == 1 ? an[m] : 0.f;
 #pragma unroll
     for (int j = 0; j < WT; ++j) {
-      const int n = n0 + wn + j * 16 + oc;
+      const int n = n0 + wn + j * 16 + 4 * fg;
       if (n >= N) continue;
+      f32x4v o = acc[i][j];
+      if (MODE == 1) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t m = m0 + wm + i * 16 + orow + e;
-        if (m >= M) continue;
-        float v = acc[i][j][e];
-        if (MODE == 1) v = fmaxf(an[m] + bn[n] - 2.f * v, 0.f);
-        Y[m * ldy + n] = v;
+        for (int e = 0; e < 4; ++e) o[e] = fmaxf(am + bn[min(n + e, N - 1)] - 2.f * o[e], 0.f);
+      }
+      float* y = Y + m * ldy + n;
+      if (y_vec && n + 3 < N) {
+        *reinterpret_cast<f32x4v*>(y) = o;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < N) y[e] = o[e];
       }
     }
+  }
 }
 
 template <int MODE>
