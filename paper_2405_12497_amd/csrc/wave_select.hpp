@@ -120,10 +120,10 @@ __device__ inline void wave_sort_sel(uint64_t* sel, int total) {
 //
 // Rows of at most 64 R values take a faster path first: each lane loads all
 // of its values at once (R loads in flight), and the cut is the P-th smallest
-// of 256 group minima (lane l, group r: the minimum of its values in batches
-// j = r mod 4). The P smallest group minima are P distinct values at or below
-// the cut, so the cut always keeps at least P values; only more than
-// kWSelCap sends the row to the exact path.
+// of the 64 lane minima when P <= 64, else of 256 group minima (lane l, group
+// r: the minimum of its values in batches j = r mod 4). The P smallest minima
+// are P distinct values at or below the cut, so the cut always keeps at least
+// P values; only more than kWSelCap sends the row to the exact path.
 //
 // load(i) returns the raw 32-bit word of value i and xf(raw) its key, so the
 // loads of a batch stay independent of the key arithmetic.
@@ -196,7 +196,14 @@ __device__ void wave_smallest(Load load, Xf xf, int n, int P, uint64_t* sel) {
 #pragma unroll
     for (int j = 0; j < RR; ++j) kr[j] = (j * kWave + lane < n) ? xf(kr[j]) : 0xFFFFFFFFu;
     uint32_t cut = 0xFFFFFFFEu;
-    if (n > 256) {
+    if (n > 256 && P <= kWave) {
+      // the P-th smallest of the 64 lane minima (every lane holds values)
+      uint32_t lm[1] = {kr[0]};
+#pragma unroll
+      for (int j = 1; j < RR; ++j) lm[0] = min(lm[0], kr[j]);
+      wave_bitonic<1>(lm);
+      cut = (uint32_t)__builtin_amdgcn_readlane((int)lm[0], P - 1);
+    } else if (n > 256) {
       uint32_t gm[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
 #pragma unroll
       for (int j = 0; j < RR; ++j) gm[j & 3] = min(gm[j & 3], kr[j]);
