@@ -264,6 +264,13 @@ rbq_status rbq_debug_export_codes(const rbq_index* idx, uint64_t* codes, float* 
 rbq_status rbq_debug_rotate(rbq_index* idx, const float* queries, int64_t nq, float* out,
                             void* stream);
 
+/* Centroid scoring (Sec. 4, IVF): queries device nq x dim -> dists device
+ * nq x nlist float32, the squared distances ||q - c_k||^2 that the probe step
+ * ranks, computed as ||q||^2 + ||c_k||^2 - 2 <q, c_k> with FP32 products on the
+ * matrix cores and clamped at 0. The caller owns dists. */
+rbq_status rbq_debug_centroid_dists(rbq_index* idx, const float* queries, int64_t nq, float* dists,
+                                    void* stream);
+
 /* Probe step: queries device nq x dim -> lists device nq x nprobe int32 (nearest
  * first, ties to the lower id), dists device nq x nprobe float32 (squared). */
 rbq_status rbq_debug_probe(rbq_index* idx, const float* queries, int64_t nq, int32_t nprobe,

@@ -8,7 +8,11 @@ namespace rbq {
 
 // ---------------------------------------------------------------- FP32 GEMM modes
 // MODE 0: Y = (A - sub[sel]) * B.  MODE 1: centroid distances
-//   Y[m][n] = an[m] + bn[n] - 2 * (A * B)[m][n], clamped at 0.
+//   Y[m][n] = an[m] + bn[n] - 2 * (A * B)[m][n], clamped at 0, and, when gmin
+//   is given (128-wide tiles only), gmin[m][g] = the minimum of Y[m][c] over
+//   the 16 columns c of group g: c = 64 (g / 4) + 4 (g % 4) + 16 j + e,
+//   j, e < 4, c < N (ceil(N / 64) * 4 groups per row). A group is the 16
+//   values one lane holds of a row of its wave's 64-column tile.
 namespace {
 constexpr int TM = 64, TN = 64;
 
@@ -32,7 +36,8 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
                                                        const float* __restrict__ B, int64_t ldb,
                                                        float* __restrict__ Y, int64_t ldy, int64_t M,
                                                        int N, int K, const float* __restrict__ an,
-                                                       const float* __restrict__ bn) {
+                                                       const float* __restrict__ bn,
+                                                       float* __restrict__ gmin) {
   constexpr int BT = 32 * WT;        // block tile (rows and columns)
   constexpr int NLD = BT * 4 / 256;  // float4 loads per thread per operand and K step
   __shared__ __attribute__((aligned(16))) float As[2][BT][MKP];
@@ -149,20 +154,26 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
   }
   // output block (i, j): lane holds row fr, columns 4 fg .. 4 fg + 3
   const bool y_vec = (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0;
+  const bool want_gmin = MODE == 1 && WT == 4 && gmin != nullptr && n0 + wn < N;
+  const int G = ((N + 63) >> 6) * 4;
 #pragma unroll
   for (int i = 0; i < WT; ++i) {
     const int64_t m = m0 + wm + i * 16 + fr;
     if (m >= M) continue;
     const float am = MODE == 1 ? an[m] : 0.f;
+    float gv = __builtin_inff();
 #pragma unroll
     for (int j = 0; j < WT; ++j) {
       const int n = n0 + wn + j * 16 + 4 * fg;
-      if (n >= N) continue;
       f32x4v o = acc[i][j];
       if (MODE == 1) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) o[e] = fmaxf(am + bn[min(n + e, N - 1)] - 2.f * o[e], 0.f);
+        for (int e = 0; e < 4; ++e) {
+          o[e] = fmaxf(am + bn[min(n + e, N - 1)] - 2.f * o[e], 0.f);
+          gv = (n + e < N) ? fminf(gv, o[e]) : gv;
+        }
       }
+      if (n >= N) continue;
       float* y = Y + m * ldy + n;
       if (y_vec && n + 3 < N) {
         *reinterpret_cast<f32x4v*>(y) = o;
@@ -172,23 +183,29 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
           if (n + e < N) y[e] = o[e];
       }
     }
+    if (want_gmin) gmin[m * G + ((n0 + wn) >> 6) * 4 + fg] = gv;
   }
 }
+
+}  // namespace
+
+bool gemm_f32_wide_tile(int64_t M, int N) { return ((M + 127) / 128) * (((int64_t)N + 127) / 128) >= 1024; }
+
+namespace {
 
 template <int MODE>
 void launch_f32_mfma(const float* A, int64_t lda, const float* sub, const int32_t* sel, const float* B,
                      int64_t ldb, float* Y, int64_t ldy, int64_t M, int N, int K, const float* an,
-                     const float* bn, hipStream_t st) {
+                     const float* bn, float* gmin, hipStream_t st) {
   // the 128 tile when it still gives at least 1024 blocks, else the 64 tile
-  const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
-  if (big >= 1024) {
+  if (gemm_f32_wide_tile(M, N)) {
     dim3 grid((unsigned)((M + 127) / 128), (N + 127) / 128);
     hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 4>), grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
-                       M, N, K, an, bn);
+                       M, N, K, an, bn, gmin);
   } else {
     dim3 grid((unsigned)((M + 63) / 64), (N + 63) / 64);
     hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 2>), grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
-                       M, N, K, an, bn);
+                       M, N, K, an, bn, gmin);
   }
 }
 
@@ -382,7 +399,7 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* sub, const 
                            const float* B, int64_t ldb, float* Y, int64_t ldy, int64_t M, int N,
                            int K, hipStream_t st) {
   if (M <= 0) return hipSuccess;
-  launch_f32_mfma<0>(A, lda, sub, sel, B, ldb, Y, ldy, M, N, K, nullptr, nullptr, st);
+  launch_f32_mfma<0>(A, lda, sub, sel, B, ldb, Y, ldy, M, N, K, nullptr, nullptr, nullptr, st);
   return hipGetLastError();
 }
 
@@ -397,13 +414,12 @@ hipError_t launch_gemm_bf16x3(const float* A, int64_t lda, const float* sub, con
 }
 
 hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float* Ct,
-                                const float* cn, int nlist, float* D, hipStream_t st) {
-  // ||q||^2 is written into the tail of D's first row block scratch: use a
-  // separate small buffer carved after D (caller provides nq floats there).
+                                const float* cn, int nlist, float* D, float* gmin, hipStream_t st) {
+  // ||q||^2 goes to the nq floats the caller provides after D
   float* qn = D + nq * (int64_t)nlist;
   hipLaunchKernelGGL(k_rownorm, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, Q, nq, dim, qn);
   launch_f32_mfma<1>(Q, (int64_t)dim, nullptr, nullptr, Ct, (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim,
-                     qn, cn, st);
+                     qn, cn, gemm_f32_wide_tile(nq, nlist) ? gmin : nullptr, st);
   return hipGetLastError();
 }
 

@@ -312,12 +312,141 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_wave(const float* 
   }
 }
 
+// ------------------------------------------------------------------ grouped wave select
+// nprobe <= 64 with the row's group minima (the minimum of each group of 16
+// lists, written by the centroid-distance kernel; group g holds lists
+// 64 (g / 4) + 4 (g % 4) + 16 j + e, j, e < 4). Lane l holds the minima of
+// groups l, l + 64, ...; the cut is the P-th smallest of the 64 lane minima,
+// so at least P group minima (P distinct distances) are at or below it. Only a
+// group whose minimum is at or below the cut can hold a distance at or below
+// it: those groups' 16 distances are read (16 lanes per group), the ones at or
+// below the cut are compacted and sorted, and the first P are the answer (the
+// P smallest are all at or below the cut). More than kGrpSelCap kept
+// distances (many equal ones) fall back to the full-row wave selection.
+constexpr int kGrpSelCap = kWSelCap / 2;   // sel entries; the group list uses the upper half
+constexpr int kGrpMaxG = 1024;             // groups per row (nlist <= 16384)
+constexpr int kGrpMaxP = kWave;
+
+template <int R>
+__global__ __launch_bounds__(kSelThreads) void k_select_probe_grp(const float* __restrict__ D,
+                                                                  const float* __restrict__ GM, int64_t nq,
+                                                                  int nlist, int nprobe,
+                                                                  const int32_t* __restrict__ nprobe_q,
+                                                                  int32_t* __restrict__ lists,
+                                                                  float* __restrict__ dists) {
+  __shared__ uint64_t selw[kWSelWaves][kWSelCap];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t q = (int64_t)blockIdx.x * kWSelWaves + wave;
+  if (q >= nq) return;   // whole waves
+  uint64_t* sel = selw[wave];
+  int32_t* grp = reinterpret_cast<int32_t*>(sel + kGrpSelCap);   // kGrpMaxG entries
+  int P = nprobe;
+  if (nprobe_q) P = uniform_i32(min(max(nprobe_q[q], 1), nprobe));
+  P = min(P, nlist);
+  const int G = ((nlist + 63) >> 6) * 4;
+  const float* row = D + q * (int64_t)nlist;
+  const float* gm = GM + q * (int64_t)G;
+  auto key = [](float v) { return __float_as_uint(fmaxf(v, 0.f)); };
+  uint32_t gk[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if ((j + 1) * kWave <= G) gk[j] = __float_as_uint(gm[j * kWave + lane]);
+    else if (j * kWave < G) gk[j] = __float_as_uint(gm[min(j * kWave + lane, G - 1)]);
+    else gk[j] = 0;
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) gk[j] = (j * kWave + lane < G) ? key(__uint_as_float(gk[j])) : 0xFFFFFFFFu;
+  uint32_t lm[1] = {gk[0]};
+#pragma unroll
+  for (int j = 1; j < R; ++j) lm[0] = min(lm[0], gk[j]);
+  wave_bitonic<1>(lm);
+  const uint32_t cut = (uint32_t)__builtin_amdgcn_readlane((int)lm[0], P - 1);
+  // the groups whose minimum is at or below the cut
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) cnt += gk[j] <= cut;
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const int ng = __builtin_amdgcn_readlane(incl, kWave - 1);
+  {
+    int at = incl - cnt;
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (gk[j] <= cut) grp[at++] = j * kWave + lane;
+  }
+  wave_lds_sync();
+  // their distances, 16 groups per round (4 per load, 16 lanes each)
+  const int sub = lane & 15, gl = lane >> 4;
+  int total = 0;
+  for (int b0 = 0; b0 < ng; b0 += 16) {
+    float rv[4];
+    int col[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int gi = b0 + u * 4 + gl;
+      const int g = grp[min(gi, ng - 1)];
+      col[u] = (g >> 2) * 64 + (g & 3) * 4 + (sub >> 2) * 16 + (sub & 3);
+      rv[u] = row[min(col[u], nlist - 1)];
+    }
+    uint32_t kv[4];
+    int c = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = b0 + u * 4 + gl < ng && col[u] < nlist;
+      kv[u] = in ? key(rv[u]) : 0xFFFFFFFFu;
+      c += kv[u] <= cut;
+    }
+    int ic = c;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(ic, o, kWave);
+      if (lane >= o) ic += y;
+    }
+    const int tot = __builtin_amdgcn_readlane(ic, kWave - 1);
+    if (total + tot <= kGrpSelCap) {
+      int at = total + ic - c;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (kv[u] <= cut) sel[at++] = ((uint64_t)kv[u] << 32) | (uint32_t)col[u];
+    }
+    total += tot;
+  }
+  if (total <= kGrpSelCap) {
+    wave_sort_sel(sel, total);
+  } else {
+    wave_lds_sync();   // the group list is no longer read
+    wave_smallest<16, 64>([&](int i) { return __float_as_uint(row[i]); },
+                          [&](uint32_t v) { return key(__uint_as_float(v)); }, nlist, P, sel);
+  }
+  for (int i = lane; i < nprobe; i += kWave) {
+    const bool live = i < P;
+    const uint64_t v = sel[min(i, P - 1)];
+    lists[q * nprobe + i] = live ? (int32_t)(uint32_t)(v & 0xffffffffu) : -1;
+    if (dists) dists[q * nprobe + i] = live ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+  }
+}
+
 }  // namespace
 
-hipError_t launch_select_probe(const float* D, int64_t nq, int nlist, int nprobe,
+hipError_t launch_select_probe(const float* D, const float* gmin, int64_t nq, int nlist, int nprobe,
                                const int32_t* nprobe_q, int32_t* lists, float* dists,
                                hipStream_t st) {
   if (nq <= 0) return hipSuccess;
+  const int G = (nlist + 63) / 64 * 4;
+  if (gmin && centroid_gmin(nq, nlist) && nprobe <= kGrpMaxP && G <= kGrpMaxG) {
+    const dim3 grid((unsigned)((nq + kWSelWaves - 1) / kWSelWaves));
+    if (G <= 4 * kWave)
+      hipLaunchKernelGGL((k_select_probe_grp<4>), grid, dim3(kSelThreads), 0, st, D, gmin, nq, nlist, nprobe,
+                         nprobe_q, lists, dists);
+    else
+      hipLaunchKernelGGL((k_select_probe_grp<kGrpMaxG / kWave>), grid, dim3(kSelThreads), 0, st, D, gmin, nq,
+                         nlist, nprobe, nprobe_q, lists, dists);
+    return hipGetLastError();
+  }
   if (nprobe > kSelCap) {
     int n2 = 1;
     while (n2 < nprobe) n2 <<= 1;

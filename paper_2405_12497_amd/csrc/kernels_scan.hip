@@ -578,17 +578,10 @@ __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const
   }
 }
 
-__device__ __forceinline__ bool less_di(float d1, int64_t i1, float d2, int64_t i2) {
-  return d1 < d2 || (d1 == d2 && i1 < i2);
-}
-
 // Float bits mapped to unsigned integers that order like the floats.
 __device__ __forceinline__ uint32_t sortable_bits(float x) {
   const uint32_t u = __float_as_uint(x);
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float from_sortable(uint32_t k) {
-  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
 // ------------------------------------------------------------------ bootstrap tau

@@ -212,9 +212,15 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* sub, const 
 hipError_t launch_gemm_bf16x3(const float* A, int64_t lda, const float* sub, const int32_t* sel,
                               const uint16_t* Bhi, const uint16_t* Blo, float* Y, int64_t ldy,
                               int64_t M, int N, int K, hipStream_t st);
-// D[b][k] = ||q_b||^2 + cn[k] - 2 <q_b, c_k>, clamped at 0 (Ct is [K x nlist]).
+// D[b][k] = ||q_b||^2 + cn[k] - 2 <q_b, c_k>, clamped at 0 (Ct is [K x nlist]);
+// D holds nq * (nlist + 1) floats (||q_b||^2 after the distances). When
+// centroid_gmin(nq, nlist) holds and gmin is not null, gmin receives the
+// minimum of each 16-list group of a row ([nq x ceil(nlist / 64) * 4]; group g
+// holds lists 64 (g / 4) + 4 (g % 4) + 16 j + e, j, e < 4).
+bool gemm_f32_wide_tile(int64_t M, int N);
+inline bool centroid_gmin(int64_t nq, int nlist) { return gemm_f32_wide_tile(nq, nlist); }
 hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float* Ct,
-                                const float* cn, int nlist, float* D, hipStream_t st);
+                                const float* cn, int nlist, float* D, float* gmin, hipStream_t st);
 // FP64 product of rows with P: Y[M x N] = X[M x K] * P[K x N] (stored as FP32).
 hipError_t launch_rotate_f64(const float* X, int64_t M, int K, const double* P, int N, float* Y,
                              hipStream_t st);
@@ -224,7 +230,11 @@ hipError_t launch_encode(const float* Y, int64_t m, int W, const float* raw, con
                          float2* fac, hipStream_t st);
 hipError_t launch_scan_factors(const float2* fac, int64_t n, float2* sfac, hipStream_t st);
 
-hipError_t launch_select_probe(const float* D, int64_t nq, int nlist, int nprobe,
+// The nprobe (or nprobe_q[b], at most nprobe) smallest entries of each row of
+// D, ties to the lower list id; gmin (optional, read when centroid_gmin holds)
+// as written by launch_centroid_dist lets small selections read only the
+// groups that can hold them.
+hipError_t launch_select_probe(const float* D, const float* gmin, int64_t nq, int nlist, int nprobe,
                                const int32_t* nprobe_q, int32_t* lists, float* dists,
                                hipStream_t st);
 

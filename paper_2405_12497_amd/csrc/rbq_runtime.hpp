@@ -44,7 +44,7 @@ bool is_device_ptr(const void* p);
 uint64_t host_splitmix64(uint64_t x);
 
 struct Workspace {
-  DBuf qrot, cd, probe, probe_d, pairs, planes, qu8, pair_choff, pair_codeoff;
+  DBuf qrot, cd, cgmin, probe, probe_d, pairs, planes, qu8, pair_choff, pair_codeoff;
   DBuf q_nch, q_p0, q_n0, q_ncode, offs, counters, seg, seg_count, p0buf, tau, seedk;
   DBuf chunk_qcode;   // chunk (query order) -> first query-code index
   DBuf q_rerank, q_cand, nprobe_q, feats, tmp;

@@ -235,7 +235,7 @@ rbq_index::~rbq_index() {
 
 std::vector<DBuf*> rbq_index::all_buffers() {
   return {&d_codes, &d_fac, &d_sfac, &d_raw, &d_ids, &d_list_off, &d_cent, &d_centT, &d_cnorm, &d_crot,
-          &d_P32, &d_Phi, &d_Plo, &ws.qrot, &ws.cd, &ws.probe, &ws.probe_d, &ws.pairs,
+          &d_P32, &d_Phi, &d_Plo, &ws.qrot, &ws.cd, &ws.cgmin, &ws.probe, &ws.probe_d, &ws.pairs,
           &ws.planes, &ws.qu8, &ws.pair_choff, &ws.pair_codeoff, &ws.q_nch, &ws.q_p0, &ws.q_n0,
           &ws.q_ncode, &ws.offs, &ws.counters, &ws.seg, &ws.seg_count, &ws.p0buf, &ws.tau,
           &ws.chunk_qcode,
@@ -515,6 +515,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   const int64_t np = nq * nprobe;
   HIPCHK(w.qrot.ensure((size_t)nq * dp * 4));
   HIPCHK(w.cd.ensure((size_t)nq * ((size_t)idx->nlist + 1) * 4));
+  HIPCHK(w.cgmin.ensure((size_t)nq * (((size_t)idx->nlist + 63) / 64 * 4) * 4));
   HIPCHK(w.probe.ensure((size_t)np * 4));
   HIPCHK(w.probe_d.ensure((size_t)np * 4));
   HIPCHK(w.pairs.ensure((size_t)np * sizeof(PairRec)));
@@ -633,8 +634,8 @@ rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   rbq_status rs = rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, (float*)w.qrot.p, st);
   if (rs != RBQ_OK) return rs;
   HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
-                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)w.cd.p, st));
-  HIPCHK(launch_select_probe((const float*)w.cd.p, nq, idx->nlist, nprobe, nprobe_q,
+                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)w.cd.p, (float*)w.cgmin.p, st));
+  HIPCHK(launch_select_probe((const float*)w.cd.p, (const float*)w.cgmin.p, nq, idx->nlist, nprobe, nprobe_q,
                              (int32_t*)w.probe.p, (float*)w.probe_d.p, st));
   return RBQ_OK;
 }
@@ -1162,6 +1163,24 @@ extern "C" rbq_status rbq_debug_rotate(rbq_index* idx, const float* queries, int
   return rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, out, (hipStream_t)stream);
 }
 
+extern "C" rbq_status rbq_debug_centroid_dists(rbq_index* idx, const float* queries, int64_t nq,
+                                               float* dists, void* stream) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
+  if (nq == 0) return RBQ_OK;
+  if (!is_device_ptr(queries) || !is_device_ptr(dists)) return fail(RBQ_EINVAL, "device pointers required");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  rbq_status rs = ensure_workspace(idx, nq, 1, 1, kDefaultChunk, false);
+  if (rs != RBQ_OK) return rs;
+  HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
+                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)idx->ws.cd.p, nullptr, st));
+  HIPCHK(hipMemcpyAsync(dists, idx->ws.cd.p, (size_t)nq * idx->nlist * sizeof(float), hipMemcpyDeviceToDevice,
+                        st));
+  return RBQ_OK;
+}
+
 extern "C" rbq_status rbq_debug_probe(rbq_index* idx, const float* queries, int64_t nq,
                                       int32_t nprobe, int32_t* lists, float* dists, void* stream) {
   if (!idx) return fail(RBQ_EINVAL, "index is NULL");
@@ -1176,8 +1195,10 @@ extern "C" rbq_status rbq_debug_probe(rbq_index* idx, const float* queries, int6
   rbq_status rs = ensure_workspace(idx, nq, nprobe, 1, kDefaultChunk, false);
   if (rs != RBQ_OK) return rs;
   HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
-                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)idx->ws.cd.p, st));
-  HIPCHK(launch_select_probe((const float*)idx->ws.cd.p, nq, idx->nlist, nprobe, nullptr, lists,
+                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)idx->ws.cd.p,
+                              (float*)idx->ws.cgmin.p, st));
+  HIPCHK(launch_select_probe((const float*)idx->ws.cd.p, (const float*)idx->ws.cgmin.p, nq, idx->nlist, nprobe,
+                             nullptr, lists,
                              dists, st));
   return RBQ_OK;
 }

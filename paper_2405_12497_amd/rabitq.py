@@ -91,6 +91,7 @@ _SIGS = {
     "rbq_mlp_loss_grad": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P]),
     "rbq_debug_export_codes": (C.c_int, [_P, _P, _P, _P]),
     "rbq_debug_rotate": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
+    "rbq_debug_centroid_dists": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
     "rbq_debug_probe": (C.c_int, [_P, _P, C.c_int64, C.c_int32, _P, _P, _P]),
     "rbq_debug_quantize": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, C.c_int64, _P, _P, _P]),
     "rbq_debug_scan": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
@@ -315,6 +316,15 @@ def rbq_debug_rotate(idx, queries, code_bits, stream=None):
     _check(lib().rbq_debug_rotate(idx, _dev(queries, torch.float32), queries.shape[0],
                                   _dev(out, torch.float32), _stream(stream)))
     return out
+
+
+def rbq_debug_centroid_dists(idx, queries, nlist, stream=None):
+    import torch
+    nq = queries.shape[0]
+    dists = torch.empty((nq, nlist), dtype=torch.float32, device=queries.device)
+    _check(lib().rbq_debug_centroid_dists(idx, _dev(queries, torch.float32), nq, _dev(dists, torch.float32),
+                                          _stream(stream)))
+    return dists
 
 
 def rbq_debug_probe(idx, queries, nprobe, stream=None):
