@@ -8,7 +8,8 @@ namespace rbq {
 
 // ---------------------------------------------------------------- FP32 GEMM modes
 // MODE 0: Y = (A - sub[sel]) * B.  MODE 1: centroid distances
-//   Y[m][n] = an[m] + bn[n] - 2 * (A * B)[m][n], clamped at 0, and, when gmin
+//   Y[m][n] = ||A[m]||^2 + bn[n] - 2 * (A * B)[m][n], clamped at 0 (the row
+//   norms are summed from the A tiles as they pass through), and, when gmin
 //   is given (128-wide tiles only), gmin[m][g] = the minimum of Y[m][c] over
 //   the 16 columns c of group g: c = 64 (g / 4) + 4 (g % 4) + 16 j + e,
 //   j, e < 4, c < N (ceil(N / 64) * 4 groups per row). A group is the 16
@@ -35,13 +36,13 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
                                                        const int32_t* __restrict__ sel,
                                                        const float* __restrict__ B, int64_t ldb,
                                                        float* __restrict__ Y, int64_t ldy, int64_t M,
-                                                       int N, int K, const float* __restrict__ an,
-                                                       const float* __restrict__ bn,
+                                                       int N, int K, const float* __restrict__ bn,
                                                        float* __restrict__ gmin) {
   constexpr int BT = 32 * WT;        // block tile (rows and columns)
   constexpr int NLD = BT * 4 / 256;  // float4 loads per thread per operand and K step
   __shared__ __attribute__((aligned(16))) float As[2][BT][MKP];
   __shared__ __attribute__((aligned(16))) float Bs[2][MKS][BT + 16];
+  __shared__ float an_s[MODE == 1 ? BT : 1];   // ||A[m]||^2 of the tile's rows
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t m0 = (int64_t)blockIdx.x * BT;
   const int n0 = blockIdx.y * BT;
@@ -116,12 +117,23 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
       rb[u] = v;
     }
   };
+  // MODE 1: thread f accumulates the squares of its four columns of row f / 4
+  // as each A tile is stashed; the row's four threads (f % 4) add up at the end
+  float asq[NLD];
+#pragma unroll
+  for (int u = 0; u < NLD; ++u) asq[u] = 0.f;
   auto stash = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
       const int f = tid + 256 * u;
       *reinterpret_cast<float4*>(&As[buf][f >> 2][(f & 3) * 4]) = ra[u];
       *reinterpret_cast<float4*>(&Bs[buf][f / (BT / 4)][(f % (BT / 4)) * 4]) = rb[u];
+      if (MODE == 1) {
+        asq[u] = fmaf(ra[u].x, ra[u].x, asq[u]);
+        asq[u] = fmaf(ra[u].y, ra[u].y, asq[u]);
+        asq[u] = fmaf(ra[u].z, ra[u].z, asq[u]);
+        asq[u] = fmaf(ra[u].w, ra[u].w, asq[u]);
+      }
     }
   };
   // double-buffered K steps: the next step's global loads are in flight
@@ -152,6 +164,16 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
     __syncthreads();
     buf ^= 1;
   }
+  if (MODE == 1) {
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      float v = asq[u];
+      v += __shfl_xor(v, 1, kWave);
+      v += __shfl_xor(v, 2, kWave);
+      if ((tid & 3) == 0) an_s[(tid + 256 * u) >> 2] = v;
+    }
+    __syncthreads();
+  }
   // output block (i, j): lane holds row fr, columns 4 fg .. 4 fg + 3
   const bool y_vec = (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0;
   const bool want_gmin = MODE == 1 && WT == 4 && gmin != nullptr && n0 + wn < N;
@@ -160,7 +182,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
   for (int i = 0; i < WT; ++i) {
     const int64_t m = m0 + wm + i * 16 + fr;
     if (m >= M) continue;
-    const float am = MODE == 1 ? an[m] : 0.f;
+    const float am = MODE == 1 ? an_s[wm + i * 16 + fr] : 0.f;
     float gv = __builtin_inff();
 #pragma unroll
     for (int j = 0; j < WT; ++j) {
@@ -195,30 +217,18 @@ namespace {
 
 template <int MODE>
 void launch_f32_mfma(const float* A, int64_t lda, const float* sub, const int32_t* sel, const float* B,
-                     int64_t ldb, float* Y, int64_t ldy, int64_t M, int N, int K, const float* an,
-                     const float* bn, float* gmin, hipStream_t st) {
+                     int64_t ldb, float* Y, int64_t ldy, int64_t M, int N, int K, const float* bn,
+                     float* gmin, hipStream_t st) {
   // the 128 tile when it still gives at least 1024 blocks, else the 64 tile
   if (gemm_f32_wide_tile(M, N)) {
     dim3 grid((unsigned)((M + 127) / 128), (N + 127) / 128);
     hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 4>), grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
-                       M, N, K, an, bn, gmin);
+                       M, N, K, bn, gmin);
   } else {
     dim3 grid((unsigned)((M + 63) / 64), (N + 63) / 64);
     hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 2>), grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
-                       M, N, K, an, bn, gmin);
+                       M, N, K, bn, gmin);
   }
-}
-
-__global__ void k_rownorm(const float* __restrict__ X, int64_t M, int K, float* __restrict__ out) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= M) return;
-  float s = 0.f;
-  for (int i = lane_id(); i < K; i += kWave) {
-    const float v = X[row * K + i];
-    s = fmaf(v, v, s);
-  }
-  s = wave_sum(s);
-  if (lane_id() == 0) out[row] = s;
 }
 
 // ---------------------------------------------------------------- split-BF16 MFMA GEMM
@@ -399,7 +409,7 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* sub, const 
                            const float* B, int64_t ldb, float* Y, int64_t ldy, int64_t M, int N,
                            int K, hipStream_t st) {
   if (M <= 0) return hipSuccess;
-  launch_f32_mfma<0>(A, lda, sub, sel, B, ldb, Y, ldy, M, N, K, nullptr, nullptr, nullptr, st);
+  launch_f32_mfma<0>(A, lda, sub, sel, B, ldb, Y, ldy, M, N, K, nullptr, nullptr, st);
   return hipGetLastError();
 }
 
@@ -415,11 +425,8 @@ hipError_t launch_gemm_bf16x3(const float* A, int64_t lda, const float* sub, con
 
 hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float* Ct,
                                 const float* cn, int nlist, float* D, float* gmin, hipStream_t st) {
-  // ||q||^2 goes to the nq floats the caller provides after D
-  float* qn = D + nq * (int64_t)nlist;
-  hipLaunchKernelGGL(k_rownorm, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, Q, nq, dim, qn);
   launch_f32_mfma<1>(Q, (int64_t)dim, nullptr, nullptr, Ct, (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim,
-                     qn, cn, gemm_f32_wide_tile(nq, nlist) ? gmin : nullptr, st);
+                     cn, gemm_f32_wide_tile(nq, nlist) ? gmin : nullptr, st);
   return hipGetLastError();
 }
 

@@ -27,6 +27,28 @@
 namespace rbq {
 namespace {
 
+// <x_bar, q_bar> = k1 <x_b, q_u> + k2 popcount(x_b) + k0 with k1 = 2 Delta / sqrt(D),
+// k2 = 2 v_l / sqrt(D) and k0 = -(Delta / sqrt(D)) sum(q_u) - sqrt(D) v_l
+// (Sec. 3.3.1-3.3.2), in FP64; rd = sqrt(D) and ird = 1 / rd come from the host.
+__device__ __forceinline__ void pair_coeffs(double vl, double delta, int sq, double rd, double ird,
+                                            PairRec& r) {
+  const double dr = delta * ird;
+  r.k1 = (float)(2.0 * dr);
+  r.k2 = (float)(2.0 * vl * ird);
+  r.k0 = (float)(-dr * (double)sq - rd * vl);
+}
+
+// v_l = rmin / b and Delta = range / (15 b) of a pair, in FP64 (0 when b = 0).
+__device__ __forceinline__ void pair_scalars(float rmin, float range, float b, double& vl, double& delta) {
+  vl = 0.0;
+  delta = 0.0;
+  if (b > 0.f) {
+    const double ib = 1.0 / (double)b;
+    vl = (double)rmin * ib;
+    delta = (double)range * ib * (1.0 / 15.0);
+  }
+}
+
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 
@@ -132,11 +154,9 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     for (int t = 0; t < WS; ++t) {
       if (t < W) {
         const int i = t * kWave + lane;
-        int qu = 0;
-        if (live) {
-          const float x = (rv[j][t] - rmin) * scale;
-          qu = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
-        }
+        // a pair that is not live has scale 0, so x = 0 and floor(u) = 0
+        const float x = (rv[j][t] - rmin) * scale;
+        const int qu = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
         sq += qu;
         if (q8) q8[i] = (int8_t)qu;
 #pragma unroll
@@ -148,16 +168,9 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     }
     sq = wave_sum_i(sq);
     if (lane == 0) {
-      // <x_bar, q_bar> = (2 Delta/sqrt D) ip + (2 v_l/sqrt D) pc - (Delta/sqrt D) sq - sqrt(D) v_l
-      const double rd = sqrt((double)s.dp);
-      double vl = 0.0, delta = 0.0;
-      if (b > 0.f) {
-        vl = (double)rmin / (double)b;
-        delta = (double)range / (15.0 * (double)b);
-      }
-      rec.k1 = (float)(2.0 * delta / rd);
-      rec.k2 = (float)(2.0 * vl / rd);
-      rec.k0 = (float)(-(delta / rd) * (double)sq - rd * vl);
+      double vl, delta;
+      pair_scalars(rmin, range, b, vl, delta);
+      pair_coeffs(vl, delta, sq, s.rd, s.ird, rec);
       rec.b = b;
       rec.vl = (float)vl;
       rec.delta = (float)delta;
@@ -197,7 +210,8 @@ __device__ __forceinline__ float row_sum_f32(float v) {
 // scale, randomized rounding) is that of k_prep_reg; only the summation
 // order of ||r||^2 differs. Every lane stays active around the DPP steps:
 // per-row conditions are applied as values, not branches.
-template <int W>
+// QU8: also store the int8 codes q_u (the MFMA scan's operand).
+template <int W, bool QU8>
 __global__ __launch_bounds__(kThreads) void k_prep_q(SearchDev s) {
   const int lane = lane_id(), row = lane >> 4, l = lane & 15;
   const int64_t npairs = s.nq * s.nprobe;
@@ -254,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_q(SearchDev s) {
   const bool live = act && (b > 0.f) && (range > 0.f);
   const float scale = live ? 15.f / range : 0.f;
   const uint64_t qid = (uint64_t)(s.qid_base + q);
-  int8_t* q8 = (s.qu8 && act) ? s.qu8 + g * s.dp : nullptr;
+  int8_t* q8 = QU8 ? s.qu8 + gc * s.dp : nullptr;
   int sq = 0;
   uint64_t myword = 0;   // lane l < 4 W of the row: plane word l (= plane jb * W + word t)
 #pragma unroll
@@ -263,10 +277,11 @@ __global__ __launch_bounds__(kThreads) void k_prep_q(SearchDev s) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int i = t * kWave + l + 16 * j;
+      // a pair that is not live has scale 0, so x = 0 and floor(u) = 0
       const float x = (rv[t][j] - rmin) * scale;
-      qu[j] = live ? min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)max(list, 0), (uint32_t)i))) : 0;
+      qu[j] = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)max(list, 0), (uint32_t)i)));
       sq += qu[j];
-      if (q8) q8[i] = (int8_t)qu[j];
+      if (QU8 && act) q8[i] = (int8_t)qu[j];
     }
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
@@ -285,16 +300,9 @@ __global__ __launch_bounds__(kThreads) void k_prep_q(SearchDev s) {
       rec.sq = 0;
       rec.list = -1;
     } else {
-      // <x_bar, q_bar> = (2 Delta/sqrt D) ip + (2 v_l/sqrt D) pc - (Delta/sqrt D) sq - sqrt(D) v_l
-      const double rd = sqrt((double)s.dp);
-      double vl = 0.0, delta = 0.0;
-      if (b > 0.f) {
-        vl = (double)rmin / (double)b;
-        delta = (double)range / (15.0 * (double)b);
-      }
-      rec.k1 = (float)(2.0 * delta / rd);
-      rec.k2 = (float)(2.0 * vl / rd);
-      rec.k0 = (float)(-(delta / rd) * (double)sq - rd * vl);
+      double vl, delta;
+      pair_scalars(rmin, range, b, vl, delta);
+      pair_coeffs(vl, delta, sq, s.rd, s.ird, rec);
       rec.b = b;
       rec.vl = (float)vl;
       rec.delta = (float)delta;
@@ -893,7 +901,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
 // ------------------------------------------------------------------ debug
 __global__ void k_debug_pack(const uint8_t* __restrict__ qu, int dp, int W, float b, float vl,
                              float delta, PairRec* rec, uint64_t* planes, int8_t* qu8,
-                             int32_t list) {
+                             int32_t list, double rd, double ird) {
   // one wave
   const int lane = lane_id();
   int sq = 0;
@@ -910,11 +918,8 @@ __global__ void k_debug_pack(const uint8_t* __restrict__ qu, int dp, int W, floa
   }
   sq = wave_sum_i(sq);
   if (lane == 0) {
-    const double rd = sqrt((double)dp);
     PairRec r;
-    r.k1 = (float)(2.0 * (double)delta / rd);
-    r.k2 = (float)(2.0 * (double)vl / rd);
-    r.k0 = (float)(-((double)delta / rd) * (double)sq - rd * (double)vl);
+    pair_coeffs((double)vl, (double)delta, sq, rd, ird, r);
     r.b = b;
     r.vl = vl;
     r.delta = delta;
@@ -960,16 +965,24 @@ __global__ __launch_bounds__(kThreads) void k_debug_scan(SearchDev s, const Pair
 
 }  // namespace
 
+template <int W>
+void launch_prep_q(const SearchDev& s, dim3 grid, hipStream_t st) {
+  if (s.qu8)
+    hipLaunchKernelGGL((k_prep_q<W, true>), grid, dim3(kThreads), 0, st, s);
+  else
+    hipLaunchKernelGGL((k_prep_q<W, false>), grid, dim3(kThreads), 0, st, s);
+}
+
 hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st) {
   const int64_t npairs = s.nq * s.nprobe;
   if (npairs <= 0) return hipSuccess;
   auto grid = [&](int ppw) { return dim3((unsigned)((npairs + ppw * kWaves - 1) / (ppw * kWaves))); };
   if (s.W <= 0 || s.W > 64) return hipErrorInvalidValue;
   switch (s.W) {
-    case 1: hipLaunchKernelGGL((k_prep_q<1>), grid(4), dim3(kThreads), 0, st, s); break;
-    case 2: hipLaunchKernelGGL((k_prep_q<2>), grid(4), dim3(kThreads), 0, st, s); break;
-    case 3: hipLaunchKernelGGL((k_prep_q<3>), grid(4), dim3(kThreads), 0, st, s); break;
-    case 4: hipLaunchKernelGGL((k_prep_q<4>), grid(4), dim3(kThreads), 0, st, s); break;
+    case 1: launch_prep_q<1>(s, grid(4), st); break;
+    case 2: launch_prep_q<2>(s, grid(4), st); break;
+    case 3: launch_prep_q<3>(s, grid(4), st); break;
+    case 4: launch_prep_q<4>(s, grid(4), st); break;
     default:
       if (s.W <= 8) {
         hipLaunchKernelGGL((k_prep_reg<8, 2>), grid(2), dim3(kThreads), 0, st, s);
@@ -1012,8 +1025,9 @@ hipError_t launch_finalize(const SearchDev& s, hipStream_t st) {
 hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, float b, float vl, float delta,
                              PairRec* rec, uint64_t* planes, int8_t* qu8, int32_t list,
                              hipStream_t st) {
+  const double rd = std::sqrt((double)dp);
   hipLaunchKernelGGL(k_debug_pack, dim3(1), dim3(kWave), 0, st, qu, dp, W, b, vl, delta, rec,
-                     planes, qu8, list);
+                     planes, qu8, list, rd, 1.0 / rd);
   return hipGetLastError();
 }
 

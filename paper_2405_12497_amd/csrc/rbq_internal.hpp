@@ -212,8 +212,8 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* sub, const 
 hipError_t launch_gemm_bf16x3(const float* A, int64_t lda, const float* sub, const int32_t* sel,
                               const uint16_t* Bhi, const uint16_t* Blo, float* Y, int64_t ldy,
                               int64_t M, int N, int K, hipStream_t st);
-// D[b][k] = ||q_b||^2 + cn[k] - 2 <q_b, c_k>, clamped at 0 (Ct is [K x nlist]);
-// D holds nq * (nlist + 1) floats (||q_b||^2 after the distances). When
+// D[b][k] = ||q_b||^2 + cn[k] - 2 <q_b, c_k>, clamped at 0 (Ct is [K x nlist],
+// D is [nq x nlist]). When
 // centroid_gmin(nq, nlist) holds and gmin is not null, gmin receives the
 // minimum of each 16-list group of a row ([nq x ceil(nlist / 64) * 4]; group g
 // holds lists 64 (g / 4) + 4 (g % 4) + 16 j + e, j, e < 4).
@@ -250,6 +250,7 @@ struct SearchDev {
   const float* crot;        // nlist x Dp (P^T c_k)
   const float* cnorm;       // nlist: ||c_k||^2
   int dim, dp, W, nlist;
+  double rd, ird;            // sqrt(dp), 1 / sqrt(dp)
   float eps0;
   uint64_t seed;
   // batch

@@ -514,7 +514,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   const int dp = idx->dp, W = idx->W;
   const int64_t np = nq * nprobe;
   HIPCHK(w.qrot.ensure((size_t)nq * dp * 4));
-  HIPCHK(w.cd.ensure((size_t)nq * ((size_t)idx->nlist + 1) * 4));
+  HIPCHK(w.cd.ensure((size_t)nq * (size_t)idx->nlist * 4));
   HIPCHK(w.cgmin.ensure((size_t)nq * (((size_t)idx->nlist + 63) / 64 * 4) * 4));
   HIPCHK(w.probe.ensure((size_t)np * 4));
   HIPCHK(w.probe_d.ensure((size_t)np * 4));
@@ -566,6 +566,8 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.cnorm = (const float*)idx->d_cnorm.p;
   s.dim = idx->dim;
   s.dp = idx->dp;
+  s.rd = std::sqrt((double)idx->dp);
+  s.ird = 1.0 / s.rd;
   s.W = idx->W;
   s.nlist = idx->nlist;
   s.eps0 = idx->prm.eps0;
