@@ -180,9 +180,16 @@ rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t nq, int32_
                         int32_t nprobe, void* stream);
 
 /* Kernel timing. When enabled, rbq_search records HIP events on its stream
- * around each launch group and accumulates, on the device, the number of codes
- * each scan phase estimated. rbq_profile_read synchronises the device and
- * returns the sums since the last enable (times in milliseconds). */
+ * and accumulates, on the device, the number of codes each scan phase
+ * estimated. rbq_profile_read synchronises the device and returns the sums
+ * since the last enable (times in milliseconds). on = RBQ_PROFILE_STAGES:
+ * events around each launch group (all six stage times); on =
+ * RBQ_PROFILE_SCAN: events around the main scan and the rerank only
+ * (ms_scan1 and ms_finalize; the other times read 0), so that fewer event
+ * records interrupt the stream; 0: off. Each event record adds a few
+ * microseconds between the kernels it separates. */
+#define RBQ_PROFILE_STAGES 1
+#define RBQ_PROFILE_SCAN 2
 typedef struct {
   int64_t searches;       /* rbq_search calls profiled (a call may run several sub-batches) */
   double ms_front;        /* rotation + centroid scoring + probe selection */
@@ -195,7 +202,7 @@ typedef struct {
   int64_t codes_scan1;    /* codes estimated by the main scan */
 } rbq_profile;
 
-rbq_status rbq_profile_enable(rbq_index* idx, int32_t on);
+rbq_status rbq_profile_enable(rbq_index* idx, int32_t on);   /* on: 0, 1 or 2 (above) */
 rbq_status rbq_profile_read(rbq_index* idx, rbq_profile* out);
 
 /* ---------------------------------------------------------------------------

@@ -683,6 +683,10 @@ __device__ __forceinline__ int fin_lds_words(int k) { return kFinWin + kFinRound
 __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
   extern __shared__ uint64_t fin_lds[];
   const int wave = threadIdx.x >> 6, lane = lane_id();
+  if (s.prof_acc && blockIdx.x == 0 && threadIdx.x == 0) {   // codes estimated by each scan phase
+    atomicAdd(&s.prof_acc[0], (unsigned long long)s.off_n0[s.nq]);
+    atomicAdd(&s.prof_acc[1], (unsigned long long)(s.off_seg[s.nq] - s.off_n0[s.nq]));
+  }
   const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
   if (q >= s.nq) return;   // whole waves
   const int K = s.k;
@@ -1080,18 +1084,4 @@ hipError_t launch_pairs_to_scal(const SearchDev& s, float* scal, hipStream_t st)
 }
 }  // namespace rbq
 
-namespace rbq {
-namespace {
-__global__ void k_profile_accum(const int64_t* __restrict__ off_seg, const int64_t* __restrict__ off_n0,
-                                int64_t nq, unsigned long long* __restrict__ acc) {
-  if (threadIdx.x == 0) {
-    atomicAdd(&acc[0], (unsigned long long)off_n0[nq]);
-    atomicAdd(&acc[1], (unsigned long long)(off_seg[nq] - off_n0[nq]));
-  }
-}
-}  // namespace
-hipError_t launch_profile_accum(const SearchDev& s, unsigned long long* acc, hipStream_t st) {
-  hipLaunchKernelGGL(k_profile_accum, dim3(1), dim3(64), 0, st, s.off_seg, s.off_n0, s.nq, acc);
-  return hipGetLastError();
-}
-}  // namespace rbq
+

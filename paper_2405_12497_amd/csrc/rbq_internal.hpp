@@ -283,6 +283,7 @@ struct SearchDev {
   int64_t* blk_sums;        // 5 per block of kOffQ queries (query-offset scan)
   int32_t* chunk_qcode;     // per chunk (query order): first query-code index of the chunk
   unsigned long long* counters;  // work counters: [2] MFMA scan
+  unsigned long long* prof_acc;  // profiling: codes of scan phase 0 / 1 (null when off)
   UnitDesc* units0;         // bootstrap work units
   UnitDesc* units1;         // main-phase work units
   // buffers

@@ -53,8 +53,10 @@ struct Workspace {
 
 struct ProfState {
   bool on = false;
+  int level = 0;   // RBQ_PROFILE_STAGES or RBQ_PROFILE_SCAN while on
   int64_t searches = 0;
   // per search: 7 events delimiting front, prep, scan0, tau, scan1, finalize
+  // (null where the level records none)
   std::vector<hipEvent_t> events;
   DBuf acc;    // int64 [2]: codes of scan0, scan1
   void clear();
@@ -73,7 +75,6 @@ bool mfma_available();
 hipError_t launch_zero_u32(void* p, int64_t nwords, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_pairs_to_scal(const SearchDev& s, float* scal, hipStream_t st);
-hipError_t launch_profile_accum(const SearchDev& s, unsigned long long* acc, hipStream_t st);
 
 }  // namespace rbq
 

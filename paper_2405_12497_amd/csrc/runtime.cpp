@@ -567,6 +567,7 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.dim = idx->dim;
   s.dp = idx->dp;
   s.rd = std::sqrt((double)idx->dp);
+  s.prof_acc = nullptr;
   s.ird = 1.0 / s.rd;
   s.W = idx->W;
   s.nlist = idx->nlist;
@@ -664,13 +665,25 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   if (rs != RBQ_OK) return rs;
   ProfState& pf = idx->prof;
   hipEvent_t ev[7] = {};
+  // stage boundaries recorded: all seven, or (scan level) those of the main
+  // scan and the rerank; unrecorded ones stay null
+  auto rec = [&](int i) -> hipError_t {
+    if (!pf.on || (pf.level == RBQ_PROFILE_SCAN && i < 4)) return hipSuccess;
+    return hipEventRecord(ev[i], st);
+  };
   if (pf.on) {
+    // timing-only events: no system-scope fence (cache write-back) at each
+    // record; rbq_profile_read synchronizes the device before reading them
     for (int i = 0; i < 7; ++i) {
-      HIPCHK(hipEventCreate(&ev[i]));
+      if (pf.level == RBQ_PROFILE_SCAN && i < 4) {
+        pf.events.push_back(nullptr);
+        continue;
+      }
+      HIPCHK(hipEventCreateWithFlags(&ev[i], hipEventDisableSystemFence));
       pf.events.push_back(ev[i]);
     }
-    HIPCHK(hipEventRecord(ev[0], st));
   }
+  HIPCHK(rec(0));
   if (learned) {
     rs = learned_nprobe(idx, queries, nq, opts.nprobe, o.nprobe, o.qid_base, st, &nprobe_q);
   } else {
@@ -681,7 +694,7 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   *used_stride = o.nprobe;
   SearchDev s = make_dev(idx, queries, nq, o.nprobe, o.k, chunk, nprobe_q, o.qid_base, mfma,
                          out_ids, out_d);
-  if (pf.on) HIPCHK(hipEventRecord(ev[1], st));
+  HIPCHK(rec(1));
   HIPCHK(launch_prep_pairs(s, st));
   HIPCHK(launch_plan(s, st));
   const int64_t chunks = idx->max_chunks(o.nprobe, chunk);
@@ -689,22 +702,20 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   // bootstrap chunks per query: whole chunks until >= boot codes, so at most boot of them
   const int grid0 = scan_grid(idx, nq, std::min<int64_t>(chunks, s.boot), bpc);
   const int grid = scan_grid(idx, nq, chunks, bpc);
-  if (pf.on) HIPCHK(hipEventRecord(ev[2], st));
+  HIPCHK(rec(2));
   HIPCHK(launch_scan_popcnt(s, 0, grid0, st));
-  if (pf.on) HIPCHK(hipEventRecord(ev[3], st));
+  HIPCHK(rec(3));
   HIPCHK(launch_tau(s, st));
-  if (pf.on) HIPCHK(hipEventRecord(ev[4], st));
+  HIPCHK(rec(4));
   if (mfma) {
     HIPCHK(launch_scan_mfma(s, 1, scan_grid(idx, nq, chunks, scan_mfma_blocks_per_cu(idx->dp)), st));
   } else {
     HIPCHK(launch_scan_popcnt(s, 1, grid, st));
   }
-  if (pf.on) HIPCHK(hipEventRecord(ev[5], st));
+  HIPCHK(rec(5));
+  s.prof_acc = pf.on ? (unsigned long long*)pf.acc.p : nullptr;   // codes counted by finalize
   HIPCHK(launch_finalize(s, st));
-  if (pf.on) {
-    HIPCHK(hipEventRecord(ev[6], st));
-    HIPCHK(launch_profile_accum(s, (unsigned long long*)pf.acc.p, st));
-  }
+  HIPCHK(rec(6));
   return RBQ_OK;
 }
 
@@ -1268,7 +1279,8 @@ extern "C" rbq_status rbq_debug_fail_alloc_after(int32_t n) {
 
 // ------------------------------------------------------------------ profiling
 void rbq::ProfState::clear() {
-  for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : events)
+    if (e) (void)hipEventDestroy(e);
   events.clear();
   searches = 0;
 }
@@ -1277,8 +1289,10 @@ extern "C" rbq_status rbq_profile_enable(rbq_index* idx, int32_t on) {
   if (!idx) return fail(RBQ_EINVAL, "index is NULL");
   std::lock_guard<std::mutex> lock(idx->mu);
   HIPCHK(hipDeviceSynchronize());
+  if (on < 0 || on > RBQ_PROFILE_SCAN) return fail(RBQ_EINVAL, "profile level must be 0, 1 or 2");
   idx->prof.clear();
   idx->prof.on = on != 0;
+  idx->prof.level = on;
   if (idx->prof.on) {
     HIPCHK(idx->prof.acc.ensure(16));
     HIPCHK(hipMemset(idx->prof.acc.p, 0, 16));
@@ -1297,6 +1311,7 @@ extern "C" rbq_status rbq_profile_read(rbq_index* idx, rbq_profile* out) {
                   &out->ms_finalize};
   for (size_t b = 0; b + 7 <= pf.events.size(); b += 7)
     for (int i = 0; i < 6; ++i) {
+      if (!pf.events[b + i] || !pf.events[b + i + 1]) continue;
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, pf.events[b + i], pf.events[b + i + 1]));
       *f[i] += ms;

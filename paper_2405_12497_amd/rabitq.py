@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "librabitq.so")
 RBQ_OK, RBQ_EINVAL, RBQ_ENOMEM, RBQ_EDEVICE, RBQ_ESTATE, RBQ_EFORMAT, RBQ_EUNSUPPORTED = range(7)
 RBQ_ROT_FP32, RBQ_ROT_BF16X3 = 0, 1
 RBQ_SCAN_AUTO, RBQ_SCAN_POPCNT, RBQ_SCAN_MFMA = 0, 1, 2
+RBQ_PROFILE_STAGES, RBQ_PROFILE_SCAN = 1, 2
 MLP_IN, MLP_HIDDEN, MLP_OUT = 96, 128, 32
 MAX_K, MAX_NPROBE, MAX_NLIST = 256, 16384, 24576
 MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
@@ -234,7 +235,8 @@ def rbq_autotune(idx, queries, k, nprobe, stream=None):
 
 
 def rbq_profile_enable(idx, on=True):
-    _check(lib().rbq_profile_enable(idx, int(bool(on))))
+    """on: False/0 off, True/RBQ_PROFILE_STAGES all stages, RBQ_PROFILE_SCAN main scan and rerank only."""
+    _check(lib().rbq_profile_enable(idx, int(on)))
 
 
 def rbq_profile_read(idx) -> dict:

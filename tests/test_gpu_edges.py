@@ -216,3 +216,39 @@ def test_sub_batches_equal_one_batch():
     np.testing.assert_array_equal(one[0].cpu().numpy(), split[0].cpu().numpy())
     np.testing.assert_array_equal(one[1].cpu().numpy(), split[1].cpu().numpy())
     assert one[2] == split[2]
+
+
+def test_profile_levels():
+    """Stage timing (RBQ_PROFILE_STAGES) bounds every stage; the scan level
+    (RBQ_PROFILE_SCAN) only the main scan and the rerank; both count the same
+    codes per scan phase, profiling leaves the results unchanged, and other
+    levels are rejected."""
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    _say("profile levels")
+    rng = np.random.default_rng(11)
+    cent = (rng.standard_normal((64, 64)) * 3).astype(np.float32)
+    data = (cent[rng.integers(0, 64, 6000)] + rng.standard_normal((6000, 64))).astype(np.float32)
+    assign = np.argmin(((data[:, None, :] - cent[None]) ** 2).sum(-1), 1).astype(np.int32)
+    idx = _index(data, cent, assign)
+    q = torch.from_numpy(data[:300] + 0.1).to(_dev())
+    ids0, d0, _ = idx.search(q, 10, 8)
+    got = {}
+    for level in (R.RBQ_PROFILE_STAGES, R.RBQ_PROFILE_SCAN):
+        R.rbq_profile_enable(idx.h, level)
+        ids, d, _ = idx.search(q, 10, 8)
+        ids, d, _ = idx.search(q, 10, 8)
+        p = R.rbq_profile_read(idx.h)
+        R.rbq_profile_enable(idx.h, False)
+        assert torch.equal(ids, ids0) and torch.equal(d, d0)
+        assert p["searches"] == 2
+        assert p["ms_scan1"] > 0 and p["ms_finalize"] > 0
+        got[level] = p
+    st, sc = got[R.RBQ_PROFILE_STAGES], got[R.RBQ_PROFILE_SCAN]
+    assert all(st[kk] > 0 for kk in ("ms_front", "ms_prep", "ms_scan0", "ms_tau"))
+    assert all(sc[kk] == 0 for kk in ("ms_front", "ms_prep", "ms_scan0", "ms_tau"))
+    assert st["codes_scan0"] == sc["codes_scan0"] > 0
+    assert st["codes_scan1"] == sc["codes_scan1"] > 0
+    with pytest.raises(R.RbqError):
+        R.rbq_profile_enable(idx.h, 3)
+    idx.close()
