@@ -30,22 +30,53 @@ constexpr int TM = 64, TN = 64;
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 constexpr int MKS = 16, MKP = MKS + 4;
 
+// One product (or centroid-distance) problem of the FP32 MFMA GEMM.
+struct GemmJob {
+  const float* A;
+  int64_t lda;
+  const float* sub;
+  const int32_t* sel;
+  const float* B;
+  int64_t ldb;
+  float* Y;
+  int64_t ldy;
+  int64_t M;
+  int N, K;
+  const float* bn;
+  float* gmin;
+};
+
+// LDS of one block: double-buffered A and B tiles, and MODE 1's row norms.
+template <int WT>
+struct GemmLds {
+  static constexpr int BT = 32 * WT;
+  float As[2][BT][MKP];
+  float Bs[2][MKS][BT + 16];
+  float an[BT];
+};
+
+// Output tile (tm, tn) of job j (rows tm * 32 WT.., columns tn * 32 WT..).
 template <int MODE, int WT>
-__global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__ A, int64_t lda,
-                                                       const float* __restrict__ sub,
-                                                       const int32_t* __restrict__ sel,
-                                                       const float* __restrict__ B, int64_t ldb,
-                                                       float* __restrict__ Y, int64_t ldy, int64_t M,
-                                                       int N, int K, const float* __restrict__ bn,
-                                                       float* __restrict__ gmin) {
+__device__ __forceinline__ void gemm_tile(const GemmJob& j, int64_t tm, int tn, GemmLds<WT>& L) {
   constexpr int BT = 32 * WT;        // block tile (rows and columns)
   constexpr int NLD = BT * 4 / 256;  // float4 loads per thread per operand and K step
-  __shared__ __attribute__((aligned(16))) float As[2][BT][MKP];
-  __shared__ __attribute__((aligned(16))) float Bs[2][MKS][BT + 16];
-  __shared__ float an_s[MODE == 1 ? BT : 1];   // ||A[m]||^2 of the tile's rows
+  const float* __restrict__ A = j.A;
+  const int64_t lda = j.lda;
+  const float* __restrict__ sub = j.sub;
+  const int32_t* __restrict__ sel = j.sel;
+  const float* __restrict__ B = j.B;
+  const int64_t ldb = j.ldb;
+  float* __restrict__ Y = j.Y;
+  const int64_t ldy = j.ldy, M = j.M;
+  const int N = j.N, K = j.K;
+  const float* __restrict__ bn = j.bn;
+  float* __restrict__ gmin = j.gmin;
+  auto& As = L.As;
+  auto& Bs = L.Bs;
+  float* an_s = L.an;   // ||A[m]||^2 of the tile's rows (MODE 1)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int64_t m0 = (int64_t)blockIdx.x * BT;
-  const int n0 = blockIdx.y * BT;
+  const int64_t m0 = tm * BT;
+  const int n0 = tn * BT;
   const int wm = (wave >> 1) * (16 * WT), wn = (wave & 1) * (16 * WT);
   f32x4v acc[WT][WT];
 #pragma unroll
@@ -209,6 +240,26 @@ __global__ __launch_bounds__(256) void k_gemm_f32_mfma(const float* __restrict__
   }
 }
 
+template <int MODE, int WT>
+__global__ __launch_bounds__(256) void k_gemm_f32_mfma(GemmJob j) {
+  __shared__ __attribute__((aligned(16))) GemmLds<WT> L;
+  gemm_tile<MODE, WT>(j, blockIdx.x, blockIdx.y, L);
+}
+
+// The query rotation (MODE 0) and the centroid distances (MODE 1) in one
+// launch: they read the same queries and are independent, so the rotation's
+// few tiles run beside the distance tiles instead of before them. Tiles are
+// numbered row tile fastest; the rotation's come first.
+__global__ __launch_bounds__(256) void k_gemm_rot_cdist(GemmJob rot, GemmJob cd, int rot_tm, int rot_tiles,
+                                                        int cd_tm) {
+  __shared__ __attribute__((aligned(16))) GemmLds<4> L;
+  const int t = blockIdx.x;
+  if (t < rot_tiles)
+    gemm_tile<0, 4>(rot, t % rot_tm, t / rot_tm, L);
+  else
+    gemm_tile<1, 4>(cd, (t - rot_tiles) % cd_tm, (t - rot_tiles) / cd_tm, L);
+}
+
 }  // namespace
 
 bool gemm_f32_wide_tile(int64_t M, int N) { return ((M + 127) / 128) * (((int64_t)N + 127) / 128) >= 1024; }
@@ -220,14 +271,13 @@ void launch_f32_mfma(const float* A, int64_t lda, const float* sub, const int32_
                      int64_t ldb, float* Y, int64_t ldy, int64_t M, int N, int K, const float* bn,
                      float* gmin, hipStream_t st) {
   // the 128 tile when it still gives at least 1024 blocks, else the 64 tile
+  const GemmJob j{A, lda, sub, sel, B, ldb, Y, ldy, M, N, K, bn, gmin};
   if (gemm_f32_wide_tile(M, N)) {
     dim3 grid((unsigned)((M + 127) / 128), (N + 127) / 128);
-    hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 4>), grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
-                       M, N, K, bn, gmin);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 4>), grid, dim3(256), 0, st, j);
   } else {
     dim3 grid((unsigned)((M + 63) / 64), (N + 63) / 64);
-    hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 2>), grid, dim3(256), 0, st, A, lda, sub, sel, B, ldb, Y, ldy,
-                       M, N, K, bn, gmin);
+    hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 2>), grid, dim3(256), 0, st, j);
   }
 }
 
@@ -427,6 +477,24 @@ hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float
                                 const float* cn, int nlist, float* D, float* gmin, hipStream_t st) {
   launch_f32_mfma<1>(Q, (int64_t)dim, nullptr, nullptr, Ct, (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim,
                      cn, gemm_f32_wide_tile(nq, nlist) ? gmin : nullptr, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_rotate_centroid(const float* Q, int64_t nq, int dim, const float* P, int dp, float* qrot,
+                                  const float* Ct, const float* cn, int nlist, float* D, float* gmin,
+                                  hipStream_t st) {
+  if (nq <= 0) return hipSuccess;
+  if (!gemm_f32_wide_tile(nq, nlist)) {
+    launch_f32_mfma<0>(Q, (int64_t)dim, nullptr, nullptr, P, (int64_t)dp, qrot, (int64_t)dp, nq, dp, dim, nullptr,
+                       nullptr, st);
+    return launch_centroid_dist(Q, nq, dim, Ct, cn, nlist, D, gmin, st);
+  }
+  const GemmJob rot{Q, (int64_t)dim, nullptr, nullptr, P, (int64_t)dp, qrot, (int64_t)dp, nq, dp, dim, nullptr, nullptr};
+  const GemmJob cd{Q, (int64_t)dim, nullptr, nullptr, Ct, (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim, cn, gmin};
+  const int tm = (int)((nq + 127) / 128);
+  const int rot_tiles = tm * ((dp + 127) / 128), cd_tiles = tm * ((nlist + 127) / 128);
+  hipLaunchKernelGGL(k_gemm_rot_cdist, dim3((unsigned)(rot_tiles + cd_tiles)), dim3(256), 0, st, rot, cd, tm,
+                     rot_tiles, tm);
   return hipGetLastError();
 }
 

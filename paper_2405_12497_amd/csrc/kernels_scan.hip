@@ -210,12 +210,13 @@ __device__ __forceinline__ float row_sum_f32(float v) {
 // scale, randomized rounding) is that of k_prep_reg; only the summation
 // order of ||r||^2 differs. Every lane stays active around the DPP steps:
 // per-row conditions are applied as values, not branches.
-// QU8: also store the int8 codes q_u (the MFMA scan's operand).
+// QU8: also store the int8 codes q_u (the MFMA scan's operand). blk: the
+// block's index among the quantisation blocks of its launch.
 template <int W, bool QU8>
-__global__ __launch_bounds__(kThreads) void k_prep_q(SearchDev s) {
+__device__ __forceinline__ void prep_q_body(const SearchDev& s, int64_t blk) {
   const int lane = lane_id(), row = lane >> 4, l = lane & 15;
   const int64_t npairs = s.nq * s.nprobe;
-  const int64_t g0 = uniform_i64(((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * 4);
+  const int64_t g0 = uniform_i64((blk * kWaves + (threadIdx.x >> 6)) * 4);
   if (g0 >= npairs) return;   // whole waves
   const int64_t g = g0 + row;
   const bool valid = g < npairs;
@@ -311,6 +312,11 @@ __global__ __launch_bounds__(kThreads) void k_prep_q(SearchDev s) {
     }
     s.pairs[g] = rec;
   }
+}
+
+template <int W, bool QU8>
+__global__ __launch_bounds__(kThreads) void k_prep_q(SearchDev s) {
+  prep_q_body<W, QU8>(s, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ planning
@@ -497,8 +503,8 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets_scan(SearchDev s) {
 // One wave per query, a lane per probe rank: the descriptors of its chunks,
 // bootstrap ones to units0 (at off_p0[q]) and the others to units1 (at
 // off_p1[q]); and each chunk's first query-code index, for finalize.
-__global__ __launch_bounds__(kThreads) void k_units(SearchDev s) {
-  const int64_t q = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+__device__ __forceinline__ void units_body(const SearchDev& s, int64_t blk) {
+  const int64_t q = blk * kWaves + (threadIdx.x >> 6);
   if (q >= s.nq) return;
   const int lane = lane_id();
   const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
@@ -510,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void k_units(SearchDev s) {
     const int c0 = choff[r], nc = choff[r + 1] - c0;
     if (nc == 0) continue;
     const int64_t g = q * s.nprobe + r;
-    const int list = s.pairs[g].list;
+    const int list = s.probe[g];   // a rank with chunks is an active one
     const int64_t lbeg = s.list_off[list];
     const int n = s.list_off[list + 1] - s.list_off[list];
     for (int c = 0; c < nc; ++c) {
@@ -529,6 +535,19 @@ __global__ __launch_bounds__(kThreads) void k_units(SearchDev s) {
       if (j < p0) s.units0[b0 + j] = d; else s.units1[b1 + (j - p0)] = d;
     }
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_units(SearchDev s) { units_body(s, blockIdx.x); }
+
+// The unit descriptors and the per-pair quantisation are independent (both
+// follow the offsets): one launch, the units' blocks first, so each fills the
+// other's idle issue slots.
+template <int W, bool QU8>
+__global__ __launch_bounds__(kThreads) void k_prep_units(SearchDev s, int64_t nunit_blocks) {
+  if ((int64_t)blockIdx.x < nunit_blocks)
+    units_body(s, blockIdx.x);
+  else
+    prep_q_body<W, QU8>(s, (int64_t)blockIdx.x - nunit_blocks);
 }
 
 // ------------------------------------------------------------------ exact distance
@@ -970,23 +989,35 @@ __global__ __launch_bounds__(kThreads) void k_debug_scan(SearchDev s, const Pair
 }  // namespace
 
 template <int W>
-void launch_prep_q(const SearchDev& s, dim3 grid, hipStream_t st) {
-  if (s.qu8)
-    hipLaunchKernelGGL((k_prep_q<W, true>), grid, dim3(kThreads), 0, st, s);
-  else
-    hipLaunchKernelGGL((k_prep_q<W, false>), grid, dim3(kThreads), 0, st, s);
+void launch_prep_q(const SearchDev& s, int64_t unit_blocks, int64_t prep_blocks, hipStream_t st) {
+  const dim3 grid((unsigned)(unit_blocks + prep_blocks));
+  if (unit_blocks > 0) {
+    if (s.qu8)
+      hipLaunchKernelGGL((k_prep_units<W, true>), grid, dim3(kThreads), 0, st, s, unit_blocks);
+    else
+      hipLaunchKernelGGL((k_prep_units<W, false>), grid, dim3(kThreads), 0, st, s, unit_blocks);
+  } else {
+    if (s.qu8)
+      hipLaunchKernelGGL((k_prep_q<W, true>), grid, dim3(kThreads), 0, st, s);
+    else
+      hipLaunchKernelGGL((k_prep_q<W, false>), grid, dim3(kThreads), 0, st, s);
+  }
 }
 
-hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st) {
+// The per-pair quantisation, and with `units` also the unit descriptors
+// (which need the plan and the query offsets): for W <= 4 in one launch.
+hipError_t launch_prep(const SearchDev& s, bool units, hipStream_t st) {
   const int64_t npairs = s.nq * s.nprobe;
   if (npairs <= 0) return hipSuccess;
   auto grid = [&](int ppw) { return dim3((unsigned)((npairs + ppw * kWaves - 1) / (ppw * kWaves))); };
+  const int64_t qblocks = (npairs + 4 * kWaves - 1) / (4 * kWaves);
+  const int64_t ublocks = units ? (s.nq + kWaves - 1) / kWaves : 0;
   if (s.W <= 0 || s.W > 64) return hipErrorInvalidValue;
   switch (s.W) {
-    case 1: launch_prep_q<1>(s, grid(4), st); break;
-    case 2: launch_prep_q<2>(s, grid(4), st); break;
-    case 3: launch_prep_q<3>(s, grid(4), st); break;
-    case 4: launch_prep_q<4>(s, grid(4), st); break;
+    case 1: launch_prep_q<1>(s, ublocks, qblocks, st); return hipGetLastError();
+    case 2: launch_prep_q<2>(s, ublocks, qblocks, st); return hipGetLastError();
+    case 3: launch_prep_q<3>(s, ublocks, qblocks, st); return hipGetLastError();
+    case 4: launch_prep_q<4>(s, ublocks, qblocks, st); return hipGetLastError();
     default:
       if (s.W <= 8) {
         hipLaunchKernelGGL((k_prep_reg<8, 2>), grid(2), dim3(kThreads), 0, st, s);
@@ -998,6 +1029,7 @@ hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st) {
         hipLaunchKernelGGL((k_prep_reg<64, 1>), grid(1), dim3(kThreads), 0, st, s);
       }
   }
+  if (units) hipLaunchKernelGGL(k_units, dim3((unsigned)ublocks), dim3(kThreads), 0, st, s);
   return hipGetLastError();
 }
 
@@ -1008,7 +1040,6 @@ hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
   const dim3 gb((unsigned)((s.nq + kOffQ - 1) / kOffQ));
   hipLaunchKernelGGL(k_offsets_sum, gb, dim3(kOffThreads), 0, st, s);
   hipLaunchKernelGGL(k_offsets_scan, gb, dim3(kOffThreads), 0, st, s);
-  hipLaunchKernelGGL(k_units, gq, dim3(kThreads), 0, st, s);
   return hipGetLastError();
 }
 

@@ -221,6 +221,11 @@ bool gemm_f32_wide_tile(int64_t M, int N);
 inline bool centroid_gmin(int64_t nq, int nlist) { return gemm_f32_wide_tile(nq, nlist); }
 hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float* Ct,
                                 const float* cn, int nlist, float* D, float* gmin, hipStream_t st);
+// The FP32 query rotation qrot = Q * P (P is [dim x dp]) and launch_centroid_dist's
+// outputs, in one launch when the distances use 128-wide tiles.
+hipError_t launch_rotate_centroid(const float* Q, int64_t nq, int dim, const float* P, int dp, float* qrot,
+                                  const float* Ct, const float* cn, int nlist, float* D, float* gmin,
+                                  hipStream_t st);
 // FP64 product of rows with P: Y[M x N] = X[M x K] * P[K x N] (stored as FP32).
 hipError_t launch_rotate_f64(const float* X, int64_t M, int K, const double* P, int N, float* Y,
                              hipStream_t st);
@@ -305,8 +310,12 @@ struct SearchDev {
   float* out_d;
 };
 
-hipError_t launch_prep_pairs(const SearchDev& s, hipStream_t st);
+// Work planning: per-query chunk and code prefixes, bootstrap extent, and the
+// query offsets (prefix sums over queries).
 hipError_t launch_plan(const SearchDev& s, hipStream_t st);
+// Per-pair quantisation (S3); with units = true also the scan's unit
+// descriptors, which need launch_plan's results.
+hipError_t launch_prep(const SearchDev& s, bool units, hipStream_t st);
 int scan_popcnt_blocks_per_cu(int W);
 int scan_mfma_blocks_per_cu(int dp);
 hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st);

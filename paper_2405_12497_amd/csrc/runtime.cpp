@@ -634,10 +634,16 @@ rbq_status scan_factors(rbq_index* idx, hipStream_t st) {
 rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
                  const int32_t* nprobe_q, hipStream_t st) {
   Workspace& w = idx->ws;
-  rbq_status rs = rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, (float*)w.qrot.p, st);
-  if (rs != RBQ_OK) return rs;
-  HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
-                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)w.cd.p, (float*)w.cgmin.p, st));
+  if (idx->prm.rot_precision == RBQ_ROT_FP32) {
+    HIPCHK(launch_rotate_centroid(queries, nq, idx->dim, (const float*)idx->d_P32.p, idx->dp, (float*)w.qrot.p,
+                                  (const float*)idx->d_centT.p, (const float*)idx->d_cnorm.p, idx->nlist,
+                                  (float*)w.cd.p, (float*)w.cgmin.p, st));
+  } else {
+    rbq_status rs = rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, (float*)w.qrot.p, st);
+    if (rs != RBQ_OK) return rs;
+    HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
+                                (const float*)idx->d_cnorm.p, idx->nlist, (float*)w.cd.p, (float*)w.cgmin.p, st));
+  }
   HIPCHK(launch_select_probe((const float*)w.cd.p, (const float*)w.cgmin.p, nq, idx->nlist, nprobe, nprobe_q,
                              (int32_t*)w.probe.p, (float*)w.probe_d.p, st));
   return RBQ_OK;
@@ -695,8 +701,8 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   SearchDev s = make_dev(idx, queries, nq, o.nprobe, o.k, chunk, nprobe_q, o.qid_base, mfma,
                          out_ids, out_d);
   HIPCHK(rec(1));
-  HIPCHK(launch_prep_pairs(s, st));
   HIPCHK(launch_plan(s, st));
+  HIPCHK(launch_prep(s, true, st));
   const int64_t chunks = idx->max_chunks(o.nprobe, chunk);
   const int bpc = scan_popcnt_blocks_per_cu(idx->W);
   // bootstrap chunks per query: whole chunks until >= boot codes, so at most boot of them
@@ -1236,7 +1242,7 @@ extern "C" rbq_status rbq_debug_quantize(rbq_index* idx, const float* queries, i
   HIPCHK(hipMemcpyAsync(idx->ws.probe.p, lists, (size_t)nq * nprobe * 4, hipMemcpyDeviceToDevice, st));
   SearchDev s = make_dev(idx, queries, nq, nprobe, 1, kDefaultChunk, nullptr, qid_base, true,
                          nullptr, nullptr);
-  HIPCHK(launch_prep_pairs(s, st));
+  HIPCHK(launch_prep(s, false, st));
   HIPCHK(hipMemcpyAsync(qu, idx->ws.qu8.p, (size_t)nq * nprobe * idx->dp, hipMemcpyDeviceToDevice, st));
   HIPCHK(launch_pairs_to_scal(s, scal, st));
   return RBQ_OK;
