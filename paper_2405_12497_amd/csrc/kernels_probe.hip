@@ -347,13 +347,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_grp(const float* _
   const float* row = D + q * (int64_t)nlist;
   const float* gm = GM + q * (int64_t)G;
   auto key = [](float v) { return __float_as_uint(fmaxf(v, 0.f)); };
-  uint32_t gk[R];
+  uint32_t gk[R];   // all R loads in flight at once (indices past G read group G - 1)
 #pragma unroll
-  for (int j = 0; j < R; ++j) {
-    if ((j + 1) * kWave <= G) gk[j] = __float_as_uint(gm[j * kWave + lane]);
-    else if (j * kWave < G) gk[j] = __float_as_uint(gm[min(j * kWave + lane, G - 1)]);
-    else gk[j] = 0;
-  }
+  for (int j = 0; j < R; ++j) gk[j] = __float_as_uint(gm[min(j * kWave + lane, G - 1)]);
 #pragma unroll
   for (int j = 0; j < R; ++j) gk[j] = (j * kWave + lane < G) ? key(__uint_as_float(gk[j])) : 0xFFFFFFFFu;
   uint32_t lm[1] = {gk[0]};

@@ -647,16 +647,21 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
       }
 #pragma unroll
       for (int j = 0; j < NC; ++j) pos[j] = slot[j] >= 0 ? est[slot[j]].pos : -1;
+      // the ids travel with the raw vectors (one round trip for both)
+      uint32_t id[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) id[j] = (uint32_t)s.ids[max(pos[j], 0)];
       float d[NC];
       group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
       wave_lds_sync();   // every lane has read its sel entries
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const int i = base + grp + j * kGroups;
+        // exact distances are >= 0, so their bits order like the values; ids < 2^31
+        const uint64_t v = ((uint64_t)__float_as_uint(d[j]) << 32) | id[j];
         if (sub == 0 && i < m) {
           s.seg[seg0 + slot[j]].pos = -1;
-          // exact distances are >= 0, so their bits order like the values; ids < 2^31
-          sel[i] = ((uint64_t)__float_as_uint(d[j]) << 32) | (uint64_t)(uint32_t)s.ids[pos[j]];
+          sel[i] = v;
         }
       }
       wave_lds_sync();
@@ -792,13 +797,18 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
         const int i = base + grp + j * kGroups;
         pos[j] = i < n ? (int32_t)(uint32_t)(rnd[i] & 0xffffffffu) : -1;
       }
+      // the ids travel with the raw vectors (one round trip for both)
+      uint32_t id[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) id[j] = (uint32_t)s.ids[max(pos[j], 0)];
       float d[NC];
       group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
       wave_lds_sync();   // every lane has read its entries
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const int i = base + grp + j * kGroups;
-        if (sub == 0 && i < n) rnd[i] = ((uint64_t)__float_as_uint(d[j]) << 32) | (uint32_t)s.ids[pos[j]];
+        const uint64_t v = ((uint64_t)__float_as_uint(d[j]) << 32) | id[j];
+        if (sub == 0 && i < n) rnd[i] = v;
       }
       wave_lds_sync();
     };

@@ -143,13 +143,12 @@ __device__ void wave_smallest(Load load, Xf xf, int n, int P, uint64_t* sel) {
       for (int j = 0; j < B; ++j) kv[j] = key(c0 + j * kWave + lane);
       fb(c0, kv);
     }
-    if (c0 < n) {
+    if (c0 < n) {   // clamped loads (all in flight together), then the keys
       uint32_t kv[B];
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-        const int i = c0 + j * kWave + lane;
-        kv[j] = i < n ? key(i) : 0xFFFFFFFFu;
-      }
+      for (int j = 0; j < B; ++j) kv[j] = load(min(c0 + j * kWave + lane, n - 1));
+#pragma unroll
+      for (int j = 0; j < B; ++j) kv[j] = c0 + j * kWave + lane < n ? xf(kv[j]) : 0xFFFFFFFFu;
       fb(c0, kv);
     }
   };
@@ -186,13 +185,11 @@ __device__ void wave_smallest(Load load, Xf xf, int n, int P, uint64_t* sel) {
   bool ok = false;
   if (R > 0 && n <= R * kWave) {
     constexpr int RR = R > 0 ? R : 1;
+    // every lane issues all RR loads at once (indices past n read value n - 1):
+    // loads under per-batch branches would each wait at the branch's join
     uint32_t kr[RR];
 #pragma unroll
-    for (int j = 0; j < RR; ++j) {
-      if ((j + 1) * kWave <= n) kr[j] = load(j * kWave + lane);
-      else if (j * kWave < n) kr[j] = load(min(j * kWave + lane, n - 1));
-      else kr[j] = 0;
-    }
+    for (int j = 0; j < RR; ++j) kr[j] = load(min(j * kWave + lane, n - 1));
 #pragma unroll
     for (int j = 0; j < RR; ++j) kr[j] = (j * kWave + lane < n) ? xf(kr[j]) : 0xFFFFFFFFu;
     uint32_t cut = 0xFFFFFFFEu;
