@@ -415,8 +415,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_grp(const float* _
     wave_sort_sel(sel, total);
   } else {
     wave_lds_sync();   // the group list is no longer read
-    wave_smallest<16, 64>([&](int i) { return __float_as_uint(row[i]); },
-                          [&](uint32_t v) { return key(__uint_as_float(v)); }, nlist, P, sel);
+    // streaming form (no resident keys), so the rare fallback does not set
+    // the kernel's register budget
+    wave_smallest<16, 0>([&](int i) { return __float_as_uint(row[i]); },
+                         [&](uint32_t v) { return key(__uint_as_float(v)); }, nlist, P, sel);
   }
   for (int i = lane; i < nprobe; i += kWave) {
     const bool live = i < P;

@@ -640,13 +640,21 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
     auto run = [&](int base, auto nc_tag) {
       constexpr int NC = decltype(nc_tag)::value;
       int32_t slot[NC], pos[NC];
+      // clamped reads, then masks: reads under per-entry branches would each
+      // wait at the branch's join
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const int i = base + grp + j * kGroups;
-        slot[j] = i < m ? (int32_t)(uint32_t)(sel[i] & 0xffffffffu) : -1;
+        slot[j] = (int32_t)(uint32_t)(sel[min(i, m - 1)] & 0xffffffffu);
       }
 #pragma unroll
-      for (int j = 0; j < NC; ++j) pos[j] = slot[j] >= 0 ? est[slot[j]].pos : -1;
+      for (int j = 0; j < NC; ++j) pos[j] = est[slot[j]].pos;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const bool in = base + grp + j * kGroups < m;
+        slot[j] = in ? slot[j] : -1;
+        pos[j] = in ? pos[j] : -1;
+      }
       // the ids travel with the raw vectors (one round trip for both)
       uint32_t id[NC];
 #pragma unroll
@@ -795,7 +803,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const int i = base + grp + j * kGroups;
-        pos[j] = i < n ? (int32_t)(uint32_t)(rnd[i] & 0xffffffffu) : -1;
+        pos[j] = (int32_t)(uint32_t)(rnd[min(i, n - 1)] & 0xffffffffu);
+        pos[j] = i < n ? pos[j] : -1;
       }
       // the ids travel with the raw vectors (one round trip for both)
       uint32_t id[NC];
@@ -867,12 +876,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
   const int64_t ch0 = uniform_i64(s.off_ch[q]);
   for (int j0 = 0; j0 < nch; j0 += kWave) {
     const int j = j0 + lane;
-    int64_t base = 0;
-    int cj = 0;
-    if (j < nch) {
-      base = seg0 + s.chunk_qcode[ch0 + j];
-      cj = s.seg_count[ch0 + j];
-    }
+    const int jc = min(j, nch - 1);   // nch >= 1 inside the loop
+    int64_t base = seg0 + s.chunk_qcode[ch0 + jc];
+    int cj = s.seg_count[ch0 + jc];
+    base = j < nch ? base : 0;
+    cj = j < nch ? cj : 0;
     int incl = cj;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
