@@ -36,10 +36,10 @@ SCAN_SOURCES = ("paper_2405_12497_amd/csrc/kernels_popcnt.hip",
 # reading of the same counter for a 1 GiB device-to-device copy
 # (FETCH_SIZE reads 0.5x the copied bytes, WRITE_SIZE 1.0x).
 SCAN_COUNTERS = {
-    "sources_sha256": "12a4d63fd82cbcc849ad02c0d80ebdb0c8fc020feb97642d90b640b6ec78d367",
+    "sources_sha256": "8586f0eedaf4c3b9cfa2f2cb581352979516762caa6333c338332bb04981a5bd",
     "workload": "sift-like n=1000000 nq=10000 nlist=4096 nprobe=20 kernel=popcnt",
-    "fetch_kib": 471180.4,
-    "write_kib": 23670.1,
+    "fetch_kib": 471000.5,
+    "write_kib": 23659.5,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
