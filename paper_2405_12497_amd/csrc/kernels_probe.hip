@@ -351,6 +351,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_grp(const float* _
 #pragma unroll
   for (int j = 0; j < R; ++j) gk[j] = __float_as_uint(gm[min(j * kWave + lane, G - 1)]);
 #pragma unroll
+  for (int j = 0; j < R; ++j) keep_loaded(gk[j]);
+#pragma unroll
   for (int j = 0; j < R; ++j) gk[j] = (j * kWave + lane < G) ? key(__uint_as_float(gk[j])) : 0xFFFFFFFFu;
   uint32_t lm[1] = {gk[0]};
 #pragma unroll

@@ -390,13 +390,15 @@ __global__ __launch_bounds__(kThreads) void k_plan(SearchDev s) {
 constexpr int kOffThreads = kOffQ / 4;
 
 __device__ __forceinline__ void off_counts(const SearchDev& s, int64_t q, int64_t (&v)[5]) {
+  // clamped loads, then masks (loads under a branch would each wait at its join)
   const bool in = q < s.nq;
-  const int64_t nch = in ? s.q_nch[q] : 0, p0 = in ? s.q_p0[q] : 0;
-  v[0] = nch;
-  v[1] = p0;
-  v[2] = nch - p0;
-  v[3] = in ? s.q_ncode[q] : 0;
-  v[4] = in ? s.q_n0[q] : 0;
+  const int64_t qc = min(q, s.nq - 1);
+  const int64_t nch = s.q_nch[qc], p0 = s.q_p0[qc], ncode = s.q_ncode[qc], n0 = s.q_n0[qc];
+  v[0] = in ? nch : 0;
+  v[1] = in ? p0 : 0;
+  v[2] = in ? nch - p0 : 0;
+  v[3] = in ? ncode : 0;
+  v[4] = in ? n0 : 0;
 }
 
 __device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t x) {
@@ -605,6 +607,11 @@ __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const
   }
 }
 
+// Low word of an id (ids are below 2^31): a 4-byte load instead of 8.
+__device__ __forceinline__ uint32_t id_lo32(const int64_t* ids, int64_t i) {
+  return reinterpret_cast<const uint32_t*>(ids)[2 * i];
+}
+
 // Float bits mapped to unsigned integers that order like the floats.
 __device__ __forceinline__ uint32_t sortable_bits(float x) {
   const uint32_t u = __float_as_uint(x);
@@ -650,6 +657,8 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
 #pragma unroll
       for (int j = 0; j < NC; ++j) pos[j] = est[slot[j]].pos;
 #pragma unroll
+      for (int j = 0; j < NC; ++j) keep_loaded(pos[j]);
+#pragma unroll
       for (int j = 0; j < NC; ++j) {
         const bool in = base + grp + j * kGroups < m;
         slot[j] = in ? slot[j] : -1;
@@ -658,9 +667,11 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
       // the ids travel with the raw vectors (one round trip for both)
       uint32_t id[NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) id[j] = (uint32_t)s.ids[max(pos[j], 0)];
+      for (int j = 0; j < NC; ++j) id[j] = id_lo32(s.ids, max(pos[j], 0));
       float d[NC];
       group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) keep_loaded(id[j]);
       wave_lds_sync();   // every lane has read its sel entries
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
@@ -729,9 +740,12 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
   int cnt = 0;
   for (int i0 = 0; i0 < K; i0 += kWave) {
     const int i = i0 + lane;
-    const SeedEnt e = s.seedk[q * K + min(i, K - 1)];
-    const bool v = i < K && e.id >= 0;
-    if (i < K) top[i] = v ? ((uint64_t)__float_as_uint(e.dist) << 32) | (uint32_t)e.id : ~0ull;
+    // one 8-byte load per seed {dist, id}
+    const uint64_t raw = reinterpret_cast<const uint64_t*>(s.seedk)[q * K + min(i, K - 1)];
+    const float dist = __uint_as_float((uint32_t)raw);
+    const int32_t id = (int32_t)(uint32_t)(raw >> 32);
+    const bool v = i < K && id >= 0;
+    if (i < K) top[i] = v ? ((uint64_t)__float_as_uint(dist) << 32) | (uint32_t)id : ~0ull;
     cnt += __popcll(__ballot(v));
   }
   wave_lds_sync();
@@ -809,9 +823,11 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
       // the ids travel with the raw vectors (one round trip for both)
       uint32_t id[NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) id[j] = (uint32_t)s.ids[max(pos[j], 0)];
+      for (int j = 0; j < NC; ++j) id[j] = id_lo32(s.ids, max(pos[j], 0));
       float d[NC];
       group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) keep_loaded(id[j]);
       wave_lds_sync();   // every lane has read its entries
 #pragma unroll
       for (int j = 0; j < NC; ++j) {

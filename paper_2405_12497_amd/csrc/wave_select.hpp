@@ -7,6 +7,15 @@
 
 namespace rbq {
 
+// Marks a loaded value as used at this point, unconditionally. A value that
+// is only consumed under a branch lets the compiler move its load into that
+// branch, where the load waits for every earlier one before it issues; a use
+// placed after a batch of loads keeps them issued together.
+template <typename T>
+__device__ __forceinline__ void keep_loaded(const T& x) {
+  asm volatile("" ::"v"(x));
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -190,6 +199,8 @@ __device__ void wave_smallest(Load load, Xf xf, int n, int P, uint64_t* sel) {
     uint32_t kr[RR];
 #pragma unroll
     for (int j = 0; j < RR; ++j) kr[j] = load(min(j * kWave + lane, n - 1));
+#pragma unroll
+    for (int j = 0; j < RR; ++j) keep_loaded(kr[j]);
 #pragma unroll
     for (int j = 0; j < RR; ++j) kr[j] = (j * kWave + lane < n) ? xf(kr[j]) : 0xFFFFFFFFu;
     uint32_t cut = 0xFFFFFFFEu;
