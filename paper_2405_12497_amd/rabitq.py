@@ -154,8 +154,9 @@ def _dev(t, dtype=None):
 
 
 def _stream(stream):
+    """A HIP stream handle: an int, a torch.cuda.Stream, or None (torch's current stream)."""
     if stream is not None:
-        return C.c_void_p(int(stream))
+        return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
