@@ -554,14 +554,17 @@ __global__ __launch_bounds__(kThreads) void k_prep_units(SearchDev s, int64_t nu
 
 // ------------------------------------------------------------------ exact distance
 // Squared distances of up to NC raw vectors (list-order positions pos[j],
-// -1 = none) to the query in LDS, by a group of 8 consecutive lanes: lane
-// `sub` accumulates the columns sub, sub + 8, ... (float4 columns when rows are
+// -1 = none) to the query, by a group of 8 consecutive lanes: lane `sub`
+// accumulates the columns sub, sub + 8, ... (float4 columns when rows are
 // 16-byte aligned) in order, then the group reduces by xor-shuffles 4, 2, 1.
-// The loads of all NC vectors are issued together. Every exact distance on
-// the device comes from this routine, so equal vectors get equal bits.
+// U columns per lane are loaded per round trip, for all NC vectors together
+// (columns past the row read its last one and add 0), so a pass costs
+// ceil(D / (32 U)) round trips; the order of the additions does not depend on
+// U. Every exact distance on the device comes from this routine, so equal
+// vectors get equal bits.
 constexpr int kLpc = 8;
 
-template <int NC>
+template <int NC, int U = 1>
 __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const int32_t (&pos)[NC], int dim,
                                             const float* __restrict__ qv, int sub, float (&out)[NC]) {
   float acc[NC];
@@ -571,29 +574,77 @@ __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const
     acc[j] = 0.f;
     base[j] = (int64_t)(pos[j] >= 0 ? pos[j] : 0) * dim;   // absent entries read row 0
   }
-  if ((dim & 3) == 0) {
+  if constexpr (U == 1) {
+    if ((dim & 3) == 0) {
+      const float4* q4 = reinterpret_cast<const float4*>(qv);
+      for (int i = sub; i < (dim >> 2); i += kLpc) {
+        const float4 b = q4[i];
+        float4 a[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) a[j] = reinterpret_cast<const float4*>(raw + base[j])[i];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float dx = a[j].x - b.x, dy = a[j].y - b.y, dz = a[j].z - b.z, dw = a[j].w - b.w;
+          acc[j] = fmaf(dx, dx, acc[j]);
+          acc[j] = fmaf(dy, dy, acc[j]);
+          acc[j] = fmaf(dz, dz, acc[j]);
+          acc[j] = fmaf(dw, dw, acc[j]);
+        }
+      }
+    } else {
+      for (int i = sub; i < dim; i += kLpc) {
+        const float b = qv[i];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float d = raw[base[j] + i] - b;
+          acc[j] = fmaf(d, d, acc[j]);
+        }
+      }
+    }
+  } else if ((dim & 3) == 0) {
+    const int n4 = dim >> 2;
     const float4* q4 = reinterpret_cast<const float4*>(qv);
-    for (int i = sub; i < (dim >> 2); i += kLpc) {
-      const float4 b = q4[i];
-      float4 a[NC];
+    for (int i0 = 0; i0 < n4; i0 += U * kLpc) {
+      float4 b[U], a[U][NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) a[j] = reinterpret_cast<const float4*>(raw + base[j])[i];
+      for (int u = 0; u < U; ++u) {
+        const int i = min(i0 + u * kLpc + sub, n4 - 1);
+        b[u] = q4[i];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const float dx = a[j].x - b.x, dy = a[j].y - b.y, dz = a[j].z - b.z, dw = a[j].w - b.w;
-        acc[j] = fmaf(dx, dx, acc[j]);
-        acc[j] = fmaf(dy, dy, acc[j]);
-        acc[j] = fmaf(dz, dz, acc[j]);
-        acc[j] = fmaf(dw, dw, acc[j]);
+        for (int j = 0; j < NC; ++j) a[u][j] = reinterpret_cast<const float4*>(raw + base[j])[i];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool live = i0 + u * kLpc + sub < n4;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float4 x = live ? a[u][j] : b[u];
+          const float dx = x.x - b[u].x, dy = x.y - b[u].y, dz = x.z - b[u].z, dw = x.w - b[u].w;
+          acc[j] = fmaf(dx, dx, acc[j]);
+          acc[j] = fmaf(dy, dy, acc[j]);
+          acc[j] = fmaf(dz, dz, acc[j]);
+          acc[j] = fmaf(dw, dw, acc[j]);
+        }
       }
     }
   } else {
-    for (int i = sub; i < dim; i += kLpc) {
-      const float b = qv[i];
+    for (int i0 = 0; i0 < dim; i0 += U * kLpc) {
+      float b[U], a[U][NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const float d = raw[base[j] + i] - b;
-        acc[j] = fmaf(d, d, acc[j]);
+      for (int u = 0; u < U; ++u) {
+        const int i = min(i0 + u * kLpc + sub, dim - 1);
+        b[u] = qv[i];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) a[u][j] = raw[base[j] + i];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool live = i0 + u * kLpc + sub < dim;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float d = (live ? a[u][j] : b[u]) - b[u];
+          acc[j] = fmaf(d, d, acc[j]);
+        }
       }
     }
   }
@@ -606,6 +657,17 @@ __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const
     out[j] = v;
   }
 }
+
+// Exact-distance shape of tau and finalize: narrow rows (D <= 256) take passes
+// of 64 vectors with one column per lane per round trip; wide rows passes of
+// 32 vectors with four columns per lane per round trip (the same bytes in
+// flight, a quarter of the round trips).
+template <bool WIDE>
+struct DistShape {
+  static constexpr int kMaxNC = WIDE ? 4 : 8;
+  static constexpr int kU = WIDE ? 4 : 1;
+};
+inline bool dist_wide(int dim) { return dim > 256; }
 
 // Low word of an id (ids are below 2^31): a 4-byte load instead of 8.
 __device__ __forceinline__ uint32_t id_lo32(const int64_t* ids, int64_t i) {
@@ -625,7 +687,9 @@ __device__ __forceinline__ uint32_t sortable_bits(float x) {
 // best of them by (distance, id) seed the top-k and tau = the k-th. The others
 // cannot enter the top-k (k better ones are known), so all m segment entries
 // are marked done (pos = -1).
+template <bool WIDE>
 __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
+  using DS = DistShape<WIDE>;
   __shared__ uint64_t selw[kWaves][kWSelCap];
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
@@ -669,7 +733,7 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
 #pragma unroll
       for (int j = 0; j < NC; ++j) id[j] = id_lo32(s.ids, max(pos[j], 0));
       float d[NC];
-      group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
+      group_dists<NC, DS::kU>(s.raw, pos, s.dim, qv, sub, d);
 #pragma unroll
       for (int j = 0; j < NC; ++j) keep_loaded(id[j]);
       wave_lds_sync();   // every lane has read its sel entries
@@ -685,12 +749,12 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
       }
       wave_lds_sync();
     };
-    for (int base = 0; base < m; base += kGroups * 8) {
-      const int per = (min(m - base, kGroups * 8) + kGroups - 1) / kGroups;
+    for (int base = 0; base < m; base += kGroups * DS::kMaxNC) {
+      const int per = (min(m - base, kGroups * DS::kMaxNC) + kGroups - 1) / kGroups;
       if (per <= 1) run(base, IntC<1>{});
       else if (per <= 2) run(base, IntC<2>{});
-      else if (per <= 4) run(base, IntC<4>{});
-      else run(base, IntC<8>{});
+      else if (per <= 4 || DS::kMaxNC == 4) run(base, IntC<4>{});
+      else run(base, IntC<DS::kMaxNC>{});
     }
     wave_sort_sel(sel, m);
   }
@@ -723,7 +787,9 @@ constexpr int kFinGather = 4;   // gather batches of 64 entries loaded together
 
 __device__ __forceinline__ int fin_lds_words(int k) { return kFinWin + kFinRoundMax + k; }
 
+template <bool WIDE>
 __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
+  using DS = DistShape<WIDE>;
   extern __shared__ uint64_t fin_lds[];
   const int wave = threadIdx.x >> 6, lane = lane_id();
   if (s.prof_acc && blockIdx.x == 0 && threadIdx.x == 0) {   // codes estimated by each scan phase
@@ -825,7 +891,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
 #pragma unroll
       for (int j = 0; j < NC; ++j) id[j] = id_lo32(s.ids, max(pos[j], 0));
       float d[NC];
-      group_dists<NC>(s.raw, pos, s.dim, qv, sub, d);
+      group_dists<NC, DS::kU>(s.raw, pos, s.dim, qv, sub, d);
 #pragma unroll
       for (int j = 0; j < NC; ++j) keep_loaded(id[j]);
       wave_lds_sync();   // every lane has read its entries
@@ -837,12 +903,12 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
       }
       wave_lds_sync();
     };
-    for (int base = 0; base < n; base += kGroups * 8) {
-      const int per = (min(n - base, kGroups * 8) + kGroups - 1) / kGroups;
+    for (int base = 0; base < n; base += kGroups * DS::kMaxNC) {
+      const int per = (min(n - base, kGroups * DS::kMaxNC) + kGroups - 1) / kGroups;
       if (per <= 1) pass(base, IntC<1>{});
       else if (per <= 2) pass(base, IntC<2>{});
-      else if (per <= 4) pass(base, IntC<4>{});
-      else pass(base, IntC<8>{});
+      else if (per <= 4 || DS::kMaxNC == 4) pass(base, IntC<4>{});
+      else pass(base, IntC<DS::kMaxNC>{});
     }
   };
 
@@ -1080,14 +1146,22 @@ hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
 
 hipError_t launch_tau(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tau, dim3((unsigned)((s.nq + kWaves - 1) / kWaves)), dim3(kThreads), 0, st, s);
+  const dim3 grid((unsigned)((s.nq + kWaves - 1) / kWaves));
+  if (dist_wide(s.dim))
+    hipLaunchKernelGGL(k_tau<true>, grid, dim3(kThreads), 0, st, s);
+  else
+    hipLaunchKernelGGL(k_tau<false>, grid, dim3(kThreads), 0, st, s);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
   const size_t shm = (size_t)kWaves * (kFinWin + kFinRoundMax + s.k) * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((s.nq + kWaves - 1) / kWaves)), dim3(kThreads), shm, st, s);
+  const dim3 grid((unsigned)((s.nq + kWaves - 1) / kWaves));
+  if (dist_wide(s.dim))
+    hipLaunchKernelGGL(k_finalize<true>, grid, dim3(kThreads), shm, st, s);
+  else
+    hipLaunchKernelGGL(k_finalize<false>, grid, dim3(kThreads), shm, st, s);
   return hipGetLastError();
 }
 
