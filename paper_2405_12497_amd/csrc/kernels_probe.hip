@@ -189,15 +189,17 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __res
 // nprobe above kSelCap: the same exact selection with the keys read from the
 // distance row in global memory and the selected (key, list) pairs sorted in
 // dynamic LDS (next power of two of nprobe entries).
-__global__ __launch_bounds__(kSelThreads) void k_select_probe_large(const float* __restrict__ D, int nlist,
-                                                                    int nprobe,
-                                                                    const int32_t* __restrict__ nprobe_q,
-                                                                    int32_t* __restrict__ lists,
-                                                                    float* __restrict__ dists) {
+constexpr int kSelLargeThreads = 1024;   // the LDS sort of thousands of keys takes the whole block
+
+__global__ __launch_bounds__(kSelLargeThreads) void k_select_probe_large(const float* __restrict__ D, int nlist,
+                                                                         int nprobe,
+                                                                         const int32_t* __restrict__ nprobe_q,
+                                                                         int32_t* __restrict__ lists,
+                                                                         float* __restrict__ dists) {
   extern __shared__ uint64_t selbig[];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t sh_prefix, sh_rank, sh_nless;
-  __shared__ uint32_t tie_scan[kSelThreads];
+  __shared__ uint32_t tie_scan[kSelLargeThreads];
   const int64_t q = blockIdx.x;
   int P = nprobe;
   if (nprobe_q) P = uniform_i32(min(max(nprobe_q[q], 1), nprobe));
@@ -211,7 +213,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_large(const float*
   __syncthreads();
   uint32_t mask = 0;
   for (int shift = 24; shift >= 0; shift -= 8) {
-    hist[threadIdx.x] = 0;
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t prefix = (uint32_t)uniform_i32((int)sh_prefix);
     for (int k = threadIdx.x; k < nlist; k += blockDim.x) {
@@ -455,14 +457,14 @@ hipError_t launch_select_probe(const float* D, const float* gmin, int64_t nq, in
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
       return hipErrorInvalidValue;
-    if (big + 4096 > (size_t)lim) return hipErrorInvalidConfiguration;
+    if (big + 8192 > (size_t)lim) return hipErrorInvalidConfiguration;   // 8 KiB for the static LDS
     static bool big_attr = false;
     if (!big_attr) {
       (void)hipFuncSetAttribute((const void*)k_select_probe_large,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lim - 4096);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim - 8192);
       big_attr = true;
     }
-    hipLaunchKernelGGL(k_select_probe_large, dim3((unsigned)nq), dim3(kSelThreads), big, st, D, nlist,
+    hipLaunchKernelGGL(k_select_probe_large, dim3((unsigned)nq), dim3(kSelLargeThreads), big, st, D, nlist,
                        nprobe, nprobe_q, lists, dists);
     return hipGetLastError();
   }

@@ -381,6 +381,93 @@ __global__ __launch_bounds__(kThreads) void k_plan(SearchDev s) {
   }
 }
 
+// k_plan for a wide probe (nprobe > kPlanWaveMax), one block per query:
+// thread t takes a contiguous run of ranks, the block scans the runs' chunk
+// and code counts, and the first rank whose codes reach s.boot (block
+// minimum) fixes the bootstrap. Same outputs as k_plan.
+constexpr int kPlanWaveMax = 1024;
+constexpr int kPlanThreads = 1024;
+
+__global__ __launch_bounds__(kPlanThreads) void k_plan_block(SearchDev s) {
+  __shared__ int32_t wsum[kPlanThreads / kWave][2];
+  __shared__ int32_t sh_rstar, sh_p0, sh_n0;
+  const int64_t q = blockIdx.x;
+  const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+  int P = s.nprobe;
+  if (s.nprobe_q) P = min(max(s.nprobe_q[q], 1), s.nprobe);
+  int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
+  int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
+  const int per = (s.nprobe + kPlanThreads - 1) / kPlanThreads;
+  const int r0 = min(t * per, s.nprobe), r1 = min(r0 + per, s.nprobe);
+  auto sizes = [&](int r, int& n, int& nc) {
+    const int list = r < P ? s.probe[q * s.nprobe + r] : -1;
+    n = list >= 0 ? s.list_off[list + 1] - s.list_off[list] : 0;
+    nc = (n + s.chunk - 1) / s.chunk;
+  };
+  int sn = 0, sc = 0;
+  for (int r = r0; r < r1; ++r) {
+    int n, nc;
+    sizes(r, n, nc);
+    sn += n;
+    sc += nc;
+  }
+  // block exclusive scan of (sc, sn)
+  int ic = sc, in = sn;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int yc = __shfl_up(ic, o, kWave), yn = __shfl_up(in, o, kWave);
+    if (lane >= o) {
+      ic += yc;
+      in += yn;
+    }
+  }
+  if (lane == kWave - 1) {
+    wsum[wave][0] = ic;
+    wsum[wave][1] = in;
+  }
+  if (t == 0) sh_rstar = INT32_MAX;
+  __syncthreads();
+  int bc = 0, bn = 0, tc = 0, tn = 0;
+  for (int w = 0; w < kPlanThreads / kWave; ++w) {
+    bc += w < wave ? wsum[w][0] : 0;
+    bn += w < wave ? wsum[w][1] : 0;
+    tc += wsum[w][0];
+    tn += wsum[w][1];
+  }
+  int exc = bc + ic - sc, exn = bn + in - sn;
+  int first = INT32_MAX;
+  for (int r = r0; r < r1; ++r) {
+    int n, nc;
+    sizes(r, n, nc);
+    choff[r] = exc;
+    codeoff[r] = exn;
+    if (first == INT32_MAX && exn + n >= s.boot) first = r;
+    exc += nc;
+    exn += n;
+  }
+  if (first != INT32_MAX) atomicMin(&sh_rstar, first);
+  __syncthreads();
+  const int rstar = sh_rstar;
+  if (rstar >= r0 && rstar < r1) {   // the owner of the first rank reaching boot
+    int n, nc;
+    sizes(rstar, n, nc);
+    const int exc_l = choff[rstar], exn_l = codeoff[rstar];
+    const int cstar = (s.boot - exn_l + s.chunk - 1) / s.chunk - 1;
+    sh_p0 = exc_l + cstar + 1;
+    sh_n0 = exn_l + min((cstar + 1) * s.chunk, n);
+  }
+  __syncthreads();
+  if (t == 0) {
+    const bool boot_all = rstar == INT32_MAX;   // fewer than boot codes probed: all bootstrap
+    choff[s.nprobe] = tc;
+    codeoff[s.nprobe] = tn;
+    s.q_nch[q] = tc;
+    s.q_p0[q] = boot_all ? tc : sh_p0;
+    s.q_n0[q] = boot_all ? tn : sh_n0;
+    s.q_ncode[q] = tn;
+  }
+}
+
 // Exclusive prefix sums over queries of five per-query counts (chunks,
 // bootstrap chunks, other chunks, codes, bootstrap codes), in two launches
 // over blocks of kOffQ queries (thread t: queries 4t..4t+3 of the block):
@@ -502,21 +589,26 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets_scan(SearchDev s) {
   }
 }
 
-// One wave per query, a lane per probe rank: the descriptors of its chunks,
+// A lane per probe rank: the descriptors of its chunks,
 // bootstrap ones to units0 (at off_p0[q]) and the others to units1 (at
 // off_p1[q]); and each chunk's first query-code index, for finalize.
+// One wave per (query, 64 probe ranks): the descriptors of those ranks' chunks.
 __device__ __forceinline__ void units_body(const SearchDev& s, int64_t blk) {
-  const int64_t q = blk * kWaves + (threadIdx.x >> 6);
-  if (q >= s.nq) return;
+  const int nrb = (s.nprobe + kWave - 1) / kWave;
+  const int64_t w = blk * kWaves + (threadIdx.x >> 6);
+  if (w >= s.nq * (int64_t)nrb) return;   // whole waves
+  const int64_t q = w / nrb;
   const int lane = lane_id();
   const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
   const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
   const int p0 = s.q_p0[q];
   const int64_t b0 = s.off_p0[q], b1 = s.off_p1[q];
   const int64_t seg0 = s.off_seg[q], n00 = s.off_n0[q], ch0 = s.off_ch[q];
-  for (int r = lane; r < s.nprobe; r += kWave) {
+  {
+    const int r = (int)(w % nrb) * kWave + lane;
+    if (r >= s.nprobe) return;
     const int c0 = choff[r], nc = choff[r + 1] - c0;
-    if (nc == 0) continue;
+    if (nc == 0) return;
     const int64_t g = q * s.nprobe + r;
     const int list = s.probe[g];   // a rank with chunks is an active one
     const int64_t lbeg = s.list_off[list];
@@ -1111,7 +1203,8 @@ hipError_t launch_prep(const SearchDev& s, bool units, hipStream_t st) {
   if (npairs <= 0) return hipSuccess;
   auto grid = [&](int ppw) { return dim3((unsigned)((npairs + ppw * kWaves - 1) / (ppw * kWaves))); };
   const int64_t qblocks = (npairs + 4 * kWaves - 1) / (4 * kWaves);
-  const int64_t ublocks = units ? (s.nq + kWaves - 1) / kWaves : 0;
+  const int64_t nrb = (s.nprobe + kWave - 1) / kWave;
+  const int64_t ublocks = units ? (s.nq * nrb + kWaves - 1) / kWaves : 0;
   if (s.W <= 0 || s.W > 64) return hipErrorInvalidValue;
   switch (s.W) {
     case 1: launch_prep_q<1>(s, ublocks, qblocks, st); return hipGetLastError();
@@ -1135,8 +1228,12 @@ hipError_t launch_prep(const SearchDev& s, bool units, hipStream_t st) {
 
 hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
-  const dim3 gq((unsigned)((s.nq + kWaves - 1) / kWaves));
-  hipLaunchKernelGGL(k_plan, gq, dim3(kThreads), 0, st, s);
+  if (s.nprobe > kPlanWaveMax) {
+    hipLaunchKernelGGL(k_plan_block, dim3((unsigned)s.nq), dim3(kPlanThreads), 0, st, s);
+  } else {
+    const dim3 gq((unsigned)((s.nq + kWaves - 1) / kWaves));
+    hipLaunchKernelGGL(k_plan, gq, dim3(kThreads), 0, st, s);
+  }
   const dim3 gb((unsigned)((s.nq + kOffQ - 1) / kOffQ));
   hipLaunchKernelGGL(k_offsets_sum, gb, dim3(kOffThreads), 0, st, s);
   hipLaunchKernelGGL(k_offsets_scan, gb, dim3(kOffThreads), 0, st, s);
