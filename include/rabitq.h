@@ -93,7 +93,15 @@ typedef struct {
   int64_t qid_base;                /* query i uses id qid_base + i in the rounding RNG */
   int32_t use_graph;               /* 1: run the search as one replay of a captured HIP
                                       graph (see below); 0: launch its kernels directly */
-  int32_t reserved;                /* 0 */
+  int32_t rerank_waves;            /* waves that share one query's rerank: 0 = chosen
+                                      from the call's batch size (1 from 2048 queries
+                                      up, more for smaller batches), n >= 1 = n; at most
+                                      64 and 1024 / k. Each wave reranks a fixed share
+                                      of the query's chunks against its own threshold,
+                                      so the result is the exact top-k of the probed
+                                      lists whenever the bounds hold, for any value;
+                                      which candidates beyond that get reranked (and
+                                      the rerank counts) depend on it */
 } rbq_search_opts;
 
 /* Graph replay (use_graph = 1). The kernel sequence of a search is captured

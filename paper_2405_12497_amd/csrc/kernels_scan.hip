@@ -20,6 +20,8 @@
 //   phase 1: the remaining chunks keep only codes with lb <= tau;
 //   final:   candidates are reranked in probe order with tau tightened after
 //            every round (the running k-th exact distance), giving the top-k.
+#include <algorithm>
+
 #include "rbq_internal.hpp"
 #include "scan_code.hpp"
 #include "wave_select.hpp"
@@ -876,11 +878,21 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
 constexpr int kFinWin = 512;
 constexpr int kFinRoundMax = 128;
 constexpr int kFinGather = 4;   // gather batches of 64 entries loaded together
+constexpr int kFinSplitWaves = 2048;   // batches below this many queries split each query's rerank
+constexpr int kFinSplitMax = 64;       // ... over at most this many waves
 
 __device__ __forceinline__ int fin_lds_words(int k) { return kFinWin + kFinRoundMax + k; }
 
+// With W > 1 (small batches), W waves share a query: wave w takes the
+// query's chunks w, w + W, ... and keeps its own tau (the k-th exact distance
+// among the seeds and its own reranked candidates, never below the query's
+// true k-th distance), so each wave's top-k contains every true top-k member
+// of its chunks whose bound holds; it writes that top-k to part and
+// k_fin_merge keeps the k best distinct keys of the W lists (the seeds appear
+// in all of them).
 template <bool WIDE>
-__global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
+__global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s, int W, uint64_t* __restrict__ part,
+                                                          int32_t* __restrict__ pst) {
   using DS = DistShape<WIDE>;
   extern __shared__ uint64_t fin_lds[];
   const int wave = threadIdx.x >> 6, lane = lane_id();
@@ -888,8 +900,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
     atomicAdd(&s.prof_acc[0], (unsigned long long)s.off_n0[s.nq]);
     atomicAdd(&s.prof_acc[1], (unsigned long long)(s.off_seg[s.nq] - s.off_n0[s.nq]));
   }
-  const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
-  if (q >= s.nq) return;   // whole waves
+  const int64_t wid = (int64_t)blockIdx.x * kWaves + wave;
+  if (wid >= s.nq * W) return;   // whole waves
+  const int64_t q = wid / W;
+  const int wsub = (int)(wid - q * W);
   const int K = s.k;
   uint64_t* win = fin_lds + (size_t)wave * fin_lds_words(K);
   uint64_t* rnd = win + kFinWin;
@@ -908,6 +922,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
   }
   wave_lds_sync();
   float tau = uniform_f32(cnt == K ? __uint_as_float((uint32_t)(top[K - 1] >> 32)) : __builtin_inff());
+  const int seeds = cnt;
   int reranked = cnt, ncand = 0, nk = 0;
   const float* qv = s.q + q * s.dim;
   const int grp = lane / kLpc, sub = lane % kLpc;
@@ -1043,18 +1058,19 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
     nk = 0;
   };
 
-  // gather: chunks in groups of 64 (lane j: chunk j0 + j), entries by a
-  // shuffle scan of the chunk counts
+  // gather: the wave's chunks (wsub, wsub + W, ...) in groups of 64 (lane j:
+  // its chunk j0 + j), entries by a shuffle scan of the chunk counts
   const int nch = uniform_i32(s.q_nch[q]);
+  const int nchw = nch > wsub ? (nch - wsub + W - 1) / W : 0;
   const int64_t seg0 = uniform_i64(s.off_seg[q]);
   const int64_t ch0 = uniform_i64(s.off_ch[q]);
-  for (int j0 = 0; j0 < nch; j0 += kWave) {
+  for (int j0 = 0; j0 < nchw; j0 += kWave) {
     const int j = j0 + lane;
-    const int jc = min(j, nch - 1);   // nch >= 1 inside the loop
+    const int jc = wsub + min(j, nchw - 1) * W;   // nchw >= 1 inside the loop
     int64_t base = seg0 + s.chunk_qcode[ch0 + jc];
     int cj = s.seg_count[ch0 + jc];
-    base = j < nch ? base : 0;
-    cj = j < nch ? cj : 0;
+    base = j < nchw ? base : 0;
+    cj = j < nchw ? cj : 0;
     int incl = cj;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -1101,15 +1117,68 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s) {
     }
   }
   process_window();
-  for (int i = lane; i < K; i += kWave) {
-    const uint64_t v = top[i];
-    const bool live = i < cnt;
-    s.out_ids[q * K + i] = live ? (int64_t)(uint32_t)(v & 0xffffffffu) : (int64_t)-1;
-    s.out_d[q * K + i] = live ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+  if (W == 1) {
+    for (int i = lane; i < K; i += kWave) {
+      const uint64_t v = top[i];
+      const bool live = i < cnt;
+      s.out_ids[q * K + i] = live ? (int64_t)(uint32_t)(v & 0xffffffffu) : (int64_t)-1;
+      s.out_d[q * K + i] = live ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+    }
+    if (lane == 0) {
+      s.q_rerank[q] = reranked;
+      s.q_cand[q] = ncand;
+    }
+  } else {
+    for (int i = lane; i < K; i += kWave) part[wid * K + i] = i < cnt ? top[i] : ~0ull;
+    if (lane == 0) {
+      pst[wid * 2] = reranked - seeds;
+      pst[wid * 2 + 1] = ncand;
+    }
   }
+}
+
+// The k best distinct (distance, id) keys of a query's W partial top-k lists
+// (W K <= kWSelCap), and its statistics: the seeds once plus every wave's own
+// reranks, and every wave's candidates.
+__global__ __launch_bounds__(kThreads) void k_fin_merge(SearchDev s, int W, const uint64_t* __restrict__ part,
+                                                        const int32_t* __restrict__ pst) {
+  __shared__ uint64_t selw[kWaves][kWSelCap];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
+  if (q >= s.nq) return;   // whole waves
+  const int K = s.k, n = W * K;
+  uint64_t* sel = selw[wave];
+  for (int i = lane; i < n; i += kWave) sel[i] = part[q * n + i];
+  wave_sort_sel(sel, n);
+  int out = 0;
+  for (int i0 = 0; i0 < n && out < K; i0 += kWave) {
+    const int i = i0 + lane;
+    const uint64_t x = sel[min(i, n - 1)], prev = sel[max(min(i, n - 1) - 1, 0)];
+    const bool keep = i < n && x != ~0ull && (i == 0 || x != prev);
+    const uint64_t b = __ballot(keep);
+    const int at = out + __popcll(b & lanemask_lt());
+    if (keep && at < K) {
+      s.out_ids[q * K + at] = (int64_t)(uint32_t)(x & 0xffffffffu);
+      s.out_d[q * K + at] = __uint_as_float((uint32_t)(x >> 32));
+    }
+    out += __popcll(b);
+  }
+  for (int i = min(out, K) + lane; i < K; i += kWave) {
+    s.out_ids[q * K + i] = -1;
+    s.out_d[q * K + i] = __builtin_inff();
+  }
+  int rer = 0, cand = 0, seeds = 0;
+  for (int w = lane; w < W; w += kWave) {
+    rer += pst[(q * W + w) * 2];
+    cand += pst[(q * W + w) * 2 + 1];
+  }
+  for (int i = lane; i < K; i += kWave) seeds += s.seedk[q * K + i].id >= 0;
+  rer = wave_sum_i(rer);
+  cand = wave_sum_i(cand);
+  seeds = wave_sum_i(seeds);
   if (lane == 0) {
-    s.q_rerank[q] = reranked;
-    s.q_cand[q] = ncand;
+    s.q_rerank[q] = seeds + rer;
+    s.q_cand[q] = cand;
   }
 }
 
@@ -1251,15 +1320,31 @@ hipError_t launch_tau(const SearchDev& s, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const SearchDev& s, hipStream_t st) {
+int finalize_split(int64_t nq, int k) {
+  if (nq <= 0 || nq >= kFinSplitWaves) return 1;
+  int w = (int)((kFinSplitWaves + nq - 1) / nq);
+  w = std::min(w, kFinSplitMax);
+  w = std::min(w, kWSelCap / std::max(k, 1));
+  return std::max(w, 1);
+}
+
+hipError_t launch_finalize_split(const SearchDev& s, int W, uint64_t* part, int32_t* pst, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
+  if (W < 1 || (W > 1 && (!part || !pst || W * s.k > kWSelCap))) return hipErrorInvalidValue;
   const size_t shm = (size_t)kWaves * (kFinWin + kFinRoundMax + s.k) * sizeof(uint64_t);
-  const dim3 grid((unsigned)((s.nq + kWaves - 1) / kWaves));
+  const dim3 grid((unsigned)((s.nq * W + kWaves - 1) / kWaves));
   if (dist_wide(s.dim))
-    hipLaunchKernelGGL(k_finalize<true>, grid, dim3(kThreads), shm, st, s);
+    hipLaunchKernelGGL(k_finalize<true>, grid, dim3(kThreads), shm, st, s, W, part, pst);
   else
-    hipLaunchKernelGGL(k_finalize<false>, grid, dim3(kThreads), shm, st, s);
+    hipLaunchKernelGGL(k_finalize<false>, grid, dim3(kThreads), shm, st, s, W, part, pst);
+  if (W > 1)
+    hipLaunchKernelGGL(k_fin_merge, dim3((unsigned)((s.nq + kWaves - 1) / kWaves)), dim3(kThreads), 0, st, s, W,
+                       part, pst);
   return hipGetLastError();
+}
+
+hipError_t launch_finalize(const SearchDev& s, hipStream_t st) {
+  return launch_finalize_split(s, 1, nullptr, nullptr, st);
 }
 
 hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, float b, float vl, float delta,

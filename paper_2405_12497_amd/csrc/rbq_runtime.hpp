@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -24,6 +25,18 @@ struct DBuf {
 // Bumped whenever any DBuf is (re)allocated or released: a captured graph
 // holds device addresses and is replayed only while this is unchanged.
 uint64_t buffer_generation();
+// Rerank waves per query for a batch of nq queries with k results (1 for
+// large batches), and the rerank with W waves per query (W > 1 needs part,
+// nq * W * k keys, and pst, nq * W * 2 counters).
+int finalize_split(int64_t nq, int k);
+// Rerank waves for a requested count (0: finalize_split's choice), clamped to
+// 1 .. min(64, 1024 / k).
+inline int fin_waves(int requested, int64_t nq, int k) {
+  if (requested <= 0) return finalize_split(nq, k);
+  const int cap = std::max(1, std::min(64, 1024 / std::max(k, 1)));
+  return std::min(requested, cap);
+}
+hipError_t launch_finalize_split(const SearchDev& s, int W, uint64_t* part, int32_t* pst, hipStream_t st);
 // Bytes of candidate segments a (sub-)batch may use (see rbq_debug_seg_budget).
 int64_t seg_budget();
 void g_seg_budget_set(int64_t b);
@@ -34,6 +47,7 @@ struct GraphEntry {
   int k = 0, nprobe = 0, kernel = 0, chunk = 0;
   bool learned = false, per_query = false;
   int64_t qid_base = 0;
+  int fin_w = 1;          // rerank waves per query
   uint64_t gen = 0;       // buffer_generation() at capture
   uint64_t last_use = 0;
   hipGraphExec_t exec = nullptr;
@@ -49,6 +63,7 @@ struct Workspace {
   DBuf chunk_qcode;   // chunk (query order) -> first query-code index
   DBuf q_rerank, q_cand, nprobe_q, feats, tmp;
   DBuf mf_cnt, mf_fill, mf_pair_off, mf_unit_off, mf_pairs, units0, units1;
+  DBuf fin_part, fin_pst;   // split rerank of small batches: partial top-k lists, statistics
 };
 
 struct ProfState {
@@ -136,7 +151,8 @@ rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int 
 rbq_status mlp_reserve(rbq_index* idx, int64_t rows);
 rbq_status rotate_rows(rbq_index* idx, const float* X, int64_t lda, const float* sub,
                        const int32_t* sel, int64_t M, float* Y, hipStream_t st);
-rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma);
+rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma,
+                            int fin_w = 1);
 SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe, int k, int chunk,
                    const int32_t* nprobe_q, int64_t qid_base, bool mfma, int64_t* out_ids,
                    float* out_d);

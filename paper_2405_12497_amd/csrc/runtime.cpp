@@ -241,7 +241,7 @@ std::vector<DBuf*> rbq_index::all_buffers() {
           &ws.chunk_qcode,
           &ws.seedk, &ws.q_rerank, &ws.q_cand, &ws.nprobe_q, &ws.feats, &ws.tmp,
           &ws.mf_cnt, &ws.mf_fill, &ws.mf_pair_off, &ws.mf_unit_off, &ws.mf_pairs, &ws.units0,
-          &ws.units1,
+          &ws.units1, &ws.fin_part, &ws.fin_pst,
           &mlp.w32, &mlp.wbf, &mlp.grad, &mlp.m, &mlp.v, &mlp.act};
 }
 
@@ -509,7 +509,7 @@ extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t
 // ------------------------------------------------------------------ search
 namespace rbq {
 
-rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma) {
+rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma, int fin_w) {
   Workspace& w = idx->ws;
   const int dp = idx->dp, W = idx->W;
   const int64_t np = nq * nprobe;
@@ -546,6 +546,10 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.seedk.ensure((size_t)nq * k * sizeof(SeedEnt)));
   HIPCHK(w.q_rerank.ensure((size_t)nq * 4));
   HIPCHK(w.q_cand.ensure((size_t)nq * 4));
+  if (fin_w > 1) {
+    HIPCHK(w.fin_part.ensure((size_t)nq * fin_w * k * 8));
+    HIPCHK(w.fin_pst.ensure((size_t)nq * fin_w * 2 * 4));
+  }
   return RBQ_OK;
 }
 
@@ -667,7 +671,8 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   // lists: the features read those, and the search reuses the selection with
   // its per-query nprobe (at most the caller's nprobe).
   if (learned) o.nprobe = std::max(o.nprobe, std::min(kMlpNear, idx->nlist));
-  rbq_status rs = ensure_workspace(idx, nq, o.nprobe, o.k, chunk, mfma);
+  const int fin_w = fin_waves(o.rerank_waves, nq, o.k);
+  rbq_status rs = ensure_workspace(idx, nq, o.nprobe, o.k, chunk, mfma, fin_w);
   if (rs != RBQ_OK) return rs;
   ProfState& pf = idx->prof;
   hipEvent_t ev[7] = {};
@@ -720,7 +725,7 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   }
   HIPCHK(rec(5));
   s.prof_acc = pf.on ? (unsigned long long*)pf.acc.p : nullptr;   // codes counted by finalize
-  HIPCHK(launch_finalize(s, st));
+  HIPCHK(launch_finalize_split(s, fin_w, (uint64_t*)idx->ws.fin_part.p, (int32_t*)idx->ws.fin_pst.p, st));
   HIPCHK(rec(6));
   return RBQ_OK;
 }
@@ -742,7 +747,7 @@ int64_t graph_rows(int64_t nq) {
 __attribute__((unused)) bool same_shape(const GraphEntry& g, const GraphEntry& k) {
   return g.nqb == k.nqb && g.k == k.k && g.nprobe == k.nprobe && g.kernel == k.kernel &&
          g.chunk == k.chunk && g.learned == k.learned && g.per_query == k.per_query &&
-         g.qid_base == k.qid_base;
+         g.qid_base == k.qid_base && g.fin_w == k.fin_w;
 }
 }  // namespace
 
@@ -759,6 +764,7 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
   key.learned = learned;
   key.per_query = !learned;   // non-learned graphs always read a staged per-query nprobe
   key.qid_base = o.qid_base;
+  key.fin_w = fin_waves(o.rerank_waves, nq, o.k);
   const int64_t nqb = key.nqb;
   // Graph mode sizes the workspace and staging for a row count that grows by
   // powers of two (at least 1024), so that batches of varying size do not
@@ -780,7 +786,7 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
   const int64_t seg_row = std::max<int64_t>(1, idx->max_codes(stride)) * (int64_t)sizeof(Cand);
   while (hint > nqb && hint * seg_row > idx->graph_mem_cap) hint = std::max(nqb, hint / 2);
   {
-    rbq_status rs = ensure_workspace(idx, hint, stride, o.k, chunk, kernel == RBQ_SCAN_MFMA);
+    rbq_status rs = ensure_workspace(idx, hint, stride, o.k, chunk, kernel == RBQ_SCAN_MFMA, key.fin_w);
     if (rs != RBQ_OK) return rs;
     if (learned) {
       HIPCHK(idx->ws.feats.ensure((size_t)hint * kMlpIn * 4));
@@ -894,6 +900,7 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
   if (o.nprobe < 1 || o.nprobe > std::min(idx->nlist, kMaxNprobe))
     return fail(RBQ_EINVAL, "nprobe=%d outside [1, %d]", o.nprobe, std::min(idx->nlist, kMaxNprobe));
   if (o.use_graph != 0 && o.use_graph != 1) return fail(RBQ_EINVAL, "use_graph must be 0 or 1");
+  if (o.rerank_waves < 0) return fail(RBQ_EINVAL, "rerank_waves must be >= 0");
   if (o.scan_kernel < RBQ_SCAN_AUTO || o.scan_kernel > RBQ_SCAN_MFMA)
     return fail(RBQ_EINVAL, "unknown scan_kernel %d", o.scan_kernel);
   if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
@@ -952,6 +959,9 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
   for (int64_t q0 = 0; q0 < nq; q0 += sub) {
     const int64_t m = std::min(sub, nq - q0);
     rbq_search_opts os = o;
+    // from the whole call's size, rounded as graph replay rounds it, so that eager
+    // and graph searches of one batch agree and a graph serves its size bucket
+    os.rerank_waves = fin_waves(o.rerank_waves, graph_rows(nq), o.k);
     os.qid_base = o.qid_base + q0;
     if (o.nprobe_per_query) os.nprobe_per_query = o.nprobe_per_query + q0;
     const float* qs = queries + q0 * idx->dim;

@@ -30,7 +30,7 @@ class RbqParams(C.Structure):
 class RbqSearchOpts(C.Structure):
     _fields_ = [("k", C.c_int32), ("nprobe", C.c_int32), ("scan_kernel", C.c_int32),
                 ("use_learned_nprobe", C.c_int32), ("nprobe_per_query", C.c_void_p),
-                ("qid_base", C.c_int64), ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+                ("qid_base", C.c_int64), ("use_graph", C.c_int32), ("rerank_waves", C.c_int32)]
 
 
 class RbqSearchStats(C.Structure):
@@ -187,7 +187,7 @@ def rbq_index_build(idx, data, centroids, assign, gauss=None, stream=None):
 
 def rbq_search(idx, queries, k, nprobe, scan_kernel=RBQ_SCAN_AUTO, use_learned_nprobe=False,
                nprobe_per_query=None, qid_base=0, stats=False, out_ids=None, out_dists=None,
-               stream=None, use_graph=False):
+               stream=None, use_graph=False, rerank_waves=0):
     """queries: float32 GPU tensor [nq, dim]. Returns (ids int64 [nq,k], dists float32 [nq,k], stats|None)."""
     import torch
     nq = queries.shape[0]
@@ -196,7 +196,7 @@ def rbq_search(idx, queries, k, nprobe, scan_kernel=RBQ_SCAN_AUTO, use_learned_n
     if out_dists is None:
         out_dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
     o = RbqSearchOpts(k, nprobe, scan_kernel, int(bool(use_learned_nprobe)),
-                      _dev(nprobe_per_query, torch.int32), qid_base, int(bool(use_graph)), 0)
+                      _dev(nprobe_per_query, torch.int32), qid_base, int(bool(use_graph)), int(rerank_waves))
     st = RbqSearchStats()
     _check(lib().rbq_search(idx, _dev(queries, torch.float32), nq, C.byref(o),
                             _dev(out_ids, torch.int64), _dev(out_dists, torch.float32),

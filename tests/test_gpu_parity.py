@@ -195,10 +195,13 @@ def _violations(b, lists, qi, top_ids, top_d):
 
 
 @pytest.mark.parametrize("name", CASES)
-def test_search_returns_exact_topk_of_probed_lists(name):
+@pytest.mark.parametrize("waves", [0, 1, 5])
+def test_search_returns_exact_topk_of_probed_lists(name, waves):
+    """waves: rerank waves per query (0: the library's choice, which splits
+    every query's rerank for these small batches; 1: one wave; 5: five)."""
     b = built(name)
     c = b.case
-    ids, d, st = b.search(scan_kernel=b.R.RBQ_SCAN_POPCNT, stats=True)
+    ids, d, st = b.search(scan_kernel=b.R.RBQ_SCAN_POPCNT, stats=True, rerank_waves=waves)
     lists, _ = b.probe()
     flagged = mism = 0
     for qi, q in enumerate(c.queries):
