@@ -781,17 +781,25 @@ __device__ __forceinline__ uint32_t sortable_bits(float x) {
 // best of them by (distance, id) seed the top-k and tau = the k-th. The others
 // cannot enter the top-k (k better ones are known), so all m segment entries
 // are marked done (pos = -1).
+// With W > 1 (small batches, large k), W waves share a query: each makes the
+// same selection, reranks its share [m w / W, m (w + 1) / W) of it and writes
+// those exact keys to tpart (stride min(kMaxK, 4k) per query); k_tau_merge
+// sorts them and writes the seeds and tau.
 template <bool WIDE>
-__global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
+__global__ __launch_bounds__(kThreads) void k_tau(SearchDev s, int W, uint64_t* __restrict__ tpart) {
   using DS = DistShape<WIDE>;
   __shared__ uint64_t selw[kWaves][kWSelCap];
   const int wave = threadIdx.x >> 6, lane = lane_id();
-  const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
-  if (q >= s.nq) return;   // whole waves
+  const int64_t wid = (int64_t)blockIdx.x * kWaves + wave;
+  if (wid >= s.nq * W) return;   // whole waves
+  const int64_t q = wid / W;
+  const int wsub = (int)(wid - q * W);
   uint64_t* sel = selw[wave];
   const int n0 = uniform_i32(s.q_n0[q]);
   const int64_t b0 = uniform_i64(s.off_n0[q]);
-  const int m = min(n0, min(kMaxK, 4 * s.k));
+  const int mstride = min(kMaxK, 4 * s.k);
+  const int m = min(n0, mstride);
+  const int lo = (int)((int64_t)m * wsub / W), hi = (int)((int64_t)m * (wsub + 1) / W);
   if (m > 0) {
     const EstEnt* est = s.p0buf + b0;
     wave_smallest<8, kMaxP0 / kWave>([&](int i) { return __float_as_uint(est[i].dist); },
@@ -800,7 +808,7 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
     const float* qv = s.q + q * s.dim;
     const int grp = lane / kLpc, sub = lane % kLpc;
     constexpr int kGroups = kWave / kLpc;
-    // passes of up to 64 selected codes: entry base + grp + 8 j, j < NC (a
+    // passes over the wave's share [lo, hi): entry base + grp + 8 j, j < NC (a
     // bootstrap entry's index is its slot in the query's segment)
     auto run = [&](int base, auto nc_tag) {
       constexpr int NC = decltype(nc_tag)::value;
@@ -810,7 +818,7 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         const int i = base + grp + j * kGroups;
-        slot[j] = (int32_t)(uint32_t)(sel[min(i, m - 1)] & 0xffffffffu);
+        slot[j] = (int32_t)(uint32_t)(sel[min(i, hi - 1)] & 0xffffffffu);
       }
 #pragma unroll
       for (int j = 0; j < NC; ++j) pos[j] = est[slot[j]].pos;
@@ -818,7 +826,7 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
       for (int j = 0; j < NC; ++j) keep_loaded(pos[j]);
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
-        const bool in = base + grp + j * kGroups < m;
+        const bool in = base + grp + j * kGroups < hi;
         slot[j] = in ? slot[j] : -1;
         pos[j] = in ? pos[j] : -1;
       }
@@ -836,22 +844,51 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s) {
         const int i = base + grp + j * kGroups;
         // exact distances are >= 0, so their bits order like the values; ids < 2^31
         const uint64_t v = ((uint64_t)__float_as_uint(d[j]) << 32) | id[j];
-        if (sub == 0 && i < m) {
+        if (sub == 0 && i < hi) {
           s.seg[seg0 + slot[j]].pos = -1;
           sel[i] = v;
         }
       }
       wave_lds_sync();
     };
-    for (int base = 0; base < m; base += kGroups * DS::kMaxNC) {
-      const int per = (min(m - base, kGroups * DS::kMaxNC) + kGroups - 1) / kGroups;
+    for (int base = lo; base < hi; base += kGroups * DS::kMaxNC) {
+      const int per = (min(hi - base, kGroups * DS::kMaxNC) + kGroups - 1) / kGroups;
       if (per <= 1) run(base, IntC<1>{});
       else if (per <= 2) run(base, IntC<2>{});
       else if (per <= 4 || DS::kMaxNC == 4) run(base, IntC<4>{});
       else run(base, IntC<DS::kMaxNC>{});
     }
+    if (W > 1) {
+      for (int i = lo + lane; i < hi; i += kWave) tpart[q * mstride + i] = sel[i];
+      return;
+    }
     wave_sort_sel(sel, m);
+  } else if (W > 1) {
+    return;   // the merge writes the empty seeds
   }
+  for (int i = lane; i < s.k; i += kWave) {
+    SeedEnt e;
+    const bool live = i < min(m, s.k);
+    const uint64_t v = live ? sel[i] : 0;
+    e.dist = live ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+    e.id = live ? (int32_t)(uint32_t)(v & 0xffffffffu) : -1;
+    s.seedk[q * s.k + i] = e;
+  }
+  if (lane == 0) s.tau[q] = (m >= s.k) ? __uint_as_float((uint32_t)(sel[s.k - 1] >> 32)) : __builtin_inff();
+}
+
+// The seeds and tau of a query whose bootstrap rerank was shared by several
+// waves: its m exact keys from tpart, sorted.
+__global__ __launch_bounds__(kThreads) void k_tau_merge(SearchDev s, const uint64_t* __restrict__ tpart) {
+  __shared__ uint64_t selw[kWaves][kMaxK];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
+  if (q >= s.nq) return;   // whole waves
+  uint64_t* sel = selw[wave];
+  const int mstride = min(kMaxK, 4 * s.k);
+  const int m = min(uniform_i32(s.q_n0[q]), mstride);
+  for (int i = lane; i < m; i += kWave) sel[i] = tpart[q * mstride + i];
+  if (m > 0) wave_sort_sel(sel, m);
   for (int i = lane; i < s.k; i += kWave) {
     SeedEnt e;
     const bool live = i < min(m, s.k);
@@ -1310,15 +1347,26 @@ hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
 }
 
 
-hipError_t launch_tau(const SearchDev& s, hipStream_t st) {
+int tau_split(int fin_w, int k) {
+  const int m = std::min(kMaxK, 4 * k);
+  return std::max(1, std::min(fin_w, m / 32));   // at least 32 entries per wave
+}
+
+hipError_t launch_tau_split(const SearchDev& s, int W, uint64_t* tpart, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((s.nq + kWaves - 1) / kWaves));
+  if (W < 1 || (W > 1 && !tpart)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((s.nq * W + kWaves - 1) / kWaves));
   if (dist_wide(s.dim))
-    hipLaunchKernelGGL(k_tau<true>, grid, dim3(kThreads), 0, st, s);
+    hipLaunchKernelGGL(k_tau<true>, grid, dim3(kThreads), 0, st, s, W, tpart);
   else
-    hipLaunchKernelGGL(k_tau<false>, grid, dim3(kThreads), 0, st, s);
+    hipLaunchKernelGGL(k_tau<false>, grid, dim3(kThreads), 0, st, s, W, tpart);
+  if (W > 1)
+    hipLaunchKernelGGL(k_tau_merge, dim3((unsigned)((s.nq + kWaves - 1) / kWaves)), dim3(kThreads), 0, st, s,
+                       tpart);
   return hipGetLastError();
 }
+
+hipError_t launch_tau(const SearchDev& s, hipStream_t st) { return launch_tau_split(s, 1, nullptr, st); }
 
 int finalize_split(int64_t nq, int k) {
   if (nq <= 0 || nq >= kFinSplitWaves) return 1;

@@ -29,6 +29,11 @@ uint64_t buffer_generation();
 // large batches), and the rerank with W waves per query (W > 1 needs part,
 // nq * W * k keys, and pst, nq * W * 2 counters).
 int finalize_split(int64_t nq, int k);
+// Waves sharing a query's bootstrap rerank (at least 32 of its min(256, 4k)
+// codes each), and that rerank with W waves (W > 1 needs tpart, nq *
+// min(256, 4k) keys).
+int tau_split(int fin_w, int k);
+hipError_t launch_tau_split(const SearchDev& s, int W, uint64_t* tpart, hipStream_t st);
 // Rerank waves for a requested count (0: finalize_split's choice), clamped to
 // 1 .. min(64, 1024 / k).
 inline int fin_waves(int requested, int64_t nq, int k) {
@@ -64,6 +69,7 @@ struct Workspace {
   DBuf q_rerank, q_cand, nprobe_q, feats, tmp;
   DBuf mf_cnt, mf_fill, mf_pair_off, mf_unit_off, mf_pairs, units0, units1;
   DBuf fin_part, fin_pst;   // split rerank of small batches: partial top-k lists, statistics
+  DBuf tau_part;            // split bootstrap rerank: exact keys, min(256, 4k) per query
 };
 
 struct ProfState {

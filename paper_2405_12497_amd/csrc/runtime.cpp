@@ -241,7 +241,7 @@ std::vector<DBuf*> rbq_index::all_buffers() {
           &ws.chunk_qcode,
           &ws.seedk, &ws.q_rerank, &ws.q_cand, &ws.nprobe_q, &ws.feats, &ws.tmp,
           &ws.mf_cnt, &ws.mf_fill, &ws.mf_pair_off, &ws.mf_unit_off, &ws.mf_pairs, &ws.units0,
-          &ws.units1, &ws.fin_part, &ws.fin_pst,
+          &ws.units1, &ws.fin_part, &ws.fin_pst, &ws.tau_part,
           &mlp.w32, &mlp.wbf, &mlp.grad, &mlp.m, &mlp.v, &mlp.act};
 }
 
@@ -550,6 +550,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
     HIPCHK(w.fin_part.ensure((size_t)nq * fin_w * k * 8));
     HIPCHK(w.fin_pst.ensure((size_t)nq * fin_w * 2 * 4));
   }
+  if (tau_split(fin_w, k) > 1) HIPCHK(w.tau_part.ensure((size_t)nq * std::min(kMaxK, 4 * k) * 8));
   return RBQ_OK;
 }
 
@@ -716,7 +717,7 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   HIPCHK(rec(2));
   HIPCHK(launch_scan_popcnt(s, 0, grid0, st));
   HIPCHK(rec(3));
-  HIPCHK(launch_tau(s, st));
+  HIPCHK(launch_tau_split(s, tau_split(fin_w, o.k), (uint64_t*)idx->ws.tau_part.p, st));
   HIPCHK(rec(4));
   if (mfma) {
     HIPCHK(launch_scan_mfma(s, 1, scan_grid(idx, nq, chunks, scan_mfma_blocks_per_cu(idx->dp)), st));
