@@ -260,6 +260,75 @@ __global__ __launch_bounds__(256) void k_gemm_rot_cdist(GemmJob rot, GemmJob cd,
     gemm_tile<1, 4>(cd, (t - rot_tiles) % cd_tm, (t - rot_tiles) / cd_tm, L);
 }
 
+// ---------------------------------------------------------------- few-query centroid distances
+// MODE 1 for at most MQ <= 8 query rows, as dot products over the transposed
+// centroids B = Ct [K][N] (a GEMM tile would leave most of its rows empty and
+// walk K in short steps). Block b covers columns 64 b .. 64 b + 63, one per
+// lane; its 16 waves split K into 16 slices, each lane summing its column's
+// MQ products over its wave's slice (each load a contiguous 256-byte row piece
+// per wave), and the wave partials (and the slices' squared row norms) are
+// added in wave order.
+constexpr int kCdThreads = 1024, kCdWaves = kCdThreads / kWave, kCdUnroll = 16;
+
+template <int MQ>
+__global__ __launch_bounds__(kCdThreads) void k_cdist_few(const float* __restrict__ A, int64_t lda, int64_t M,
+                                                          const float* __restrict__ B, int64_t ldb, int N, int K,
+                                                          const float* __restrict__ bn, float* __restrict__ Y,
+                                                          int64_t ldy) {
+  __shared__ float part[kCdWaves][MQ][kWave];
+  __shared__ float nrm[kCdWaves][MQ];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int n = blockIdx.x * kWave + lane;
+  const int nc = min(n, N - 1);
+  const int ks = (K + kCdWaves - 1) / kCdWaves;
+  const int k0 = min(K, wave * ks), k1 = min(K, k0 + ks);
+  const float* arow[MQ];
+#pragma unroll
+  for (int m = 0; m < MQ; ++m) arow[m] = A + (int64_t)min<int64_t>(m, M - 1) * lda;   // rows >= M: discarded
+  float acc[MQ], sq[MQ];
+#pragma unroll
+  for (int m = 0; m < MQ; ++m) acc[m] = sq[m] = 0.f;
+  for (int kb = k0; kb < k1; kb += kCdUnroll) {
+    float c[kCdUnroll];
+#pragma unroll
+    for (int u = 0; u < kCdUnroll; ++u) c[u] = B[(int64_t)min(kb + u, k1 - 1) * ldb + nc];
+#pragma unroll
+    for (int u = 0; u < kCdUnroll; ++u) {
+      if (kb + u < k1) {
+#pragma unroll
+        for (int m = 0; m < MQ; ++m) {
+          const float a = arow[m][kb + u];
+          acc[m] = fmaf(a, c[u], acc[m]);
+          sq[m] = fmaf(a, a, sq[m]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < MQ; ++m) part[wave][m][lane] = acc[m];
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < MQ; ++m) nrm[wave][m] = sq[m];
+  }
+  __syncthreads();
+  if (wave == 0 && n < N) {
+    const float cb = bn[n];
+#pragma unroll
+    for (int m = 0; m < MQ; ++m) {
+      if (m >= M) break;
+      float dot = 0.f, an = 0.f;
+#pragma unroll
+      for (int w = 0; w < kCdWaves; ++w) {
+        dot += part[w][m][lane];
+        an += nrm[w][m];
+      }
+      Y[(int64_t)m * ldy + n] = fmaxf(an + cb - 2.f * dot, 0.f);
+    }
+  }
+}
+
+constexpr int kCdFewMax = 8;   // query rows handled by k_cdist_few
+
 }  // namespace
 
 bool gemm_f32_wide_tile(int64_t M, int N) { return ((M + 127) / 128) * (((int64_t)N + 127) / 128) >= 1024; }
@@ -272,6 +341,19 @@ void launch_f32_mfma(const float* A, int64_t lda, const float* sub, const int32_
                      float* gmin, hipStream_t st) {
   // the 128 tile when it still gives at least 1024 blocks, else the 64 tile
   const GemmJob j{A, lda, sub, sel, B, ldb, Y, ldy, M, N, K, bn, gmin};
+  if (M <= 0) return;
+  if (MODE == 1 && M <= kCdFewMax && !sel && !gmin) {
+    const dim3 grid((unsigned)((N + kWave - 1) / kWave));
+    if (M <= 1)
+      hipLaunchKernelGGL(k_cdist_few<1>, grid, dim3(kCdThreads), 0, st, A, lda, M, B, ldb, N, K, bn, Y, ldy);
+    else if (M <= 2)
+      hipLaunchKernelGGL(k_cdist_few<2>, grid, dim3(kCdThreads), 0, st, A, lda, M, B, ldb, N, K, bn, Y, ldy);
+    else if (M <= 4)
+      hipLaunchKernelGGL(k_cdist_few<4>, grid, dim3(kCdThreads), 0, st, A, lda, M, B, ldb, N, K, bn, Y, ldy);
+    else
+      hipLaunchKernelGGL(k_cdist_few<8>, grid, dim3(kCdThreads), 0, st, A, lda, M, B, ldb, N, K, bn, Y, ldy);
+    return;
+  }
   if (gemm_f32_wide_tile(M, N)) {
     dim3 grid((unsigned)((M + 127) / 128), (N + 127) / 128);
     hipLaunchKernelGGL((k_gemm_f32_mfma<MODE, 4>), grid, dim3(256), 0, st, j);

@@ -282,6 +282,79 @@ __global__ __launch_bounds__(kSelLargeThreads) void k_select_probe_large(const f
   }
 }
 
+// ------------------------------------------------------------------ rank select
+// Few queries with a large nprobe: the selection as ranks, spread over many
+// blocks instead of one block per query. A list's rank in its query's row is
+// the number of lists whose key (distance bits, then list id) is smaller; the
+// lists of rank < P land in slot rank. Block (b, q) ranks lists
+// 16 b .. 16 b + 15 of query q: each of its 512 threads holds KP keys of the
+// row (lists t + 512 r) in registers and counts those below each of the 16
+// keys, and the counts are summed over the block. nlist^2 compares per query.
+constexpr int kRankThreads = 512, kRankElems = 16;
+
+template <int KP>
+__global__ __launch_bounds__(kRankThreads) void k_select_probe_rank(const float* __restrict__ D, int nlist,
+                                                                    int nprobe,
+                                                                    const int32_t* __restrict__ nprobe_q,
+                                                                    int32_t* __restrict__ lists,
+                                                                    float* __restrict__ dists) {
+  __shared__ int part[kRankThreads / kWave][kRankElems];
+  const int64_t q = blockIdx.y;
+  const int i0 = blockIdx.x * kRankElems;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+  int P = nprobe;
+  if (nprobe_q) P = uniform_i32(min(max(nprobe_q[q], 1), nprobe));
+  P = min(P, nlist);
+  const float* row = D + q * (int64_t)nlist;
+  auto key_of = [&](int k) {
+    return ((uint64_t)__float_as_uint(fmaxf(row[k], 0.f)) << 32) | (uint32_t)k;
+  };
+  uint64_t kj[KP];
+#pragma unroll
+  for (int r = 0; r < KP; ++r) {
+    const int j = tid + kRankThreads * r;
+    kj[r] = key_of(min(j, nlist - 1));
+  }
+#pragma unroll
+  for (int r = 0; r < KP; ++r) kj[r] = tid + kRankThreads * r < nlist ? kj[r] : ~0ull;
+  int cnt[kRankElems];
+#pragma unroll
+  for (int e = 0; e < kRankElems; ++e) {
+    const uint64_t ki = key_of(min(i0 + e, nlist - 1));   // the same for every lane
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < KP; ++r) c += kj[r] < ki ? 1 : 0;
+    cnt[e] = c;
+  }
+#pragma unroll
+  for (int e = 0; e < kRankElems; ++e) {
+    const int c = wave_sum_i(cnt[e]);
+    if (lane == 0) part[wave][e] = c;
+  }
+  __syncthreads();
+  if (tid < kRankElems && i0 + tid < nlist) {
+    int rank = 0;
+#pragma unroll
+    for (int w = 0; w < kRankThreads / kWave; ++w) rank += part[w][tid];
+    if (rank < P) {
+      const int i = i0 + tid;
+      lists[q * nprobe + rank] = i;
+      if (dists) dists[q * nprobe + rank] = fmaxf(row[i], 0.f);
+    }
+  }
+  if (blockIdx.x == 0) {
+    for (int i = P + tid; i < nprobe; i += kRankThreads) {
+      lists[q * nprobe + i] = -1;
+      if (dists) dists[q * nprobe + i] = __builtin_inff();
+    }
+  }
+}
+
+// The rank selection's cost bound: at most 16 queries and nq * nlist^2 <= 2^31.
+bool rank_select(int64_t nq, int nlist) {
+  return nq <= 16 && nlist <= kRankThreads * 32 && (double)nq * nlist * nlist <= 2147483648.0;
+}
+
 // ------------------------------------------------------------------ wave select
 // One wave per query for nprobe <= kWSelMaxP: the wave selection over the
 // query's distance row (keys: distance bits, non-negative floats ordering like
@@ -447,6 +520,23 @@ hipError_t launch_select_probe(const float* D, const float* gmin, int64_t nq, in
     else
       hipLaunchKernelGGL((k_select_probe_grp<kGrpMaxG / kWave>), grid, dim3(kSelThreads), 0, st, D, gmin, nq,
                          nlist, nprobe, nprobe_q, lists, dists);
+    return hipGetLastError();
+  }
+  if (nprobe > kWSelMaxP && rank_select(nq, nlist)) {
+    const dim3 grid((unsigned)((nlist + kRankElems - 1) / kRankElems), (unsigned)nq);
+    const int kp = (nlist + kRankThreads - 1) / kRankThreads;
+    if (kp <= 1)
+      hipLaunchKernelGGL(k_select_probe_rank<1>, grid, dim3(kRankThreads), 0, st, D, nlist, nprobe, nprobe_q, lists, dists);
+    else if (kp <= 2)
+      hipLaunchKernelGGL(k_select_probe_rank<2>, grid, dim3(kRankThreads), 0, st, D, nlist, nprobe, nprobe_q, lists, dists);
+    else if (kp <= 4)
+      hipLaunchKernelGGL(k_select_probe_rank<4>, grid, dim3(kRankThreads), 0, st, D, nlist, nprobe, nprobe_q, lists, dists);
+    else if (kp <= 8)
+      hipLaunchKernelGGL(k_select_probe_rank<8>, grid, dim3(kRankThreads), 0, st, D, nlist, nprobe, nprobe_q, lists, dists);
+    else if (kp <= 16)
+      hipLaunchKernelGGL(k_select_probe_rank<16>, grid, dim3(kRankThreads), 0, st, D, nlist, nprobe, nprobe_q, lists, dists);
+    else
+      hipLaunchKernelGGL(k_select_probe_rank<32>, grid, dim3(kRankThreads), 0, st, D, nlist, nprobe, nprobe_q, lists, dists);
     return hipGetLastError();
   }
   if (nprobe > kSelCap) {

@@ -7,7 +7,10 @@ larger than the number of list groups, the grouped selection (nprobe <= 64
 on batches whose centroid product uses 128-wide tiles, so the group minima
 exist: ceil(nq / 128) * ceil(nlist / 128) >= 1024), the full-row wave
 selection (nprobe > 64, and a small batch), 16,384 lists, exact ties from
-duplicated centroids and queries placed on centroids."""
+duplicated centroids and queries placed on centroids. Batches of at most 16
+queries with nprobe above 256 take the rank selection, and batches of at
+most 8 queries the few-row distance kernel, whose distances are also checked
+against FP64."""
 import sys
 
 import numpy as np
@@ -61,6 +64,55 @@ def test_probe_selection_exact_on_gpu_distances(dim, nlist, nq, dup):
         assert np.all(D >= 0) and np.all(np.isfinite(D))
         order = np.argsort(D, axis=1, kind="stable")
         for nprobe in NPROBES:
+            if nprobe > nlist:
+                continue
+            lists, d = R.rbq_debug_probe(idx.h, qt, nprobe)
+            lists, d = lists.cpu().numpy(), d.cpu().numpy()
+            want = order[:, :nprobe]
+            np.testing.assert_array_equal(lists, want, err_msg=f"nprobe={nprobe}")
+            np.testing.assert_array_equal(d, np.take_along_axis(D, want, 1), err_msg=f"nprobe={nprobe}")
+    finally:
+        idx.close()
+
+
+FEW_CASES = [
+    # dim, nlist, nq, duplicated centroids
+    (32, 300, 1, True),
+    (48, 1000, 3, True),
+    (128, 4096, 8, False),
+    (64, 2500, 16, True),
+    (96, 16384, 1, False),
+    (200, 5000, 5, False),
+]
+
+
+@pytest.mark.parametrize("dim,nlist,nq,dup", FEW_CASES, ids=[f"n{c[1]}q{c[2]}" + ("dup" if c[3] else "") for c in FEW_CASES])
+def test_few_query_probe_selection_exact(dim, nlist, nq, dup):
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    _say(f"few-query probe selection dim={dim} nlist={nlist} nq={nq} dup={dup}")
+    rng = np.random.default_rng(7 * nlist + dim)
+    cent = (rng.standard_normal((nlist, dim)) * 2).astype(np.float32)
+    if dup:
+        lo, hi = nlist // 5, nlist // 2
+        cent[lo:hi] = cent[lo - 1]
+    n = 2 * nlist + 64
+    data = (cent[rng.integers(0, nlist, n)] + rng.standard_normal((n, dim))).astype(np.float32)
+    assign = rng.integers(0, nlist, n).astype(np.int32)
+    q = (cent[rng.integers(0, nlist, nq)] + rng.standard_normal((nq, dim))).astype(np.float32)
+    q[::3] = cent[rng.integers(0, nlist, len(q[::3]))]   # on a centroid: distance 0
+    idx = R.Index(dim, nlist, seed=9)
+    try:
+        idx.build(data, cent, assign)
+        qt = torch.from_numpy(q).to("cuda")
+        D = R.rbq_debug_centroid_dists(idx.h, qt, nlist).cpu().numpy()
+        # FP32 sums of dim products: within 1e-5 of the scale |q|^2 + |c|^2
+        q64, c64 = q.astype(np.float64), cent.astype(np.float64)
+        exact = ((q64[:, None, :] - c64[None]) ** 2).sum(-1)
+        scale = (q64 ** 2).sum(1)[:, None] + (c64 ** 2).sum(1)[None]
+        assert np.all(np.abs(D - exact) <= 1e-5 * scale + 1e-6)
+        order = np.argsort(D, axis=1, kind="stable")
+        for nprobe in (1, 64, 256, 257, 1000, 2048, 2049, nlist):
             if nprobe > nlist:
                 continue
             lists, d = R.rbq_debug_probe(idx.h, qt, nprobe)
