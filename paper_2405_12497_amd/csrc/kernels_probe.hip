@@ -9,25 +9,6 @@ namespace {
 constexpr int kSelThreads = 256;
 constexpr int kSelCap = 2048;   // nprobe handled with the keys in LDS; above: k_select_probe_large
 
-// Bitonic sort of n (power of two) 64-bit keys in LDS, ascending.
-__device__ void bitonic_sort_u64(uint64_t* a, int n) {
-  for (int size = 2; size <= n; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
-        const int lo = 2 * i - (i & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = ((lo & size) == 0);
-        const uint64_t x = a[lo], y = a[hi];
-        if ((x > y) == up) {
-          a[lo] = y;
-          a[hi] = x;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 // keys: distances as uint32 (non-negative floats order like their bit patterns).
 // Radix select of the P-th smallest key, then ordered collection of ties.
 __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __restrict__ D,

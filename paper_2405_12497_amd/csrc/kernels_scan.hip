@@ -389,6 +389,8 @@ __global__ __launch_bounds__(kThreads) void k_plan(SearchDev s) {
 // minimum) fixes the bootstrap. Same outputs as k_plan.
 constexpr int kPlanWaveMax = 1024;
 constexpr int kPlanThreads = 1024;
+constexpr int kPlanPer = 16;   // ranks per thread
+static_assert(kMaxNprobe <= kPlanThreads * kPlanPer, "k_plan_block covers every rank");
 
 __global__ __launch_bounds__(kPlanThreads) void k_plan_block(SearchDev s) {
   __shared__ int32_t wsum[kPlanThreads / kWave][2];
@@ -401,17 +403,41 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_block(SearchDev s) {
   int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
   const int per = (s.nprobe + kPlanThreads - 1) / kPlanThreads;
   const int r0 = min(t * per, s.nprobe), r1 = min(r0 + per, s.nprobe);
+  // the thread's list sizes, loaded once with every read in flight together
+  // (clamped ranks, masked after)
+  int ln[kPlanPer];
+  {
+    int lid[kPlanPer];
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i) lid[i] = s.probe[q * s.nprobe + min(r0 + i, s.nprobe - 1)];
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i) keep_loaded(lid[i]);
+    int lo[kPlanPer], hi[kPlanPer];
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i) {
+      const int l = max(lid[i], 0);
+      lo[i] = s.list_off[l];
+      hi[i] = s.list_off[l + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i) {
+      keep_loaded(lo[i]);
+      keep_loaded(hi[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i) ln[i] = (r0 + i < r1 && r0 + i < P && lid[i] >= 0) ? hi[i] - lo[i] : 0;
+  }
   auto sizes = [&](int r, int& n, int& nc) {
-    const int list = r < P ? s.probe[q * s.nprobe + r] : -1;
-    n = list >= 0 ? s.list_off[list + 1] - s.list_off[list] : 0;
+    n = 0;
+#pragma unroll
+    for (int i = 0; i < kPlanPer; ++i) n = (r == r0 + i) ? ln[i] : n;
     nc = (n + s.chunk - 1) / s.chunk;
   };
   int sn = 0, sc = 0;
-  for (int r = r0; r < r1; ++r) {
-    int n, nc;
-    sizes(r, n, nc);
-    sn += n;
-    sc += nc;
+#pragma unroll
+  for (int i = 0; i < kPlanPer; ++i) {
+    sn += ln[i];
+    sc += (ln[i] + s.chunk - 1) / s.chunk;
   }
   // block exclusive scan of (sc, sn)
   int ic = sc, in = sn;
@@ -438,12 +464,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_block(SearchDev s) {
   }
   int exc = bc + ic - sc, exn = bn + in - sn;
   int first = INT32_MAX;
-  for (int r = r0; r < r1; ++r) {
-    int n, nc;
-    sizes(r, n, nc);
-    choff[r] = exc;
-    codeoff[r] = exn;
-    if (first == INT32_MAX && exn + n >= s.boot) first = r;
+#pragma unroll
+  for (int i = 0; i < kPlanPer; ++i) {
+    const int r = r0 + i, n = ln[i], nc = (n + s.chunk - 1) / s.chunk;
+    if (r < r1) {
+      choff[r] = exc;
+      codeoff[r] = exn;
+      if (first == INT32_MAX && exn + n >= s.boot) first = r;
+    }
     exc += nc;
     exn += n;
   }
@@ -1174,19 +1202,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s, int W, ui
   }
 }
 
-// The k best distinct (distance, id) keys of a query's W partial top-k lists
-// (W K <= kWSelCap), and its statistics: the seeds once plus every wave's own
-// reranks, and every wave's candidates.
-__global__ __launch_bounds__(kThreads) void k_fin_merge(SearchDev s, int W, const uint64_t* __restrict__ part,
-                                                        const int32_t* __restrict__ pst) {
-  __shared__ uint64_t selw[kWaves][kWSelCap];
-  const int wave = threadIdx.x >> 6, lane = lane_id();
-  const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
-  if (q >= s.nq) return;   // whole waves
-  const int K = s.k, n = W * K;
-  uint64_t* sel = selw[wave];
-  for (int i = lane; i < n; i += kWave) sel[i] = part[q * n + i];
-  wave_sort_sel(sel, n);
+// Merge of a query's W partial top-k lists (W K <= kWSelCap keys): the k best
+// distinct (distance, id) keys, and the statistics: the seeds once plus every
+// wave's own reranks, and every wave's candidates. fin_merge_out takes the
+// keys sorted in sel[0..n); one wave.
+__device__ __forceinline__ void fin_merge_out(const SearchDev& s, int64_t q, int W, const uint64_t* sel, int n,
+                                              const int32_t* __restrict__ pst) {
+  const int lane = lane_id();
+  const int K = s.k;
   int out = 0;
   for (int i0 = 0; i0 < n && out < K; i0 += kWave) {
     const int i = i0 + lane;
@@ -1217,6 +1240,38 @@ __global__ __launch_bounds__(kThreads) void k_fin_merge(SearchDev s, int W, cons
     s.q_rerank[q] = seeds + rer;
     s.q_cand[q] = cand;
   }
+}
+
+// At most kMergeWaveMax keys per query: one wave per query, sorted in
+// registers.
+constexpr int kMergeWaveMax = 256;
+__global__ __launch_bounds__(kThreads) void k_fin_merge(SearchDev s, int W, const uint64_t* __restrict__ part,
+                                                        const int32_t* __restrict__ pst) {
+  __shared__ uint64_t selw[kWaves][kMergeWaveMax];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t q = (int64_t)blockIdx.x * kWaves + wave;
+  if (q >= s.nq) return;   // whole waves
+  const int n = W * s.k;
+  uint64_t* sel = selw[wave];
+  for (int i = lane; i < n; i += kWave) sel[i] = part[q * n + i];
+  wave_sort_sel(sel, n);
+  fin_merge_out(s, q, W, sel, n, pst);
+}
+
+// More keys (up to kWSelCap): one block per query sorts them in LDS.
+constexpr int kMergeThreads = 512;
+__global__ __launch_bounds__(kMergeThreads) void k_fin_merge_block(SearchDev s, int W,
+                                                                   const uint64_t* __restrict__ part,
+                                                                   const int32_t* __restrict__ pst) {
+  __shared__ uint64_t sel[kWSelCap];
+  const int64_t q = blockIdx.x;
+  const int n = W * s.k;
+  int n2 = 1;
+  while (n2 < n) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += kMergeThreads) sel[i] = i < n ? part[q * n + i] : ~0ull;
+  __syncthreads();
+  bitonic_sort_u64(sel, n2);
+  if (threadIdx.x < kWave) fin_merge_out(s, q, W, sel, n, pst);
 }
 
 // ------------------------------------------------------------------ debug
@@ -1385,7 +1440,9 @@ hipError_t launch_finalize_split(const SearchDev& s, int W, uint64_t* part, int3
     hipLaunchKernelGGL(k_finalize<true>, grid, dim3(kThreads), shm, st, s, W, part, pst);
   else
     hipLaunchKernelGGL(k_finalize<false>, grid, dim3(kThreads), shm, st, s, W, part, pst);
-  if (W > 1)
+  if (W > 1 && W * s.k > kMergeWaveMax)
+    hipLaunchKernelGGL(k_fin_merge_block, dim3((unsigned)s.nq), dim3(kMergeThreads), 0, st, s, W, part, pst);
+  else if (W > 1)
     hipLaunchKernelGGL(k_fin_merge, dim3((unsigned)((s.nq + kWaves - 1) / kWaves)), dim3(kThreads), 0, st, s, W,
                        part, pst);
   return hipGetLastError();

@@ -303,4 +303,24 @@ __device__ void wave_smallest(Load load, Xf xf, int n, int P, uint64_t* sel) {
   wave_sort_sel(sel, total);
 }
 
+// Bitonic sort of n (power of two) 64-bit keys in LDS, ascending, by the
+// whole block (every thread calls it).
+__device__ inline void bitonic_sort_u64(uint64_t* a, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = ((lo & size) == 0);
+        const uint64_t x = a[lo], y = a[hi];
+        if ((x > y) == up) {
+          a[lo] = y;
+          a[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace rbq
