@@ -96,7 +96,7 @@ typedef struct {
   int32_t rerank_waves;            /* waves that share one query's rerank: 0 = chosen
                                       from the call's batch size (1 from 2048 queries
                                       up, more for smaller batches), n >= 1 = n; at most
-                                      64 and 1024 / k. Each wave reranks a fixed share
+                                      64 and 4096 / k. Each wave reranks a fixed share
                                       of the query's chunks against its own threshold,
                                       so the result is the exact top-k of the probed
                                       lists whenever the bounds hold, for any value;

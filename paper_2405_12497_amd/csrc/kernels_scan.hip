@@ -25,6 +25,7 @@
 #include "rbq_internal.hpp"
 #include "scan_code.hpp"
 #include "wave_select.hpp"
+#include "rbq_runtime.hpp"
 
 namespace rbq {
 namespace {
@@ -956,7 +957,7 @@ __device__ __forceinline__ int fin_lds_words(int k) { return kFinWin + kFinRound
 // k_fin_merge keeps the k best distinct keys of the W lists (the seeds appear
 // in all of them).
 template <bool WIDE>
-__global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s, int W, uint64_t* __restrict__ part,
+__global__ __launch_bounds__(kThreads, WIDE ? 3 : 4) void k_finalize(SearchDev s, int W, uint64_t* __restrict__ part,
                                                           int32_t* __restrict__ pst) {
   using DS = DistShape<WIDE>;
   extern __shared__ uint64_t fin_lds[];
@@ -1202,7 +1203,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_finalize(SearchDev s, int W, ui
   }
 }
 
-// Merge of a query's W partial top-k lists (W K <= kWSelCap keys): the k best
+// Merge of a query's W partial top-k lists (W K <= kFinMergeCap keys): the k best
 // distinct (distance, id) keys, and the statistics: the seeds once plus every
 // wave's own reranks, and every wave's candidates. fin_merge_out takes the
 // keys sorted in sel[0..n); one wave.
@@ -1258,12 +1259,12 @@ __global__ __launch_bounds__(kThreads) void k_fin_merge(SearchDev s, int W, cons
   fin_merge_out(s, q, W, sel, n, pst);
 }
 
-// More keys (up to kWSelCap): one block per query sorts them in LDS.
+// More keys (up to kFinMergeCap): one block per query sorts them in LDS.
 constexpr int kMergeThreads = 512;
 __global__ __launch_bounds__(kMergeThreads) void k_fin_merge_block(SearchDev s, int W,
                                                                    const uint64_t* __restrict__ part,
                                                                    const int32_t* __restrict__ pst) {
-  __shared__ uint64_t sel[kWSelCap];
+  __shared__ uint64_t sel[kFinMergeCap];
   const int64_t q = blockIdx.x;
   const int n = W * s.k;
   int n2 = 1;
@@ -1427,13 +1428,13 @@ int finalize_split(int64_t nq, int k) {
   if (nq <= 0 || nq >= kFinSplitWaves) return 1;
   int w = (int)((kFinSplitWaves + nq - 1) / nq);
   w = std::min(w, kFinSplitMax);
-  w = std::min(w, kWSelCap / std::max(k, 1));
+  w = std::min(w, kFinMergeCap / std::max(k, 1));
   return std::max(w, 1);
 }
 
 hipError_t launch_finalize_split(const SearchDev& s, int W, uint64_t* part, int32_t* pst, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
-  if (W < 1 || (W > 1 && (!part || !pst || W * s.k > kWSelCap))) return hipErrorInvalidValue;
+  if (W < 1 || (W > 1 && (!part || !pst || W * s.k > kFinMergeCap))) return hipErrorInvalidValue;
   const size_t shm = (size_t)kWaves * (kFinWin + kFinRoundMax + s.k) * sizeof(uint64_t);
   const dim3 grid((unsigned)((s.nq * W + kWaves - 1) / kWaves));
   if (dist_wide(s.dim))

@@ -35,10 +35,11 @@ int finalize_split(int64_t nq, int k);
 int tau_split(int fin_w, int k);
 hipError_t launch_tau_split(const SearchDev& s, int W, uint64_t* tpart, hipStream_t st);
 // Rerank waves for a requested count (0: finalize_split's choice), clamped to
-// 1 .. min(64, 1024 / k).
+// 1 .. min(64, kFinMergeCap / k).
+constexpr int kFinMergeCap = 4096;   // keys of a query's split-rerank merge (W k)
 inline int fin_waves(int requested, int64_t nq, int k) {
   if (requested <= 0) return finalize_split(nq, k);
-  const int cap = std::max(1, std::min(64, 1024 / std::max(k, 1)));
+  const int cap = std::max(1, std::min(64, kFinMergeCap / std::max(k, 1)));
   return std::min(requested, cap);
 }
 hipError_t launch_finalize_split(const SearchDev& s, int W, uint64_t* part, int32_t* pst, hipStream_t st);
