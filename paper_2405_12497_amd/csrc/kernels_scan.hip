@@ -471,12 +471,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_block(SearchDev s) {
     if (r < r1) {
       choff[r] = exc;
       codeoff[r] = exn;
-      if (first == INT32_MAX && exn + n >= s.boot) first = r;
+      // the first rank reaching boot codes is the one rank whose exclusive
+      // count is below boot and inclusive count is not (counts only grow)
+      if (exn < s.boot && exn + n >= s.boot) first = r;
     }
     exc += nc;
     exn += n;
   }
-  if (first != INT32_MAX) atomicMin(&sh_rstar, first);
+  if (first != INT32_MAX) sh_rstar = first;   // a single writer
   __syncthreads();
   const int rstar = sh_rstar;
   if (rstar >= r0 && rstar < r1) {   // the owner of the first rank reaching boot
