@@ -367,10 +367,14 @@ void launch_f32_mfma(const float* A, int64_t lda, const float* sub, const int32_
 // Y = X * P with X split per element as hi = bf16(x), lo = bf16(x - hi) and P
 // given as transposed BF16 hi/lo planes Bt[n][k]. Each 16x16 output block sums
 // hi*hi + hi*lo + lo*hi with v_mfma_f32_16x16x32_bf16 (FP32 accumulation).
-// Block tile 64 x 64, K step 32, 4 waves each owning a 32 x 32 quadrant.
+// Block tile T x T (T = 64, or 32 when 64-wide tiles would leave most of the
+// chip idle), K step 32, 4 waves each owning a T/2 x T/2 quadrant. The next K
+// step's global reads are issued before this step's MFMAs. The tile size does
+// not change any output's sum (same K steps, same products, same order).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float x) {   // round to nearest even
   uint32_t u = __float_as_uint(x);
@@ -381,6 +385,7 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 constexpr int BK = 32;
 
+template <int T>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3(const float* __restrict__ A, int64_t lda,
                                                      const float* __restrict__ sub,
                                                      const int32_t* __restrict__ sel,
@@ -388,76 +393,108 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const float* __restrict__ A
                                                      const uint16_t* __restrict__ Blo,
                                                      float* __restrict__ Y, int64_t ldy, int64_t M,
                                                      int N, int K) {
+  constexpr int EPT = T * BK / 256;   // operand elements per thread and K step (8 or 4)
+  constexpr int TPR = BK / EPT;       // threads per tile row
+  constexpr int WB = T / 32;          // 16x16 blocks per wave and dimension
   // k-contiguous rows, padded by 8 elements so 16-byte reads stay aligned
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[TM][BK + 8], Al[TM][BK + 8];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[TN][BK + 8], Bl[TN][BK + 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[T][BK + 8], Al[T][BK + 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[T][BK + 8], Bl[T][BK + 8];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int64_t m0 = (int64_t)blockIdx.x * TM;
-  const int n0 = blockIdx.y * TN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  f32x4 acc[2][2];
+  const int64_t m0 = (int64_t)blockIdx.x * T;
+  const int n0 = blockIdx.y * T;
+  const int wm = (wave >> 1) * (T / 2), wn = (wave & 1) * (T / 2);
+  f32x4 acc[WB][WB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // A loader: row tid>>2, 8 consecutive k starting at (tid&3)*8
-  const int la_r = tid >> 2, la_k = (tid & 3) * 8;
+    for (int j = 0; j < WB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // A loader: row tid / TPR, EPT consecutive k from (tid % TPR) * EPT
+  const int la_r = tid / TPR, la_k = (tid % TPR) * EPT;
   const int64_t am = m0 + la_r;
   const float* arow = (am < M) ? A + am * lda : nullptr;
   const float* srow = (am < M && sel) ? sub + (int64_t)sel[am] * K : nullptr;
-  // B loader: n row tid>>2, 8 consecutive k
-  const int lb_n = tid >> 2, lb_k = (tid & 3) * 8;
+  // B loader: n row tid / TPR, EPT consecutive k
+  const int lb_n = tid / TPR, lb_k = (tid % TPR) * EPT;
   const int bn = n0 + lb_n;
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    u16x8 hv, lv;
+  float av[EPT];
+  uint16_t bhv[EPT], blv[EPT];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < EPT; ++i) {
       const int kk = k0 + la_k + i;
       float v = 0.f;
       if (arow && kk < K) {
         v = arow[kk];
         if (srow) v -= srow[kk];
       }
-      const uint16_t h = f2bf(v);
-      hv[i] = h;
-      lv[i] = f2bf(v - bf2f(h));
+      av[i] = v;
     }
-    *reinterpret_cast<u16x8*>(&Ah[la_r][la_k]) = hv;
-    *reinterpret_cast<u16x8*>(&Al[la_r][la_k]) = lv;
-    u16x8 bh = {}, bl = {};
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) bhv[i] = blv[i] = 0;
     if (bn < N) {
       const int64_t o = (int64_t)bn * K + k0 + lb_k;
-      if (k0 + lb_k + 8 <= K && (o & 7) == 0) {
-        bh = *reinterpret_cast<const u16x8*>(Bhi + o);
-        bl = *reinterpret_cast<const u16x8*>(Blo + o);
-      } else {
+      if constexpr (EPT == 8) {
+        if (k0 + lb_k + 8 <= K && (o & 7) == 0) {
+          const u16x8 h = *reinterpret_cast<const u16x8*>(Bhi + o);
+          const u16x8 l = *reinterpret_cast<const u16x8*>(Blo + o);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          if (k0 + lb_k + i < K) {
-            bh[i] = Bhi[o + i];
-            bl[i] = Blo[o + i];
+          for (int i = 0; i < 8; ++i) {
+            bhv[i] = h[i];
+            blv[i] = l[i];
           }
+          return;
+        }
+      } else {
+        if (k0 + lb_k + 4 <= K && (o & 3) == 0) {
+          const u16x4 h = *reinterpret_cast<const u16x4*>(Bhi + o);
+          const u16x4 l = *reinterpret_cast<const u16x4*>(Blo + o);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            bhv[i] = h[i];
+            blv[i] = l[i];
+          }
+          return;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        if (k0 + lb_k + i < K) {
+          bhv[i] = Bhi[o + i];
+          blv[i] = Blo[o + i];
         }
       }
     }
-    *reinterpret_cast<u16x8*>(&Bh[lb_n][lb_k]) = bh;
-    *reinterpret_cast<u16x8*>(&Bl[lb_n][lb_k]) = bl;
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const uint16_t h = f2bf(av[i]);
+      Ah[la_r][la_k + i] = h;
+      Al[la_r][la_k + i] = f2bf(av[i] - bf2f(h));
+      Bh[lb_n][lb_k + i] = bhv[i];
+      Bl[lb_n][lb_k + i] = blv[i];
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    stash();
     __syncthreads();
+    if (k0 + BK < K) fetch(k0 + BK);   // in flight during this step's MFMAs
     // operand fragments: row (or column) lane%16, k = (lane/16)*8 .. +7
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    bf16x8 ah[2], al[2], bh2[2], bl2[2];
+    bf16x8 ah[WB], al[WB], bh2[WB], bl2[WB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < WB; ++i) {
       ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[wm + i * 16 + fr][fk]);
       al[i] = *reinterpret_cast<const bf16x8*>(&Al[wm + i * 16 + fr][fk]);
       bh2[i] = *reinterpret_cast<const bf16x8*>(&Bh[wn + i * 16 + fr][fk]);
       bl2[i] = *reinterpret_cast<const bf16x8*>(&Bl[wn + i * 16 + fr][fk]);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WB; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < WB; ++j) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh2[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl2[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh2[j], acc[i][j], 0, 0, 0);
@@ -467,9 +504,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const float* __restrict__ A
   // output fragment: column lane%16, rows (lane/16)*4 + 0..3
   const int oc = lane & 15, orow = (lane >> 4) * 4;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < WB; ++j) {
       const int n = n0 + wn + j * 16 + oc;
       if (n >= N) continue;
 #pragma unroll
@@ -480,7 +517,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const float* __restrict__ A
     }
 }
 
-// ---------------------------------------------------------------- FP64 rotation (centroids)
 __global__ void k_rotate_f64(const float* __restrict__ X, int64_t M, int K,
                              const double* __restrict__ P, int N, float* __restrict__ Y) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -549,9 +585,13 @@ hipError_t launch_gemm_bf16x3(const float* A, int64_t lda, const float* sub, con
                               const uint16_t* Bhi, const uint16_t* Blo, float* Y, int64_t ldy,
                               int64_t M, int N, int K, hipStream_t st) {
   if (M <= 0) return hipSuccess;
-  dim3 grid((unsigned)((M + TM - 1) / TM), (N + TN - 1) / TN);
-  hipLaunchKernelGGL(k_gemm_bf16x3, grid, dim3(256), 0, st, A, lda, sub, sel, Bhi, Blo, Y, ldy, M,
-                     N, K);
+  if (((M + 63) / 64) * (((int64_t)N + 63) / 64) >= 256) {
+    dim3 grid((unsigned)((M + 63) / 64), (N + 63) / 64);
+    hipLaunchKernelGGL(k_gemm_bf16x3<64>, grid, dim3(256), 0, st, A, lda, sub, sel, Bhi, Blo, Y, ldy, M, N, K);
+  } else {
+    dim3 grid((unsigned)((M + 31) / 32), (N + 31) / 32);
+    hipLaunchKernelGGL(k_gemm_bf16x3<32>, grid, dim3(256), 0, st, A, lda, sub, sel, Bhi, Blo, Y, ldy, M, N, K);
+  }
   return hipGetLastError();
 }
 
