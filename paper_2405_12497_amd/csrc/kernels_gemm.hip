@@ -15,7 +15,6 @@ namespace rbq {
 //   j, e < 4, c < N (ceil(N / 64) * 4 groups per row). A group is the 16
 //   values one lane holds of a row of its wave's 64-column tile.
 namespace {
-constexpr int TM = 64, TN = 64;
 
 // ---------------------------------------------------------------- FP32 MFMA GEMM
 // Same modes on the matrix cores (v_mfma_f32_16x16x4_f32: FP32 products, FP32

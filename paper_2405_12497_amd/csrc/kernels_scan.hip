@@ -393,24 +393,32 @@ constexpr int kPlanThreads = 1024;
 constexpr int kPlanPer = 16;   // ranks per thread
 static_assert(kMaxNprobe <= kPlanThreads * kPlanPer, "k_plan_block covers every rank");
 
+// The query's list sizes are gathered once by rank-strided threads (reads of
+// the probe row coalesced) into LDS, each thread then scans its contiguous run
+// from LDS (rows padded by one word per 16 so the runs fall in distinct
+// banks), and the offsets go back out rank-strided: the one CU running the
+// block does not serve 64 cache lines per load and store.
+__host__ __device__ inline int plan_pad(int r) { return r + (r >> 4); }
+constexpr size_t kPlanLdsBytes = 2 * (size_t)(kMaxNprobe + kMaxNprobe / 16 + 1) * sizeof(int32_t);
+
 __global__ __launch_bounds__(kPlanThreads) void k_plan_block(SearchDev s) {
+  extern __shared__ int32_t plan_lds[];
   __shared__ int32_t wsum[kPlanThreads / kWave][2];
   __shared__ int32_t sh_rstar, sh_p0, sh_n0;
   const int64_t q = blockIdx.x;
   const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
   int P = s.nprobe;
   if (s.nprobe_q) P = min(max(s.nprobe_q[q], 1), s.nprobe);
-  int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
-  int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
-  const int per = (s.nprobe + kPlanThreads - 1) / kPlanThreads;
-  const int r0 = min(t * per, s.nprobe), r1 = min(r0 + per, s.nprobe);
-  // the thread's list sizes, loaded once with every read in flight together
-  // (clamped ranks, masked after)
-  int ln[kPlanPer];
+  const int np = s.nprobe;
+  int32_t* lco = plan_lds;                      // sizes, then code offsets
+  int32_t* lch = plan_lds + plan_pad(np) + 1;   // chunk offsets
+  int32_t* choff = s.pair_choff + q * (np + 1);
+  int32_t* codeoff = s.pair_codeoff + q * (np + 1);
   {
+    // rank t + kPlanThreads i: clamped reads all in flight, then masks
     int lid[kPlanPer];
 #pragma unroll
-    for (int i = 0; i < kPlanPer; ++i) lid[i] = s.probe[q * s.nprobe + min(r0 + i, s.nprobe - 1)];
+    for (int i = 0; i < kPlanPer; ++i) lid[i] = s.probe[q * np + min(t + kPlanThreads * i, np - 1)];
 #pragma unroll
     for (int i = 0; i < kPlanPer; ++i) keep_loaded(lid[i]);
     int lo[kPlanPer], hi[kPlanPer];
@@ -422,18 +430,17 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_block(SearchDev s) {
     }
 #pragma unroll
     for (int i = 0; i < kPlanPer; ++i) {
-      keep_loaded(lo[i]);
-      keep_loaded(hi[i]);
+      const int r = t + kPlanThreads * i;
+      if (r < np) lco[plan_pad(r)] = (r < P && lid[i] >= 0) ? hi[i] - lo[i] : 0;
     }
-#pragma unroll
-    for (int i = 0; i < kPlanPer; ++i) ln[i] = (r0 + i < r1 && r0 + i < P && lid[i] >= 0) ? hi[i] - lo[i] : 0;
   }
-  auto sizes = [&](int r, int& n, int& nc) {
-    n = 0;
+  if (t == 0) sh_rstar = INT32_MAX;
+  __syncthreads();
+  const int per = (np + kPlanThreads - 1) / kPlanThreads;
+  const int r0 = min(t * per, np), r1 = min(r0 + per, np);
+  int ln[kPlanPer];
 #pragma unroll
-    for (int i = 0; i < kPlanPer; ++i) n = (r == r0 + i) ? ln[i] : n;
-    nc = (n + s.chunk - 1) / s.chunk;
-  };
+  for (int i = 0; i < kPlanPer; ++i) ln[i] = r0 + i < r1 ? lco[plan_pad(r0 + i)] : 0;
   int sn = 0, sc = 0;
 #pragma unroll
   for (int i = 0; i < kPlanPer; ++i) {
@@ -454,7 +461,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_block(SearchDev s) {
     wsum[wave][0] = ic;
     wsum[wave][1] = in;
   }
-  if (t == 0) sh_rstar = INT32_MAX;
   __syncthreads();
   int bc = 0, bn = 0, tc = 0, tn = 0;
   for (int w = 0; w < kPlanThreads / kWave; ++w) {
@@ -464,36 +470,40 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_block(SearchDev s) {
     tn += wsum[w][1];
   }
   int exc = bc + ic - sc, exn = bn + in - sn;
-  int first = INT32_MAX;
+  int first = INT32_MAX, f_exc = 0, f_exn = 0, f_n = 0;
 #pragma unroll
   for (int i = 0; i < kPlanPer; ++i) {
     const int r = r0 + i, n = ln[i], nc = (n + s.chunk - 1) / s.chunk;
     if (r < r1) {
-      choff[r] = exc;
-      codeoff[r] = exn;
+      lch[plan_pad(r)] = exc;
+      lco[plan_pad(r)] = exn;   // its own size was read above
       // the first rank reaching boot codes is the one rank whose exclusive
       // count is below boot and inclusive count is not (counts only grow)
-      if (exn < s.boot && exn + n >= s.boot) first = r;
+      if (exn < s.boot && exn + n >= s.boot) {
+        first = r;
+        f_exc = exc;
+        f_exn = exn;
+        f_n = n;
+      }
     }
     exc += nc;
     exn += n;
   }
-  if (first != INT32_MAX) sh_rstar = first;   // a single writer
-  __syncthreads();
-  const int rstar = sh_rstar;
-  if (rstar >= r0 && rstar < r1) {   // the owner of the first rank reaching boot
-    int n, nc;
-    sizes(rstar, n, nc);
-    const int exc_l = choff[rstar], exn_l = codeoff[rstar];
-    const int cstar = (s.boot - exn_l + s.chunk - 1) / s.chunk - 1;
-    sh_p0 = exc_l + cstar + 1;
-    sh_n0 = exn_l + min((cstar + 1) * s.chunk, n);
+  if (first != INT32_MAX) {   // a single thread
+    sh_rstar = first;
+    const int cstar = (s.boot - f_exn + s.chunk - 1) / s.chunk - 1;
+    sh_p0 = f_exc + cstar + 1;
+    sh_n0 = f_exn + min((cstar + 1) * s.chunk, f_n);
   }
   __syncthreads();
+  for (int r = t; r < np; r += kPlanThreads) {
+    choff[r] = lch[plan_pad(r)];
+    codeoff[r] = lco[plan_pad(r)];
+  }
   if (t == 0) {
-    const bool boot_all = rstar == INT32_MAX;   // fewer than boot codes probed: all bootstrap
-    choff[s.nprobe] = tc;
-    codeoff[s.nprobe] = tn;
+    const bool boot_all = sh_rstar == INT32_MAX;   // fewer than boot codes probed: all bootstrap
+    choff[np] = tc;
+    codeoff[np] = tn;
     s.q_nch[q] = tc;
     s.q_p0[q] = boot_all ? tc : sh_p0;
     s.q_n0[q] = boot_all ? tn : sh_n0;
@@ -1393,7 +1403,14 @@ hipError_t launch_prep(const SearchDev& s, bool units, hipStream_t st) {
 hipError_t launch_plan(const SearchDev& s, hipStream_t st) {
   if (s.nq <= 0) return hipSuccess;
   if (s.nprobe > kPlanWaveMax) {
-    hipLaunchKernelGGL(k_plan_block, dim3((unsigned)s.nq), dim3(kPlanThreads), 0, st, s);
+    static bool attr_done = false;
+    if (!attr_done) {
+      (void)hipFuncSetAttribute((const void*)k_plan_block, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kPlanLdsBytes);
+      attr_done = true;
+    }
+    const size_t shm = 2 * ((size_t)plan_pad(s.nprobe) + 1) * sizeof(int32_t);
+    hipLaunchKernelGGL(k_plan_block, dim3((unsigned)s.nq), dim3(kPlanThreads), shm, st, s);
   } else {
     const dim3 gq((unsigned)((s.nq + kWaves - 1) / kWaves));
     hipLaunchKernelGGL(k_plan, gq, dim3(kThreads), 0, st, s);
