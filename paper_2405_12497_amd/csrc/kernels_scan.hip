@@ -95,14 +95,25 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     qq[j] = 0.f;
     const float* qrot = s.qrot + qj[j] * s.dp;
     const float* crot = s.crot + (int64_t)max(list[j], 0) * s.dp;
+    // all words' reads issued before any is used (used one by one, each
+    // would wait for its own round trip)
+    float xs[WS], cs[WS];
 #pragma unroll
     for (int t = 0; t < WS; ++t) {
       const int tt = min(t, W - 1);
-      const float x = qrot[tt * kWave + lane];
-      const float c = crot[tt * kWave + lane];
+      xs[t] = qrot[tt * kWave + lane];
+      cs[t] = crot[tt * kWave + lane];
+    }
+#pragma unroll
+    for (int t = 0; t < WS; ++t) {
+      keep_loaded(xs[t]);
+      keep_loaded(cs[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < WS; ++t) {
       const bool in = t < W;
-      rv[j][t] = in ? x - c : 0.f;
-      qq[j] = in ? fmaf(x, x, qq[j]) : qq[j];
+      rv[j][t] = in ? xs[t] - cs[t] : 0.f;
+      qq[j] = in ? fmaf(xs[t], xs[t], qq[j]) : qq[j];
     }
   }
 #pragma unroll
