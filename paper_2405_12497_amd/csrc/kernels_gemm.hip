@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_gemm_rot_cdist(GemmJob rot, GemmJob cd,
 // MQ products over its wave's slice (each load a contiguous 256-byte row piece
 // per wave), and the wave partials (and the slices' squared row norms) are
 // added in wave order.
-constexpr int kCdThreads = 1024, kCdWaves = kCdThreads / kWave, kCdUnroll = 16;
+constexpr int kCdThreads = 1024, kCdWaves = kCdThreads / kWave;
 
 template <int MQ>
 __global__ __launch_bounds__(kCdThreads) void k_cdist_few(const float* __restrict__ A, int64_t lda, int64_t M,
@@ -287,6 +287,9 @@ __global__ __launch_bounds__(kCdThreads) void k_cdist_few(const float* __restric
   float acc[MQ], sq[MQ];
 #pragma unroll
   for (int m = 0; m < MQ; ++m) acc[m] = sq[m] = 0.f;
+  // a wave's whole slice (48 rows at D = 768) in one batch of reads where the
+  // registers allow it
+  constexpr int kCdUnroll = MQ <= 4 ? 48 : 16;
   for (int kb = k0; kb < k1; kb += kCdUnroll) {
     float c[kCdUnroll];
 #pragma unroll
