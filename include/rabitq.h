@@ -10,7 +10,7 @@
  *     ||o_r - c||;
  *   - the query phase (Algorithm 2; Sec. 3.2-3.3) and IVF search with the
  *     error-bound rerank (Sec. 4): rotate, probe the nearest lists, quantise
- *     the query to B_q = 4 bits with randomised rounding per (query, list),
+ *     the query to B_q bits (1..8, default 4) with randomised rounding per (query, list),
  *     integer <x_b, q_u> by AND + popcount or int8 MFMA, the unbiased estimate,
  *     the lower distance bound, exact rerank, top-k.
  *
@@ -76,7 +76,8 @@ typedef struct {
   int32_t dim;           /* D, raw vector length, >= 1 */
   int32_t code_bits;     /* 0 => 64*ceil(D/64); else a multiple of 64, >= D, <= 4096 */
   int32_t nlist;         /* number of IVF lists, 1..24576 (1 = flat index) */
-  int32_t bq;            /* bits of the quantised query; must be 4 */
+  int32_t bq;            /* B_q, bits of the quantised query, 1..8 (Sec. 3.3.1;
+                            Sec. 5.1 uses 4): q_u in 0..2^B_q - 1, B_q bit planes */
   float eps0;            /* confidence parameter of the error bound (Theorem 3.2) */
   int32_t rot_precision; /* RBQ_ROT_FP32 or RBQ_ROT_BF16X3 */
   uint64_t seed;         /* seeds the randomised rounding (and P if none is given) */
@@ -89,7 +90,7 @@ typedef struct {
   int32_t scan_kernel;             /* RBQ_SCAN_* */
   int32_t use_learned_nprobe;      /* 1: per-query nprobe from the loaded MLP
                                       (falls back to `nprobe` when none is set) */
-  const int32_t* nprobe_per_query; /* device, nq entries in 1..nprobe, or NULL */
+  const int32_t* nprobe_per_query; /* host or device, nq entries in 1..nprobe, or NULL */
   int64_t qid_base;                /* query i uses id qid_base + i in the rounding RNG */
   int32_t use_graph;               /* 1: run the search as one replay of a captured HIP
                                       graph (see below); 0: launch its kernels directly */
@@ -121,8 +122,12 @@ typedef struct {
   int64_t queries;
   int64_t pairs;              /* (query, list) pairs probed */
   int64_t codes_scanned;      /* codes whose distance was estimated */
-  int64_t reranked;           /* exact distances computed */
+  int64_t reranked;           /* exact distances computed (bootstrap + final rerank) */
   int64_t candidates;         /* codes that passed the bound filter during the scan */
+  int64_t reranked_bootstrap; /* of `reranked`: those of the bootstrap rerank (the
+                                 min(4k, 256) best-estimated early codes per query) */
+  int64_t nonfinite_fallbacks;/* learned nprobe: queries whose model output was not
+                                 finite and that searched with the fixed nprobe */
 } rbq_search_stats;
 
 typedef struct {
@@ -133,7 +138,7 @@ typedef struct {
   int64_t graphs_cached;      /* captured graphs currently held */
 } rbq_index_info;
 
-/* Fills defaults: code_bits 0, bq 4, eps0 1.9, FP32 rotation, seed 0. */
+/* Fills defaults: code_bits 0, bq 4, eps0 1.9, FP32 rotation, seed 0 (Sec. 5.1). */
 rbq_status rbq_params_default(rbq_params* p, int32_t dim, int32_t nlist);
 
 /* Creates an empty index with validated parameters. *out is owned by the caller
@@ -141,31 +146,77 @@ rbq_status rbq_params_default(rbq_params* p, int32_t dim, int32_t nlist);
 rbq_status rbq_index_create(const rbq_params* p, rbq_index** out);
 
 /* Index phase (Algorithm 1; Sec. 3.1; IVF buckets of Sec. 4).
- *   data      host, n x dim float32, row-major; vector i gets id i
- *   centroids host, nlist x dim float32 (the IVF centroids, e.g. k-means)
- *   assign    host, n int32 in [0, nlist): list of each vector
- *   gauss     host, code_bits x code_bits float64 standard Gaussian draw, or
- *             NULL to draw it from params.seed. P is obtained by
- *             orthonormalising its rows (Gram-Schmidt, Appendix B), so P is
- *             Haar distributed. Codes are sign(P^T (o_r - c)) (Sec. 3.1.3).
+ *   data      host or device, n x dim float32, row-major; vector i gets id i
+ *   centroids host or device, nlist x dim float32 (the IVF centroids, e.g. k-means)
+ *   assign    host or device, n int32 in [0, nlist): list of each vector
+ *   gauss     host or device, code_bits x code_bits float64 standard Gaussian
+ *             draw, or NULL to draw it from params.seed. P is obtained by
+ *             orthonormalising its rows (Gram-Schmidt, Sec. 3.1.2 and
+ *             Appendix B), so P is Haar distributed. Codes are the signs of
+ *             P^T (o_r - c) / ||o_r - c|| (Sec. 3.1.3); with D < code_bits the
+ *             vectors are zero-padded (Sec. 5.1).
+ * Each pointer may be host or device memory independently; device data is
+ * reordered into list order on the device, host data is staged in blocks.
  * n is below 2^31 - 64, and 64*ceil(n/64) * code_bits/64 below 2^32 (32-bit
- * word offsets in the scan).
- * Rebuilding an index replaces its contents. */
+ * word offsets in the scan). Errors: RBQ_EINVAL for a NULL or out-of-range
+ * argument (assign outside [0, nlist), non-finite values, a rank-deficient
+ * draw), RBQ_ENOMEM / RBQ_EDEVICE from the device. Synchronises `stream`.
+ * Rebuilding an index replaces its contents (and drops a learned-nprobe
+ * model, whose features refer to the old lists). */
 rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t n,
                            const float* centroids, const int32_t* assign,
                            const double* gauss, void* stream);
 
+/* Algorithm 1 with a caller-supplied rotation: P is the code_bits x
+ * code_bits orthogonal matrix of Sec. 3.1.2 (host or device float64,
+ * row-major); codes use P^T v (P^{-1} = P^T, Sec. 3.1.3). Orthogonality is
+ * checked on four seeded vectors (||P P^T x - x|| <= 1e-6 ||x||), otherwise
+ * RBQ_EINVAL. Other arguments and errors as rbq_index_build. */
+rbq_status rbq_index_build_rotation(rbq_index* idx, const float* data, int64_t n,
+                                    const float* centroids, const int32_t* assign,
+                                    const double* P, void* stream);
+
+/* IVF clustering for the index phase (Sec. 4 groups the data into lists by
+ * k-means before RaBitQ quantises each list against its centroid): Lloyd's
+ * algorithm on the GPU.
+ *   data       host or device, n x dim float32
+ *   sample     rows used for the iterations: a seeded sample of that many
+ *              (0 = all n); the final assignment covers all n rows
+ *   init       host or device nlist x dim float32 initial centroids, or NULL
+ *              for nlist distinct seeded sample rows
+ *   centroids  host or device nlist x dim float32 (output)
+ *   assign     host or device n int32 (output): the nearest final centroid
+ * Each of `iters` rounds assigns every sample row to its nearest centroid
+ * (squared distance ||c||^2 - 2 <x, c> in FP32 on the matrix cores, ties to
+ * the lower list) and moves each non-empty list's centroid to the mean of its
+ * rows (empty lists keep theirs). The means are summed in 64-bit fixed point,
+ * so the result does not depend on the order of the parallel additions: the
+ * same inputs and seed give the same bits. Temporary device memory: the data
+ * (if given on the host), the sample, and up to 1 GiB of distances.
+ * Errors: RBQ_EINVAL (NULL, n, dim or nlist out of range, nlist above the
+ * sample size, non-finite data), RBQ_ENOMEM / RBQ_EDEVICE. Synchronises. */
+rbq_status rbq_kmeans(const float* data, int64_t n, int32_t dim, int32_t nlist, int32_t iters,
+                      int64_t sample, uint64_t seed, const float* init, float* centroids,
+                      int32_t* assign, void* stream);
+
 /* Query phase + IVF search (Algorithm 2; Sec. 4).
- *   queries   device, nq x dim float32 row-major
- *   out_ids   device, nq x k int64: ids of the k nearest by exact distance among
- *             the reranked candidates of the probed lists, ordered by
+ *   queries   host or device, nq x dim float32 row-major
+ *   out_ids   host or device, nq x k int64: ids of the k nearest by exact distance
+ *             among the reranked candidates of the probed lists, ordered by
  *             (distance, id); -1 pads when fewer than k vectors were probed
- *   out_dists device, nq x k float32 exact squared distances (+inf pads)
+ *   out_dists host or device, nq x k float32 exact squared distances (+inf pads)
  *   stats     host or NULL (see rbq_search_stats)
- * nq may be 0 (nothing is launched). */
+ * Host queries (and a host opts->nprobe_per_query) are copied to the device
+ * on `stream`; host outputs are copied back and the stream is synchronised
+ * before returning. nq may be 0 (nothing is launched). */
 rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t nq,
                       const rbq_search_opts* opts, int64_t* out_ids, float* out_dists,
                       rbq_search_stats* stats, void* stream);
+
+/* Sets the confidence parameter eps0 of the error bound (Theorem 3.2) used by
+ * later searches: the lower bound widens with eps0 and more candidates are
+ * reranked (Sec. 5.2.4 studies recall against eps0). Codes are unchanged. */
+rbq_status rbq_index_set_eps0(rbq_index* idx, float eps0);
 
 rbq_status rbq_index_info_get(const rbq_index* idx, rbq_index_info* out);
 
@@ -253,9 +304,30 @@ rbq_status rbq_nprobe_model_set(rbq_index* idx, const float* weights, float thre
 rbq_status rbq_nprobe_model_get(const rbq_index* idx, float* weights, float* threshold);
 
 /* Per-query nprobe from the model: feats device nq x 96 -> nprobe device nq int32,
- * logits device nq x 32 float32 (or NULL). */
+ * logits device nq x 32 float32 (or NULL). Logits that are not all finite
+ * give the largest nprobe (min(nlist, 512)).
+ * In rbq_search (use_learned_nprobe = 1) the features, the network and this
+ * policy run fused in one launch after the probe selection, with the same
+ * BF16 arithmetic; there a query with non-finite logits searches with the
+ * caller's fixed `nprobe`, and rbq_search_stats.nonfinite_fallbacks counts it. */
 rbq_status rbq_nprobe_predict(rbq_index* idx, const float* feats, int64_t nq,
                               int32_t* nprobe, float* logits, void* stream);
+
+/* The 32 bucket nprobe values b_0..b_31 (host int32[32]). */
+rbq_status rbq_nprobe_bucket_table(int32_t* nprobe);
+
+/* Training labels from neighbour lists (the traces a model is trained on).
+ *   queries  device nq x dim float32
+ *   nn_ids   device nq x k int64: each query's neighbours (e.g. the ids an
+ *            rbq_search returned, or exact nearest neighbours); ids < 0 skipped
+ *   need     device nq int32 or NULL: the smallest nprobe whose probed lists
+ *            (the IVF probe order of Sec. 4: centroid distance, then list id,
+ *            as rbq_search ranks them) hold every neighbour, 0 if none is valid
+ *   labels   device nq int32: the smallest bucket whose nprobe >= need (31 if none)
+ * Builds an id -> list map on first use (4 bytes per indexed vector, held by
+ * the index). */
+rbq_status rbq_nprobe_labels(rbq_index* idx, const float* queries, int64_t nq, const int64_t* nn_ids,
+                             int32_t k, int32_t* labels, int32_t* need, void* stream);
 
 /* One forward/backward of the MLP on given FP32 weights, for gradient checks:
  * x device n x 96, labels device n, weights/grads device 16,544 floats,
@@ -264,8 +336,11 @@ rbq_status rbq_mlp_loss_grad(const float* x, const int32_t* labels, int64_t n,
                              const float* weights, float* grads, float* loss, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Parity / debug exports. They run the same kernels as rbq_search on inputs
- * chosen by the caller; not meant for production use.
+ * Parity / debug exports: the search's own arithmetic on inputs chosen by the
+ * caller, for checking it against an independent implementation; not meant
+ * for production use. rbq_debug_scan runs the production scan kernels
+ * themselves (an export phase of the popcount scan, the debug instance of
+ * the MFMA scan's unit routine).
  */
 
 /* Codes and factors as encoded on the GPU, in the caller's original vector
@@ -291,14 +366,19 @@ rbq_status rbq_debug_centroid_dists(rbq_index* idx, const float* queries, int64_
 rbq_status rbq_debug_probe(rbq_index* idx, const float* queries, int64_t nq, int32_t nprobe,
                            int32_t* lists, float* dists, void* stream);
 
-/* Per-pair quantisation (S3): queries device nq x dim, lists device nq x nprobe.
- * qu device (nq*nprobe) x code_bits uint8 (0..15); scal device (nq*nprobe) x 4
+/* Per-pair quantisation of the query (Sec. 3.1.1 normalisation against the
+ * list centroid, Sec. 3.3.1 randomised uniform scalar quantisation with B_q
+ * bits): queries device nq x dim, lists device nq x nprobe.
+ * qu device (nq*nprobe) x code_bits uint8 (0..2^B_q - 1); scal device (nq*nprobe) x 4
  * float32 {||q_r - c||, v_l, Delta, sum q_u}. */
 rbq_status rbq_debug_quantize(rbq_index* idx, const float* queries, int64_t nq,
                               const int32_t* lists, int32_t nprobe, int64_t qid_base,
                               uint8_t* qu, float* scal, void* stream);
 
-/* Scan arithmetic of one list for a caller-given quantised query (S4 + S6):
+/* Scan arithmetic of one list for a caller-given quantised query: the integer
+ * <x_b, q_u> and popcount (Sec. 3.3.2), the estimate <x_bar,q_bar>/<o_bar,o>
+ * (Theorem 3.2, with the Sec. 3.3.2 decomposition), the distance by Eq. (2)
+ * and its lower bound with the half-width of Theorem 3.2:
  * qu device code_bits uint8, scal host 4 floats {b, v_l, Delta, (unused)};
  * outputs device, one per member of the list in list order (ids of
  * rbq_debug_list_ids): ip, pc int32; est, dist, lb float32.

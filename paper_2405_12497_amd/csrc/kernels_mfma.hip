@@ -65,7 +65,8 @@ __device__ void mfma_unit(const SearchDev& s, int64_t start, int64_t end, const 
     int pc = pcp + __shfl_xor(pcp, 16, kWave);
     pc += __shfl_xor(pc, 32, kWave);
     const float2 sf = s.sfac[p];
-    // acc[i] = IP of row 4 grp + i with code `col`
+    // acc[i] + qoff * pc = IP of row 4 grp + i with code `col` (the int8 operand
+    // holds q_u - qoff, so that B_q = 8 values fit)
     bool pass[4];
     float lbv[4];
 #pragma unroll
@@ -74,14 +75,15 @@ __device__ void mfma_unit(const SearchDev& s, int64_t start, int64_t end, const 
       const RowInfo& ri = rows[row];
       const PairRec& r = ri.rec;
       float dist, lbe;
-      estimate(r, pair_terms(r, hwk), sf, acc[i], pc, dist, lbe);
+      const int ipv = acc[i] + s.qoff * pc;
+      estimate(r, pair_terms(r, hwk), sf, ipv, pc, dist, lbe);
       const bool live = pvalid && ri.valid;
       const float lb = live ? lbe : __builtin_inff();
       if (DEBUG && row == 0 && live) {
         const int64_t o = p - dbg_base;
-        dbg_ip[o] = acc[i];
+        dbg_ip[o] = ipv;
         dbg_pc[o] = pc;
-        dbg_est[o] = estimate_est(r, s.fac[p].y, acc[i], pc);
+        dbg_est[o] = estimate_est(r, s.fac[p].y, ipv, pc);
         dbg_dist[o] = dist;
         dbg_lb[o] = lb;
       }

@@ -19,13 +19,11 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {   // round to nearest eve
 }
 
 // ------------------------------------------------------------------ features
-// One wave per query. probe_d: the query's 64 (or nlist) nearest squared
-// centroid distances, nearest first; probe: their list ids.
-__global__ __launch_bounds__(256) void k_features(FeatDev f) {
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= f.nq) return;
+// The 96 features of query q by one wave, written to out (global or LDS).
+// probe_d: the query's 64 (or nlist) nearest squared centroid distances,
+// nearest first; probe: their list ids.
+__device__ __forceinline__ void query_features(const FeatDev& f, int64_t q, float* out) {
   const int lane = lane_id();
-  float* out = f.feats + q * kMlpIn;
   const float* dq = f.probe_d + q * f.stride;
   const int navail = f.navail;
   const float tiny = 1e-30f;
@@ -83,6 +81,13 @@ __global__ __launch_bounds__(256) void k_features(FeatDev f) {
       o[3] = (float)sq / (15.f * (float)f.dp);
     }
   }
+}
+
+// One wave per query.
+__global__ __launch_bounds__(256) void k_features(FeatDev f) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= f.nq) return;
+  query_features(f, q, f.feats + q * kMlpIn);
 }
 
 // ------------------------------------------------------------------ BF16 GEMM
@@ -237,25 +242,117 @@ __global__ void k_gather_rows(const float* __restrict__ X, const int32_t* __rest
   if (c == 0) yo[r] = y[src];
 }
 
-// nprobe of the smallest bucket whose cumulative softmax reaches `thr`.
-__global__ void k_policy(const float* __restrict__ Z, int64_t n, float thr, int nprobe_max,
-                         int32_t* __restrict__ out) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+// nprobe of the smallest bucket whose cumulative softmax of the logits z
+// (stride zs) reaches `thr`, at most nprobe_max. Logits that are not all
+// finite give nprobe_max (the fixed-nprobe fallback); *fallback tells which.
+__device__ __forceinline__ int policy_pick(const float* z, int zs, float thr, int nprobe_max, bool* fallback) {
   float mx = -__builtin_inff();
-  for (int j = 0; j < kMlpOut; ++j) mx = fmaxf(mx, Z[r * kMlpOut + j]);
+  bool finite = true;
+  for (int j = 0; j < kMlpOut; ++j) {
+    const float v = z[j * zs];
+    finite = finite && isfinite(v);
+    mx = fmaxf(mx, v);
+  }
+  *fallback = !finite;
+  if (!finite) return nprobe_max;
   float se = 0.f;
-  for (int j = 0; j < kMlpOut; ++j) se += expf(Z[r * kMlpOut + j] - mx);
+  for (int j = 0; j < kMlpOut; ++j) se += expf(z[j * zs] - mx);
   float cum = 0.f;
   int pick = kMlpOut - 1;
   for (int j = 0; j < kMlpOut; ++j) {
-    cum += expf(Z[r * kMlpOut + j] - mx) / se;
+    cum += expf(z[j * zs] - mx) / se;
     if (cum >= thr - 1e-6f) {
       pick = j;
       break;
     }
   }
-  out[r] = min(max(mlp_bucket_nprobe(pick), 1), nprobe_max);
+  return min(max(mlp_bucket_nprobe(pick), 1), nprobe_max);
+}
+
+__global__ void k_policy(const float* __restrict__ Z, int64_t n, float thr, int nprobe_max,
+                         int32_t* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  bool fb;
+  out[r] = policy_pick(Z + r * kMlpOut, 1, thr, nprobe_max, &fb);
+}
+
+// ------------------------------------------------------------------ fused inference
+// Features, both layers and the policy of 16 queries per block of 4 waves,
+// after the probe step: each wave computes the features of 4 queries into
+// LDS, then layer 1 (X[16 x 96] W1 + b1, ReLU; wave w takes hidden tiles
+// 2w, 2w + 1) and layer 2 (H[16 x 128] W2 + b2; waves 0 and 1 take one
+// 16-wide output tile each) run on v_mfma_f32_16x16x32_bf16 with the operands
+// rounded to BF16 as the training GEMM stages them, K in the same order, so
+// the logits equal those of the separate forward pass. The weights come in
+// fragment order (pack_mlp_fragments): one 16-byte load per lane per MFMA.
+constexpr int kFuseQ = 16;
+__global__ __launch_bounds__(256) void k_learned_front(FeatDev f, const u16x8* __restrict__ wfrag,
+                                                       const float* __restrict__ w32, float thr,
+                                                       int nprobe_max, int32_t* __restrict__ nprobe_out,
+                                                       int32_t* __restrict__ fallback_out) {
+  __shared__ float X[kFuseQ][kMlpIn];
+  __shared__ __attribute__((aligned(16))) uint16_t Hs[kFuseQ][kMlpHidden + 8];
+  __shared__ float Z[kFuseQ][kMlpOut + 1];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t q0 = (int64_t)blockIdx.x * kFuseQ;
+  for (int r = wave; r < kFuseQ; r += 4) {
+    if (q0 + r < f.nq) {
+      query_features(f, q0 + r, X[r]);
+    } else {
+      for (int j = lane; j < kMlpIn; j += kWave) X[r][j] = 0.f;
+    }
+  }
+  __syncthreads();
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  const int orow = (lane >> 4) * 4;
+  // layer 1
+  {
+    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int ks = 0; ks < kMlpIn / 32; ++ks) {
+      u16x8 av;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) av[i] = to_bf16(X[fr][ks * 32 + fk + i]);
+      const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int tile = 2 * wave + t;
+        const bf16x8 b = __builtin_bit_cast(bf16x8, wfrag[(tile * (kMlpIn / 32) + ks) * kWave + lane]);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int col = (2 * wave + t) * 16 + fr;
+      const float bias = w32[kMlpB1 + col];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Hs[orow + e][col] = to_bf16(fmaxf(acc[t][e] + bias, 0.f));
+    }
+  }
+  __syncthreads();
+  // layer 2
+  if (wave < 2) {
+    constexpr int kW1Frags = (kMlpHidden / 16) * (kMlpIn / 32) * kWave;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kMlpHidden / 32; ++ks) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&Hs[fr][ks * 32 + fk]);
+      const bf16x8 b = __builtin_bit_cast(bf16x8, wfrag[kW1Frags + (wave * (kMlpHidden / 32) + ks) * kWave + lane]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    const int col = wave * 16 + fr;
+    const float bias = w32[kMlpB2 + col];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Z[orow + e][col] = acc[e] + bias;
+  }
+  __syncthreads();
+  if (threadIdx.x < kFuseQ && q0 + threadIdx.x < f.nq) {
+    const int r = threadIdx.x;
+    bool fb;
+    nprobe_out[q0 + r] = policy_pick(Z[r], 1, thr, nprobe_max, &fb);
+    fallback_out[q0 + r] = fb ? 1 : 0;
+  }
 }
 
 // Per-feature mean and 1/std (population), one block per feature.
@@ -363,6 +460,33 @@ hipError_t launch_gather_rows(const float* X, const int32_t* y, const int32_t* i
   if (t <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, X, y, idx, n,
                      cols, Xo, yo);
+  return hipGetLastError();
+}
+
+namespace {
+// Bucket label of each query: the smallest bucket whose nprobe is at least
+// need[i] (the last bucket when none is).
+__global__ void k_bucket_labels(const int32_t* __restrict__ need, int64_t n, int32_t* __restrict__ labels) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int v = need[i];
+  int j = 0;
+  while (j < kMlpOut - 1 && mlp_bucket_nprobe(j) < v) ++j;
+  labels[i] = j;
+}
+}  // namespace
+
+hipError_t launch_bucket_labels(const int32_t* need, int64_t n, int32_t* labels, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bucket_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, need, n, labels);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_front(const FeatDev& f, const uint16_t* wfrag, const float* w32, float thr,
+                                int nprobe_max, int32_t* nprobe, int32_t* fallback, hipStream_t st) {
+  if (f.nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_learned_front, dim3((unsigned)((f.nq + kFuseQ - 1) / kFuseQ)), dim3(256), 0, st, f,
+                     reinterpret_cast<const u16x8*>(wfrag), w32, thr, nprobe_max, nprobe, fallback);
   return hipGetLastError();
 }
 

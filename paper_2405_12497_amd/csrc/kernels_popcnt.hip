@@ -15,7 +15,9 @@ constexpr int kWaves = kThreads / kWave;
 // each code. PHASE 0 (bootstrap) keeps every code: its candidate entry and
 // its estimated distance go to the unit's segment and bootstrap slots.
 // PHASE 1 keeps the codes with lb <= tau, compacted into the segment.
-template <int WS, int UN, int PHASE, typename PL>
+// PHASE 2 (parity export) writes every code's ip, popcount, estimate,
+// distance and bound to the debug arrays at its offset from s.dbg_base.
+template <int WS, int UN, int PHASE, int NPL, typename PL>
 __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w, int32_t b0, int32_t wend,
                                           const PairRec& rec, const PairTerms& pt, const PL& pl, float tau, int& count) {
   const int lane = lane_id();
@@ -41,21 +43,25 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
       for (int t = 0; t < WS; ++t) x[u][t] = row[u][64 * t];
 #pragma unroll
     for (int u = 0; u < UN; ++u) {
-      int s0 = 0, s1 = 0, s2 = 0, s3 = 0, c = 0;
+      int sj[NPL];
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) sj[j] = 0;
+      int c = 0;
 #pragma unroll
       for (int t = 0; t < WS; ++t) {
         c += __popcll(x[u][t]);
-        s0 += __popcll(x[u][t] & pl.get(0, t));
-        s1 += __popcll(x[u][t] & pl.get(1, t));
-        s2 += __popcll(x[u][t] & pl.get(2, t));
-        s3 += __popcll(x[u][t] & pl.get(3, t));
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) sj[j] += __popcll(x[u][t] & pl.get(j, t));
       }
-      ip[u] = s0 + 2 * s1 + 4 * s2 + 8 * s3;
+      int v = 0;
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) v += sj[j] << j;
+      ip[u] = v;
       pc[u] = c;
     }
   } else {
 #pragma unroll
-    for (int u = 0; u < UN; ++u) code_ip<0>(row[u], W, pl, ip[u], pc[u]);
+    for (int u = 0; u < UN; ++u) code_ip<0, NPL>(row[u], W, pl, ip[u], pc[u]);
   }
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
@@ -73,6 +79,15 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
         e.pos = p[u];
         s.p0buf[w.p0slot + off] = e;
       }
+    } else if constexpr (PHASE == 2) {
+      if (valid[u]) {
+        const int64_t o = (int64_t)p[u] - s.dbg_base;
+        s.dbg_ip[o] = ip[u];
+        s.dbg_pc[o] = pc[u];
+        s.dbg_est[o] = estimate_est(rec, s.fac[p[u]].y, ip[u], pc[u]);
+        s.dbg_dist[o] = dist;
+        s.dbg_lb[o] = lb;
+      }
     } else {
       const bool pass = valid[u] && (lb <= tau);
       const uint64_t m = __ballot(pass);
@@ -89,7 +104,7 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
 
 // One unit: steps of UN blocks of 64 codes while they are full, then single
 // blocks for the rest (short lists do not pay for a mostly masked wide step).
-template <int WS, int UN, int PHASE, typename PL>
+template <int WS, int UN, int PHASE, int NPL, typename PL>
 __device__ __forceinline__ int scan_unit(const SearchDev& s, const UnitDesc& w, const PairRec& rec, const PL& pl,
                                          float tau, float hwk) {
   const PairTerms pt = pair_terms(rec, hwk);
@@ -100,10 +115,10 @@ __device__ __forceinline__ int scan_unit(const SearchDev& s, const UnitDesc& w, 
     // LDS planes are re-read every step (shared by its UN codes) rather than
     // hoisted into 8W registers, which would cut the occupancy
     if constexpr (!(WS >= 1 && WS <= 4)) asm volatile("" ::: "memory");
-    scan_step<WS, UN, PHASE>(s, w, b0, wend, rec, pt, pl, tau, count);
+    scan_step<WS, UN, PHASE, NPL>(s, w, b0, wend, rec, pt, pl, tau, count);
   }
-  for (; b0 < wend; b0 += 64) scan_step<WS, 1, PHASE>(s, w, b0, wend, rec, pt, pl, tau, count);
-  return PHASE == 0 ? w.len : count;
+  for (; b0 < wend; b0 += 64) scan_step<WS, 1, PHASE, NPL>(s, w, b0, wend, rec, pt, pl, tau, count);
+  return PHASE == 0 ? w.len : PHASE == 1 ? count : 0;
 }
 
 // Persistent scan: wave i of the grid takes units i, i + nwaves, ... of the
@@ -112,17 +127,17 @@ __device__ __forceinline__ int scan_unit(const SearchDev& s, const UnitDesc& w, 
 // loop is pipelined: while a unit is scanned, the descriptor two units ahead
 // and the pair record and bit planes (one word per lane) of the next unit are
 // already being loaded.
-template <int WS, int UN, int PHASE>
+template <int WS, int UN, int PHASE, int NPL>
 __global__ __launch_bounds__(kThreads) void k_scan_popcnt(SearchDev s) {
-  __shared__ uint64_t lds_planes[kWaves][4 * (kMaxCodeBits / 64)];
+  __shared__ uint64_t lds_planes[kWaves][NPL * (kMaxCodeBits / 64)];
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int64_t total = uniform_i64((PHASE == 0 ? s.off_p0 : s.off_p1)[s.nq]);
-  const UnitDesc* tab = PHASE == 0 ? s.units0 : s.units1;
+  const UnitDesc* tab = PHASE == 0 ? s.units0 : s.units1;   // phase 2 runs the main-phase table
   const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
   const int64_t nw = (int64_t)gridDim.x * kWaves;
-  const int nplw = 4 * s.W;                       // plane words of a pair
-  // plane words per lane: 4 W words spread over the wave
-  constexpr int kPlPerLane = WS > 0 ? (4 * WS + kWave - 1) / kWave : kMaxCodeBits / 64 * 4 / kWave;
+  const int nplw = NPL * s.W;                     // plane words of a pair
+  // plane words per lane: NPL W words spread over the wave
+  constexpr int kPlPerLane = WS > 0 ? (NPL * WS + kWave - 1) / kWave : kMaxCodeBits / 64 * NPL / kWave;
   int64_t u = uniform_i64((int64_t)blockIdx.x * kWaves + wave);
   UnitDesc w, wn;
   PairRec rec;
@@ -148,10 +163,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_popcnt(SearchDev s) {
     PairRec recn;
     uint64_t plvn[kPlPerLane];
     if (u1 < total) fetch_pair(wn, recn, plvn);
-    PlanesFor<WS> pl;
+    PlanesFor<WS, NPL> pl;
     if constexpr (WS >= 1 && WS <= 4) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < NPL; ++j)
 #pragma unroll
         for (int t = 0; t < WS; ++t) {
           const int k = j * WS + t;   // word k sits in lane k % 64 of register k / 64
@@ -169,8 +184,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_popcnt(SearchDev s) {
       pl.p = dst;
       pl.Wr = s.W;
     }
-    const float tau = PHASE == 0 ? __builtin_inff() : uniform_f32(s.tau[w.q]);
-    const int count = scan_unit<WS, UN, PHASE>(s, w, rec, pl, tau, hwk);
+    const float tau = PHASE == 1 ? uniform_f32(s.tau[w.q]) : __builtin_inff();
+    const int count = scan_unit<WS, UN, PHASE, NPL>(s, w, rec, pl, tau, hwk);
     if (lane == 0) s.seg_count[w.count_slot] = count;
     u = u1;
     w = wn;
@@ -181,47 +196,61 @@ __global__ __launch_bounds__(kThreads) void k_scan_popcnt(SearchDev s) {
   }
 }
 
+template <int WS, int UN, int NPL>
+void launch_scan_np(const SearchDev& s, int phase, int grid, hipStream_t st) {
+  if (phase == 0) {
+    hipLaunchKernelGGL((k_scan_popcnt<WS, UN, 0, NPL>), dim3(grid), dim3(kThreads), 0, st, s);
+  } else if (phase == 1) {
+    hipLaunchKernelGGL((k_scan_popcnt<WS, UN, 1, NPL>), dim3(grid), dim3(kThreads), 0, st, s);
+  } else {
+    hipLaunchKernelGGL((k_scan_popcnt<WS, UN, 2, NPL>), dim3(grid), dim3(kThreads), 0, st, s);
+  }
+}
 template <int WS, int UN>
 void launch_scan_ws(const SearchDev& s, int phase, int grid, hipStream_t st) {
-  if (phase == 0) {
-    hipLaunchKernelGGL((k_scan_popcnt<WS, UN, 0>), dim3(grid), dim3(kThreads), 0, st, s);
+  if (s.npl == 8) {
+    launch_scan_np<WS, UN, 8>(s, phase, grid, st);
   } else {
-    hipLaunchKernelGGL((k_scan_popcnt<WS, UN, 1>), dim3(grid), dim3(kThreads), 0, st, s);
+    launch_scan_np<WS, UN, 4>(s, phase, grid, st);
   }
 }
 
 }  // namespace
 
 namespace {
-template <int WS, int UN>
-int blocks_per_cu_ws() {
+template <int WS, int UN, int NPL>
+int blocks_per_cu_np() {
   static int nb = 0;
   if (nb == 0) {
     int v0 = 0, v1 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v0, (const void*)k_scan_popcnt<WS, UN, 0>, kThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v0, (const void*)k_scan_popcnt<WS, UN, 0, NPL>, kThreads, 0) !=
             hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&v1, (const void*)k_scan_popcnt<WS, UN, 1>, kThreads, 0) !=
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&v1, (const void*)k_scan_popcnt<WS, UN, 1, NPL>, kThreads, 0) !=
             hipSuccess)
       v0 = v1 = 1;
     nb = std::max(1, std::min(v0, v1));
   }
   return nb;
 }
+template <int WS, int UN>
+int blocks_per_cu_ws(int npl) {
+  return npl == 8 ? blocks_per_cu_np<WS, UN, 8>() : blocks_per_cu_np<WS, UN, 4>();
+}
 }  // namespace
 
-// Resident blocks per CU of the scan instantiation used for W words (the
+// Resident blocks per CU of the scan instantiation used for W words and npl planes (the
 // smaller of its two phases): the persistent grid is sized to what fits, so
 // that the static round-robin of units never waits for a second wave
 // generation.
-int scan_popcnt_blocks_per_cu(int W) {
+int scan_popcnt_blocks_per_cu(int W, int npl) {
   switch (W) {
-    case 1: return blocks_per_cu_ws<1, 4>();
-    case 2: return blocks_per_cu_ws<2, 4>();
-    case 3: return blocks_per_cu_ws<3, 4>();
-    case 4: return blocks_per_cu_ws<4, 4>();
-    case 12: return blocks_per_cu_ws<12, 4>();
-    case 15: return blocks_per_cu_ws<15, 2>();
-    default: return blocks_per_cu_ws<0, 2>();
+    case 1: return blocks_per_cu_ws<1, 4>(npl);
+    case 2: return blocks_per_cu_ws<2, 4>(npl);
+    case 3: return blocks_per_cu_ws<3, 4>(npl);
+    case 4: return blocks_per_cu_ws<4, 4>(npl);
+    case 12: return blocks_per_cu_ws<12, 4>(npl);
+    case 15: return blocks_per_cu_ws<15, 2>(npl);
+    default: return blocks_per_cu_ws<0, 2>(npl);
   }
 }
 

@@ -488,6 +488,54 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe_grp(const float* _
 
 }  // namespace
 
+// Probe rank of the neighbours' lists (training labels of the learned
+// nprobe). One wave per query: among the lists of its k neighbour ids (ids < 0
+// are skipped) the one latest in probe order, i.e. with the largest key
+// (squared centroid distance, list id), and its rank = the number of lists
+// with a smaller key, so that the smallest nprobe probing every neighbour's
+// list is rank + 1 (0 when no id is valid).
+__global__ __launch_bounds__(kSelThreads) void k_probe_need(const float* __restrict__ D, int64_t nq, int nlist,
+                                                            const int64_t* __restrict__ nn, int k,
+                                                            const int32_t* __restrict__ id2list, int64_t n,
+                                                            int32_t* __restrict__ need) {
+  const int64_t q = (int64_t)blockIdx.x * (kSelThreads / kWave) + (threadIdx.x >> 6);
+  if (q >= nq) return;   // whole waves
+  const int lane = lane_id();
+  const float* row = D + q * (int64_t)nlist;
+  // the largest (distance bits, list) key among the neighbours' lists
+  uint64_t worst = 0;
+  bool any = false;
+  for (int j = lane; j < k; j += kWave) {
+    const int64_t id = nn[q * k + j];
+    if (id < 0 || id >= n) continue;
+    const int32_t l = id2list[id];
+    const uint64_t key = ((uint64_t)__float_as_uint(fmaxf(row[l], 0.f)) << 32) | (uint32_t)l;
+    worst = any && worst > key ? worst : key;
+    any = true;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t y = __shfl_xor(worst, o, kWave);
+    worst = worst > y ? worst : y;
+  }
+  const bool has = __ballot(any) != 0ull;
+  int cnt = 0;
+  for (int l = lane; l < nlist; l += kWave) {
+    const uint64_t key = ((uint64_t)__float_as_uint(fmaxf(row[l], 0.f)) << 32) | (uint32_t)l;
+    cnt += key < worst;
+  }
+  cnt = wave_sum_i(cnt);
+  if (lane == 0) need[q] = has ? cnt + 1 : 0;
+}
+
+hipError_t launch_probe_need(const float* D, int64_t nq, int nlist, const int64_t* nn, int k, const int32_t* id2list,
+                             int64_t n, int32_t* need, hipStream_t st) {
+  if (nq <= 0) return hipSuccess;
+  const int per = kSelThreads / kWave;
+  hipLaunchKernelGGL(k_probe_need, dim3((unsigned)((nq + per - 1) / per)), dim3(kSelThreads), 0, st, D, nq, nlist,
+                     nn, k, id2list, n, need);
+  return hipGetLastError();
+}
+
 hipError_t launch_select_probe(const float* D, const float* gmin, int64_t nq, int nlist, int nprobe,
                                const int32_t* nprobe_q, int32_t* lists, float* dists,
                                hipStream_t st) {

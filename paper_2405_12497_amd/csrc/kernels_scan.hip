@@ -41,14 +41,15 @@ __device__ __forceinline__ void pair_coeffs(double vl, double delta, int sq, dou
   r.k0 = (float)(-dr * (double)sq - rd * vl);
 }
 
-// v_l = rmin / b and Delta = range / (15 b) of a pair, in FP64 (0 when b = 0).
-__device__ __forceinline__ void pair_scalars(float rmin, float range, float b, double& vl, double& delta) {
+// v_l = rmin / b and Delta = range / ((2^B_q - 1) b) of a pair, in FP64 (0 when b = 0).
+__device__ __forceinline__ void pair_scalars(float rmin, float range, float b, int qmax, double& vl,
+                                             double& delta) {
   vl = 0.0;
   delta = 0.0;
   if (b > 0.f) {
     const double ib = 1.0 / (double)b;
     vl = (double)rmin * ib;
-    delta = (double)range * ib * (1.0 / 15.0);
+    delta = (double)range * ib / (double)qmax;
   }
 }
 
@@ -57,9 +58,9 @@ constexpr int kWaves = kThreads / kWave;
 
 // Per (query, list) pair, Section 3.3.1: residual r = q_rot - c_rot (the
 // rotated-space form of P^T (q_r - c)), b = ||r|| (= ||q_r - c|| since P is
-// orthogonal), v_l / v_r = min / max of r / b, Delta = (v_r - v_l) / 15 and
-// the randomized rounding q_u[i] = min(15, floor((r_i/b - v_l)/Delta + u_i)),
-// written as 4 bit planes (and as int8 for the MFMA scan), plus the pair's
+// orthogonal), v_l / v_r = min / max of r / b, Delta = (v_r - v_l) / (2^B_q - 1)
+// and the randomized rounding q_u[i] = min(2^B_q - 1, floor((r_i/b - v_l)/Delta + u_i)),
+// written as s.npl bit planes (and as int8 q_u - s.qoff for the MFMA scan), plus the pair's
 // estimator constants. One wave handles PPW pairs with the residual held in
 // registers (WS >= W words of 64 coordinates, compile-time bound), so each
 // coordinate is loaded once.
@@ -159,10 +160,11 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     rmax = wave_max(rmax);
     const float range = rmax - rmin;
     const bool live = (b > 0.f) && (range > 0.f);
-    const float scale = live ? 15.f / range : 0.f;
+    const float scale = live ? (float)s.qmax / range : 0.f;
     const uint64_t qid = (uint64_t)(s.qid_base + q);
     int sq = 0;
-    uint64_t* pl = s.planes + g * 4 * W;
+    const int npl = s.npl;
+    uint64_t* pl = s.planes + g * npl * W;
     int8_t* q8 = s.qu8 ? s.qu8 + g * s.dp : nullptr;
 #pragma unroll
     for (int t = 0; t < WS; ++t) {
@@ -170,11 +172,10 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
         const int i = t * kWave + lane;
         // a pair that is not live has scale 0, so x = 0 and floor(u) = 0
         const float x = (rv[j][t] - rmin) * scale;
-        const int qu = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
+        const int qu = min(s.qmax, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
         sq += qu;
-        if (q8) q8[i] = (int8_t)qu;
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
+        if (q8) q8[i] = (int8_t)(qu - s.qoff);
+        for (int jb = 0; jb < npl; ++jb) {
           const uint64_t w = __ballot((qu >> jb) & 1);
           if (lane == 0) pl[jb * W + t] = w;
         }
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     sq = wave_sum_i(sq);
     if (lane == 0) {
       double vl, delta;
-      pair_scalars(rmin, range, b, vl, delta);
+      pair_scalars(rmin, range, b, s.qmax, vl, delta);
       pair_coeffs(vl, delta, sq, s.rd, s.ird, rec);
       rec.b = b;
       rec.vl = (float)vl;
@@ -281,7 +282,7 @@ __device__ __forceinline__ void prep_q_body(const SearchDev& s, int64_t blk) {
   }
   const float range = rmax - rmin;
   const bool live = act && (b > 0.f) && (range > 0.f);
-  const float scale = live ? 15.f / range : 0.f;
+  const float scale = live ? (float)s.qmax / range : 0.f;   // B_q <= 4 on this path (s.npl == 4)
   const uint64_t qid = (uint64_t)(s.qid_base + q);
   int8_t* q8 = QU8 ? s.qu8 + gc * s.dp : nullptr;
   int sq = 0;
@@ -294,9 +295,9 @@ __device__ __forceinline__ void prep_q_body(const SearchDev& s, int64_t blk) {
       const int i = t * kWave + l + 16 * j;
       // a pair that is not live has scale 0, so x = 0 and floor(u) = 0
       const float x = (rv[t][j] - rmin) * scale;
-      qu[j] = min(15, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)max(list, 0), (uint32_t)i)));
+      qu[j] = min(s.qmax, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)max(list, 0), (uint32_t)i)));
       sq += qu[j];
-      if (QU8 && act) q8[i] = (int8_t)qu[j];
+      if (QU8 && act) q8[i] = (int8_t)(qu[j] - s.qoff);
     }
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
@@ -316,7 +317,7 @@ __device__ __forceinline__ void prep_q_body(const SearchDev& s, int64_t blk) {
       rec.list = -1;
     } else {
       double vl, delta;
-      pair_scalars(rmin, range, b, vl, delta);
+      pair_scalars(rmin, range, b, s.qmax, vl, delta);
       pair_coeffs(vl, delta, sq, s.rd, s.ird, rec);
       rec.b = b;
       rec.vl = (float)vl;
@@ -852,6 +853,7 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s, int W, uint64_t* 
   const int mstride = min(kMaxK, 4 * s.k);
   const int m = min(n0, mstride);
   const int lo = (int)((int64_t)m * wsub / W), hi = (int)((int64_t)m * (wsub + 1) / W);
+  if (wsub == 0 && lane == 0) s.q_boot[q] = m;   // exact distances of the bootstrap rerank
   if (m > 0) {
     const EstEnt* est = s.p0buf + b0;
     wave_smallest<8, kMaxP0 / kWave>([&](int i) { return __float_as_uint(est[i].dist); },
@@ -1214,7 +1216,7 @@ __global__ __launch_bounds__(kThreads, WIDE ? 3 : 4) void k_finalize(SearchDev s
       s.out_d[q * K + i] = live ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
     }
     if (lane == 0) {
-      s.q_rerank[q] = reranked;
+      s.q_rerank[q] = reranked - seeds;   // the seeds' distances were computed by the bootstrap rerank
       s.q_cand[q] = ncand;
     }
   } else {
@@ -1227,8 +1229,8 @@ __global__ __launch_bounds__(kThreads, WIDE ? 3 : 4) void k_finalize(SearchDev s
 }
 
 // Merge of a query's W partial top-k lists (W K <= kFinMergeCap keys): the k best
-// distinct (distance, id) keys, and the statistics: the seeds once plus every
-// wave's own reranks, and every wave's candidates. fin_merge_out takes the
+// distinct (distance, id) keys, and the statistics: every wave's own reranks
+// (the seeds were reranked by the bootstrap) and every wave's candidates. fin_merge_out takes the
 // keys sorted in sel[0..n); one wave.
 __device__ __forceinline__ void fin_merge_out(const SearchDev& s, int64_t q, int W, const uint64_t* sel, int n,
                                               const int32_t* __restrict__ pst) {
@@ -1251,17 +1253,15 @@ __device__ __forceinline__ void fin_merge_out(const SearchDev& s, int64_t q, int
     s.out_ids[q * K + i] = -1;
     s.out_d[q * K + i] = __builtin_inff();
   }
-  int rer = 0, cand = 0, seeds = 0;
+  int rer = 0, cand = 0;
   for (int w = lane; w < W; w += kWave) {
     rer += pst[(q * W + w) * 2];
     cand += pst[(q * W + w) * 2 + 1];
   }
-  for (int i = lane; i < K; i += kWave) seeds += s.seedk[q * K + i].id >= 0;
   rer = wave_sum_i(rer);
   cand = wave_sum_i(cand);
-  seeds = wave_sum_i(seeds);
   if (lane == 0) {
-    s.q_rerank[q] = seeds + rer;
+    s.q_rerank[q] = rer;
     s.q_cand[q] = cand;
   }
 }
@@ -1299,7 +1299,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_fin_merge_block(SearchDev s, 
 }
 
 // ------------------------------------------------------------------ debug
-__global__ void k_debug_pack(const uint8_t* __restrict__ qu, int dp, int W, float b, float vl,
+__global__ void k_debug_pack(const uint8_t* __restrict__ qu, int dp, int W, int npl, int qoff, float b, float vl,
                              float delta, PairRec* rec, uint64_t* planes, int8_t* qu8,
                              int32_t list, double rd, double ird) {
   // one wave
@@ -1309,9 +1309,8 @@ __global__ void k_debug_pack(const uint8_t* __restrict__ qu, int dp, int W, floa
     const int i = t * kWave + lane;
     const int v = qu[i];
     sq += v;
-    if (qu8) qu8[i] = (int8_t)v;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    if (qu8) qu8[i] = (int8_t)(v - qoff);
+    for (int j = 0; j < npl; ++j) {
       const uint64_t w = __ballot((v >> j) & 1);
       if (lane == 0) planes[j * W + t] = w;
     }
@@ -1329,38 +1328,6 @@ __global__ void k_debug_pack(const uint8_t* __restrict__ qu, int dp, int W, floa
   }
 }
 
-template <int WS>
-__global__ __launch_bounds__(kThreads) void k_debug_scan(SearchDev s, const PairRec* recp,
-                                                         const uint64_t* planes, int32_t list,
-                                                         int32_t* ip_o, int32_t* pc_o, float* est_o,
-                                                         float* dist_o, float* lb_o) {
-  __shared__ uint64_t lds_planes[4 * (kMaxCodeBits / 64)];
-  const int64_t beg = uniform_i64(s.list_off[list]), end = uniform_i64(s.list_off[list + 1]);
-  const PairRec rec = *recp;
-  for (int i = threadIdx.x; i < 4 * s.W; i += blockDim.x) lds_planes[i] = planes[i];
-  __syncthreads();
-  PlanesFor<WS> pl;
-  if constexpr (WS >= 1 && WS <= 4) {
-    pl.load(planes);
-  } else {
-    pl.p = lds_planes;
-    pl.Wr = s.W;
-  }
-  const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
-  const int64_t p = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= end) return;
-  int ip, pc;
-  float est, dist, lb;
-  code_ip<WS>(code_row(s.codes, (int32_t)p, s.W), s.W, pl, ip, pc);
-  estimate(rec, pair_terms(rec, hwk), s.sfac[p], ip, pc, dist, lb);
-  est = estimate_est(rec, s.fac[p].y, ip, pc);
-  const int64_t o = p - beg;
-  ip_o[o] = ip;
-  pc_o[o] = pc;
-  est_o[o] = est;
-  dist_o[o] = dist;
-  lb_o[o] = lb;
-}
 
 
 }  // namespace
@@ -1391,6 +1358,11 @@ hipError_t launch_prep(const SearchDev& s, bool units, hipStream_t st) {
   const int64_t nrb = (s.nprobe + kWave - 1) / kWave;
   const int64_t ublocks = units ? (s.nq * nrb + kWaves - 1) / kWaves : 0;
   if (s.W <= 0 || s.W > 64) return hipErrorInvalidValue;
+  if (s.npl == 8 && s.W <= 4) {   // the quarter-wave form holds 4 W plane words per row: B_q <= 4 only
+    hipLaunchKernelGGL((k_prep_reg<4, 2>), grid(2), dim3(kThreads), 0, st, s);
+    if (units) hipLaunchKernelGGL(k_units, dim3((unsigned)ublocks), dim3(kThreads), 0, st, s);
+    return hipGetLastError();
+  }
   switch (s.W) {
     case 1: launch_prep_q<1>(s, ublocks, qblocks, st); return hipGetLastError();
     case 2: launch_prep_q<2>(s, ublocks, qblocks, st); return hipGetLastError();
@@ -1483,11 +1455,11 @@ hipError_t launch_finalize(const SearchDev& s, hipStream_t st) {
   return launch_finalize_split(s, 1, nullptr, nullptr, st);
 }
 
-hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, float b, float vl, float delta,
+hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, int npl, int qoff, float b, float vl, float delta,
                              PairRec* rec, uint64_t* planes, int8_t* qu8, int32_t list,
                              hipStream_t st) {
   const double rd = std::sqrt((double)dp);
-  hipLaunchKernelGGL(k_debug_pack, dim3(1), dim3(kWave), 0, st, qu, dp, W, b, vl, delta, rec,
+  hipLaunchKernelGGL(k_debug_pack, dim3(1), dim3(kWave), 0, st, qu, dp, W, npl, qoff, b, vl, delta, rec,
                      planes, qu8, list, rd, 1.0 / rd);
   return hipGetLastError();
 }
@@ -1505,18 +1477,12 @@ hipError_t launch_debug_scan(const SearchDev& s, const PairRec* rec, const uint6
   if (n == 0) return hipSuccess;
   if (kernel == 2)
     return launch_debug_mfma(s, rec, qu8, list, (n + s.chunk - 1) / s.chunk, ip, pc, est, dist, lb, st);
-  const dim3 grid((n + kThreads - 1) / kThreads);
-  switch (s.W) {
-    case 2:
-      hipLaunchKernelGGL(k_debug_scan<2>, grid, dim3(kThreads), 0, st, s, rec, planes, list, ip, pc,
-                         est, dist, lb);
-      break;
-    default:
-      hipLaunchKernelGGL(k_debug_scan<0>, grid, dim3(kThreads), 0, st, s, rec, planes, list, ip, pc,
-                         est, dist, lb);
-      break;
-  }
-  return hipGetLastError();
+  // the production popcount scan, phase 2, over the unit table the caller
+  // prepared in s.units1 (s.off_p1[s.nq] units of pair 0)
+  (void)planes;
+  const int units = (n + s.chunk - 1) / s.chunk;   // one wave each
+  const int grid = std::max(1, (units + 3) / 4);
+  return launch_scan_popcnt(s, 2, grid, st);
 }
 
 }  // namespace rbq

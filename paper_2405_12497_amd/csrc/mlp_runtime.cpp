@@ -99,10 +99,36 @@ void init_weights(uint64_t seed, std::vector<float>& w) {
   for (int i = 0; i < kMlpHidden * kMlpOut; ++i) w[kMlpW2 + i] = (float)((2 * uni(1000000 + i) - 1) * a2);
 }
 
+// FP32 -> BF16, round to nearest even (the rounding the GEMM kernels apply
+// when they stage operands).
+uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ search hook
 namespace rbq {
+
+// Uploads the current FP32 weights (m.host_w) and their BF16 fragment-order
+// copy that the fused inference kernel reads.
+rbq_status upload_model_weights(MlpState& m) {
+  std::vector<uint16_t> frag(kMlpFragWords);
+  for (int i = 0; i < kMlpIn; ++i)
+    for (int j = 0; j < kMlpHidden; ++j)
+      frag[mlp_fragment_index(1, i, j)] = bf16_rne(m.host_w[kMlpW1 + i * kMlpHidden + j]);
+  for (int i = 0; i < kMlpHidden; ++i)
+    for (int j = 0; j < kMlpOut; ++j)
+      frag[mlp_fragment_index(2, i, j)] = bf16_rne(m.host_w[kMlpW2 + i * kMlpOut + j]);
+  HIPCHK(m.w32.ensure((size_t)kMlpParams * 4));
+  HIPCHK(m.wfrag.ensure(frag.size() * 2));
+  HIPCHK(hipMemcpy(m.w32.p, m.host_w.data(), (size_t)kMlpParams * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(m.wfrag.p, frag.data(), frag.size() * 2, hipMemcpyHostToDevice));
+  return RBQ_OK;
+}
 
 rbq_status features_into(rbq_index* idx, const float* queries, int64_t nq, int64_t qid_base,
                          float* feats, hipStream_t st) {
@@ -149,17 +175,20 @@ rbq_status predict_into(rbq_index* idx, const float* feats, int64_t nq, int npro
 }
 
 // Learned path of a search: one centroid scoring / probe selection with `stride`
-// lists per query (>= 64 when the index has that many lists); the features
-// read the nearest 64 of them, and the search reuses the same selection.
+// lists per query (>= 64 when the index has that many lists), then one fused
+// launch computes each query's features from the nearest 64 of them, the MLP
+// and the policy; the search reuses the same selection with the per-query
+// nprobe. A query whose logits are not finite gets nprobe_max, the caller's
+// fixed nprobe (flagged in ws.q_fb).
 rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int nprobe_max, int stride,
                           int64_t qid_base, hipStream_t st, const int32_t** out) {
   Workspace& w = idx->ws;
-  HIPCHK(w.feats.ensure((size_t)nq * kMlpIn * 4));
   HIPCHK(w.nprobe_q.ensure((size_t)nq * 4));
+  HIPCHK(w.q_fb.ensure((size_t)nq * 4));
   rbq_status rs = front(idx, queries, nq, stride, nullptr, st);
   if (rs != RBQ_OK) return rs;
   FeatDev f;
-  f.feats = (float*)w.feats.p;
+  f.feats = nullptr;
   f.probe_d = (const float*)w.probe_d.p;
   f.probe = (const int32_t*)w.probe.p;
   f.stride = stride;
@@ -174,9 +203,8 @@ rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int 
   f.nq = nq;
   f.qid_base = qid_base;
   f.seed = idx->prm.seed;
-  HIPCHK(launch_features(f, st));
-  rs = predict_into(idx, (const float*)w.feats.p, nq, nprobe_max, (int32_t*)w.nprobe_q.p, nullptr, st);
-  if (rs != RBQ_OK) return rs;
+  HIPCHK(launch_learned_front(f, (const uint16_t*)idx->mlp.wfrag.p, (const float*)idx->mlp.w32.p,
+                              idx->mlp.threshold, nprobe_max, (int32_t*)w.nprobe_q.p, (int32_t*)w.q_fb.p, st));
   *out = (const int32_t*)w.nprobe_q.p;
   return RBQ_OK;
 }
@@ -211,8 +239,8 @@ extern "C" rbq_status rbq_nprobe_model_set(rbq_index* idx, const float* weights,
   for (int i = 0; i < kMlpParams; ++i)
     if (!std::isfinite(weights[i])) return fail(RBQ_EINVAL, "weights contain non-finite values");
   m.host_w.assign(weights, weights + kMlpParams);
-  HIPCHK(m.w32.ensure((size_t)kMlpParams * 4));
-  HIPCHK(hipMemcpy(m.w32.p, weights, (size_t)kMlpParams * 4, hipMemcpyHostToDevice));
+  rbq_status rs = upload_model_weights(m);
+  if (rs != RBQ_OK) return rs;
   m.threshold = threshold;
   m.has_model = true;
   return RBQ_OK;
@@ -249,7 +277,7 @@ extern "C" rbq_status rbq_mlp_loss_grad(const float* x, const int32_t* labels, i
   if (!is_device_ptr(x) || !is_device_ptr(labels) || !is_device_ptr(weights) || !is_device_ptr(grads))
     return fail(RBQ_EINVAL, "x, labels, weights and grads must be device pointers");
   hipStream_t st = (hipStream_t)stream;
-  DBuf buf;
+  TmpBuf buf;
   HIPCHK(buf.ensure(pass_floats(n) * 4));
   const Pass p = carve((float*)buf.p, n);
   HIPCHK(hipMemsetAsync(p.loss, 0, 4, st));
@@ -287,7 +315,7 @@ extern "C" rbq_status rbq_nprobe_model_train(rbq_index* idx, const float* feats,
   HIPCHK(hipMemsetAsync(m.v.p, 0, (size_t)kMlpParams * 4, st));
   // Inputs are standardised per feature for training; the statistics are
   // folded into W1 and b1 afterwards, so the model consumes raw features.
-  DBuf xs, stats;
+  TmpBuf xs, stats;
   HIPCHK(xs.ensure((size_t)n * kMlpIn * 4));
   HIPCHK(stats.ensure((size_t)2 * kMlpIn * 4));
   float* mu = (float*)stats.p;
@@ -298,7 +326,7 @@ extern "C" rbq_status rbq_nprobe_model_train(rbq_index* idx, const float* feats,
   const int64_t B = std::min<int64_t>(cfg->batch, n);
   HIPCHK(m.act.ensure(pass_floats(B) * 4));
   const Pass p = carve((float*)m.act.p, B);
-  DBuf xb, yb, perm;
+  TmpBuf xb, yb, perm;
   HIPCHK(xb.ensure((size_t)B * kMlpIn * 4));
   HIPCHK(yb.ensure((size_t)B * 4));
   HIPCHK(perm.ensure((size_t)n * 4));
@@ -344,13 +372,59 @@ extern "C" rbq_status rbq_nprobe_model_train(rbq_index* idx, const float* feats,
       }
       m.host_w[kMlpB1 + j] -= (float)shift;
     }
-    HIPCHK(hipMemcpy(m.w32.p, m.host_w.data(), (size_t)kMlpParams * 4, hipMemcpyHostToDevice));
   }
   for (float v : m.host_w)
     if (!std::isfinite(v)) {
       m.has_model = false;
       return fail(RBQ_EDEVICE, "training diverged (non-finite weights); model disabled");
     }
+  rbq_status rs = upload_model_weights(m);
+  if (rs != RBQ_OK) return rs;
   m.has_model = true;
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_nprobe_bucket_table(int32_t* nprobe) {
+  if (!nprobe) return fail(RBQ_EINVAL, "NULL argument");
+  for (int j = 0; j < kMlpOut; ++j) nprobe[j] = mlp_bucket_nprobe(j);
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_nprobe_labels(rbq_index* idx, const float* queries, int64_t nq, const int64_t* nn_ids,
+                                        int32_t k, int32_t* labels, int32_t* need, void* stream) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  if (nq < 0 || k < 1 || k > kMaxK) return fail(RBQ_EINVAL, "nq < 0 or k outside [1, %d]", kMaxK);
+  if (nq == 0) return RBQ_OK;
+  if (!is_device_ptr(queries) || !is_device_ptr(nn_ids) || !is_device_ptr(labels) || (need && !is_device_ptr(need)))
+    return fail(RBQ_EINVAL, "queries, nn_ids, labels and need must be device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  if (!idx->d_id2list.p) {
+    std::vector<int32_t> m(idx->n);
+    for (int l = 0; l < idx->nlist; ++l)
+      for (int64_t p = idx->h_list_off[l]; p < idx->h_list_off[l + 1]; ++p) m[idx->h_ids[p]] = l;
+    HIPCHK(idx->d_id2list.ensure((size_t)idx->n * 4));
+    HIPCHK(hipMemcpy(idx->d_id2list.p, m.data(), (size_t)idx->n * 4, hipMemcpyHostToDevice));
+  }
+  // centroid distances in sub-batches of at most 256 MiB
+  const int64_t rows = std::max<int64_t>(16, std::min<int64_t>(nq, (256ll << 20) / ((int64_t)idx->nlist * 4)));
+  rbq_status rs = ensure_workspace(idx, std::min(rows, nq), 1, 1, kDefaultChunk, false);
+  if (rs != RBQ_OK) return rs;
+  TmpBuf tmp;
+  int32_t* nd = need;
+  if (!nd) {
+    HIPCHK(tmp.ensure((size_t)nq * 4));
+    nd = (int32_t*)tmp.p;
+  }
+  for (int64_t q0 = 0; q0 < nq; q0 += rows) {
+    const int64_t m = std::min(rows, nq - q0);
+    HIPCHK(launch_centroid_dist(queries + q0 * idx->dim, m, idx->dim, (const float*)idx->d_centT.p,
+                                (const float*)idx->d_cnorm.p, idx->nlist, (float*)idx->ws.cd.p, nullptr, st));
+    HIPCHK(launch_probe_need((const float*)idx->ws.cd.p, m, idx->nlist, nn_ids + q0 * k, k,
+                             (const int32_t*)idx->d_id2list.p, idx->n, nd + q0, st));
+  }
+  HIPCHK(launch_bucket_labels(nd, nq, labels, st));
+  if (tmp.p) HIPCHK(hipStreamSynchronize(st));   // tmp is freed on return
   return RBQ_OK;
 }

@@ -230,6 +230,8 @@ hipError_t launch_rotate_centroid(const float* Q, int64_t nq, int dim, const flo
 hipError_t launch_rotate_f64(const float* X, int64_t M, int K, const double* P, int N, float* Y,
                              hipStream_t st);
 
+// dst[p] = src[ids[p]] (rows of D floats): raw vectors in list order.
+hipError_t launch_gather_raw(const float* src, const int64_t* ids, int64_t n, int D, float* dst, hipStream_t st);
 hipError_t launch_encode(const float* Y, int64_t m, int W, const float* raw, const float* cent,
                          const int32_t* list_of, int dim, int64_t pos0, uint64_t* codes,
                          float2* fac, hipStream_t st);
@@ -243,6 +245,11 @@ hipError_t launch_select_probe(const float* D, const float* gmin, int64_t nq, in
                                const int32_t* nprobe_q, int32_t* lists, float* dists,
                                hipStream_t st);
 
+// Per query: 1 + the probe rank of the latest-probed list among the lists of
+// its k neighbour ids nn[nq x k] (ids < 0 skipped; 0 if none), ranks by (D, list id).
+hipError_t launch_probe_need(const float* D, int64_t nq, int nlist, const int64_t* nn, int k, const int32_t* id2list,
+                             int64_t n, int32_t* need, hipStream_t st);
+
 struct SearchDev {
   // index
   const uint64_t* codes;
@@ -255,6 +262,9 @@ struct SearchDev {
   const float* crot;        // nlist x Dp (P^T c_k)
   const float* cnorm;       // nlist: ||c_k||^2
   int dim, dp, W, nlist;
+  int qmax;                 // 2^B_q - 1: largest quantised query value (Sec. 3.3.1)
+  int npl;                  // bit planes stored per pair: 4 (B_q <= 4) or 8
+  int qoff;                 // int8 copy of q_u holds q_u - qoff (128 for B_q = 8, else 0)
   double rd, ird;            // sqrt(dp), 1 / sqrt(dp)
   float eps0;
   uint64_t seed;
@@ -271,7 +281,7 @@ struct SearchDev {
   const int32_t* nprobe_q;  // nq or null
   // per pair
   PairRec* pairs;           // nq x nprobe
-  uint64_t* planes;         // nq x nprobe x 4 x W
+  uint64_t* planes;         // nq x nprobe x npl x W
   int8_t* qu8;              // nq x nprobe x Dp (MFMA path) or null
   int32_t* pair_choff;      // nq x (nprobe+1) local chunk prefix
   int32_t* pair_codeoff;    // nq x (nprobe+1) local code prefix
@@ -297,7 +307,8 @@ struct SearchDev {
   EstEnt* p0buf;
   float* tau;               // nq
   SeedEnt* seedk;           // nq x k
-  int32_t* q_rerank;        // nq
+  int32_t* q_boot;          // nq: exact distances of the bootstrap rerank
+  int32_t* q_rerank;        // nq: exact distances of the final rerank
   int32_t* q_cand;          // nq
   // MFMA grouping of main-phase pairs by list
   int32_t* mf_cnt;          // nlist: pairs per list
@@ -308,6 +319,10 @@ struct SearchDev {
   // outputs
   int64_t* out_ids;
   float* out_d;
+  // parity export (scan phase 2): per code of the list at positions >= dbg_base
+  int64_t dbg_base;
+  int32_t *dbg_ip, *dbg_pc;
+  float *dbg_est, *dbg_dist, *dbg_lb;
 };
 
 // Work planning: per-query chunk and code prefixes, bootstrap extent, and the
@@ -316,17 +331,32 @@ hipError_t launch_plan(const SearchDev& s, hipStream_t st);
 // Per-pair quantisation (S3); with units = true also the scan's unit
 // descriptors, which need launch_plan's results.
 hipError_t launch_prep(const SearchDev& s, bool units, hipStream_t st);
-int scan_popcnt_blocks_per_cu(int W);
+int scan_popcnt_blocks_per_cu(int W, int npl);
 int scan_mfma_blocks_per_cu(int dp);
+// phase 0: bootstrap units, 1: main units with the bound filter, 2: parity
+// export of the main-phase table (s.dbg_*).
 hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st);
 hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t st);
 hipError_t launch_tau(const SearchDev& s, hipStream_t st);
 hipError_t launch_finalize(const SearchDev& s, hipStream_t st);
 
 // debug: list scan with a given quantised query
-hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, float b, float vl, float delta,
+hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, int npl, int qoff, float b, float vl, float delta,
                              PairRec* rec, uint64_t* planes, int8_t* qu8, int32_t list,
                              hipStream_t st);
+// k-means building blocks (kernels_index.hip): max |x| as float bits
+// (atomicMax into *out, which the caller zeroes), per-row argmin over a
+// distance matrix (ties to the lower list), fixed-point member sums
+// (sums[l][d] += round(x * scale), cnt[l] += 1), and the centroid update
+// (non-empty lists: sum / (scale cnt); writes cent, its transpose and norms).
+hipError_t launch_absmax(const float* x, int64_t n, uint32_t* out, hipStream_t st);
+hipError_t launch_row_argmin(const float* D, int64_t rows, int nlist, int32_t* lab, hipStream_t st);
+hipError_t launch_fixed_sums(const float* x, const int32_t* lab, int64_t rows, int dim, double scale,
+                             unsigned long long* sums, unsigned int* cnt, hipStream_t st);
+hipError_t launch_update_centroids(const unsigned long long* sums, const unsigned int* cnt, int nlist, int dim,
+                                   double inv_scale, float* cent, float* centT, float* cnorm, hipStream_t st);
+// x[i] ^= v for n bytes (the int8 copy of q_u back to 0 .. 2^B_q - 1)
+hipError_t launch_xor_u8(uint8_t* x, int64_t n, uint8_t v, hipStream_t st);
 hipError_t launch_debug_mfma(const SearchDev& s, const PairRec* rec, const int8_t* qu8,
                              int32_t list, int nchunks, int32_t* ip, int32_t* pc, float* est,
                              float* dist, float* lb, hipStream_t st);

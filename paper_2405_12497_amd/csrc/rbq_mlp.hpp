@@ -54,6 +54,24 @@ hipError_t launch_gather_rows(const float* X, const int32_t* y, const int32_t* i
 hipError_t launch_feat_stats(const float* X, int64_t rows, int cols, float* mu, float* inv_sd, hipStream_t st);
 hipError_t launch_standardize(const float* X, int64_t rows, int cols, const float* mu, const float* inv_sd,
                               float* Y, hipStream_t st);
+// Fused learned-nprobe step after the probe selection: features, MLP and
+// policy of every query in one launch. wfrag: the weights in fragment order
+// (kMlpFragWords uint16, see mlp_fragment_index); w32: the FP32 weights
+// (biases read from it); fallback: per query 1 when the logits were not finite.
+constexpr int kMlpFragWords = (kMlpHidden / 16) * (kMlpIn / 32) * 64 * 8 + (kMlpOut / 16) * (kMlpHidden / 32) * 64 * 8;
+hipError_t launch_learned_front(const FeatDev& f, const uint16_t* wfrag, const float* w32, float thr,
+                                int nprobe_max, int32_t* nprobe, int32_t* fallback, hipStream_t st);
+// Position in the fragment array of weight (i, j) of layer 1 (W1[i][j], i < 96
+// inputs, j < 128 hidden) or layer 2 (W2[i][j], i < 128, j < 32): the B operand
+// of v_mfma_f32_16x16x32_bf16 for output tile j / 16 and K step i / 32, whose
+// lane (j % 16) + 16 ((i % 32) / 8) holds element (i % 32) % 8.
+inline int mlp_fragment_index(int layer, int i, int j) {
+  const int lane = (j % 16) + 16 * ((i % 32) / 8), e = (i % 32) % 8;
+  if (layer == 1) return (((j / 16) * (kMlpIn / 32) + i / 32) * 64 + lane) * 8 + e;
+  const int base = (kMlpHidden / 16) * (kMlpIn / 32) * 64 * 8;
+  return base + (((j / 16) * (kMlpHidden / 32) + i / 32) * 64 + lane) * 8 + e;
+}
+hipError_t launch_bucket_labels(const int32_t* need, int64_t n, int32_t* labels, hipStream_t st);
 hipError_t launch_policy(const float* Z, int64_t n, float thr, int nprobe_max, int32_t* out, hipStream_t st);
 
 }  // namespace rbq

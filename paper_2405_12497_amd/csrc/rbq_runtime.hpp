@@ -22,6 +22,15 @@ struct DBuf {
   void release();
 };
 
+// A DBuf for temporaries of one call: released when it goes out of scope,
+// on every return path (hipFree waits for the device work that uses it).
+struct TmpBuf : DBuf {
+  TmpBuf() = default;
+  TmpBuf(const TmpBuf&) = delete;
+  TmpBuf& operator=(const TmpBuf&) = delete;
+  ~TmpBuf() { release(); }
+};
+
 // Bumped whenever any DBuf is (re)allocated or released: a captured graph
 // holds device addresses and is replayed only while this is unchanged.
 uint64_t buffer_generation();
@@ -60,6 +69,8 @@ struct GraphEntry {
 };
 
 hipError_t dmalloc(void** p, size_t bytes);
+rbq_status set_error(rbq_status st, const char* msg);
+
 bool is_device_ptr(const void* p);
 uint64_t host_splitmix64(uint64_t x);
 
@@ -67,7 +78,7 @@ struct Workspace {
   DBuf qrot, cd, cgmin, probe, probe_d, pairs, planes, qu8, pair_choff, pair_codeoff;
   DBuf q_nch, q_p0, q_n0, q_ncode, offs, counters, seg, seg_count, p0buf, tau, seedk;
   DBuf chunk_qcode;   // chunk (query order) -> first query-code index
-  DBuf q_rerank, q_cand, nprobe_q, feats, tmp;
+  DBuf q_boot, q_rerank, q_cand, nprobe_q, q_fb, feats, tmp;
   DBuf mf_cnt, mf_fill, mf_pair_off, mf_unit_off, mf_pairs, units0, units1;
   DBuf fin_part, fin_pst;   // split rerank of small batches: partial top-k lists, statistics
   DBuf tau_part;            // split bootstrap rerank: exact keys, min(256, 4k) per query
@@ -88,7 +99,7 @@ struct MlpState {
   bool has_model = false;
   float threshold = 0.9f;
   std::vector<float> host_w;   // FP32 weights, rbq_nprobe_model_set order
-  DBuf w32, wbf, grad, m, v, act;
+  DBuf w32, wbf, wfrag, grad, m, v, act;   // wfrag: BF16 weights in MFMA fragment order
 };
 
 // MFMA scan availability (kernels_mfma.hip).
@@ -120,6 +131,7 @@ struct rbq_index {
   rbq::DBuf d_codes, d_fac, d_raw, d_ids, d_list_off, d_cent, d_centT, d_cnorm, d_crot;
   rbq::DBuf d_sfac;   // scan factors per code (see estimate), derived from d_fac
   rbq::DBuf d_P32, d_Phi, d_Plo;
+  rbq::DBuf d_id2list;   // id -> list (built on first use by rbq_nprobe_labels)
 
   rbq::Workspace ws;
   rbq::MlpState mlp;
@@ -143,6 +155,7 @@ struct rbq_index {
   int64_t graph_captures = 0;
   hipStream_t cap_stream = nullptr;
   rbq::DBuf g_q, g_ids, g_d, g_npq;
+  rbq::DBuf h_stage_q, h_stage_npq, h_stage_ids, h_stage_d;   // device copies of host search arguments
   void graphs_clear();
   int pick_kernel(int64_t nq, int nprobe) const {
     (void)nprobe;

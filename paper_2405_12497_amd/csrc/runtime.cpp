@@ -207,7 +207,7 @@ rbq_status check_params(const rbq_params* p) {
     return fail(RBQ_EINVAL, "code_bits %d must be 0 or a multiple of 64 in [dim, %d]", p->code_bits, kMaxCodeBits);
   if (p->nlist < 1 || p->nlist > kMaxNlist)
     return fail(RBQ_EINVAL, "nlist %d outside [1, %d]", p->nlist, kMaxNlist);
-  if (p->bq != 4) return fail(RBQ_EUNSUPPORTED, "bq=%d: only 4-bit queries are implemented", p->bq);
+  if (p->bq < 1 || p->bq > 8) return fail(RBQ_EINVAL, "bq=%d outside [1, 8]", p->bq);
   if (!(p->eps0 >= 0.f) || !std::isfinite(p->eps0)) return fail(RBQ_EINVAL, "eps0 must be finite and >= 0");
   if (p->rot_precision != RBQ_ROT_FP32 && p->rot_precision != RBQ_ROT_BF16X3)
     return fail(RBQ_EINVAL, "unknown rot_precision %d", p->rot_precision);
@@ -226,7 +226,7 @@ void rbq_index::graphs_clear() {
 rbq_index::~rbq_index() {
   graphs_clear();
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  for (DBuf* b : {&g_q, &g_ids, &g_d, &g_npq}) b->release();
+  for (DBuf* b : {&g_q, &g_ids, &g_d, &g_npq, &h_stage_q, &h_stage_npq, &h_stage_ids, &h_stage_d}) b->release();
   prof.clear();
   prof.acc.release();
   for (DBuf* b : all_buffers()) b->release();
@@ -235,14 +235,14 @@ rbq_index::~rbq_index() {
 
 std::vector<DBuf*> rbq_index::all_buffers() {
   return {&d_codes, &d_fac, &d_sfac, &d_raw, &d_ids, &d_list_off, &d_cent, &d_centT, &d_cnorm, &d_crot,
-          &d_P32, &d_Phi, &d_Plo, &ws.qrot, &ws.cd, &ws.cgmin, &ws.probe, &ws.probe_d, &ws.pairs,
+          &d_P32, &d_Phi, &d_Plo, &d_id2list, &ws.qrot, &ws.cd, &ws.cgmin, &ws.probe, &ws.probe_d, &ws.pairs,
           &ws.planes, &ws.qu8, &ws.pair_choff, &ws.pair_codeoff, &ws.q_nch, &ws.q_p0, &ws.q_n0,
           &ws.q_ncode, &ws.offs, &ws.counters, &ws.seg, &ws.seg_count, &ws.p0buf, &ws.tau,
           &ws.chunk_qcode,
-          &ws.seedk, &ws.q_rerank, &ws.q_cand, &ws.nprobe_q, &ws.feats, &ws.tmp,
+          &ws.seedk, &ws.q_boot, &ws.q_rerank, &ws.q_cand, &ws.nprobe_q, &ws.q_fb, &ws.feats, &ws.tmp,
           &ws.mf_cnt, &ws.mf_fill, &ws.mf_pair_off, &ws.mf_unit_off, &ws.mf_pairs, &ws.units0,
           &ws.units1, &ws.fin_part, &ws.fin_pst, &ws.tau_part,
-          &mlp.w32, &mlp.wbf, &mlp.grad, &mlp.m, &mlp.v, &mlp.act};
+          &mlp.w32, &mlp.wbf, &mlp.wfrag, &mlp.grad, &mlp.m, &mlp.v, &mlp.act};
 }
 
 int64_t rbq_index::max_codes(int nprobe) const {
@@ -292,6 +292,15 @@ rbq_status rbq_index_create(const rbq_params* p, rbq_index** out) {
 rbq_status rbq_index_destroy(rbq_index* idx) {
   if (!idx) return fail(RBQ_EINVAL, "index is NULL");
   delete idx;
+  return RBQ_OK;
+}
+
+rbq_status rbq_index_set_eps0(rbq_index* idx, float eps0) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!(eps0 >= 0.f) || !std::isfinite(eps0)) return fail(RBQ_EINVAL, "eps0 must be finite and >= 0");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  idx->prm.eps0 = eps0;
+  idx->graphs_clear();   // captured searches hold the old bound
   return RBQ_OK;
 }
 
@@ -359,7 +368,7 @@ rbq_status upload_model(rbq_index* idx, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(idx->d_centT.p, ct.data(), ct.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(idx->d_cnorm.p, cn.data(), cn.size() * 4, hipMemcpyHostToDevice, st));
   // P^T c_k in FP64 on the device, stored as FP32
-  DBuf p64;
+  TmpBuf p64;
   HIPCHK(p64.ensure((size_t)D * dp * 8));
   HIPCHK(hipMemcpyAsync(p64.p, idx->h_P.data(), (size_t)D * dp * 8, hipMemcpyHostToDevice, st));
   for (int k0 = 0; k0 < L; k0 += 32768) {
@@ -407,20 +416,31 @@ void account_bytes(rbq_index* idx) {
 
 }  // namespace rbq
 
-extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t n,
-                                      const float* centroids, const int32_t* assign,
-                                      const double* gauss, void* stream) {
-  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
-  if (!data || !centroids || !assign) return fail(RBQ_EINVAL, "data, centroids and assign are required");
-  if (is_device_ptr(data) || is_device_ptr(centroids) || is_device_ptr(assign) ||
-      (gauss && is_device_ptr(gauss)))
-    return fail(RBQ_EINVAL, "rbq_index_build takes host pointers");
-  if (n < 1 || n > (int64_t)INT32_MAX - 64) return fail(RBQ_EINVAL, "n=%lld out of range", (long long)n);
-  if ((uint64_t)((n + 63) / 64 * 64) * (uint64_t)idx->W >= (1ull << 32))
-    return fail(RBQ_EINVAL, "n=%lld codes of %d words exceed 2^32 words", (long long)n, idx->W);
-  hipStream_t st = (hipStream_t)stream;
-  std::lock_guard<std::mutex> lock(idx->mu);
-  const int D = idx->dim, dp = idx->dp, L = idx->nlist, W = idx->W;
+namespace rbq {
+
+// Copy of `count` elements of a buffer that lives in host or device memory.
+template <typename T>
+rbq_status host_copy(const T* src, size_t count, std::vector<T>& out) {
+  try {
+    out.resize(count);
+  } catch (...) {
+    return fail(RBQ_ENOMEM, "host allocation failed");
+  }
+  if (count == 0) return RBQ_OK;
+  if (is_device_ptr(src)) {
+    HIPCHK(hipMemcpy(out.data(), src, count * sizeof(T), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(out.data(), src, count * sizeof(T));
+  }
+  return RBQ_OK;
+}
+
+// Algorithm 1 for data (host or device), host centroids and assignments, and
+// the rotation P (rows of the matrix whose transpose rotates: P^T v).
+rbq_status build_impl(rbq_index* idx, const float* data, int64_t n, const std::vector<float>& cent,
+                      const std::vector<int32_t>& assign, std::vector<double>& P, hipStream_t st) {
+  const int D = idx->dim, L = idx->nlist, W = idx->W;
+  const bool data_dev = is_device_ptr(data);
   // list layout (counting sort, stable in the original id)
   std::vector<int64_t> off(L + 1, 0);
   for (int64_t i = 0; i < n; ++i) {
@@ -434,22 +454,15 @@ extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t
     std::vector<int64_t> fill(off.begin(), off.end() - 1);
     for (int64_t i = 0; i < n; ++i) ids[fill[assign[i]]++] = i;
   }
-  // rotation P
-  std::vector<double> P;
-  if (gauss) {
-    P.assign(gauss, gauss + (size_t)dp * dp);
-  } else {
-    gaussian_from_seed(idx->prm.seed, dp, P);
-  }
-  for (double v : P)
-    if (!std::isfinite(v)) return fail(RBQ_EINVAL, "gauss has non-finite entries");
-  if (!orthonormalise_rows(P, dp)) return fail(RBQ_EINVAL, "gauss is rank deficient");
+  for (float v : cent)
+    if (!std::isfinite(v)) return fail(RBQ_EINVAL, "centroids have non-finite entries");
   // release an old build
   idx->built = false;
   for (DBuf* b : idx->all_buffers()) b->release();
   idx->graphs_clear();
+  idx->mlp.has_model = false;   // a model's features refer to the old lists
   idx->h_P.swap(P);
-  idx->h_cent.assign(centroids, centroids + (size_t)L * D);
+  idx->h_cent = cent;
   idx->h_list_off = off;
   idx->h_ids = ids;
   idx->n = n;
@@ -460,19 +473,22 @@ extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t
   HIPCHK(idx->d_fac.ensure((size_t)npad * sizeof(float2)));
   HIPCHK(idx->d_raw.ensure((size_t)n * D * 4));
   HIPCHK(idx->d_ids.ensure((size_t)n * 8));
-  HIPCHK(hipMemsetAsync(idx->d_codes.p, 0, (size_t)npad * W * 8, st));
-  HIPCHK(hipMemsetAsync(idx->d_fac.p, 0, (size_t)npad * sizeof(float2), st));
+  HIPCHK(launch_zero_u32(idx->d_codes.p, (int64_t)npad * W * 2, st));
+  HIPCHK(launch_zero_u32(idx->d_fac.p, (int64_t)npad * 2, st));
   HIPCHK(hipMemcpyAsync(idx->d_ids.p, ids.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
-  DBuf listof;
+  TmpBuf listof;
   HIPCHK(listof.ensure((size_t)n * 4));
   {
     std::vector<int32_t> lof(n);
     for (int k = 0; k < L; ++k)
       for (int64_t p = off[k]; p < off[k + 1]; ++p) lof[p] = k;
-    HIPCHK(hipMemcpy(listof.p, lof.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(listof.p, lof.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
   }
-  // raw vectors in list order, staged in blocks
-  {
+  // raw vectors in list order: gathered on the device, or staged from the host in blocks
+  if (data_dev) {
+    HIPCHK(launch_gather_raw(data, (const int64_t*)idx->d_ids.p, n, D, (float*)idx->d_raw.p, st));
+  } else {
     const int64_t blk = std::max<int64_t>(1, (int64_t)(64ll << 20) / ((int64_t)D * 4));
     std::vector<float> stage((size_t)std::min(blk, n) * D);
     for (int64_t p0 = 0; p0 < n; p0 += blk) {
@@ -485,8 +501,9 @@ extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t
   }
   // rotate residuals and encode, in blocks of rows
   {
+    const int dp = idx->dp;
     const int64_t blk = std::max<int64_t>(64, std::min<int64_t>(n, (int64_t)(256ll << 20) / ((int64_t)dp * 4)));
-    DBuf y;
+    TmpBuf y;
     HIPCHK(y.ensure((size_t)blk * dp * 4));
     for (int64_t p0 = 0; p0 < n; p0 += blk) {
       const int64_t m = std::min(blk, n - p0);
@@ -506,6 +523,83 @@ extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t
   return RBQ_OK;
 }
 
+rbq_status build_checks(rbq_index* idx, const float* data, int64_t n, const float* centroids,
+                        const int32_t* assign) {
+  if (!idx) return fail(RBQ_EINVAL, "index is NULL");
+  if (!data || !centroids || !assign) return fail(RBQ_EINVAL, "data, centroids and assign are required");
+  if (n < 1 || n > (int64_t)INT32_MAX - 64) return fail(RBQ_EINVAL, "n=%lld out of range", (long long)n);
+  if ((uint64_t)((n + 63) / 64 * 64) * (uint64_t)idx->W >= (1ull << 32))
+    return fail(RBQ_EINVAL, "n=%lld codes of %d words exceed 2^32 words", (long long)n, idx->W);
+  return RBQ_OK;
+}
+
+}  // namespace rbq
+
+extern "C" rbq_status rbq_index_build(rbq_index* idx, const float* data, int64_t n,
+                                      const float* centroids, const int32_t* assign,
+                                      const double* gauss, void* stream) {
+  rbq_status rs = build_checks(idx, data, n, centroids, assign);
+  if (rs != RBQ_OK) return rs;
+  std::lock_guard<std::mutex> lock(idx->mu);
+  const int dp = idx->dp;
+  std::vector<float> cent;
+  std::vector<int32_t> asg;
+  std::vector<double> P;
+  if ((rs = host_copy(centroids, (size_t)idx->nlist * idx->dim, cent)) != RBQ_OK) return rs;
+  if ((rs = host_copy(assign, (size_t)n, asg)) != RBQ_OK) return rs;
+  // rotation P: the Gaussian draw given or drawn from the seed, rows orthonormalised
+  if (gauss) {
+    if ((rs = host_copy(gauss, (size_t)dp * dp, P)) != RBQ_OK) return rs;
+  } else {
+    gaussian_from_seed(idx->prm.seed, dp, P);
+  }
+  for (double v : P)
+    if (!std::isfinite(v)) return fail(RBQ_EINVAL, "gauss has non-finite entries");
+  if (!orthonormalise_rows(P, dp)) return fail(RBQ_EINVAL, "gauss is rank deficient");
+  return build_impl(idx, data, n, cent, asg, P, (hipStream_t)stream);
+}
+
+extern "C" rbq_status rbq_index_build_rotation(rbq_index* idx, const float* data, int64_t n,
+                                               const float* centroids, const int32_t* assign,
+                                               const double* P, void* stream) {
+  rbq_status rs = build_checks(idx, data, n, centroids, assign);
+  if (rs != RBQ_OK) return rs;
+  if (!P) return fail(RBQ_EINVAL, "P is required (rbq_index_build draws one)");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  const int dp = idx->dp;
+  std::vector<float> cent;
+  std::vector<int32_t> asg;
+  std::vector<double> p;
+  if ((rs = host_copy(centroids, (size_t)idx->nlist * idx->dim, cent)) != RBQ_OK) return rs;
+  if ((rs = host_copy(assign, (size_t)n, asg)) != RBQ_OK) return rs;
+  if ((rs = host_copy(P, (size_t)dp * dp, p)) != RBQ_OK) return rs;
+  for (double v : p)
+    if (!std::isfinite(v)) return fail(RBQ_EINVAL, "P has non-finite entries");
+  // orthogonality, checked on a few seeded vectors: ||P (P^T x) - x|| <= 1e-6 ||x||
+  std::vector<double> x(dp), y(dp), z(dp);
+  for (int t = 0; t < 4; ++t) {
+    double nx = 0.0;
+    for (int i = 0; i < dp; ++i) {
+      x[i] = (double)(host_splitmix64(0x4F5254ull * 1000003ull + (uint64_t)t * dp + i) >> 11) * 0x1.0p-53 - 0.5;
+      nx += x[i] * x[i];
+    }
+    for (int j = 0; j < dp; ++j) {   // y = P^T x
+      double a = 0.0;
+      for (int i = 0; i < dp; ++i) a += p[(size_t)i * dp + j] * x[i];
+      y[j] = a;
+    }
+    double err = 0.0;
+    for (int i = 0; i < dp; ++i) {   // z = P y
+      double a = 0.0;
+      for (int j = 0; j < dp; ++j) a += p[(size_t)i * dp + j] * y[j];
+      err += (a - x[i]) * (a - x[i]);
+    }
+    if (!(err <= 1e-12 * nx)) return fail(RBQ_EINVAL, "P is not orthogonal (||P P^T x - x|| / ||x|| = %.3g)",
+                                          std::sqrt(err / nx));
+  }
+  return build_impl(idx, data, n, cent, asg, p, (hipStream_t)stream);
+}
+
 // ------------------------------------------------------------------ search
 namespace rbq {
 
@@ -519,7 +613,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.probe.ensure((size_t)np * 4));
   HIPCHK(w.probe_d.ensure((size_t)np * 4));
   HIPCHK(w.pairs.ensure((size_t)np * sizeof(PairRec)));
-  HIPCHK(w.planes.ensure((size_t)np * 4 * W * 8));
+  HIPCHK(w.planes.ensure((size_t)np * (idx->prm.bq <= 4 ? 4 : 8) * W * 8));
   if (mfma) {
     HIPCHK(w.qu8.ensure((size_t)np * dp));
     HIPCHK(w.mf_cnt.ensure((size_t)idx->nlist * 4));
@@ -544,6 +638,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.p0buf.ensure((size_t)nq * (boot_codes(k, chunk) - 1 + chunk) * sizeof(EstEnt)));
   HIPCHK(w.tau.ensure((size_t)nq * 4));
   HIPCHK(w.seedk.ensure((size_t)nq * k * sizeof(SeedEnt)));
+  HIPCHK(w.q_boot.ensure((size_t)nq * 4));
   HIPCHK(w.q_rerank.ensure((size_t)nq * 4));
   HIPCHK(w.q_cand.ensure((size_t)nq * 4));
   if (fin_w > 1) {
@@ -576,6 +671,9 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.ird = 1.0 / s.rd;
   s.W = idx->W;
   s.nlist = idx->nlist;
+  s.qmax = (1 << idx->prm.bq) - 1;
+  s.npl = idx->prm.bq <= 4 ? 4 : 8;
+  s.qoff = idx->prm.bq == 8 ? 128 : 0;
   s.eps0 = idx->prm.eps0;
   s.seed = idx->prm.seed;
   s.q = queries;
@@ -610,6 +708,7 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.p0buf = (EstEnt*)w.p0buf.p;
   s.tau = (float*)w.tau.p;
   s.seedk = (SeedEnt*)w.seedk.p;
+  s.q_boot = (int32_t*)w.q_boot.p;
   s.q_rerank = (int32_t*)w.q_rerank.p;
   s.q_cand = (int32_t*)w.q_cand.p;
   s.mf_cnt = (int32_t*)w.mf_cnt.p;
@@ -710,7 +809,7 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   HIPCHK(launch_plan(s, st));
   HIPCHK(launch_prep(s, true, st));
   const int64_t chunks = idx->max_chunks(o.nprobe, chunk);
-  const int bpc = scan_popcnt_blocks_per_cu(idx->W);
+  const int bpc = scan_popcnt_blocks_per_cu(idx->W, s.npl);
   // bootstrap chunks per query: whole chunks until >= boot codes, so at most boot of them
   const int grid0 = scan_grid(idx, nq, std::min<int64_t>(chunks, s.boot), bpc);
   const int grid = scan_grid(idx, nq, chunks, bpc);
@@ -790,8 +889,8 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
     rbq_status rs = ensure_workspace(idx, hint, stride, o.k, chunk, kernel == RBQ_SCAN_MFMA, key.fin_w);
     if (rs != RBQ_OK) return rs;
     if (learned) {
-      HIPCHK(idx->ws.feats.ensure((size_t)hint * kMlpIn * 4));
       HIPCHK(idx->ws.nprobe_q.ensure((size_t)hint * 4));
+      HIPCHK(idx->ws.q_fb.ensure((size_t)hint * 4));
       rs = mlp_reserve(idx, hint);
       if (rs != RBQ_OK) return rs;
     }
@@ -896,7 +995,7 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
                                  rbq_search_stats* stats, void* stream) {
   if (!idx || !opts) return fail(RBQ_EINVAL, "NULL argument");
   if (!idx->built) return fail(RBQ_ESTATE, "index not built");
-  const rbq_search_opts o = *opts;
+  rbq_search_opts o = *opts;
   if (o.k < 1 || o.k > kMaxK) return fail(RBQ_EINVAL, "k=%d outside [1, %d]", o.k, kMaxK);
   if (o.nprobe < 1 || o.nprobe > std::min(idx->nlist, kMaxNprobe))
     return fail(RBQ_EINVAL, "nprobe=%d outside [1, %d]", o.nprobe, std::min(idx->nlist, kMaxNprobe));
@@ -907,16 +1006,35 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
   if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (nq == 0) return RBQ_OK;
-  if (!is_device_ptr(queries) || !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
-    return fail(RBQ_EINVAL, "queries, out_ids and out_dists must be device pointers");
-  if (o.nprobe_per_query && !is_device_ptr(o.nprobe_per_query))
-    return fail(RBQ_EINVAL, "nprobe_per_query must be a device pointer");
+  if (!queries || !out_ids || !out_dists) return fail(RBQ_EINVAL, "queries, out_ids and out_dists are required");
   if (o.qid_base < 0 || o.qid_base + nq > (1ll << 24))
     return fail(RBQ_EINVAL, "query ids must stay below 2^24 (qid_base %lld, nq %lld)",
                 (long long)o.qid_base, (long long)nq);
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> lock(idx->mu);
   if (idx->done_event) HIPCHK(hipStreamWaitEvent(st, idx->done_event, 0));
+  // Host buffers are staged through device copies (the copies are part of the call).
+  int64_t* const user_ids = out_ids;
+  float* const user_d = out_dists;
+  const bool ids_host = !is_device_ptr(out_ids), d_host = !is_device_ptr(out_dists);
+  if (!is_device_ptr(queries)) {
+    HIPCHK(idx->h_stage_q.ensure((size_t)nq * idx->dim * 4));
+    HIPCHK(hipMemcpyAsync(idx->h_stage_q.p, queries, (size_t)nq * idx->dim * 4, hipMemcpyHostToDevice, st));
+    queries = (const float*)idx->h_stage_q.p;
+  }
+  if (o.nprobe_per_query && !is_device_ptr(o.nprobe_per_query)) {
+    HIPCHK(idx->h_stage_npq.ensure((size_t)nq * 4));
+    HIPCHK(hipMemcpyAsync(idx->h_stage_npq.p, o.nprobe_per_query, (size_t)nq * 4, hipMemcpyHostToDevice, st));
+    o.nprobe_per_query = (const int32_t*)idx->h_stage_npq.p;
+  }
+  if (ids_host) {
+    HIPCHK(idx->h_stage_ids.ensure((size_t)nq * o.k * 8));
+    out_ids = (int64_t*)idx->h_stage_ids.p;
+  }
+  if (d_host) {
+    HIPCHK(idx->h_stage_d.ensure((size_t)nq * o.k * 4));
+    out_dists = (float*)idx->h_stage_d.p;
+  }
   int kernel = o.scan_kernel;
   int chunk = idx->tuned_chunk > 0 ? idx->tuned_chunk : kDefaultChunk;
   chunk = std::min(chunk, kMaxP0 + 1 - o.k);   // bootstrap codes (k - 1 + chunk) fit the seed sort
@@ -933,8 +1051,9 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
   const bool graph = o.use_graph && !idx->prof.on && sub == nq;
   auto add_stats = [&](int64_t m, const int32_t* npq, int stride) -> rbq_status {
     HIPCHK(hipStreamSynchronize(st));
-    std::vector<int32_t> rr(m), cc(m);
+    std::vector<int32_t> rb(m), rr(m), cc(m);
     std::vector<int64_t> nc(m);
+    HIPCHK(hipMemcpy(rb.data(), idx->ws.q_boot.p, m * 4, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(rr.data(), idx->ws.q_rerank.p, m * 4, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(cc.data(), idx->ws.q_cand.p, m * 4, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(nc.data(), idx->ws.q_ncode.p, m * 8, hipMemcpyDeviceToHost));
@@ -942,7 +1061,8 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
     HIPCHK(hipMemcpy(probe.data(), idx->ws.probe.p, probe.size() * 4, hipMemcpyDeviceToHost));
     stats->queries += m;
     for (int64_t i = 0; i < m; ++i) {
-      stats->reranked += rr[i];
+      stats->reranked += rb[i] + rr[i];
+      stats->reranked_bootstrap += rb[i];
       stats->candidates += cc[i];
       stats->codes_scanned += nc[i];
     }
@@ -950,6 +1070,11 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
     if (npq) {
       pq.resize(m);
       HIPCHK(hipMemcpy(pq.data(), npq, m * 4, hipMemcpyDeviceToHost));
+    }
+    if (learned) {
+      std::vector<int32_t> fb(m);
+      HIPCHK(hipMemcpy(fb.data(), idx->ws.q_fb.p, m * 4, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < m; ++i) stats->nonfinite_fallbacks += fb[i];
     }
     for (int64_t i = 0; i < m; ++i) {
       const int P = npq ? std::min(std::max(pq[i], 1), stride) : stride;
@@ -979,8 +1104,11 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
     }
   }
   if (idx->prof.on) idx->prof.searches++;   // one per call, however many sub-batches it ran
+  if (ids_host) HIPCHK(hipMemcpyAsync(user_ids, out_ids, (size_t)nq * o.k * 8, hipMemcpyDeviceToHost, st));
+  if (d_host) HIPCHK(hipMemcpyAsync(user_d, out_dists, (size_t)nq * o.k * 4, hipMemcpyDeviceToHost, st));
   if (!idx->done_event) HIPCHK(hipEventCreateWithFlags(&idx->done_event, hipEventDisableTiming));
   HIPCHK(hipEventRecord(idx->done_event, st));
+  if (ids_host || d_host) HIPCHK(hipStreamSynchronize(st));
   return RBQ_OK;
 }
 
@@ -1255,6 +1383,7 @@ extern "C" rbq_status rbq_debug_quantize(rbq_index* idx, const float* queries, i
                          nullptr, nullptr);
   HIPCHK(launch_prep(s, false, st));
   HIPCHK(hipMemcpyAsync(qu, idx->ws.qu8.p, (size_t)nq * nprobe * idx->dp, hipMemcpyDeviceToDevice, st));
+  if (s.qoff) HIPCHK(launch_xor_u8(qu, (int64_t)nq * nprobe * idx->dp, (uint8_t)s.qoff, st));   // back to 0..255
   HIPCHK(launch_pairs_to_scal(s, scal, st));
   return RBQ_OK;
 }
@@ -1275,9 +1404,37 @@ extern "C" rbq_status rbq_debug_scan(rbq_index* idx, int32_t list, const uint8_t
   rbq_status rs = ensure_workspace(idx, 1, 1, 1, kDefaultChunk, true);
   if (rs != RBQ_OK) return rs;
   Workspace& w = idx->ws;
-  HIPCHK(launch_debug_pack(qu, idx->dp, idx->W, scal[0], scal[1], scal[2], (PairRec*)w.pairs.p,
-                           (uint64_t*)w.planes.p, (int8_t*)w.qu8.p, list, st));
   SearchDev s = make_dev(idx, nullptr, 1, 1, 1, kDefaultChunk, nullptr, 0, true, nullptr, nullptr);
+  HIPCHK(launch_debug_pack(qu, idx->dp, idx->W, s.npl, s.qoff, scal[0], scal[1], scal[2], (PairRec*)w.pairs.p,
+                           (uint64_t*)w.planes.p, (int8_t*)w.qu8.p, list, st));
+  if (kernel == RBQ_SCAN_POPCNT) {
+    // the list as main-phase work units of pair 0, for the production scan's export phase
+    const int64_t beg = idx->h_list_off[list], end = idx->h_list_off[list + 1];
+    std::vector<UnitDesc> units;
+    for (int64_t p0 = beg; p0 < end; p0 += s.chunk) {
+      UnitDesc u;
+      std::memset(&u, 0, sizeof(u));
+      u.start = p0;
+      u.g = 0;
+      u.count_slot = (int64_t)units.size();
+      u.len = (int32_t)std::min<int64_t>(s.chunk, end - p0);
+      units.push_back(u);
+    }
+    if (units.empty()) return RBQ_OK;
+    HIPCHK(w.units1.ensure(units.size() * sizeof(UnitDesc)));
+    HIPCHK(w.seg_count.ensure(units.size() * 4));
+    const int64_t off_p1[2] = {0, (int64_t)units.size()};
+    HIPCHK(hipMemcpyAsync(w.units1.p, units.data(), units.size() * sizeof(UnitDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(s.off_p1, off_p1, sizeof(off_p1), hipMemcpyHostToDevice, st));
+    s = make_dev(idx, nullptr, 1, 1, 1, kDefaultChunk, nullptr, 0, true, nullptr, nullptr);
+    s.dbg_base = beg;
+    s.dbg_ip = ip;
+    s.dbg_pc = pc;
+    s.dbg_est = est;
+    s.dbg_dist = dist;
+    s.dbg_lb = lb;
+    HIPCHK(hipStreamSynchronize(st));   // the host tables above are stack memory
+  }
   HIPCHK(launch_debug_scan(s, (const PairRec*)w.pairs.p, (const uint64_t*)w.planes.p,
                            (const int8_t*)w.qu8.p, list, kernel, ip, pc, est, dist, lb, st));
   return RBQ_OK;
@@ -1351,7 +1508,7 @@ extern "C" rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t
   if (nq < 1 || k < 1 || k > kMaxK || nprobe < 1 || nprobe > std::min(idx->nlist, kMaxNprobe))
     return fail(RBQ_EINVAL, "bad nq, k or nprobe");
   hipStream_t st = (hipStream_t)stream;
-  DBuf dq, di, dd;
+  TmpBuf dq, di, dd;
   HIPCHK(dq.ensure((size_t)nq * idx->dim * 4));
   HIPCHK(di.ensure((size_t)nq * k * 8));
   HIPCHK(dd.ensure((size_t)nq * k * 4));

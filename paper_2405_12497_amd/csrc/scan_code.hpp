@@ -11,20 +11,16 @@ namespace rbq {
 namespace {
 
 // ------------------------------------------------------------------ scan arithmetic (S4 + S6)
-// Integer <x_b, q_u> = sum_j 2^j popcount(x_b AND plane_j) and popcount(x_b).
-// Planes<WS>: the pair's 4 bit planes in registers (1 <= WS <= 4 words, W == WS).
-template <int WS>
+// Integer <x_b, q_u> = sum_j 2^j popcount(x_b AND plane_j) and popcount(x_b)
+// (Sec. 3.3.2), with NPL bit planes: 4 for B_q <= 4 (the planes j >= B_q are
+// zero), 8 for B_q = 5..8.
+// Planes<WS, NPL>: the pair's planes in registers (1 <= WS <= 4 words, W == WS).
+template <int WS, int NPL>
 struct Planes {
-  uint64_t w[4][WS];
-  __device__ __forceinline__ void load(const uint64_t* src) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int t = 0; t < WS; ++t) w[j][t] = src[j * WS + t];
-  }
+  uint64_t w[NPL][WS];
   __device__ __forceinline__ uint64_t get(int j, int t) const { return w[j][t]; }
 };
-// PlanesLds<WS>: the planes in LDS ([4][W]), W == WS > 4 known at compile
+// PlanesLds<WS>: the planes in LDS ([NPL][W]), W == WS > 4 known at compile
 // time, or runtime W when WS == 0.
 template <int WS>
 struct PlanesLds {
@@ -32,8 +28,8 @@ struct PlanesLds {
   int Wr;
   __device__ __forceinline__ uint64_t get(int j, int t) const { return p[j * (WS > 0 ? WS : Wr) + t]; }
 };
-template <int WS>
-using PlanesFor = typename std::conditional<(WS >= 1 && WS <= 4), Planes<WS>, PlanesLds<WS>>::type;
+template <int WS, int NPL>
+using PlanesFor = typename std::conditional<(WS >= 1 && WS <= 4), Planes<WS, NPL>, PlanesLds<WS>>::type;
 
 // Word 0 of the code at list-order position p; word t is row[64 * t]
 // (interleaved layout: word w of 64 consecutive codes is one 512-byte row).
@@ -42,21 +38,25 @@ __device__ __forceinline__ const uint64_t* code_row(const uint64_t* __restrict__
   return codes + ((uint32_t)(p >> 6) * (uint32_t)(W * 64) + (uint32_t)(p & 63));
 }
 
-template <int WS, typename PL>
+template <int WS, int NPL, typename PL>
 __device__ __forceinline__ void code_ip(const uint64_t* __restrict__ row, int W, const PL& pl, int& ip,
                                         int& pc) {
   const int Wn = WS > 0 ? WS : W;
-  int s0 = 0, s1 = 0, s2 = 0, s3 = 0, c = 0;
+  int sj[NPL];
+#pragma unroll
+  for (int j = 0; j < NPL; ++j) sj[j] = 0;
+  int c = 0;
 #pragma unroll
   for (int t = 0; t < Wn; ++t) {
     const uint64_t x = row[64 * t];
     c += __popcll(x);
-    s0 += __popcll(x & pl.get(0, t));
-    s1 += __popcll(x & pl.get(1, t));
-    s2 += __popcll(x & pl.get(2, t));
-    s3 += __popcll(x & pl.get(3, t));
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) sj[j] += __popcll(x & pl.get(j, t));
   }
-  ip = s0 + 2 * s1 + 4 * s2 + 8 * s3;
+  int v = 0;
+#pragma unroll
+  for (int j = 0; j < NPL; ++j) v += sj[j] << j;
+  ip = v;
   pc = c;
 }
 

@@ -35,7 +35,8 @@ class RbqSearchOpts(C.Structure):
 
 class RbqSearchStats(C.Structure):
     _fields_ = [("queries", C.c_int64), ("pairs", C.c_int64), ("codes_scanned", C.c_int64),
-                ("reranked", C.c_int64), ("candidates", C.c_int64)]
+                ("reranked", C.c_int64), ("candidates", C.c_int64),
+                ("reranked_bootstrap", C.c_int64), ("nonfinite_fallbacks", C.c_int64)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -74,8 +75,12 @@ _SIGS = {
     "rbq_params_default": (C.c_int, [C.POINTER(RbqParams), C.c_int32, C.c_int32]),
     "rbq_index_create": (C.c_int, [C.POINTER(RbqParams), C.POINTER(_P)]),
     "rbq_index_build": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P]),
+    "rbq_index_build_rotation": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P]),
     "rbq_search": (C.c_int, [_P, _P, C.c_int64, C.POINTER(RbqSearchOpts), _P, _P,
                              C.POINTER(RbqSearchStats), _P]),
+    "rbq_index_set_eps0": (C.c_int, [_P, C.c_float]),
+    "rbq_kmeans": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_uint64, _P, _P, _P,
+                             _P]),
     "rbq_index_info_get": (C.c_int, [_P, C.POINTER(RbqIndexInfo)]),
     "rbq_index_list_sizes": (C.c_int, [_P, _P]),
     "rbq_index_save": (C.c_int, [_P, C.c_char_p]),
@@ -90,6 +95,8 @@ _SIGS = {
     "rbq_nprobe_model_get": (C.c_int, [_P, _P, _P]),
     "rbq_nprobe_predict": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P]),
     "rbq_mlp_loss_grad": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P]),
+    "rbq_nprobe_bucket_table": (C.c_int, [_P]),
+    "rbq_nprobe_labels": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P, _P, _P]),
     "rbq_debug_export_codes": (C.c_int, [_P, _P, _P, _P]),
     "rbq_debug_rotate": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
     "rbq_debug_centroid_dists": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
@@ -175,20 +182,58 @@ def rbq_index_create(params: RbqParams):
     return h
 
 
+def _any(a, np_dtype):
+    """(keep-alive object, pointer) of a numpy array (host) or a contiguous GPU tensor."""
+    if hasattr(a, "is_cuda") and a.is_cuda:
+        import torch
+        want = {np.float32: torch.float32, np.int32: torch.int32, np.float64: torch.float64,
+                np.int64: torch.int64}[np_dtype]
+        return a, _dev(a, want)
+    return _host(a, np_dtype)
+
+
 def rbq_index_build(idx, data, centroids, assign, gauss=None, stream=None):
-    d, dp = _host(data, np.float32)
-    c, cp = _host(centroids, np.float32)
-    a, ap = _host(assign, np.int32)
+    """data, centroids, assign, gauss: numpy arrays (host) or GPU tensors, independently."""
+    d, dp = _any(data, np.float32)
+    c, cp = _any(centroids, np.float32)
+    a, ap = _any(assign, np.int32)
     gp = None
     if gauss is not None:
-        g, gp = _host(gauss, np.float64)
+        g, gp = _any(gauss, np.float64)
     _check(lib().rbq_index_build(idx, dp, d.shape[0], cp, ap, gp, _stream(stream)))
+
+
+def rbq_index_build_rotation(idx, data, centroids, assign, P, stream=None):
+    """As rbq_index_build with a caller-supplied orthogonal P [code_bits x code_bits] float64."""
+    d, dp = _any(data, np.float32)
+    c, cp = _any(centroids, np.float32)
+    a, ap = _any(assign, np.int32)
+    p, pp = _any(P, np.float64)
+    _check(lib().rbq_index_build_rotation(idx, dp, d.shape[0], cp, ap, pp, _stream(stream)))
 
 
 def rbq_search(idx, queries, k, nprobe, scan_kernel=RBQ_SCAN_AUTO, use_learned_nprobe=False,
                nprobe_per_query=None, qid_base=0, stats=False, out_ids=None, out_dists=None,
                stream=None, use_graph=False, rerank_waves=0):
-    """queries: float32 GPU tensor [nq, dim]. Returns (ids int64 [nq,k], dists float32 [nq,k], stats|None)."""
+    """queries: float32 GPU tensor [nq, dim] (outputs are GPU tensors), or a numpy
+    array (host pointers through the C ABI; outputs are numpy arrays).
+    Returns (ids int64 [nq,k], dists float32 [nq,k], stats|None)."""
+    if not hasattr(queries, "is_cuda"):
+        q, qp = _host(queries, np.float32)
+        nq = q.shape[0]
+        ids = np.empty((nq, k), np.int64)
+        ds = np.empty((nq, k), np.float32)
+        npq = None
+        if nprobe_per_query is not None:
+            npq, _ = _host(nprobe_per_query, np.int32)
+        o = RbqSearchOpts(k, nprobe, scan_kernel, int(bool(use_learned_nprobe)),
+                          None if npq is None else npq.ctypes.data, qid_base, int(bool(use_graph)),
+                          int(rerank_waves))
+        st = RbqSearchStats()
+        _check(lib().rbq_search(idx, qp, nq, C.byref(o), ids.ctypes.data_as(C.c_void_p),
+                                ds.ctypes.data_as(C.c_void_p), C.byref(st) if stats else None,
+                                _stream(stream)))
+        return ids, ds, (st.as_dict() if stats else None)
     import torch
     nq = queries.shape[0]
     if out_ids is None:
@@ -202,6 +247,31 @@ def rbq_search(idx, queries, k, nprobe, scan_kernel=RBQ_SCAN_AUTO, use_learned_n
                             _dev(out_ids, torch.int64), _dev(out_dists, torch.float32),
                             C.byref(st) if stats else None, _stream(stream)))
     return out_ids, out_dists, (st.as_dict() if stats else None)
+
+
+def rbq_kmeans(data, nlist, iters=10, sample=0, seed=0, init=None, stream=None):
+    """data: numpy [n, dim] or a GPU tensor. Returns (centroids, assign) as numpy
+    arrays for numpy data, GPU tensors for GPU data."""
+    n, dim = data.shape
+    d, dp = _any(data, np.float32)
+    ip = None
+    if init is not None:
+        i_, ip = _any(init, np.float32)
+    if hasattr(data, "is_cuda") and data.is_cuda:
+        import torch
+        cent = torch.empty((nlist, dim), dtype=torch.float32, device=data.device)
+        asg = torch.empty(n, dtype=torch.int32, device=data.device)
+        cp, ap = _dev(cent, torch.float32), _dev(asg, torch.int32)
+    else:
+        cent = np.empty((nlist, dim), np.float32)
+        asg = np.empty(n, np.int32)
+        cp, ap = cent.ctypes.data_as(C.c_void_p), asg.ctypes.data_as(C.c_void_p)
+    _check(lib().rbq_kmeans(dp, n, dim, nlist, iters, sample, seed, ip, cp, ap, _stream(stream)))
+    return cent, asg
+
+
+def rbq_index_set_eps0(idx, eps0):
+    _check(lib().rbq_index_set_eps0(idx, float(eps0)))
 
 
 def rbq_index_info_get(idx) -> dict:
@@ -304,6 +374,23 @@ def rbq_mlp_loss_grad(x, labels, weights, stream=None):
     return float(loss[0]), grads
 
 
+def rbq_nprobe_bucket_table():
+    out = np.zeros(MLP_OUT, dtype=np.int32)
+    _check(lib().rbq_nprobe_bucket_table(out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def rbq_nprobe_labels(idx, queries, nn_ids, stream=None):
+    """queries GPU float32 [nq, dim], nn_ids GPU int64 [nq, k] -> (labels int32 [nq], need int32 [nq])."""
+    import torch
+    nq, k = nn_ids.shape
+    labels = torch.empty(nq, dtype=torch.int32, device=queries.device)
+    need = torch.empty(nq, dtype=torch.int32, device=queries.device)
+    _check(lib().rbq_nprobe_labels(idx, _dev(queries, torch.float32), nq, _dev(nn_ids, torch.int64), k,
+                                   _dev(labels, torch.int32), _dev(need, torch.int32), _stream(stream)))
+    return labels, need
+
+
 def rbq_debug_export_codes(idx, n, words):
     codes = np.zeros((n, words), dtype=np.uint64)
     norm = np.zeros(n, dtype=np.float32)
@@ -386,12 +473,13 @@ class Index:
     """Owns an rbq_index handle."""
 
     def __init__(self, dim, nlist, code_bits=0, eps0=1.9, rot_precision=RBQ_ROT_FP32, seed=0,
-                 handle=None):
+                 handle=None, bq=4):
         if handle is not None:
             self.h = handle
         else:
             p = rbq_params_default(dim, nlist)
             p.code_bits = code_bits
+            p.bq = bq
             p.eps0 = eps0
             p.rot_precision = rot_precision
             p.seed = seed
@@ -405,6 +493,10 @@ class Index:
 
     def build(self, data, centroids, assign, gauss=None):
         rbq_index_build(self.h, data, centroids, assign, gauss)
+        return self
+
+    def build_rotation(self, data, centroids, assign, P):
+        rbq_index_build_rotation(self.h, data, centroids, assign, P)
         return self
 
     def search(self, queries, k, nprobe, **kw):

@@ -168,6 +168,14 @@ def embedding_like_gpu(n: int, nq: int, device, dim: int = 768, seed_data: int =
     return draw(seed_data, n), draw(seed_query, nq)
 
 
+def embedding_queries_gpu(nq: int, device, seed_query: int, dim: int = 768, seed_data: int = 1004,
+                          exponent: float = 1.0, chunk: int = 1 << 18):
+    """Queries from the distribution of `embedding_like_gpu(..., seed_data)` with
+    their own seed, without drawing the data again."""
+    return embedding_like_gpu(0, nq, device, dim=dim, seed_data=seed_data, seed_query=seed_query,
+                              exponent=exponent, chunk=chunk)[1]
+
+
 def kmeans_gpu(x, nlist: int, iters: int = 10, seed: int = 7, sample: int | None = None,
                chunk: int = 8192, init: np.ndarray | None = None):
     """Lloyd k-means of a float32 GPU tensor x [n, dim]: seeded init from a

@@ -84,6 +84,18 @@ def make_case(name: str) -> Case:
         cent, assign = synth.kmeans(data, 24, iters=4, seed=173)
         return Case(name, data, qs, cent, assign, synth.gaussian_matrix(256, 174), 10, 5,
                     R.RBQ_ROT_BF16X3, 4108)
+    if name == "ivf512":
+        # W = 8 words per code: the two-pairs-per-wave quantisation and the runtime-width scan
+        data, qs = synth.mixture_flat(4000, 10, dim=512, seed_data=181, seed_query=182)
+        cent, assign = synth.kmeans(data, 16, iters=4, seed=183)
+        return Case(name, data, qs, cent, assign, synth.gaussian_matrix(512, 184), 10, 4,
+                    R.RBQ_ROT_BF16X3, 4109)
+    if name == "cb2048":
+        # code length 2048 for D = 160 (W = 32, padded far beyond D; planes in LDS)
+        data, qs = synth.mixture_flat(2500, 8, dim=160, seed_data=191, seed_query=192)
+        cent, assign = synth.kmeans(data, 8, iters=4, seed=193)
+        return Case(name, data, qs, cent, assign, synth.gaussian_matrix(2048, 194), 10, 3,
+                    R.RBQ_ROT_FP32, 4110, code_bits=2048)
     raise KeyError(name)
 
 

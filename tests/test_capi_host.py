@@ -42,7 +42,7 @@ def test_params_default_and_validation():
 
 @pytest.mark.parametrize("field,value,status", [
     ("dim", 0, R.RBQ_EINVAL), ("dim", 5000, R.RBQ_EINVAL), ("code_bits", 100, R.RBQ_EINVAL),
-    ("code_bits", 64, R.RBQ_EINVAL), ("nlist", 0, R.RBQ_EINVAL), ("bq", 3, R.RBQ_EUNSUPPORTED),
+    ("code_bits", 64, R.RBQ_EINVAL), ("nlist", 0, R.RBQ_EINVAL), ("bq", 0, R.RBQ_EINVAL), ("bq", 9, R.RBQ_EINVAL),
     ("eps0", -1.0, R.RBQ_EINVAL), ("rot_precision", 7, R.RBQ_EINVAL)])
 def test_create_rejects_bad_params(field, value, status):
     p = R.rbq_params_default(128, 16)

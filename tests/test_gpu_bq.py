@@ -1,0 +1,268 @@
+"""B_q as a parameter (Sec. 3.3.1: q_u in 0..2^B_q - 1, Delta = (v_r - v_l) /
+(2^B_q - 1)) against the FP64 oracle at B_q = 1..8, and the paper's
+verification studies on synthetic data (Sec. 5.2.4 recall against eps0 with
+every distance estimated, Sec. 5.2.5 average relative error against B_q,
+Sec. 5.2.6 unbiasedness by linear regression of estimated on true squared
+distances)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rabitq_oracle as O
+import synth
+
+from gpu_common import near_integer, oracle_estimates_on, rel_ok, sqdist64, tie_equivalent, unpack_codes
+
+pytestmark = pytest.mark.gpu
+_IDX = {}
+
+
+def _say(msg):
+    print(f"[{msg}]", flush=True)
+    sys.stdout.flush()
+
+
+def _data():
+    if "data" not in _IDX:
+        data, qs = synth.sift_like(12000, 16, seed_data=211, seed_query=212)
+        cent, assign = synth.kmeans(data, 24, iters=4, seed=213)
+        gauss = synth.gaussian_matrix(128, 214)
+        _IDX["data"] = (data, qs, cent, assign, gauss, O.build_index(data, cent, assign, gauss))
+    return _IDX["data"]
+
+
+def _index(bq, rot=None):
+    from paper_2405_12497_amd import rabitq as R
+    key = ("idx", bq)
+    if key not in _IDX:
+        data, qs, cent, assign, gauss, _ = _data()
+        idx = R.Index(128, len(cent), seed=4200 + bq, bq=bq)
+        idx.build(data, cent, assign, gauss)
+        _IDX[key] = idx
+    return _IDX[key]
+
+
+@pytest.mark.parametrize("bq", [1, 2, 3, 5, 7, 8])
+def test_quantized_query_matches_oracle_at_bq(bq):
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    _say(f"quantisation B_q={bq}")
+    data, qs, cent, assign, gauss, oidx = _data()
+    idx = _index(bq)
+    q = torch.from_numpy(qs).cuda()
+    nprobe = 6
+    lists, _ = R.rbq_debug_probe(idx.h, q, nprobe)
+    lists = lists.cpu().numpy()
+    qu, scal = R.rbq_debug_quantize(idx.h, q, torch.from_numpy(lists).cuda(), 128, qid_base=0)
+    qu = qu.cpu().numpy().reshape(len(qs), nprobe, 128).astype(np.int64)
+    scal = scal.cpu().numpy().reshape(len(qs), nprobe, 4)
+    top = (1 << bq) - 1
+    flips = 0
+    for qi in range(len(qs)):
+        for r in range(nprobe):
+            lid = int(lists[qi, r])
+            u = O.rounding_uniforms_fast(4200 + bq, qi, lid, 128)
+            oq = O.quantize_query(qs[qi], cent[lid], oidx.p, u, bq)
+            assert qu[qi, r].max() <= top
+            assert scal[qi, r, 2] == pytest.approx(oq.delta, rel=1e-4)
+            x = (oq.qprime - oq.vl) / oq.delta + u
+            tol = 1e-4 * top
+            d = qu[qi, r] != oq.qu
+            assert np.all(near_integer(x[d], tol)), f"query {qi} list {lid}: {d.sum()} differ"
+            assert np.all(np.abs(qu[qi, r] - oq.qu) <= 1)
+            flips += int(d.sum())
+    print(f"B_q={bq}: {flips} quantised coordinates differ from FP64")
+
+
+@pytest.mark.parametrize("kernel", ["popcnt", "mfma"])
+@pytest.mark.parametrize("bq", [1, 3, 5, 8])
+def test_scan_bitexact_at_bq(bq, kernel):
+    """Integer <x_b, q_u> over B_q bit planes (popcount) or int8 (MFMA, with
+    q_u - 128 for B_q = 8) equals the oracle's naive sum bit for bit."""
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    _say(f"scan B_q={bq} {kernel}")
+    kern = R.RBQ_SCAN_POPCNT if kernel == "popcnt" else R.RBQ_SCAN_MFMA
+    data, qs, cent, assign, gauss, oidx = _data()
+    idx = _index(bq)
+    codes, norm, ipo = R.rbq_debug_export_codes(idx.h, len(data), 2)
+    bits = unpack_codes(codes, 128)
+    sizes = idx.list_sizes()
+    for lid in np.argsort(-sizes)[:3]:
+        n = int(sizes[lid])
+        ids = R.rbq_debug_list_ids(idx.h, int(lid), n)
+        u = O.rounding_uniforms_fast(4200 + bq, 3, int(lid), 128)
+        oq = O.quantize_query(qs[3], cent[lid], oidx.p, u, bq)
+        qb, vl, dl = np.float32(oq.b), np.float32(oq.vl), np.float32(oq.delta)
+        ip, pc, est, dist, lb = R.rbq_debug_scan(idx.h, int(lid), torch.from_numpy(oq.qu.astype(np.uint8)).cuda(),
+                                                 qb, vl, dl, n, kernel=kern)
+        oip, opc, oest, odist, olb = oracle_estimates_on(bits[ids], norm[ids], ipo[ids], oq.qu, float(qb),
+                                                         float(vl), float(dl), 128)
+        np.testing.assert_array_equal(ip.cpu().numpy(), oip)
+        np.testing.assert_array_equal(pc.cpu().numpy(), opc)
+        np.testing.assert_array_equal(O.ip_bitplanes(bits[ids], oq.qu, bq), oip)
+        est = est.cpu().numpy()
+        assert np.all(rel_ok(est, oest, np.maximum(1.0, np.abs(oest)), 1e-5))
+        scale = norm[ids].astype(np.float64) ** 2 + float(qb) ** 2
+        assert np.all(rel_ok(dist.cpu().numpy(), odist, np.maximum(np.abs(odist), scale), 1e-5))
+
+
+@pytest.mark.parametrize("bq", [1, 2, 6, 8])
+def test_search_topk_at_bq(bq):
+    """Exact top-k of the probed lists at every B_q, except where a true
+    neighbour's bound failed (checked on the GPU path's own quantised query)."""
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    _say(f"search B_q={bq}")
+    data, qs, cent, assign, gauss, oidx = _data()
+    idx = _index(bq)
+    codes, norm, ipo = R.rbq_debug_export_codes(idx.h, len(data), 2)
+    bits = unpack_codes(codes, 128)
+    q = torch.from_numpy(qs).cuda()
+    nprobe = 6
+    for kern in (R.RBQ_SCAN_POPCNT, R.RBQ_SCAN_MFMA):
+        ids, _, _ = idx.search(q, 10, nprobe, scan_kernel=kern)
+        ids = ids.cpu().numpy()
+        lists, _ = R.rbq_debug_probe(idx.h, q, nprobe)
+        lists = lists.cpu().numpy()
+        bad = 0
+        for qi in range(len(qs)):
+            cand = np.flatnonzero(np.isin(assign, lists[qi]))
+            t_ids, t_d = O.exact_topk(data, qs[qi], 10, cand)
+            if tie_equivalent(ids[qi], t_ids, qs[qi], data):
+                continue
+            qu, scal = R.rbq_debug_quantize(idx.h, q[qi:qi + 1].contiguous(),
+                                            torch.from_numpy(lists[qi:qi + 1]).cuda(), 128, qid_base=qi)
+            qu, scal = qu.cpu().numpy().astype(np.int64), scal.cpu().numpy()
+            fail = False
+            for oid, dv in zip(t_ids, t_d):
+                r = int(np.flatnonzero(lists[qi] == assign[oid])[0])
+                lbv = oracle_estimates_on(bits[oid:oid + 1], norm[oid:oid + 1], ipo[oid:oid + 1], qu[r],
+                                          scal[r, 0], scal[r, 1], scal[r, 2], 128)[4][0]
+                fail |= lbv > dv * (1 + 1e-6)
+            assert fail, f"B_q={bq} query {qi}: differs without a bound failure"
+            bad += 1
+        print(f"B_q={bq} kernel {kern}: {bad} of {len(qs)} queries differ (bound failures)")
+
+
+def _flat_gist(n=20000, nq=10):
+    if "gist" not in _IDX:
+        data, qs, _ = synth.gist_like(n, nq, dim=960, ncomp=64, seed_data=221, seed_query=222)
+        _IDX["gist"] = (data, qs, synth.gaussian_matrix(960, 223))
+    return _IDX["gist"]
+
+
+def _all_estimates(idx, qs, n, dp):
+    """GPU estimated squared distances of every vector to every query (one
+    flat list), from the search's own quantisation and scan routines."""
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    q = torch.from_numpy(qs).cuda()
+    lists = torch.zeros((len(qs), 1), dtype=torch.int32, device="cuda")
+    qu, scal = R.rbq_debug_quantize(idx.h, q, lists, dp, qid_base=0)
+    ids = R.rbq_debug_list_ids(idx.h, 0, n)
+    est = np.empty((len(qs), n))
+    for qi in range(len(qs)):
+        s = scal[qi].cpu().numpy()
+        _, _, _, d, _ = R.rbq_debug_scan(idx.h, 0, qu[qi].contiguous(), s[0], s[1], s[2], n)
+        est[qi, ids] = d.cpu().numpy()
+    return est
+
+
+def test_relative_error_against_bq():
+    """Sec. 5.2.5: the average relative error of the estimated squared
+    distances falls with B_q and has converged by B_q = 4; B_q = 1 is far worse.
+    The GPU's error equals the oracle's (same codes, same u) to 2%."""
+    from paper_2405_12497_amd import rabitq as R
+    _say("error vs B_q")
+    data, qs, gauss = _flat_gist()
+    n = len(data)
+    cent = data.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    assign = np.zeros(n, np.int32)
+    true = np.stack([O.exact_sqdist(data, q) for q in qs])
+    oidx = O.OracleIndex(data, cent, assign, O.orthogonal_from_gaussian(gauss))
+    errs, oerrs = [], []
+    for bq in range(1, 9):
+        idx = R.Index(960, 1, seed=4300, bq=bq, rot_precision=R.RBQ_ROT_BF16X3)
+        idx.build(data, cent, assign, gauss)
+        est = _all_estimates(idx, qs, n, 960)
+        errs.append(float(np.mean(np.abs(est - true) / true)))
+        oe = []
+        for qi in range(3):
+            u = O.rounding_uniforms_fast(4300, qi, 0, 960)
+            oq = O.quantize_query(qs[qi], cent[0], oidx.p, u, bq)
+            pe = O.pair_estimates(oidx, 0, oq)
+            oe.append(np.abs(pe["dist"] - true[qi][pe["ids"]]) / true[qi][pe["ids"]])
+        oerrs.append(float(np.mean(oe)))
+        gpu3 = float(np.mean(np.abs(est[:3] - true[:3]) / true[:3]))
+        print(f"B_q={bq}: average relative error {errs[-1]:.5f} (GPU, 10 queries), first 3 queries GPU "
+              f"{gpu3:.5f} oracle {oerrs[-1]:.5f}")
+        assert gpu3 == pytest.approx(oerrs[-1], rel=0.02)
+        idx.close()
+    assert errs[0] > 1.5 * errs[3]
+    assert all(errs[i + 1] < errs[i] for i in range(3))
+    assert abs(errs[7] - errs[3]) <= 0.1 * errs[3]
+
+
+def test_unbiasedness_regression():
+    """Sec. 5.2.6: linear regression of estimated on true squared distances
+    (both divided by the largest true one) over every (query, vector) pair has
+    slope 1 and intercept 0 for an unbiased estimator (Theorem 3.2)."""
+    from paper_2405_12497_amd import rabitq as R
+    _say("unbiasedness")
+    data, qs, gauss = _flat_gist()
+    n = len(data)
+    cent = data.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    idx = R.Index(960, 1, seed=4301, rot_precision=R.RBQ_ROT_BF16X3)
+    idx.build(data, cent, np.zeros(n, np.int32), gauss)
+    est = _all_estimates(idx, qs, n, 960).ravel()
+    true = np.stack([O.exact_sqdist(data, q) for q in qs]).ravel()
+    m = true.max()
+    slope, icpt = np.polyfit(true / m, est / m, 1)
+    print(f"regression over {len(true)} pairs: slope {slope:.4f}, intercept {icpt:.5f}")
+    assert abs(slope - 1.0) < 0.02
+    assert abs(icpt) < 0.01
+    idx.close()
+
+
+def test_recall_against_eps0():
+    """Sec. 5.2.4: every distance estimated (one flat list), candidates reranked
+    by the Sec. 4 rule; recall@10 rises with eps0 and is near perfect from
+    eps0 = 1.9. The GPU's parallel rerank and the oracle's sequential one give
+    recalls within 0.03 of each other."""
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    _say("recall vs eps0")
+    wl = synth.workload(1)
+    q = torch.from_numpy(wl.queries).cuda()
+    idx = R.Index(128, 1, seed=wl.seed)
+    idx.build(wl.data, wl.centroids, wl.assign, wl.gauss)
+    oidx = O.build_index(wl.data, wl.centroids, wl.assign, wl.gauss)
+    gt = [O.exact_topk(wl.data, x, 10) for x in wl.queries]
+    nq_o = 30
+    prev = 0.0
+    curve = {}
+    for eps in (0.0, 0.5, 1.0, 1.5, 1.9, 2.5, 3.0, 4.0):
+        R.rbq_index_set_eps0(idx.h, eps)
+        ids, _, st = idx.search(q, 10, 1, stats=True)
+        ids = ids.cpu().numpy()
+        hits = sum(np.sum(sqdist64(wl.data[ids[i][ids[i] >= 0]], wl.queries[i]) <= gt[i][1][-1] * (1 + 1e-6))
+                   for i in range(len(ids)))
+        rc = hits / (10 * len(ids))
+        ohits = 0
+        for i in range(nq_o):
+            oi, od, _ = O.search(oidx, wl.queries[i], i, 10, 1, wl.seed, eps0=eps)
+            ohits += int(np.sum(od <= gt[i][1][-1] * (1 + 1e-6)))
+        orc = ohits / (10 * nq_o)
+        grc = sum(np.sum(sqdist64(wl.data[ids[i][ids[i] >= 0]], wl.queries[i]) <= gt[i][1][-1] * (1 + 1e-6))
+                  for i in range(nq_o)) / (10 * nq_o)
+        curve[eps] = (rc, orc, st["reranked"] / len(ids))
+        print(f"eps0={eps}: GPU recall@10 {rc:.4f} (first {nq_o}: {grc:.4f}), oracle {orc:.4f}, "
+              f"reranked per query {st['reranked'] / len(ids):.0f}")
+        assert rc >= prev - 0.003
+        assert abs(grc - orc) <= 0.03
+        prev = rc
+    assert curve[1.9][0] >= 0.99
+    assert curve[0.0][0] < curve[1.9][0]
+    idx.close()

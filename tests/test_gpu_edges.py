@@ -115,12 +115,11 @@ def test_argument_errors():
         with pytest.raises(R.RbqError) as e:
             idx.search(q, k, nprobe)
         assert e.value.status == R.RBQ_EINVAL
-    # host pointer where a device pointer is required
+    # NULL buffers are rejected
     o = R.RbqSearchOpts(5, 1, 0, 0, None, 0, 0, 0)
     out_i = torch.empty((2, 5), dtype=torch.int64, device=_dev())
     out_d = torch.empty((2, 5), dtype=torch.float32, device=_dev())
-    host_q = np.ascontiguousarray(data[:2])
-    st = R.lib().rbq_search(idx.h, host_q.ctypes.data_as(C.c_void_p), 2, C.byref(o),
+    st = R.lib().rbq_search(idx.h, None, 2, C.byref(o),
                             C.c_void_p(out_i.data_ptr()), C.c_void_p(out_d.data_ptr()), None, None)
     assert st == R.RBQ_EINVAL
     # build rejects out-of-range assignments and leaves nothing half-built

@@ -24,7 +24,8 @@ from gpu_common import (Built, make_case, near_integer, oracle_estimates_on, rel
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["flat128", "ivf128", "pad100", "ivf960z", "ivf768", "many2500", "ivf192", "ivf256"]
+CASES = ["flat128", "ivf128", "pad100", "ivf960z", "ivf768", "many2500", "ivf192", "ivf256", "ivf512",
+         "cb2048"]
 _BUILT = {}
 
 
