@@ -467,7 +467,7 @@ def time_batches(idx, batches, k, nprobe, steps, warmup, **kw):
     dt = time.perf_counter() - t
     prof = R.rbq_profile_read(idx.h)
     R.rbq_profile_enable(idx.h, False)
-    return dt / steps, nq, prof
+    return dt / steps, nq, prof, torch.cat([o[0] for o in outs])
 
 
 def stage_times(idx, batch, k, nprobe, **kw):
@@ -687,13 +687,19 @@ def bench_learned(args):
     log(f"calibrated in {calib_s:.1f}s: learned threshold {thr:.5f} (test recall {rc_l:.4f}, mean nprobe "
         f"{st_l['pairs'] / nte:.1f}), fixed nprobe {fixed} (test recall {rc_f:.4f})")
     batches = [q_test[s0:s0 + batch].contiguous() for s0 in range(0, nte, batch)]
+    kern = {"popcnt": R.RBQ_SCAN_POPCNT, "mfma": R.RBQ_SCAN_MFMA, "auto": R.RBQ_SCAN_AUTO}[args.kernel]
     # timed: learned, then fixed
     R.rbq_nprobe_model_set(idx.h, w, thr)
-    t_l, nq_l, prof_l = time_batches(idx, batches, k, cap, args.steps, args.warmup, use_learned_nprobe=True)
-    stages_l = stage_times(idx, batches[0], k, cap, use_learned_nprobe=True)
+    t_l, nq_l, prof_l, out_l = time_batches(idx, batches, k, cap, args.steps, args.warmup, use_learned_nprobe=True,
+                                            scan_kernel=kern)
+    stages_l = stage_times(idx, batches[0], k, cap, use_learned_nprobe=True, scan_kernel=kern)
     R.rbq_nprobe_model_set(idx.h, None, 0.9)
-    t_f, nq_f, prof_f = time_batches(idx, batches, k, fixed, args.steps, args.warmup)
-    stages_f = stage_times(idx, batches[0], k, fixed)
+    t_f, nq_f, prof_f, out_f = time_batches(idx, batches, k, fixed, args.steps, args.warmup, scan_kernel=kern)
+    stages_f = stage_times(idx, batches[0], k, fixed, scan_kernel=kern)
+    # recall of the timed searches' own outputs (every test batch was searched at least once when steps >= 10)
+    if args.steps >= len(batches):
+        rc_l = rec(out_l, gte_d, q_test)
+        rc_f = rec(out_f, gte_d, q_test)
     qps_l, qps_f = batch / t_l, batch / t_f
     log(f"learned {qps_l:.0f} QPS ({t_l * 1e3:.3f} ms per batch of {batch}), fixed {qps_f:.0f} QPS "
         f"({t_f * 1e3:.3f} ms); speedup {t_f / t_l:.3f}")

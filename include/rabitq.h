@@ -232,11 +232,33 @@ rbq_status rbq_index_destroy(rbq_index* idx);
 
 const char* rbq_last_error(void);
 
-/* Preferred scan kernel and chunk length chosen by timing both kernels on a
- * query sample (host queries, nq x dim). The choice is stored in the index and
- * used by RBQ_SCAN_AUTO for batches near that size. */
+/* Autotuner of the search's launch shapes (batching of Algorithm 2's scans).
+ * For batch-size buckets of 1, 8, 64, ... queries up to the sample (and the
+ * sample itself), it times whole searches of the first rows of `queries` (host
+ * or device, nq x dim, nq <= 2^24) at (k, nprobe): every chunk length (codes
+ * per work unit of the persistent scans: 256, 512, 1024, 2048) with every scan
+ * kernel (popcount, MFMA), then, for batches that split a query's rerank over
+ * several waves, rerank waves 1..64 at the best pair. A search with
+ * scan_kernel = RBQ_SCAN_AUTO and rerank_waves = 0 then uses the choices of
+ * the bucket its batch size falls in (up to the geometric middle between two
+ * tuned sizes); the chunk length applies to every later search. Results stay
+ * the exact top-k of the probed lists whenever the bounds hold. Errors as
+ * rbq_search; RBQ_ESTATE while profiling is enabled. Synchronises. */
 rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t nq, int32_t k,
                         int32_t nprobe, void* stream);
+
+typedef struct {
+  int64_t max_nq;        /* batches of at most this many queries use this entry */
+  int32_t chunk;         /* codes per work unit */
+  int32_t scan_kernel;   /* RBQ_SCAN_POPCNT or RBQ_SCAN_MFMA */
+  int32_t rerank_waves;  /* 0: chosen from the batch size */
+  float ms;              /* the trial search's time at the bucket's size */
+} rbq_tune_entry;
+
+/* The autotuner's table: up to max_entries entries (host) and *count, the
+ * table's length (0 before rbq_autotune). */
+rbq_status rbq_autotune_get(const rbq_index* idx, int32_t max_entries, rbq_tune_entry* entries,
+                            int32_t* count);
 
 /* Kernel timing. When enabled, rbq_search records HIP events on its stream
  * and accumulates, on the device, the number of codes each scan phase

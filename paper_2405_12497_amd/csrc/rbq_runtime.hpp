@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -55,6 +56,17 @@ hipError_t launch_finalize_split(const SearchDev& s, int W, uint64_t* part, int3
 // Bytes of candidate segments a (sub-)batch may use (see rbq_debug_seg_budget).
 int64_t seg_budget();
 void g_seg_budget_set(int64_t b);
+
+// Per batch-size bucket choices of the autotuner: batches of at most max_nq
+// queries use this chunk length (codes per work unit), scan kernel and rerank
+// waves per query (0: chosen from the batch size).
+struct TuneEntry {
+  int64_t max_nq = INT64_MAX;
+  int chunk = kDefaultChunk;
+  int kernel = RBQ_SCAN_POPCNT;
+  int fin_w = 0;
+  float ms = 0.f;   // measured time of the trial batch
+};
 
 // One captured search (graph replay of rbq_search with use_graph = 1).
 struct GraphEntry {
@@ -137,11 +149,9 @@ struct rbq_index {
   rbq::MlpState mlp;
   rbq::ProfState prof;
 
-  // autotuned choices
-  int tuned_chunk = 0;
-  int tuned_kernel_small = RBQ_SCAN_POPCNT;   // for batches below tuned_batch_split
-  int tuned_kernel_large = RBQ_SCAN_POPCNT;
-  int64_t tuned_batch_split = 0;
+  // autotuned choices per batch-size bucket (empty: defaults)
+  std::vector<rbq::TuneEntry> tune;
+  rbq::TuneEntry tuned_for(int64_t nq) const;
 
   ~rbq_index();
   std::vector<rbq::DBuf*> all_buffers();
@@ -157,11 +167,6 @@ struct rbq_index {
   rbq::DBuf g_q, g_ids, g_d, g_npq;
   rbq::DBuf h_stage_q, h_stage_npq, h_stage_ids, h_stage_d;   // device copies of host search arguments
   void graphs_clear();
-  int pick_kernel(int64_t nq, int nprobe) const {
-    (void)nprobe;
-    if (!rbq::mfma_available()) return RBQ_SCAN_POPCNT;
-    return nq >= tuned_batch_split && tuned_batch_split > 0 ? tuned_kernel_large : tuned_kernel_small;
-  }
 };
 
 namespace rbq {
@@ -182,6 +187,8 @@ rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
 // One search on `st`. `learned`: per-query nprobe from the model (the caller
 // checked that one is set). Reports the per-query nprobe array in effect
 // (NULL: all use the fixed value) and the probe stride.
+rbq_status search_locked(rbq_index* idx, const float* queries, int64_t nq, rbq_search_opts o, int64_t* out_ids,
+                         float* out_dists, rbq_search_stats* stats, hipStream_t st, const TuneEntry* force);
 rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& opts,
                       int scan_kernel, int chunk, bool learned, int64_t* out_ids, float* out_d,
                       hipStream_t st, const int32_t** used_npq, int* used_stride);

@@ -1012,6 +1012,15 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
                 (long long)o.qid_base, (long long)nq);
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> lock(idx->mu);
+  return rbq::search_locked(idx, queries, nq, o, out_ids, out_dists, stats, st, nullptr);
+}
+
+// The body of rbq_search for validated arguments, with idx->mu held. `force`
+// (the autotuner's trials) fixes the chunk length, scan kernel and rerank
+// waves instead of the tuned or default choice.
+rbq_status rbq::search_locked(rbq_index* idx, const float* queries, int64_t nq, rbq_search_opts o,
+                              int64_t* out_ids, float* out_dists, rbq_search_stats* stats, hipStream_t st,
+                              const TuneEntry* force) {
   if (idx->done_event) HIPCHK(hipStreamWaitEvent(st, idx->done_event, 0));
   // Host buffers are staged through device copies (the copies are part of the call).
   int64_t* const user_ids = out_ids;
@@ -1035,12 +1044,16 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
     HIPCHK(idx->h_stage_d.ensure((size_t)nq * o.k * 4));
     out_dists = (float*)idx->h_stage_d.p;
   }
-  int kernel = o.scan_kernel;
-  int chunk = idx->tuned_chunk > 0 ? idx->tuned_chunk : kDefaultChunk;
-  chunk = std::min(chunk, kMaxP0 + 1 - o.k);   // bootstrap codes (k - 1 + chunk) fit the seed sort
-  if (kernel == RBQ_SCAN_AUTO) kernel = idx->pick_kernel(nq, o.nprobe);
-  if (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())
-    return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this build");
+  // chunk length, scan kernel and rerank waves: forced, tuned for this batch size, or the defaults
+  const TuneEntry tc = force ? *force : idx->tuned_for(nq);
+  int kernel = o.scan_kernel == RBQ_SCAN_AUTO ? tc.kernel : o.scan_kernel;
+  const int chunk = std::min(tc.chunk, kMaxP0 + 1 - o.k);   // bootstrap codes (k - 1 + chunk) fit the seed sort
+  if (o.rerank_waves == 0) o.rerank_waves = tc.fin_w;
+  if (kernel == RBQ_SCAN_AUTO || (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())) {
+    if (kernel == RBQ_SCAN_MFMA && o.scan_kernel == RBQ_SCAN_MFMA)
+      return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this build");
+    kernel = RBQ_SCAN_POPCNT;
+  }
   const bool learned = !o.nprobe_per_query && o.use_learned_nprobe && idx->mlp.has_model;
   // A query's candidate segment reserves a slot for each probed code, so a
   // batch is searched in sub-batches whose segments stay within kSegBudget
@@ -1500,75 +1513,132 @@ extern "C" rbq_status rbq_profile_read(rbq_index* idx, rbq_profile* out) {
 }
 
 // ------------------------------------------------------------------ autotuner
+namespace {
+struct EventHolder {
+  hipEvent_t e = nullptr;
+  ~EventHolder() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+}  // namespace
+
+rbq::TuneEntry rbq_index::tuned_for(int64_t nq) const {
+  rbq::TuneEntry d;
+  if (tune.empty()) return d;
+  for (const rbq::TuneEntry& t : tune)
+    if (nq <= t.max_nq) return t;
+  return tune.back();
+}
+
 extern "C" rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t nq, int32_t k,
                                    int32_t nprobe, void* stream) {
   if (!idx || !queries) return fail(RBQ_EINVAL, "NULL argument");
   if (!idx->built) return fail(RBQ_ESTATE, "index not built");
-  if (is_device_ptr(queries)) return fail(RBQ_EINVAL, "rbq_autotune takes host queries");
-  if (nq < 1 || k < 1 || k > kMaxK || nprobe < 1 || nprobe > std::min(idx->nlist, kMaxNprobe))
+  if (nq < 1 || nq > (1ll << 24) || k < 1 || k > kMaxK || nprobe < 1 || nprobe > std::min(idx->nlist, kMaxNprobe))
     return fail(RBQ_EINVAL, "bad nq, k or nprobe");
   hipStream_t st = (hipStream_t)stream;
   TmpBuf dq, di, dd;
-  HIPCHK(dq.ensure((size_t)nq * idx->dim * 4));
+  const float* q = queries;
+  if (!is_device_ptr(queries)) {
+    HIPCHK(dq.ensure((size_t)nq * idx->dim * 4));
+    HIPCHK(hipMemcpy(dq.p, queries, (size_t)nq * idx->dim * 4, hipMemcpyHostToDevice));
+    q = (const float*)dq.p;
+  }
   HIPCHK(di.ensure((size_t)nq * k * 8));
   HIPCHK(dd.ensure((size_t)nq * k * 4));
-  HIPCHK(hipMemcpy(dq.p, queries, (size_t)nq * idx->dim * 4, hipMemcpyHostToDevice));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  EventHolder e0, e1;
+  HIPCHK(hipEventCreate(&e0.e));
+  HIPCHK(hipEventCreate(&e1.e));
   rbq_search_opts o;
   std::memset(&o, 0, sizeof(o));
   o.k = k;
   o.nprobe = nprobe;
   std::lock_guard<std::mutex> lock(idx->mu);
-  if (idx->done_event) HIPCHK(hipStreamWaitEvent(st, idx->done_event, 0));
-  auto timed = [&](int64_t n, int kernel, int chunk, float* ms) -> rbq_status {
+  if (idx->prof.on) return fail(RBQ_ESTATE, "profiling is enabled");
+  // each trial is a whole rbq_search (validation done, sub-batches, the same
+  // kernels): the best of three timed runs after one warm-up
+  auto timed = [&](int64_t n, const TuneEntry& t, float* ms) -> rbq_status {
     float best = 1e30f;
     for (int rep = 0; rep < 4; ++rep) {
-      HIPCHK(hipEventRecord(e0, st));
-      const int32_t* npq = nullptr;
-      int stride = 0;
-      rbq_status rs = run_search(idx, (const float*)dq.p, n, o, kernel, chunk, false, (int64_t*)di.p,
-                                 (float*)dd.p, st, &npq, &stride);
+      HIPCHK(hipEventRecord(e0.e, st));
+      rbq_status rs = search_locked(idx, q, n, o, (int64_t*)di.p, (float*)dd.p, nullptr, st, &t);
       if (rs != RBQ_OK) return rs;
-      HIPCHK(hipEventRecord(e1, st));
-      HIPCHK(hipEventSynchronize(e1));
-      float t = 0.f;
-      HIPCHK(hipEventElapsedTime(&t, e0, e1));
-      if (rep > 0) best = std::min(best, t);   // the first run allocates and warms up
+      HIPCHK(hipEventRecord(e1.e, st));
+      HIPCHK(hipEventSynchronize(e1.e));
+      float v = 0.f;
+      HIPCHK(hipEventElapsedTime(&v, e0.e, e1.e));
+      if (rep > 0) best = std::min(best, v);
     }
     *ms = best;
     return RBQ_OK;
   };
+  // batch-size buckets: powers of 8 up to the sample, and the sample itself
+  std::vector<int64_t> sizes;
+  for (int64_t m = 1; m < nq; m *= 8) sizes.push_back(m);
+  sizes.push_back(nq);
+  std::vector<TuneEntry> table;
   const int chunks[] = {256, 512, 1024, 2048};
-  const int kernels[] = {RBQ_SCAN_POPCNT, RBQ_SCAN_MFMA};
-  float best = 1e30f;
-  int best_chunk = kDefaultChunk, best_kernel = RBQ_SCAN_POPCNT;
-  for (int c : chunks) {
-    if (c > kMaxP0 + 1 - k) continue;
-    for (int kern : kernels) {
-      float ms = 0.f;
-      rbq_status rs = timed(nq, kern, c, &ms);
-      if (rs != RBQ_OK) return rs;
-      if (ms < best) {
-        best = ms;
-        best_chunk = c;
-        best_kernel = kern;
+  std::vector<int> kernels = {RBQ_SCAN_POPCNT};
+  if (rbq::mfma_available()) kernels.push_back(RBQ_SCAN_MFMA);
+  for (int64_t m : sizes) {
+    TuneEntry best;
+    float best_ms = 1e30f;
+    for (int c : chunks) {
+      if (c > kMaxP0 + 1 - k) continue;
+      for (int kern : kernels) {
+        TuneEntry t;
+        t.chunk = c;
+        t.kernel = kern;
+        t.fin_w = 0;
+        float ms = 0.f;
+        rbq_status rs = timed(m, t, &ms);
+        if (rs != RBQ_OK) return rs;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
       }
     }
+    // rerank waves per query (only small batches split a query's rerank)
+    if (graph_rows(m) < 2048) {
+      for (int w : {1, 2, 4, 8, 16, 32, 64}) {
+        if (w > fin_waves(64, m, k)) break;
+        TuneEntry t = best;
+        t.fin_w = w;
+        float ms = 0.f;
+        rbq_status rs = timed(m, t, &ms);
+        if (rs != RBQ_OK) return rs;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+    }
+    best.max_nq = m;
+    best.ms = best_ms;
+    table.push_back(best);
   }
-  // kernel choice for small batches at the chosen chunk length
-  const int64_t small = std::max<int64_t>(1, nq / 16);
-  float tp = 0.f, tm = 0.f;
-  rbq_status rs = timed(small, RBQ_SCAN_POPCNT, best_chunk, &tp);
-  if (rs == RBQ_OK) rs = timed(small, RBQ_SCAN_MFMA, best_chunk, &tm);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (rs != RBQ_OK) return rs;
-  idx->tuned_chunk = best_chunk;
-  idx->tuned_kernel_large = best_kernel;
-  idx->tuned_kernel_small = tm < tp ? RBQ_SCAN_MFMA : RBQ_SCAN_POPCNT;
-  idx->tuned_batch_split = std::max<int64_t>(2, (nq + small) / 2);
+  // each entry serves the batch sizes up to the geometric middle between its size and the next
+  for (size_t i = 0; i + 1 < table.size(); ++i)
+    table[i].max_nq = (int64_t)std::sqrt((double)table[i].max_nq * (double)table[i + 1].max_nq);
+  table.back().max_nq = INT64_MAX;
+  idx->tune = table;
+  idx->graphs_clear();   // captured searches hold the old choices
   HIPCHK(hipStreamSynchronize(st));
+  return RBQ_OK;
+}
+
+extern "C" rbq_status rbq_autotune_get(const rbq_index* idx, int32_t max_entries, rbq_tune_entry* entries,
+                                       int32_t* count) {
+  if (!idx || !count || (max_entries > 0 && !entries)) return fail(RBQ_EINVAL, "NULL argument");
+  *count = (int32_t)idx->tune.size();
+  for (int32_t i = 0; i < std::min<int32_t>(max_entries, *count); ++i) {
+    const rbq::TuneEntry& t = idx->tune[i];
+    entries[i].max_nq = t.max_nq;
+    entries[i].chunk = t.chunk;
+    entries[i].scan_kernel = t.kernel;
+    entries[i].rerank_waves = t.fin_w;
+    entries[i].ms = t.ms;
+  }
   return RBQ_OK;
 }

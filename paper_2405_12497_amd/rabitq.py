@@ -87,6 +87,7 @@ _SIGS = {
     "rbq_index_load": (C.c_int, [C.c_char_p, C.POINTER(_P)]),
     "rbq_index_destroy": (C.c_int, [_P]),
     "rbq_autotune": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, _P]),
+    "rbq_autotune_get": (C.c_int, [_P, C.c_int32, _P, _P]),
     "rbq_profile_enable": (C.c_int, [_P, C.c_int32]),
     "rbq_profile_read": (C.c_int, [_P, C.POINTER(RbqProfile)]),
     "rbq_nprobe_features": (C.c_int, [_P, _P, C.c_int64, C.c_int64, _P, _P]),
@@ -300,9 +301,23 @@ def rbq_index_destroy(idx):
     _check(lib().rbq_index_destroy(idx))
 
 
+class RbqTuneEntry(C.Structure):
+    _fields_ = [("max_nq", C.c_int64), ("chunk", C.c_int32), ("scan_kernel", C.c_int32),
+                ("rerank_waves", C.c_int32), ("ms", C.c_float)]
+
+
 def rbq_autotune(idx, queries, k, nprobe, stream=None):
-    q, qp = _host(queries, np.float32)
+    """queries: numpy (host) or a GPU tensor [nq, dim]."""
+    q, qp = _any(queries, np.float32)
     _check(lib().rbq_autotune(idx, qp, q.shape[0], k, nprobe, _stream(stream)))
+
+
+def rbq_autotune_get(idx):
+    n = C.c_int32()
+    _check(lib().rbq_autotune_get(idx, 0, None, C.byref(n)))
+    arr = (RbqTuneEntry * max(1, n.value))()
+    _check(lib().rbq_autotune_get(idx, n.value, arr, C.byref(n)))
+    return [{f: getattr(arr[i], f) for f, _ in RbqTuneEntry._fields_} for i in range(n.value)]
 
 
 def rbq_profile_enable(idx, on=True):
