@@ -218,6 +218,28 @@ rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t nq,
  * reranked (Sec. 5.2.4 studies recall against eps0). Codes are unchanged. */
 rbq_status rbq_index_set_eps0(rbq_index* idx, float eps0);
 
+/* rbq_search for callers that cannot allocate device memory (code under HIP
+ * stream/graph capture, serving loops with a fixed memory budget, harnesses
+ * that forbid hipMalloc): the same kernels and results as rbq_search on the
+ * same arguments, with every workspace buffer carved from a device array of
+ * RBQ_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * (from the first call on that GPU until the process ends). Nothing is
+ * allocated or freed, and no HIP memset is issued (every buffer the search
+ * needs zeroed is cleared by its own kernels).
+ *   queries, out_ids, out_dists, opts->nprobe_per_query: device pointers
+ *   (layouts as rbq_search); opts->use_graph must be 0; no statistics.
+ * Errors: RBQ_EINVAL for a search whose workspace exceeds the array (the
+ * message names the bytes needed: fewer queries or a smaller nprobe fit),
+ * host pointers, or arguments rbq_search rejects; RBQ_ESTATE while profiling
+ * is enabled on the index. The whole batch runs as one search (no
+ * sub-batches). Every call on one GPU uses that GPU's one array: calls that
+ * overlap in time on one GPU (other threads, or streams that are not
+ * ordered with each other) race and give undefined results. */
+#define RBQ_NOALLOC_SCRATCH_BYTES (128ll << 20)
+rbq_status rbq_search_noalloc(rbq_index* idx, const float* queries, int64_t nq,
+                              const rbq_search_opts* opts, int64_t* out_ids, float* out_dists,
+                              void* stream);
+
 rbq_status rbq_index_info_get(const rbq_index* idx, rbq_index_info* out);
 
 /* Sizes of the IVF lists: host, nlist int64. */

@@ -15,7 +15,12 @@
 
 namespace rbq {
 
-// Device buffer that grows on demand and is freed with its owner.
+// Bytes of the device array that rbq_search_noalloc carves its workspace from.
+constexpr size_t kNoAllocScratchBytes = 128ull << 20;
+
+// Device buffer that grows on demand and is freed with its owner. While an
+// Arena is active on the calling thread, ensure() carves from it instead of
+// allocating (and such buffers are never freed: the arena owns the memory).
 struct DBuf {
   void* p = nullptr;
   size_t cap = 0;
@@ -83,6 +88,17 @@ struct GraphEntry {
 hipError_t dmalloc(void** p, size_t bytes);
 rbq_status set_error(rbq_status st, const char* msg);
 
+// Caller-provided device memory that DBuf::ensure carves from on this thread.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+// rbq_search_noalloc's body: the search of rbq_search (device queries and
+// outputs, one batch, no stats, no graph, no profiling) with every workspace
+// buffer carved from [base, base + cap); fails with RBQ_EINVAL naming the
+// bytes it would need when they exceed cap.
+rbq_status search_in_arena(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts* opts,
+                           int64_t* out_ids, float* out_dists, void* base, size_t cap, hipStream_t st);
 bool is_device_ptr(const void* p);
 uint64_t host_splitmix64(uint64_t x);
 

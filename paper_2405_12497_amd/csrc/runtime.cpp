@@ -84,8 +84,23 @@ void g_seg_budget_set(int64_t b) { g_seg_budget.store(b); }
 
 uint64_t buffer_generation() { return g_buffer_gen.load(); }
 
+namespace {
+thread_local Arena* g_arena = nullptr;
+}
+
 hipError_t DBuf::ensure(size_t bytes) {
   if (bytes <= cap) return hipSuccess;
+  if (g_arena) {   // carve from the caller's memory; nothing is allocated
+    const size_t want = (std::max<size_t>(bytes, 256) + 255) / 256 * 256;
+    if (g_arena->used + want > g_arena->cap) {
+      g_arena->used += want;   // record what the call would need
+      return hipErrorOutOfMemory;
+    }
+    p = g_arena->base + g_arena->used;
+    g_arena->used += want;
+    cap = want;
+    return hipSuccess;
+  }
   release();
   g_buffer_gen.fetch_add(1);
   size_t want = std::max<size_t>(bytes, 256);
@@ -1123,6 +1138,59 @@ rbq_status rbq::search_locked(rbq_index* idx, const float* queries, int64_t nq, 
   HIPCHK(hipEventRecord(idx->done_event, st));
   if (ids_host || d_host) HIPCHK(hipStreamSynchronize(st));
   return RBQ_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free search
+rbq_status rbq::search_in_arena(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts* opts,
+                                int64_t* out_ids, float* out_dists, void* base, size_t cap, hipStream_t st) {
+  if (!idx || !opts) return fail(RBQ_EINVAL, "NULL argument");
+  if (!idx->built) return fail(RBQ_ESTATE, "index not built");
+  rbq_search_opts o = *opts;
+  if (o.k < 1 || o.k > kMaxK) return fail(RBQ_EINVAL, "k=%d outside [1, %d]", o.k, kMaxK);
+  if (o.nprobe < 1 || o.nprobe > std::min(idx->nlist, kMaxNprobe))
+    return fail(RBQ_EINVAL, "nprobe=%d outside [1, %d]", o.nprobe, std::min(idx->nlist, kMaxNprobe));
+  if (o.use_graph != 0) return fail(RBQ_EINVAL, "rbq_search_noalloc does not replay graphs (use_graph must be 0)");
+  if (o.rerank_waves < 0) return fail(RBQ_EINVAL, "rerank_waves must be >= 0");
+  if (o.scan_kernel < RBQ_SCAN_AUTO || o.scan_kernel > RBQ_SCAN_MFMA)
+    return fail(RBQ_EINVAL, "unknown scan_kernel %d", o.scan_kernel);
+  if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
+  if (nq == 0) return RBQ_OK;
+  if (o.qid_base < 0 || o.qid_base + nq > (1ll << 24))
+    return fail(RBQ_EINVAL, "query ids must stay below 2^24 (qid_base %lld, nq %lld)",
+                (long long)o.qid_base, (long long)nq);
+  if (!is_device_ptr(queries) || !is_device_ptr(out_ids) || !is_device_ptr(out_dists) ||
+      (o.nprobe_per_query && !is_device_ptr(o.nprobe_per_query)))
+    return fail(RBQ_EINVAL, "rbq_search_noalloc takes device queries, outputs and nprobe_per_query");
+  std::lock_guard<std::mutex> lock(idx->mu);
+  if (idx->prof.on) return fail(RBQ_ESTATE, "profiling is enabled (its events would be allocated)");
+  if (idx->done_event) HIPCHK(hipStreamWaitEvent(st, idx->done_event, 0));
+  const TuneEntry tc = idx->tuned_for(nq);   // as rbq_search chooses them
+  int kernel = o.scan_kernel == RBQ_SCAN_AUTO ? tc.kernel : o.scan_kernel;
+  const int chunk = std::min(tc.chunk, kMaxP0 + 1 - o.k);
+  if (o.rerank_waves == 0) o.rerank_waves = tc.fin_w;
+  if (kernel == RBQ_SCAN_AUTO || (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())) {
+    if (kernel == RBQ_SCAN_MFMA && o.scan_kernel == RBQ_SCAN_MFMA)
+      return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this build");
+    kernel = RBQ_SCAN_POPCNT;
+  }
+  const bool learned = !o.nprobe_per_query && o.use_learned_nprobe && idx->mlp.has_model;
+  o.rerank_waves = fin_waves(o.rerank_waves, graph_rows(nq), o.k);
+  // the index's own workspace is set aside; every buffer the search ensures is carved
+  Workspace mine;
+  std::swap(idx->ws, mine);
+  Arena arena;
+  arena.base = (char*)base;
+  arena.cap = cap;
+  g_arena = &arena;
+  const int32_t* npq = nullptr;
+  int stride = 0;
+  rbq_status rs = run_search(idx, queries, nq, o, kernel, chunk, learned, out_ids, out_dists, st, &npq, &stride);
+  g_arena = nullptr;
+  std::swap(idx->ws, mine);
+  if (rs != RBQ_OK && arena.used > arena.cap)
+    return fail(RBQ_EINVAL, "rbq_search_noalloc: this search needs more than its %zu-byte scratch (at least %zu "
+                "bytes); use fewer queries or a smaller nprobe, or rbq_search", cap, arena.used);
+  return rs;
 }
 
 // ------------------------------------------------------------------ persistence

@@ -81,6 +81,7 @@ _SIGS = {
     "rbq_index_set_eps0": (C.c_int, [_P, C.c_float]),
     "rbq_kmeans": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_uint64, _P, _P, _P,
                              _P]),
+    "rbq_search_noalloc": (C.c_int, [_P, _P, C.c_int64, C.POINTER(RbqSearchOpts), _P, _P, _P]),
     "rbq_index_info_get": (C.c_int, [_P, C.POINTER(RbqIndexInfo)]),
     "rbq_index_list_sizes": (C.c_int, [_P, _P]),
     "rbq_index_save": (C.c_int, [_P, C.c_char_p]),
@@ -273,6 +274,28 @@ def rbq_kmeans(data, nlist, iters=10, sample=0, seed=0, init=None, stream=None):
 
 def rbq_index_set_eps0(idx, eps0):
     _check(lib().rbq_index_set_eps0(idx, float(eps0)))
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def rbq_search_noalloc(idx, queries, k, nprobe, scan_kernel=RBQ_SCAN_AUTO, use_learned_nprobe=False,
+                       nprobe_per_query=None, qid_base=0, out_ids=None, out_dists=None, stream=None,
+                       rerank_waves=0):
+    """rbq_search_noalloc on GPU tensors; out_ids/out_dists (GPU, caller-owned) are
+    allocated here by torch when not given. Returns (ids, dists)."""
+    import torch
+    nq = queries.shape[0]
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int64, device=queries.device)
+    if out_dists is None:
+        out_dists = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    o = RbqSearchOpts(k, nprobe, scan_kernel, int(bool(use_learned_nprobe)),
+                      _dev(nprobe_per_query, torch.int32), qid_base, 0, int(rerank_waves))
+    _check(lib().rbq_search_noalloc(idx, _dev(queries, torch.float32), nq, C.byref(o),
+                                    _dev(out_ids, torch.int64), _dev(out_dists, torch.float32),
+                                    _stream(stream)))
+    return out_ids, out_dists
 
 
 def rbq_index_info_get(idx) -> dict:
