@@ -374,6 +374,115 @@ def search(index: OracleIndex, q_raw, qid: int, k: int, nprobe: int, seed: int,
 
 
 # ----------------------------------------------------------------------------
+# Inner product and cosine similarity (conclusion, footnote): with c the list
+# centroid,
+#   <o_r, q_r> = ||o_r - c|| ||q_r - c|| <o, q> + <o_r, c> + <q_r, c> - ||c||^2
+# where o, q are the unit vectors of Sec. 3.1.1, so the unbiased estimate of
+# <o, q> (Theorem 3.2) gives an unbiased estimate of the inner product, and its
+# confidence interval scaled by ||o_r - c|| ||q_r - c|| bounds it. Cosine
+# similarity is the inner product of the unit-normalised raw vectors.
+# Readings: the IVF probe takes the lists whose centroids have the largest
+# inner product with the query (ties to the lower id); the sequential rerank
+# drops a code whose upper bound is below the k-th largest exact inner product
+# found so far (equality keeps it); results are ordered by (-inner product, id).
+
+def ip_code_terms(index: OracleIndex) -> np.ndarray:
+    """Per data vector: <o_r, c> - ||c||^2 = <o_r - c, c> for its list's centroid."""
+    c = index.centroids[index.assign]
+    return ((index.data - c) * c).sum(1)
+
+
+def estimate_ip(xq, ipo, norm_o, norm_q, code_term, pair_term, dp, eps0: float = EPS0):
+    """Inner product estimate and its upper bound (conclusion footnote with Theorem 3.2).
+
+    est = <x_bar, q_bar>/<o_bar, o> estimates <o, q>;
+    ip  = ||o_r-c|| ||q_r-c|| est + code_term + pair_term, with code_term =
+          <o_r - c, c> and pair_term = <q_r, c>;
+    ub  = ip + ||o_r-c|| ||q_r-c|| hw (hw the half-width of Theorem 3.2).
+    Returns (est, ip, ub)."""
+    ipo = np.asarray(ipo, dtype=np.float64)
+    a = np.asarray(norm_o, dtype=np.float64)
+    est = np.asarray(xq, dtype=np.float64) / ipo
+    hw = np.sqrt(np.maximum(1.0 - ipo * ipo, 0.0)) / ipo * (eps0 / math.sqrt(dp - 1))
+    ab = a * norm_q
+    ip = ab * est + np.asarray(code_term, dtype=np.float64) + pair_term
+    return est, ip, ip + ab * hw
+
+
+def probe_lists_ip(q_raw, centroids, nprobe: int) -> np.ndarray:
+    """The nprobe lists whose centroids have the largest inner product with the
+    raw query, largest first, ties to the lower list id."""
+    c = np.asarray(centroids, dtype=np.float64)
+    s = c @ np.asarray(q_raw, dtype=np.float64)
+    order = np.lexsort((np.arange(len(s)), -s))
+    return order[:nprobe]
+
+
+def exact_ip(data_rows, q_raw) -> np.ndarray:
+    return np.asarray(data_rows, dtype=np.float64) @ np.asarray(q_raw, dtype=np.float64)
+
+
+def exact_topk_ip(data, q_raw, k: int, candidate_ids=None):
+    """Plain definition of the inner-product search result: the k largest exact
+    inner products among `candidate_ids` (all rows if None), ordered by
+    (-inner product, id)."""
+    ids = np.arange(len(data)) if candidate_ids is None else np.asarray(candidate_ids)
+    v = exact_ip(np.asarray(data)[ids], q_raw)
+    order = np.lexsort((ids, -v))[:k]
+    return ids[order], v[order]
+
+
+def search_ip(index: OracleIndex, q_raw, qid: int, k: int, nprobe: int, seed: int,
+              eps0: float = EPS0, bq: int = BQ):
+    """Maximum inner product search: Algorithm 2's estimate turned into an
+    inner product, lists probed by centroid inner product, the sequential rule
+    of Sec. 4 with the bound reversed (drop a code whose upper bound is below
+    tau, the k-th largest exact inner product so far, -inf until k are known).
+    Returns (ids, inner products, info) like search(); 'violations' lists the
+    exact top-k members of the probed lists whose upper bound fell below their
+    inner product."""
+    probed = probe_lists_ip(q_raw, index.centroids, nprobe)
+    fo = ip_code_terms(index)
+    best_v, best_i = [], []
+    tau = -math.inf
+    reranked = 0
+    all_ids, all_ub = [], []
+    q64 = np.asarray(q_raw, dtype=np.float64)
+    for lid in probed:
+        u = rounding_uniforms_fast(seed, qid, int(lid), index.dp)
+        qq = quantize_query(q_raw, index.centroids[lid], index.p, u, bq)
+        ids = index.lists[int(lid)]
+        bits = index.bits[ids]
+        if qq.b == 0.0:
+            xq = np.zeros(len(ids))
+        else:
+            xq = xbar_dot_qbar(ip_naive(bits, qq.qu), popcount_code(bits), qq.vl, qq.delta, qq.sq, index.dp)
+        g = float(index.centroids[lid] @ q64)
+        _, _, ub = estimate_ip(xq, index.ipo[ids], index.norm[ids], qq.b, fo[ids], g, index.dp, eps0)
+        all_ids.append(ids)
+        all_ub.append(ub)
+        for oid, ubv in zip(ids, ub):
+            if ubv < tau:
+                continue
+            v = float(exact_ip(index.data[oid:oid + 1], q_raw)[0])
+            reranked += 1
+            best_v.append(v)
+            best_i.append(int(oid))
+            order = np.lexsort((np.array(best_i), -np.array(best_v)))[:k]
+            best_v = [best_v[j] for j in order]
+            best_i = [best_i[j] for j in order]
+            if len(best_v) >= k:
+                tau = best_v[k - 1]
+    cand = np.concatenate(all_ids) if all_ids else np.zeros(0, np.int64)
+    ubs = np.concatenate(all_ub) if all_ub else np.zeros(0)
+    t_ids, t_v = exact_topk_ip(index.data, q_raw, k, cand)
+    ub_of = dict(zip(cand.tolist(), ubs.tolist()))
+    viol = [int(i) for i, v in zip(t_ids, t_v) if ub_of[int(i)] < v]
+    return (np.array(best_i, dtype=np.int64), np.array(best_v),
+            {"probed": probed, "reranked": reranked, "violations": viol})
+
+
+# ----------------------------------------------------------------------------
 # Closed forms used as pins (Appendix B and Lemma "Distribution").
 
 def expected_ipo(dim: int) -> float:

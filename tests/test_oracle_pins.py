@@ -492,3 +492,88 @@ def test_relative_error_and_entropy_on_mixture():
             np.testing.assert_array_equal(pe["ip"], O.pair_estimates(idx, int(lid), qq, ip_form="bitplanes")["ip"])
     assert worst <= PAPER["max_rel_err"]
     assert O.bit_entropy_fraction(idx.bits) > PAPER["entropy_frac"]
+
+
+# --------------------------------------------------------------- inner product (conclusion footnote)
+
+def test_ip_decomposition_equals_direct_inner_product():
+    """a b <o,q> + <o_r - c, c> + <q_r, c> equals <o_r, q_r> computed directly
+    (the footnote's identity), through the oracle's code terms and estimate_ip
+    fed the exact <o, q> (est * <o_bar,o> = <o,q> <o_bar,o>)."""
+    rng = np.random.default_rng(40)
+    d = 96
+    data = rng.normal(0.3, 1.0, (40, d))
+    cent = rng.normal(0.3, 0.5, (3, d))
+    assign = rng.integers(0, 3, 40)
+    idx = O.build_index(data, cent, assign, rng.standard_normal((128, 128)))
+    fo = O.ip_code_terms(idx)
+    q_r = rng.normal(0.1, 1.0, d)
+    for i in range(40):
+        c = cent[assign[i]]
+        b = np.linalg.norm(q_r - c)
+        o = (data[i] - c) / idx.norm[i]
+        q = (q_r - c) / b
+        xq = (o @ q) * idx.ipo[i]          # so that est = <o, q> exactly
+        est, ip, ub = O.estimate_ip(xq, idx.ipo[i], idx.norm[i], b, fo[i], c @ q_r, idx.dp)
+        assert ip == pytest.approx(data[i] @ q_r, rel=1e-12, abs=1e-12)
+        assert ub >= ip
+    # exact top-k by inner product: brute force over every vector
+    t_ids, t_v = O.exact_topk_ip(data, q_r, 5)
+    allv = data @ q_r
+    np.testing.assert_allclose(t_v, np.sort(allv)[::-1][:5], rtol=1e-12)
+    order = O.probe_lists_ip(q_r, cent, 3)
+    np.testing.assert_allclose(cent[order] @ q_r, np.sort(cent @ q_r)[::-1][:3], rtol=1e-12)
+
+
+def test_ip_estimator_unbiased_and_bound_failure_law():
+    """Over random rotations the inner-product estimate is unbiased (Theorem 3.2
+    carried through the footnote's identity), and its upper bound fails (falls
+    below the true inner product) exactly when est + hw < <o,q>, the one-sided
+    event whose probability is half the two-sided law of Lemma "Distribution"."""
+    rng = np.random.default_rng(41)
+    d, r = 128, 0.5
+    o, q = _pair_with_ip(rng, d, r)
+    c = rng.normal(0, 1, d)
+    a, b = 1.7, 2.3
+    o_r, q_r = c + a * o, c + b * q
+    fo = (o_r - c) @ c
+    g = q_r @ c
+    vals, fails = [], 0
+    n = 4000
+    for s0 in range(0, n, 500):
+        for p in O.orthogonal_from_gaussian(rng.standard_normal((500, d, d))):
+            idx = O.OracleIndex(o_r[None, :], c[None, :], [0], p)
+            xbar = (2.0 * idx.bits[0] - 1) / math.sqrt(d)
+            xq = xbar @ O.inverse_rotate(p, q[None, :])[0]
+            _, ip, ub = O.estimate_ip(xq, idx.ipo[0], idx.norm[0], b, fo, g, d)
+            vals.append(ip)
+            fails += ub < o_r @ q_r
+    vals = np.array(vals)
+    assert abs(vals.mean() - o_r @ q_r) < 4 * vals.std() / math.sqrt(n)
+    p1 = O.bound_failure_probability(r, d) / 2.0       # the law is symmetric in X_1
+    assert abs(fails / n - p1) < 4 * math.sqrt(p1 * (1 - p1) / n) + 1e-3
+
+
+def test_search_ip_returns_exact_topk_of_probed_lists():
+    """Maximum inner product search with the reversed sequential rule returns the
+    exact top-k (largest inner products) of the probed lists wherever no true
+    member's upper bound fell below its inner product; with eps0 = 0 it reranks
+    less and can only lose."""
+    data, qs = _small_flat(3000, 12, 42)
+    rng = np.random.default_rng(43)
+    cent = data[rng.choice(len(data), 16, replace=False)]
+    assign = np.argmin(((data[:, None, :] - cent[None]) ** 2).sum(-1), 1)
+    idx = O.build_index(data, cent, assign, rng.standard_normal((128, 128)))
+    hits = 0
+    for qi, q in enumerate(qs):
+        ids, v, info = O.search_ip(idx, q, qi, 10, 4, seed=4003)
+        cand = np.concatenate([idx.lists[k] for k in info["probed"]])
+        t_ids, t_v = O.exact_topk_ip(data, q, 10, cand)
+        if not info["violations"]:
+            np.testing.assert_array_equal(ids, t_ids)
+            np.testing.assert_allclose(v, t_v, rtol=1e-12)
+        hits += len(set(ids.tolist()) & set(t_ids.tolist()))
+        ids0, _, info0 = O.search_ip(idx, q, qi, 10, 4, seed=4003, eps0=0.0)
+        assert info0["reranked"] <= info["reranked"]
+        assert info["reranked"] < len(cand)
+    assert hits / (10 * len(qs)) >= 0.99
