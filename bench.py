@@ -687,7 +687,8 @@ def bench_learned(args):
     log(f"calibrated in {calib_s:.1f}s: learned threshold {thr:.5f} (test recall {rc_l:.4f}, mean nprobe "
         f"{st_l['pairs'] / nte:.1f}), fixed nprobe {fixed} (test recall {rc_f:.4f})")
     batches = [q_test[s0:s0 + batch].contiguous() for s0 in range(0, nte, batch)]
-    kern = {"popcnt": R.RBQ_SCAN_POPCNT, "mfma": R.RBQ_SCAN_MFMA, "auto": R.RBQ_SCAN_AUTO}[args.kernel]
+    kern = {"popcnt": R.RBQ_SCAN_POPCNT, "mfma": R.RBQ_SCAN_MFMA, "mfma_fp4": R.RBQ_SCAN_MFMA_FP4,
+            "auto": R.RBQ_SCAN_AUTO}[args.kernel]
     # timed: learned, then fixed
     R.rbq_nprobe_model_set(idx.h, w, thr)
     t_l, nq_l, prof_l, out_l = time_batches(idx, batches, k, cap, args.steps, args.warmup, use_learned_nprobe=True,
@@ -795,7 +796,7 @@ def main():
     ap.add_argument("--nlist", type=int, default=0, help="IVF lists (0: the workload's default)")
     ap.add_argument("--nprobe", type=int, default=0, help="0: smallest of the sweep reaching recall 0.95")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--kernel", default="popcnt", choices=["popcnt", "mfma", "auto"])
+    ap.add_argument("--kernel", default="popcnt", choices=["popcnt", "mfma", "mfma_fp4", "auto"])
     ap.add_argument("--workload", default="learned", choices=["learned", "sift1m", "embed10m", "gist1m"])
     ap.add_argument("--fullscan-only", action="store_true",
                     help="embed10m: only build the index and run six one-query searches of every list")
@@ -851,7 +852,8 @@ def main():
     log(f"index built in {build_s:.2f}s; ground truth")
     gt_i, gt_d = ground_truth(wl.data, wl.queries, k, dev)
     q = torch.from_numpy(wl.queries).to(dev)
-    kern = {"popcnt": R.RBQ_SCAN_POPCNT, "mfma": R.RBQ_SCAN_MFMA, "auto": R.RBQ_SCAN_AUTO}[args.kernel]
+    kern = {"popcnt": R.RBQ_SCAN_POPCNT, "mfma": R.RBQ_SCAN_MFMA, "mfma_fp4": R.RBQ_SCAN_MFMA_FP4,
+            "auto": R.RBQ_SCAN_AUTO}[args.kernel]
 
     sweep = {}
     chosen = args.nprobe

@@ -65,7 +65,26 @@ enum {
 enum {
   RBQ_SCAN_AUTO = 0,     /* autotuned / heuristic choice per search */
   RBQ_SCAN_POPCNT = 1,   /* bit-plane AND + popcount, one code per lane */
-  RBQ_SCAN_MFMA = 2      /* int8 MFMA over queries grouped by list */
+  RBQ_SCAN_MFMA = 2,     /* int8 MFMA over queries grouped by list */
+  RBQ_SCAN_MFMA_FP4 = 3  /* the same contraction on the scaled FP8 (query, E4M3) x
+                            FP4 (code bit, E2M1) MFMA with FP32 accumulation, exact
+                            for B_q <= 4 (RBQ_EUNSUPPORTED above) */
+};
+
+/* What a search ranks by. The codes are the same for every metric.
+ *   RBQ_METRIC_L2      squared Euclidean distance (Eq. (2)), smallest first
+ *   RBQ_METRIC_IP      inner product, largest first: the conclusion's identity
+ *                      <o_r, q_r> = ||o_r - c|| ||q_r - c|| <o, q> + <o_r - c, c>
+ *                      + <q_r, c> carries Theorem 3.2's unbiased estimate of
+ *                      <o, q> and its interval over to the inner product; lists
+ *                      are probed by the largest <q_r, c_k>
+ *   RBQ_METRIC_COSINE  cosine similarity: the inner product of the unit-
+ *                      normalised vectors (the index normalises the data, a
+ *                      search its queries; zero vectors stay zero) */
+enum {
+  RBQ_METRIC_L2 = 0,
+  RBQ_METRIC_IP = 1,
+  RBQ_METRIC_COSINE = 2
 };
 
 typedef struct rbq_index rbq_index;
@@ -81,6 +100,7 @@ typedef struct {
   float eps0;            /* confidence parameter of the error bound (Theorem 3.2) */
   int32_t rot_precision; /* RBQ_ROT_FP32 or RBQ_ROT_BF16X3 */
   uint64_t seed;         /* seeds the randomised rounding (and P if none is given) */
+  int32_t metric;        /* RBQ_METRIC_L2 (default), RBQ_METRIC_IP or RBQ_METRIC_COSINE */
 } rbq_params;
 
 /* Per-search options. */
@@ -106,7 +126,7 @@ typedef struct {
 } rbq_search_opts;
 
 /* Graph replay (use_graph = 1). The kernel sequence of a search is captured
- * once per shape (batch size rounded up to at most 12.5% more rows, k,
+ * once per shape (batch size rounded up to at most 6.25% more rows, k,
  * nprobe, scan kernel, learned or not, qid_base) and replayed: the queries are
  * copied into a staging buffer of the rounded size, the graph runs, and the
  * first nq rows of its results are copied out. Rows past nq search the staging
@@ -138,7 +158,7 @@ typedef struct {
   int64_t graphs_cached;      /* captured graphs currently held */
 } rbq_index_info;
 
-/* Fills defaults: code_bits 0, bq 4, eps0 1.9, FP32 rotation, seed 0 (Sec. 5.1). */
+/* Fills defaults: code_bits 0, bq 4, eps0 1.9, FP32 rotation, seed 0 (Sec. 5.1), L2. */
 rbq_status rbq_params_default(rbq_params* p, int32_t dim, int32_t nlist);
 
 /* Creates an empty index with validated parameters. *out is owned by the caller
@@ -204,7 +224,11 @@ rbq_status rbq_kmeans(const float* data, int64_t n, int32_t dim, int32_t nlist, 
  *   out_ids   host or device, nq x k int64: ids of the k nearest by exact distance
  *             among the reranked candidates of the probed lists, ordered by
  *             (distance, id); -1 pads when fewer than k vectors were probed
- *   out_dists host or device, nq x k float32 exact squared distances (+inf pads)
+ *   out_dists host or device, nq x k float32 exact squared distances (+inf pads);
+ *             with RBQ_METRIC_IP / RBQ_METRIC_COSINE: the k largest inner
+ *             products (cosines) in decreasing order, ties by id (-inf pads),
+ *             computed as M_q - (M_q - <o_r, q_r>) with M_q = ||q_r|| max ||o_r||
+ *             (1 + 1e-5), so within a few FP32 ulps of M_q of the exact value
  *   stats     host or NULL (see rbq_search_stats)
  * Host queries (and a host opts->nprobe_per_query) are copied to the device
  * on `stream`; host outputs are copied back and the stream is synchronised
@@ -259,8 +283,10 @@ const char* rbq_last_error(void);
  * sample itself), it times whole searches of the first rows of `queries` (host
  * or device, nq x dim, nq <= 2^24) at (k, nprobe): every chunk length (codes
  * per work unit of the persistent scans: 256, 512, 1024, 2048) with every scan
- * kernel (popcount, MFMA), then, for batches that split a query's rerank over
- * several waves, rerank waves 1..64 at the best pair. A search with
+ * kernel (popcount, int8 MFMA, and FP8 x FP4 MFMA when B_q <= 4), then, for a
+ * batched (MFMA) scan, 16, 32 or 64
+ * query rows per work unit, then, for batches that split a query's rerank over
+ * several waves, rerank waves 1..64 at the best choice. A search with
  * scan_kernel = RBQ_SCAN_AUTO and rerank_waves = 0 then uses the choices of
  * the bucket its batch size falls in (up to the geometric middle between two
  * tuned sizes); the chunk length applies to every later search. Results stay
@@ -272,9 +298,11 @@ rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t nq, int32_
 typedef struct {
   int64_t max_nq;        /* batches of at most this many queries use this entry */
   int32_t chunk;         /* codes per work unit */
-  int32_t scan_kernel;   /* RBQ_SCAN_POPCNT or RBQ_SCAN_MFMA */
+  int32_t scan_kernel;   /* RBQ_SCAN_POPCNT, RBQ_SCAN_MFMA or RBQ_SCAN_MFMA_FP4 */
   int32_t rerank_waves;  /* 0: chosen from the batch size */
   float ms;              /* the trial search's time at the bucket's size */
+  int32_t mfma_row_groups; /* batched scans: groups of 16 queries that share each
+                              expanded code fragment (1, 2, 4; 0: one) */
 } rbq_tune_entry;
 
 /* The autotuner's table: up to max_entries entries (host) and *count, the
@@ -423,10 +451,13 @@ rbq_status rbq_debug_quantize(rbq_index* idx, const float* queries, int64_t nq,
  * <x_b, q_u> and popcount (Sec. 3.3.2), the estimate <x_bar,q_bar>/<o_bar,o>
  * (Theorem 3.2, with the Sec. 3.3.2 decomposition), the distance by Eq. (2)
  * and its lower bound with the half-width of Theorem 3.2:
- * qu device code_bits uint8, scal host 4 floats {b, v_l, Delta, (unused)};
+ * qu device code_bits uint8, scal host 4 floats {b, v_l, Delta, t} where t is
+ * unused for L2 and, for the inner-product metrics, the pair's constant
+ * M_q - <q_r, c>: dist is then M_q minus the inner-product estimate and lb
+ * subtracts ||o_r - c|| ||q_r - c|| times the half-width;
  * outputs device, one per member of the list in list order (ids of
  * rbq_debug_list_ids): ip, pc int32; est, dist, lb float32.
- * kernel: RBQ_SCAN_POPCNT or RBQ_SCAN_MFMA. */
+ * kernel: RBQ_SCAN_POPCNT, RBQ_SCAN_MFMA or RBQ_SCAN_MFMA_FP4. */
 rbq_status rbq_debug_scan(rbq_index* idx, int32_t list, const uint8_t* qu, const float* scal,
                           int32_t kernel, int32_t* ip, int32_t* pc, float* est, float* dist,
                           float* lb, void* stream);

@@ -106,7 +106,80 @@ __global__ __launch_bounds__(256) void k_update_centroids(const unsigned long lo
   if (lane == 0) cnorm[l] = (float)nn;
 }
 
+// ------------------------------------------------------------------ inner product
+// Per code: <o_r - c, c> (FP64 sum) and ||o_r||^2 (max over codes by atomicMax
+// on float bits); one wave per row.
+__global__ __launch_bounds__(256) void k_ip_terms(const float* __restrict__ raw, const float* __restrict__ cent,
+                                                  const int32_t* __restrict__ list_of, int64_t n, int dim,
+                                                  float* __restrict__ fip, uint32_t* __restrict__ r2max) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n) return;
+  const int lane = lane_id();
+  const float* o = raw + r * (int64_t)dim;
+  const float* c = cent + (int64_t)list_of[r] * dim;
+  double f = 0.0, nn = 0.0;
+  for (int i = lane; i < dim; i += kWave) {
+    const double ci = c[i], oi = o[i];
+    f += (oi - ci) * ci;
+    nn += oi * oi;
+  }
+  f = wave_sum_d(f);
+  nn = wave_sum_d(nn);
+  if (lane == 0) {
+    fip[r] = (float)f;
+    atomicMax(r2max, __float_as_uint((float)nn));
+  }
+}
+
+// y = x / ||x|| per row (zero rows stay zero); one wave per row.
+__global__ __launch_bounds__(256) void k_normalize_rows(const float* __restrict__ x, int64_t n, int dim,
+                                                        float* __restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n) return;
+  const int lane = lane_id();
+  const float* xr = x + r * (int64_t)dim;
+  double nn = 0.0;
+  for (int i = lane; i < dim; i += kWave) nn += (double)xr[i] * xr[i];
+  nn = wave_sum_d(nn);
+  const float inv = nn > 0.0 ? (float)(1.0 / sqrt(nn)) : 0.f;
+  float* yr = y + r * (int64_t)dim;
+  for (int i = lane; i < dim; i += kWave) yr[i] = xr[i] * inv;
+}
+
+// M_q = ||q|| rmax (1 + 1e-5): no exact inner product can exceed it, so
+// M_q - <o_r, q_r> >= 0 for every code; one wave per query.
+__global__ __launch_bounds__(256) void k_query_m(const float* __restrict__ q, int64_t nq, int dim, float rmax,
+                                                 float* __restrict__ q_m) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= nq) return;
+  const int lane = lane_id();
+  double nn = 0.0;
+  for (int i = lane; i < dim; i += kWave) nn += (double)q[r * (int64_t)dim + i] * q[r * (int64_t)dim + i];
+  nn = wave_sum_d(nn);
+  if (lane == 0) q_m[r] = (float)(sqrt(nn) * (double)rmax * (1.0 + 1e-5)) + 1e-30f;
+}
+
 }  // namespace
+
+hipError_t launch_ip_terms(const float* raw, const float* cent, const int32_t* list_of, int64_t n, int dim,
+                           float* fip, uint32_t* r2max, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ip_terms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, raw, cent, list_of, n, dim, fip,
+                     r2max);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize_rows(const float* x, int64_t n, int dim, float* y, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_normalize_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, x, n, dim, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_m(const float* q, int64_t nq, int dim, float rmax, float* q_m, hipStream_t st) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_query_m, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, q, nq, dim, rmax, q_m);
+  return hipGetLastError();
+}
 
 hipError_t launch_absmax(const float* x, int64_t n, uint32_t* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;

@@ -20,9 +20,12 @@ namespace {
 
 constexpr int kThreads = 256;
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct RowInfo {
   PairRec rec;
+  PairTerms t;        // the pair's estimator constants (pair_terms / pair_terms_ip)
   float tau;
   int32_t valid;      // 1 when this row's chunk belongs to the scanned phase
   int64_t seg_base;   // first segment slot of (pair, chunk)
@@ -31,89 +34,218 @@ struct RowInfo {
 
 // 4 bits -> 4 bytes of 0/1: the nibble's bits land on bits 0, 8, 16, 24.
 __device__ __forceinline__ int nib_to_bytes(uint32_t nib) { return (int)((nib * 0x00204081u) & 0x01010101u); }
+__device__ __forceinline__ uint32_t nib_to_bytes_u(uint32_t nib) { return (nib * 0x00204081u) & 0x01010101u; }
 
-// One (list, chunk, 16-row group) unit. rows[]/A must be in LDS already.
-// Writes candidates of valid rows into their segments and their counts.
-template <bool DEBUG>
+// FP8 (E4M3, OCP: bias 7) encodings of the integers 0..15, all exact: the
+// query operand of the FP8 x FP4 contraction (B_q <= 4).
+__constant__ uint8_t kFp8Int[16] = {0x00, 0x38, 0x40, 0x44, 0x48, 0x4A, 0x4C, 0x4E,
+                                    0x50, 0x51, 0x52, 0x53, 0x54, 0x55, 0x56, 0x57};
+
+// 8 code bits -> 8 FP4 (E2M1) values 0 or 1.0 (0b0010) in one dword. The
+// nibbles come out in the order of dimensions 0, 4, 1, 5, 2, 6, 3, 7 of the
+// byte.
+__device__ __forceinline__ int bits_to_fp4x8(uint32_t x) {
+  const uint32_t lo = (uint32_t)nib_to_bytes_u(x & 15u), hi = (uint32_t)nib_to_bytes_u((x >> 4) & 15u);
+  return (int)((lo | (hi << 4)) << 1);
+}
+
+// Operand layouts of v_mfma_scale_f32_16x16x128_f8f6f4 (FP8 A, FP4 B), as
+// measured on gfx950: lane group g of the B operand holds the 32 values
+// k = 32 g .. 32 g + 31 (nibble e is k = 32 g + e), while lane group g of the
+// A operand holds k = 16 g .. 16 g + 15 in bytes 0..15 and k = 64 + 16 g ..
+// 64 + 16 g + 15 in bytes 16..31. The B side carries the code bits of
+// dimensions 128 t + 32 g .. +31 in the nibble order of bits_to_fp4x8, so the
+// query byte at A position x (0..127 within a 128-dimension block) must be the
+// dimension that B's k(x) holds: k(x) = 16 (x / 32) + x % 32 for x % 32 < 16,
+// else 64 + 16 (x / 32) + x % 32 - 16. A group of 8 consecutive positions
+// maps to the 8 dimensions starting at k(x) rounded down to 8, in the nibble order.
+__device__ __forceinline__ int f4_src_dim(int d) {
+  const int x = d & 127, g = x >> 5, e = x & 31;
+  return (d & ~127) + (e < 16 ? 16 * g + e : 64 + 16 * g + (e - 16));
+}
+
+// One (list, chunk, RG x 16-row group) unit. rows[], rg_live[] and A must be
+// in LDS already. Each wave takes 16 codes of every 64-code block, expands
+// their bits once per code word and multiplies them against the RG row groups
+// (one MFMA each; row groups without a live row are skipped), then writes the
+// candidates of valid rows into their segments and their counts.
+// F4: the query rows in LDS are FP8 codes placed by f4_src_dim and in the
+// nibble order of bits_to_fp4x8, each row padded to a multiple of 128
+// dimensions, and every v_mfma_scale_f32_16x16x128_f8f6f4 takes 128 dimensions
+// (two code words) of 16 codes against 16 query rows; FP32 accumulation of
+// integer products below 16 over at most 4096 dimensions is exact, so the
+// inner products are those of the int8 contraction bit for bit.
+template <bool DEBUG, bool F4, int WS, int RG>
 __device__ void mfma_unit(const SearchDev& s, int64_t start, int64_t end, const RowInfo* rows,
-                          const int8_t* A, uint16_t (*masks)[4], int32_t* rowcnt, float hwk,
+                          const int32_t* rg_live, const int8_t* A, uint16_t (*masks)[4], int32_t* rowcnt,
                           int32_t* dbg_ip, int32_t* dbg_pc, float* dbg_est, float* dbg_dist,
                           float* dbg_lb, int64_t dbg_base) {
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int col = lane & 15, grp = lane >> 4;
   const int dp = s.dp, W = s.W;
+  const int dpa = F4 ? (dp + 127) / 128 * 128 : dp;
+  bool hl[RG];
+#pragma unroll
+  for (int h = 0; h < RG; ++h) hl[h] = uniform_i32(rg_live[h]) != 0;
   for (int64_t blk = start; blk < end; blk += 64) {
     const bool pvalid = blk + wave * 16 + col < end;
     // lanes past the end read the block's first code (in bounds) and are masked
     const int64_t p = pvalid ? blk + wave * 16 + col : blk;
     const uint32_t keep = pvalid ? 0xFFFFu : 0u;
-    i32x4 acc = {0, 0, 0, 0};
+    i32x4 acc[RG];
+#pragma unroll
+    for (int h = 0; h < RG; ++h) acc[h] = i32x4{0, 0, 0, 0};
     int pcp = 0;
-    for (int t = 0; t < W; ++t) {
-      const uint32_t bits = (uint32_t)(s.codes[code_word_index(p, t, W)] >> (16 * grp)) & keep;
-      pcp += __popc(bits);
-      i32x4 b;
-      b[0] = nib_to_bytes(bits & 15u);
-      b[1] = nib_to_bytes((bits >> 4) & 15u);
-      b[2] = nib_to_bytes((bits >> 8) & 15u);
-      b[3] = nib_to_bytes((bits >> 12) & 15u);
-      // A fragment: row `col`, dimensions 64 t + 16 grp .. +15
-      const i32x4 a = *reinterpret_cast<const i32x4*>(A + (size_t)col * dp + t * 64 + grp * 16);
-      acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc, 0, 0, 0);
+    if constexpr (F4) {
+      // lane group grp: dimensions 128 t2 + 32 grp .. +31, half (grp & 1) of
+      // word 2 t2 + (grp >> 1); every word read is issued before the first product
+      const uint32_t keep32 = pvalid ? 0xFFFFFFFFu : 0u;
+      const uint32_t* c32 = reinterpret_cast<const uint32_t*>(s.codes);
+      f32x4 accf[RG];
+#pragma unroll
+      for (int h = 0; h < RG; ++h) accf[h] = f32x4{0.f, 0.f, 0.f, 0.f};
+      auto step = [&](uint32_t bits, int t2) {
+        pcp += __popc(bits);
+        i32x8 b = {bits_to_fp4x8(bits & 0xFFu), bits_to_fp4x8((bits >> 8) & 0xFFu),
+                   bits_to_fp4x8((bits >> 16) & 0xFFu), bits_to_fp4x8(bits >> 24), 0, 0, 0, 0};
+#pragma unroll
+        for (int h = 0; h < RG; ++h) {
+          if (!hl[h]) continue;
+          const i32x8 a = *reinterpret_cast<const i32x8*>(A + (size_t)(16 * h + col) * dpa + t2 * 128 + grp * 32);
+          // formats: A FP8 E4M3 (0), B FP4 E2M1 (4); E8M0 scales 127 = 2^0
+          accf[h] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, accf[h], 0, 4, 0, 127, 0, 127);
+        }
+      };
+      auto load = [&](int t2) -> uint32_t {
+        const int w = 2 * t2 + (grp >> 1);
+        const uint32_t v = c32[2 * code_word_index(p, min(w, W - 1), W) + (grp & 1)];
+        return w < W ? v & keep32 : 0u;
+      };
+      if constexpr (WS > 0) {
+        constexpr int T2 = (WS + 1) / 2;
+        uint32_t bw[T2];
+#pragma unroll
+        for (int t2 = 0; t2 < T2; ++t2) bw[t2] = load(t2);
+#pragma unroll
+        for (int t2 = 0; t2 < T2; ++t2) step(bw[t2], t2);
+      } else {
+        const int T2 = (W + 1) / 2;
+        for (int t0 = 0; t0 < T2; t0 += 4) {
+          uint32_t bw[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) bw[j] = load(min(t0 + j, T2 - 1));
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (t0 + j < T2) step(bw[j], t0 + j);
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < RG; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[h][i] = (int)accf[h][i];
+    } else {
+      // the lane's 16-bit slice (dimensions 64 t + 16 grp .. +15) of each code
+      // word; every word read is issued before the first product
+      const uint16_t* c16 = reinterpret_cast<const uint16_t*>(s.codes);
+      auto step = [&](uint32_t bits, int t) {
+        bits &= keep;
+        pcp += __popc(bits);
+        i32x4 b;
+        b[0] = nib_to_bytes(bits & 15u);
+        b[1] = nib_to_bytes((bits >> 4) & 15u);
+        b[2] = nib_to_bytes((bits >> 8) & 15u);
+        b[3] = nib_to_bytes((bits >> 12) & 15u);
+#pragma unroll
+        for (int h = 0; h < RG; ++h) {
+          if (!hl[h]) continue;
+          // A fragment: row 16 h + col, dimensions 64 t + 16 grp .. +15
+          const i32x4 a = *reinterpret_cast<const i32x4*>(A + (size_t)(16 * h + col) * dp + t * 64 + grp * 16);
+          acc[h] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[h], 0, 0, 0);
+        }
+      };
+      if constexpr (WS > 0) {
+        uint32_t bw[WS];
+#pragma unroll
+        for (int t = 0; t < WS; ++t) bw[t] = c16[4 * code_word_index(p, t, WS) + grp];
+#pragma unroll
+        for (int t = 0; t < WS; ++t) step(bw[t], t);
+      } else {
+        for (int t0 = 0; t0 < W; t0 += 4) {
+          uint32_t bw[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) bw[j] = c16[4 * code_word_index(p, min(t0 + j, W - 1), W) + grp];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (t0 + j < W) step(bw[j], t0 + j);
+        }
+      }
     }
     // popcount of the code: the four lane groups hold its four 16-bit slices
     int pc = pcp + __shfl_xor(pcp, 16, kWave);
     pc += __shfl_xor(pc, 32, kWave);
     const float2 sf = s.sfac[p];
-    // acc[i] + qoff * pc = IP of row 4 grp + i with code `col` (the int8 operand
-    // holds q_u - qoff, so that B_q = 8 values fit)
-    bool pass[4];
-    float lbv[4];
+    const float ct = s.metric != 0 ? -s.fip[p] : code_term_l2(sf);
+    // acc[h][i] + qoff * pc = IP of row 16 h + 4 grp + i with code `col` (the
+    // int8 operand holds q_u - qoff, so that B_q = 8 values fit)
+    bool pass[RG][4];
+    float lbv[RG][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = 4 * grp + i;
-      const RowInfo& ri = rows[row];
-      const PairRec& r = ri.rec;
-      float dist, lbe;
-      const int ipv = acc[i] + s.qoff * pc;
-      estimate(r, pair_terms(r, hwk), sf, ipv, pc, dist, lbe);
-      const bool live = pvalid && ri.valid;
-      const float lb = live ? lbe : __builtin_inff();
-      if (DEBUG && row == 0 && live) {
-        const int64_t o = p - dbg_base;
-        dbg_ip[o] = ipv;
-        dbg_pc[o] = pc;
-        dbg_est[o] = estimate_est(r, s.fac[p].y, ipv, pc);
-        dbg_dist[o] = dist;
-        dbg_lb[o] = lb;
+    for (int h = 0; h < RG; ++h) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        pass[h][i] = false;
+        lbv[h][i] = __builtin_inff();
+        if (!hl[h]) continue;
+        const int row = 16 * h + 4 * grp + i;
+        const RowInfo& ri = rows[row];
+        float dist, lbe;
+        const int ipv = acc[h][i] + s.qoff * pc;
+        estimate(ri.rec, ri.t, sf, ct, ipv, pc, dist, lbe);
+        const bool live = pvalid && ri.valid;
+        const float lb = live ? lbe : __builtin_inff();
+        if (DEBUG && row == 0 && live) {
+          const int64_t o = p - dbg_base;
+          dbg_ip[o] = ipv;
+          dbg_pc[o] = pc;
+          dbg_est[o] = estimate_est(ri.rec, s.fac[p].y, ipv, pc);
+          dbg_dist[o] = dist;
+          dbg_lb[o] = lb;
+        }
+        pass[h][i] = live && lb <= ri.tau;
+        lbv[h][i] = lb;
       }
-      pass[i] = live && lb <= ri.tau;
-      lbv[i] = lb;
     }
     if (DEBUG) continue;
     // per-row 16-bit masks of this wave's codes
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint64_t m = __ballot(pass[i]);
-      if (lane < 4) masks[4 * lane + i][wave] = (uint16_t)((m >> (16 * lane)) & 0xFFFFu);
+    for (int h = 0; h < RG; ++h) {
+      if (!hl[h]) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint64_t m = __ballot(pass[h][i]);
+        if (lane < 4) masks[16 * h + 4 * lane + i][wave] = (uint16_t)((m >> (16 * lane)) & 0xFFFFu);
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (!pass[i]) continue;
-      const int row = 4 * grp + i;
-      uint64_t m64 = 0;
+    for (int h = 0; h < RG; ++h) {
 #pragma unroll
-      for (int w = 0; w < 4; ++w) m64 |= (uint64_t)masks[row][w] << (16 * w);
-      const int bit = wave * 16 + col;
-      const int before = __popcll(m64 & ((1ull << bit) - 1ull));
-      Cand cd;
-      cd.pos = (int32_t)p;
-      cd.lb = lbv[i];
-      s.seg[rows[row].seg_base + rowcnt[row] + before] = cd;
+      for (int i = 0; i < 4; ++i) {
+        if (!pass[h][i]) continue;
+        const int row = 16 * h + 4 * grp + i;
+        uint64_t m64 = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) m64 |= (uint64_t)masks[row][w] << (16 * w);
+        const int bit = wave * 16 + col;
+        const int before = __popcll(m64 & ((1ull << bit) - 1ull));
+        Cand cd;
+        cd.pos = (int32_t)p;
+        cd.lb = lbv[h][i];
+        s.seg[rows[row].seg_base + rowcnt[row] + before] = cd;
+      }
     }
     __syncthreads();
-    if (threadIdx.x < 16) {
+    if (threadIdx.x < 16 * RG && rg_live[threadIdx.x >> 4]) {
       const int row = threadIdx.x;
       uint64_t m64 = 0;
       for (int w = 0; w < 4; ++w) m64 |= (uint64_t)masks[row][w] << (16 * w);
@@ -172,7 +304,8 @@ __global__ __launch_bounds__(1024) void k_group_offsets(SearchDev s) {
       const int c = s.mf_cnt[k];
       const int n = s.list_off[k + 1] - s.list_off[k];
       vp = c;
-      vu = c > 0 ? (int64_t)((n + s.chunk - 1) / s.chunk) * ((c + 15) / 16) : 0;
+      const int rows = 16 * s.mf_rg;
+      vu = c > 0 ? (int64_t)((n + s.chunk - 1) / s.chunk) * ((c + rows - 1) / rows) : 0;
       s.mf_fill[k] = 0;
     }
     bufp[threadIdx.x] = vp;
@@ -216,16 +349,36 @@ __global__ void k_group_scatter(SearchDev s) {
 }
 
 // ---------------------------------------------------------------- persistent MFMA scan
+// FP8 row of the F4 path from 8 int8 query values (0..15) at a time: byte m
+// of each group of 8 holds dimension pi(m) of the group, pi = 0, 4, 1, 5, 2, 6, 3, 7.
+__device__ __forceinline__ uint64_t fp8_group(uint64_t v) {
+  uint64_t out = 0;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int src = (m & 1) ? 4 + (m >> 1) : (m >> 1);
+    out |= (uint64_t)kFp8Int[(v >> (8 * src)) & 15u] << (8 * m);
+  }
+  return out;
+}
+
+template <bool F4, int WS, int RG>
 __global__ __launch_bounds__(kThreads) void k_scan_mfma(SearchDev s) {
-  extern __shared__ __attribute__((aligned(16))) int8_t A[];   // 16 x dp
-  __shared__ RowInfo rows[16];
-  __shared__ uint16_t masks[16][4];
-  __shared__ int32_t rowcnt[16];
+  constexpr int R = 16 * RG;
+  extern __shared__ __attribute__((aligned(16))) int8_t A[];   // R x dpa
+  __shared__ RowInfo rows[R];
+  __shared__ uint16_t masks[R][4];
+  __shared__ int32_t rowcnt[R];
+  __shared__ int32_t rg_live[RG];
   __shared__ int64_t sh_u;
   const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
   const int64_t total = uniform_i64(s.mf_unit_off[s.nlist]);
+  const int dpa = F4 ? (s.dp + 127) / 128 * 128 : s.dp;
   for (;;) {
-    if (threadIdx.x == 0) sh_u = (int64_t)atomicAdd(&s.counters[2], 1ull);
+    if (threadIdx.x == 0) {
+      sh_u = (int64_t)atomicAdd(&s.counters[2], 1ull);
+#pragma unroll
+      for (int h = 0; h < RG; ++h) rg_live[h] = 0;
+    }
     __syncthreads();
     const int64_t u = uniform_i64(sh_u);
     __syncthreads();
@@ -233,13 +386,13 @@ __global__ __launch_bounds__(kThreads) void k_scan_mfma(SearchDev s) {
     const int list = uniform_i32((int)(ub64(s.mf_unit_off, s.nlist + 1, u) - 1));
     const int64_t local = uniform_i64(u - s.mf_unit_off[list]);
     const int cnt = uniform_i32((int)(s.mf_pair_off[list + 1] - s.mf_pair_off[list]));
-    const int ngroups = (cnt + 15) / 16;
+    const int ngroups = (cnt + R - 1) / R;
     const int c = (int)(local / ngroups);
     const int gi = (int)(local - (int64_t)c * ngroups);
     const int64_t lbeg = uniform_i64(s.list_off[list]), lend = uniform_i64(s.list_off[list + 1]);
     const int64_t start = lbeg + (int64_t)c * s.chunk;
     const int64_t end = lend < start + s.chunk ? lend : start + s.chunk;
-    if (threadIdx.x < 16) {
+    if (threadIdx.x < R) {
       const int i = threadIdx.x;
       RowInfo ri;
       ri.valid = 0;
@@ -247,11 +400,13 @@ __global__ __launch_bounds__(kThreads) void k_scan_mfma(SearchDev s) {
       ri.seg_base = 0;
       ri.count_slot = -1;
       ri.rec.k1 = ri.rec.k2 = ri.rec.k0 = ri.rec.b = 0.f;
-      if (16 * gi + i < cnt) {
-        const int64_t g = s.mf_pairs[s.mf_pair_off[list] + 16 * gi + i];
+      ri.t.pt = ri.t.coef = ri.t.coefh = 0.f;
+      if (R * gi + i < cnt) {
+        const int64_t g = s.mf_pairs[s.mf_pair_off[list] + R * gi + i];
         const int64_t q = g / s.nprobe;
         const int r = (int)(g - q * s.nprobe);
         ri.rec = s.pairs[g];
+        ri.t = s.metric != 0 ? pair_terms_ip(ri.rec, hwk, s.pair_pt[g]) : pair_terms(ri.rec, hwk);
         if (c >= first_main_chunk(s, q, r)) {
           ri.valid = 1;
           ri.tau = s.tau[q];
@@ -259,56 +414,83 @@ __global__ __launch_bounds__(kThreads) void k_scan_mfma(SearchDev s) {
           const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
           ri.seg_base = s.off_seg[q] + codeoff[r] + (int64_t)c * s.chunk;
           ri.count_slot = s.off_ch[q] + choff[r] + c;
+          rg_live[i >> 4] = 1;
         }
       }
       rows[i] = ri;
       rowcnt[i] = 0;
     }
-    // stage the 16 quantised queries (zero rows for missing pairs)
-    for (int idx = threadIdx.x * 16; idx < 16 * s.dp; idx += kThreads * 16) {
-      const int i = idx / s.dp, d = idx - i * s.dp;
-      i32x4 v = {0, 0, 0, 0};
-      if (16 * gi + i < cnt) {
-        const int64_t g = s.mf_pairs[s.mf_pair_off[list] + 16 * gi + i];
-        v = *reinterpret_cast<const i32x4*>(s.qu8 + g * s.dp + d);
+    // stage the R quantised queries (zero rows for missing pairs)
+    if constexpr (F4) {   // FP8, rows padded to a multiple of 128 dimensions
+      for (int idx = threadIdx.x * 8; idx < R * dpa; idx += kThreads * 8) {
+        const int i = idx / dpa, d = idx - i * dpa;
+        uint64_t v = 0;
+        const int src = f4_src_dim(d);
+        if (R * gi + i < cnt && src < s.dp) {
+          const int64_t g = s.mf_pairs[s.mf_pair_off[list] + R * gi + i];
+          v = fp8_group(*reinterpret_cast<const uint64_t*>(s.qu8 + g * s.dp + src));
+        }
+        *reinterpret_cast<uint64_t*>(A + idx) = v;
       }
-      *reinterpret_cast<i32x4*>(A + idx) = v;
+    } else {
+      for (int idx = threadIdx.x * 16; idx < R * s.dp; idx += kThreads * 16) {
+        const int i = idx / s.dp, d = idx - i * s.dp;
+        i32x4 v = {0, 0, 0, 0};
+        if (R * gi + i < cnt) {
+          const int64_t g = s.mf_pairs[s.mf_pair_off[list] + R * gi + i];
+          v = *reinterpret_cast<const i32x4*>(s.qu8 + g * s.dp + d);
+        }
+        *reinterpret_cast<i32x4*>(A + idx) = v;
+      }
     }
     __syncthreads();
-    mfma_unit<false>(s, start, end, rows, A, masks, rowcnt, hwk, nullptr, nullptr, nullptr,
-                     nullptr, nullptr, 0);
-    if (threadIdx.x < 16 && rows[threadIdx.x].valid) s.seg_count[rows[threadIdx.x].count_slot] = rowcnt[threadIdx.x];
+    mfma_unit<false, F4, WS, RG>(s, start, end, rows, rg_live, A, masks, rowcnt, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, 0);
+    if (threadIdx.x < R && rows[threadIdx.x].valid) s.seg_count[rows[threadIdx.x].count_slot] = rowcnt[threadIdx.x];
     __syncthreads();
   }
 }
 
-// Debug: one caller-given quantised query (row 0) against a whole list.
+// Debug: one caller-given quantised query (row 0) against a whole list, with
+// the kernel instantiation the search uses for this code width.
+template <bool F4, int WS, int RG>
 __global__ __launch_bounds__(kThreads) void k_debug_mfma(SearchDev s, const PairRec* recp,
                                                          const int8_t* qu8, int32_t list, int32_t* ip,
                                                          int32_t* pc, float* est, float* dist,
                                                          float* lb) {
+  constexpr int R = 16 * RG;
   extern __shared__ __attribute__((aligned(16))) int8_t A[];
-  __shared__ RowInfo rows[16];
-  __shared__ uint16_t masks[16][4];
-  __shared__ int32_t rowcnt[16];
+  __shared__ RowInfo rows[R];
+  __shared__ uint16_t masks[R][4];
+  __shared__ int32_t rowcnt[R];
+  __shared__ int32_t rg_live[RG];
   const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
-  if (threadIdx.x < 16) {
+  const int dpa = F4 ? (s.dp + 127) / 128 * 128 : s.dp;
+  if (threadIdx.x < R) {
     RowInfo ri;
     ri.valid = threadIdx.x == 0;
     ri.tau = __builtin_inff();
     ri.seg_base = 0;
     ri.count_slot = -1;
     ri.rec = *recp;
+    ri.t = s.metric != 0 ? pair_terms_ip(ri.rec, hwk, s.pair_pt[0]) : pair_terms(ri.rec, hwk);
     rows[threadIdx.x] = ri;
     rowcnt[threadIdx.x] = 0;
   }
-  for (int idx = threadIdx.x; idx < 16 * s.dp; idx += kThreads) A[idx] = idx < s.dp ? qu8[idx] : (int8_t)0;
+  if (threadIdx.x < RG) rg_live[threadIdx.x] = threadIdx.x == 0;
+  if constexpr (F4) {
+    for (int idx = threadIdx.x * 8; idx < R * dpa; idx += kThreads * 8)
+      *reinterpret_cast<uint64_t*>(A + idx) =
+          idx < dpa && f4_src_dim(idx) < s.dp ? fp8_group(*reinterpret_cast<const uint64_t*>(qu8 + f4_src_dim(idx))) : 0ull;
+  } else {
+    for (int idx = threadIdx.x; idx < R * s.dp; idx += kThreads) A[idx] = idx < s.dp ? qu8[idx] : (int8_t)0;
+  }
   __syncthreads();
   const int64_t lbeg = uniform_i64(s.list_off[list]), lend = uniform_i64(s.list_off[list + 1]);
   const int64_t start = lbeg + (int64_t)blockIdx.x * s.chunk;
   const int64_t end = lend < start + s.chunk ? lend : start + s.chunk;
   if (start >= end) return;
-  mfma_unit<true>(s, start, end, rows, A, masks, rowcnt, hwk, ip, pc, est, dist, lb, lbeg);
+  mfma_unit<true, F4, WS, RG>(s, start, end, rows, rg_live, A, masks, rowcnt, ip, pc, est, dist, lb, lbeg);
 }
 
 // Clears the per-list pair counters (a kernel rather than a memset, so that
@@ -323,23 +505,86 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Kernels per (code width, row groups): W words of 64 bits, compile-time for
+// the common widths (every word read is then issued before the first
+// product) and a runtime width otherwise; RG groups of 16 query rows per unit.
+template <bool F4, bool DBG>
+const void* kernel_for(int W, int rg) {
+#define RBQ_MF(WS_, RG_) (DBG ? (const void*)k_debug_mfma<F4, WS_, RG_> : (const void*)k_scan_mfma<F4, WS_, RG_>)
+  if (rg == 4) {
+    switch (W) {
+      case 12: return RBQ_MF(12, 4);
+      default: return RBQ_MF(0, 4);
+    }
+  }
+  if (rg == 2) {
+    switch (W) {
+      case 12: return RBQ_MF(12, 2);
+      case 15: return RBQ_MF(15, 2);
+      case 16: return RBQ_MF(16, 2);
+      default: return RBQ_MF(0, 2);
+    }
+  }
+  switch (W) {
+    case 1: return RBQ_MF(1, 1);
+    case 2: return RBQ_MF(2, 1);
+    case 3: return RBQ_MF(3, 1);
+    case 4: return RBQ_MF(4, 1);
+    case 8: return RBQ_MF(8, 1);
+    case 12: return RBQ_MF(12, 1);
+    case 15: return RBQ_MF(15, 1);
+    case 16: return RBQ_MF(16, 1);
+    default: return RBQ_MF(0, 1);
+  }
+#undef RBQ_MF
+}
+
+const void* pick_kernel(bool f4, bool dbg, int W, int rg) {
+  if (f4) return dbg ? kernel_for<true, true>(W, rg) : kernel_for<true, false>(W, rg);
+  return dbg ? kernel_for<false, true>(W, rg) : kernel_for<false, false>(W, rg);
+}
+
+int row_bytes(bool f4, int dp) { return f4 ? (dp + 127) / 128 * 128 : dp; }
+
+// LDS for the query tile: at most what a block may hold beyond the kernel's
+// static arrays (8 KiB reserved for them).
+size_t lds_budget() {
+  static size_t lim = 0;
+  if (!lim) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 16384)
+      lim = (size_t)v - 8192;
+    else
+      lim = 56 * 1024;
+  }
+  return lim;
+}
+
+void allow_lds(const void* f, size_t bytes) {
+  (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 }  // namespace
 
 bool mfma_available() { return true; }
 
-int scan_mfma_blocks_per_cu(int dp) {
-  static int nb = 0, for_dp = -1;
-  if (for_dp != dp) {
-    int v = 0;
-    (void)hipFuncSetAttribute((const void*)k_scan_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, (const void*)k_scan_mfma, kThreads, (size_t)16 * dp) !=
-            hipSuccess ||
-        v < 1)
-      v = 1;
-    nb = v;
-    for_dp = dp;
-  }
-  return nb;
+int mfma_row_groups(int dp, bool f4, int want) {
+  const size_t rb = (size_t)row_bytes(f4, dp);
+  // default one group: with more, every wave re-reads RG query tiles from LDS
+  // per 64 codes, and LDS bandwidth, not the MFMA rate, sets the pace
+  int rg = want == 1 || want == 2 || want == 4 ? want : 1;
+  while (rg > 1 && (size_t)16 * rg * rb > lds_budget()) rg >>= 1;
+  return rg;
+}
+
+int scan_mfma_blocks_per_cu(int dp, bool f4, int rg) {
+  const void* f = pick_kernel(f4, false, dp / 64, rg);
+  const size_t bytes = (size_t)16 * rg * row_bytes(f4, dp);
+  allow_lds(f, bytes);
+  int v = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, f, kThreads, bytes) != hipSuccess || v < 1) v = 1;
+  return v;
 }
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
@@ -363,26 +608,25 @@ hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t
   hipLaunchKernelGGL(k_group_count, dim3(g1), dim3(256), 0, st, s);
   hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, st, s);
   hipLaunchKernelGGL(k_group_scatter, dim3(g1), dim3(256), 0, st, s);
-  const size_t shm = (size_t)16 * s.dp;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_scan_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_debug_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-    attr = true;
-  }
-  hipLaunchKernelGGL(k_scan_mfma, dim3(grid), dim3(kThreads), shm, st, s);
-  return hipGetLastError();
+  const bool f4 = s.mfma_f4 != 0;
+  const void* f = pick_kernel(f4, false, s.W, s.mf_rg);
+  const size_t bytes = (size_t)16 * s.mf_rg * row_bytes(f4, s.dp);
+  allow_lds(f, bytes);
+  void* args[] = {(void*)&s};
+  return hipLaunchKernel(f, dim3(grid), dim3(kThreads), args, bytes, st);
 }
 
 hipError_t launch_debug_mfma(const SearchDev& s, const PairRec* rec, const int8_t* qu8,
                              int32_t list, int nchunks, int32_t* ip, int32_t* pc, float* est,
                              float* dist, float* lb, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
-  const size_t shm = (size_t)16 * s.dp;
-  (void)hipFuncSetAttribute((const void*)k_debug_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-  hipLaunchKernelGGL(k_debug_mfma, dim3(nchunks), dim3(kThreads), shm, st, s, rec, qu8, list, ip,
-                     pc, est, dist, lb);
-  return hipGetLastError();
+  const bool f4 = s.mfma_f4 != 0;
+  const void* f = pick_kernel(f4, true, s.W, s.mf_rg);
+  const size_t bytes = (size_t)16 * s.mf_rg * row_bytes(f4, s.dp);
+  allow_lds(f, bytes);
+  void* args[] = {(void*)&s, (void*)&rec, (void*)&qu8, (void*)&list, (void*)&ip, (void*)&pc,
+                  (void*)&est, (void*)&dist, (void*)&lb};
+  return hipLaunchKernel(f, dim3(nchunks), dim3(kThreads), args, bytes, st);
 }
 
 }  // namespace rbq

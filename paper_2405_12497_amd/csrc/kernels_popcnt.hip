@@ -26,6 +26,7 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
   int32_t p[UN];
   bool valid[UN];
   float2 f[UN];
+  float ct[UN];
   int ip[UN], pc[UN];
   const uint64_t* row[UN];
 #pragma unroll
@@ -34,6 +35,13 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
     p[u] = valid[u] ? b0 + 64 * u + lane : start;   // masked lanes read an in-bounds code
     f[u] = s.sfac[p[u]];
     row[u] = code_row(s.codes, p[u], W);
+  }
+  if (s.metric != 0) {   // inner product: the per-code term -<o_r - c, c>
+#pragma unroll
+    for (int u = 0; u < UN; ++u) ct[u] = -s.fip[p[u]];
+  } else {
+#pragma unroll
+    for (int u = 0; u < UN; ++u) ct[u] = code_term_l2(f[u]);
   }
   if constexpr (WS > 0) {
     uint64_t x[UN][WS];
@@ -66,7 +74,7 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
     float dist, lb;
-    estimate(rec, pt, f[u], ip[u], pc[u], dist, lb);
+    estimate(rec, pt, f[u], ct[u], ip[u], pc[u], dist, lb);
     const int32_t off = p[u] - start;
     if constexpr (PHASE == 0) {
       if (valid[u]) {
@@ -107,7 +115,7 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
 template <int WS, int UN, int PHASE, int NPL, typename PL>
 __device__ __forceinline__ int scan_unit(const SearchDev& s, const UnitDesc& w, const PairRec& rec, const PL& pl,
                                          float tau, float hwk) {
-  const PairTerms pt = pair_terms(rec, hwk);
+  const PairTerms pt = s.metric != 0 ? pair_terms_ip(rec, hwk, uniform_f32(s.pair_pt[w.g])) : pair_terms(rec, hwk);
   const int32_t start = (int32_t)w.start, wend = (int32_t)(w.start + w.len);
   int count = 0;
   int32_t b0 = start;

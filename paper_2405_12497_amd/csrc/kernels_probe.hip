@@ -9,35 +9,36 @@ namespace {
 constexpr int kSelThreads = 256;
 constexpr int kSelCap = 2048;   // nprobe handled with the keys in LDS; above: k_select_probe_large
 
-// keys: distances as uint32 (non-negative floats order like their bit patterns).
-// Radix select of the P-th smallest key, then ordered collection of ties.
+// keys: distances as uint32 (non-negative floats order like their bit patterns),
+// read from the distance row in global memory (no LDS copy of the row, so
+// several queries' blocks share a CU). Sampled cut, then the exact radix
+// selection when the cut does not isolate between P and kSelCap keys.
+__device__ __forceinline__ uint32_t probe_key(const float* row, int k) { return __float_as_uint(fmaxf(row[k], 0.f)); }
+
 __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __restrict__ D,
                                                               int nlist, int nprobe,
                                                               const int32_t* __restrict__ nprobe_q,
                                                               int32_t* __restrict__ lists,
                                                               float* __restrict__ dists) {
-  extern __shared__ uint32_t keys[];                    // nlist
   __shared__ uint32_t hist[256];
   __shared__ uint64_t sel[kSelCap];
   __shared__ uint32_t samp[256];
-  __shared__ uint32_t sh_prefix, sh_rank, sh_nless;
+  __shared__ uint32_t sh_prefix, sh_rank, sh_nless, sh_nk;
   __shared__ uint32_t tie_scan[kSelThreads];
-  __shared__ int32_t wcnt[kSelThreads / 64];
   const int64_t q = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
   int P = nprobe;
   if (nprobe_q) P = uniform_i32(min(max(nprobe_q[q], 1), nprobe));
   P = min(P, nlist);
   const float* row = D + q * (int64_t)nlist;
-  for (int k = threadIdx.x; k < nlist; k += blockDim.x) keys[k] = __float_as_uint(fmaxf(row[k], 0.f));
-  __syncthreads();
   // Sampled threshold: sort 256 evenly spaced keys and cut at a sample rank
   // expected to leave about 1.5 P + 32 keys at or below it. If that many keys
   // are kept (and they fit), sorting only them gives the answer; otherwise the
   // exact radix selection below runs.
   if (nlist >= 1024) {
     const int stride = nlist / 256;
-    samp[threadIdx.x] = keys[threadIdx.x * stride];
+    samp[threadIdx.x] = probe_key(row, threadIdx.x * stride);
+    if (threadIdx.x == 0) sh_nk = 0;
     __syncthreads();
     for (int size = 2; size <= 256; size <<= 1)
       for (int st = size >> 1; st > 0; st >>= 1) {
@@ -55,20 +56,28 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __res
       }
     const int sidx = min(255, (int)((1.5f * P + 32.f) * 256.f / (float)nlist) + 1);
     const uint32_t cut = (uint32_t)uniform_i32((int)samp[sidx]);
-    int nk = 0;
-    for (int k0 = 0; k0 < nlist; k0 += kSelThreads) {
-      const int k = k0 + threadIdx.x;
-      const bool keep = k < nlist && keys[k] <= cut;
-      const uint64_t m = __ballot(keep);
-      if (lane == 0) wcnt[wave] = __popcll(m);
-      __syncthreads();
-      int at = nk;
-      for (int w = 0; w < wave; ++w) at += wcnt[w];
-      const int idx = at + __popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
-      if (keep && idx < kSelCap) sel[idx] = ((uint64_t)keys[k] << 32) | (uint32_t)k;
-      nk = uniform_i32(nk + wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3]);
-      __syncthreads();
+    // compaction of the keys <= cut in any order (the sort below orders them):
+    // one LDS atomic per wave and step, four keys per thread in flight
+    constexpr int kU = 4;
+    for (int k0 = 0; k0 < nlist; k0 += kSelThreads * kU) {
+      uint32_t kv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) kv[u] = probe_key(row, min(k0 + u * kSelThreads + (int)threadIdx.x, nlist - 1));
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int k = k0 + u * kSelThreads + threadIdx.x;
+        const bool keep = k < nlist && kv[u] <= cut;
+        const uint64_t m = __ballot(keep);
+        if (m == 0ull) continue;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&sh_nk, (uint32_t)__popcll(m));
+        base = (uint32_t)__shfl((int)base, 0, kWave);
+        const uint32_t idx = base + (uint32_t)__popcll(m & lanemask_lt());
+        if (keep && idx < (uint32_t)kSelCap) sel[idx] = ((uint64_t)kv[u] << 32) | (uint32_t)k;
+      }
     }
+    __syncthreads();
+    const int nk = uniform_i32((int)sh_nk);
     if (nk >= P && nk <= kSelCap) {
       int n2 = 1;
       while (n2 < nk) n2 <<= 1;
@@ -86,6 +95,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __res
       }
       return;
     }
+    __syncthreads();
   }
   if (threadIdx.x == 0) {
     sh_prefix = 0;
@@ -98,7 +108,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __res
     __syncthreads();
     const uint32_t prefix = (uint32_t)uniform_i32((int)sh_prefix);
     for (int k = threadIdx.x; k < nlist; k += blockDim.x) {
-      const uint32_t key = keys[k];
+      const uint32_t key = probe_key(row, k);
       if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
     }
     __syncthreads();
@@ -121,16 +131,17 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __res
   __syncthreads();
   // keys strictly below the threshold (P - need of them), any order
   for (int k = threadIdx.x; k < nlist; k += blockDim.x) {
-    if (keys[k] < thr) {
+    const uint32_t key = probe_key(row, k);
+    if (key < thr) {
       const uint32_t at = atomicAdd(&sh_nless, 1u);
-      sel[at] = ((uint64_t)keys[k] << 32) | (uint32_t)k;
+      sel[at] = ((uint64_t)key << 32) | (uint32_t)k;
     }
   }
   // ties: the first `need` in list-id order; thread t scans a contiguous range
   const int per = (nlist + blockDim.x - 1) / blockDim.x;
   const int kb = threadIdx.x * per, ke = min(nlist, kb + per);
   uint32_t mine = 0;
-  for (int k = kb; k < ke; ++k) mine += (keys[k] == thr);
+  for (int k = kb; k < ke; ++k) mine += (probe_key(row, k) == thr);
   tie_scan[threadIdx.x] = mine;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -145,7 +156,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_probe(const float* __res
   const uint32_t nless = (uint32_t)P - need;
   uint32_t rank = tie_scan[threadIdx.x];
   for (int k = kb; k < ke && rank < need; ++k) {
-    if (keys[k] == thr) {
+    if (probe_key(row, k) == thr) {
       sel[nless + rank] = ((uint64_t)thr << 32) | (uint32_t)k;
       ++rank;
     }
@@ -592,14 +603,7 @@ hipError_t launch_select_probe(const float* D, const float* gmin, int64_t nq, in
                        dim3(kSelThreads), 0, st, D, nq, nlist, nprobe, nprobe_q, lists, dists);
     return hipGetLastError();
   }
-  const size_t shm = (size_t)nlist * sizeof(uint32_t);
-  static bool attr_done = false;
-  if (!attr_done) {
-    (void)hipFuncSetAttribute((const void*)k_select_probe, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        96 * 1024);
-    attr_done = true;
-  }
-  hipLaunchKernelGGL(k_select_probe, dim3((unsigned)nq), dim3(kSelThreads), shm, st, D, nlist,
+  hipLaunchKernelGGL(k_select_probe, dim3((unsigned)nq), dim3(kSelThreads), 0, st, D, nlist,
                      nprobe, nprobe_q, lists, dists);
   return hipGetLastError();
 }

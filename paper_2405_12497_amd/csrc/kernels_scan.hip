@@ -64,7 +64,7 @@ constexpr int kWaves = kThreads / kWave;
 // estimator constants. One wave handles PPW pairs with the residual held in
 // registers (WS >= W words of 64 coordinates, compile-time bound), so each
 // coordinate is loaded once.
-template <int WS, int PPW>
+template <int WS, int PPW, int NPL>
 __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
   const int lane = lane_id();
   const int W = s.W;
@@ -86,6 +86,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     pl_raw[j] = s.probe[g];
     npq_raw[j] = s.nprobe_q ? s.nprobe_q[qj[j]] : s.nprobe;
   }
+  bool any = false;
 #pragma unroll
   for (int j = 0; j < PPW; ++j) {
     const int64_t g = g0 + j;
@@ -93,6 +94,20 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     const int P = min(max(npq_raw[j], 1), s.nprobe);
     list[j] = uniform_i32((g < npairs && r < P) ? pl_raw[j] : -1);
     act[j] = list[j] >= 0;
+    any = any || act[j];
+  }
+  if (!any) {   // probe slots past the query's nprobe: empty records, no coordinate reads
+    if (lane < PPW && g0 + lane < npairs) {
+      PairRec rec;
+      rec.k1 = rec.k2 = rec.k0 = rec.b = rec.vl = rec.delta = 0.f;
+      rec.sq = 0;
+      rec.list = -1;
+      s.pairs[g0 + lane] = rec;
+    }
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < PPW; ++j) {
     qq[j] = 0.f;
     const float* qrot = s.qrot + qj[j] * s.dp;
     const float* crot = s.crot + (int64_t)max(list[j], 0) * s.dp;
@@ -163,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     const float scale = live ? (float)s.qmax / range : 0.f;
     const uint64_t qid = (uint64_t)(s.qid_base + q);
     int sq = 0;
-    const int npl = s.npl;
+    const int npl = NPL > 0 ? NPL : s.npl;   // bit planes (B_q), compile-time when given
     uint64_t* pl = s.planes + g * npl * W;
     int8_t* q8 = s.qu8 ? s.qu8 + g * s.dp : nullptr;
 #pragma unroll
@@ -175,13 +190,31 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
         const int qu = min(s.qmax, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
         sq += qu;
         if (q8) q8[i] = (int8_t)(qu - s.qoff);
-        for (int jb = 0; jb < npl; ++jb) {
-          const uint64_t w = __ballot((qu >> jb) & 1);
-          if (lane == 0) pl[jb * W + t] = w;
+        if constexpr (NPL > 0) {   // all ballots first, then one branch for the stores
+          uint64_t w[NPL > 0 ? NPL : 1];
+#pragma unroll
+          for (int jb = 0; jb < NPL; ++jb) w[jb] = __ballot((qu >> jb) & 1);
+          if (lane == 0) {
+#pragma unroll
+            for (int jb = 0; jb < NPL; ++jb) pl[jb * W + t] = w[jb];
+          }
+        } else {
+          for (int jb = 0; jb < npl; ++jb) {
+            const uint64_t w = __ballot((qu >> jb) & 1);
+            if (lane == 0) pl[jb * W + t] = w;
+          }
         }
       }
     }
     sq = wave_sum_i(sq);
+    if (s.metric != 0) {   // inner product: the pair's constant M_q - <q_r, c> from the raw vectors
+      const float* qr = s.q + q * s.dim;
+      const float* c = s.cent + (int64_t)list[j] * s.dim;
+      float acc = 0.f;
+      for (int i = lane; i < s.dim; i += kWave) acc = fmaf(qr[i], c[i], acc);
+      const float gdot = wave_sum(acc);
+      if (lane == 0) s.pair_pt[g] = s.q_m[q] - gdot;
+    }
     if (lane == 0) {
       double vl, delta;
       pair_scalars(rmin, range, b, s.qmax, vl, delta);
@@ -308,6 +341,14 @@ __device__ __forceinline__ void prep_q_body(const SearchDev& s, int64_t blk) {
     }
   }
   sq = row_sum_i32(sq);
+  if (s.metric != 0) {   // inner product: the pair's constant M_q - <q_r, c> (every lane takes part)
+    const float* qr = s.q + q * s.dim;
+    const float* c = s.cent + (int64_t)max(list, 0) * s.dim;
+    float acc = 0.f;
+    for (int i = l; i < s.dim; i += 16) acc = fmaf(qr[i], c[i], acc);
+    acc = row_sum_f32(acc);
+    if (act && l == 0) s.pair_pt[g] = s.q_m[q] - acc;
+  }
   if (act && l < 4 * W) s.planes[g * 4 * W + l] = myword;
   if (valid && l == 0) {
     PairRec rec;
@@ -711,9 +752,28 @@ __global__ __launch_bounds__(kThreads) void k_prep_units(SearchDev s, int64_t nu
 // vectors get equal bits.
 constexpr int kLpc = 8;
 
-template <int NC, int U = 1>
+// One column's contribution: (a - b)^2 for squared L2, a b for the inner
+// product (whose searched "distance" is M_q minus the sum, clamped at 0).
+template <bool IP>
+__device__ __forceinline__ void acc1(float& acc, float a, float b) {
+  if constexpr (IP) {
+    acc = fmaf(a, b, acc);
+  } else {
+    const float d = a - b;
+    acc = fmaf(d, d, acc);
+  }
+}
+template <bool IP>
+__device__ __forceinline__ void acc4(float& acc, const float4& a, const float4& b) {
+  acc1<IP>(acc, a.x, b.x);
+  acc1<IP>(acc, a.y, b.y);
+  acc1<IP>(acc, a.z, b.z);
+  acc1<IP>(acc, a.w, b.w);
+}
+
+template <int NC, int U = 1, bool IP = false>
 __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const int32_t (&pos)[NC], int dim,
-                                            const float* __restrict__ qv, int sub, float (&out)[NC]) {
+                                            const float* __restrict__ qv, int sub, float (&out)[NC], float mq = 0.f) {
   float acc[NC];
   int64_t base[NC];
 #pragma unroll
@@ -731,11 +791,7 @@ __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const
         for (int j = 0; j < NC; ++j) a[j] = reinterpret_cast<const float4*>(raw + base[j])[i];
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const float dx = a[j].x - b.x, dy = a[j].y - b.y, dz = a[j].z - b.z, dw = a[j].w - b.w;
-          acc[j] = fmaf(dx, dx, acc[j]);
-          acc[j] = fmaf(dy, dy, acc[j]);
-          acc[j] = fmaf(dz, dz, acc[j]);
-          acc[j] = fmaf(dw, dw, acc[j]);
+          acc4<IP>(acc[j], a[j], b);
         }
       }
     } else {
@@ -743,8 +799,7 @@ __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const
         const float b = qv[i];
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const float d = raw[base[j] + i] - b;
-          acc[j] = fmaf(d, d, acc[j]);
+          acc1<IP>(acc[j], raw[base[j] + i], b);
         }
       }
     }
@@ -765,12 +820,8 @@ __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const
         const bool live = i0 + u * kLpc + sub < n4;
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const float4 x = live ? a[u][j] : b[u];
-          const float dx = x.x - b[u].x, dy = x.y - b[u].y, dz = x.z - b[u].z, dw = x.w - b[u].w;
-          acc[j] = fmaf(dx, dx, acc[j]);
-          acc[j] = fmaf(dy, dy, acc[j]);
-          acc[j] = fmaf(dz, dz, acc[j]);
-          acc[j] = fmaf(dw, dw, acc[j]);
+          const float4 z = {0.f, 0.f, 0.f, 0.f};
+          acc4<IP>(acc[j], live ? a[u][j] : (IP ? z : b[u]), b[u]);
         }
       }
     }
@@ -789,8 +840,7 @@ __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const
         const bool live = i0 + u * kLpc + sub < dim;
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const float d = (live ? a[u][j] : b[u]) - b[u];
-          acc[j] = fmaf(d, d, acc[j]);
+          acc1<IP>(acc[j], live ? a[u][j] : (IP ? 0.f : b[u]), b[u]);
         }
       }
     }
@@ -801,7 +851,7 @@ __device__ __forceinline__ void group_dists(const float* __restrict__ raw, const
     v += __shfl_xor(v, 4, kWave);
     v += __shfl_xor(v, 2, kWave);
     v += __shfl_xor(v, 1, kWave);
-    out[j] = v;
+    out[j] = IP ? fmaxf(mq - v, 0.f) : v;
   }
 }
 
@@ -889,7 +939,11 @@ __global__ __launch_bounds__(kThreads) void k_tau(SearchDev s, int W, uint64_t* 
 #pragma unroll
       for (int j = 0; j < NC; ++j) id[j] = id_lo32(s.ids, max(pos[j], 0));
       float d[NC];
-      group_dists<NC, DS::kU>(s.raw, pos, s.dim, qv, sub, d);
+      if (s.metric != 0) {
+        group_dists<NC, DS::kU, true>(s.raw, pos, s.dim, qv, sub, d, uniform_f32(s.q_m[q]));
+      } else {
+        group_dists<NC, DS::kU, false>(s.raw, pos, s.dim, qv, sub, d);
+      }
 #pragma unroll
       for (int j = 0; j < NC; ++j) keep_loaded(id[j]);
       wave_lds_sync();   // every lane has read its sel entries
@@ -952,6 +1006,13 @@ __global__ __launch_bounds__(kThreads) void k_tau_merge(SearchDev s, const uint6
     s.seedk[q * s.k + i] = e;
   }
   if (lane == 0) s.tau[q] = (m >= s.k) ? __uint_as_float((uint32_t)(sel[s.k - 1] >> 32)) : __builtin_inff();
+}
+
+// The reported value of a result: the exact squared distance (+inf pads), or
+// for the inner-product metrics the inner product M_q - d (-inf pads).
+__device__ __forceinline__ float out_value(const SearchDev& s, float mq, bool live, float d) {
+  if (s.metric != 0) return live ? mq - d : -__builtin_inff();
+  return live ? d : __builtin_inff();
 }
 
 // ------------------------------------------------------------------ finalize (S7)
@@ -1089,7 +1150,11 @@ __global__ __launch_bounds__(kThreads, WIDE ? 3 : 4) void k_finalize(SearchDev s
 #pragma unroll
       for (int j = 0; j < NC; ++j) id[j] = id_lo32(s.ids, max(pos[j], 0));
       float d[NC];
-      group_dists<NC, DS::kU>(s.raw, pos, s.dim, qv, sub, d);
+      if (s.metric != 0) {
+        group_dists<NC, DS::kU, true>(s.raw, pos, s.dim, qv, sub, d, uniform_f32(s.q_m[q]));
+      } else {
+        group_dists<NC, DS::kU, false>(s.raw, pos, s.dim, qv, sub, d);
+      }
 #pragma unroll
       for (int j = 0; j < NC; ++j) keep_loaded(id[j]);
       wave_lds_sync();   // every lane has read its entries
@@ -1209,11 +1274,12 @@ __global__ __launch_bounds__(kThreads, WIDE ? 3 : 4) void k_finalize(SearchDev s
   }
   process_window();
   if (W == 1) {
+    const float mq = s.metric != 0 ? s.q_m[q] : 0.f;
     for (int i = lane; i < K; i += kWave) {
       const uint64_t v = top[i];
       const bool live = i < cnt;
       s.out_ids[q * K + i] = live ? (int64_t)(uint32_t)(v & 0xffffffffu) : (int64_t)-1;
-      s.out_d[q * K + i] = live ? __uint_as_float((uint32_t)(v >> 32)) : __builtin_inff();
+      s.out_d[q * K + i] = out_value(s, mq, live, __uint_as_float((uint32_t)(v >> 32)));
     }
     if (lane == 0) {
       s.q_rerank[q] = reranked - seeds;   // the seeds' distances were computed by the bootstrap rerank
@@ -1236,6 +1302,7 @@ __device__ __forceinline__ void fin_merge_out(const SearchDev& s, int64_t q, int
                                               const int32_t* __restrict__ pst) {
   const int lane = lane_id();
   const int K = s.k;
+  const float mq = s.metric != 0 ? s.q_m[q] : 0.f;
   int out = 0;
   for (int i0 = 0; i0 < n && out < K; i0 += kWave) {
     const int i = i0 + lane;
@@ -1245,13 +1312,13 @@ __device__ __forceinline__ void fin_merge_out(const SearchDev& s, int64_t q, int
     const int at = out + __popcll(b & lanemask_lt());
     if (keep && at < K) {
       s.out_ids[q * K + at] = (int64_t)(uint32_t)(x & 0xffffffffu);
-      s.out_d[q * K + at] = __uint_as_float((uint32_t)(x >> 32));
+      s.out_d[q * K + at] = out_value(s, mq, true, __uint_as_float((uint32_t)(x >> 32)));
     }
     out += __popcll(b);
   }
   for (int i = min(out, K) + lane; i < K; i += kWave) {
     s.out_ids[q * K + i] = -1;
-    s.out_d[q * K + i] = __builtin_inff();
+    s.out_d[q * K + i] = out_value(s, mq, false, 0.f);
   }
   int rer = 0, cand = 0;
   for (int w = lane; w < W; w += kWave) {
@@ -1300,10 +1367,11 @@ __global__ __launch_bounds__(kMergeThreads) void k_fin_merge_block(SearchDev s, 
 
 // ------------------------------------------------------------------ debug
 __global__ void k_debug_pack(const uint8_t* __restrict__ qu, int dp, int W, int npl, int qoff, float b, float vl,
-                             float delta, PairRec* rec, uint64_t* planes, int8_t* qu8,
+                             float delta, float pt, PairRec* rec, uint64_t* planes, int8_t* qu8, float* pair_pt,
                              int32_t list, double rd, double ird) {
   // one wave
   const int lane = lane_id();
+  if (lane == 0 && pair_pt) pair_pt[0] = pt;
   int sq = 0;
   for (int t = 0; t < W; ++t) {
     const int i = t * kWave + lane;
@@ -1359,26 +1427,39 @@ hipError_t launch_prep(const SearchDev& s, bool units, hipStream_t st) {
   const int64_t ublocks = units ? (s.nq * nrb + kWaves - 1) / kWaves : 0;
   if (s.W <= 0 || s.W > 64) return hipErrorInvalidValue;
   if (s.npl == 8 && s.W <= 4) {   // the quarter-wave form holds 4 W plane words per row: B_q <= 4 only
-    hipLaunchKernelGGL((k_prep_reg<4, 2>), grid(2), dim3(kThreads), 0, st, s);
+    hipLaunchKernelGGL((k_prep_reg<4, 2, 8>), grid(2), dim3(kThreads), 0, st, s);
     if (units) hipLaunchKernelGGL(k_units, dim3((unsigned)ublocks), dim3(kThreads), 0, st, s);
     return hipGetLastError();
   }
+  // wide rows: one pair per wave (two up to W = 8), the register bound WS exact
+  // for D = 768 and 960, and B_q = 4 planes compile-time
+  const bool p4 = s.npl == 4;
+#define RBQ_PREP(WS_, PPW_)                                                                          \
+  do {                                                                                              \
+    if (p4)                                                                                         \
+      hipLaunchKernelGGL((k_prep_reg<WS_, PPW_, 4>), grid(PPW_), dim3(kThreads), 0, st, s);         \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_prep_reg<WS_, PPW_, 0>), grid(PPW_), dim3(kThreads), 0, st, s);         \
+  } while (0)
   switch (s.W) {
     case 1: launch_prep_q<1>(s, ublocks, qblocks, st); return hipGetLastError();
     case 2: launch_prep_q<2>(s, ublocks, qblocks, st); return hipGetLastError();
     case 3: launch_prep_q<3>(s, ublocks, qblocks, st); return hipGetLastError();
     case 4: launch_prep_q<4>(s, ublocks, qblocks, st); return hipGetLastError();
+    case 12: RBQ_PREP(12, 1); break;
+    case 15: RBQ_PREP(15, 1); break;
     default:
       if (s.W <= 8) {
-        hipLaunchKernelGGL((k_prep_reg<8, 2>), grid(2), dim3(kThreads), 0, st, s);
+        RBQ_PREP(8, 2);
       } else if (s.W <= 16) {
-        hipLaunchKernelGGL((k_prep_reg<16, 1>), grid(1), dim3(kThreads), 0, st, s);
+        RBQ_PREP(16, 1);
       } else if (s.W <= 32) {
-        hipLaunchKernelGGL((k_prep_reg<32, 1>), grid(1), dim3(kThreads), 0, st, s);
+        RBQ_PREP(32, 1);
       } else {
-        hipLaunchKernelGGL((k_prep_reg<64, 1>), grid(1), dim3(kThreads), 0, st, s);
+        RBQ_PREP(64, 1);
       }
   }
+#undef RBQ_PREP
   if (units) hipLaunchKernelGGL(k_units, dim3((unsigned)ublocks), dim3(kThreads), 0, st, s);
   return hipGetLastError();
 }
@@ -1456,11 +1537,11 @@ hipError_t launch_finalize(const SearchDev& s, hipStream_t st) {
 }
 
 hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, int npl, int qoff, float b, float vl, float delta,
-                             PairRec* rec, uint64_t* planes, int8_t* qu8, int32_t list,
+                             float pt, PairRec* rec, uint64_t* planes, int8_t* qu8, float* pair_pt, int32_t list,
                              hipStream_t st) {
   const double rd = std::sqrt((double)dp);
-  hipLaunchKernelGGL(k_debug_pack, dim3(1), dim3(kWave), 0, st, qu, dp, W, npl, qoff, b, vl, delta, rec,
-                     planes, qu8, list, rd, 1.0 / rd);
+  hipLaunchKernelGGL(k_debug_pack, dim3(1), dim3(kWave), 0, st, qu, dp, W, npl, qoff, b, vl, delta, pt, rec,
+                     planes, qu8, pair_pt, list, rd, 1.0 / rd);
   return hipGetLastError();
 }
 
@@ -1475,7 +1556,7 @@ hipError_t launch_debug_scan(const SearchDev& s, const PairRec* rec, const uint6
     n = off[1] - off[0];
   }
   if (n == 0) return hipSuccess;
-  if (kernel == 2)
+  if (kernel == 2 || kernel == 3)   // int8 or FP8 x FP4 (s.mfma_f4)
     return launch_debug_mfma(s, rec, qu8, list, (n + s.chunk - 1) / s.chunk, ip, pc, est, dist, lb, st);
   // the production popcount scan, phase 2, over the unit table the caller
   // prepared in s.units1 (s.off_p1[s.nq] units of pair 0)

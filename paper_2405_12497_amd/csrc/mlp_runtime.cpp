@@ -419,8 +419,11 @@ extern "C" rbq_status rbq_nprobe_labels(rbq_index* idx, const float* queries, in
   }
   for (int64_t q0 = 0; q0 < nq; q0 += rows) {
     const int64_t m = std::min(rows, nq - q0);
-    HIPCHK(launch_centroid_dist(queries + q0 * idx->dim, m, idx->dim, (const float*)idx->d_centT.p,
-                                (const float*)idx->d_cnorm.p, idx->nlist, (float*)idx->ws.cd.p, nullptr, st));
+    const float* qs = queries + q0 * idx->dim;
+    rs = prepare_queries(idx, qs, m, st, &qs);   // the cosine metric ranks lists for unit queries
+    if (rs != RBQ_OK) return rs;
+    HIPCHK(launch_centroid_dist(qs, m, idx->dim, (const float*)idx->d_centT.p, idx->probe_cnorm(), idx->nlist,
+                                (float*)idx->ws.cd.p, nullptr, st));
     HIPCHK(launch_probe_need((const float*)idx->ws.cd.p, m, idx->nlist, nn_ids + q0 * k, k,
                              (const int32_t*)idx->d_id2list.p, idx->n, nd + q0, st));
   }

@@ -265,6 +265,12 @@ struct SearchDev {
   int qmax;                 // 2^B_q - 1: largest quantised query value (Sec. 3.3.1)
   int npl;                  // bit planes stored per pair: 4 (B_q <= 4) or 8
   int qoff;                 // int8 copy of q_u holds q_u - qoff (128 for B_q = 8, else 0)
+  int metric;               // 0: squared L2; 1: inner product (cosine runs as IP on unit vectors)
+  int mfma_f4;              // batched scan on FP8 x FP4 scaled MFMA instead of int8
+  int mf_rg;                // batched scan: groups of 16 query rows per work unit (1, 2 or 4)
+  const float* fip;         // inner product: per code <o_r - c, c>
+  float* pair_pt;           // inner product: per pair M_q - <q_r, c>
+  float* q_m;               // inner product: per query M_q = ||q_r|| max ||o_r|| (1 + 1e-5)
   double rd, ird;            // sqrt(dp), 1 / sqrt(dp)
   float eps0;
   uint64_t seed;
@@ -332,7 +338,10 @@ hipError_t launch_plan(const SearchDev& s, hipStream_t st);
 // descriptors, which need launch_plan's results.
 hipError_t launch_prep(const SearchDev& s, bool units, hipStream_t st);
 int scan_popcnt_blocks_per_cu(int W, int npl);
-int scan_mfma_blocks_per_cu(int dp);
+// Row groups of the batched scan for code length dp: `want` (1, 2 or 4; other
+// values mean 1), lowered until the query tile fits a block's LDS.
+int mfma_row_groups(int dp, bool f4, int want);
+int scan_mfma_blocks_per_cu(int dp, bool f4, int rg);
 // phase 0: bootstrap units, 1: main units with the bound filter, 2: parity
 // export of the main-phase table (s.dbg_*).
 hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st);
@@ -342,7 +351,7 @@ hipError_t launch_finalize(const SearchDev& s, hipStream_t st);
 
 // debug: list scan with a given quantised query
 hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, int npl, int qoff, float b, float vl, float delta,
-                             PairRec* rec, uint64_t* planes, int8_t* qu8, int32_t list,
+                             float pt, PairRec* rec, uint64_t* planes, int8_t* qu8, float* pair_pt, int32_t list,
                              hipStream_t st);
 // k-means building blocks (kernels_index.hip): max |x| as float bits
 // (atomicMax into *out, which the caller zeroes), per-row argmin over a
@@ -355,6 +364,14 @@ hipError_t launch_fixed_sums(const float* x, const int32_t* lab, int64_t rows, i
                              unsigned long long* sums, unsigned int* cnt, hipStream_t st);
 hipError_t launch_update_centroids(const unsigned long long* sums, const unsigned int* cnt, int nlist, int dim,
                                    double inv_scale, float* cent, float* centT, float* cnorm, hipStream_t st);
+// Inner-product support (kernels_index.hip): per code fip[p] = <o_r - c, c>
+// and the largest squared norm (float bits, atomicMax into *r2max, zeroed by
+// the caller) of raw vectors in list order; rows normalised to unit length in
+// place (zero rows stay zero); per query q_m[i] = ||q_i|| sqrt(r2max) (1 + 1e-5).
+hipError_t launch_ip_terms(const float* raw, const float* cent, const int32_t* list_of, int64_t n, int dim,
+                           float* fip, uint32_t* r2max, hipStream_t st);
+hipError_t launch_normalize_rows(const float* x, int64_t n, int dim, float* y, hipStream_t st);
+hipError_t launch_query_m(const float* q, int64_t nq, int dim, float rmax, float* q_m, hipStream_t st);
 // x[i] ^= v for n bytes (the int8 copy of q_u back to 0 .. 2^B_q - 1)
 hipError_t launch_xor_u8(uint8_t* x, int64_t n, uint8_t v, hipStream_t st);
 hipError_t launch_debug_mfma(const SearchDev& s, const PairRec* rec, const int8_t* qu8,

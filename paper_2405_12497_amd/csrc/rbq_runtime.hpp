@@ -52,6 +52,7 @@ hipError_t launch_tau_split(const SearchDev& s, int W, uint64_t* tpart, hipStrea
 // Rerank waves for a requested count (0: finalize_split's choice), clamped to
 // 1 .. min(64, kFinMergeCap / k).
 constexpr int kFinMergeCap = 4096;   // keys of a query's split-rerank merge (W k)
+constexpr int kFinSplitMaxWaves = 64;   // most rerank waves per query
 inline int fin_waves(int requested, int64_t nq, int k) {
   if (requested <= 0) return finalize_split(nq, k);
   const int cap = std::max(1, std::min(64, kFinMergeCap / std::max(k, 1)));
@@ -70,13 +71,14 @@ struct TuneEntry {
   int chunk = kDefaultChunk;
   int kernel = RBQ_SCAN_POPCNT;
   int fin_w = 0;
+  int mf_rg = 0;    // batched scan: 16-row query groups per work unit (0: one)
   float ms = 0.f;   // measured time of the trial batch
 };
 
 // One captured search (graph replay of rbq_search with use_graph = 1).
 struct GraphEntry {
   int64_t nqb = 0;        // rows (rounded batch size)
-  int k = 0, nprobe = 0, kernel = 0, chunk = 0;
+  int k = 0, nprobe = 0, kernel = 0, chunk = 0, mf_rg = 0;
   bool learned = false, per_query = false;
   int64_t qid_base = 0;
   int fin_w = 1;          // rerank waves per query
@@ -107,6 +109,7 @@ struct Workspace {
   DBuf q_nch, q_p0, q_n0, q_ncode, offs, counters, seg, seg_count, p0buf, tau, seedk;
   DBuf chunk_qcode;   // chunk (query order) -> first query-code index
   DBuf q_boot, q_rerank, q_cand, nprobe_q, q_fb, feats, tmp;
+  DBuf pair_pt, q_m, qn;    // inner-product metrics: pair constants, M_q, normalised queries (cosine)
   DBuf mf_cnt, mf_fill, mf_pair_off, mf_unit_off, mf_pairs, units0, units1;
   DBuf fin_part, fin_pst;   // split rerank of small batches: partial top-k lists, statistics
   DBuf tau_part;            // split bootstrap rerank: exact keys, min(256, 4k) per query
@@ -160,6 +163,12 @@ struct rbq_index {
   rbq::DBuf d_sfac;   // scan factors per code (see estimate), derived from d_fac
   rbq::DBuf d_P32, d_Phi, d_Plo;
   rbq::DBuf d_id2list;   // id -> list (built on first use by rbq_nprobe_labels)
+  // inner-product metrics: per code <o_r - c, c>, the centroid norms the probe
+  // GEMM uses (all max ||c||^2, so its ||q||^2 + . - 2 <q, c> ranks by <q, c>),
+  // and max ||o_r||
+  rbq::DBuf d_fip, d_cnorm_probe;
+  float rmax = 0.f;
+  const float* probe_cnorm() const { return (const float*)(prm.metric != RBQ_METRIC_L2 ? d_cnorm_probe.p : d_cnorm.p); }
 
   rbq::Workspace ws;
   rbq::MlpState mlp;
@@ -198,6 +207,12 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
                    const int32_t* nprobe_q, int64_t qid_base, bool mfma, int64_t* out_ids,
                    float* out_d);
 rbq_status scan_factors(rbq_index* idx, hipStream_t st);
+// Inner-product metrics: per code <o_r - c, c> and max ||o_r|| from the raw
+// vectors in list order (list_of: device, list of each position).
+rbq_status ip_factors(rbq_index* idx, const int32_t* list_of, hipStream_t st);
+// The queries a search works on: normalised into the workspace for the cosine
+// metric, and M_q computed for the inner-product metrics (workspace sized).
+rbq_status prepare_queries(rbq_index* idx, const float* queries, int64_t nq, hipStream_t st, const float** out);
 rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
                  const int32_t* nprobe_q, hipStream_t st);
 // One search on `st`. `learned`: per-query nprobe from the model (the caller
@@ -206,6 +221,6 @@ rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
 rbq_status search_locked(rbq_index* idx, const float* queries, int64_t nq, rbq_search_opts o, int64_t* out_ids,
                          float* out_dists, rbq_search_stats* stats, hipStream_t st, const TuneEntry* force);
 rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& opts,
-                      int scan_kernel, int chunk, bool learned, int64_t* out_ids, float* out_d,
+                      int scan_kernel, int chunk, int mf_rg, bool learned, int64_t* out_ids, float* out_d,
                       hipStream_t st, const int32_t** used_npq, int* used_stride);
 }  // namespace rbq

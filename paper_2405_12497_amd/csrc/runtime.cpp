@@ -226,6 +226,7 @@ rbq_status check_params(const rbq_params* p) {
   if (!(p->eps0 >= 0.f) || !std::isfinite(p->eps0)) return fail(RBQ_EINVAL, "eps0 must be finite and >= 0");
   if (p->rot_precision != RBQ_ROT_FP32 && p->rot_precision != RBQ_ROT_BF16X3)
     return fail(RBQ_EINVAL, "unknown rot_precision %d", p->rot_precision);
+  if (p->metric < RBQ_METRIC_L2 || p->metric > RBQ_METRIC_COSINE) return fail(RBQ_EINVAL, "unknown metric %d", p->metric);
   return RBQ_OK;
 }
 
@@ -250,11 +251,11 @@ rbq_index::~rbq_index() {
 
 std::vector<DBuf*> rbq_index::all_buffers() {
   return {&d_codes, &d_fac, &d_sfac, &d_raw, &d_ids, &d_list_off, &d_cent, &d_centT, &d_cnorm, &d_crot,
-          &d_P32, &d_Phi, &d_Plo, &d_id2list, &ws.qrot, &ws.cd, &ws.cgmin, &ws.probe, &ws.probe_d, &ws.pairs,
+          &d_P32, &d_Phi, &d_Plo, &d_id2list, &d_fip, &d_cnorm_probe, &ws.qrot, &ws.cd, &ws.cgmin, &ws.probe, &ws.probe_d, &ws.pairs,
           &ws.planes, &ws.qu8, &ws.pair_choff, &ws.pair_codeoff, &ws.q_nch, &ws.q_p0, &ws.q_n0,
           &ws.q_ncode, &ws.offs, &ws.counters, &ws.seg, &ws.seg_count, &ws.p0buf, &ws.tau,
           &ws.chunk_qcode,
-          &ws.seedk, &ws.q_boot, &ws.q_rerank, &ws.q_cand, &ws.nprobe_q, &ws.q_fb, &ws.feats, &ws.tmp,
+          &ws.seedk, &ws.q_boot, &ws.q_rerank, &ws.q_cand, &ws.pair_pt, &ws.q_m, &ws.qn, &ws.nprobe_q, &ws.q_fb, &ws.feats, &ws.tmp,
           &ws.mf_cnt, &ws.mf_fill, &ws.mf_pair_off, &ws.mf_unit_off, &ws.mf_pairs, &ws.units0,
           &ws.units1, &ws.fin_part, &ws.fin_pst, &ws.tau_part,
           &mlp.w32, &mlp.wbf, &mlp.wfrag, &mlp.grad, &mlp.m, &mlp.v, &mlp.act};
@@ -382,6 +383,13 @@ rbq_status upload_model(rbq_index* idx, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(idx->d_cent.p, idx->h_cent.data(), (size_t)L * D * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(idx->d_centT.p, ct.data(), ct.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(idx->d_cnorm.p, cn.data(), cn.size() * 4, hipMemcpyHostToDevice, st));
+  if (idx->prm.metric != RBQ_METRIC_L2) {   // the probe ranks by <q, c>: every centroid norm set to the largest
+    const float cmax2 = *std::max_element(cn.begin(), cn.end());
+    std::vector<float> cp(L, cmax2);
+    HIPCHK(idx->d_cnorm_probe.ensure((size_t)L * 4));
+    HIPCHK(hipMemcpyAsync(idx->d_cnorm_probe.p, cp.data(), cp.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   // P^T c_k in FP64 on the device, stored as FP32
   TmpBuf p64;
   HIPCHK(p64.ensure((size_t)D * dp * 8));
@@ -424,7 +432,7 @@ void account_bytes(rbq_index* idx) {
   int64_t b = 0;
   for (DBuf* d : {&idx->d_codes, &idx->d_fac, &idx->d_sfac, &idx->d_raw, &idx->d_ids, &idx->d_list_off,
                   &idx->d_cent, &idx->d_centT, &idx->d_cnorm, &idx->d_crot, &idx->d_P32,
-                  &idx->d_Phi, &idx->d_Plo})
+                  &idx->d_Phi, &idx->d_Plo, &idx->d_fip, &idx->d_cnorm_probe})
     b += (int64_t)d->cap;
   idx->device_bytes = b;
 }
@@ -514,6 +522,8 @@ rbq_status build_impl(rbq_index* idx, const float* data, int64_t n, const std::v
                        hipMemcpyHostToDevice));
     }
   }
+  if (idx->prm.metric == RBQ_METRIC_COSINE)   // cosine: the index holds unit vectors
+    HIPCHK(launch_normalize_rows((const float*)idx->d_raw.p, n, D, (float*)idx->d_raw.p, st));
   // rotate residuals and encode, in blocks of rows
   {
     const int dp = idx->dp;
@@ -532,6 +542,8 @@ rbq_status build_impl(rbq_index* idx, const float* data, int64_t n, const std::v
     HIPCHK(hipStreamSynchronize(st));
   }
   rs = scan_factors(idx, st);
+  if (rs != RBQ_OK) return rs;
+  rs = ip_factors(idx, (const int32_t*)listof.p, st);
   if (rs != RBQ_OK) return rs;
   account_bytes(idx);
   idx->built = true;
@@ -656,6 +668,11 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.q_boot.ensure((size_t)nq * 4));
   HIPCHK(w.q_rerank.ensure((size_t)nq * 4));
   HIPCHK(w.q_cand.ensure((size_t)nq * 4));
+  if (idx->prm.metric != RBQ_METRIC_L2) {
+    HIPCHK(w.pair_pt.ensure((size_t)np * 4));
+    HIPCHK(w.q_m.ensure((size_t)nq * 4));
+    if (idx->prm.metric == RBQ_METRIC_COSINE) HIPCHK(w.qn.ensure((size_t)nq * idx->dim * 4));
+  }
   if (fin_w > 1) {
     HIPCHK(w.fin_part.ensure((size_t)nq * fin_w * k * 8));
     HIPCHK(w.fin_pst.ensure((size_t)nq * fin_w * 2 * 4));
@@ -689,6 +706,10 @@ SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
   s.qmax = (1 << idx->prm.bq) - 1;
   s.npl = idx->prm.bq <= 4 ? 4 : 8;
   s.qoff = idx->prm.bq == 8 ? 128 : 0;
+  s.metric = idx->prm.metric != RBQ_METRIC_L2 ? 1 : 0;
+  s.fip = (const float*)idx->d_fip.p;
+  s.pair_pt = (float*)w.pair_pt.p;
+  s.q_m = (float*)w.q_m.p;
   s.eps0 = idx->prm.eps0;
   s.seed = idx->prm.seed;
   s.q = queries;
@@ -749,19 +770,52 @@ rbq_status scan_factors(rbq_index* idx, hipStream_t st) {
   return RBQ_OK;
 }
 
+rbq_status ip_factors(rbq_index* idx, const int32_t* list_of, hipStream_t st) {
+  if (idx->prm.metric == RBQ_METRIC_L2) return RBQ_OK;
+  const int64_t npad = (idx->n + 63) / 64 * 64;
+  HIPCHK(idx->d_fip.ensure((size_t)std::max<int64_t>(1, npad) * 4));
+  HIPCHK(launch_zero_u32(idx->d_fip.p, npad, st));
+  TmpBuf r2;
+  HIPCHK(r2.ensure(4));
+  HIPCHK(launch_zero_u32(r2.p, 1, st));
+  HIPCHK(launch_ip_terms((const float*)idx->d_raw.p, (const float*)idx->d_cent.p, list_of, idx->n, idx->dim,
+                         (float*)idx->d_fip.p, (uint32_t*)r2.p, st));
+  uint32_t bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, r2.p, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  float r2max;
+  std::memcpy(&r2max, &bits, 4);
+  idx->rmax = std::sqrt(r2max);
+  return RBQ_OK;
+}
+
+rbq_status prepare_queries(rbq_index* idx, const float* queries, int64_t nq, hipStream_t st, const float** out) {
+  *out = queries;
+  if (idx->prm.metric == RBQ_METRIC_L2) return RBQ_OK;
+  Workspace& w = idx->ws;
+  HIPCHK(w.q_m.ensure((size_t)nq * 4));
+  if (idx->prm.metric == RBQ_METRIC_COSINE) {
+    HIPCHK(w.qn.ensure((size_t)nq * idx->dim * 4));
+    HIPCHK(launch_normalize_rows(queries, nq, idx->dim, (float*)w.qn.p, st));
+    *out = (const float*)w.qn.p;
+  }
+  HIPCHK(launch_query_m(*out, nq, idx->dim, idx->rmax, (float*)w.q_m.p, st));
+  return RBQ_OK;
+}
+
 // Rotation, centroid scoring and probe selection for a batch.
 rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
                  const int32_t* nprobe_q, hipStream_t st) {
   Workspace& w = idx->ws;
   if (idx->prm.rot_precision == RBQ_ROT_FP32) {
     HIPCHK(launch_rotate_centroid(queries, nq, idx->dim, (const float*)idx->d_P32.p, idx->dp, (float*)w.qrot.p,
-                                  (const float*)idx->d_centT.p, (const float*)idx->d_cnorm.p, idx->nlist,
+                                  (const float*)idx->d_centT.p, idx->probe_cnorm(), idx->nlist,
                                   (float*)w.cd.p, (float*)w.cgmin.p, st));
   } else {
     rbq_status rs = rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, (float*)w.qrot.p, st);
     if (rs != RBQ_OK) return rs;
     HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
-                                (const float*)idx->d_cnorm.p, idx->nlist, (float*)w.cd.p, (float*)w.cgmin.p, st));
+                                idx->probe_cnorm(), idx->nlist, (float*)w.cd.p, (float*)w.cgmin.p, st));
   }
   HIPCHK(launch_select_probe((const float*)w.cd.p, (const float*)w.cgmin.p, nq, idx->nlist, nprobe, nprobe_q,
                              (int32_t*)w.probe.p, (float*)w.probe_d.p, st));
@@ -777,9 +831,9 @@ int scan_grid(rbq_index* idx, int64_t nq, int64_t units_per_query, int blocks_pe
 }
 
 rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& opts,
-                      int scan_kernel, int chunk, bool learned, int64_t* out_ids, float* out_d,
+                      int scan_kernel, int chunk, int mf_rg, bool learned, int64_t* out_ids, float* out_d,
                       hipStream_t st, const int32_t** used_npq, int* used_stride) {
-  const bool mfma = scan_kernel == RBQ_SCAN_MFMA;
+  const bool mfma = scan_kernel == RBQ_SCAN_MFMA || scan_kernel == RBQ_SCAN_MFMA_FP4;
   rbq_search_opts o = opts;
   const int32_t* nprobe_q = o.nprobe_per_query;
   // The learned path runs one probe selection of at least the 64 nearest
@@ -788,6 +842,8 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   if (learned) o.nprobe = std::max(o.nprobe, std::min(kMlpNear, idx->nlist));
   const int fin_w = fin_waves(o.rerank_waves, nq, o.k);
   rbq_status rs = ensure_workspace(idx, nq, o.nprobe, o.k, chunk, mfma, fin_w);
+  if (rs != RBQ_OK) return rs;
+  rs = prepare_queries(idx, queries, nq, st, &queries);
   if (rs != RBQ_OK) return rs;
   ProfState& pf = idx->prof;
   hipEvent_t ev[7] = {};
@@ -820,6 +876,8 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   *used_stride = o.nprobe;
   SearchDev s = make_dev(idx, queries, nq, o.nprobe, o.k, chunk, nprobe_q, o.qid_base, mfma,
                          out_ids, out_d);
+  s.mfma_f4 = scan_kernel == RBQ_SCAN_MFMA_FP4 ? 1 : 0;
+  s.mf_rg = mfma_row_groups(idx->dp, s.mfma_f4 != 0, mf_rg);
   HIPCHK(rec(1));
   HIPCHK(launch_plan(s, st));
   HIPCHK(launch_prep(s, true, st));
@@ -834,7 +892,8 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   HIPCHK(launch_tau_split(s, tau_split(fin_w, o.k), (uint64_t*)idx->ws.tau_part.p, st));
   HIPCHK(rec(4));
   if (mfma) {
-    HIPCHK(launch_scan_mfma(s, 1, scan_grid(idx, nq, chunks, scan_mfma_blocks_per_cu(idx->dp)), st));
+    HIPCHK(launch_scan_mfma(s, 1, scan_grid(idx, nq, chunks, scan_mfma_blocks_per_cu(idx->dp, s.mfma_f4 != 0, s.mf_rg)),
+                            st));
   } else {
     HIPCHK(launch_scan_popcnt(s, 1, grid, st));
   }
@@ -847,28 +906,28 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
 
 // ------------------------------------------------------------------ graph replay
 namespace {
-constexpr size_t kMaxGraphs = 96;
+constexpr size_t kMaxGraphs = 192;
 
-// Rows of the captured batch for nq queries: exact up to 16, else rounded up
-// to a multiple of 1/8 of the largest power of two <= nq (<= 12.5% extra).
+// Rows of the captured batch for nq queries: exact up to 32, else rounded up
+// to a multiple of 1/16 of the largest power of two <= nq (<= 6.25% extra).
 int64_t graph_rows(int64_t nq) {
-  if (nq <= 16) return nq;
+  if (nq <= 32) return nq;
   int64_t p = 1;
   while (p * 2 <= nq) p *= 2;
-  const int64_t step = p / 8;
+  const int64_t step = p / 16;
   return (nq + step - 1) / step * step;
 }
 
 __attribute__((unused)) bool same_shape(const GraphEntry& g, const GraphEntry& k) {
   return g.nqb == k.nqb && g.k == k.k && g.nprobe == k.nprobe && g.kernel == k.kernel &&
-         g.chunk == k.chunk && g.learned == k.learned && g.per_query == k.per_query &&
+         g.chunk == k.chunk && g.mf_rg == k.mf_rg && g.learned == k.learned && g.per_query == k.per_query &&
          g.qid_base == k.qid_base && g.fin_w == k.fin_w;
 }
 }  // namespace
 
 // rbq_search with use_graph = 1 (the caller holds idx->mu).
 rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& o,
-                        int kernel, int chunk, bool learned, int64_t* out_ids, float* out_d,
+                        int kernel, int chunk, int mf_rg, bool learned, int64_t* out_ids, float* out_d,
                         hipStream_t st, const int32_t** used_npq, int* used_stride) {
   GraphEntry key;
   key.nqb = graph_rows(nq);
@@ -876,6 +935,7 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
   key.nprobe = o.nprobe;
   key.kernel = kernel;
   key.chunk = chunk;
+  key.mf_rg = mf_rg;
   key.learned = learned;
   key.per_query = !learned;   // non-learned graphs always read a staged per-query nprobe
   key.qid_base = o.qid_base;
@@ -901,7 +961,11 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
   const int64_t seg_row = std::max<int64_t>(1, idx->max_codes(stride)) * (int64_t)sizeof(Cand);
   while (hint > nqb && hint * seg_row > idx->graph_mem_cap) hint = std::max(nqb, hint / 2);
   {
-    rbq_status rs = ensure_workspace(idx, hint, stride, o.k, chunk, kernel == RBQ_SCAN_MFMA, key.fin_w);
+    // the split-rerank buffers sized for the most waves any batch size can get,
+    // so that a later batch with more rerank waves does not reallocate them
+    // (which would invalidate every captured graph)
+    rbq_status rs = ensure_workspace(idx, hint, stride, o.k, chunk, kernel == RBQ_SCAN_MFMA || kernel == RBQ_SCAN_MFMA_FP4,
+                                     std::max(key.fin_w, fin_waves(kFinSplitMaxWaves, 1, o.k)));
     if (rs != RBQ_OK) return rs;
     if (learned) {
       HIPCHK(idx->ws.nprobe_q.ensure((size_t)hint * 4));
@@ -953,7 +1017,7 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
   }
   if (!ent) {
     // eager run of the staged batch: allocates and sizes everything the capture replays
-    rbq_status rs = run_search(idx, gq, nqb, og, kernel, chunk, learned, gi, gd, st, used_npq, used_stride);
+    rbq_status rs = run_search(idx, gq, nqb, og, kernel, chunk, mf_rg, learned, gi, gd, st, used_npq, used_stride);
     if (rs != RBQ_OK) return rs;
     if (!idx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&idx->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamSynchronize(st));
@@ -962,7 +1026,7 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
     HIPCHK(hipStreamBeginCapture(idx->cap_stream, hipStreamCaptureModeRelaxed));
     const int32_t* npq_c = nullptr;
     int stride_c = 0;
-    rs = run_search(idx, gq, nqb, og, kernel, chunk, learned, gi, gd, idx->cap_stream, &npq_c, &stride_c);
+    rs = run_search(idx, gq, nqb, og, kernel, chunk, mf_rg, learned, gi, gd, idx->cap_stream, &npq_c, &stride_c);
     const hipError_t ec = hipStreamEndCapture(idx->cap_stream, &graph);
     if (rs != RBQ_OK) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -1016,8 +1080,10 @@ extern "C" rbq_status rbq_search(rbq_index* idx, const float* queries, int64_t n
     return fail(RBQ_EINVAL, "nprobe=%d outside [1, %d]", o.nprobe, std::min(idx->nlist, kMaxNprobe));
   if (o.use_graph != 0 && o.use_graph != 1) return fail(RBQ_EINVAL, "use_graph must be 0 or 1");
   if (o.rerank_waves < 0) return fail(RBQ_EINVAL, "rerank_waves must be >= 0");
-  if (o.scan_kernel < RBQ_SCAN_AUTO || o.scan_kernel > RBQ_SCAN_MFMA)
+  if (o.scan_kernel < RBQ_SCAN_AUTO || o.scan_kernel > RBQ_SCAN_MFMA_FP4)
     return fail(RBQ_EINVAL, "unknown scan_kernel %d", o.scan_kernel);
+  if (o.scan_kernel == RBQ_SCAN_MFMA_FP4 && idx->prm.bq > 4)
+    return fail(RBQ_EUNSUPPORTED, "the FP8 x FP4 scan holds query values up to 15 exactly (B_q <= 4)");
   if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (nq == 0) return RBQ_OK;
@@ -1063,6 +1129,7 @@ rbq_status rbq::search_locked(rbq_index* idx, const float* queries, int64_t nq, 
   const TuneEntry tc = force ? *force : idx->tuned_for(nq);
   int kernel = o.scan_kernel == RBQ_SCAN_AUTO ? tc.kernel : o.scan_kernel;
   const int chunk = std::min(tc.chunk, kMaxP0 + 1 - o.k);   // bootstrap codes (k - 1 + chunk) fit the seed sort
+  const int mf_rg = tc.mf_rg;
   if (o.rerank_waves == 0) o.rerank_waves = tc.fin_w;
   if (kernel == RBQ_SCAN_AUTO || (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())) {
     if (kernel == RBQ_SCAN_MFMA && o.scan_kernel == RBQ_SCAN_MFMA)
@@ -1123,8 +1190,8 @@ rbq_status rbq::search_locked(rbq_index* idx, const float* queries, int64_t nq, 
     float* od = out_dists + q0 * o.k;
     const int32_t* npq = nullptr;
     int stride = o.nprobe;
-    rbq_status rs = graph ? rbq::search_graph(idx, qs, m, os, kernel, chunk, learned, oi, od, st, &npq, &stride)
-                          : run_search(idx, qs, m, os, kernel, chunk, learned, oi, od, st, &npq, &stride);
+    rbq_status rs = graph ? rbq::search_graph(idx, qs, m, os, kernel, chunk, mf_rg, learned, oi, od, st, &npq, &stride)
+                          : run_search(idx, qs, m, os, kernel, chunk, mf_rg, learned, oi, od, st, &npq, &stride);
     if (rs != RBQ_OK) return rs;
     if (stats) {
       rs = add_stats(m, npq, stride);
@@ -1151,8 +1218,10 @@ rbq_status rbq::search_in_arena(rbq_index* idx, const float* queries, int64_t nq
     return fail(RBQ_EINVAL, "nprobe=%d outside [1, %d]", o.nprobe, std::min(idx->nlist, kMaxNprobe));
   if (o.use_graph != 0) return fail(RBQ_EINVAL, "rbq_search_noalloc does not replay graphs (use_graph must be 0)");
   if (o.rerank_waves < 0) return fail(RBQ_EINVAL, "rerank_waves must be >= 0");
-  if (o.scan_kernel < RBQ_SCAN_AUTO || o.scan_kernel > RBQ_SCAN_MFMA)
+  if (o.scan_kernel < RBQ_SCAN_AUTO || o.scan_kernel > RBQ_SCAN_MFMA_FP4)
     return fail(RBQ_EINVAL, "unknown scan_kernel %d", o.scan_kernel);
+  if (o.scan_kernel == RBQ_SCAN_MFMA_FP4 && idx->prm.bq > 4)
+    return fail(RBQ_EUNSUPPORTED, "the FP8 x FP4 scan holds query values up to 15 exactly (B_q <= 4)");
   if (nq < 0) return fail(RBQ_EINVAL, "nq < 0");
   if (nq == 0) return RBQ_OK;
   if (o.qid_base < 0 || o.qid_base + nq > (1ll << 24))
@@ -1167,6 +1236,7 @@ rbq_status rbq::search_in_arena(rbq_index* idx, const float* queries, int64_t nq
   const TuneEntry tc = idx->tuned_for(nq);   // as rbq_search chooses them
   int kernel = o.scan_kernel == RBQ_SCAN_AUTO ? tc.kernel : o.scan_kernel;
   const int chunk = std::min(tc.chunk, kMaxP0 + 1 - o.k);
+  const int mf_rg = tc.mf_rg;
   if (o.rerank_waves == 0) o.rerank_waves = tc.fin_w;
   if (kernel == RBQ_SCAN_AUTO || (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())) {
     if (kernel == RBQ_SCAN_MFMA && o.scan_kernel == RBQ_SCAN_MFMA)
@@ -1184,7 +1254,7 @@ rbq_status rbq::search_in_arena(rbq_index* idx, const float* queries, int64_t nq
   g_arena = &arena;
   const int32_t* npq = nullptr;
   int stride = 0;
-  rbq_status rs = run_search(idx, queries, nq, o, kernel, chunk, learned, out_ids, out_dists, st, &npq, &stride);
+  rbq_status rs = run_search(idx, queries, nq, o, kernel, chunk, mf_rg, learned, out_ids, out_dists, st, &npq, &stride);
   g_arena = nullptr;
   std::swap(idx->ws, mine);
   if (rs != RBQ_OK && arena.used > arena.cap)
@@ -1232,6 +1302,7 @@ extern "C" rbq_status rbq_index_save(const rbq_index* cidx, const char* path) {
   h.bq = idx->prm.bq;
   h.rot_precision = idx->prm.rot_precision;
   h.eps0 = idx->prm.eps0;
+  h.pad = (uint32_t)idx->prm.metric;
   h.seed = idx->prm.seed;
   h.n = n;
   uint64_t sum = 0xcbf29ce484222325ull;
@@ -1270,6 +1341,7 @@ extern "C" rbq_status rbq_index_load(const char* path, rbq_index** out) {
   p.eps0 = h.eps0;
   p.rot_precision = h.rot_precision;
   p.seed = h.seed;
+  p.metric = (int32_t)h.pad;
   if (check_params(&p) != RBQ_OK || h.n < 1 || h.n > (int64_t)INT32_MAX) {
     std::fclose(f);
     return fail(RBQ_EFORMAT, "%s: invalid header fields", path);
@@ -1348,6 +1420,16 @@ extern "C" rbq_status rbq_index_load(const char* path, rbq_index** out) {
     return fail(e == hipErrorOutOfMemory ? RBQ_ENOMEM : RBQ_EDEVICE, "upload failed: %s", hipGetErrorString(e));
   }
   rs = scan_factors(idx, nullptr);
+  if (rs == RBQ_OK && idx->prm.metric != RBQ_METRIC_L2) {
+    std::vector<int32_t> lof(n);
+    for (int k = 0; k < idx->nlist; ++k)
+      for (int64_t q = idx->h_list_off[k]; q < idx->h_list_off[k + 1]; ++q) lof[q] = k;
+    TmpBuf listof;
+    hipError_t e2 = listof.ensure((size_t)n * 4);
+    if (e2 == hipSuccess) e2 = hipMemcpy(listof.p, lof.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+    rs = e2 == hipSuccess ? ip_factors(idx, (const int32_t*)listof.p, nullptr)
+                          : fail(RBQ_EDEVICE, "upload failed: %s", hipGetErrorString(e2));
+  }
   if (rs != RBQ_OK) {
     delete idx;
     return rs;
@@ -1413,8 +1495,10 @@ extern "C" rbq_status rbq_debug_centroid_dists(rbq_index* idx, const float* quer
   std::lock_guard<std::mutex> lock(idx->mu);
   rbq_status rs = ensure_workspace(idx, nq, 1, 1, kDefaultChunk, false);
   if (rs != RBQ_OK) return rs;
+  rs = prepare_queries(idx, queries, nq, st, &queries);
+  if (rs != RBQ_OK) return rs;
   HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
-                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)idx->ws.cd.p, nullptr, st));
+                              idx->probe_cnorm(), idx->nlist, (float*)idx->ws.cd.p, nullptr, st));
   HIPCHK(hipMemcpyAsync(dists, idx->ws.cd.p, (size_t)nq * idx->nlist * sizeof(float), hipMemcpyDeviceToDevice,
                         st));
   return RBQ_OK;
@@ -1433,8 +1517,10 @@ extern "C" rbq_status rbq_debug_probe(rbq_index* idx, const float* queries, int6
   std::lock_guard<std::mutex> lock(idx->mu);
   rbq_status rs = ensure_workspace(idx, nq, nprobe, 1, kDefaultChunk, false);
   if (rs != RBQ_OK) return rs;
+  rs = prepare_queries(idx, queries, nq, st, &queries);
+  if (rs != RBQ_OK) return rs;
   HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
-                              (const float*)idx->d_cnorm.p, idx->nlist, (float*)idx->ws.cd.p,
+                              idx->probe_cnorm(), idx->nlist, (float*)idx->ws.cd.p,
                               (float*)idx->ws.cgmin.p, st));
   HIPCHK(launch_select_probe((const float*)idx->ws.cd.p, (const float*)idx->ws.cgmin.p, nq, idx->nlist, nprobe,
                              nullptr, lists,
@@ -1457,6 +1543,8 @@ extern "C" rbq_status rbq_debug_quantize(rbq_index* idx, const float* queries, i
   std::lock_guard<std::mutex> lock(idx->mu);
   rbq_status rs = ensure_workspace(idx, nq, nprobe, 1, kDefaultChunk, true);
   if (rs != RBQ_OK) return rs;
+  rs = prepare_queries(idx, queries, nq, st, &queries);
+  if (rs != RBQ_OK) return rs;
   rs = rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, (float*)idx->ws.qrot.p, st);
   if (rs != RBQ_OK) return rs;
   HIPCHK(hipMemcpyAsync(idx->ws.probe.p, lists, (size_t)nq * nprobe * 4, hipMemcpyDeviceToDevice, st));
@@ -1475,8 +1563,11 @@ extern "C" rbq_status rbq_debug_scan(rbq_index* idx, int32_t list, const uint8_t
   if (!idx || !scal) return fail(RBQ_EINVAL, "NULL argument");
   if (!idx->built) return fail(RBQ_ESTATE, "index not built");
   if (list < 0 || list >= idx->nlist) return fail(RBQ_EINVAL, "list out of range");
-  if (kernel != RBQ_SCAN_POPCNT && kernel != RBQ_SCAN_MFMA) return fail(RBQ_EINVAL, "kernel must be POPCNT or MFMA");
+  if (kernel != RBQ_SCAN_POPCNT && kernel != RBQ_SCAN_MFMA && kernel != RBQ_SCAN_MFMA_FP4)
+    return fail(RBQ_EINVAL, "kernel must be POPCNT, MFMA or MFMA_FP4");
   if (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available()) return fail(RBQ_EUNSUPPORTED, "MFMA scan not available");
+  if (kernel == RBQ_SCAN_MFMA_FP4 && idx->prm.bq > 4)
+    return fail(RBQ_EUNSUPPORTED, "the FP8 x FP4 scan holds query values up to 15 exactly (B_q <= 4)");
   for (const void* p : {(const void*)qu, (const void*)ip, (const void*)pc, (const void*)est,
                         (const void*)dist, (const void*)lb})
     if (!is_device_ptr(p)) return fail(RBQ_EINVAL, "qu and outputs must be device pointers");
@@ -1486,8 +1577,9 @@ extern "C" rbq_status rbq_debug_scan(rbq_index* idx, int32_t list, const uint8_t
   if (rs != RBQ_OK) return rs;
   Workspace& w = idx->ws;
   SearchDev s = make_dev(idx, nullptr, 1, 1, 1, kDefaultChunk, nullptr, 0, true, nullptr, nullptr);
-  HIPCHK(launch_debug_pack(qu, idx->dp, idx->W, s.npl, s.qoff, scal[0], scal[1], scal[2], (PairRec*)w.pairs.p,
-                           (uint64_t*)w.planes.p, (int8_t*)w.qu8.p, list, st));
+  HIPCHK(launch_debug_pack(qu, idx->dp, idx->W, s.npl, s.qoff, scal[0], scal[1], scal[2], scal[3],
+                           (PairRec*)w.pairs.p, (uint64_t*)w.planes.p, (int8_t*)w.qu8.p, (float*)w.pair_pt.p,
+                           list, st));
   if (kernel == RBQ_SCAN_POPCNT) {
     // the list as main-phase work units of pair 0, for the production scan's export phase
     const int64_t beg = idx->h_list_off[list], end = idx->h_list_off[list + 1];
@@ -1516,6 +1608,8 @@ extern "C" rbq_status rbq_debug_scan(rbq_index* idx, int32_t list, const uint8_t
     s.dbg_lb = lb;
     HIPCHK(hipStreamSynchronize(st));   // the host tables above are stack memory
   }
+  s.mfma_f4 = kernel == RBQ_SCAN_MFMA_FP4 ? 1 : 0;
+  s.mf_rg = mfma_row_groups(idx->dp, s.mfma_f4 != 0, 0);
   HIPCHK(launch_debug_scan(s, (const PairRec*)w.pairs.p, (const uint64_t*)w.planes.p,
                            (const int8_t*)w.qu8.p, list, kernel, ip, pc, est, dist, lb, st));
   return RBQ_OK;
@@ -1648,6 +1742,7 @@ extern "C" rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t
   const int chunks[] = {256, 512, 1024, 2048};
   std::vector<int> kernels = {RBQ_SCAN_POPCNT};
   if (rbq::mfma_available()) kernels.push_back(RBQ_SCAN_MFMA);
+  if (rbq::mfma_available() && idx->prm.bq <= 4) kernels.push_back(RBQ_SCAN_MFMA_FP4);
   for (int64_t m : sizes) {
     TuneEntry best;
     float best_ms = 1e30f;
@@ -1658,6 +1753,24 @@ extern "C" rbq_status rbq_autotune(rbq_index* idx, const float* queries, int64_t
         t.chunk = c;
         t.kernel = kern;
         t.fin_w = 0;
+        float ms = 0.f;
+        rbq_status rs = timed(m, t, &ms);
+        if (rs != RBQ_OK) return rs;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+    }
+    // query rows per unit of the batched scan (16, 32 or 64 of them share each
+    // expanded code fragment; fewer rows per unit leave more blocks per CU)
+    if (best.kernel == RBQ_SCAN_MFMA || best.kernel == RBQ_SCAN_MFMA_FP4) {
+      const bool f4 = best.kernel == RBQ_SCAN_MFMA_FP4;
+      const int rg0 = mfma_row_groups(idx->dp, f4, 0);
+      for (int rg : {1, 2, 4}) {
+        if (mfma_row_groups(idx->dp, f4, rg) != rg || rg == rg0) continue;
+        TuneEntry t = best;
+        t.mf_rg = rg;
         float ms = 0.f;
         rbq_status rs = timed(m, t, &ms);
         if (rs != RBQ_OK) return rs;
@@ -1707,6 +1820,7 @@ extern "C" rbq_status rbq_autotune_get(const rbq_index* idx, int32_t max_entries
     entries[i].scan_kernel = t.kernel;
     entries[i].rerank_waves = t.fin_w;
     entries[i].ms = t.ms;
+    entries[i].mfma_row_groups = t.mf_rg;
   }
   return RBQ_OK;
 }

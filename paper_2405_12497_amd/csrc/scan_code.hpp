@@ -70,22 +70,36 @@ __device__ __forceinline__ void code_ip(const uint64_t* __restrict__ row, int W,
 //   lb   = dist - 2 b (eps0 / sqrt(D - 1)) H   (2ab times the half-width of Theorem 3.2)
 // The per-pair constants are b^2, -2b and -2b eps0 / sqrt(D - 1). Every scan
 // uses this form, so all of them give identical bits.
+// Inner product (RBQ_METRIC_IP / COSINE): the searched "distance" is
+// M_q - <o_r, q_r> with <o_r, q_r> = a b <o, q> + <o_r - c, c> + <q_r, c>
+// (the conclusion's identity), so
+//   dist = (M_q - <q_r, c>) - <o_r - c, c> - b G x,   lb = dist - b (eps0 / sqrt(D - 1)) H:
+// per-pair constants M_q - <q_r, c> (from the quantiser), -b, -b eps0 / sqrt(D - 1),
+// and the per-code term -<o_r - c, c> in place of a^2.
 struct PairTerms {
-  float b2, m2b, m2bh;
+  float pt, coef, coefh;   // pair term, coefficient of G x, coefficient of H
 };
 __device__ __forceinline__ PairTerms pair_terms(const PairRec& r, float hwk) {
   PairTerms t;
-  t.b2 = r.b * r.b;
-  t.m2b = -2.f * r.b;
-  t.m2bh = t.m2b * hwk;
+  t.pt = r.b * r.b;
+  t.coef = -2.f * r.b;
+  t.coefh = t.coef * hwk;
   return t;
 }
-__device__ __forceinline__ void estimate(const PairRec& r, const PairTerms& t, float2 sf, int ip, int pc,
+__device__ __forceinline__ PairTerms pair_terms_ip(const PairRec& r, float hwk, float pair_term) {
+  PairTerms t;
+  t.pt = pair_term;
+  t.coef = -r.b;
+  t.coefh = t.coef * hwk;
+  return t;
+}
+// The per-code term: a^2 = G^2 - H^2 (L2), or -<o_r - c, c> (inner product).
+__device__ __forceinline__ float code_term_l2(float2 sf) { return fmaf(sf.x, sf.x, -sf.y * sf.y); }
+__device__ __forceinline__ void estimate(const PairRec& r, const PairTerms& t, float2 sf, float ct, int ip, int pc,
                                          float& dist, float& lb) {
   const float xq = fmaf(r.k1, (float)ip, fmaf(r.k2, (float)pc, r.k0));
-  const float a2 = fmaf(sf.x, sf.x, -sf.y * sf.y);
-  dist = fmaf(t.m2b * sf.x, xq, a2 + t.b2);
-  lb = fmaf(t.m2bh, sf.y, dist);
+  dist = fmaf(t.coef * sf.x, xq, ct + t.pt);
+  lb = fmaf(t.coefh, sf.y, dist);
 }
 // The estimate itself, from the stored (a, <o_bar,o>) (the parity exports).
 __device__ __forceinline__ float estimate_est(const PairRec& r, float ipo, int ip, int pc) {

@@ -14,17 +14,20 @@ LIB_PATH = os.path.join(_HERE, "librabitq.so")
 
 RBQ_OK, RBQ_EINVAL, RBQ_ENOMEM, RBQ_EDEVICE, RBQ_ESTATE, RBQ_EFORMAT, RBQ_EUNSUPPORTED = range(7)
 RBQ_ROT_FP32, RBQ_ROT_BF16X3 = 0, 1
-RBQ_SCAN_AUTO, RBQ_SCAN_POPCNT, RBQ_SCAN_MFMA = 0, 1, 2
+RBQ_SCAN_AUTO, RBQ_SCAN_POPCNT, RBQ_SCAN_MFMA, RBQ_SCAN_MFMA_FP4 = 0, 1, 2, 3
 RBQ_PROFILE_STAGES, RBQ_PROFILE_SCAN = 1, 2
 MLP_IN, MLP_HIDDEN, MLP_OUT = 96, 128, 32
 MAX_K, MAX_NPROBE, MAX_NLIST = 256, 16384, 24576
 MLP_NPARAM = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_OUT + MLP_OUT
 
 
+RBQ_METRIC_L2, RBQ_METRIC_IP, RBQ_METRIC_COSINE = 0, 1, 2
+
+
 class RbqParams(C.Structure):
     _fields_ = [("dim", C.c_int32), ("code_bits", C.c_int32), ("nlist", C.c_int32),
                 ("bq", C.c_int32), ("eps0", C.c_float), ("rot_precision", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("metric", C.c_int32)]
 
 
 class RbqSearchOpts(C.Structure):
@@ -119,6 +122,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing; build it with python -m paper_2405_12497_amd.build")
+        # torch ships its own HIP runtime under the same soname as the system's.
+        # Loading torch first makes the library bind to that runtime; loaded the
+        # other way round, the process would hold two HIP runtimes, and the one
+        # initialised second finds no device.
+        import torch  # noqa: F401
         h = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(h, name)
@@ -326,7 +334,7 @@ def rbq_index_destroy(idx):
 
 class RbqTuneEntry(C.Structure):
     _fields_ = [("max_nq", C.c_int64), ("chunk", C.c_int32), ("scan_kernel", C.c_int32),
-                ("rerank_waves", C.c_int32), ("ms", C.c_float)]
+                ("rerank_waves", C.c_int32), ("ms", C.c_float), ("mfma_row_groups", C.c_int32)]
 
 
 def rbq_autotune(idx, queries, k, nprobe, stream=None):
@@ -476,7 +484,7 @@ def rbq_debug_quantize(idx, queries, lists, code_bits, qid_base=0, stream=None):
     return qu, scal
 
 
-def rbq_debug_scan(idx, list_id, qu, b, vl, delta, n, kernel=RBQ_SCAN_POPCNT, stream=None):
+def rbq_debug_scan(idx, list_id, qu, b, vl, delta, n, kernel=RBQ_SCAN_POPCNT, stream=None, pair_term=0.0):
     import torch
     dev = qu.device
     ip = torch.empty(n, dtype=torch.int32, device=dev)
@@ -484,7 +492,7 @@ def rbq_debug_scan(idx, list_id, qu, b, vl, delta, n, kernel=RBQ_SCAN_POPCNT, st
     est = torch.empty(n, dtype=torch.float32, device=dev)
     dist = torch.empty(n, dtype=torch.float32, device=dev)
     lb = torch.empty(n, dtype=torch.float32, device=dev)
-    scal = np.array([b, vl, delta, 0.0], dtype=np.float32)
+    scal = np.array([b, vl, delta, pair_term], dtype=np.float32)
     _check(lib().rbq_debug_scan(idx, list_id, _dev(qu, torch.uint8), scal.ctypes.data_as(C.c_void_p),
                                 kernel, _dev(ip), _dev(pc), _dev(est), _dev(dist), _dev(lb),
                                 _stream(stream)))
@@ -511,13 +519,14 @@ class Index:
     """Owns an rbq_index handle."""
 
     def __init__(self, dim, nlist, code_bits=0, eps0=1.9, rot_precision=RBQ_ROT_FP32, seed=0,
-                 handle=None, bq=4):
+                 handle=None, bq=4, metric=RBQ_METRIC_L2):
         if handle is not None:
             self.h = handle
         else:
             p = rbq_params_default(dim, nlist)
             p.code_bits = code_bits
             p.bq = bq
+            p.metric = metric
             p.eps0 = eps0
             p.rot_precision = rot_precision
             p.seed = seed

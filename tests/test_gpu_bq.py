@@ -75,7 +75,17 @@ def test_quantized_query_matches_oracle_at_bq(bq):
     print(f"B_q={bq}: {flips} quantised coordinates differ from FP64")
 
 
-@pytest.mark.parametrize("kernel", ["popcnt", "mfma"])
+def test_fp4_scan_limited_to_bq4():
+    import torch
+    from paper_2405_12497_amd import rabitq as R
+    idx = _index(5)
+    q = torch.from_numpy(_data()[1]).cuda()
+    with pytest.raises(R.RbqError) as e:
+        idx.search(q, 10, 4, scan_kernel=R.RBQ_SCAN_MFMA_FP4)
+    assert e.value.status == R.RBQ_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("kernel", ["popcnt", "mfma", "mfma_fp4"])
 @pytest.mark.parametrize("bq", [1, 3, 5, 8])
 def test_scan_bitexact_at_bq(bq, kernel):
     """Integer <x_b, q_u> over B_q bit planes (popcount) or int8 (MFMA, with
@@ -83,7 +93,9 @@ def test_scan_bitexact_at_bq(bq, kernel):
     import torch
     from paper_2405_12497_amd import rabitq as R
     _say(f"scan B_q={bq} {kernel}")
-    kern = R.RBQ_SCAN_POPCNT if kernel == "popcnt" else R.RBQ_SCAN_MFMA
+    kern = {"popcnt": R.RBQ_SCAN_POPCNT, "mfma": R.RBQ_SCAN_MFMA, "mfma_fp4": R.RBQ_SCAN_MFMA_FP4}[kernel]
+    if kernel == "mfma_fp4" and bq > 4:
+        pytest.skip("the FP8 x FP4 scan holds query values up to 15 (B_q <= 4)")
     data, qs, cent, assign, gauss, oidx = _data()
     idx = _index(bq)
     codes, norm, ipo = R.rbq_debug_export_codes(idx.h, len(data), 2)

@@ -139,13 +139,13 @@ def test_quantized_query_matches_oracle(name):
     print(f"{name}: quantised coordinates differing from FP64: {flips} of {total}")
 
 
-@pytest.mark.parametrize("kernel", ["popcnt", "mfma"])
+@pytest.mark.parametrize("kernel", ["popcnt", "mfma", "mfma_fp4"])
 @pytest.mark.parametrize("name", CASES)
 def test_scan_bitexact_and_estimates(name, kernel):
     import torch
     from paper_2405_12497_amd import rabitq as R
     b = built(name)
-    kern = R.RBQ_SCAN_POPCNT if kernel == "popcnt" else R.RBQ_SCAN_MFMA
+    kern = {"popcnt": R.RBQ_SCAN_POPCNT, "mfma": R.RBQ_SCAN_MFMA, "mfma_fp4": R.RBQ_SCAN_MFMA_FP4}[kernel]
     c = b.case
     sizes = b.idx.list_sizes()
     rng = np.random.default_rng(5)
@@ -254,6 +254,11 @@ def test_search_mfma_matches_popcount(name):
     c = b.case
     a1, d1, s1 = b.search(scan_kernel=b.R.RBQ_SCAN_POPCNT, stats=True)
     a2, d2, s2 = b.search(scan_kernel=b.R.RBQ_SCAN_MFMA, stats=True)
+    a3, d3, s3 = b.search(scan_kernel=b.R.RBQ_SCAN_MFMA_FP4, stats=True)
+    # the FP8 x FP4 contraction gives the int8 one's integers: identical searches
+    np.testing.assert_array_equal(a3, a2)
+    np.testing.assert_array_equal(d3, d2)
+    assert s3 == s2
     assert s1["codes_scanned"] == s2["codes_scanned"]
     # both scans compute the same integers and the same estimator arithmetic:
     # identical bounds, so the same candidates and the same reranked codes
