@@ -29,20 +29,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA
+FP8_PEAK_TFLOPS = 5000.0       # MI355X dense FP8 MFMA (the FP8 x FP4 products run at the FP8 operand's rate)
 
-# Sources of the phase-1 popcount scan kernel; stored counter readings apply
-# only while their hash matches.
-SCAN_SOURCES = ("paper_2405_12497_amd/csrc/kernels_popcnt.hip",
-                "paper_2405_12497_amd/csrc/scan_code.hpp",
-                "paper_2405_12497_amd/csrc/rbq_internal.hpp")
-# HBM traffic of one phase-1 scan launch per workload, from rocprofv3 --pmc
-# FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch, mean over the timed
-# steps' phase-1 dispatches), each scaled by the reading of the same counter
-# for a 1 GiB device-to-device copy (FETCH_SIZE reads 0.5x the copied bytes,
-# WRITE_SIZE 1.0x). A reading applies only while the scan sources hash to the
-# value it was taken on and the workload key matches.
+# Kernel sources per scan kind; stored counter readings apply only while their
+# sources hash to the value they were taken on.
+SCAN_SOURCES = {
+    "popcnt": ("paper_2405_12497_amd/csrc/kernels_popcnt.hip", "paper_2405_12497_amd/csrc/scan_code.hpp",
+               "paper_2405_12497_amd/csrc/rbq_internal.hpp"),
+    "mfma": ("paper_2405_12497_amd/csrc/kernels_mfma.hip", "paper_2405_12497_amd/csrc/scan_code.hpp",
+             "paper_2405_12497_amd/csrc/rbq_internal.hpp"),
+}
+# HBM traffic of one scan launch per workload, from rocprofv3 --pmc FETCH_SIZE
+# and --pmc WRITE_SIZE (KiB per dispatch, mean over the timed steps' dispatches
+# of that kernel), each scaled by the reading of the same counter for a 1 GiB
+# device-to-device copy (FETCH_SIZE reads 0.5x the copied bytes, WRITE_SIZE
+# 1.0x). A reading applies only while the kernel's sources hash to the value
+# it was taken on and the workload key matches.
 COUNTERS = {
     "sift": {
+        "kind": "popcnt",
         "sources_sha256": "8586f0eedaf4c3b9cfa2f2cb581352979516762caa6333c338332bb04981a5bd",
         "workload": "sift-like n=1000000 nq=10000 nlist=4096 nprobe=20 kernel=popcnt",
         "fetch_kib": 471000.5, "write_kib": 23659.5, "fetch_scale": 2.0, "write_scale": 1.0,
@@ -52,22 +58,48 @@ NPROBE_SWEEP = (8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 80, 96, 128, 160, 192, 25
 METRIC = "QPS at recall@10≥0.95, learned vs fixed nprobe; code-scan GB/s vs HBM peak"
 
 
-def scan_sources_sha256():
+def scan_sources_sha256(kind="popcnt"):
     import hashlib
     h = hashlib.sha256()
-    for rel in SCAN_SOURCES:
+    for rel in SCAN_SOURCES[kind]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
 def stored_traffic(name, workload_key):
-    """HBM bytes per phase-1 scan launch from the stored counter readings, or
-    None when there are none for this workload or they were taken on other sources."""
+    """HBM bytes per scan launch from the stored counter readings, or None when
+    there are none for this workload or they were taken on other sources."""
     c = COUNTERS.get(name)
-    if not c or c["sources_sha256"] != scan_sources_sha256() or c["workload"] != workload_key:
+    if not c or c["sources_sha256"] != scan_sources_sha256(c["kind"]) or c["workload"] != workload_key:
         return None
     return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
+
+
+def scan_roofline(kernel, codes, ms, dim, bpc, wkey):
+    """Roofline of the phase-1 scan of one batch (the dominant kernel of the
+    learned step): the batched MFMA scans against the matrix-core peak of their
+    operand type, with 2 D integer operations per (query, code) pair (D products
+    and D additions of <x_b, q_u>); the popcount scan against HBM with its
+    algorithmic bytes per (query, code) pair."""
+    if kernel in ("mfma", "mfma_fp4"):
+        ops = codes * 2.0 * dim
+        achieved = ops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        peak = INT8_PEAK_TOPS if kernel == "mfma" else FP8_PEAK_TFLOPS
+        name = ("k_scan_mfma_w<false,12,1> (phase-1 batched scan, int8 MFMA)" if kernel == "mfma" else
+                "k_scan_mfma_w<true,12,1> (phase-1 batched scan, FP8 x FP4 MFMA)")
+        return {"bound": "mfma", "achieved": achieved, "peak": peak,
+                "unit": "TOP/s" if kernel == "mfma" else "TFLOP/s", "frac": achieved / peak,
+                "traffic": stored_traffic("learned_" + kernel, wkey), "kernel": name,
+                "algorithmic_ops_per_code": 2 * dim, "ops_per_launch": ops, "avg_launch_ms": ms,
+                "counters_workload": wkey}
+    achieved = codes * bpc / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("learned", wkey),
+            "kernel": "k_scan_popcnt<12,4,1> (phase-1 scan, learned batches; codes served mostly from cache: "
+                      "each list is scanned by many queries of the batch)",
+            "algorithmic_bytes_per_code": bpc, "bytes_per_launch": codes * bpc, "avg_launch_ms": ms,
+            "counters_workload": wkey}
 
 
 def finalize_roofline(st, dim, nq, ms):
@@ -706,7 +738,8 @@ def bench_learned(args):
         f"({t_f * 1e3:.3f} ms); speedup {t_f / t_l:.3f}")
     bpc = dim // 8 + 8
     scan_ms = prof_l["ms_scan1"] / max(1, prof_l["searches"])
-    scan_bytes = prof_l["codes_scan1"] / max(1, prof_l["searches"]) * bpc
+    scan_codes = prof_l["codes_scan1"] / max(1, prof_l["searches"])   # (query, code) pairs of the phase-1 scan
+    scan_bytes = scan_codes * bpc
     scan_gbs = scan_bytes / (scan_ms * 1e-3) / 1e9 if scan_ms > 0 else 0.0
     fin_ms = prof_l["ms_finalize"] / max(1, prof_l["searches"])
     # finalize's own reranks (its seeds were reranked by the bootstrap kernel)
@@ -764,11 +797,7 @@ def bench_learned(args):
             "single_query_full_scan": {"nprobe": min(nlist, R.MAX_NPROBE), "ms_per_search": full_lat * 1e3,
                                        "stage_ms": full_stages},
         },
-        "roofline": {"bound": "hbm", "achieved": scan_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": scan_gbs / HBM_PEAK_GBS, "traffic": stored_traffic("learned", wkey),
-                     "kernel": "k_scan_popcnt<12,4,1> (phase-1 scan, learned batches)",
-                     "algorithmic_bytes_per_code": bpc, "bytes_per_launch": scan_bytes, "avg_launch_ms": scan_ms,
-                     "counters_workload": wkey},
+        "roofline": scan_roofline(args.kernel, scan_codes, scan_ms, dim, bpc, wkey),
         "roofline_fullscan": {"bound": "hbm", "achieved": full_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": full_gbs / HBM_PEAK_GBS, "traffic": stored_traffic("fullscan", fkey),
                               "kernel": "k_scan_popcnt<12,4,1> (one query, every list)",

@@ -101,12 +101,23 @@ def policy(logits, threshold):
 
 # ------------------------------------------------------------------ features
 
+def expected_sq_fraction(qq) -> float:
+    """E[S_q] / (15 * code length) of a quantised pair: E[q_u,i] = (q'_i - v_l)/Delta
+    (Theorem 3.3), Delta = (v_r - v_l)/15; 0 when b = 0 or v_r = v_l."""
+    if qq.b == 0.0 or qq.vr <= qq.vl:
+        return 0.0
+    qp = np.asarray(qq.qprime, np.float64)
+    return float(np.mean((qp - qq.vl) / (qq.vr - qq.vl)))
+
+
 def features(index: "O.OracleIndex", q_raw, qid: int, seed: int):
     """96 features of one query:
     [0]      log d_(1), the squared distance to the nearest centroid
     [1..63]  log(d_(j)/d_(1)) for the 2nd..64th nearest centroids
     [64..95] for each of the 8 nearest lists: ||q_r - c_k||/||q_r - c_1||, v_l, v_r,
-             sum q_u / (15 * code length)  (Sec. 3.3.1 quantiser of that pair)
+             E[sum q_u] / (15 * code length) = the mean of (q'_i - v_l) / (v_r - v_l)
+             over the code length (Sec. 3.3.1 quantiser of that pair; the
+             randomized rounding is unbiased, Theorem 3.3, so no draw is needed)
     Missing centroids (fewer than 64 lists) repeat the last available value.
     """
     c = index.centroids
@@ -130,5 +141,5 @@ def features(index: "O.OracleIndex", q_raw, qid: int, seed: int):
         f[base + 0] = qq.b / b1
         f[base + 1] = qq.vl
         f[base + 2] = qq.vr
-        f[base + 3] = qq.sq / (15.0 * index.dp)
+        f[base + 3] = expected_sq_fraction(qq)
     return f

@@ -11,6 +11,8 @@
 // expands their bits to bytes in registers and issues one MFMA per 64
 // dimensions. Candidates (lb <= tau) are compacted per pair in code order, so
 // the segments are identical to those of the popcount scan.
+#include <type_traits>
+
 #include "rbq_internal.hpp"
 #include "rbq_runtime.hpp"
 #include "scan_code.hpp"
@@ -493,6 +495,299 @@ __global__ __launch_bounds__(kThreads) void k_debug_mfma(SearchDev s, const Pair
   mfma_unit<true, F4, WS, RG>(s, start, end, rows, rg_live, A, masks, rowcnt, ip, pc, est, dist, lb, lbeg);
 }
 
+// ---------------------------------------------------------------- wave-unit MFMA scan
+// The same work units (list, chunk, group of R = 16 RG pairs), each taken by a
+// single wave: the wave keeps its R query rows' MFMA fragments in registers
+// for the whole unit (no LDS traffic per code block), counts each row's
+// candidates in registers and places them with ballots alone, so no unit
+// needs a block barrier. Only the rows' estimator constants sit in LDS, in the
+// wave's own slice. Widths up to 16 words (the fragments of 16 RG rows must
+// fit in registers); wider codes use the block kernel above.
+
+// The list holding unit u: the largest l < n with off[l] <= u, by a 64-way
+// search (three rounds of loads for 16,384 lists).
+__device__ __forceinline__ int wave_find_list(const int64_t* __restrict__ off, int n, int64_t u) {
+  int lo = 0, hi = n;   // off[lo] <= u, and the list is in [lo, hi)
+  const int lane = lane_id();
+  while (hi - lo > 1) {
+    const int step = (hi - lo + kWave - 1) / kWave;
+    const int idx = lo + lane * step;
+    const bool ok = idx < hi && off[min(idx, n - 1)] <= u;
+    const uint64_t m = __ballot(ok);
+    const int j = 63 - __clzll((long long)m);   // lane 0 always holds (off[lo] <= u)
+    lo = uniform_i32(lo + j * step);
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
+// One unit on one wave. rows: the wave's R row records (LDS); g: lane i < R
+// holds its row's pair id (-1: none), whose quantised query is row g of `qbase`
+// (dp bytes per row). Counts and candidates as mfma_unit.
+template <bool DEBUG, bool F4, int WS, int RG>
+__device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, const RowInfo* rows, int g,
+                               const int8_t* __restrict__ qbase, int32_t* dbg_ip, int32_t* dbg_pc,
+                               float* dbg_est, float* dbg_dist, float* dbg_lb, int64_t dbg_base) {
+  static_assert(WS >= 1 && WS <= 16, "fragments held in registers");
+  const int lane = lane_id();
+  const int col = lane & 15, grp = lane >> 4;
+  const int dp = s.dp, W = s.W;
+  constexpr int T2 = (WS + 1) / 2;
+  constexpr int NA = F4 ? T2 : WS;   // MFMA steps per code
+  // query fragments of rows 16 h + col: int8 dims 64 t + 16 grp .. +15, or
+  // FP8 positions 128 t2 + 32 grp .. +31 (dimensions by f4_src_dim)
+  typedef typename std::conditional<F4, i32x8, i32x4>::type AFrag;
+  AFrag a[RG][NA];
+#pragma unroll
+  for (int h = 0; h < RG; ++h) {
+    const int gh = __shfl(g, 16 * h + col, kWave);
+    const int8_t* qr = qbase + (int64_t)max(gh, 0) * dp;
+#pragma unroll
+    for (int t = 0; t < NA; ++t) {
+      if constexpr (F4) {
+        const int d0 = 128 * t + 16 * grp, d1 = 128 * t + 64 + 16 * grp;
+        i32x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (gh >= 0) {
+          const uint64_t* p0 = reinterpret_cast<const uint64_t*>(qr + min(d0, dp - 16));
+          const uint64_t* p1 = reinterpret_cast<const uint64_t*>(qr + min(d1, dp - 16));
+          const uint64_t x0 = p0[0], x1 = p0[1], y0 = p1[0], y1 = p1[1];
+          const uint64_t f0 = d0 < dp ? fp8_group(x0) : 0ull, f1 = d0 < dp ? fp8_group(x1) : 0ull;
+          const uint64_t f2 = d1 < dp ? fp8_group(y0) : 0ull, f3 = d1 < dp ? fp8_group(y1) : 0ull;
+          v[0] = (int)(uint32_t)f0; v[1] = (int)(uint32_t)(f0 >> 32);
+          v[2] = (int)(uint32_t)f1; v[3] = (int)(uint32_t)(f1 >> 32);
+          v[4] = (int)(uint32_t)f2; v[5] = (int)(uint32_t)(f2 >> 32);
+          v[6] = (int)(uint32_t)f3; v[7] = (int)(uint32_t)(f3 >> 32);
+        }
+        a[h][t] = v;
+      } else {
+        i32x4 v = {0, 0, 0, 0};
+        if (gh >= 0) v = *reinterpret_cast<const i32x4*>(qr + t * 64 + grp * 16);
+        a[h][t] = v;
+      }
+    }
+  }
+  bool hl[RG];   // row group with a live row (wave-uniform)
+#pragma unroll
+  for (int h = 0; h < RG; ++h) {
+    const bool mine = lane < 16 && rows[16 * h + lane].valid;
+    hl[h] = __ballot(mine) != 0ull;
+  }
+  int cnt[RG][4];
+#pragma unroll
+  for (int h = 0; h < RG; ++h)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cnt[h][i] = 0;
+  // code words of 16 codes, the next block's in flight while this one computes
+  const uint16_t* c16 = reinterpret_cast<const uint16_t*>(s.codes);
+  const uint32_t* c32 = reinterpret_cast<const uint32_t*>(s.codes);
+  auto load_block = [&](int64_t blk, uint32_t* bw) {
+    const int64_t p = min(blk + col, end - 1);   // in bounds; masked later
+    if constexpr (F4) {
+#pragma unroll
+      for (int t = 0; t < T2; ++t) {
+        const int w = 2 * t + (grp >> 1);
+        const uint32_t v = c32[2 * code_word_index(p, min(w, W - 1), W) + (grp & 1)];
+        bw[t] = w < W ? v : 0u;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < WS; ++t) bw[t] = c16[4 * code_word_index(p, t, WS) + grp];
+    }
+  };
+  // the code's scan factors (and inner-product term) travel with its words
+  auto load_fac = [&](int64_t blk, float2& sf, float& fi) {
+    const int64_t p = min(blk + col, end - 1);
+    sf = s.sfac[p];
+    fi = s.metric != 0 ? s.fip[p] : 0.f;
+  };
+  uint32_t bw[NA];
+  float2 sf;
+  float fi;
+  load_block(start, bw);
+  load_fac(start, sf, fi);
+  for (int64_t blk = start; blk < end; blk += 16) {
+    uint32_t nb[NA];
+    float2 nsf;
+    float nfi;
+    load_block(min(blk + 16, end - 1), nb);
+    load_fac(min(blk + 16, end - 1), nsf, nfi);
+    const bool pvalid = blk + col < end;
+    const int64_t p = pvalid ? blk + col : blk;
+    const uint32_t keep = pvalid ? 0xFFFFFFFFu : 0u;
+    i32x4 acc[RG];
+    int pcp = 0;
+    if constexpr (F4) {
+      f32x4 accf[RG];
+#pragma unroll
+      for (int h = 0; h < RG; ++h) accf[h] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < T2; ++t) {
+        const uint32_t bits = bw[t] & keep;
+        pcp += __popc(bits);
+        const i32x8 b = {bits_to_fp4x8(bits & 0xFFu), bits_to_fp4x8((bits >> 8) & 0xFFu),
+                         bits_to_fp4x8((bits >> 16) & 0xFFu), bits_to_fp4x8(bits >> 24), 0, 0, 0, 0};
+#pragma unroll
+        for (int h = 0; h < RG; ++h)
+          if (hl[h]) accf[h] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[h][t], b, accf[h], 0, 4, 0, 127, 0, 127);
+      }
+#pragma unroll
+      for (int h = 0; h < RG; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[h][i] = (int)accf[h][i];
+    } else {
+#pragma unroll
+      for (int h = 0; h < RG; ++h) acc[h] = i32x4{0, 0, 0, 0};
+#pragma unroll
+      for (int t = 0; t < WS; ++t) {
+        const uint32_t bits = bw[t] & keep & 0xFFFFu;
+        pcp += __popc(bits);
+        i32x4 b;
+        b[0] = nib_to_bytes(bits & 15u);
+        b[1] = nib_to_bytes((bits >> 4) & 15u);
+        b[2] = nib_to_bytes((bits >> 8) & 15u);
+        b[3] = nib_to_bytes((bits >> 12) & 15u);
+#pragma unroll
+        for (int h = 0; h < RG; ++h)
+          if (hl[h]) acc[h] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[h][t], b, acc[h], 0, 0, 0);
+      }
+    }
+    int pc = pcp + __shfl_xor(pcp, 16, kWave);
+    pc += __shfl_xor(pc, 32, kWave);
+    // lanes past the end hold the last code's factors; their rows do not pass
+    const float ct = s.metric != 0 ? -fi : code_term_l2(sf);
+#pragma unroll
+    for (int h = 0; h < RG; ++h) {
+      if (!hl[h]) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * h + 4 * grp + i;
+        const RowInfo& ri = rows[row];
+        float dist, lbe;
+        const int ipv = acc[h][i] + s.qoff * pc;
+        estimate(ri.rec, ri.t, sf, ct, ipv, pc, dist, lbe);
+        const bool live = pvalid && ri.valid;
+        const float lb = live ? lbe : __builtin_inff();
+        const bool pass = live && lb <= ri.tau;
+        if constexpr (DEBUG) {
+          if (row == 0 && live) {
+            const int64_t o = p - dbg_base;
+            dbg_ip[o] = ipv;
+            dbg_pc[o] = pc;
+            dbg_est[o] = estimate_est(ri.rec, s.fac[p].y, ipv, pc);
+            dbg_dist[o] = dist;
+            dbg_lb[o] = lb;
+          }
+        } else {
+          // this row group's 16 codes: bits 16 grp .. +15 of the ballot
+          const uint32_t mine = (uint32_t)(__ballot(pass) >> (16 * grp)) & 0xFFFFu;
+          if (pass) {
+            Cand cd;
+            cd.pos = (int32_t)p;
+            cd.lb = lb;
+            s.seg[ri.seg_base + cnt[h][i] + __popc(mine & ((1u << col) - 1u))] = cd;
+          }
+          cnt[h][i] += __popc(mine);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NA; ++t) bw[t] = nb[t];
+    sf = nsf;
+    fi = nfi;
+  }
+  if constexpr (!DEBUG) {
+    if (col == 0) {
+#pragma unroll
+      for (int h = 0; h < RG; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const RowInfo& ri = rows[16 * h + 4 * grp + i];
+          if (ri.valid) s.seg_count[ri.count_slot] = cnt[h][i];
+        }
+    }
+  }
+}
+
+template <bool F4, int WS, int RG>
+__global__ __launch_bounds__(kThreads) void k_scan_mfma_w(SearchDev s) {
+  constexpr int R = 16 * RG;
+  __shared__ RowInfo rows_all[kThreads / kWave][R];
+  const int lane = lane_id();
+  RowInfo* rows = rows_all[threadIdx.x / kWave];
+  const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
+  const int64_t total = uniform_i64(s.mf_unit_off[s.nlist]);
+  for (;;) {
+    unsigned long long cl = 0;
+    if (lane == 0) cl = atomicAdd(&s.counters[2], 1ull);
+    const int64_t u = uniform_i64((int64_t)cl);   // lane 0's claim (every lane is active)
+    if (u >= total) break;
+    const int list = wave_find_list(s.mf_unit_off, s.nlist, u);
+    const int64_t local = uniform_i64(u - s.mf_unit_off[list]);
+    const int cnt = uniform_i32((int)(s.mf_pair_off[list + 1] - s.mf_pair_off[list]));
+    const int ngroups = (cnt + R - 1) / R;
+    const int c = (int)(local / ngroups);
+    const int gi = (int)(local - (int64_t)c * ngroups);
+    const int64_t lbeg = uniform_i64(s.list_off[list]), lend = uniform_i64(s.list_off[list + 1]);
+    const int64_t start = lbeg + (int64_t)c * s.chunk;
+    const int64_t end = lend < start + s.chunk ? lend : start + s.chunk;
+    int g = -1;
+    if (lane < R) {
+      RowInfo ri;
+      ri.valid = 0;
+      ri.tau = -__builtin_inff();
+      ri.seg_base = 0;
+      ri.count_slot = -1;
+      ri.rec.k1 = ri.rec.k2 = ri.rec.k0 = ri.rec.b = 0.f;
+      ri.t.pt = ri.t.coef = ri.t.coefh = 0.f;
+      if (R * gi + lane < cnt) {
+        g = s.mf_pairs[s.mf_pair_off[list] + R * gi + lane];
+        const int64_t q = g / s.nprobe;
+        const int r = (int)(g - q * s.nprobe);
+        ri.rec = s.pairs[g];
+        ri.t = s.metric != 0 ? pair_terms_ip(ri.rec, hwk, s.pair_pt[g]) : pair_terms(ri.rec, hwk);
+        if (c >= first_main_chunk(s, q, r)) {
+          ri.valid = 1;
+          ri.tau = s.tau[q];
+          const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
+          const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
+          ri.seg_base = s.off_seg[q] + codeoff[r] + (int64_t)c * s.chunk;
+          ri.count_slot = s.off_ch[q] + choff[r] + c;
+        }
+      }
+      rows[lane] = ri;
+    }
+    mfma_wave_unit<false, F4, WS, RG>(s, start, end, rows, g, s.qu8, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                      0);
+  }
+}
+
+// Debug: one caller-given quantised query (row 0) against a whole list, one
+// wave per chunk, through the wave-unit code the search runs.
+template <bool F4, int WS, int RG>
+__global__ __launch_bounds__(kWave) void k_debug_mfma_w(SearchDev s, const PairRec* recp, const int8_t* qu8,
+                                                        int32_t list, int32_t* ip, int32_t* pc, float* est,
+                                                        float* dist, float* lb) {
+  constexpr int R = 16 * RG;
+  __shared__ RowInfo rows[R];
+  const int lane = lane_id();
+  const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
+  if (lane < R) {
+    RowInfo ri;
+    ri.valid = lane == 0;
+    ri.tau = __builtin_inff();
+    ri.seg_base = 0;
+    ri.count_slot = -1;
+    ri.rec = *recp;
+    ri.t = s.metric != 0 ? pair_terms_ip(ri.rec, hwk, s.pair_pt[0]) : pair_terms(ri.rec, hwk);
+    rows[lane] = ri;
+  }
+  const int64_t lbeg = uniform_i64(s.list_off[list]), lend = uniform_i64(s.list_off[list + 1]);
+  const int64_t start = lbeg + (int64_t)blockIdx.x * s.chunk;
+  const int64_t end = lend < start + s.chunk ? lend : start + s.chunk;
+  if (start >= end) return;
+  mfma_wave_unit<true, F4, WS, RG>(s, start, end, rows, lane == 0 ? 0 : -1, qu8, ip, pc, est, dist, lb, lbeg);
+}
+
 // Clears the per-list pair counters (a kernel rather than a memset, so that
 // the sequence can be captured in a graph).
 __global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
@@ -539,7 +834,43 @@ const void* kernel_for(int W, int rg) {
 #undef RBQ_MF
 }
 
-const void* pick_kernel(bool f4, bool dbg, int W, int rg) {
+// Wave-unit kernels: the query fragments of 16 RG rows in registers, for the
+// exact compile-time widths (RG = 2 up to 12 words).
+template <bool F4, bool DBG>
+const void* wave_kernel_for(int W, int rg) {
+#define RBQ_MW(WS_, RG_) (DBG ? (const void*)k_debug_mfma_w<F4, WS_, RG_> : (const void*)k_scan_mfma_w<F4, WS_, RG_>)
+  if (rg == 1) {
+    switch (W) {
+      case 1: return RBQ_MW(1, 1);
+      case 2: return RBQ_MW(2, 1);
+      case 3: return RBQ_MW(3, 1);
+      case 4: return RBQ_MW(4, 1);
+      case 8: return RBQ_MW(8, 1);
+      case 12: return RBQ_MW(12, 1);
+      case 15: return RBQ_MW(15, 1);
+      case 16: return RBQ_MW(16, 1);
+      default: return nullptr;
+    }
+  }
+  if (rg == 2) {
+    switch (W) {
+      case 2: return RBQ_MW(2, 2);
+      case 4: return RBQ_MW(4, 2);
+      case 12: return RBQ_MW(12, 2);
+      default: return nullptr;
+    }
+  }
+  return nullptr;
+#undef RBQ_MW
+}
+
+// The batched scan kernel for (W, rg): the wave-unit form where it exists,
+// else the block form. *wave tells which.
+const void* pick_kernel(bool f4, bool dbg, int W, int rg, bool* wave) {
+  const void* f = f4 ? (dbg ? wave_kernel_for<true, true>(W, rg) : wave_kernel_for<true, false>(W, rg))
+                     : (dbg ? wave_kernel_for<false, true>(W, rg) : wave_kernel_for<false, false>(W, rg));
+  *wave = f != nullptr;
+  if (f) return f;
   if (f4) return dbg ? kernel_for<true, true>(W, rg) : kernel_for<true, false>(W, rg);
   return dbg ? kernel_for<false, true>(W, rg) : kernel_for<false, false>(W, rg);
 }
@@ -579,9 +910,10 @@ int mfma_row_groups(int dp, bool f4, int want) {
 }
 
 int scan_mfma_blocks_per_cu(int dp, bool f4, int rg) {
-  const void* f = pick_kernel(f4, false, dp / 64, rg);
-  const size_t bytes = (size_t)16 * rg * row_bytes(f4, dp);
-  allow_lds(f, bytes);
+  bool wave = false;
+  const void* f = pick_kernel(f4, false, dp / 64, rg, &wave);
+  const size_t bytes = wave ? 0 : (size_t)16 * rg * row_bytes(f4, dp);
+  if (!wave) allow_lds(f, bytes);
   int v = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, f, kThreads, bytes) != hipSuccess || v < 1) v = 1;
   return v;
@@ -609,9 +941,10 @@ hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t
   hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, st, s);
   hipLaunchKernelGGL(k_group_scatter, dim3(g1), dim3(256), 0, st, s);
   const bool f4 = s.mfma_f4 != 0;
-  const void* f = pick_kernel(f4, false, s.W, s.mf_rg);
-  const size_t bytes = (size_t)16 * s.mf_rg * row_bytes(f4, s.dp);
-  allow_lds(f, bytes);
+  bool wave = false;
+  const void* f = pick_kernel(f4, false, s.W, s.mf_rg, &wave);
+  const size_t bytes = wave ? 0 : (size_t)16 * s.mf_rg * row_bytes(f4, s.dp);
+  if (!wave) allow_lds(f, bytes);
   void* args[] = {(void*)&s};
   return hipLaunchKernel(f, dim3(grid), dim3(kThreads), args, bytes, st);
 }
@@ -621,12 +954,13 @@ hipError_t launch_debug_mfma(const SearchDev& s, const PairRec* rec, const int8_
                              float* dist, float* lb, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
   const bool f4 = s.mfma_f4 != 0;
-  const void* f = pick_kernel(f4, true, s.W, s.mf_rg);
-  const size_t bytes = (size_t)16 * s.mf_rg * row_bytes(f4, s.dp);
-  allow_lds(f, bytes);
+  bool wave = false;
+  const void* f = pick_kernel(f4, true, s.W, s.mf_rg, &wave);
+  const size_t bytes = wave ? 0 : (size_t)16 * s.mf_rg * row_bytes(f4, s.dp);
+  if (!wave) allow_lds(f, bytes);
   void* args[] = {(void*)&s, (void*)&rec, (void*)&qu8, (void*)&list, (void*)&ip, (void*)&pc,
                   (void*)&est, (void*)&dist, (void*)&lb};
-  return hipLaunchKernel(f, dim3(nchunks), dim3(kThreads), args, bytes, st);
+  return hipLaunchKernel(f, dim3(nchunks), dim3(wave ? kWave : kThreads), args, bytes, st);
 }
 
 }  // namespace rbq

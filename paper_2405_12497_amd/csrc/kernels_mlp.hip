@@ -19,68 +19,87 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {   // round to nearest eve
 }
 
 // ------------------------------------------------------------------ features
+// Quantiser statistics of query q against its r-th nearest list, by one wave:
+// b = ||q_r - c|| (raw vectors), v_l = min / b and v_r = max / b of the
+// rotated residual q_rot - c_rot, and E[S_q] / (15 dp), the expectation of the
+// randomized rounding's sum (unbiased, Theorem 3.3): the mean of
+// (r_i - min) / (max - min) over the dp coordinates. out: {b, v_l, v_r, esq}.
+__device__ __forceinline__ void list_stats(const FeatDev& f, int64_t q, int r, float* out) {
+  const int lane = lane_id();
+  const int navail = f.navail;
+  const float* qr = f.q + q * f.dim;
+  const float* qrot = f.qrot + q * f.dp;
+  const int list = uniform_i32(f.probe[q * f.stride + min(r, navail - 1)]);
+  const float* c = f.cent + (int64_t)list * f.dim;
+  const float* crot = f.crot + (int64_t)list * f.dp;
+  float acc = 0.f;
+  for (int i = lane; i < f.dim; i += kWave) {
+    const float d = qr[i] - c[i];
+    acc = fmaf(d, d, acc);
+  }
+  const float b = sqrtf(wave_sum(acc));
+  float rmin = __builtin_inff(), rmax = -__builtin_inff(), rsum = 0.f;
+  for (int t = 0; t < f.W; ++t) {
+    const float v = qrot[t * kWave + lane] - crot[t * kWave + lane];
+    rmin = fminf(rmin, v);
+    rmax = fmaxf(rmax, v);
+    rsum += v;
+  }
+  rmin = wave_min(rmin);
+  rmax = wave_max(rmax);
+  rsum = wave_sum(rsum);
+  const float range = rmax - rmin;
+  const bool live = (b > 0.f) && (range > 0.f);
+  if (lane == 0) {
+    out[0] = b;
+    out[1] = b > 0.f ? rmin / b : 0.f;
+    out[2] = b > 0.f ? rmax / b : 0.f;
+    out[3] = live ? (rsum - (float)f.dp * rmin) / (range * (float)f.dp) : 0.f;
+  }
+}
+
+// Slots 0..63 of query q's features: log d_(1) and log(d_(j) / d_(1)) of its 64
+// nearest squared centroid distances (probe_d, nearest first), by one wave.
+__device__ __forceinline__ void distance_features(const FeatDev& f, int64_t q, float* out) {
+  const int lane = lane_id();
+  const float* dq = f.probe_d + q * f.stride;
+  const float tiny = 1e-30f;
+  const float l1 = logf(fmaxf(dq[0], tiny));
+  const int j = lane;   // 64 lanes, 64 slots
+  const float dj = fmaxf(dq[min(j, f.navail - 1)], tiny);
+  out[j] = j == 0 ? l1 : logf(dj) - l1;
+}
+
+// Slots 64..95 from the 8 lists' statistics st[r][0..3] (lanes 0..31).
+__device__ __forceinline__ void stats_features(const float* st, float* out) {
+  const int lane = lane_id();
+  if (lane < 4 * kMlpStats) {
+    const int r = lane >> 2, k = lane & 3;
+    const float b0 = fmaxf(st[0], 1e-30f);
+    const float v = st[4 * r + k];
+    out[kMlpNear + lane] = k == 0 ? v / b0 : v;
+  }
+}
+
 // The 96 features of query q by one wave, written to out (global or LDS).
 // probe_d: the query's 64 (or nlist) nearest squared centroid distances,
 // nearest first; probe: their list ids.
 __device__ __forceinline__ void query_features(const FeatDev& f, int64_t q, float* out) {
-  const int lane = lane_id();
-  const float* dq = f.probe_d + q * f.stride;
-  const int navail = f.navail;
-  const float tiny = 1e-30f;
-  // slots 0..63
-  const float d1 = fmaxf(dq[0], tiny);
-  const float l1 = logf(d1);
-  {
-    const int j = lane;   // 64 lanes, 64 slots
-    const float dj = fmaxf(dq[min(j, navail - 1)], tiny);
-    out[j] = j == 0 ? l1 : logf(dj) - l1;
-  }
-  // slots 64..95: quantiser statistics of the 8 nearest lists
-  const float* qr = f.q + q * f.dim;
-  const float* qrot = f.qrot + q * f.dp;
-  float b0 = 0.f;
-  for (int r = 0; r < kMlpStats; ++r) {
-    const int list = uniform_i32(f.probe[q * f.stride + min(r, navail - 1)]);
-    const float* c = f.cent + (int64_t)list * f.dim;
-    const float* crot = f.crot + (int64_t)list * f.dp;
-    float acc = 0.f;
-    for (int i = lane; i < f.dim; i += kWave) {
-      const float d = qr[i] - c[i];
-      acc = fmaf(d, d, acc);
-    }
-    const float b = sqrtf(wave_sum(acc));
-    float rmin = __builtin_inff(), rmax = -__builtin_inff();
-    for (int t = 0; t < f.W; ++t) {
-      const float v = qrot[t * kWave + lane] - crot[t * kWave + lane];
-      rmin = fminf(rmin, v);
-      rmax = fmaxf(rmax, v);
-    }
-    rmin = wave_min(rmin);
-    rmax = wave_max(rmax);
-    const float range = rmax - rmin;
-    const bool live = (b > 0.f) && (range > 0.f);
-    const float scale = live ? 15.f / range : 0.f;
-    const uint64_t qid = (uint64_t)(f.qid_base + q);
-    int sq = 0;
-    for (int t = 0; t < f.W; ++t) {
-      const int i = t * kWave + lane;
-      if (live) {
-        const float x = (qrot[i] - crot[i] - rmin) * scale;
-        sq += min(15, (int)floorf(x + rounding_u(f.seed, qid, (uint32_t)list, (uint32_t)i)));
-      }
-    }
-    sq = wave_sum_i(sq);
-    if (r == 0) b0 = fmaxf(b, tiny);
-    if (lane == 0) {
-      const float vl = b > 0.f ? rmin / b : 0.f;
-      const float vr = b > 0.f ? rmax / b : 0.f;
-      float* o = out + kMlpNear + 4 * r;
-      o[0] = b / b0;
-      o[1] = vl;
-      o[2] = vr;
-      o[3] = (float)sq / (15.f * (float)f.dp);
-    }
-  }
+  distance_features(f, q, out);
+  __shared__ float st_all[4][4 * kMlpStats];   // per wave of a 256-thread block
+  float* st = st_all[(threadIdx.x >> 6) & 3];
+  for (int r = 0; r < kMlpStats; ++r) list_stats(f, q, r, st + 4 * r);
+  __builtin_amdgcn_wave_barrier();
+  stats_features(st, out);
+}
+
+// One wave per (query, list rank < 8).
+__global__ __launch_bounds__(256) void k_list_stats(FeatDev f) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= f.nq * kMlpStats) return;   // whole waves
+  const int64_t q = w / kMlpStats;
+  const int r = (int)(w - q * kMlpStats);
+  list_stats(f, q, r, f.stats + w * 4);
 }
 
 // One wave per query.
@@ -296,9 +315,11 @@ __global__ __launch_bounds__(256) void k_learned_front(FeatDev f, const u16x8* _
   __shared__ float Z[kFuseQ][kMlpOut + 1];
   const int wave = threadIdx.x >> 6, lane = lane_id();
   const int64_t q0 = (int64_t)blockIdx.x * kFuseQ;
+  // features: distances from the probe, list statistics from k_list_stats
   for (int r = wave; r < kFuseQ; r += 4) {
     if (q0 + r < f.nq) {
-      query_features(f, q0 + r, X[r]);
+      distance_features(f, q0 + r, X[r]);
+      stats_features(f.stats + (q0 + r) * 4 * kMlpStats, X[r]);
     } else {
       for (int j = lane; j < kMlpIn; j += kWave) X[r][j] = 0.f;
     }
@@ -479,6 +500,12 @@ __global__ void k_bucket_labels(const int32_t* __restrict__ need, int64_t n, int
 hipError_t launch_bucket_labels(const int32_t* need, int64_t n, int32_t* labels, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bucket_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, need, n, labels);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_stats(const FeatDev& f, hipStream_t st) {
+  if (f.nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_list_stats, dim3((unsigned)((f.nq * kMlpStats + 3) / 4)), dim3(256), 0, st, f);
   return hipGetLastError();
 }
 

@@ -181,6 +181,11 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     const int npl = NPL > 0 ? NPL : s.npl;   // bit planes (B_q), compile-time when given
     uint64_t* pl = s.planes + g * npl * W;
     int8_t* q8 = s.qu8 ? s.qu8 + g * s.dp : nullptr;
+    // with the MFMA scan, only the pairs whose first chunk is a bootstrap chunk
+    // (scanned by the popcount phase 0) need bit planes
+    const int64_t r = g - q * s.nprobe;
+    const bool planes =
+        !s.boot_planes_only || uniform_i32(s.pair_choff[q * (s.nprobe + 1) + r]) < uniform_i32(s.q_p0[q]);
 #pragma unroll
     for (int t = 0; t < WS; ++t) {
       if (t < W) {
@@ -190,6 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
         const int qu = min(s.qmax, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
         sq += qu;
         if (q8) q8[i] = (int8_t)(qu - s.qoff);
+        if (!planes) continue;
         if constexpr (NPL > 0) {   // all ballots first, then one branch for the stores
           uint64_t w[NPL > 0 ? NPL : 1];
 #pragma unroll
@@ -1054,8 +1060,9 @@ __global__ __launch_bounds__(kThreads, WIDE ? 3 : 4) void k_finalize(SearchDev s
   }
   const int64_t wid = (int64_t)blockIdx.x * kWaves + wave;
   if (wid >= s.nq * W) return;   // whole waves
-  const int64_t q = wid / W;
-  const int wsub = (int)(wid - q * W);
+  const int64_t qi = wid / W;
+  const int64_t q = s.q_order ? (int64_t)uniform_i32(s.q_order[qi]) : qi;
+  const int wsub = (int)(wid - qi * W);
   const int K = s.k;
   uint64_t* win = fin_lds + (size_t)wave * fin_lds_words(K);
   uint64_t* rnd = win + kFinWin;
@@ -1286,10 +1293,11 @@ __global__ __launch_bounds__(kThreads, WIDE ? 3 : 4) void k_finalize(SearchDev s
       s.q_cand[q] = ncand;
     }
   } else {
-    for (int i = lane; i < K; i += kWave) part[wid * K + i] = i < cnt ? top[i] : ~0ull;
+    const int64_t slot = q * W + wsub;   // the merge reads query q's W partial results
+    for (int i = lane; i < K; i += kWave) part[slot * K + i] = i < cnt ? top[i] : ~0ull;
     if (lane == 0) {
-      pst[wid * 2] = reranked - seeds;
-      pst[wid * 2 + 1] = ncand;
+      pst[slot * 2] = reranked - seeds;
+      pst[slot * 2 + 1] = ncand;
     }
   }
 }
@@ -1513,6 +1521,56 @@ int finalize_split(int64_t nq, int k) {
   w = std::min(w, kFinSplitMax);
   w = std::min(w, kFinMergeCap / std::max(k, 1));
   return std::max(w, 1);
+}
+
+namespace {
+constexpr int kOrderBins = 64;
+
+__global__ void k_zero_i32(int32_t* __restrict__ p, int64_t n) {   // a kernel, not a memset: capturable
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__device__ __forceinline__ int order_bin(int npq, int nprobe) {
+  return min(kOrderBins - 1, (int)((int64_t)min(max(npq, 1), nprobe) * kOrderBins / (nprobe + 1)));
+}
+
+__global__ void k_order_hist(const int32_t* __restrict__ npq, int64_t nq, int nprobe, int32_t* hist) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nq) atomicAdd(&hist[order_bin(npq[q], nprobe)], 1);
+}
+
+// One wave: hist[b] -> the first slot of bin b, bins in descending order.
+__global__ void k_order_scan(int32_t* hist) {
+  const int lane = threadIdx.x;   // kOrderBins == kWave
+  const int b = kOrderBins - 1 - lane;   // lane 0 holds the heaviest bin
+  const int c = hist[b];
+  int inc = c;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  hist[kOrderBins + b] = inc - c;
+}
+
+__global__ void k_order_scatter(const int32_t* __restrict__ npq, int64_t nq, int nprobe, int32_t* hist,
+                                int32_t* __restrict__ order) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nq) order[atomicAdd(&hist[kOrderBins + order_bin(npq[q], nprobe)], 1)] = (int32_t)q;
+}
+}  // namespace
+
+hipError_t launch_query_order(const int32_t* nprobe_q, int64_t nq, int nprobe, int32_t* hist, int32_t* order,
+                              hipStream_t st) {
+  static_assert(kOrderBins == kWave, "one lane per bin");
+  if (nq <= 0) return hipSuccess;
+  const unsigned g = (unsigned)((nq + 255) / 256);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(2 * kOrderBins), 0, st, hist, (int64_t)(2 * kOrderBins));
+  hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, st, nprobe_q, nq, nprobe, hist);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kWave), 0, st, hist);
+  hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, st, nprobe_q, nq, nprobe, hist, order);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize_split(const SearchDev& s, int W, uint64_t* part, int32_t* pst, hipStream_t st) {

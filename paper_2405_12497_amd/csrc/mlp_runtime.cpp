@@ -138,6 +138,7 @@ rbq_status features_into(rbq_index* idx, const float* queries, int64_t nq, int64
   rs = front(idx, queries, nq, nsel, nullptr, st);
   if (rs != RBQ_OK) return rs;
   FeatDev f;
+  f.stats = nullptr;
   f.feats = feats;
   f.probe_d = (const float*)idx->ws.probe_d.p;
   f.probe = (const int32_t*)idx->ws.probe.p;
@@ -185,9 +186,11 @@ rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int 
   Workspace& w = idx->ws;
   HIPCHK(w.nprobe_q.ensure((size_t)nq * 4));
   HIPCHK(w.q_fb.ensure((size_t)nq * 4));
+  HIPCHK(w.lstats.ensure((size_t)nq * kMlpStats * 4 * sizeof(float)));
   rbq_status rs = front(idx, queries, nq, stride, nullptr, st);
   if (rs != RBQ_OK) return rs;
   FeatDev f;
+  f.stats = (float*)w.lstats.p;
   f.feats = nullptr;
   f.probe_d = (const float*)w.probe_d.p;
   f.probe = (const int32_t*)w.probe.p;
@@ -203,6 +206,7 @@ rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int 
   f.nq = nq;
   f.qid_base = qid_base;
   f.seed = idx->prm.seed;
+  HIPCHK(launch_list_stats(f, st));
   HIPCHK(launch_learned_front(f, (const uint16_t*)idx->mlp.wfrag.p, (const float*)idx->mlp.w32.p,
                               idx->mlp.threshold, nprobe_max, (int32_t*)w.nprobe_q.p, (int32_t*)w.q_fb.p, st));
   *out = (const int32_t*)w.nprobe_q.p;

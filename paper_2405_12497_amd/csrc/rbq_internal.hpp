@@ -267,6 +267,7 @@ struct SearchDev {
   int qoff;                 // int8 copy of q_u holds q_u - qoff (128 for B_q = 8, else 0)
   int metric;               // 0: squared L2; 1: inner product (cosine runs as IP on unit vectors)
   int mfma_f4;              // batched scan on FP8 x FP4 scaled MFMA instead of int8
+  int boot_planes_only;     // 1: bit planes only for the pairs phase 0 scans (the rest go to the MFMA scan)
   int mf_rg;                // batched scan: groups of 16 query rows per work unit (1, 2 or 4)
   const float* fip;         // inner product: per code <o_r - c, c>
   float* pair_pt;           // inner product: per pair M_q - <q_r, c>
@@ -285,6 +286,7 @@ struct SearchDev {
   int boot;                 // bootstrap target: phase 0 covers >= boot codes (boot >= k)
   const int32_t* probe;     // nq x nprobe
   const int32_t* nprobe_q;  // nq or null
+  const int32_t* q_order;   // nq or null: the rerank's query order (largest nprobe first)
   // per pair
   PairRec* pairs;           // nq x nprobe
   uint64_t* planes;         // nq x nprobe x npl x W
@@ -348,6 +350,11 @@ hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream
 hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t st);
 hipError_t launch_tau(const SearchDev& s, hipStream_t st);
 hipError_t launch_finalize(const SearchDev& s, hipStream_t st);
+// Query order for the rerank: queries by descending per-query nprobe (64
+// bins; order within a bin unspecified), so the longest reranks start first.
+// hist: 128 int32 of scratch; order: nq int32.
+hipError_t launch_query_order(const int32_t* nprobe_q, int64_t nq, int nprobe, int32_t* hist, int32_t* order,
+                              hipStream_t st);
 
 // debug: list scan with a given quantised query
 hipError_t launch_debug_pack(const uint8_t* qu, int dp, int W, int npl, int qoff, float b, float vl, float delta,

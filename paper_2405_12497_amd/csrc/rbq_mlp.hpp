@@ -36,9 +36,13 @@ struct FeatDev {
   int dim, dp, W;
   int64_t nq, qid_base;
   uint64_t seed;
+  float* stats;            // nq x 8 x 4: {b, v_l, v_r, E[S_q] / (15 dp)} of the 8 nearest lists
 };
 
 hipError_t launch_features(const FeatDev& f, hipStream_t st);
+// The quantiser statistics of each query's 8 nearest lists into f.stats, one
+// wave per (query, list); launch_learned_front reads them.
+hipError_t launch_list_stats(const FeatDev& f, hipStream_t st);
 hipError_t launch_gemm_bf16(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk,
                             int64_t sbn, float* C, int64_t ldc, int M, int N, int K, bool accumulate,
                             hipStream_t st);

@@ -107,6 +107,8 @@ uint64_t host_splitmix64(uint64_t x);
 struct Workspace {
   DBuf qrot, cd, cgmin, probe, probe_d, pairs, planes, qu8, pair_choff, pair_codeoff;
   DBuf q_nch, q_p0, q_n0, q_ncode, offs, counters, seg, seg_count, p0buf, tau, seedk;
+  DBuf q_order, order_hist;   // rerank query order (per-query nprobe)
+  DBuf lstats;                // learned nprobe: statistics of each query's 8 nearest lists
   DBuf chunk_qcode;   // chunk (query order) -> first query-code index
   DBuf q_boot, q_rerank, q_cand, nprobe_q, q_fb, feats, tmp;
   DBuf pair_pt, q_m, qn;    // inner-product metrics: pair constants, M_q, normalised queries (cosine)
@@ -201,8 +203,10 @@ rbq_status learned_nprobe(rbq_index* idx, const float* queries, int64_t nq, int 
 rbq_status mlp_reserve(rbq_index* idx, int64_t rows);
 rbq_status rotate_rows(rbq_index* idx, const float* X, int64_t lda, const float* sub,
                        const int32_t* sel, int64_t M, float* Y, hipStream_t st);
+// seg_exact: leave the candidate segments to the caller (sized after the plan
+// from the exact code counts) instead of the worst case nq * max_codes(nprobe).
 rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma,
-                            int fin_w = 1);
+                            int fin_w = 1, bool seg_exact = false);
 SearchDev make_dev(rbq_index* idx, const float* queries, int64_t nq, int nprobe, int k, int chunk,
                    const int32_t* nprobe_q, int64_t qid_base, bool mfma, int64_t* out_ids,
                    float* out_d);
@@ -220,7 +224,12 @@ rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
 // (NULL: all use the fixed value) and the probe stride.
 rbq_status search_locked(rbq_index* idx, const float* queries, int64_t nq, rbq_search_opts o, int64_t* out_ids,
                          float* out_dists, rbq_search_stats* stats, hipStream_t st, const TuneEntry* force);
+// seg_cap > 0: size the candidate segments from the plan's exact code counts
+// (one stream synchronisation) and search only the first *done queries whose
+// segments fit in seg_cap bytes (at least one); seg_cap = 0: all nq queries
+// with worst-case segments.
 rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& opts,
                       int scan_kernel, int chunk, int mf_rg, bool learned, int64_t* out_ids, float* out_d,
-                      hipStream_t st, const int32_t** used_npq, int* used_stride);
+                      hipStream_t st, const int32_t** used_npq, int* used_stride, int64_t seg_cap = 0,
+                      int64_t* done = nullptr);
 }  // namespace rbq

@@ -255,7 +255,7 @@ std::vector<DBuf*> rbq_index::all_buffers() {
           &ws.planes, &ws.qu8, &ws.pair_choff, &ws.pair_codeoff, &ws.q_nch, &ws.q_p0, &ws.q_n0,
           &ws.q_ncode, &ws.offs, &ws.counters, &ws.seg, &ws.seg_count, &ws.p0buf, &ws.tau,
           &ws.chunk_qcode,
-          &ws.seedk, &ws.q_boot, &ws.q_rerank, &ws.q_cand, &ws.pair_pt, &ws.q_m, &ws.qn, &ws.nprobe_q, &ws.q_fb, &ws.feats, &ws.tmp,
+          &ws.seedk, &ws.q_order, &ws.order_hist, &ws.lstats, &ws.q_boot, &ws.q_rerank, &ws.q_cand, &ws.pair_pt, &ws.q_m, &ws.qn, &ws.nprobe_q, &ws.q_fb, &ws.feats, &ws.tmp,
           &ws.mf_cnt, &ws.mf_fill, &ws.mf_pair_off, &ws.mf_unit_off, &ws.mf_pairs, &ws.units0,
           &ws.units1, &ws.fin_part, &ws.fin_pst, &ws.tau_part,
           &mlp.w32, &mlp.wbf, &mlp.wfrag, &mlp.grad, &mlp.m, &mlp.v, &mlp.act};
@@ -630,7 +630,8 @@ extern "C" rbq_status rbq_index_build_rotation(rbq_index* idx, const float* data
 // ------------------------------------------------------------------ search
 namespace rbq {
 
-rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma, int fin_w) {
+rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int chunk, bool mfma, int fin_w,
+                            bool seg_exact) {
   Workspace& w = idx->ws;
   const int dp = idx->dp, W = idx->W;
   const int64_t np = nq * nprobe;
@@ -657,7 +658,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.q_ncode.ensure((size_t)nq * 8));
   HIPCHK(w.offs.ensure((size_t)5 * (nq + 1 + (nq + kOffQ - 1) / kOffQ) * 8));
   HIPCHK(w.counters.ensure(64));
-  HIPCHK(w.seg.ensure((size_t)nq * std::max<int64_t>(1, idx->max_codes(nprobe)) * sizeof(Cand)));
+  if (!seg_exact) HIPCHK(w.seg.ensure((size_t)nq * std::max<int64_t>(1, idx->max_codes(nprobe)) * sizeof(Cand)));
   HIPCHK(w.seg_count.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
   HIPCHK(w.chunk_qcode.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
   HIPCHK(w.units0.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * sizeof(UnitDesc)));
@@ -832,7 +833,9 @@ int scan_grid(rbq_index* idx, int64_t nq, int64_t units_per_query, int blocks_pe
 
 rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rbq_search_opts& opts,
                       int scan_kernel, int chunk, int mf_rg, bool learned, int64_t* out_ids, float* out_d,
-                      hipStream_t st, const int32_t** used_npq, int* used_stride) {
+                      hipStream_t st, const int32_t** used_npq, int* used_stride, int64_t seg_cap,
+                      int64_t* done) {
+  if (done) *done = nq;
   const bool mfma = scan_kernel == RBQ_SCAN_MFMA || scan_kernel == RBQ_SCAN_MFMA_FP4;
   rbq_search_opts o = opts;
   const int32_t* nprobe_q = o.nprobe_per_query;
@@ -841,7 +844,7 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   // its per-query nprobe (at most the caller's nprobe).
   if (learned) o.nprobe = std::max(o.nprobe, std::min(kMlpNear, idx->nlist));
   const int fin_w = fin_waves(o.rerank_waves, nq, o.k);
-  rbq_status rs = ensure_workspace(idx, nq, o.nprobe, o.k, chunk, mfma, fin_w);
+  rbq_status rs = ensure_workspace(idx, nq, o.nprobe, o.k, chunk, mfma, fin_w, seg_cap > 0);
   if (rs != RBQ_OK) return rs;
   rs = prepare_queries(idx, queries, nq, st, &queries);
   if (rs != RBQ_OK) return rs;
@@ -878,8 +881,24 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
                          out_ids, out_d);
   s.mfma_f4 = scan_kernel == RBQ_SCAN_MFMA_FP4 ? 1 : 0;
   s.mf_rg = mfma_row_groups(idx->dp, s.mfma_f4 != 0, mf_rg);
+  s.boot_planes_only = mfma ? 1 : 0;
   HIPCHK(rec(1));
   HIPCHK(launch_plan(s, st));
+  if (seg_cap > 0) {
+    // the plan's exact code counts: the longest prefix of the batch whose
+    // segments fit in seg_cap (the rest is searched by the caller's next call)
+    std::vector<int64_t> off((size_t)nq + 1);
+    HIPCHK(hipMemcpyAsync(off.data(), s.off_seg, off.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t cap_codes = seg_cap / (int64_t)sizeof(Cand);
+    int64_t m = (int64_t)(std::upper_bound(off.begin() + 1, off.end(), cap_codes) - off.begin()) - 1;
+    m = std::max<int64_t>(1, std::min(m, nq));
+    HIPCHK(idx->ws.seg.ensure((size_t)std::max<int64_t>(1, off[(size_t)m]) * sizeof(Cand)));
+    s.seg = (Cand*)idx->ws.seg.p;
+    s.nq = m;
+    nq = m;
+    if (done) *done = m;
+  }
   HIPCHK(launch_prep(s, true, st));
   const int64_t chunks = idx->max_chunks(o.nprobe, chunk);
   const int bpc = scan_popcnt_blocks_per_cu(idx->W, s.npl);
@@ -899,6 +918,13 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   }
   HIPCHK(rec(5));
   s.prof_acc = pf.on ? (unsigned long long*)pf.acc.p : nullptr;   // codes counted by finalize
+  if (nprobe_q) {   // uneven reranks: the largest nprobe first
+    HIPCHK(idx->ws.q_order.ensure((size_t)nq * 4));
+    HIPCHK(idx->ws.order_hist.ensure(128 * 4));
+    HIPCHK(launch_query_order(nprobe_q, nq, o.nprobe, (int32_t*)idx->ws.order_hist.p, (int32_t*)idx->ws.q_order.p,
+                              st));
+    s.q_order = (const int32_t*)idx->ws.q_order.p;
+  }
   HIPCHK(launch_finalize_split(s, fin_w, (uint64_t*)idx->ws.fin_part.p, (int32_t*)idx->ws.fin_pst.p, st));
   HIPCHK(rec(6));
   return RBQ_OK;
@@ -970,6 +996,7 @@ rbq_status search_graph(rbq_index* idx, const float* queries, int64_t nq, const 
     if (learned) {
       HIPCHK(idx->ws.nprobe_q.ensure((size_t)hint * 4));
       HIPCHK(idx->ws.q_fb.ensure((size_t)hint * 4));
+      HIPCHK(idx->ws.lstats.ensure((size_t)hint * kMlpStats * 4 * sizeof(float)));
       rs = mlp_reserve(idx, hint);
       if (rs != RBQ_OK) return rs;
     }
@@ -1142,8 +1169,19 @@ rbq_status rbq::search_locked(rbq_index* idx, const float* queries, int64_t nq, 
   // (same stream and workspace; queries keep their ids qid_base + i).
   const int stride_req = learned ? std::max(o.nprobe, std::min(kMlpNear, idx->nlist)) : o.nprobe;
   const int64_t seg_row = std::max<int64_t>(1, idx->max_codes(stride_req)) * (int64_t)sizeof(Cand);
-  const int64_t sub = std::max<int64_t>(1, std::min<int64_t>(nq, seg_budget() / seg_row));
+  const int64_t budget = seg_budget();
+  const int64_t sub = std::max<int64_t>(1, std::min<int64_t>(nq, budget / seg_row));
   const bool graph = o.use_graph && !idx->prof.on && sub == nq;
+  // Where the worst case would split an eager batch, the segments are sized
+  // from the plan's exact code counts instead (one synchronisation per
+  // sub-batch); the sub-batch is then bounded by the other per-query buffers.
+  const bool exact = !graph && sub < nq;
+  const bool mf = kernel == RBQ_SCAN_MFMA || kernel == RBQ_SCAN_MFMA_FP4;
+  const int64_t chunks_row = std::max<int64_t>(1, idx->max_chunks(stride_req, chunk));
+  const int64_t other_row = (int64_t)idx->nlist * 4 +
+                            (int64_t)stride_req * (int64_t)(8 + 8 + sizeof(PairRec) + 8 * 8 * idx->W + (mf ? idx->dp + 8 : 0)) +
+                            chunks_row * (int64_t)(2 * sizeof(UnitDesc) + 8);
+  const int64_t rows = exact ? std::max<int64_t>(sub, std::min<int64_t>(nq, budget / other_row)) : sub;
   auto add_stats = [&](int64_t m, const int32_t* npq, int stride) -> rbq_status {
     HIPCHK(hipStreamSynchronize(st));
     std::vector<int32_t> rb(m), rr(m), cc(m);
@@ -1177,8 +1215,8 @@ rbq_status rbq::search_locked(rbq_index* idx, const float* queries, int64_t nq, 
     }
     return RBQ_OK;
   };
-  for (int64_t q0 = 0; q0 < nq; q0 += sub) {
-    const int64_t m = std::min(sub, nq - q0);
+  for (int64_t q0 = 0; q0 < nq;) {
+    int64_t m = std::min(rows, nq - q0);
     rbq_search_opts os = o;
     // from the whole call's size, rounded as graph replay rounds it, so that eager
     // and graph searches of one batch agree and a graph serves its size bucket
@@ -1191,12 +1229,14 @@ rbq_status rbq::search_locked(rbq_index* idx, const float* queries, int64_t nq, 
     const int32_t* npq = nullptr;
     int stride = o.nprobe;
     rbq_status rs = graph ? rbq::search_graph(idx, qs, m, os, kernel, chunk, mf_rg, learned, oi, od, st, &npq, &stride)
-                          : run_search(idx, qs, m, os, kernel, chunk, mf_rg, learned, oi, od, st, &npq, &stride);
+                          : run_search(idx, qs, m, os, kernel, chunk, mf_rg, learned, oi, od, st, &npq, &stride,
+                                       exact ? budget : 0, &m);
     if (rs != RBQ_OK) return rs;
     if (stats) {
       rs = add_stats(m, npq, stride);
       if (rs != RBQ_OK) return rs;
     }
+    q0 += m;
   }
   if (idx->prof.on) idx->prof.searches++;   // one per call, however many sub-batches it ran
   if (ids_host) HIPCHK(hipMemcpyAsync(user_ids, out_ids, (size_t)nq * o.k * 8, hipMemcpyDeviceToHost, st));

@@ -55,8 +55,8 @@ def test_features_match_reference():
         np.testing.assert_allclose(f[qi, 64::4], want[64::4], rtol=1e-5)       # b ratios
         np.testing.assert_allclose(f[qi, 65::4], want[65::4], rtol=1e-4, atol=1e-6)   # v_l
         np.testing.assert_allclose(f[qi, 66::4], want[66::4], rtol=1e-4, atol=1e-6)   # v_r
-        # sum q_u may differ by a rounding flip or two
-        np.testing.assert_allclose(f[qi, 67::4], want[67::4], atol=3.0 / (15 * c.dp))
+        # expected S_q fraction: a mean of dp terms, FP32 on the GPU
+        np.testing.assert_allclose(f[qi, 67::4], want[67::4], rtol=1e-4, atol=1e-5)
 
 
 def test_forward_logits_match_reference():

@@ -68,3 +68,27 @@ def test_feature_layout():
     assert np.all(f[64::4][:8] >= 1.0 - 1e-12)
     assert np.all(f[65::4][:8] < 0) and np.all(f[66::4][:8] > 0)
     assert np.all((f[67::4][:8] >= 0) & (f[67::4][:8] <= 1))
+
+
+def test_expected_sq_feature_is_the_mean_of_the_randomized_rounding():
+    """The S_q feature is E[S_q] / (15 D): averaged over many independent
+    roundings (Sec. 3.3.1 with u_i uniform), the drawn S_q / (15 D) converges to
+    it (unbiasedness, Theorem 3.3). 4000 draws: the sample mean's standard error
+    is below sqrt(D) / 2 / (15 D) / sqrt(4000)."""
+    rng = np.random.default_rng(21)
+    dim = 64
+    data = rng.normal(0, 1, (300, dim))
+    cent = data[rng.choice(300, 10, replace=False)] + 0.05
+    assign = np.argmin(((data[:, None] - cent[None]) ** 2).sum(-1), 1)
+    idx = O.build_index(data, cent, assign, rng.normal(0, 1, (dim, dim)))
+    q = rng.normal(0, 1, dim)
+    for lid in range(3):
+        qq0 = O.quantize_query(q, cent[lid], idx.p, np.zeros(idx.dp))
+        want = M.expected_sq_fraction(qq0)
+        draws = 4000
+        tot = 0.0
+        for _ in range(draws):
+            qq = O.quantize_query(q, cent[lid], idx.p, rng.random(idx.dp))
+            tot += qq.sq / (15.0 * idx.dp)
+        se = math.sqrt(idx.dp) / 2 / (15.0 * idx.dp) / math.sqrt(draws)
+        assert abs(tot / draws - want) <= 5 * se, (lid, tot / draws, want)
