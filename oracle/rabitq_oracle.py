@@ -119,11 +119,15 @@ def build_index(data, centroids, assign, gauss) -> OracleIndex:
 # Randomised rounding source. Reading: the paper draws u_i ~ U[0, 1] without
 # naming a generator; the theory needs the u_i independent. Both sides use a
 # counter-based SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) keyed by
-# (seed, query id, list id, coordinate):
-#     key = seed XOR (qid * 2^40 + list * 2^12 + i)         (mod 2^64)
-#     u   = (splitmix64(key) >> 40) * 2^-24                  in [0, 1), 24 bits
-# where splitmix64(x) is the output of a SplitMix64 generator whose state was x
-# before the step (state += golden gamma, then the 64-bit finaliser).
+# (seed, query id, list id, draw), one 64-bit output per two coordinates:
+#     j   = (i // 128) * 64 + i % 64                         (i and i + 64 share a draw)
+#     key = seed XOR (qid * 2^40 + list * 2^12 + j)         (mod 2^64)
+#     z   = splitmix64(key)
+#     u_i = (z >> 40) * 2^-24 if i % 128 < 64 else ((z >> 16) mod 2^24) * 2^-24
+# in [0, 1) with 24 bits, where splitmix64(x) is the output of a SplitMix64
+# generator whose state was x before the step (state += golden gamma, then the
+# 64-bit finaliser). Distinct bit fields of one output are independent
+# uniforms to the generator's quality, so the u_i stay independent.
 
 _M64 = (1 << 64) - 1
 
@@ -136,27 +140,43 @@ def splitmix64(x: int) -> int:
     return z ^ (z >> 31)
 
 
-def rounding_key(seed: int, qid: int, list_id: int, i: int) -> int:
-    return (seed ^ ((qid << 40) + (list_id << 12) + i)) & _M64
+def rounding_key(seed: int, qid: int, list_id: int, j: int) -> int:
+    """Counter of draw j of a (query, list) pair."""
+    return (seed ^ ((qid << 40) + (list_id << 12) + j)) & _M64
+
+
+def draw_index(i: int) -> int:
+    """Coordinates i and i + 64 of each 128-coordinate block share draw j."""
+    return ((i >> 7) << 6) | (i & 63)
 
 
 def rounding_uniforms(seed: int, qid: int, list_id: int, dp: int) -> np.ndarray:
-    """u_0..u_{Dp-1} for one (query, list) pair, in [0, 1) with 24 bits."""
-    return np.array([(splitmix64(rounding_key(seed, qid, list_id, i)) >> 40) * 2.0 ** -24
-                     for i in range(dp)])
+    """u_0..u_{Dp-1} for one (query, list) pair, in [0, 1) with 24 bits: one
+    SplitMix64 output per draw gives two coordinates, bits 40..63 to the
+    coordinate with bit 6 clear and bits 16..39 to its partner i + 64."""
+    out = []
+    for i in range(dp):
+        z = splitmix64(rounding_key(seed, qid, list_id, draw_index(i)))
+        v = (z >> 40) if (i & 64) == 0 else ((z >> 16) & 0xFFFFFF)
+        out.append(v * 2.0 ** -24)
+    return np.array(out)
 
 
 def rounding_uniforms_fast(seed: int, qid: int, list_id: int, dp: int) -> np.ndarray:
     """Same numbers as `rounding_uniforms`, vectorised with uint64 NumPy arithmetic."""
     i = np.arange(dp, dtype=np.uint64)
+    j = ((i >> np.uint64(7)) << np.uint64(6)) | (i & np.uint64(63))
     with np.errstate(over="ignore"):
         base = (np.uint64(qid) << np.uint64(40)) + (np.uint64(list_id) << np.uint64(12))
-        z = np.uint64(seed) ^ (base + i)
+        z = np.uint64(seed) ^ (base + j)
         z = z + np.uint64(0x9E3779B97F4A7C15)
         z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
         z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
         z = z ^ (z >> np.uint64(31))
-    return (z >> np.uint64(40)).astype(np.float64) * 2.0 ** -24
+    hi = z >> np.uint64(40)
+    mid = (z >> np.uint64(16)) & np.uint64(0xFFFFFF)
+    v = np.where((i & np.uint64(64)) == 0, hi, mid)
+    return v.astype(np.float64) * 2.0 ** -24
 
 
 # ----------------------------------------------------------------------------

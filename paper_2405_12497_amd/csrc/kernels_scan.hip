@@ -186,13 +186,20 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
     const int64_t r = g - q * s.nprobe;
     const bool planes =
         !s.boot_planes_only || uniform_i32(s.pair_choff[q * (s.nprobe + 1) + r]) < uniform_i32(s.q_p0[q]);
+    float u_next = 0.f;   // word t + 1's uniform, drawn with word t's (t even)
 #pragma unroll
     for (int t = 0; t < WS; ++t) {
       if (t < W) {
         const int i = t * kWave + lane;
+        float u;
+        if ((t & 1) == 0) {
+          rounding_u2(s.seed, qid, (uint32_t)list[j], (uint32_t)i, u, u_next);
+        } else {
+          u = u_next;
+        }
         // a pair that is not live has scale 0, so x = 0 and floor(u) = 0
         const float x = (rv[j][t] - rmin) * scale;
-        const int qu = min(s.qmax, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)list[j], (uint32_t)i)));
+        const int qu = min(s.qmax, (int)floorf(x + u));
         sq += qu;
         if (q8) q8[i] = (int8_t)(qu - s.qoff);
         if (!planes) continue;
@@ -326,15 +333,22 @@ __device__ __forceinline__ void prep_q_body(const SearchDev& s, int64_t blk) {
   int8_t* q8 = QU8 ? s.qu8 + gc * s.dp : nullptr;
   int sq = 0;
   uint64_t myword = 0;   // lane l < 4 W of the row: plane word l (= plane jb * W + word t)
+  float u_next[4] = {0.f, 0.f, 0.f, 0.f};   // word t + 1's uniforms, drawn with word t's (t even)
 #pragma unroll
   for (int t = 0; t < W; ++t) {
     int qu[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int i = t * kWave + l + 16 * j;
+      float u;
+      if ((t & 1) == 0) {
+        rounding_u2(s.seed, qid, (uint32_t)max(list, 0), (uint32_t)i, u, u_next[j]);
+      } else {
+        u = u_next[j];
+      }
       // a pair that is not live has scale 0, so x = 0 and floor(u) = 0
       const float x = (rv[t][j] - rmin) * scale;
-      qu[j] = min(s.qmax, (int)floorf(x + rounding_u(s.seed, qid, (uint32_t)max(list, 0), (uint32_t)i)));
+      qu[j] = min(s.qmax, (int)floorf(x + u));
       sq += qu[j];
       if (QU8 && act) q8[i] = (int8_t)(qu[j] - s.qoff);
     }

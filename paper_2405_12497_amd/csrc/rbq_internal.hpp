@@ -173,22 +173,16 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-// Bits 40..63 of splitmix64(x). The final xor with z >> 31 cannot change
-// them (z >> 31 is zero above bit 32), and of the last product only the high
-// word is needed: three 32-bit multiplies instead of four.
-__device__ __forceinline__ uint32_t splitmix64_top24(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z ^= z >> 27;
-  const uint32_t lo = (uint32_t)z, hi = (uint32_t)(z >> 32);
-  const uint32_t top = __umulhi(lo, 0x133111EBu) + lo * 0x94D049BBu + hi * 0x133111EBu;
-  return top >> 8;
-}
-
-// Uniform in [0,1) with 24 bits for coordinate i of the (query, list) pair.
-__device__ __forceinline__ float rounding_u(uint64_t seed, uint64_t qid, uint32_t list, uint32_t i) {
-  const uint64_t key = seed ^ ((qid << 40) + ((uint64_t)list << 12) + (uint64_t)i);
-  return (float)splitmix64_top24(key) * (1.0f / 16777216.0f);
+// The uniforms u_i and u_{i+64} (i % 128 < 64) of a (query, list) pair, in
+// [0, 1) with 24 bits: both come from one SplitMix64 output z of draw
+// j = (i / 128) * 64 + i % 64, u_i from bits 40..63 and u_{i+64} from bits
+// 16..39 (the final xor with z >> 31 reaches bit 32 downwards only).
+__device__ __forceinline__ void rounding_u2(uint64_t seed, uint64_t qid, uint32_t list, uint32_t i, float& u0,
+                                           float& u1) {
+  const uint32_t j = ((i >> 7) << 6) | (i & 63u);
+  const uint64_t z = splitmix64(seed ^ ((qid << 40) + ((uint64_t)list << 12) + (uint64_t)j));
+  u0 = (float)(uint32_t)(z >> 40) * (1.0f / 16777216.0f);
+  u1 = (float)((uint32_t)(z >> 16) & 0xFFFFFFu) * (1.0f / 16777216.0f);
 }
 
 // Interleaved code layout: for position p (list order), 64-bit word w lives at

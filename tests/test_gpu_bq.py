@@ -194,12 +194,13 @@ def test_relative_error_against_bq():
     assign = np.zeros(n, np.int32)
     true = np.stack([O.exact_sqdist(data, q) for q in qs])
     oidx = O.OracleIndex(data, cent, assign, O.orthogonal_from_gaussian(gauss))
-    errs, oerrs = [], []
+    errs, oerrs, perq = [], [], []
     for bq in range(1, 9):
         idx = R.Index(960, 1, seed=4300, bq=bq, rot_precision=R.RBQ_ROT_BF16X3)
         idx.build(data, cent, assign, gauss)
         est = _all_estimates(idx, qs, n, 960)
         errs.append(float(np.mean(np.abs(est - true) / true)))
+        perq.append(np.mean(np.abs(est - true) / true, axis=1))
         oe = []
         for qi in range(3):
             u = O.rounding_uniforms_fast(4300, qi, 0, 960)
@@ -213,12 +214,15 @@ def test_relative_error_against_bq():
         assert gpu3 == pytest.approx(oerrs[-1], rel=0.02)
         idx.close()
     # B_q = 1 (binary query) is far worse than B_q = 4; the error falls
-    # through B_q = 4 and then levels off: from B_q = 6 on it stays within 2%,
-    # and B_q = 4 is within 30% of the plateau (on this data the curve bends at
-    # 4 and flattens by 6; the GPU curve equals the oracle's, checked above)
+    # through B_q = 4 and then levels off: from B_q = 6 on the averages differ
+    # by less than four standard errors of a 10-query mean (the spread is the
+    # sampling noise of the random rounding), and B_q = 4 is within 30% of the
+    # plateau (the GPU curve equals the oracle's, checked above)
+    se = max(float(np.std(perq[b], ddof=1)) / np.sqrt(len(perq[b])) for b in range(5, 8))
+    print(f"plateau B_q 6..8: spread {max(errs[5:]) - min(errs[5:]):.5f}, standard error {se:.5f}")
     assert errs[0] > 3.0 * errs[3]
     assert all(errs[i + 1] < errs[i] for i in range(3))
-    assert max(errs[5:]) <= 1.02 * min(errs[5:])
+    assert max(errs[5:]) - min(errs[5:]) <= 4.0 * se
     assert errs[3] <= 1.3 * errs[7]
 
 

@@ -222,7 +222,12 @@ def test_search_returns_exact_topk_of_probed_lists(name, waves):
     assert st["codes_scanned"] == sum(int(np.isin(c.assign, lists[qi]).sum()) for qi in range(len(c.queries)))
     assert st["reranked"] >= min(c.k, len(c.data)) * len(c.queries)
     print(f"{name}: mismatches {mism} (all with bound failures: {flagged}); stats {st}")
-    assert mism <= max(1, len(c.queries) // 4)
+    # every mismatch is explained by a bound failure (checked above); this cap
+    # only guards against a systematically wrong bound: with eps0 = 1.9 a true
+    # top-k member's bound fails with a probability of a few percent
+    # (Theorem 3.2), so a query with k = 10 such members meets one with a
+    # probability of up to about 1 - 0.95^10 = 40%
+    assert mism <= max(1, int(0.6 * len(c.queries)))
 
 
 @pytest.mark.parametrize("name", ["ivf128", "ivf960z"])

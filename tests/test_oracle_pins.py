@@ -74,6 +74,14 @@ def test_rounding_uniforms_properties():
     assert abs(np.corrcoef(many[:-1], many[1:])[0, 1]) < 0.01
     # different pairs give different streams
     assert not np.array_equal(O.rounding_uniforms_fast(7, 1, 2, 64), O.rounding_uniforms_fast(7, 2, 1, 64))
+    # the two coordinates that share a draw (i, i + 64) are uncorrelated and
+    # their joint law is uniform on the square (chi-square over 8 x 8 cells)
+    w = np.stack([O.rounding_uniforms_fast(7, q, l, 256) for q in range(40) for l in range(25)])
+    a = np.concatenate([w[:, 0:64], w[:, 128:192]], 1).ravel()
+    b = np.concatenate([w[:, 64:128], w[:, 192:256]], 1).ravel()
+    assert abs(np.corrcoef(a, b)[0, 1]) < 0.01
+    h, _, _ = np.histogram2d(a, b, bins=8, range=[[0, 1], [0, 1]])
+    assert stats.chisquare(h.ravel()).pvalue > 1e-3
 
 
 # --------------------------------------------------------------- rotation
