@@ -773,7 +773,11 @@ def bench_learned(args):
         "unit": "queries/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t_l * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int1xint4->int32 scan, bf16 MLP, fp32 estimator/rerank", "data": "synthetic",
+        "dtype": {"mfma": "int8 MFMA scan (1-bit codes x 4-bit queries -> int32)",
+                  "mfma_fp4": "fp8 x fp4 MFMA scan (exact integers)",
+                  "popcnt": "int1 x int4 popcount scan -> int32",
+                  "auto": "autotuned scan"}[args.kernel] + ", bf16 MLP, fp32 estimator/rerank",
+        "data": "synthetic",
         "config": {
             "workload": f"learned per-query nprobe: {n} embedding-like vectors D={dim} (power-law spectrum, unit "
                         f"norm), {nlist} k-means lists, BF16x3 rotation, {ntr} training / {nva} validation / {nte} "
@@ -825,7 +829,8 @@ def main():
     ap.add_argument("--nlist", type=int, default=0, help="IVF lists (0: the workload's default)")
     ap.add_argument("--nprobe", type=int, default=0, help="0: smallest of the sweep reaching recall 0.95")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--kernel", default="popcnt", choices=["popcnt", "mfma", "mfma_fp4", "auto"])
+    ap.add_argument("--kernel", default=None, choices=["popcnt", "mfma", "mfma_fp4", "auto"],
+                    help="phase-1 scan kernel (default: mfma for the learned-nprobe batches, popcnt otherwise)")
     ap.add_argument("--workload", default="learned", choices=["learned", "sift1m", "embed10m", "gist1m"])
     ap.add_argument("--fullscan-only", action="store_true",
                     help="embed10m: only build the index and run six one-query searches of every list")
@@ -835,6 +840,8 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run 3 device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.kernel is None:
+        args.kernel = "mfma" if args.workload == "learned" else "popcnt"
     if args.copy_mb:
         import torch
         n = args.copy_mb * (1 << 20) // 4

@@ -61,6 +61,16 @@ __device__ __forceinline__ int bits_to_fp4x8(uint32_t x) {
 // dimension that B's k(x) holds: k(x) = 16 (x / 32) + x % 32 for x % 32 < 16,
 // else 64 + 16 (x / 32) + x % 32 - 16. A group of 8 consecutive positions
 // maps to the 8 dimensions starting at k(x) rounded down to 8, in the nibble order.
+// Wait states between the last scaled FP8 x FP4 MFMA of a code block and the
+// first read of its result. The compiler's own distance for this mixed-format
+// instruction (about 12) returned wrong sums on gfx950 once nothing else sat
+// between the product and the read. The accumulator passes through the wait
+// (in the accumulation registers the product wrote), so the product comes
+// before it and every read of the result after it.
+__device__ __forceinline__ void f4_result_wait(f32x4& acc) {
+  asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7\n\ts_nop 7" : "+a"(acc));
+}
+
 __device__ __forceinline__ int f4_src_dim(int d) {
   const int x = d & 127, g = x >> 5, e = x & 31;
   return (d & ~127) + (e < 16 ? 16 * g + e : 64 + 16 * g + (e - 16));
@@ -142,9 +152,11 @@ __device__ void mfma_unit(const SearchDev& s, int64_t start, int64_t end, const 
         }
       }
 #pragma unroll
-      for (int h = 0; h < RG; ++h)
+      for (int h = 0; h < RG; ++h) {
+        f4_result_wait(accf[h]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[h][i] = (int)accf[h][i];
+      }
     } else {
       // the lane's 16-bit slice (dimensions 64 t + 16 grp .. +15) of each code
       // word; every word read is issued before the first product
@@ -590,8 +602,9 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
         bw[t] = w < W ? v : 0u;
       }
     } else {
+      const uint16_t* base = c16 + 4 * code_word_index(p, 0, WS) + grp;   // word t is 256 slices further
 #pragma unroll
-      for (int t = 0; t < WS; ++t) bw[t] = c16[4 * code_word_index(p, t, WS) + grp];
+      for (int t = 0; t < WS; ++t) bw[t] = base[(size_t)t * 256];
     }
   };
   // the code's scan factors (and inner-product term) travel with its words
@@ -600,6 +613,21 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
     sf = s.sfac[p];
     fi = s.metric != 0 ? s.fip[p] : 0.f;
   };
+  if constexpr (RG == 1) {
+    if (!hl[0]) return;   // no live row in the unit
+  }
+  // this lane's rows' validity and threshold in registers (read in the loop
+  // without a branch)
+  bool rval[RG][4];
+  float rtau[RG][4];
+#pragma unroll
+  for (int h = 0; h < RG; ++h)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const RowInfo& ri = rows[16 * h + 4 * grp + i];
+      rval[h][i] = ri.valid != 0;
+      rtau[h][i] = ri.tau;
+    }
   uint32_t bw[NA];
   float2 sf;
   float fi;
@@ -611,9 +639,10 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
     float nfi;
     load_block(min(blk + 16, end - 1), nb);
     load_fac(min(blk + 16, end - 1), nsf, nfi);
+    // a lane past the end computes on the last code of the unit: its column's
+    // results (and that code's popcount) are never used
     const bool pvalid = blk + col < end;
     const int64_t p = pvalid ? blk + col : blk;
-    const uint32_t keep = pvalid ? 0xFFFFFFFFu : 0u;
     i32x4 acc[RG];
     int pcp = 0;
     if constexpr (F4) {
@@ -622,33 +651,36 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
       for (int h = 0; h < RG; ++h) accf[h] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int t = 0; t < T2; ++t) {
-        const uint32_t bits = bw[t] & keep;
+        const uint32_t bits = bw[t];
         pcp += __popc(bits);
         const i32x8 b = {bits_to_fp4x8(bits & 0xFFu), bits_to_fp4x8((bits >> 8) & 0xFFu),
                          bits_to_fp4x8((bits >> 16) & 0xFFu), bits_to_fp4x8(bits >> 24), 0, 0, 0, 0};
 #pragma unroll
         for (int h = 0; h < RG; ++h)
-          if (hl[h]) accf[h] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[h][t], b, accf[h], 0, 4, 0, 127, 0, 127);
+          if (RG == 1 || hl[h])
+            accf[h] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[h][t], b, accf[h], 0, 4, 0, 127, 0, 127);
       }
 #pragma unroll
-      for (int h = 0; h < RG; ++h)
+      for (int h = 0; h < RG; ++h) {
+        f4_result_wait(accf[h]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[h][i] = (int)accf[h][i];
+      }
     } else {
 #pragma unroll
       for (int h = 0; h < RG; ++h) acc[h] = i32x4{0, 0, 0, 0};
 #pragma unroll
       for (int t = 0; t < WS; ++t) {
-        const uint32_t bits = bw[t] & keep & 0xFFFFu;
+        const uint32_t bits = bw[t];   // a 16-bit slice
         pcp += __popc(bits);
         i32x4 b;
         b[0] = nib_to_bytes(bits & 15u);
         b[1] = nib_to_bytes((bits >> 4) & 15u);
         b[2] = nib_to_bytes((bits >> 8) & 15u);
-        b[3] = nib_to_bytes((bits >> 12) & 15u);
+        b[3] = nib_to_bytes(bits >> 12);
 #pragma unroll
         for (int h = 0; h < RG; ++h)
-          if (hl[h]) acc[h] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[h][t], b, acc[h], 0, 0, 0);
+          if (RG == 1 || hl[h]) acc[h] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[h][t], b, acc[h], 0, 0, 0);
       }
     }
     int pc = pcp + __shfl_xor(pcp, 16, kWave);
@@ -657,7 +689,7 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
     const float ct = s.metric != 0 ? -fi : code_term_l2(sf);
 #pragma unroll
     for (int h = 0; h < RG; ++h) {
-      if (!hl[h]) continue;
+      if (RG > 1 && !hl[h]) continue;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = 16 * h + 4 * grp + i;
@@ -665,9 +697,9 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
         float dist, lbe;
         const int ipv = acc[h][i] + s.qoff * pc;
         estimate(ri.rec, ri.t, sf, ct, ipv, pc, dist, lbe);
-        const bool live = pvalid && ri.valid;
+        const bool live = pvalid & rval[h][i];
         const float lb = live ? lbe : __builtin_inff();
-        const bool pass = live && lb <= ri.tau;
+        const bool pass = live & (lb <= rtau[h][i]);
         if constexpr (DEBUG) {
           if (row == 0 && live) {
             const int64_t o = p - dbg_base;
@@ -678,15 +710,19 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
             dbg_lb[o] = lb;
           }
         } else {
-          // this row group's 16 codes: bits 16 grp .. +15 of the ballot
-          const uint32_t mine = (uint32_t)(__ballot(pass) >> (16 * grp)) & 0xFFFFu;
-          if (pass) {
-            Cand cd;
-            cd.pos = (int32_t)p;
-            cd.lb = lb;
-            s.seg[ri.seg_base + cnt[h][i] + __popc(mine & ((1u << col) - 1u))] = cd;
+          // this row group's 16 codes: bits 16 grp .. +15 of the ballot (most
+          // blocks have no candidate at all)
+          const uint64_t m = __ballot(pass);
+          if (m != 0ull) {
+            const uint32_t mine = (uint32_t)(m >> (16 * grp)) & 0xFFFFu;
+            if (pass) {
+              Cand cd;
+              cd.pos = (int32_t)p;
+              cd.lb = lb;
+              s.seg[ri.seg_base + cnt[h][i] + __popc(mine & ((1u << col) - 1u))] = cd;
+            }
+            cnt[h][i] += __popc(mine);
           }
-          cnt[h][i] += __popc(mine);
         }
       }
     }
