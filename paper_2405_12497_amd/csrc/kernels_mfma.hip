@@ -38,6 +38,30 @@ struct RowInfo {
 __device__ __forceinline__ int nib_to_bytes(uint32_t nib) { return (int)((nib * 0x00204081u) & 0x01010101u); }
 __device__ __forceinline__ uint32_t nib_to_bytes_u(uint32_t nib) { return (nib * 0x00204081u) & 0x01010101u; }
 
+// Masked expansion of the wave-unit int8 scan (B_q <= 4). Each block of 128
+// dimensions takes two K-steps; lane group g reads the 32 code bits w of
+// dimensions 32 g .. 32 g + 31 of the block (half g & 1 of code word
+// 2 j + (g >> 1)). w & (0x01010101 << m) and (w >> 4) & (0x01010101 << m),
+// m = 0..3, are the B dwords of the two K-steps: byte b of dword m holds bit
+// 8 b + m (resp. 8 b + 4 + m) of w times 2^m, one AND per dword. The query
+// side carries the matching dimension times 2^(3 - m) (at most 15 * 8 = 120),
+// so every product is 8 q_u x_b and the accumulator holds 8 <x_b, q_u>
+// exactly. scaled_cols returns, for rows r0..r3 of four bytes, the dwords
+// whose byte b is byte m of r_b, shifted left by 3 - m (bytewise exact:
+// bytes <= 15).
+__device__ __forceinline__ i32x4 scaled_cols(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3) {
+  const uint32_t lo01 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);   // r0.0 r1.0 r0.1 r1.1
+  const uint32_t hi01 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);   // r0.2 r1.2 r0.3 r1.3
+  const uint32_t lo23 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+  const uint32_t hi23 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+  i32x4 v;
+  v[0] = (int)(__builtin_amdgcn_perm(lo23, lo01, 0x05040100u) << 3);
+  v[1] = (int)(__builtin_amdgcn_perm(lo23, lo01, 0x07060302u) << 2);
+  v[2] = (int)(__builtin_amdgcn_perm(hi23, hi01, 0x05040100u) << 1);
+  v[3] = (int)__builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+  return v;
+}
+
 // FP8 (E4M3, OCP: bias 7) encodings of the integers 0..15, all exact: the
 // query operand of the FP8 x FP4 contraction (B_q <= 4).
 __constant__ uint8_t kFp8Int[16] = {0x00, 0x38, 0x40, 0x44, 0x48, 0x4A, 0x4C, 0x4E,
@@ -310,6 +334,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(SearchDev s) {
     carry[0] = carry[1] = 0;
     s.counters[2] = 0;
   }
+  if (threadIdx.x < kScanSlices) s.counters[kScanSliceCtr + kScanSliceStride * threadIdx.x] = 0;
   __syncthreads();
   for (int base = 0; base < s.nlist; base += 1024) {
     const int k = base + threadIdx.x;
@@ -545,7 +570,7 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
   const int col = lane & 15, grp = lane >> 4;
   const int dp = s.dp, W = s.W;
   constexpr int T2 = (WS + 1) / 2;
-  constexpr int NA = F4 ? T2 : WS;   // MFMA steps per code
+  constexpr int NA = F4 ? T2 : 2 * T2;   // MFMA steps per code (int8: two per 128 dimensions)
   // query fragments of rows 16 h + col: int8 dims 64 t + 16 grp .. +15, or
   // FP8 positions 128 t2 + 32 grp .. +31 (dimensions by f4_src_dim)
   typedef typename std::conditional<F4, i32x8, i32x4>::type AFrag;
@@ -571,10 +596,17 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
           v[6] = (int)(uint32_t)f3; v[7] = (int)(uint32_t)(f3 >> 32);
         }
         a[h][t] = v;
-      } else {
-        i32x4 v = {0, 0, 0, 0};
-        if (gh >= 0) v = *reinterpret_cast<const i32x4*>(qr + t * 64 + grp * 16);
-        a[h][t] = v;
+      } else if (t % 2 == 0) {
+        // int8: K-steps t and t + 1 of the masked expansion, dimensions
+        // 64 t + 32 grp .. +31 (zero past the row)
+        const int d0 = 64 * t + 32 * grp;
+        i32x4 l0 = {0, 0, 0, 0}, l1 = {0, 0, 0, 0};
+        if (gh >= 0 && d0 < dp) {
+          l0 = *reinterpret_cast<const i32x4*>(qr + d0);
+          l1 = *reinterpret_cast<const i32x4*>(qr + d0 + 16);
+        }
+        a[h][t] = scaled_cols((uint32_t)l0[0], (uint32_t)l0[2], (uint32_t)l1[0], (uint32_t)l1[2]);
+        a[h][t + 1] = scaled_cols((uint32_t)l0[1], (uint32_t)l0[3], (uint32_t)l1[1], (uint32_t)l1[3]);
       }
     }
   }
@@ -589,35 +621,45 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
   for (int h = 0; h < RG; ++h)
 #pragma unroll
     for (int i = 0; i < 4; ++i) cnt[h][i] = 0;
-  // code words of 16 codes, the next block's in flight while this one computes
-  const uint16_t* c16 = reinterpret_cast<const uint16_t*>(s.codes);
-  const uint32_t* c32 = reinterpret_cast<const uint32_t*>(s.codes);
-  auto load_block = [&](int64_t blk, uint32_t* bw) {
-    const int64_t p = min(blk + col, end - 1);   // in bounds; masked later
-    if constexpr (F4) {
+  // Code words of 16 codes, the next block's in flight while this one
+  // computes, addressed from the unit's first 64-code row with 32-bit offsets:
+  // unit position x (the start at o0) has word w at ((x >> 6) W + w) 64 + (x & 63).
+  const int n = (int)(end - start);
+  const int o0 = (int)(start & 63);
+  const int64_t row0 = start >> 6;
+  constexpr int NB = T2;   // registers of code bits per block
+  // this lane group's first word (2 t + (grp >> 1) for pair t) folded into the base
+  const uint32_t* c32 = reinterpret_cast<const uint32_t*>(s.codes) + (size_t)row0 * WS * 128 + (grp & 1);
+  const uint32_t* c32g = c32 + 128 * (grp >> 1);
+  const float2* sfu = s.sfac + start;
+  const float* fiu = s.metric != 0 ? s.fip + start : nullptr;
+  // the block at unit offset rel: this lane's code (clamped into the unit; the
+  // columns past its end are never used), its bits and its scan factors (and
+  // inner-product term)
+  auto load_block = [&](int rel, uint32_t* bw, float2& sf, float& fi) {
+    const int r = min(rel + col, n - 1);
+    const int x = o0 + r;
+    const uint32_t word0 = (uint32_t)((x >> 6) * WS * 64 + (x & 63));   // the wave-unit kernels have W == WS
+    // 32 bits of dimensions 128 t + 32 grp .. +31: half grp & 1 of word
+    // 2 t + (grp >> 1) (for an odd width, zero past the code's last word)
 #pragma unroll
-      for (int t = 0; t < T2; ++t) {
-        const int w = 2 * t + (grp >> 1);
-        const uint32_t v = c32[2 * code_word_index(p, min(w, W - 1), W) + (grp & 1)];
-        bw[t] = w < W ? v : 0u;
+    for (int t = 0; t < T2; ++t) {
+      if (WS % 2 == 0 || t + 1 < T2) {
+        bw[t] = c32g[2 * word0 + 256 * t];
+      } else {
+        const uint32_t v = c32[2 * (word0 + (WS - 1) * 64)];
+        bw[t] = grp < 2 ? v : 0u;
       }
-    } else {
-      const uint16_t* base = c16 + 4 * code_word_index(p, 0, WS) + grp;   // word t is 256 slices further
-#pragma unroll
-      for (int t = 0; t < WS; ++t) bw[t] = base[(size_t)t * 256];
     }
-  };
-  // the code's scan factors (and inner-product term) travel with its words
-  auto load_fac = [&](int64_t blk, float2& sf, float& fi) {
-    const int64_t p = min(blk + col, end - 1);
-    sf = s.sfac[p];
-    fi = s.metric != 0 ? s.fip[p] : 0.f;
+    sf = sfu[r];
+    fi = fiu != nullptr ? fiu[r] : 0.f;
   };
   if constexpr (RG == 1) {
     if (!hl[0]) return;   // no live row in the unit
   }
-  // this lane's rows' validity and threshold in registers (read in the loop
-  // without a branch)
+  // this lane's rows' thresholds in registers, -inf for rows outside the
+  // scanned phase (read in the loop without a branch), and their validity
+  // (the parity export reports live rows only)
   bool rval[RG][4];
   float rtau[RG][4];
 #pragma unroll
@@ -626,23 +668,14 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
     for (int i = 0; i < 4; ++i) {
       const RowInfo& ri = rows[16 * h + 4 * grp + i];
       rval[h][i] = ri.valid != 0;
-      rtau[h][i] = ri.tau;
+      rtau[h][i] = ri.valid != 0 ? ri.tau : -__builtin_inff();
     }
-  uint32_t bw[NA];
-  float2 sf;
-  float fi;
-  load_block(start, bw);
-  load_fac(start, sf, fi);
-  for (int64_t blk = start; blk < end; blk += 16) {
-    uint32_t nb[NA];
-    float2 nsf;
-    float nfi;
-    load_block(min(blk + 16, end - 1), nb);
-    load_fac(min(blk + 16, end - 1), nsf, nfi);
+  // one block of 16 codes at unit offset rb, from its loaded bits and factors
+  auto block = [&](int rb, const uint32_t* bw, float2 sf, float fi) {
     // a lane past the end computes on the last code of the unit: its column's
     // results (and that code's popcount) are never used
-    const bool pvalid = blk + col < end;
-    const int64_t p = pvalid ? blk + col : blk;
+    const bool pvalid = rb + col < n;
+    const int64_t p = start + (pvalid ? rb + col : rb);
     i32x4 acc[RG];
     int pcp = 0;
     if constexpr (F4) {
@@ -670,18 +703,24 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
 #pragma unroll
       for (int h = 0; h < RG; ++h) acc[h] = i32x4{0, 0, 0, 0};
 #pragma unroll
-      for (int t = 0; t < WS; ++t) {
-        const uint32_t bits = bw[t];   // a 16-bit slice
-        pcp += __popc(bits);
-        i32x4 b;
-        b[0] = nib_to_bytes(bits & 15u);
-        b[1] = nib_to_bytes((bits >> 4) & 15u);
-        b[2] = nib_to_bytes((bits >> 8) & 15u);
-        b[3] = nib_to_bytes(bits >> 12);
+      for (int j = 0; j < T2; ++j) {
+        const uint32_t w = bw[j], w4 = w >> 4;
+        pcp += __popc(w);
+        const i32x4 b0 = {(int)(w & 0x01010101u), (int)(w & 0x02020202u), (int)(w & 0x04040404u),
+                          (int)(w & 0x08080808u)};
+        const i32x4 b1 = {(int)(w4 & 0x01010101u), (int)(w4 & 0x02020202u), (int)(w4 & 0x04040404u),
+                          (int)(w4 & 0x08080808u)};
 #pragma unroll
         for (int h = 0; h < RG; ++h)
-          if (RG == 1 || hl[h]) acc[h] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[h][t], b, acc[h], 0, 0, 0);
+          if (RG == 1 || hl[h]) {
+            acc[h] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[h][2 * j], b0, acc[h], 0, 0, 0);
+            acc[h] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[h][2 * j + 1], b1, acc[h], 0, 0, 0);
+          }
       }
+#pragma unroll
+      for (int h = 0; h < RG; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[h][i] >>= 3;   // 8 <x_b, q_u>, exact
     }
     int pc = pcp + __shfl_xor(pcp, 16, kWave);
     pc += __shfl_xor(pc, 32, kWave);
@@ -695,13 +734,12 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
         const int row = 16 * h + 4 * grp + i;
         const RowInfo& ri = rows[row];
         float dist, lbe;
-        const int ipv = acc[h][i] + s.qoff * pc;
+        const int ipv = acc[h][i];   // B_q <= 4 on this path: q_u - qoff = q_u
         estimate(ri.rec, ri.t, sf, ct, ipv, pc, dist, lbe);
-        const bool live = pvalid & rval[h][i];
-        const float lb = live ? lbe : __builtin_inff();
-        const bool pass = live & (lb <= rtau[h][i]);
+        const float lb = lbe;
+        const bool pass = pvalid & (lb <= rtau[h][i]);
         if constexpr (DEBUG) {
-          if (row == 0 && live) {
+          if (row == 0 && pvalid && rval[h][i]) {
             const int64_t o = p - dbg_base;
             dbg_ip[o] = ipv;
             dbg_pc[o] = pc;
@@ -712,7 +750,7 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
         } else {
           // this row group's 16 codes: bits 16 grp .. +15 of the ballot (most
           // blocks have no candidate at all)
-          const uint64_t m = __ballot(pass);
+          const uint64_t m = __builtin_amdgcn_ballot_w64(pass);
           if (m != 0ull) {
             const uint32_t mine = (uint32_t)(m >> (16 * grp)) & 0xFFFFu;
             if (pass) {
@@ -726,10 +764,19 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
         }
       }
     }
-#pragma unroll
-    for (int t = 0; t < NA; ++t) bw[t] = nb[t];
-    sf = nsf;
-    fi = nfi;
+  };
+  // two register sets in turn: the next block's loads are in flight while
+  // this one computes
+  uint32_t bA[NB], bB[NB];
+  float2 sA, sB;
+  float fA, fB;
+  load_block(0, bA, sA, fA);
+  for (int rb = 0; rb < n; rb += 32) {
+    load_block(min(rb + 16, n - 1), bB, sB, fB);
+    block(rb, bA, sA, fA);
+    if (rb + 16 >= n) break;
+    load_block(min(rb + 32, n - 1), bA, sA, fA);
+    block(rb + 16, bB, sB, fB);
   }
   if constexpr (!DEBUG) {
     if (col == 0) {
@@ -752,48 +799,59 @@ __global__ __launch_bounds__(kThreads) void k_scan_mfma_w(SearchDev s) {
   RowInfo* rows = rows_all[threadIdx.x / kWave];
   const float hwk = s.eps0 / sqrtf((float)(s.dp - 1));
   const int64_t total = uniform_i64(s.mf_unit_off[s.nlist]);
-  for (;;) {
-    unsigned long long cl = 0;
-    if (lane == 0) cl = atomicAdd(&s.counters[2], 1ull);
-    const int64_t u = uniform_i64((int64_t)cl);   // lane 0's claim (every lane is active)
-    if (u >= total) break;
-    const int list = wave_find_list(s.mf_unit_off, s.nlist, u);
-    const int64_t local = uniform_i64(u - s.mf_unit_off[list]);
-    const int cnt = uniform_i32((int)(s.mf_pair_off[list + 1] - s.mf_pair_off[list]));
-    const int ngroups = (cnt + R - 1) / R;
-    const int c = (int)(local / ngroups);
-    const int gi = (int)(local - (int64_t)c * ngroups);
-    const int64_t lbeg = uniform_i64(s.list_off[list]), lend = uniform_i64(s.list_off[list + 1]);
-    const int64_t start = lbeg + (int64_t)c * s.chunk;
-    const int64_t end = lend < start + s.chunk ? lend : start + s.chunk;
-    int g = -1;
-    if (lane < R) {
-      RowInfo ri;
-      ri.valid = 0;
-      ri.tau = -__builtin_inff();
-      ri.seg_base = 0;
-      ri.count_slot = -1;
-      ri.rec.k1 = ri.rec.k2 = ri.rec.k0 = ri.rec.b = 0.f;
-      ri.t.pt = ri.t.coef = ri.t.coefh = 0.f;
-      if (R * gi + lane < cnt) {
-        g = s.mf_pairs[s.mf_pair_off[list] + R * gi + lane];
-        const int64_t q = g / s.nprobe;
-        const int r = (int)(g - q * s.nprobe);
-        ri.rec = s.pairs[g];
-        ri.t = s.metric != 0 ? pair_terms_ip(ri.rec, hwk, s.pair_pt[g]) : pair_terms(ri.rec, hwk);
-        if (c >= first_main_chunk(s, q, r)) {
-          ri.valid = 1;
-          ri.tau = s.tau[q];
-          const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
-          const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
-          ri.seg_base = s.off_seg[q] + codeoff[r] + (int64_t)c * s.chunk;
-          ri.count_slot = s.off_ch[q] + choff[r] + c;
+  // The units (ordered by list, then chunk, then row group) are cut into
+  // kScanSlices contiguous slices; a block starts on the slice of its XCD
+  // (workgroups go to the XCDs in turn), so the row groups of one code chunk
+  // run on one XCD and share its L2, then moves on to the other slices.
+  const int x0 = (int)(blockIdx.x % kScanSlices);
+  for (int j = 0; j < kScanSlices; ++j) {
+    const int x = (x0 + j) % kScanSlices;
+    const int64_t hi = total * (x + 1) / kScanSlices;
+    const int64_t lo = total * x / kScanSlices;
+    unsigned long long* ctr = s.counters + kScanSliceCtr + kScanSliceStride * x;
+    for (;;) {
+      unsigned long long cl = 0;
+      if (lane == 0) cl = atomicAdd(ctr, 1ull);
+      const int64_t u = lo + uniform_i64((int64_t)cl);   // lane 0's claim (every lane is active)
+      if (u >= hi) break;
+      const int list = wave_find_list(s.mf_unit_off, s.nlist, u);
+      const int64_t local = uniform_i64(u - s.mf_unit_off[list]);
+      const int cnt = uniform_i32((int)(s.mf_pair_off[list + 1] - s.mf_pair_off[list]));
+      const int ngroups = (cnt + R - 1) / R;
+      const int c = (int)(local / ngroups);
+      const int gi = (int)(local - (int64_t)c * ngroups);
+      const int64_t lbeg = uniform_i64(s.list_off[list]), lend = uniform_i64(s.list_off[list + 1]);
+      const int64_t start = lbeg + (int64_t)c * s.chunk;
+      const int64_t end = lend < start + s.chunk ? lend : start + s.chunk;
+      int g = -1;
+      if (lane < R) {
+        RowInfo ri;
+        ri.valid = 0;
+        ri.tau = -__builtin_inff();
+        ri.seg_base = 0;
+        ri.count_slot = -1;
+        ri.rec.k1 = ri.rec.k2 = ri.rec.k0 = ri.rec.b = 0.f;
+        ri.t.pt = ri.t.coef = ri.t.coefh = 0.f;
+        if (R * gi + lane < cnt) {
+          g = s.mf_pairs[s.mf_pair_off[list] + R * gi + lane];
+          const int64_t q = g / s.nprobe;
+          const int r = (int)(g - q * s.nprobe);
+          ri.rec = s.pairs[g];
+          ri.t = s.metric != 0 ? pair_terms_ip(ri.rec, hwk, s.pair_pt[g]) : pair_terms(ri.rec, hwk);
+          if (c >= first_main_chunk(s, q, r)) {
+            ri.valid = 1;
+            ri.tau = s.tau[q];
+            const int32_t* choff = s.pair_choff + q * (s.nprobe + 1);
+            const int32_t* codeoff = s.pair_codeoff + q * (s.nprobe + 1);
+            ri.seg_base = s.off_seg[q] + codeoff[r] + (int64_t)c * s.chunk;
+            ri.count_slot = s.off_ch[q] + choff[r] + c;
+          }
         }
+        rows[lane] = ri;
       }
-      rows[lane] = ri;
+      mfma_wave_unit<false, F4, WS, RG>(s, start, end, rows, g, s.qu8, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                        0);
     }
-    mfma_wave_unit<false, F4, WS, RG>(s, start, end, rows, g, s.qu8, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                      0);
   }
 }
 
@@ -900,11 +958,13 @@ const void* wave_kernel_for(int W, int rg) {
 #undef RBQ_MW
 }
 
-// The batched scan kernel for (W, rg): the wave-unit form where it exists,
-// else the block form. *wave tells which.
-const void* pick_kernel(bool f4, bool dbg, int W, int rg, bool* wave) {
+// The batched scan kernel for (W, rg): the wave-unit form where it exists
+// (for the int8 contraction only when B_q <= 4, `narrow`: its masked expansion
+// needs query values below 16), else the block form. *wave tells which.
+const void* pick_kernel(bool f4, bool dbg, int W, int rg, bool narrow, bool* wave) {
   const void* f = f4 ? (dbg ? wave_kernel_for<true, true>(W, rg) : wave_kernel_for<true, false>(W, rg))
-                     : (dbg ? wave_kernel_for<false, true>(W, rg) : wave_kernel_for<false, false>(W, rg));
+                : !narrow ? nullptr
+                          : (dbg ? wave_kernel_for<false, true>(W, rg) : wave_kernel_for<false, false>(W, rg));
   *wave = f != nullptr;
   if (f) return f;
   if (f4) return dbg ? kernel_for<true, true>(W, rg) : kernel_for<true, false>(W, rg);
@@ -945,9 +1005,9 @@ int mfma_row_groups(int dp, bool f4, int want) {
   return rg;
 }
 
-int scan_mfma_blocks_per_cu(int dp, bool f4, int rg) {
+int scan_mfma_blocks_per_cu(int dp, bool f4, int rg, bool narrow) {
   bool wave = false;
-  const void* f = pick_kernel(f4, false, dp / 64, rg, &wave);
+  const void* f = pick_kernel(f4, false, dp / 64, rg, narrow, &wave);
   const size_t bytes = wave ? 0 : (size_t)16 * rg * row_bytes(f4, dp);
   if (!wave) allow_lds(f, bytes);
   int v = 0;
@@ -978,7 +1038,7 @@ hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t
   hipLaunchKernelGGL(k_group_scatter, dim3(g1), dim3(256), 0, st, s);
   const bool f4 = s.mfma_f4 != 0;
   bool wave = false;
-  const void* f = pick_kernel(f4, false, s.W, s.mf_rg, &wave);
+  const void* f = pick_kernel(f4, false, s.W, s.mf_rg, s.npl == 4, &wave);
   const size_t bytes = wave ? 0 : (size_t)16 * s.mf_rg * row_bytes(f4, s.dp);
   if (!wave) allow_lds(f, bytes);
   void* args[] = {(void*)&s};
@@ -991,7 +1051,7 @@ hipError_t launch_debug_mfma(const SearchDev& s, const PairRec* rec, const int8_
   if (nchunks <= 0) return hipSuccess;
   const bool f4 = s.mfma_f4 != 0;
   bool wave = false;
-  const void* f = pick_kernel(f4, true, s.W, s.mf_rg, &wave);
+  const void* f = pick_kernel(f4, true, s.W, s.mf_rg, s.npl == 4, &wave);
   const size_t bytes = wave ? 0 : (size_t)16 * s.mf_rg * row_bytes(f4, s.dp);
   if (!wave) allow_lds(f, bytes);
   void* args[] = {(void*)&s, (void*)&rec, (void*)&qu8, (void*)&list, (void*)&ip, (void*)&pc,

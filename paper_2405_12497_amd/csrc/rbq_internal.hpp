@@ -9,6 +9,12 @@
 namespace rbq {
 
 constexpr int kWave = 64;          // CDNA wavefront
+// Work counters of the wave-unit MFMA scan: one per slice of its units (one
+// slice per XCD), 128 bytes apart, after the 8 general counters.
+constexpr int kScanSlices = 8;
+constexpr int kScanSliceCtr = 16;
+constexpr int kScanSliceStride = 16;
+constexpr size_t kCounterBytes = 8 * (kScanSliceCtr + kScanSliceStride * kScanSlices);
 constexpr int kMaxK = 256;         // largest k returned by a search
 constexpr int kMaxNprobe = 16384;   // the selection of more than 2048 lists sorts them in LDS
 constexpr int kMaxNlist = 24576;    // probe selection keeps a query's centroid distances in LDS
@@ -337,7 +343,7 @@ int scan_popcnt_blocks_per_cu(int W, int npl);
 // Row groups of the batched scan for code length dp: `want` (1, 2 or 4; other
 // values mean 1), lowered until the query tile fits a block's LDS.
 int mfma_row_groups(int dp, bool f4, int want);
-int scan_mfma_blocks_per_cu(int dp, bool f4, int rg);
+int scan_mfma_blocks_per_cu(int dp, bool f4, int rg, bool narrow);
 // phase 0: bootstrap units, 1: main units with the bound filter, 2: parity
 // export of the main-phase table (s.dbg_*).
 hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st);

@@ -657,7 +657,7 @@ rbq_status ensure_workspace(rbq_index* idx, int64_t nq, int nprobe, int k, int c
   HIPCHK(w.q_n0.ensure((size_t)nq * 4));
   HIPCHK(w.q_ncode.ensure((size_t)nq * 8));
   HIPCHK(w.offs.ensure((size_t)5 * (nq + 1 + (nq + kOffQ - 1) / kOffQ) * 8));
-  HIPCHK(w.counters.ensure(64));
+  HIPCHK(w.counters.ensure(kCounterBytes));
   if (!seg_exact) HIPCHK(w.seg.ensure((size_t)nq * std::max<int64_t>(1, idx->max_codes(nprobe)) * sizeof(Cand)));
   HIPCHK(w.seg_count.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
   HIPCHK(w.chunk_qcode.ensure((size_t)nq * std::max<int64_t>(1, idx->max_chunks(nprobe, chunk)) * 4));
@@ -911,7 +911,7 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   HIPCHK(launch_tau_split(s, tau_split(fin_w, o.k), (uint64_t*)idx->ws.tau_part.p, st));
   HIPCHK(rec(4));
   if (mfma) {
-    HIPCHK(launch_scan_mfma(s, 1, scan_grid(idx, nq, chunks, scan_mfma_blocks_per_cu(idx->dp, s.mfma_f4 != 0, s.mf_rg)),
+    HIPCHK(launch_scan_mfma(s, 1, scan_grid(idx, nq, chunks, scan_mfma_blocks_per_cu(idx->dp, s.mfma_f4 != 0, s.mf_rg, s.npl == 4)),
                             st));
   } else {
     HIPCHK(launch_scan_popcnt(s, 1, grid, st));
