@@ -25,6 +25,10 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Ordered "less or equal" of __builtin_amdgcn_fcmpf (the compare's lane mask
+// directly; false where either operand is NaN).
+constexpr int kCmpOLE = 5;
+
 struct RowInfo {
   PairRec rec;
   PairTerms t;        // the pair's estimator constants (pair_terms / pair_terms_ip)
@@ -236,20 +240,20 @@ __device__ void mfma_unit(const SearchDev& s, int64_t start, int64_t end, const 
         if (!hl[h]) continue;
         const int row = 16 * h + 4 * grp + i;
         const RowInfo& ri = rows[row];
-        float dist, lbe;
+        float d0, l0;
         const int ipv = acc[h][i] + s.qoff * pc;
-        estimate(ri.rec, ri.t, sf, ct, ipv, pc, dist, lbe);
+        est_dl(ri.t, sf, ct, est_y(ri.t, ipv, pc), d0, l0);
         const bool live = pvalid && ri.valid;
-        const float lb = live ? lbe : __builtin_inff();
+        const float lb = live ? l0 + ri.t.pt : __builtin_inff();
         if (DEBUG && row == 0 && live) {
           const int64_t o = p - dbg_base;
           dbg_ip[o] = ipv;
           dbg_pc[o] = pc;
           dbg_est[o] = estimate_est(ri.rec, s.fac[p].y, ipv, pc);
-          dbg_dist[o] = dist;
+          dbg_dist[o] = d0 + ri.t.pt;
           dbg_lb[o] = lb;
         }
-        pass[h][i] = live && lb <= ri.tau;
+        pass[h][i] = live && l0 <= ri.tau - ri.t.pt;   // the bound test without the pair term
         lbv[h][i] = lb;
       }
     }
@@ -439,7 +443,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_mfma(SearchDev s) {
       ri.seg_base = 0;
       ri.count_slot = -1;
       ri.rec.k1 = ri.rec.k2 = ri.rec.k0 = ri.rec.b = 0.f;
-      ri.t.pt = ri.t.coef = ri.t.coefh = 0.f;
+      ri.t.a1 = ri.t.a2 = ri.t.a0 = ri.t.pt = ri.t.coefh = 0.f;
       if (R * gi + i < cnt) {
         const int64_t g = s.mf_pairs[s.mf_pair_off[list] + R * gi + i];
         const int64_t q = g / s.nprobe;
@@ -657,18 +661,24 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
   if constexpr (RG == 1) {
     if (!hl[0]) return;   // no live row in the unit
   }
-  // this lane's rows' thresholds in registers, -inf for rows outside the
-  // scanned phase (read in the loop without a branch), and their validity
-  // (the parity export reports live rows only)
+  // this lane's rows' estimator constants in registers: y = a1 acc + a2 pc +
+  // a0 (the int8 accumulator is 8 <x_b, q_u>, so its a1 is divided by 8,
+  // exactly), coefh, and the threshold tau - pt of the bound test (-inf for
+  // rows outside the scanned phase, so the loop reads it without a branch);
+  // their validity for the parity export
   bool rval[RG][4];
-  float rtau[RG][4];
+  float ra1[RG][4], ra2[RG][4], ra0[RG][4], rch[RG][4], rtp[RG][4];
 #pragma unroll
   for (int h = 0; h < RG; ++h)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const RowInfo& ri = rows[16 * h + 4 * grp + i];
       rval[h][i] = ri.valid != 0;
-      rtau[h][i] = ri.valid != 0 ? ri.tau : -__builtin_inff();
+      ra1[h][i] = F4 ? ri.t.a1 : ri.t.a1 * 0.125f;
+      ra2[h][i] = ri.t.a2;
+      ra0[h][i] = ri.t.a0;
+      rch[h][i] = ri.t.coefh;
+      rtp[h][i] = ri.valid != 0 ? ri.tau - ri.t.pt : -__builtin_inff();
     }
   // one block of 16 codes at unit offset rb, from its loaded bits and factors
   auto block = [&](int rb, const uint32_t* bw, float2 sf, float fi) {
@@ -717,13 +727,11 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
             acc[h] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[h][2 * j + 1], b1, acc[h], 0, 0, 0);
           }
       }
-#pragma unroll
-      for (int h = 0; h < RG; ++h)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[h][i] >>= 3;   // 8 <x_b, q_u>, exact
     }
     int pc = pcp + __shfl_xor(pcp, 16, kWave);
     pc += __shfl_xor(pc, 32, kWave);
+    const float pcf = (float)pc;
+    const uint64_t pvmask = __builtin_amdgcn_ballot_w64(pvalid);
     // lanes past the end hold the last code's factors; their rows do not pass
     const float ct = s.metric != 0 ? -fi : code_term_l2(sf);
 #pragma unroll
@@ -732,31 +740,32 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = 16 * h + 4 * grp + i;
-        const RowInfo& ri = rows[row];
-        float dist, lbe;
-        const int ipv = acc[h][i];   // B_q <= 4 on this path: q_u - qoff = q_u
-        estimate(ri.rec, ri.t, sf, ct, ipv, pc, dist, lbe);
-        const float lb = lbe;
-        const bool pass = pvalid & (lb <= rtau[h][i]);
+        // the same y, d0 and l0 as est_y / est_dl on the integer inner product
+        const float y = fmaf(ra1[h][i], (float)acc[h][i], fmaf(ra2[h][i], pcf, ra0[h][i]));
+        const float d0 = fmaf(sf.x, y, ct);
+        const float l0 = fmaf(rch[h][i], sf.y, d0);
         if constexpr (DEBUG) {
           if (row == 0 && pvalid && rval[h][i]) {
+            const RowInfo& ri = rows[row];
+            const int ipv = F4 ? acc[h][i] : acc[h][i] >> 3;   // B_q <= 4 here: q_u - qoff = q_u
             const int64_t o = p - dbg_base;
             dbg_ip[o] = ipv;
             dbg_pc[o] = pc;
             dbg_est[o] = estimate_est(ri.rec, s.fac[p].y, ipv, pc);
-            dbg_dist[o] = dist;
-            dbg_lb[o] = lb;
+            dbg_dist[o] = d0 + ri.t.pt;
+            dbg_lb[o] = l0 + ri.t.pt;
           }
         } else {
           // this row group's 16 codes: bits 16 grp .. +15 of the ballot (most
           // blocks have no candidate at all)
-          const uint64_t m = __builtin_amdgcn_ballot_w64(pass);
+          const uint64_t m = __builtin_amdgcn_fcmpf(l0, rtp[h][i], kCmpOLE) & pvmask;
           if (m != 0ull) {
             const uint32_t mine = (uint32_t)(m >> (16 * grp)) & 0xFFFFu;
-            if (pass) {
+            if ((mine >> col) & 1u) {
+              const RowInfo& ri = rows[row];
               Cand cd;
               cd.pos = (int32_t)p;
-              cd.lb = lb;
+              cd.lb = l0 + ri.t.pt;
               s.seg[ri.seg_base + cnt[h][i] + __popc(mine & ((1u << col) - 1u))] = cd;
             }
             cnt[h][i] += __popc(mine);
@@ -831,7 +840,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_mfma_w(SearchDev s) {
         ri.seg_base = 0;
         ri.count_slot = -1;
         ri.rec.k1 = ri.rec.k2 = ri.rec.k0 = ri.rec.b = 0.f;
-        ri.t.pt = ri.t.coef = ri.t.coefh = 0.f;
+        ri.t.a1 = ri.t.a2 = ri.t.a0 = ri.t.pt = ri.t.coefh = 0.f;
         if (R * gi + lane < cnt) {
           g = s.mf_pairs[s.mf_pair_off[list] + R * gi + lane];
           const int64_t q = g / s.nprobe;

@@ -73,8 +73,9 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
   }
 #pragma unroll
   for (int u = 0; u < UN; ++u) {
-    float dist, lb;
-    estimate(rec, pt, f[u], ct[u], ip[u], pc[u], dist, lb);
+    float d0, l0;
+    est_dl(pt, f[u], ct[u], est_y(pt, ip[u], pc[u]), d0, l0);
+    const float dist = d0 + pt.pt, lb = l0 + pt.pt;
     const int32_t off = p[u] - start;
     if constexpr (PHASE == 0) {
       if (valid[u]) {
@@ -97,7 +98,7 @@ __device__ __forceinline__ void scan_step(const SearchDev& s, const UnitDesc& w,
         s.dbg_lb[o] = lb;
       }
     } else {
-      const bool pass = valid[u] && (lb <= tau);
+      const bool pass = valid[u] && (l0 <= tau);   // tau here is tau - pt
       const uint64_t m = __ballot(pass);
       if (pass) {
         Cand cd;
@@ -116,6 +117,7 @@ template <int WS, int UN, int PHASE, int NPL, typename PL>
 __device__ __forceinline__ int scan_unit(const SearchDev& s, const UnitDesc& w, const PairRec& rec, const PL& pl,
                                          float tau, float hwk) {
   const PairTerms pt = s.metric != 0 ? pair_terms_ip(rec, hwk, uniform_f32(s.pair_pt[w.g])) : pair_terms(rec, hwk);
+  tau -= pt.pt;   // the bound test takes lb - pt against tau - pt
   const int32_t start = (int32_t)w.start, wend = (int32_t)(w.start + w.len);
   int count = 0;
   int32_t b0 = start;

@@ -76,30 +76,51 @@ __device__ __forceinline__ void code_ip(const uint64_t* __restrict__ row, int W,
 //   dist = (M_q - <q_r, c>) - <o_r - c, c> - b G x,   lb = dist - b (eps0 / sqrt(D - 1)) H:
 // per-pair constants M_q - <q_r, c> (from the quantiser), -b, -b eps0 / sqrt(D - 1),
 // and the per-code term -<o_r - c, c> in place of a^2.
+// Per-pair constants of the scan's estimator (Theorem 3.2 through the scan
+// factors G, H): with x the estimate of <o_bar, q> from (ip, pc) (k1 ip +
+// k2 pc + k0) and coef its coefficient in the distance, y = coef x =
+// a1 ip + a2 pc + a0 (coef folded into k1, k2, k0), the distance estimate is
+// G y + ct + pt and its lower bound adds coefh H. The bound test compares the
+// bound without the pair term pt against tau - pt.
 struct PairTerms {
-  float pt, coef, coefh;   // pair term, coefficient of G x, coefficient of H
+  float a1, a2, a0;   // coef k1, coef k2, coef k0
+  float pt, coefh;    // pair term, coefficient of H
 };
-__device__ __forceinline__ PairTerms pair_terms(const PairRec& r, float hwk) {
+__device__ __forceinline__ PairTerms pair_terms_from(const PairRec& r, float coef, float hwk, float pt) {
   PairTerms t;
-  t.pt = r.b * r.b;
-  t.coef = -2.f * r.b;
-  t.coefh = t.coef * hwk;
+  t.a1 = coef * r.k1;
+  t.a2 = coef * r.k2;
+  t.a0 = coef * r.k0;
+  t.pt = pt;
+  t.coefh = coef * hwk;
   return t;
 }
+// L2: -2 ||q_r - c|| <o_bar, q> and pair term ||q_r - c||^2.
+__device__ __forceinline__ PairTerms pair_terms(const PairRec& r, float hwk) {
+  return pair_terms_from(r, -2.f * r.b, hwk, r.b * r.b);
+}
+// inner product: -||q_r - c|| <o_bar, q> and pair term M_q - <q_r, c>.
 __device__ __forceinline__ PairTerms pair_terms_ip(const PairRec& r, float hwk, float pair_term) {
-  PairTerms t;
-  t.pt = pair_term;
-  t.coef = -r.b;
-  t.coefh = t.coef * hwk;
-  return t;
+  return pair_terms_from(r, -r.b, hwk, pair_term);
 }
 // The per-code term: a^2 = G^2 - H^2 (L2), or -<o_r - c, c> (inner product).
 __device__ __forceinline__ float code_term_l2(float2 sf) { return fmaf(sf.x, sf.x, -sf.y * sf.y); }
-__device__ __forceinline__ void estimate(const PairRec& r, const PairTerms& t, float2 sf, float ct, int ip, int pc,
-                                         float& dist, float& lb) {
-  const float xq = fmaf(r.k1, (float)ip, fmaf(r.k2, (float)pc, r.k0));
-  dist = fmaf(t.coef * sf.x, xq, ct + t.pt);
-  lb = fmaf(t.coefh, sf.y, dist);
+// y from the integer inner product and popcount.
+__device__ __forceinline__ float est_y(const PairTerms& t, int ip, int pc) {
+  return fmaf(t.a1, (float)ip, fmaf(t.a2, (float)pc, t.a0));
+}
+// Distance estimate and lower bound, both without the pair term pt.
+__device__ __forceinline__ void est_dl(const PairTerms& t, float2 sf, float ct, float y, float& d0, float& l0) {
+  d0 = fmaf(sf.x, y, ct);
+  l0 = fmaf(t.coefh, sf.y, d0);
+}
+// Distance estimate and lower bound (the bootstrap and parity exports).
+__device__ __forceinline__ void estimate(const PairTerms& t, float2 sf, float ct, int ip, int pc, float& dist,
+                                         float& lb) {
+  float d0, l0;
+  est_dl(t, sf, ct, est_y(t, ip, pc), d0, l0);
+  dist = d0 + t.pt;
+  lb = l0 + t.pt;
 }
 // The estimate itself, from the stored (a, <o_bar,o>) (the parity exports).
 __device__ __forceinline__ float estimate_est(const PairRec& r, float ipo, int ip, int pc) {
