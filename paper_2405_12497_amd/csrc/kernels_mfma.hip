@@ -774,18 +774,22 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
       }
     }
   };
-  // two register sets in turn: the next block's loads are in flight while
-  // this one computes
-  uint32_t bA[NB], bB[NB];
-  float2 sA, sB;
-  float fA, fB;
+  // three register sets in turn: the next two blocks' loads are in flight
+  // while this one computes (blocks past the end reload the last code)
+  uint32_t bA[NB], bB[NB], bC[NB];
+  float2 sA, sB, sC;
+  float fA, fB, fC;
   load_block(0, bA, sA, fA);
-  for (int rb = 0; rb < n; rb += 32) {
-    load_block(min(rb + 16, n - 1), bB, sB, fB);
+  load_block(min(16, n - 1), bB, sB, fB);
+  for (int rb = 0; rb < n; rb += 48) {
+    load_block(min(rb + 32, n - 1), bC, sC, fC);
     block(rb, bA, sA, fA);
     if (rb + 16 >= n) break;
-    load_block(min(rb + 32, n - 1), bA, sA, fA);
+    load_block(min(rb + 48, n - 1), bA, sA, fA);
     block(rb + 16, bB, sB, fB);
+    if (rb + 32 >= n) break;
+    load_block(min(rb + 64, n - 1), bB, sB, fB);
+    block(rb + 32, bC, sC, fC);
   }
   if constexpr (!DEBUG) {
     if (col == 0) {

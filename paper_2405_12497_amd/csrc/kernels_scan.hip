@@ -69,7 +69,10 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
   const int lane = lane_id();
   const int W = s.W;
   const int64_t npairs = s.nq * s.nprobe;
-  const int64_t g0 = uniform_i64(((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * PPW);
+  // one query's pairs are consecutive: a contiguous run of blocks per XCD
+  // reads the query's rotated vector into one L2
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t g0 = uniform_i64((blk * kWaves + (threadIdx.x >> 6)) * PPW);
   if (g0 >= npairs) return;
   float rv[PPW][WS];
   float qq[PPW];

@@ -191,6 +191,16 @@ __device__ __forceinline__ void rounding_u2(uint64_t seed, uint64_t qid, uint32_
   u1 = (float)((uint32_t)(z >> 16) & 0xFFFFFFu) * (1.0f / 16777216.0f);
 }
 
+// Workgroups go to the XCDs in turn (workgroup b to XCD b % 8): this block
+// order gives each XCD a contiguous run of the nb blocks (the remainder past
+// a multiple of 8 keeps its place), so work on neighbouring items shares one
+// L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t per = nb / kScanSlices;
+  if (b >= per * kScanSlices) return b;
+  return (b % kScanSlices) * per + b / kScanSlices;
+}
+
 // Interleaved code layout: for position p (list order), 64-bit word w lives at
 // codes[((p >> 6) * W + w) * 64 + (p & 63)], so word w of 64 consecutive codes
 // is one contiguous 512-byte row.
