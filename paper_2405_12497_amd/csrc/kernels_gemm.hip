@@ -519,6 +519,151 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const float* __restrict__ A
     }
 }
 
+// ---------------------------------------------------------------- split-BF16 centroid distances
+// MODE 1 of the FP32 GEMM with the product <A[m], C[n]> summed as
+// hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 (FP32 accumulation): A is
+// split per element as it is stashed, the centroids C come as hi/lo planes
+// [n][k]. Tile 128 x 128, K step 32, four waves in a 2 x 2 grid each owning
+// 4 x 4 blocks of 16 x 16. The MFMA takes the centroid fragment first, so
+// lane l ends with row l % 16 and columns 4 (l / 16) .. + 3 of each block: the
+// output and the group minima are laid out as in the FP32 kernel. The next K
+// step's global reads are in flight during this step's MFMAs.
+constexpr int CDT = 128, CDK = 32, CDP = CDK + 8;   // tile, K step, padded LDS row (bf16)
+__global__ __launch_bounds__(256) void k_cd_bf16x3(const float* __restrict__ A, int64_t lda,
+                                                   const uint16_t* __restrict__ Chi,
+                                                   const uint16_t* __restrict__ Clo, const float* __restrict__ bn,
+                                                   float* __restrict__ Y, int64_t ldy, int64_t M, int N, int K,
+                                                   float* __restrict__ gmin) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[CDT][CDP], Al[CDT][CDP], Bh[CDT][CDP], Bl[CDT][CDP];
+  __shared__ float an_s[CDT];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t m0 = (int64_t)blockIdx.x * CDT;
+  const int n0 = blockIdx.y * CDT;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // loaders: thread t takes row t / 2 of both tiles, 16 consecutive k from (t % 2) * 16
+  const int lr = tid >> 1, lk = (tid & 1) * 16;
+  const int64_t am = m0 + lr;
+  const int bnr = n0 + lr;
+  const float* arow = am < M ? A + am * lda : nullptr;
+  const uint16_t* hrow = bnr < N ? Chi + (int64_t)bnr * K : nullptr;
+  const uint16_t* lrow = bnr < N ? Clo + (int64_t)bnr * K : nullptr;
+  const bool kvec = (K & 15) == 0 && (lda & 3) == 0;
+  float av[16];
+  u16x8 bh[2], bl[2];
+  auto fetch = [&](int k0) {
+    const int k = k0 + lk;
+    if (kvec && k < K) {   // 16 consecutive k inside the row
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (arow) v = *reinterpret_cast<const float4*>(arow + k + 4 * q);
+        av[4 * q] = v.x;
+        av[4 * q + 1] = v.y;
+        av[4 * q + 2] = v.z;
+        av[4 * q + 3] = v.w;
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        bh[q] = hrow ? *reinterpret_cast<const u16x8*>(hrow + k + 8 * q) : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        bl[q] = lrow ? *reinterpret_cast<const u16x8*>(lrow + k + 8 * q) : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      }
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const bool in = k + i < K;
+      av[i] = (arow && in) ? arow[k + i] : 0.f;
+      bh[i >> 3][i & 7] = (hrow && in) ? hrow[k + i] : (uint16_t)0;
+      bl[i >> 3][i & 7] = (lrow && in) ? lrow[k + i] : (uint16_t)0;
+    }
+  };
+  // the A tile's squared row norms, summed as the tiles are stashed (the two
+  // threads of a row add up at the end)
+  float asq = 0.f;
+  auto stash = [&]() {
+    // hardware conversions, round to nearest even (as f2bf)
+    bf16x8 h[2], l[2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const __bf16 hv = (__bf16)av[i];
+      h[i >> 3][i & 7] = hv;
+      l[i >> 3][i & 7] = (__bf16)(av[i] - (float)hv);
+      asq = fmaf(av[i], av[i], asq);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      *reinterpret_cast<bf16x8*>(&Ah[lr][lk + 8 * q]) = h[q];
+      *reinterpret_cast<bf16x8*>(&Al[lr][lk + 8 * q]) = l[q];
+      *reinterpret_cast<u16x8*>(&Bh[lr][lk + 8 * q]) = bh[q];
+      *reinterpret_cast<u16x8*>(&Bl[lr][lk + 8 * q]) = bl[q];
+    }
+  };
+  fetch(0);
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  for (int k0 = 0; k0 < K; k0 += CDK) {
+    stash();
+    __syncthreads();
+    if (k0 + CDK < K) fetch(k0 + CDK);   // in flight during this step's MFMAs
+    bf16x8 a_h[4], a_l[4], b_h[4], b_l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a_h[i] = *reinterpret_cast<const bf16x8*>(&Ah[wm + 16 * i + fr][fk]);
+      a_l[i] = *reinterpret_cast<const bf16x8*>(&Al[wm + 16 * i + fr][fk]);
+      b_h[i] = *reinterpret_cast<const bf16x8*>(&Bh[wn + 16 * i + fr][fk]);
+      b_l[i] = *reinterpret_cast<const bf16x8*>(&Bl[wn + 16 * i + fr][fk]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b_l[j], a_h[i], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b_h[j], a_l[i], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b_h[j], a_h[i], acc[i][j], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+  asq += __shfl_xor(asq, 1, kWave);
+  if ((tid & 1) == 0) an_s[lr] = asq;
+  __syncthreads();
+  // output block (i, j): lane holds row fr, columns 4 fg .. 4 fg + 3
+  const int fg = lane >> 4;
+  const bool y_vec = (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0;
+  const bool want_gmin = gmin != nullptr && n0 + wn < N;
+  const int G = ((N + 63) >> 6) * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t m = m0 + wm + i * 16 + fr;
+    if (m >= M) continue;
+    const float amv = an_s[wm + i * 16 + fr];
+    float gv = __builtin_inff();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn + j * 16 + 4 * fg;
+      f32x4 o = acc[i][j];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        o[e] = fmaxf(amv + bn[min(n + e, N - 1)] - 2.f * o[e], 0.f);
+        gv = (n + e < N) ? fminf(gv, o[e]) : gv;
+      }
+      if (n >= N) continue;
+      float* y = Y + m * ldy + n;
+      if (y_vec && n + 3 < N) {
+        *reinterpret_cast<f32x4*>(y) = o;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (n + e < N) y[e] = o[e];
+      }
+    }
+    if (want_gmin) gmin[m * G + ((n0 + wn) >> 6) * 4 + fg] = gv;
+  }
+}
+
 __global__ void k_rotate_f64(const float* __restrict__ X, int64_t M, int K,
                              const double* __restrict__ P, int N, float* __restrict__ Y) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -598,7 +743,14 @@ hipError_t launch_gemm_bf16x3(const float* A, int64_t lda, const float* sub, con
 }
 
 hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float* Ct,
-                                const float* cn, int nlist, float* D, float* gmin, hipStream_t st) {
+                                const float* cn, int nlist, float* D, float* gmin, hipStream_t st,
+                                const uint16_t* Chi, const uint16_t* Clo) {
+  if (Chi != nullptr && nq > kCdFewMax) {   // split-BF16 products, always the 128 tile (gmin when asked)
+    const dim3 grid((unsigned)((nq + CDT - 1) / CDT), (unsigned)((nlist + CDT - 1) / CDT));
+    hipLaunchKernelGGL(k_cd_bf16x3, grid, dim3(256), 0, st, Q, (int64_t)dim, Chi, Clo, cn, D, (int64_t)nlist, nq,
+                       nlist, dim, gmin);
+    return hipGetLastError();
+  }
   launch_f32_mfma<1>(Q, (int64_t)dim, nullptr, nullptr, Ct, (int64_t)nlist, D, (int64_t)nlist, nq, nlist, dim,
                      cn, gemm_f32_wide_tile(nq, nlist) ? gmin : nullptr, st);
   return hipGetLastError();

@@ -632,31 +632,35 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
   const int o0 = (int)(start & 63);
   const int64_t row0 = start >> 6;
   constexpr int NB = T2;   // registers of code bits per block
-  // this lane group's first word (2 t + (grp >> 1) for pair t) folded into the base
-  const uint32_t* c32 = reinterpret_cast<const uint32_t*>(s.codes) + (size_t)row0 * WS * 128 + (grp & 1);
-  const uint32_t* c32g = c32 + 128 * (grp >> 1);
-  const float2* sfu = s.sfac + start;
-  const float* fiu = s.metric != 0 ? s.fip + start : nullptr;
+  // wave-uniform bases (the unit's first code row, its first factors) and
+  // per-lane 32-bit byte offsets, so the loads take the scalar-base form
+  const char* cbase = reinterpret_cast<const char*>(s.codes) + (size_t)row0 * WS * 512;
+  const char* sbase = reinterpret_cast<const char*>(s.sfac + start);
+  const char* fbase = s.metric != 0 ? reinterpret_cast<const char*>(s.fip + start) : nullptr;
+  // this lane's half (grp & 1) of word 2 t + (grp >> 1)
+  const uint32_t lane_b = 4u * (128u * (uint32_t)(grp >> 1) + (uint32_t)(grp & 1));
   // the block at unit offset rel: this lane's code (clamped into the unit; the
   // columns past its end are never used), its bits and its scan factors (and
   // inner-product term)
   auto load_block = [&](int rel, uint32_t* bw, float2& sf, float& fi) {
-    const int r = min(rel + col, n - 1);
-    const int x = o0 + r;
-    const uint32_t word0 = (uint32_t)((x >> 6) * WS * 64 + (x & 63));   // the wave-unit kernels have W == WS
+    const uint32_t r = (uint32_t)min(rel + col, n - 1);
+    const uint32_t x = (uint32_t)o0 + r;
+    // word 0 of position x (the wave-unit kernels have W == WS), in bytes
+    const uint32_t wb = 8u * ((x >> 6) * (uint32_t)WS * 64u + (x & 63u));
     // 32 bits of dimensions 128 t + 32 grp .. +31: half grp & 1 of word
     // 2 t + (grp >> 1) (for an odd width, zero past the code's last word)
 #pragma unroll
     for (int t = 0; t < T2; ++t) {
       if (WS % 2 == 0 || t + 1 < T2) {
-        bw[t] = c32g[2 * word0 + 256 * t];
+        bw[t] = *reinterpret_cast<const uint32_t*>(cbase + (wb + lane_b + 1024u * (uint32_t)t));
       } else {
-        const uint32_t v = c32[2 * (word0 + (WS - 1) * 64)];
+        const uint32_t v =
+            *reinterpret_cast<const uint32_t*>(cbase + (wb + 512u * (uint32_t)(WS - 1) + 4u * (uint32_t)(grp & 1)));
         bw[t] = grp < 2 ? v : 0u;
       }
     }
-    sf = sfu[r];
-    fi = fiu != nullptr ? fiu[r] : 0.f;
+    sf = *reinterpret_cast<const float2*>(sbase + 8u * r);
+    fi = fbase != nullptr ? *reinterpret_cast<const float*>(fbase + 4u * r) : 0.f;
   };
   if constexpr (RG == 1) {
     if (!hl[0]) return;   // no live row in the unit

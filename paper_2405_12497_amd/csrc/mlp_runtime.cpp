@@ -427,7 +427,7 @@ extern "C" rbq_status rbq_nprobe_labels(rbq_index* idx, const float* queries, in
     rs = prepare_queries(idx, qs, m, st, &qs);   // the cosine metric ranks lists for unit queries
     if (rs != RBQ_OK) return rs;
     HIPCHK(launch_centroid_dist(qs, m, idx->dim, (const float*)idx->d_centT.p, idx->probe_cnorm(), idx->nlist,
-                                (float*)idx->ws.cd.p, nullptr, st));
+                                (float*)idx->ws.cd.p, nullptr, st, idx->cent_hi(), idx->cent_lo()));
     HIPCHK(launch_probe_need((const float*)idx->ws.cd.p, m, idx->nlist, nn_ids + q0 * k, k,
                              (const int32_t*)idx->d_id2list.p, idx->n, nd + q0, st));
   }

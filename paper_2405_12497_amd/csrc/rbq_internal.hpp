@@ -187,8 +187,10 @@ __device__ __forceinline__ void rounding_u2(uint64_t seed, uint64_t qid, uint32_
                                            float& u1) {
   const uint32_t j = ((i >> 7) << 6) | (i & 63u);
   const uint64_t z = splitmix64(seed ^ ((qid << 40) + ((uint64_t)list << 12) + (uint64_t)j));
-  u0 = (float)(uint32_t)(z >> 40) * (1.0f / 16777216.0f);
-  u1 = (float)((uint32_t)(z >> 16) & 0xFFFFFFu) * (1.0f / 16777216.0f);
+  // 24-bit fields from the two 32-bit halves (exact in FP32)
+  const uint32_t hi = (uint32_t)(z >> 32), lo = (uint32_t)z;
+  u0 = (float)(hi >> 8) * (1.0f / 16777216.0f);
+  u1 = (float)(__builtin_amdgcn_alignbit(hi, lo, 16) & 0xFFFFFFu) * (1.0f / 16777216.0f);
 }
 
 // Workgroups go to the XCDs in turn (workgroup b to XCD b % 8): this block
@@ -229,8 +231,13 @@ hipError_t launch_gemm_bf16x3(const float* A, int64_t lda, const float* sub, con
 // holds lists 64 (g / 4) + 4 (g % 4) + 16 j + e, j, e < 4).
 bool gemm_f32_wide_tile(int64_t M, int N);
 inline bool centroid_gmin(int64_t nq, int nlist) { return gemm_f32_wide_tile(nq, nlist); }
+// Chi, Clo (optional): the centroids as BF16 hi/lo planes [nlist][dim]; given,
+// batches of more than 8 queries take split-BF16 products (hi*hi + hi*lo +
+// lo*hi) on the BF16 matrix cores, always with 128-wide tiles (gmin written
+// when given).
 hipError_t launch_centroid_dist(const float* Q, int64_t nq, int dim, const float* Ct,
-                                const float* cn, int nlist, float* D, float* gmin, hipStream_t st);
+                                const float* cn, int nlist, float* D, float* gmin, hipStream_t st,
+                                const uint16_t* Chi = nullptr, const uint16_t* Clo = nullptr);
 // The FP32 query rotation qrot = Q * P (P is [dim x dp]) and launch_centroid_dist's
 // outputs, in one launch when the distances use 128-wide tiles.
 hipError_t launch_rotate_centroid(const float* Q, int64_t nq, int dim, const float* P, int dp, float* qrot,

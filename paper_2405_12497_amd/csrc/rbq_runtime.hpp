@@ -164,6 +164,11 @@ struct rbq_index {
   rbq::DBuf d_codes, d_fac, d_raw, d_ids, d_list_off, d_cent, d_centT, d_cnorm, d_crot;
   rbq::DBuf d_sfac;   // scan factors per code (see estimate), derived from d_fac
   rbq::DBuf d_P32, d_Phi, d_Plo;
+  // BF16X3 indexes: the centroids as BF16 hi/lo planes [nlist][dim] for the
+  // split-BF16 centroid distances (null otherwise)
+  rbq::DBuf d_chi, d_clo;
+  const uint16_t* cent_hi() const { return (const uint16_t*)d_chi.p; }
+  const uint16_t* cent_lo() const { return (const uint16_t*)d_clo.p; }
   rbq::DBuf d_id2list;   // id -> list (built on first use by rbq_nprobe_labels)
   // inner-product metrics: per code <o_r - c, c>, the centroid norms the probe
   // GEMM uses (all max ||c||^2, so its ||q||^2 + . - 2 <q, c> ranks by <q, c>),

@@ -251,7 +251,7 @@ rbq_index::~rbq_index() {
 
 std::vector<DBuf*> rbq_index::all_buffers() {
   return {&d_codes, &d_fac, &d_sfac, &d_raw, &d_ids, &d_list_off, &d_cent, &d_centT, &d_cnorm, &d_crot,
-          &d_P32, &d_Phi, &d_Plo, &d_id2list, &d_fip, &d_cnorm_probe, &ws.qrot, &ws.cd, &ws.cgmin, &ws.probe, &ws.probe_d, &ws.pairs,
+          &d_P32, &d_Phi, &d_Plo, &d_chi, &d_clo, &d_id2list, &d_fip, &d_cnorm_probe, &ws.qrot, &ws.cd, &ws.cgmin, &ws.probe, &ws.probe_d, &ws.pairs,
           &ws.planes, &ws.qu8, &ws.pair_choff, &ws.pair_codeoff, &ws.q_nch, &ws.q_p0, &ws.q_n0,
           &ws.q_ncode, &ws.offs, &ws.counters, &ws.seg, &ws.seg_count, &ws.p0buf, &ws.tau,
           &ws.chunk_qcode,
@@ -383,6 +383,22 @@ rbq_status upload_model(rbq_index* idx, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(idx->d_cent.p, idx->h_cent.data(), (size_t)L * D * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(idx->d_centT.p, ct.data(), ct.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(idx->d_cnorm.p, cn.data(), cn.size() * 4, hipMemcpyHostToDevice, st));
+  if (idx->prm.rot_precision == RBQ_ROT_BF16X3) {   // centroid hi/lo planes for the split-BF16 distances
+    std::vector<uint16_t> chi((size_t)L * D), clo((size_t)L * D);
+    for (size_t e = 0; e < chi.size(); ++e) {
+      const float v = idx->h_cent[e];
+      chi[e] = f2bf_host(v);
+      clo[e] = f2bf_host(v - bf2f_host(chi[e]));
+    }
+    HIPCHK(idx->d_chi.ensure(chi.size() * 2));
+    HIPCHK(idx->d_clo.ensure(clo.size() * 2));
+    HIPCHK(hipMemcpyAsync(idx->d_chi.p, chi.data(), chi.size() * 2, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(idx->d_clo.p, clo.data(), clo.size() * 2, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  } else {
+    idx->d_chi.release();
+    idx->d_clo.release();
+  }
   if (idx->prm.metric != RBQ_METRIC_L2) {   // the probe ranks by <q, c>: every centroid norm set to the largest
     const float cmax2 = *std::max_element(cn.begin(), cn.end());
     std::vector<float> cp(L, cmax2);
@@ -432,7 +448,7 @@ void account_bytes(rbq_index* idx) {
   int64_t b = 0;
   for (DBuf* d : {&idx->d_codes, &idx->d_fac, &idx->d_sfac, &idx->d_raw, &idx->d_ids, &idx->d_list_off,
                   &idx->d_cent, &idx->d_centT, &idx->d_cnorm, &idx->d_crot, &idx->d_P32,
-                  &idx->d_Phi, &idx->d_Plo, &idx->d_fip, &idx->d_cnorm_probe})
+                  &idx->d_Phi, &idx->d_Plo, &idx->d_chi, &idx->d_clo, &idx->d_fip, &idx->d_cnorm_probe})
     b += (int64_t)d->cap;
   idx->device_bytes = b;
 }
@@ -816,7 +832,7 @@ rbq_status front(rbq_index* idx, const float* queries, int64_t nq, int nprobe,
     rbq_status rs = rotate_rows(idx, queries, idx->dim, nullptr, nullptr, nq, (float*)w.qrot.p, st);
     if (rs != RBQ_OK) return rs;
     HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
-                                idx->probe_cnorm(), idx->nlist, (float*)w.cd.p, (float*)w.cgmin.p, st));
+                                idx->probe_cnorm(), idx->nlist, (float*)w.cd.p, (float*)w.cgmin.p, st, idx->cent_hi(), idx->cent_lo()));
   }
   HIPCHK(launch_select_probe((const float*)w.cd.p, (const float*)w.cgmin.p, nq, idx->nlist, nprobe, nprobe_q,
                              (int32_t*)w.probe.p, (float*)w.probe_d.p, st));
@@ -1538,7 +1554,7 @@ extern "C" rbq_status rbq_debug_centroid_dists(rbq_index* idx, const float* quer
   rs = prepare_queries(idx, queries, nq, st, &queries);
   if (rs != RBQ_OK) return rs;
   HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
-                              idx->probe_cnorm(), idx->nlist, (float*)idx->ws.cd.p, nullptr, st));
+                              idx->probe_cnorm(), idx->nlist, (float*)idx->ws.cd.p, nullptr, st, idx->cent_hi(), idx->cent_lo()));
   HIPCHK(hipMemcpyAsync(dists, idx->ws.cd.p, (size_t)nq * idx->nlist * sizeof(float), hipMemcpyDeviceToDevice,
                         st));
   return RBQ_OK;
@@ -1561,7 +1577,7 @@ extern "C" rbq_status rbq_debug_probe(rbq_index* idx, const float* queries, int6
   if (rs != RBQ_OK) return rs;
   HIPCHK(launch_centroid_dist(queries, nq, idx->dim, (const float*)idx->d_centT.p,
                               idx->probe_cnorm(), idx->nlist, (float*)idx->ws.cd.p,
-                              (float*)idx->ws.cgmin.p, st));
+                              (float*)idx->ws.cgmin.p, st, idx->cent_hi(), idx->cent_lo()));
   HIPCHK(launch_select_probe((const float*)idx->ws.cd.p, (const float*)idx->ws.cgmin.p, nq, idx->nlist, nprobe,
                              nullptr, lists,
                              dists, st));
