@@ -534,8 +534,10 @@ __global__ __launch_bounds__(256) void k_cd_bf16x3(const float* __restrict__ A, 
                                                    const uint16_t* __restrict__ Clo, const float* __restrict__ bn,
                                                    float* __restrict__ Y, int64_t ldy, int64_t M, int N, int K,
                                                    float* __restrict__ gmin) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[CDT][CDP], Al[CDT][CDP], Bh[CDT][CDP], Bl[CDT][CDP];
-  __shared__ float an_s[CDT];
+  // two buffers of the four operand tiles (80 KiB: two blocks per CU); the
+  // row norms reuse buffer 0 after the K loop
+  __shared__ __attribute__((aligned(16))) uint16_t Ts[2][4][CDT][CDP];
+  float* an_s = reinterpret_cast<float*>(&Ts[0][0][0][0]);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t m0 = (int64_t)blockIdx.x * CDT;
   const int n0 = blockIdx.y * CDT;
@@ -585,7 +587,11 @@ __global__ __launch_bounds__(256) void k_cd_bf16x3(const float* __restrict__ A, 
   // the A tile's squared row norms, summed as the tiles are stashed (the two
   // threads of a row add up at the end)
   float asq = 0.f;
-  auto stash = [&]() {
+  auto stash = [&](int buf) {
+    auto& Ah = Ts[buf][0];
+    auto& Al = Ts[buf][1];
+    auto& Bh = Ts[buf][2];
+    auto& Bl = Ts[buf][3];
     // hardware conversions, round to nearest even (as f2bf)
     bf16x8 h[2], l[2];
 #pragma unroll
@@ -604,11 +610,17 @@ __global__ __launch_bounds__(256) void k_cd_bf16x3(const float* __restrict__ A, 
     }
   };
   fetch(0);
+  stash(0);
+  __syncthreads();
   const int fr = lane & 15, fk = (lane >> 4) * 8;
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += CDK) {
-    stash();
-    __syncthreads();
-    if (k0 + CDK < K) fetch(k0 + CDK);   // in flight during this step's MFMAs
+    const bool more = k0 + CDK < K;
+    if (more) fetch(k0 + CDK);   // in flight during this step's MFMAs
+    const auto& Ah = Ts[buf][0];
+    const auto& Al = Ts[buf][1];
+    const auto& Bh = Ts[buf][2];
+    const auto& Bl = Ts[buf][3];
     bf16x8 a_h[4], a_l[4], b_h[4], b_l[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -625,7 +637,9 @@ __global__ __launch_bounds__(256) void k_cd_bf16x3(const float* __restrict__ A, 
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b_h[j], a_l[i], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b_h[j], a_h[i], acc[i][j], 0, 0, 0);
       }
+    if (more) stash(buf ^ 1);   // the other buffer: last read before the previous barrier
     __syncthreads();
+    buf ^= 1;
   }
   asq += __shfl_xor(asq, 1, kWave);
   if ((tid & 1) == 0) an_s[lr] = asq;

@@ -66,6 +66,38 @@ __device__ __forceinline__ i32x4 scaled_cols(uint32_t r0, uint32_t r1, uint32_t 
   return v;
 }
 
+// Masked expansion of the wave-unit FP8 x FP4 scan (B_q <= 4). The B dwords
+// of a 128-dimension block are w & 0x11111111, w & 0x22222222,
+// w & 0x44444444 and (w >> 1) & 0x44444444: nibble n of dword m holds bit
+// 4 n + m of the lane group's 32 code bits as E2M1 0.5, 1, 2 or 2 (so B
+// nibble e = 8 m + n, which is k = 32 g + e, carries dimension
+// 32 g + 4 n + m of the block). The FP8 query side carries, for that k, the
+// dimension times 2, 1, 1/2 or 1/2: every product is q_u x_b and the FP32
+// sum is <x_b, q_u> exactly.
+// fp8_scaled: four bytes q (0..15) -> E4M3 codes of 2 q (cls 0), q (1) or
+// q / 2 (2), exact: a byte lookup for q < 8 and code = offset + q above.
+__device__ __forceinline__ uint32_t fp8_scaled(uint32_t q, int cls) {
+  const uint32_t t0 = cls == 0 ? 0x4C484000u : cls == 1 ? 0x44403800u : 0x3C383000u;
+  const uint32_t t1 = cls == 0 ? 0x56545250u : cls == 1 ? 0x4E4C4A48u : 0x46444240u;
+  const uint32_t off = cls == 0 ? 0x50505050u : cls == 1 ? 0x48484848u : 0x40404040u;
+  const uint32_t lo = __builtin_amdgcn_perm(t1, t0, q & 0x07070707u);
+  const uint32_t mask = ((q & 0x08080808u) >> 3) * 0xFFu;
+  return ((q + off) & mask) | (lo & ~mask);
+}
+// Columns r0 = 2 o, r1 = 2 o + 1 of eight dwords d (row n = dword n): the
+// bytes of column r0 for n = 0..3, 4..7, then those of column r1.
+__device__ __forceinline__ void cols2(const i32x4& x0, const i32x4& x1, int o, uint32_t out[4]) {
+  const uint32_t sel = o == 0 ? 0x05010400u : 0x07030602u;
+  const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)x0[1], (uint32_t)x0[0], sel);
+  const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)x0[3], (uint32_t)x0[2], sel);
+  const uint32_t p45 = __builtin_amdgcn_perm((uint32_t)x1[1], (uint32_t)x1[0], sel);
+  const uint32_t p67 = __builtin_amdgcn_perm((uint32_t)x1[3], (uint32_t)x1[2], sel);
+  out[0] = __builtin_amdgcn_perm(p23, p01, 0x05040100u);
+  out[1] = __builtin_amdgcn_perm(p67, p45, 0x05040100u);
+  out[2] = __builtin_amdgcn_perm(p23, p01, 0x07060302u);
+  out[3] = __builtin_amdgcn_perm(p67, p45, 0x07060302u);
+}
+
 // FP8 (E4M3, OCP: bias 7) encodings of the integers 0..15, all exact: the
 // query operand of the FP8 x FP4 contraction (B_q <= 4).
 __constant__ uint8_t kFp8Int[16] = {0x00, 0x38, 0x40, 0x44, 0x48, 0x4A, 0x4C, 0x4E,
@@ -586,19 +618,34 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
 #pragma unroll
     for (int t = 0; t < NA; ++t) {
       if constexpr (F4) {
-        const int d0 = 128 * t + 16 * grp, d1 = 128 * t + 64 + 16 * grp;
-        i32x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (gh >= 0) {
-          const uint64_t* p0 = reinterpret_cast<const uint64_t*>(qr + min(d0, dp - 16));
-          const uint64_t* p1 = reinterpret_cast<const uint64_t*>(qr + min(d1, dp - 16));
-          const uint64_t x0 = p0[0], x1 = p0[1], y0 = p1[0], y1 = p1[1];
-          const uint64_t f0 = d0 < dp ? fp8_group(x0) : 0ull, f1 = d0 < dp ? fp8_group(x1) : 0ull;
-          const uint64_t f2 = d1 < dp ? fp8_group(y0) : 0ull, f3 = d1 < dp ? fp8_group(y1) : 0ull;
-          v[0] = (int)(uint32_t)f0; v[1] = (int)(uint32_t)(f0 >> 32);
-          v[2] = (int)(uint32_t)f1; v[3] = (int)(uint32_t)(f1 >> 32);
-          v[4] = (int)(uint32_t)f2; v[5] = (int)(uint32_t)(f2 >> 32);
-          v[6] = (int)(uint32_t)f3; v[7] = (int)(uint32_t)(f3 >> 32);
+        // masked FP4 expansion: lane group grp = 2 h2 + o holds, in bytes
+        // 8 b + n (b = 0..3), dimension 128 t + 64 (b >> 1) + 32 h2 + 4 n +
+        // 2 o + (b & 1) (column 2 o + (b & 1) of a 32-dimension window), times
+        // 2 (o = 0, b even), 1 (o = 0, b odd) or 1/2 (o = 1); zero past the row
+        const int h2 = grp >> 1, o = grp & 1;
+        const int w0 = 128 * t + 32 * h2, w1 = w0 + 64;
+        i32x4 x0 = {0, 0, 0, 0}, x1 = {0, 0, 0, 0}, y0 = {0, 0, 0, 0}, y1 = {0, 0, 0, 0};
+        if (gh >= 0 && w0 < dp) {
+          x0 = *reinterpret_cast<const i32x4*>(qr + w0);
+          x1 = *reinterpret_cast<const i32x4*>(qr + w0 + 16);
         }
+        if (gh >= 0 && w1 < dp) {
+          y0 = *reinterpret_cast<const i32x4*>(qr + w1);
+          y1 = *reinterpret_cast<const i32x4*>(qr + w1 + 16);
+        }
+        uint32_t cx[4], cy[4];
+        cols2(x0, x1, o, cx);
+        cols2(y0, y1, o, cy);
+        const int c0 = o == 0 ? 0 : 2, c1 = o == 0 ? 1 : 2;   // scale class of columns 2 o and 2 o + 1
+        i32x8 v;
+        v[0] = (int)fp8_scaled(cx[0], c0);
+        v[1] = (int)fp8_scaled(cx[1], c0);
+        v[2] = (int)fp8_scaled(cx[2], c1);
+        v[3] = (int)fp8_scaled(cx[3], c1);
+        v[4] = (int)fp8_scaled(cy[0], c0);
+        v[5] = (int)fp8_scaled(cy[1], c0);
+        v[6] = (int)fp8_scaled(cy[2], c1);
+        v[7] = (int)fp8_scaled(cy[3], c1);
         a[h][t] = v;
       } else if (t % 2 == 0) {
         // int8: K-steps t and t + 1 of the masked expansion, dimensions
@@ -700,8 +747,8 @@ __device__ void mfma_wave_unit(const SearchDev& s, int64_t start, int64_t end, c
       for (int t = 0; t < T2; ++t) {
         const uint32_t bits = bw[t];
         pcp += __popc(bits);
-        const i32x8 b = {bits_to_fp4x8(bits & 0xFFu), bits_to_fp4x8((bits >> 8) & 0xFFu),
-                         bits_to_fp4x8((bits >> 16) & 0xFFu), bits_to_fp4x8(bits >> 24), 0, 0, 0, 0};
+        const i32x8 b = {(int)(bits & 0x11111111u), (int)(bits & 0x22222222u), (int)(bits & 0x44444444u),
+                         (int)((bits >> 1) & 0x44444444u), 0, 0, 0, 0};
 #pragma unroll
         for (int h = 0; h < RG; ++h)
           if (RG == 1 || hl[h])
