@@ -61,9 +61,111 @@ constexpr int kWaves = kThreads / kWave;
 // orthogonal), v_l / v_r = min / max of r / b, Delta = (v_r - v_l) / (2^B_q - 1)
 // and the randomized rounding q_u[i] = min(2^B_q - 1, floor((r_i/b - v_l)/Delta + u_i)),
 // written as s.npl bit planes (and as int8 q_u - s.qoff for the MFMA scan), plus the pair's
-// estimator constants. One wave handles PPW pairs with the residual held in
-// registers (WS >= W words of 64 coordinates, compile-time bound), so each
-// coordinate is loaded once.
+// estimator constants. prep_pair does this for pair g = (query q, list) from
+// the residual rv (this lane's coordinates t * 64 + lane, WS >= W words, a
+// compile-time bound) and the query's norm qn.
+template <int WS, int NPL>
+__device__ __forceinline__ void prep_pair(const SearchDev& s, int64_t g, int64_t q, int list, const float* rv,
+                                          float qn) {
+  const int lane = lane_id();
+  const int W = s.W;
+  PairRec rec;
+  float rmin = rv[0], rmax = rv[0], ss = 0.f;
+#pragma unroll
+  for (int t = 0; t < WS; ++t) {
+    if (t < W) {
+      rmin = fminf(rmin, rv[t]);
+      rmax = fmaxf(rmax, rv[t]);
+      ss = fmaf(rv[t], rv[t], ss);
+    }
+  }
+  float b = uniform_f32(sqrtf(wave_sum(ss)));
+  // Near a centroid the rotated residual is dominated by the rotation's
+  // rounding (~1e-6 (||q|| + ||c||)): take b from the raw vectors there, so
+  // that b is exactly 0 when the query coincides with the centroid.
+  const float scale_qc = uniform_f32(qn + sqrtf(s.cnorm[list]));
+  if (b <= 1e-4f * scale_qc) {
+    const float* qr = s.q + q * s.dim;
+    const float* c = s.cent + (int64_t)list * s.dim;
+    float acc = 0.f;
+    for (int i = lane; i < s.dim; i += kWave) {
+      const float d = qr[i] - c[i];
+      acc = fmaf(d, d, acc);
+    }
+    b = uniform_f32(sqrtf(wave_sum(acc)));
+  }
+  rmin = wave_min(rmin);
+  rmax = wave_max(rmax);
+  const float range = rmax - rmin;
+  const bool live = (b > 0.f) && (range > 0.f);
+  const float scale = live ? (float)s.qmax / range : 0.f;
+  const uint64_t qid = (uint64_t)(s.qid_base + q);
+  int sq = 0;
+  const int npl = NPL > 0 ? NPL : s.npl;   // bit planes (B_q), compile-time when given
+  uint64_t* pl = s.planes + g * npl * W;
+  int8_t* q8 = s.qu8 ? s.qu8 + g * s.dp : nullptr;
+  // with the MFMA scan, only the pairs whose first chunk is a bootstrap chunk
+  // (scanned by the popcount phase 0) need bit planes
+  const int64_t r = g - q * s.nprobe;
+  const bool planes =
+      !s.boot_planes_only || uniform_i32(s.pair_choff[q * (s.nprobe + 1) + r]) < uniform_i32(s.q_p0[q]);
+  float u_next = 0.f;   // word t + 1's uniform, drawn with word t's (t even)
+#pragma unroll
+  for (int t = 0; t < WS; ++t) {
+    if (t < W) {
+      const int i = t * kWave + lane;
+      float u;
+      if ((t & 1) == 0) {
+        rounding_u2(s.seed, qid, (uint32_t)list, (uint32_t)i, u, u_next);
+      } else {
+        u = u_next;
+      }
+      // a pair that is not live has scale 0, so x = 0 and floor(u) = 0
+      const float x = (rv[t] - rmin) * scale;
+      const int qu = min(s.qmax, (int)floorf(x + u));
+      sq += qu;
+      if (q8) q8[(uint32_t)i] = (int8_t)(qu - s.qoff);
+      if (!planes) continue;
+      if constexpr (NPL > 0) {   // all ballots first, then one branch for the stores
+        uint64_t w[NPL > 0 ? NPL : 1];
+#pragma unroll
+        for (int jb = 0; jb < NPL; ++jb) w[jb] = __ballot((qu >> jb) & 1);
+        if (lane == 0) {
+#pragma unroll
+          for (int jb = 0; jb < NPL; ++jb) pl[jb * W + t] = w[jb];
+        }
+      } else {
+        for (int jb = 0; jb < npl; ++jb) {
+          const uint64_t w = __ballot((qu >> jb) & 1);
+          if (lane == 0) pl[jb * W + t] = w;
+        }
+      }
+    }
+  }
+  sq = wave_sum_i(sq);
+  if (s.metric != 0) {   // inner product: the pair's constant M_q - <q_r, c> from the raw vectors
+    const float* qr = s.q + q * s.dim;
+    const float* c = s.cent + (int64_t)list * s.dim;
+    float acc = 0.f;
+    for (int i = lane; i < s.dim; i += kWave) acc = fmaf(qr[i], c[i], acc);
+    const float gdot = wave_sum(acc);
+    if (lane == 0) s.pair_pt[g] = s.q_m[q] - gdot;
+  }
+  if (lane == 0) {
+    double vl, delta;
+    pair_scalars(rmin, range, b, s.qmax, vl, delta);
+    pair_coeffs(vl, delta, sq, s.rd, s.ird, rec);
+    rec.b = b;
+    rec.vl = (float)vl;
+    rec.delta = (float)delta;
+    rec.sq = sq;
+    rec.list = list;
+    s.pairs[g] = rec;
+  }
+}
+
+// One wave per PPW consecutive pairs, residuals held in registers (each
+// coordinate loaded once).
 template <int WS, int PPW, int NPL>
 __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
   const int lane = lane_id();
@@ -120,8 +222,10 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
 #pragma unroll
     for (int t = 0; t < WS; ++t) {
       const int tt = min(t, W - 1);
-      xs[t] = qrot[tt * kWave + lane];
-      cs[t] = crot[tt * kWave + lane];
+      // wave-uniform row bases, 32-bit lane offsets (scalar-base loads)
+      const uint32_t off = 4u * (uint32_t)(tt * kWave + lane);
+      xs[t] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(qrot) + off);
+      cs[t] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(crot) + off);
     }
 #pragma unroll
     for (int t = 0; t < WS; ++t) {
@@ -139,8 +243,8 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
   for (int j = 0; j < PPW; ++j) {
     const int64_t g = g0 + j;
     if (g >= npairs) break;
-    PairRec rec;
     if (!act[j]) {
+      PairRec rec;
       if (lane == 0) {
         rec.k1 = rec.k2 = rec.k0 = rec.b = rec.vl = rec.delta = 0.f;
         rec.sq = 0;
@@ -149,99 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_reg(SearchDev s) {
       }
       continue;
     }
-    const int64_t q = g / s.nprobe;
-    float rmin = rv[j][0], rmax = rv[j][0], ss = 0.f;
-#pragma unroll
-    for (int t = 0; t < WS; ++t) {
-      if (t < W) {
-        rmin = fminf(rmin, rv[j][t]);
-        rmax = fmaxf(rmax, rv[j][t]);
-        ss = fmaf(rv[j][t], rv[j][t], ss);
-      }
-    }
-    float b = uniform_f32(sqrtf(wave_sum(ss)));
-    // Near a centroid the rotated residual is dominated by the rotation's
-    // rounding (~1e-6 (||q|| + ||c||)): take b from the raw vectors there, so
-    // that b is exactly 0 when the query coincides with the centroid.
-    const float scale_qc = uniform_f32(sqrtf(wave_sum(qq[j])) + sqrtf(s.cnorm[list[j]]));
-    if (b <= 1e-4f * scale_qc) {
-      const float* qr = s.q + q * s.dim;
-      const float* c = s.cent + (int64_t)list[j] * s.dim;
-      float acc = 0.f;
-      for (int i = lane; i < s.dim; i += kWave) {
-        const float d = qr[i] - c[i];
-        acc = fmaf(d, d, acc);
-      }
-      b = uniform_f32(sqrtf(wave_sum(acc)));
-    }
-    rmin = wave_min(rmin);
-    rmax = wave_max(rmax);
-    const float range = rmax - rmin;
-    const bool live = (b > 0.f) && (range > 0.f);
-    const float scale = live ? (float)s.qmax / range : 0.f;
-    const uint64_t qid = (uint64_t)(s.qid_base + q);
-    int sq = 0;
-    const int npl = NPL > 0 ? NPL : s.npl;   // bit planes (B_q), compile-time when given
-    uint64_t* pl = s.planes + g * npl * W;
-    int8_t* q8 = s.qu8 ? s.qu8 + g * s.dp : nullptr;
-    // with the MFMA scan, only the pairs whose first chunk is a bootstrap chunk
-    // (scanned by the popcount phase 0) need bit planes
-    const int64_t r = g - q * s.nprobe;
-    const bool planes =
-        !s.boot_planes_only || uniform_i32(s.pair_choff[q * (s.nprobe + 1) + r]) < uniform_i32(s.q_p0[q]);
-    float u_next = 0.f;   // word t + 1's uniform, drawn with word t's (t even)
-#pragma unroll
-    for (int t = 0; t < WS; ++t) {
-      if (t < W) {
-        const int i = t * kWave + lane;
-        float u;
-        if ((t & 1) == 0) {
-          rounding_u2(s.seed, qid, (uint32_t)list[j], (uint32_t)i, u, u_next);
-        } else {
-          u = u_next;
-        }
-        // a pair that is not live has scale 0, so x = 0 and floor(u) = 0
-        const float x = (rv[j][t] - rmin) * scale;
-        const int qu = min(s.qmax, (int)floorf(x + u));
-        sq += qu;
-        if (q8) q8[i] = (int8_t)(qu - s.qoff);
-        if (!planes) continue;
-        if constexpr (NPL > 0) {   // all ballots first, then one branch for the stores
-          uint64_t w[NPL > 0 ? NPL : 1];
-#pragma unroll
-          for (int jb = 0; jb < NPL; ++jb) w[jb] = __ballot((qu >> jb) & 1);
-          if (lane == 0) {
-#pragma unroll
-            for (int jb = 0; jb < NPL; ++jb) pl[jb * W + t] = w[jb];
-          }
-        } else {
-          for (int jb = 0; jb < npl; ++jb) {
-            const uint64_t w = __ballot((qu >> jb) & 1);
-            if (lane == 0) pl[jb * W + t] = w;
-          }
-        }
-      }
-    }
-    sq = wave_sum_i(sq);
-    if (s.metric != 0) {   // inner product: the pair's constant M_q - <q_r, c> from the raw vectors
-      const float* qr = s.q + q * s.dim;
-      const float* c = s.cent + (int64_t)list[j] * s.dim;
-      float acc = 0.f;
-      for (int i = lane; i < s.dim; i += kWave) acc = fmaf(qr[i], c[i], acc);
-      const float gdot = wave_sum(acc);
-      if (lane == 0) s.pair_pt[g] = s.q_m[q] - gdot;
-    }
-    if (lane == 0) {
-      double vl, delta;
-      pair_scalars(rmin, range, b, s.qmax, vl, delta);
-      pair_coeffs(vl, delta, sq, s.rd, s.ird, rec);
-      rec.b = b;
-      rec.vl = (float)vl;
-      rec.delta = (float)delta;
-      rec.sq = sq;
-      rec.list = list[j];
-      s.pairs[g] = rec;
-    }
+    prep_pair<WS, NPL>(s, g, g / s.nprobe, list[j], rv[j], sqrtf(wave_sum(qq[j])));
   }
 }
 
