@@ -39,19 +39,37 @@ SCAN_SOURCES = {
                "paper_2405_12497_amd/csrc/rbq_internal.hpp"),
     "mfma": ("paper_2405_12497_amd/csrc/kernels_mfma.hip", "paper_2405_12497_amd/csrc/scan_code.hpp",
              "paper_2405_12497_amd/csrc/rbq_internal.hpp"),
+    "finalize": ("paper_2405_12497_amd/csrc/kernels_scan.hip", "paper_2405_12497_amd/csrc/wave_select.hpp",
+                 "paper_2405_12497_amd/csrc/rbq_internal.hpp"),
 }
-# HBM traffic of one scan launch per workload, from rocprofv3 --pmc FETCH_SIZE
-# and --pmc WRITE_SIZE (KiB per dispatch, mean over the timed steps' dispatches
-# of that kernel), each scaled by the reading of the same counter for a 1 GiB
+# HBM traffic of one launch per workload, from rocprofv3 --pmc FETCH_SIZE and
+# --pmc WRITE_SIZE (KiB per dispatch, mean over the timed steps' dispatches of
+# that kernel), each scaled by the reading of the same counter for a 1 GiB
 # device-to-device copy (FETCH_SIZE reads 0.5x the copied bytes, WRITE_SIZE
 # 1.0x). A reading applies only while the kernel's sources hash to the value
 # it was taken on and the workload key matches.
 COUNTERS = {
-    "sift": {
+    "learned_mfma": {
+        "kind": "mfma",
+        "sources_sha256": "effe3d43f3f1890aee0b9d23aa294e21b38897b58d613440da5cbb9991cac9e9",
+        "workload": "learned n=10000000 nlist=16384 batch=10000",
+        "fetch_kib": 2308801.4, "write_kib": 1008186.1, "fetch_scale": 2.0, "write_scale": 1.0,
+        # SQ counters of the same dispatches: SQ_VALU_MFMA_BUSY_CYCLES and
+        # 4 x SQ_INSTS_VALU over (GRBM_GUI_ACTIVE / 8 XCDs) x 1024 SIMDs, and
+        # SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES
+        "sq": {"mfma_busy": 0.186, "valu_busy": 0.640, "wave_wait_frac": 0.451},
+    },
+    "fullscan": {
         "kind": "popcnt",
-        "sources_sha256": "8586f0eedaf4c3b9cfa2f2cb581352979516762caa6333c338332bb04981a5bd",
-        "workload": "sift-like n=1000000 nq=10000 nlist=4096 nprobe=20 kernel=popcnt",
-        "fetch_kib": 471000.5, "write_kib": 23659.5, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sources_sha256": "1278f4a38262bec68207cdf10beb63ee30fda320a5b4b5e8326dab9947da0949",
+        "workload": "fullscan n=10000000 nlist=16384",
+        "fetch_kib": 540390.8, "write_kib": 624.3, "fetch_scale": 2.0, "write_scale": 1.0,
+    },
+    "finalize": {
+        "kind": "finalize",
+        "sources_sha256": "a984c38231fa8836e13dff6b154782b16d05137f73fbef724619d09080e2b1cf",
+        "workload": "learned n=10000000 nlist=16384 batch=10000",
+        "fetch_kib": 6355428.6, "write_kib": 2191.0, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 NPROBE_SWEEP = (8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256)
@@ -65,6 +83,14 @@ def scan_sources_sha256(kind="popcnt"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def stored_sq(name, workload_key):
+    """The stored SQ counter fractions of a kernel, under the same conditions as stored_traffic."""
+    c = COUNTERS.get(name)
+    if not c or "sq" not in c or c["sources_sha256"] != scan_sources_sha256(c["kind"]) or c["workload"] != workload_key:
+        return None
+    return c["sq"]
 
 
 def stored_traffic(name, workload_key):
@@ -90,7 +116,8 @@ def scan_roofline(kernel, codes, ms, dim, bpc, wkey):
                 "k_scan_mfma_w<true,12,1> (phase-1 batched scan, FP8 x FP4 MFMA)")
         return {"bound": "mfma", "achieved": achieved, "peak": peak,
                 "unit": "TOP/s" if kernel == "mfma" else "TFLOP/s", "frac": achieved / peak,
-                "traffic": stored_traffic("learned_" + kernel, wkey), "kernel": name,
+                "traffic": stored_traffic("learned_" + kernel, wkey), "sq_counters": stored_sq("learned_" + kernel, wkey),
+                "kernel": name,
                 "algorithmic_ops_per_code": 2 * dim, "ops_per_launch": ops, "avg_launch_ms": ms,
                 "counters_workload": wkey}
     achieved = codes * bpc / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -807,9 +834,11 @@ def bench_learned(args):
                               "kernel": "k_scan_popcnt<12,4,1> (one query, every list)",
                               "bytes_per_launch": full_bytes, "avg_launch_ms": full_ms, "counters_workload": fkey},
         "roofline_finalize": {"bound": "hbm", "achieved": fin_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": fin_gbs / HBM_PEAK_GBS, "kernel": "k_finalize (error-bound rerank)",
+                              "frac": fin_gbs / HBM_PEAK_GBS, "traffic": stored_traffic("finalize", wkey),
+                              "kernel": "k_finalize (error-bound rerank)",
                               "bytes_per_launch": fin_bytes, "avg_launch_ms": fin_ms,
-                              "algorithmic_bytes": "own reranks x (4 D + 8) + candidate entries x 8"},
+                              "algorithmic_bytes": "own reranks x (4 D + 8) + candidate entries x 8",
+                              "counters_workload": wkey},
         "cpu_baseline": None,
     }
     if not args.no_cpu:
