@@ -1091,8 +1091,7 @@ hipError_t launch_zero_u32(void* p, int64_t nwords, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t st) {
-  (void)phase;
+hipError_t launch_group_mfma(const SearchDev& s, hipStream_t st) {
   const int64_t np = s.nq * s.nprobe;
   const unsigned g1 = (unsigned)((np + 255) / 256);
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((s.nlist + 255) / 256)), dim3(256), 0, st,
@@ -1100,6 +1099,11 @@ hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t
   hipLaunchKernelGGL(k_group_count, dim3(g1), dim3(256), 0, st, s);
   hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, st, s);
   hipLaunchKernelGGL(k_group_scatter, dim3(g1), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t st) {
+  (void)phase;
   const bool f4 = s.mfma_f4 != 0;
   bool wave = false;
   const void* f = pick_kernel(f4, false, s.W, s.mf_rg, s.npl == 4, &wave);

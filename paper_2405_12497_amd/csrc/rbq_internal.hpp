@@ -364,6 +364,9 @@ int scan_mfma_blocks_per_cu(int dp, bool f4, int rg, bool narrow);
 // phase 0: bootstrap units, 1: main units with the bound filter, 2: parity
 // export of the main-phase table (s.dbg_*).
 hipError_t launch_scan_popcnt(const SearchDev& s, int phase, int grid, hipStream_t st);
+// The main-phase pairs grouped by list (mf_cnt, mf_pair_off, mf_unit_off,
+// mf_pairs), which launch_scan_mfma's units read; independent of tau.
+hipError_t launch_group_mfma(const SearchDev& s, hipStream_t st);
 hipError_t launch_scan_mfma(const SearchDev& s, int phase, int grid, hipStream_t st);
 hipError_t launch_tau(const SearchDev& s, hipStream_t st);
 hipError_t launch_finalize(const SearchDev& s, hipStream_t st);

@@ -925,6 +925,9 @@ rbq_status run_search(rbq_index* idx, const float* queries, int64_t nq, const rb
   HIPCHK(launch_scan_popcnt(s, 0, grid0, st));
   HIPCHK(rec(3));
   HIPCHK(launch_tau_split(s, tau_split(fin_w, o.k), (uint64_t*)idx->ws.tau_part.p, st));
+  // the batched scan's grouping of pairs by list (timed with the bootstrap
+  // rerank, so that the phase-1 events bound the scan kernel alone)
+  if (mfma) HIPCHK(launch_group_mfma(s, st));
   HIPCHK(rec(4));
   if (mfma) {
     HIPCHK(launch_scan_mfma(s, 1, scan_grid(idx, nq, chunks, scan_mfma_blocks_per_cu(idx->dp, s.mfma_f4 != 0, s.mf_rg, s.npl == 4)),
