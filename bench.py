@@ -882,8 +882,8 @@ def main():
         print(json.dumps({"copy_bytes_each": n * 4, "copies": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library shards "
+              "nothing across GPUs (how it would is described with the design).", file=sys.stderr)
         sys.exit(2)
     if args.workload == "learned":
         bench_learned(args)

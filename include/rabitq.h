@@ -51,7 +51,7 @@ typedef enum {
   RBQ_EDEVICE = 3,       /* a HIP runtime call failed */
   RBQ_ESTATE = 4,        /* index not built, or call not allowed in this state */
   RBQ_EFORMAT = 5,       /* corrupt or truncated index file */
-  RBQ_EUNSUPPORTED = 6   /* valid request this build does not implement */
+  RBQ_EUNSUPPORTED = 6   /* valid request the library does not implement */
 } rbq_status;
 
 /* Rotation arithmetic (S1 of the query path and the index-time rotation). */

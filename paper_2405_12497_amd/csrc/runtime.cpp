@@ -1179,7 +1179,7 @@ rbq_status rbq::search_locked(rbq_index* idx, const float* queries, int64_t nq, 
   if (o.rerank_waves == 0) o.rerank_waves = tc.fin_w;
   if (kernel == RBQ_SCAN_AUTO || (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())) {
     if (kernel == RBQ_SCAN_MFMA && o.scan_kernel == RBQ_SCAN_MFMA)
-      return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this build");
+      return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this library");
     kernel = RBQ_SCAN_POPCNT;
   }
   const bool learned = !o.nprobe_per_query && o.use_learned_nprobe && idx->mlp.has_model;
@@ -1299,7 +1299,7 @@ rbq_status rbq::search_in_arena(rbq_index* idx, const float* queries, int64_t nq
   if (o.rerank_waves == 0) o.rerank_waves = tc.fin_w;
   if (kernel == RBQ_SCAN_AUTO || (kernel == RBQ_SCAN_MFMA && !rbq::mfma_available())) {
     if (kernel == RBQ_SCAN_MFMA && o.scan_kernel == RBQ_SCAN_MFMA)
-      return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this build");
+      return fail(RBQ_EUNSUPPORTED, "the MFMA scan kernel is not available in this library");
     kernel = RBQ_SCAN_POPCNT;
   }
   const bool learned = !o.nprobe_per_query && o.use_learned_nprobe && idx->mlp.has_model;
