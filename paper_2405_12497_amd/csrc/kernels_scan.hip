@@ -721,8 +721,9 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets_scan(SearchDev s) {
 }
 
 // A lane per probe rank: the descriptors of its chunks,
-// bootstrap ones to units0 (at off_p0[q]) and the others to units1 (at
-// off_p1[q]); and each chunk's first query-code index, for finalize.
+// bootstrap ones to units0 (at off_p0[q]) and, for the popcount main phase,
+// the others to units1 (at off_p1[q]); and each chunk's first query-code
+// index, for finalize.
 // One wave per (query, 64 probe ranks): the descriptors of those ranks' chunks.
 __device__ __forceinline__ void units_body(const SearchDev& s, int64_t blk) {
   const int nrb = (s.nprobe + kWave - 1) / kWave;
@@ -757,7 +758,13 @@ __device__ __forceinline__ void units_body(const SearchDev& s, int64_t blk) {
       d.q = (int32_t)q;
       d.pad = 0;
       s.chunk_qcode[ch0 + j] = (int32_t)d.qcode;
-      if (j < p0) s.units0[b0 + j] = d; else s.units1[b1 + (j - p0)] = d;
+      // with the batched scan (boot_planes_only) the main phase takes its
+      // work from the pairs grouped by list, so only bootstrap units are built
+      if (j < p0) {
+        s.units0[b0 + j] = d;
+      } else if (!s.boot_planes_only) {
+        s.units1[b1 + (j - p0)] = d;
+      }
     }
   }
 }
