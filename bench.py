@@ -67,9 +67,9 @@ COUNTERS = {
     },
     "finalize": {
         "kind": "finalize",
-        "sources_sha256": "a984c38231fa8836e13dff6b154782b16d05137f73fbef724619d09080e2b1cf",
+        "sources_sha256": "f4437b650ca24495580c991eacba6fa405e43ffd54af47d10710ab9f9d3d2c62",
         "workload": "learned n=10000000 nlist=16384 batch=10000",
-        "fetch_kib": 6355428.6, "write_kib": 2191.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "fetch_kib": 6355367.4, "write_kib": 2191.3, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 NPROBE_SWEEP = (8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256)
